@@ -1,0 +1,254 @@
+/*
+ * mqhelm.h -- C ABI of the MI355X (gfx950) GKB / Ine-TSVD / HKT solver for
+ * multiquadric-RBF Kansa collocation of the 3-D Helmholtz problem.
+ *
+ * Paper: M. El Guide, K. Jbilou, K. Lachhab, D. Ouazar, "Efficient
+ * Krylov-Regularization Solvers for Multiquadric RBF Discretizations of the
+ * 3D Helmholtz Equation" (arXiv 2511.09798).
+ *
+ * Problem (Section 2.1):  Lap u + kappa^2 u = f in Omega, u = g on its boundary.
+ * Unknowns: coefficients c of u(X) = sum_j c_j phi(|X - X_j|) with the
+ * multiquadric phi(r) = sqrt(1 + eps^2 r^2) (eq. MQ) centred at the nodes.
+ * Kansa matrix A (N x N, eqs. H_entries, augmented_system, full_system):
+ *   interior rows i < N_I :  A_ij = Lap phi(r_ij) + kappa^2 phi(r_ij),
+ *                            Lap phi(r) = eps^2 (3 + 2 eps^2 r^2) / (1 + eps^2 r^2)^{3/2};
+ *   boundary rows i >= N_I:  A_ij = phi(r_ij)   (Dirichlet data);
+ * right-hand side f = [f_I; g_B].
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Node arrays are row-major n x 3 float64 (x, y, z interleaved).  The node
+ *   (= centre = coefficient) order is [interior; boundary].
+ * - All other arrays are contiguous float64 (int32 where stated).
+ * - Pointers are host pointers unless the call's flags carry
+ *   MQH_FLAG_DEVICE_PTRS, in which case every array argument of that call is
+ *   a device pointer on the problem's device (e.g. a torch tensor's data_ptr()).
+ * - The caller owns every array it passes.  Inputs are read during the call
+ *   (host inputs are copied); outputs are written before the call returns
+ *   (device outputs: written in stream order on the call's stream; the call
+ *   synchronises that stream before returning).
+ * - Return value: MQH_OK (0); a negative error (outputs untouched, any
+ *   *info still filled); or a positive warning (outputs valid).  No C++
+ *   exception or abort crosses this interface.  mqh_last_error() returns a
+ *   thread-local message for the last failure.
+ * - A problem handle is used by one host thread at a time; calls on one
+ *   handle are serialised on its stream.
+ */
+#ifndef MQHELM_H
+#define MQHELM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MQH_VERSION 10000 /* 1.0.0 */
+
+/* ---- status codes ---- */
+#define MQH_OK 0
+#define MQH_EINVAL (-1)   /* bad argument: NaN/Inf input, n <= 0, eps <= 0, ell < 1, ell > n or > MQH_MAX_ELL, ... */
+#define MQH_ENOMEM (-2)   /* device allocation failed (e.g. the stored matrix does not fit) */
+#define MQH_EDEVICE (-3)  /* a HIP runtime call or kernel launch failed */
+#define MQH_WBREAKDOWN 1  /* Golub-Kahan stopped early (ell_done < ell); outputs valid for ell_done steps */
+#define MQH_WEDGE 2       /* chosen lambda sits at an end of the search grid */
+
+/* ---- operator modes (how A enters the products) ---- */
+#define MQH_OP_STORED_FP64 0   /* A assembled once in HBM (8 N^2 bytes, row-major), FP64 products */
+#define MQH_OP_MATFREE_FP64 1  /* entries regenerated inside every product, FP64 throughout */
+#define MQH_OP_MATFREE_FP32 2  /* entries evaluated in FP32, accumulated in FP64 */
+
+/* ---- methods and parameter-choice rules ---- */
+#define MQH_METHOD_INE_TSVD 0 /* Algorithm 2 */
+#define MQH_METHOD_HKT 1      /* Algorithm 4 */
+#define MQH_RULE_GCV 0        /* eq. gcv_proj (HKT) / projected TSVD-GCV (Ine-TSVD) */
+#define MQH_RULE_LCURVE 1     /* maximum curvature of (log rho, log eta) on the grid */
+#define MQH_RULE_FIXED 2      /* lambda = lambda_fixed (HKT) / k = k_trunc (Ine-TSVD) */
+
+/* ---- call flags ---- */
+#define MQH_FLAG_DEVICE_PTRS 1u     /* array arguments are device pointers */
+#define MQH_FLAG_TIME_PRODUCTS 2u   /* mqh_solve: time every product kernel with HIP events on the problem's stream */
+
+/* ---- info flags ---- */
+#define MQH_INFO_BREAKDOWN 1u
+#define MQH_INFO_GCV_AT_EDGE 2u
+#define MQH_INFO_LCURVE_AT_EDGE 4u
+
+/* Largest number of Golub-Kahan steps a solve accepts (projected problem size). */
+#define MQH_MAX_ELL 1024
+
+typedef struct mqh_problem mqh_problem;
+
+/* Options of a solve (Algorithms 2 and 4; Section 3). */
+typedef struct {
+    int32_t ell;          /* Golub-Kahan steps, 1 <= ell <= min(n, MQH_MAX_ELL) */
+    int32_t reorth;       /* 1: full reorthogonalisation (classical Gram-Schmidt twice); 0: none */
+    int32_t method;       /* MQH_METHOD_* */
+    int32_t rule;         /* MQH_RULE_* */
+    int32_t k_trunc;      /* Ine-TSVD with MQH_RULE_FIXED: rank k (1..ell) */
+    int32_t n_grid;       /* lambda grid size J (>= 3; 0 -> 200) */
+    double lambda_fixed;  /* HKT with MQH_RULE_FIXED: lambda >= 0 */
+    uint32_t flags;       /* MQH_FLAG_* for this call */
+    int32_t reserved;
+} mqh_solve_opts;
+
+/* Outcome of a solve. */
+typedef struct {
+    int32_t ell_done;      /* Golub-Kahan steps kept (< ell after a breakdown) */
+    int32_t k_chosen;      /* Ine-TSVD rank (0 for HKT) */
+    double lambda_chosen;  /* HKT lambda (0 for Ine-TSVD) */
+    double crit;           /* GCV value at the choice, or curvature for the L-curve rule */
+    double resid_norm;     /* projected residual norm rho_l at the choice (eq. rho_proj) */
+    double sol_norm;       /* projected solution norm eta_l = ||y|| (eq. eta_proj) */
+    uint32_t flags;        /* MQH_INFO_* */
+    int32_t reserved;
+    double t_ms[8];        /* [0] data upload, [1] Golub-Kahan loop, [2] projected SVD,
+                              [3] parameter choice + projected solution, [4] lift,
+                              [5] total (upload to results on host),
+                              [6] summed time of the ell A^T-product kernels,
+                              [7] summed time of the ell A-product kernels
+                              ([6],[7] only with MQH_FLAG_TIME_PRODUCTS; the split-K
+                              reduction that follows a product is not included) */
+} mqh_solve_info;
+
+int mqh_version(void);
+const char* mqh_status_str(int status);
+const char* mqh_last_error(void);
+
+/*
+ * Create a problem: copies the nodes to the device and, for
+ * MQH_OP_STORED_FP64, assembles A there (eqs. H_entries, augmented_system).
+ *   x_int    n_int x 3 interior nodes (may be NULL when n_int == 0)
+ *   x_bnd    n_bnd x 3 boundary nodes (may be NULL when n_bnd == 0)
+ *   kappa    wavenumber (finite); eps > 0 shape parameter (eq. MQ)
+ *   op_mode  MQH_OP_*
+ *   stream   hipStream_t to run on, or NULL for a stream the library creates
+ *   flags    MQH_FLAG_DEVICE_PTRS if x_int / x_bnd are device pointers
+ * Errors: MQH_EINVAL (n_int < 0, n_bnd < 0, n = 0, non-finite input,
+ * eps <= 0, unknown mode), MQH_ENOMEM (stored matrix or buffers do not fit),
+ * MQH_EDEVICE.  On error *out is set to NULL.
+ */
+int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, int64_t n_bnd, double kappa,
+                       double eps, int32_t op_mode, void* stream, uint32_t flags, mqh_problem** out);
+
+/* Free every device buffer of the problem (NULL is accepted). */
+int mqh_problem_destroy(mqh_problem* p);
+
+/* Problem size n = n_int + n_bnd, or -1 for NULL. */
+int64_t mqh_problem_size(const mqh_problem* p);
+
+/*
+ * One product of the Golub-Kahan recurrence (Algorithm 1, steps 3 and 5):
+ *   trans = 0:  y = A x - shift * z
+ *   trans = 1:  y = A^T x - shift * z
+ * x, z, y have length n; z may be NULL (then the shift is ignored).  y must
+ * not alias x.  The product runs in the problem's operator mode.
+ */
+int mqh_apply(mqh_problem* p, int32_t trans, const double* x, double shift, const double* z, double* y,
+              uint32_t flags);
+
+/*
+ * Rows [row0, row0 + count) of A as the problem's operator mode sees them
+ * (the stored matrix, or entries generated the way the matrix-free products
+ * generate them, FP32-evaluated in MQH_OP_MATFREE_FP32), written row-major
+ * count x n to out.  For checks of the entry generator (eq. H_entries).
+ */
+int mqh_matrix_rows(mqh_problem* p, int64_t row0, int64_t count, double* out, uint32_t flags);
+
+/*
+ * Golub-Kahan bidiagonalisation (Algorithm 1) started from f (length n),
+ * ell steps, with full reorthogonalisation (classical Gram-Schmidt twice,
+ * applied before each norm) when reorth = 1.
+ * Outputs (any may be NULL):
+ *   W      n x (ell+1) column-major (column k = w_{k+1}), leading dimension n
+ *   Z      n x ell column-major (column k = z_{k+1})
+ *   alpha  ell values alpha_1..alpha_ell
+ *   beta   ell+1 values beta_1 = ||f|| .. beta_{ell+1}
+ *   ell_done  host int32: steps kept.  A step stops when alpha_j or
+ *             beta_{j+1} <= n * DBL_EPSILON * max(alpha_i, beta_{i+1} so far);
+ *             an alpha breakdown keeps j-1 steps, a beta breakdown keeps j
+ *             steps with beta_{j+1} = 0.  Entries past ell_done are zero.
+ * Returns MQH_WBREAKDOWN when ell_done < ell or beta_{ell+1} = 0 was forced.
+ */
+int mqh_gkb(mqh_problem* p, const double* f, int32_t ell, int32_t reorth, double* W, double* Z, double* alpha,
+            double* beta, int32_t* ell_done, uint32_t flags);
+
+/*
+ * SVD of the (ell+1) x ell lower bidiagonal C_ell with diagonal
+ * alpha_1..alpha_ell and subdiagonal beta_2..beta_{ell+1} (Algorithm 2
+ * step 2, Algorithm 4 step 2), computed on the device:
+ *   sv    ell singular values, descending
+ *   ftil  ell+1 projected data f~ = U~^T (beta_1 e_1) (f~_{ell+1} is the
+ *         least-squares residual of min ||C y - beta_1 e_1||)
+ *   V     ell x ell column-major right singular vectors (column i = v~_i),
+ *         may be NULL
+ * alpha (ell) and beta (ell+1, beta[0] = beta_1) are inputs.  Signs of
+ * singular vectors are arbitrary (f~_i and v~_i flip together).
+ * stream: hipStream_t or NULL (default stream).  1 <= ell <= MQH_MAX_ELL.
+ */
+int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* sv, double* ftil, double* V,
+                 void* stream, uint32_t flags);
+
+/*
+ * Parameter choice on the projected problem (Section 3.2-3.3), on the device.
+ *   method HKT:      rule GCV    -> lambda* = argmin GCV_l (eq. gcv_proj) on a
+ *                                   log grid of n_grid points over
+ *                                   [max(s_l, 16 eps_mach s_1), s_1], then
+ *                                   golden-section refinement of log lambda
+ *                                   in the bracketing cells;
+ *                    rule LCURVE -> grid point of maximum signed curvature
+ *                                   of (log rho_l, log eta_l), end points excluded;
+ *                    rule FIXED  -> lambda_fixed.
+ *   method INE_TSVD: rule FIXED  -> k = k_trunc; otherwise k* = argmin over
+ *                                   k = 1..max(1, ell/2) of
+ *                                   (sum_{i>k} f~_i^2 + f~_{l+1}^2)/((l+1)-k)^2.
+ * Inputs sv (ell, descending), ftil (ell+1).  Outputs (host scalars; NULL
+ * allowed): lambda, k, crit (GCV value / curvature at the choice),
+ * info_flags (MQH_INFO_*); curve (n_grid values of the criterion on the
+ * grid, pointer kind per flags, NULL allowed).
+ * Returns MQH_WEDGE when the choice is at a grid end.
+ */
+int mqh_param_choice(const double* sv, const double* ftil, int32_t ell, int32_t method, int32_t rule,
+                     int32_t n_grid, double lambda_fixed, int32_t k_trunc, double* lambda, int32_t* k,
+                     double* crit, uint32_t* info_flags, double* curve, void* stream, uint32_t flags);
+
+/*
+ * Projected solution (Algorithm 2 step 5 / Algorithm 4 step 8 in SVD form):
+ *   HKT:      y = sum_i s_i / (s_i^2 + lambda^2) f~_i v~_i
+ *   Ine-TSVD: y = sum_{i<=k} f~_i / s_i v~_i
+ * sv (ell), ftil (ell+1), V (ell x ell column-major) in; y (ell) out.
+ */
+int mqh_proj_solution(const double* sv, const double* ftil, const double* V, int32_t ell, int32_t method,
+                      double lambda, int32_t k, double* y, void* stream, uint32_t flags);
+
+/*
+ * Lift coef = Z y (Algorithm 2 step 5, Algorithm 4 last step): Z is
+ * n x ell column-major with leading dimension n, y has ell entries,
+ * coef n entries.
+ */
+int mqh_lift(const double* Z, int64_t n, int32_t ell, const double* y, double* coef, void* stream,
+             uint32_t flags);
+
+/*
+ * Whole solve (Algorithm 2 or 4): f = [f_int (n_int); g_bnd (n_bnd)] ->
+ * Golub-Kahan (ell steps) -> projected SVD -> parameter choice -> projected
+ * solution -> coef = Z y (n).  Optional outputs (NULL allowed): gkb_alpha
+ * (ell), gkb_beta (ell+1), ritz_sv (ell); entries past info->ell_done are 0.
+ * info may be NULL.  opts->flags decides the pointer kind of every array.
+ * Returns MQH_OK, MQH_WBREAKDOWN, MQH_WEDGE (edge and breakdown: breakdown
+ * wins) or an error.
+ */
+int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts, double* coef,
+              double* gkb_alpha, double* gkb_beta, double* ritz_sv, mqh_solve_info* info);
+
+/*
+ * Evaluate u(X_e) = sum_j coef_j phi(|X_e - X_j|) at m points
+ * (eq. u_reconstruction), FP64: coef (n), x_eval (m x 3) in, u (m) out.
+ */
+int mqh_eval(mqh_problem* p, const double* coef, const double* x_eval, int64_t m, double* u, uint32_t flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MQHELM_H */

@@ -1,0 +1,884 @@
+// capi.hip -- host runtime and C ABI (include/mqhelm.h) of the MQ-RBF
+// Golub-Kahan / Ine-TSVD / HKT solver on one gfx950 GPU.
+//
+// Every call enqueues its kernels on the problem's stream, keeps all
+// Golub-Kahan scalars on the device (no host synchronisation inside the
+// loop) and synchronises once before it returns.
+#include <math.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mqhelm.h"
+
+using namespace mqh;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? MQH_ENOMEM : MQH_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                                          \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);     \
+    } while (0)
+
+#define LAUNCHCHK(what)                                       \
+    do {                                                      \
+        hipError_t _e = hipGetLastError();                    \
+        if (_e != hipSuccess) return hip_fail(_e, what);      \
+    } while (0)
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+template <typename T>
+int dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return hip_fail(e, "hipMalloc");
+    }
+    return MQH_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p != nullptr) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+bool all_finite(const double* x, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!isfinite(x[i])) return false;
+    return true;
+}
+
+hipMemcpyKind kind_in(uint32_t flags) { return (flags & MQH_FLAG_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+hipMemcpyKind kind_out(uint32_t flags) { return (flags & MQH_FLAG_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+
+// Small device-to-host results of a solve, in pinned memory.
+struct HostResults {
+    GkbState st;
+    ParamOut po;
+    int32_t svd_status;
+    int32_t pad;
+};
+
+}  // namespace
+
+struct mqh_problem {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t n = 0, n_int = 0, n_bnd = 0, ldn = 0;
+    double kappa = 0.0, eps = 1.0;
+    int32_t mode = 0;
+    double center[3] = {0.0, 0.0, 0.0};
+    EntryConst ec{};
+    double4* X64 = nullptr;
+    float4* X32 = nullptr;
+    double* A = nullptr;
+    int64_t lda = 0;
+    // length-ldn vectors (zero past n)
+    double* vx = nullptr;
+    double* vy = nullptr;
+    double* vz = nullptr;
+    // split-K partials, P_rows x ldn
+    double* P = nullptr;
+    int64_t P_rows = 0;
+    // launch shapes
+    int S_rows = 1, S_cols = 1;
+    int64_t slice_rows = 0, slice_cols = 0;
+    int stored_rw = 4;
+    int64_t stored_tile_rows = 0;
+    int stored_tiles = 1;
+    // Golub-Kahan workspace
+    int32_t ell_cap = 0;
+    double* W = nullptr;
+    double* Z = nullptr;
+    double* alpha = nullptr;
+    double* beta = nullptr;
+    GkbState* st = nullptr;
+    double* gpart = nullptr;
+    double* cvec = nullptr;
+    double* npart = nullptr;
+    // projected problem
+    double* sv = nullptr;
+    double* ftil = nullptr;
+    double* Vw = nullptr;
+    double* V = nullptr;
+    double* y = nullptr;
+    ParamOut* pout = nullptr;
+    int32_t* svd_status = nullptr;
+    double* coef = nullptr;
+    HostResults* hres = nullptr;
+    // evaluation
+    double4* E = nullptr;
+    int64_t E_cap = 0;
+    double* EP = nullptr;
+    int64_t EP_cap = 0;
+    double* u = nullptr;
+    // timing
+    hipEvent_t ev[8] = {};
+    std::vector<hipEvent_t> pev;
+};
+
+namespace {
+
+void to_records(const mqh_problem* p, const double* xyz, int64_t m, double4* r64, float4* r32) {
+    for (int64_t i = 0; i < m; ++i) {
+        const double x = p->eps * (xyz[3 * i + 0] - p->center[0]);
+        const double y = p->eps * (xyz[3 * i + 1] - p->center[1]);
+        const double z = p->eps * (xyz[3 * i + 2] - p->center[2]);
+        if (r64) r64[i] = make_double4(x, y, z, 0.0);
+        if (r32) r32[i] = make_float4((float)x, (float)y, (float)z, 0.0f);
+    }
+}
+
+void choose_shapes(mqh_problem* p) {
+    const int64_t n = p->n;
+    const int64_t target_blocks = 4096;  // 16 waves per SIMD over 256 CUs
+    const int64_t nb_rows = (p->n_int + kBlock - 1) / kBlock + (p->n_bnd + kBlock - 1) / kBlock;
+    const int64_t nb_cols = (n + kBlock - 1) / kBlock;
+    auto pick = [&](int64_t nb, int& S, int64_t& len) {
+        int64_t s = (target_blocks + nb - 1) / nb;
+        if (s < 1) s = 1;
+        if (s > 64) s = 64;
+        int64_t l = (n + s - 1) / s;
+        l = round_up(l < 64 ? 64 : l, 2);
+        s = (n + l - 1) / l;
+        S = (int)(s < 1 ? 1 : s);
+        len = l;
+    };
+    pick(nb_rows, p->S_rows, p->slice_rows);
+    pick(nb_cols, p->S_cols, p->slice_cols);
+    p->stored_rw = n >= 50000 ? 8 : (n >= 5000 ? 4 : 2);
+    const int64_t col_tiles = (p->ldn + 2 * kBlock - 1) / (2 * kBlock);
+    int64_t tiles = (target_blocks + col_tiles - 1) / col_tiles;
+    if (tiles > 128) tiles = 128;
+    if (tiles > n) tiles = n;
+    if (tiles < 1) tiles = 1;
+    p->stored_tile_rows = (n + tiles - 1) / tiles;
+    p->stored_tiles = (int)((n + p->stored_tile_rows - 1) / p->stored_tile_rows);
+    int64_t rows = p->S_rows;
+    if (p->S_cols > rows) rows = p->S_cols;
+    if (p->stored_tiles > rows) rows = p->stored_tiles;
+    p->P_rows = rows;
+}
+
+// One product y = op(A) x - shift z on device vectors (x, z of length ldn,
+// zero-padded).  shift from *shift_ptr when non-null.
+int op_product(mqh_problem* p, int trans, const double* x, const double* shift_ptr, double shift_val, const double* z,
+               double* y, const GkbState* st, bool timed) {
+    hipStream_t s = p->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        size_t k = p->pev.size();
+        for (int q = 0; q < 2; ++q) {
+            hipEvent_t ev;
+            HIPCHK(hipEventCreate(&ev));
+            p->pev.push_back(ev);
+        }
+        e0 = p->pev[k];
+        e1 = p->pev[k + 1];
+        HIPCHK(hipEventRecord(e0, s));
+    }
+    if (p->mode == MQH_OP_STORED_FP64) {
+        if (!trans) {
+            launch_stored_rows(p->stored_rw, p->A, p->lda, p->n, x, shift_ptr, shift_val, z, y, st, s);
+            LAUNCHCHK("stored rows product");
+            if (timed) HIPCHK(hipEventRecord(e1, s));
+        } else {
+            launch_stored_cols(p->A, p->lda, p->n, x, p->stored_tile_rows, p->stored_tiles, p->P, p->ldn, st, s);
+            LAUNCHCHK("stored columns product");
+            if (timed) HIPCHK(hipEventRecord(e1, s));
+            launch_reduce_slices(p->P, p->ldn, p->stored_tiles, p->n, shift_ptr, shift_val, z, y, st, s);
+            LAUNCHCHK("slice reduction");
+        }
+        return MQH_OK;
+    }
+    const int prec = p->mode == MQH_OP_MATFREE_FP64 ? 64 : 32;
+    const void* X = prec == 64 ? (const void*)p->X64 : (const void*)p->X32;
+    int S;
+    if (!trans) {
+        S = p->S_rows;
+        launch_mf_rows(prec, X, x, p->n, p->n_int, S, p->slice_rows, p->ec, p->P, p->ldn, st, s);
+    } else {
+        S = p->S_cols;
+        launch_mf_cols(prec, X, x, p->n, p->n_int, S, p->slice_cols, p->ec, p->P, p->ldn, st, s);
+    }
+    LAUNCHCHK("matrix-free product");
+    if (timed) HIPCHK(hipEventRecord(e1, s));
+    launch_reduce_slices(p->P, p->ldn, S, p->n, shift_ptr, shift_val, z, y, st, s);
+    LAUNCHCHK("slice reduction");
+    return MQH_OK;
+}
+
+int ensure_gkb(mqh_problem* p, int32_t ell) {
+    if (ell <= p->ell_cap) return MQH_OK;
+    dfree(p->W);
+    dfree(p->Z);
+    dfree(p->alpha);
+    dfree(p->beta);
+    dfree(p->gpart);
+    dfree(p->cvec);
+    dfree(p->sv);
+    dfree(p->ftil);
+    dfree(p->Vw);
+    dfree(p->V);
+    dfree(p->y);
+    p->ell_cap = 0;
+    const int64_t cols = (int64_t)ell + 1;
+    int rc;
+    if ((rc = dalloc(&p->W, (size_t)(cols * p->ldn)))) return rc;
+    if ((rc = dalloc(&p->Z, (size_t)(cols * p->ldn)))) return rc;
+    HIPCHK(hipMemsetAsync(p->W, 0, (size_t)(cols * p->ldn) * sizeof(double), p->stream));
+    HIPCHK(hipMemsetAsync(p->Z, 0, (size_t)(cols * p->ldn) * sizeof(double), p->stream));
+    if ((rc = dalloc(&p->alpha, (size_t)cols))) return rc;
+    if ((rc = dalloc(&p->beta, (size_t)cols + 1))) return rc;
+    if ((rc = dalloc(&p->gpart, (size_t)gemvt_blocks(p->n) * (size_t)cols))) return rc;
+    if ((rc = dalloc(&p->cvec, (size_t)cols))) return rc;
+    if ((rc = dalloc(&p->sv, (size_t)cols))) return rc;
+    if ((rc = dalloc(&p->ftil, (size_t)cols + 1))) return rc;
+    if ((rc = dalloc(&p->Vw, (size_t)ell * (size_t)ell))) return rc;
+    if ((rc = dalloc(&p->V, (size_t)ell * (size_t)ell))) return rc;
+    if ((rc = dalloc(&p->y, (size_t)cols))) return rc;
+    p->ell_cap = ell;
+    return MQH_OK;
+}
+
+// f must be staged in p->vx.  Runs Algorithm 1 with ell steps; everything stays on the device.
+int run_gkb(mqh_problem* p, int32_t ell, int32_t reorth, bool timed) {
+    hipStream_t s = p->stream;
+    const int64_t n = p->n, ldn = p->ldn;
+    const int nbq = sumsq_blocks(n);
+    const int nbu = update_blocks(n);
+    launch_init_state(p->st, ell, p->alpha, p->beta, s);
+    LAUNCHCHK("init state");
+    launch_sumsq_partial(p->vx, n, p->npart, nbq, p->st, s);
+    launch_norm_finalize(p->npart, nbq, 0, 0, n, p->alpha, p->beta, p->st, s);
+    launch_scale(p->vx, n, p->beta, p->W, p->st, s);
+    LAUNCHCHK("initial normalisation");
+    auto orthonormalize = [&](double* v, const double* V, int32_t m, int kind, int32_t j, double* dst) -> int {
+        int nparts;
+        if (reorth && m > 0) {
+            launch_gemvt(V, ldn, n, m, v, p->gpart, p->cvec, p->st, s);
+            launch_update(V, ldn, n, m, p->cvec, v, nullptr, p->st, s);
+            launch_gemvt(V, ldn, n, m, v, p->gpart, p->cvec, p->st, s);
+            launch_update(V, ldn, n, m, p->cvec, v, p->npart, p->st, s);
+            nparts = nbu;
+        } else {
+            launch_sumsq_partial(v, n, p->npart, nbq, p->st, s);
+            nparts = nbq;
+        }
+        launch_norm_finalize(p->npart, nparts, kind, j, n, p->alpha, p->beta, p->st, s);
+        const double* div = kind == 1 ? p->alpha + j : p->beta + j + 1;
+        launch_scale(v, n, div, dst, p->st, s);
+        LAUNCHCHK("reorthogonalisation / normalisation");
+        return MQH_OK;
+    };
+    int rc;
+    for (int32_t j = 0; j < ell; ++j) {
+        double* Wj = p->W + (int64_t)j * ldn;
+        double* Zj = p->Z + (int64_t)j * ldn;
+        // r = A^T w_j - beta_j z_{j-1}
+        if ((rc = op_product(p, 1, Wj, p->beta + j, 0.0, j > 0 ? p->Z + (int64_t)(j - 1) * ldn : nullptr, p->vy,
+                             p->st, timed)))
+            return rc;
+        if ((rc = orthonormalize(p->vy, p->Z, j, 1, j, Zj))) return rc;
+        // p = A z_j - alpha_j w_j
+        if ((rc = op_product(p, 0, Zj, p->alpha + j, 0.0, Wj, p->vy, p->st, timed))) return rc;
+        if ((rc = orthonormalize(p->vy, p->W, j + 1, 2, j, p->W + (int64_t)(j + 1) * ldn))) return rc;
+    }
+    return MQH_OK;
+}
+
+int stage_in(double* dst, const double* src, int64_t count, uint32_t flags, hipStream_t s) {
+    if (count <= 0) return MQH_OK;
+    if (!(flags & MQH_FLAG_DEVICE_PTRS) && !all_finite(src, count)) return fail(MQH_EINVAL, "non-finite input");
+    HIPCHK(hipMemcpyAsync(dst, src, (size_t)count * sizeof(double), kind_in(flags), s));
+    return MQH_OK;
+}
+
+int check_problem(const mqh_problem* p) {
+    if (p == nullptr) return fail(MQH_EINVAL, "NULL problem");
+    return MQH_OK;
+}
+
+void clear_info(mqh_solve_info* info) {
+    if (info) memset(info, 0, sizeof(*info));
+}
+
+}  // namespace
+
+extern "C" {
+
+int mqh_version(void) { return MQH_VERSION; }
+
+const char* mqh_status_str(int status) {
+    switch (status) {
+        case MQH_OK: return "ok";
+        case MQH_EINVAL: return "invalid argument";
+        case MQH_ENOMEM: return "out of device memory";
+        case MQH_EDEVICE: return "device error";
+        case MQH_WBREAKDOWN: return "Golub-Kahan breakdown (fewer steps kept)";
+        case MQH_WEDGE: return "parameter at the end of the search grid";
+        default: return "unknown status";
+    }
+}
+
+const char* mqh_last_error(void) { return g_last_error.c_str(); }
+
+int64_t mqh_problem_size(const mqh_problem* p) { return p ? p->n : -1; }
+
+int mqh_problem_destroy(mqh_problem* p) {
+    if (p == nullptr) return MQH_OK;
+    (void)hipSetDevice(p->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    dfree(p->X64);
+    dfree(p->X32);
+    dfree(p->A);
+    dfree(p->vx);
+    dfree(p->vy);
+    dfree(p->vz);
+    dfree(p->P);
+    dfree(p->W);
+    dfree(p->Z);
+    dfree(p->alpha);
+    dfree(p->beta);
+    dfree(p->st);
+    dfree(p->gpart);
+    dfree(p->cvec);
+    dfree(p->npart);
+    dfree(p->sv);
+    dfree(p->ftil);
+    dfree(p->Vw);
+    dfree(p->V);
+    dfree(p->y);
+    dfree(p->pout);
+    dfree(p->svd_status);
+    dfree(p->coef);
+    dfree(p->E);
+    dfree(p->EP);
+    dfree(p->u);
+    if (p->hres) (void)hipHostFree(p->hres);
+    for (auto& e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : p->pev) (void)hipEventDestroy(e);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+    return MQH_OK;
+}
+
+int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, int64_t n_bnd, double kappa,
+                       double eps, int32_t op_mode, void* stream, uint32_t flags, mqh_problem** out) {
+    if (out == nullptr) return fail(MQH_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_int < 0 || n_bnd < 0 || n_int + n_bnd <= 0) return fail(MQH_EINVAL, "need n_int >= 0, n_bnd >= 0, n >= 1");
+    if (n_int + n_bnd > (int64_t)1 << 31) return fail(MQH_EINVAL, "n too large");
+    if ((n_int > 0 && x_int == nullptr) || (n_bnd > 0 && x_bnd == nullptr)) return fail(MQH_EINVAL, "NULL nodes");
+    if (!isfinite(kappa) || !isfinite(eps) || !(eps > 0.0)) return fail(MQH_EINVAL, "need finite kappa and eps > 0");
+    if (op_mode < MQH_OP_STORED_FP64 || op_mode > MQH_OP_MATFREE_FP32) return fail(MQH_EINVAL, "unknown op_mode");
+    const int64_t n = n_int + n_bnd;
+    std::vector<double> xyz((size_t)(3 * n));
+    if (flags & MQH_FLAG_DEVICE_PTRS) {
+        if (n_int) HIPCHK(hipMemcpy(xyz.data(), x_int, (size_t)(3 * n_int) * sizeof(double), hipMemcpyDeviceToHost));
+        if (n_bnd)
+            HIPCHK(hipMemcpy(xyz.data() + 3 * n_int, x_bnd, (size_t)(3 * n_bnd) * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        if (n_int) memcpy(xyz.data(), x_int, (size_t)(3 * n_int) * sizeof(double));
+        if (n_bnd) memcpy(xyz.data() + 3 * n_int, x_bnd, (size_t)(3 * n_bnd) * sizeof(double));
+    }
+    if (!all_finite(xyz.data(), 3 * n)) return fail(MQH_EINVAL, "non-finite node coordinate");
+
+    mqh_problem* p = new mqh_problem();
+    int rc = MQH_OK;
+    auto bail = [&](int code) {
+        mqh_problem_destroy(p);
+        return code;
+    };
+    HIPCHK(hipGetDevice(&p->device));
+    p->n = n;
+    p->n_int = n_int;
+    p->n_bnd = n_bnd;
+    p->ldn = round_up(n, 64);
+    p->kappa = kappa;
+    p->eps = eps;
+    p->mode = op_mode;
+    p->ec.k2 = kappa * kappa;
+    p->ec.e2 = eps * eps;
+    p->ec.e2x2 = 2.0 * eps * eps;
+    p->ec.k2f = (float)p->ec.k2;
+    p->ec.e2f = (float)p->ec.e2;
+    p->ec.e2x2f = (float)p->ec.e2x2;
+    for (int a = 0; a < 3; ++a) {
+        double lo = xyz[a], hi = xyz[a];
+        for (int64_t i = 1; i < n; ++i) {
+            lo = xyz[3 * i + a] < lo ? xyz[3 * i + a] : lo;
+            hi = xyz[3 * i + a] > hi ? xyz[3 * i + a] : hi;
+        }
+        p->center[a] = 0.5 * (lo + hi);
+    }
+    if (stream != nullptr) {
+        p->stream = (hipStream_t)stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipStreamCreate"));
+        p->own_stream = true;
+    }
+    for (auto& e : p->ev)
+        if (hipEventCreate(&e) != hipSuccess) return bail(hip_fail(hipErrorUnknown, "hipEventCreate"));
+    std::vector<double4> r64((size_t)n);
+    std::vector<float4> r32((size_t)n);
+    to_records(p, xyz.data(), n, r64.data(), r32.data());
+    choose_shapes(p);
+    if ((rc = dalloc(&p->X64, (size_t)n))) return bail(rc);
+    if ((rc = dalloc(&p->X32, (size_t)n))) return bail(rc);
+    if ((rc = dalloc(&p->vx, (size_t)p->ldn))) return bail(rc);
+    if ((rc = dalloc(&p->vy, (size_t)p->ldn))) return bail(rc);
+    if ((rc = dalloc(&p->vz, (size_t)p->ldn))) return bail(rc);
+    if ((rc = dalloc(&p->P, (size_t)(p->P_rows * p->ldn)))) return bail(rc);
+    if ((rc = dalloc(&p->st, 1))) return bail(rc);
+    if ((rc = dalloc(&p->npart, (size_t)(update_blocks(n) > 1024 ? update_blocks(n) : 1024)))) return bail(rc);
+    if ((rc = dalloc(&p->pout, 1))) return bail(rc);
+    if ((rc = dalloc(&p->svd_status, 1))) return bail(rc);
+    if ((rc = dalloc(&p->coef, (size_t)p->ldn))) return bail(rc);
+    {
+        hipError_t e = hipHostMalloc((void**)&p->hres, sizeof(HostResults), hipHostMallocDefault);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipHostMalloc"));
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(p->X64, r64.data(), (size_t)n * sizeof(double4), hipMemcpyHostToDevice, p->stream)) ||
+        (e = hipMemcpyAsync(p->X32, r32.data(), (size_t)n * sizeof(float4), hipMemcpyHostToDevice, p->stream)) ||
+        (e = hipMemsetAsync(p->vx, 0, (size_t)p->ldn * sizeof(double), p->stream)) ||
+        (e = hipMemsetAsync(p->vy, 0, (size_t)p->ldn * sizeof(double), p->stream)) ||
+        (e = hipMemsetAsync(p->vz, 0, (size_t)p->ldn * sizeof(double), p->stream)) ||
+        (e = hipMemsetAsync(p->coef, 0, (size_t)p->ldn * sizeof(double), p->stream)))
+        return bail(hip_fail(e, "upload"));
+    if (op_mode == MQH_OP_STORED_FP64) {
+        p->lda = p->ldn;
+        if ((rc = dalloc(&p->A, (size_t)(n * p->lda)))) return bail(rc);
+        launch_assemble(p->X64, n, n_int, p->lda, p->ec, p->A, p->stream);
+        if ((e = hipGetLastError())) return bail(hip_fail(e, "assembly launch"));
+    }
+    if ((e = hipStreamSynchronize(p->stream))) return bail(hip_fail(e, "create"));
+    *out = p;
+    return MQH_OK;
+}
+
+int mqh_apply(mqh_problem* p, int32_t trans, const double* x, double shift, const double* z, double* y, uint32_t flags) {
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (x == nullptr || y == nullptr) return fail(MQH_EINVAL, "NULL vector");
+    if (trans != 0 && trans != 1) return fail(MQH_EINVAL, "trans must be 0 or 1");
+    if (!isfinite(shift)) return fail(MQH_EINVAL, "non-finite shift");
+    HIPCHK(hipSetDevice(p->device));
+    if ((rc = stage_in(p->vx, x, p->n, flags, p->stream))) return rc;
+    if (z && (rc = stage_in(p->vz, z, p->n, flags, p->stream))) return rc;
+    if ((rc = op_product(p, trans, p->vx, nullptr, shift, z ? p->vz : nullptr, p->vy, nullptr, false))) return rc;
+    HIPCHK(hipMemcpyAsync(y, p->vy, (size_t)p->n * sizeof(double), kind_out(flags), p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return MQH_OK;
+}
+
+int mqh_matrix_rows(mqh_problem* p, int64_t row0, int64_t count, double* out, uint32_t flags) {
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (out == nullptr || row0 < 0 || count < 1 || row0 + count > p->n) return fail(MQH_EINVAL, "bad row range");
+    HIPCHK(hipSetDevice(p->device));
+    const bool dev = (flags & MQH_FLAG_DEVICE_PTRS) != 0;
+    const int64_t chunk = 1024;
+    double* tmp = nullptr;
+    if (!dev && (rc = dalloc(&tmp, (size_t)(chunk * p->n)))) return rc;
+    for (int64_t r = row0; r < row0 + count; r += chunk) {
+        const int64_t c = (row0 + count - r) < chunk ? (row0 + count - r) : chunk;
+        double* dst = dev ? out + (r - row0) * p->n : tmp;
+        hipError_t e;
+        if (p->mode == MQH_OP_STORED_FP64) {
+            e = hipMemcpy2DAsync(dst, (size_t)p->n * sizeof(double), p->A + r * p->lda, (size_t)p->lda * sizeof(double),
+                                 (size_t)p->n * sizeof(double), (size_t)c, hipMemcpyDeviceToDevice, p->stream);
+        } else {
+            launch_gen_rows(p->mode == MQH_OP_MATFREE_FP64 ? 64 : 32,
+                            p->mode == MQH_OP_MATFREE_FP64 ? (const void*)p->X64 : (const void*)p->X32, p->n, p->n_int,
+                            r, c, p->ec, dst, p->stream);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && !dev)
+            e = hipMemcpyAsync(out + (r - row0) * p->n, tmp, (size_t)(c * p->n) * sizeof(double), hipMemcpyDeviceToHost,
+                               p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) {
+            dfree(tmp);
+            return hip_fail(e, "matrix rows");
+        }
+    }
+    dfree(tmp);
+    return MQH_OK;
+}
+
+int mqh_gkb(mqh_problem* p, const double* f, int32_t ell, int32_t reorth, double* W, double* Z, double* alpha,
+            double* beta, int32_t* ell_done, uint32_t flags) {
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (f == nullptr) return fail(MQH_EINVAL, "NULL f");
+    if (ell < 1 || ell > p->n || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= min(n, MQH_MAX_ELL)");
+    if (reorth != 0 && reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
+    HIPCHK(hipSetDevice(p->device));
+    if ((rc = ensure_gkb(p, ell))) return rc;
+    if ((rc = stage_in(p->vx, f, p->n, flags, p->stream))) return rc;
+    if ((rc = run_gkb(p, ell, reorth, false))) return rc;
+    HIPCHK(hipMemcpyAsync(&p->hres->st, p->st, sizeof(GkbState), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    double b1 = 0.0;
+    HIPCHK(hipMemcpy(&b1, p->beta, sizeof(double), hipMemcpyDeviceToHost));
+    if (!isfinite(b1)) return fail(MQH_EINVAL, "non-finite right-hand side");
+    const int32_t done = p->hres->st.ell_done;
+    const hipMemcpyKind ko = kind_out(flags);
+    const int64_t n = p->n;
+    // columns past the kept steps are zero in the outputs
+    auto copy_cols = [&](double* dst, const double* src, int32_t total, int32_t valid) -> int {
+        if (dst == nullptr) return MQH_OK;
+        if (valid > 0)
+            HIPCHK(hipMemcpy2DAsync(dst, (size_t)n * sizeof(double), src, (size_t)p->ldn * sizeof(double),
+                                    (size_t)n * sizeof(double), (size_t)valid, ko, p->stream));
+        if (total > valid) {
+            if (flags & MQH_FLAG_DEVICE_PTRS) {
+                launch_fill(dst + (int64_t)valid * n, (int64_t)(total - valid) * n, 0.0, p->stream);
+                LAUNCHCHK("fill");
+            } else {
+                memset(dst + (int64_t)valid * n, 0, (size_t)(total - valid) * n * sizeof(double));
+            }
+        }
+        return MQH_OK;
+    };
+    const int32_t wcols = p->hres->st.flag == 2 ? done : done + 1;  // w_{done+1} is zero after a beta breakdown
+    if ((rc = copy_cols(W, p->W, ell + 1, wcols))) return rc;
+    if ((rc = copy_cols(Z, p->Z, ell, done))) return rc;
+    if (alpha) HIPCHK(hipMemcpyAsync(alpha, p->alpha, (size_t)ell * sizeof(double), ko, p->stream));
+    if (beta) HIPCHK(hipMemcpyAsync(beta, p->beta, (size_t)(ell + 1) * sizeof(double), ko, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    if (ell_done) *ell_done = done;
+    return (done < ell || p->hres->st.flag != 0) ? MQH_WBREAKDOWN : MQH_OK;
+}
+
+int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts, double* coef,
+              double* gkb_alpha, double* gkb_beta, double* ritz_sv, mqh_solve_info* info) {
+    clear_info(info);
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (opts == nullptr) return fail(MQH_EINVAL, "NULL opts");
+    if (coef == nullptr) return fail(MQH_EINVAL, "NULL coef");
+    if ((p->n_int > 0 && f_int == nullptr) || (p->n_bnd > 0 && g_bnd == nullptr)) return fail(MQH_EINVAL, "NULL data");
+    const int32_t ell = opts->ell;
+    if (ell < 1 || ell > p->n || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= min(n, MQH_MAX_ELL)");
+    if (opts->reorth != 0 && opts->reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
+    if (opts->method != MQH_METHOD_INE_TSVD && opts->method != MQH_METHOD_HKT) return fail(MQH_EINVAL, "method");
+    if (opts->rule < MQH_RULE_GCV || opts->rule > MQH_RULE_FIXED) return fail(MQH_EINVAL, "rule");
+    const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
+    if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
+    if (opts->method == MQH_METHOD_HKT && opts->rule == MQH_RULE_FIXED &&
+        (!isfinite(opts->lambda_fixed) || opts->lambda_fixed < 0.0))
+        return fail(MQH_EINVAL, "lambda_fixed must be finite and >= 0");
+    if (opts->method == MQH_METHOD_INE_TSVD && opts->rule == MQH_RULE_FIXED &&
+        (opts->k_trunc < 1 || opts->k_trunc > ell))
+        return fail(MQH_EINVAL, "k_trunc must be in [1, ell]");
+    const uint32_t flags = opts->flags;
+    const bool timed = (flags & MQH_FLAG_TIME_PRODUCTS) != 0;
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t s = p->stream;
+    if ((rc = ensure_gkb(p, ell))) return rc;
+    for (auto& e : p->pev) (void)hipEventDestroy(e);
+    p->pev.clear();
+    if (timed) p->pev.reserve((size_t)ell * 4);
+    HIPCHK(hipEventRecord(p->ev[0], s));
+    if ((rc = stage_in(p->vx, f_int, p->n_int, flags, s))) return rc;
+    if ((rc = stage_in(p->vx + p->n_int, g_bnd, p->n_bnd, flags, s))) return rc;
+    HIPCHK(hipEventRecord(p->ev[1], s));
+    if ((rc = run_gkb(p, ell, opts->reorth, timed))) return rc;
+    HIPCHK(hipEventRecord(p->ev[2], s));
+    const int32_t* lp = &p->st->ell_done;
+    launch_fill(p->sv, ell, 0.0, s);
+    launch_bidiag_svd(p->alpha, p->beta, ell, lp, p->Vw, ell, p->sv, p->ftil, p->V, ell, p->svd_status, s);
+    LAUNCHCHK("projected SVD");
+    HIPCHK(hipEventRecord(p->ev[3], s));
+    launch_param_choice(p->sv, p->ftil, ell, lp, opts->method, opts->rule, J, opts->lambda_fixed, opts->k_trunc,
+                        nullptr, p->pout, s);
+    launch_proj_solution(p->sv, p->ftil, p->V, ell, ell, lp, opts->method, 0.0, 0, p->pout, p->y, ell, s);
+    LAUNCHCHK("parameter choice");
+    HIPCHK(hipEventRecord(p->ev[4], s));
+    launch_lift(p->Z, p->ldn, p->n, ell, lp, p->y, p->coef, s);
+    LAUNCHCHK("lift");
+    HIPCHK(hipEventRecord(p->ev[5], s));
+    HIPCHK(hipMemcpyAsync(&p->hres->st, p->st, sizeof(GkbState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&p->hres->po, p->pout, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&p->hres->svd_status, p->svd_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double b1 = 0.0;
+    HIPCHK(hipMemcpy(&b1, p->beta, sizeof(double), hipMemcpyDeviceToHost));
+    if (!isfinite(b1)) return fail(MQH_EINVAL, "non-finite right-hand side");
+    if (p->hres->svd_status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    const hipMemcpyKind ko = kind_out(flags);
+    HIPCHK(hipMemcpyAsync(coef, p->coef, (size_t)p->n * sizeof(double), ko, s));
+    if (gkb_alpha) HIPCHK(hipMemcpyAsync(gkb_alpha, p->alpha, (size_t)ell * sizeof(double), ko, s));
+    if (gkb_beta) HIPCHK(hipMemcpyAsync(gkb_beta, p->beta, (size_t)(ell + 1) * sizeof(double), ko, s));
+    if (ritz_sv) HIPCHK(hipMemcpyAsync(ritz_sv, p->sv, (size_t)ell * sizeof(double), ko, s));
+    HIPCHK(hipEventRecord(p->ev[6], s));
+    HIPCHK(hipStreamSynchronize(s));
+    const GkbState& st = p->hres->st;
+    const ParamOut& po = p->hres->po;
+    uint32_t iflags = po.flags;
+    if (st.flag != 0) iflags |= MQH_INFO_BREAKDOWN;
+    if (info) {
+        info->ell_done = st.ell_done;
+        info->k_chosen = po.k;
+        info->lambda_chosen = po.lambda;
+        info->crit = po.crit;
+        info->resid_norm = po.rho;
+        info->sol_norm = po.eta;
+        info->flags = iflags;
+        float ms = 0.f;
+        const int pairs[6][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {0, 6}};
+        for (int q = 0; q < 6; ++q) {
+            if (hipEventElapsedTime(&ms, p->ev[pairs[q][0]], p->ev[pairs[q][1]]) == hipSuccess) info->t_ms[q] = ms;
+        }
+        if (timed) {
+            // products alternate A^T (even pairs) and A (odd pairs)
+            double tt = 0.0, ta = 0.0;
+            for (size_t q = 0; q + 1 < p->pev.size(); q += 2)
+                if (hipEventElapsedTime(&ms, p->pev[q], p->pev[q + 1]) == hipSuccess) ((q / 2) % 2 == 0 ? tt : ta) += ms;
+            info->t_ms[6] = tt;
+            info->t_ms[7] = ta;
+        }
+    }
+    if (st.flag != 0) return MQH_WBREAKDOWN;
+    if (iflags & (MQH_INFO_GCV_AT_EDGE | MQH_INFO_LCURVE_AT_EDGE)) return MQH_WEDGE;
+    return MQH_OK;
+}
+
+int mqh_eval(mqh_problem* p, const double* coef, const double* x_eval, int64_t m, double* u, uint32_t flags) {
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (coef == nullptr || x_eval == nullptr || u == nullptr || m < 1) return fail(MQH_EINVAL, "bad eval arguments");
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t s = p->stream;
+    std::vector<double> xyz((size_t)(3 * m));
+    if (flags & MQH_FLAG_DEVICE_PTRS)
+        HIPCHK(hipMemcpy(xyz.data(), x_eval, (size_t)(3 * m) * sizeof(double), hipMemcpyDeviceToHost));
+    else
+        memcpy(xyz.data(), x_eval, (size_t)(3 * m) * sizeof(double));
+    if (!all_finite(xyz.data(), 3 * m)) return fail(MQH_EINVAL, "non-finite evaluation point");
+    std::vector<double4> rec((size_t)m);
+    to_records(p, xyz.data(), m, rec.data(), nullptr);
+    const int64_t mb = (m + kBlock - 1) / kBlock;
+    int64_t S = (4096 + mb - 1) / mb;
+    if (S > 256) S = 256;
+    int64_t len = (p->n + S - 1) / S;
+    len = round_up(len < 64 ? 64 : len, 2);
+    S = (p->n + len - 1) / len;
+    const int64_t ldm = round_up(m, 64);
+    if (m > p->E_cap) {
+        dfree(p->E);
+        dfree(p->u);
+        p->E_cap = 0;
+        if ((rc = dalloc(&p->E, (size_t)m))) return rc;
+        if ((rc = dalloc(&p->u, (size_t)ldm))) return rc;
+        p->E_cap = m;
+    }
+    if (S * ldm > p->EP_cap) {
+        dfree(p->EP);
+        p->EP_cap = 0;
+        if ((rc = dalloc(&p->EP, (size_t)(S * ldm)))) return rc;
+        p->EP_cap = S * ldm;
+    }
+    if ((rc = stage_in(p->vx, coef, p->n, flags, s))) return rc;
+    HIPCHK(hipMemcpyAsync(p->E, rec.data(), (size_t)m * sizeof(double4), hipMemcpyHostToDevice, s));
+    launch_eval_partial(p->X64, p->vx, p->n, p->E, m, (int)S, len, p->ec, p->EP, ldm, s);
+    LAUNCHCHK("evaluation");
+    launch_reduce_slices(p->EP, ldm, (int)S, m, nullptr, 0.0, nullptr, p->u, nullptr, s);
+    LAUNCHCHK("evaluation reduction");
+    HIPCHK(hipMemcpyAsync(u, p->u, (size_t)m * sizeof(double), kind_out(flags), s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MQH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Standalone projected-problem calls (own temporary buffers)
+// ---------------------------------------------------------------------------
+
+namespace {
+struct Tmp {
+    std::vector<void*> bufs;
+    ~Tmp() {
+        for (void* b : bufs) (void)hipFree(b);
+    }
+    template <typename T>
+    int get(T** p, size_t count) {
+        int rc = dalloc(p, count);
+        if (rc == MQH_OK) bufs.push_back((void*)*p);
+        return rc;
+    }
+};
+
+// device copy of an input array (returns the device pointer to use)
+template <typename T>
+int dev_in(Tmp& t, const T* src, size_t count, uint32_t flags, hipStream_t s, const T** out) {
+    if (flags & MQH_FLAG_DEVICE_PTRS) {
+        *out = src;
+        return MQH_OK;
+    }
+    T* d;
+    int rc = t.get(&d, count);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(d, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+    *out = d;
+    return MQH_OK;
+}
+
+template <typename T>
+int dev_out(Tmp& t, T* dst, size_t count, uint32_t flags, T** out) {
+    if (flags & MQH_FLAG_DEVICE_PTRS) {
+        *out = dst;
+        return MQH_OK;
+    }
+    return t.get(out, count);
+}
+}  // namespace
+
+extern "C" {
+
+int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* sv, double* ftil, double* V,
+                 void* stream, uint32_t flags) {
+    if (alpha == nullptr || beta == nullptr || sv == nullptr || ftil == nullptr) return fail(MQH_EINVAL, "NULL array");
+    if (ell < 1 || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= MQH_MAX_ELL");
+    if (!(flags & MQH_FLAG_DEVICE_PTRS) && (!all_finite(alpha, ell) || !all_finite(beta, ell + 1)))
+        return fail(MQH_EINVAL, "non-finite input");
+    hipStream_t s = (hipStream_t)stream;
+    Tmp t;
+    int rc;
+    const double *da, *db;
+    double *dsv, *dft, *dV, *dVw;
+    int32_t* dst;
+    if ((rc = dev_in(t, alpha, (size_t)ell, flags, s, &da))) return rc;
+    if ((rc = dev_in(t, beta, (size_t)ell + 1, flags, s, &db))) return rc;
+    if ((rc = dev_out(t, sv, (size_t)ell, flags, &dsv))) return rc;
+    if ((rc = dev_out(t, ftil, (size_t)ell + 1, flags, &dft))) return rc;
+    if (V != nullptr) {
+        if ((rc = dev_out(t, V, (size_t)ell * ell, flags, &dV))) return rc;
+    } else if ((rc = t.get(&dV, (size_t)ell * ell))) {
+        return rc;
+    }
+    if ((rc = t.get(&dVw, (size_t)ell * ell))) return rc;
+    if ((rc = t.get(&dst, 1))) return rc;
+    launch_bidiag_svd(da, db, ell, nullptr, dVw, ell, dsv, dft, dV, ell, dst, s);
+    LAUNCHCHK("projected SVD");
+    int32_t status = 0;
+    HIPCHK(hipMemcpyAsync(&status, dst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (!(flags & MQH_FLAG_DEVICE_PTRS)) {
+        HIPCHK(hipMemcpyAsync(sv, dsv, (size_t)ell * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(ftil, dft, (size_t)(ell + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (V) HIPCHK(hipMemcpyAsync(V, dV, (size_t)ell * ell * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    return MQH_OK;
+}
+
+int mqh_param_choice(const double* sv, const double* ftil, int32_t ell, int32_t method, int32_t rule, int32_t n_grid,
+                     double lambda_fixed, int32_t k_trunc, double* lambda, int32_t* k, double* crit,
+                     uint32_t* info_flags, double* curve, void* stream, uint32_t flags) {
+    if (sv == nullptr || ftil == nullptr) return fail(MQH_EINVAL, "NULL array");
+    if (ell < 1 || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= MQH_MAX_ELL");
+    if (method != MQH_METHOD_INE_TSVD && method != MQH_METHOD_HKT) return fail(MQH_EINVAL, "method");
+    if (rule < MQH_RULE_GCV || rule > MQH_RULE_FIXED) return fail(MQH_EINVAL, "rule");
+    const int32_t J = n_grid == 0 ? 200 : n_grid;
+    if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
+    if (method == MQH_METHOD_HKT && rule == MQH_RULE_FIXED && (!isfinite(lambda_fixed) || lambda_fixed < 0.0))
+        return fail(MQH_EINVAL, "lambda_fixed");
+    if (method == MQH_METHOD_INE_TSVD && rule == MQH_RULE_FIXED && (k_trunc < 1 || k_trunc > ell))
+        return fail(MQH_EINVAL, "k_trunc");
+    if (!(flags & MQH_FLAG_DEVICE_PTRS) && (!all_finite(sv, ell) || !all_finite(ftil, ell + 1)))
+        return fail(MQH_EINVAL, "non-finite input");
+    hipStream_t s = (hipStream_t)stream;
+    Tmp t;
+    int rc;
+    const double *dsv, *dft;
+    double* dcurve = nullptr;
+    ParamOut* dpo;
+    if ((rc = dev_in(t, sv, (size_t)ell, flags, s, &dsv))) return rc;
+    if ((rc = dev_in(t, ftil, (size_t)ell + 1, flags, s, &dft))) return rc;
+    if (curve != nullptr && (rc = dev_out(t, curve, (size_t)J, flags, &dcurve))) return rc;
+    if ((rc = t.get(&dpo, 1))) return rc;
+    launch_param_choice(dsv, dft, ell, nullptr, method, rule, J, lambda_fixed, k_trunc, dcurve, dpo, s);
+    LAUNCHCHK("parameter choice");
+    ParamOut po;
+    HIPCHK(hipMemcpyAsync(&po, dpo, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
+    if (curve != nullptr && !(flags & MQH_FLAG_DEVICE_PTRS))
+        HIPCHK(hipMemcpyAsync(curve, dcurve, (size_t)J * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (lambda) *lambda = po.lambda;
+    if (k) *k = po.k;
+    if (crit) *crit = po.crit;
+    if (info_flags) *info_flags = po.flags;
+    return (po.flags & (MQH_INFO_GCV_AT_EDGE | MQH_INFO_LCURVE_AT_EDGE)) ? MQH_WEDGE : MQH_OK;
+}
+
+int mqh_proj_solution(const double* sv, const double* ftil, const double* V, int32_t ell, int32_t method, double lambda,
+                      int32_t k, double* y, void* stream, uint32_t flags) {
+    if (sv == nullptr || ftil == nullptr || V == nullptr || y == nullptr) return fail(MQH_EINVAL, "NULL array");
+    if (ell < 1 || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= MQH_MAX_ELL");
+    if (method != MQH_METHOD_INE_TSVD && method != MQH_METHOD_HKT) return fail(MQH_EINVAL, "method");
+    if (method == MQH_METHOD_HKT && (!isfinite(lambda) || lambda < 0.0)) return fail(MQH_EINVAL, "lambda");
+    if (method == MQH_METHOD_INE_TSVD && (k < 1 || k > ell)) return fail(MQH_EINVAL, "k");
+    hipStream_t s = (hipStream_t)stream;
+    Tmp t;
+    int rc;
+    const double *dsv, *dft, *dV;
+    double* dy;
+    if ((rc = dev_in(t, sv, (size_t)ell, flags, s, &dsv))) return rc;
+    if ((rc = dev_in(t, ftil, (size_t)ell + 1, flags, s, &dft))) return rc;
+    if ((rc = dev_in(t, V, (size_t)ell * ell, flags, s, &dV))) return rc;
+    if ((rc = dev_out(t, y, (size_t)ell, flags, &dy))) return rc;
+    launch_proj_solution(dsv, dft, dV, ell, ell, nullptr, method, lambda, k, nullptr, dy, ell, s);
+    LAUNCHCHK("projected solution");
+    if (!(flags & MQH_FLAG_DEVICE_PTRS))
+        HIPCHK(hipMemcpyAsync(y, dy, (size_t)ell * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MQH_OK;
+}
+
+int mqh_lift(const double* Z, int64_t n, int32_t ell, const double* y, double* coef, void* stream, uint32_t flags) {
+    if (Z == nullptr || y == nullptr || coef == nullptr) return fail(MQH_EINVAL, "NULL array");
+    if (n < 1 || ell < 1) return fail(MQH_EINVAL, "need n >= 1, ell >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    Tmp t;
+    int rc;
+    const double *dZ, *dy;
+    double* dc;
+    if ((rc = dev_in(t, Z, (size_t)(n * ell), flags, s, &dZ))) return rc;
+    if ((rc = dev_in(t, y, (size_t)ell, flags, s, &dy))) return rc;
+    if ((rc = dev_out(t, coef, (size_t)n, flags, &dc))) return rc;
+    launch_lift(dZ, n, n, ell, nullptr, dy, dc, s);
+    LAUNCHCHK("lift");
+    if (!(flags & MQH_FLAG_DEVICE_PTRS))
+        HIPCHK(hipMemcpyAsync(coef, dc, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return MQH_OK;
+}
+
+}  // extern "C"

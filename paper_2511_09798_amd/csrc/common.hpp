@@ -1,0 +1,135 @@
+// common.hpp -- device helpers shared by the gfx950 kernels of the MQ-RBF
+// Golub-Kahan solver: launch constants, deterministic wave/block reductions,
+// the Golub-Kahan device state and the multiquadric entry generators.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mqh {
+
+constexpr int kBlock = 256;  // threads per workgroup for the streaming kernels
+constexpr int kWave = 64;    // CDNA wavefront
+
+// Device-resident state of one Golub-Kahan run.  Every kernel of the loop
+// reads `stopped` first and returns at once after a breakdown, so the host
+// can enqueue all ell steps without synchronising.
+struct GkbState {
+    int32_t stopped;   // 1 after a breakdown
+    int32_t ell_done;  // steps kept (initialised to ell)
+    int32_t flag;      // 0, 1 = alpha breakdown, 2 = beta breakdown
+    int32_t pad;
+    double scale;      // running max of alpha_j, beta_{j+1}: the operator scale
+};
+
+// Native 2 x FP64 vector for 16-byte (non-temporal) loads and stores.
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ v2d load_nt(const double* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
+}
+__device__ __forceinline__ void store_nt(double* p, v2d v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<v2d*>(p));
+}
+__device__ __forceinline__ v2d load2(const double* p) { return *reinterpret_cast<const v2d*>(p); }
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions (fixed butterfly / fixed order, no atomics)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum over a whole block of NT threads; every thread gets the total.
+// `lds` must hold NT/64 doubles.  Contains barriers: call from all threads.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / kWave; ++i) s += lds[i];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Multiquadric entries.  Nodes are stored centred on their bounding box and
+// pre-multiplied by eps, so for two stored nodes P, Q
+//     t = 1 + |P - Q|^2 = 1 + eps^2 r^2 .
+// With s = t^{-1/2}:
+//   boundary row (Dirichlet, eq. MQ):     phi      = sqrt(t)          = t s
+//   interior row (eq. H_entries):         L phi    = eps^2 (2t+1) t^{-3/2} + kappa^2 t^{1/2}
+//                                                  = (kappa^2 t^2 + 2 eps^2 t + eps^2) s^3
+// (the Laplacian of phi in 3-D is eps^2 (3 + 2 eps^2 r^2) / t^{3/2}, and
+//  3 + 2 eps^2 r^2 = 2t + 1).
+// ---------------------------------------------------------------------------
+
+struct EntryConst {
+    double k2;    // kappa^2
+    double e2;    // eps^2
+    double e2x2;  // 2 eps^2
+    float k2f, e2f, e2x2f, padf;
+};
+
+// 1/sqrt(t) for t >= 1 in FP64: the hardware estimate refined by two Newton
+// steps s <- s + s (1 - t s^2) / 2 (each step roughly doubles the number of
+// correct bits of the ~23-bit estimate).
+__device__ __forceinline__ double rsqrt_f64(double t) {
+    double s = __builtin_amdgcn_rsq(t);
+    double h = t * s;
+    double r = fma(-h, s, 1.0);
+    s = fma(0.5 * s, r, s);
+    h = t * s;
+    r = fma(-h, s, 1.0);
+    s = fma(0.5 * s, r, s);
+    return s;
+}
+
+__device__ __forceinline__ double t_of(double px, double py, double pz, double qx, double qy, double qz) {
+    const double dx = px - qx, dy = py - qy, dz = pz - qz;
+    return fma(dz, dz, fma(dy, dy, fma(dx, dx, 1.0)));
+}
+
+__device__ __forceinline__ float t_of(float px, float py, float pz, float qx, float qy, float qz) {
+    const float dx = px - qx, dy = py - qy, dz = pz - qz;
+    return fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 1.0f)));
+}
+
+__device__ __forceinline__ double entry_interior(double t, const EntryConst& c) {
+    const double s = rsqrt_f64(t);
+    const double p = fma(fma(c.k2, t, c.e2x2), t, c.e2);
+    return p * (s * s * s);
+}
+
+__device__ __forceinline__ double entry_boundary(double t, const EntryConst&) { return t * rsqrt_f64(t); }
+
+// FP32 evaluation: one v_rsq_f32 per entry (1 ulp), the rest in FP32.
+__device__ __forceinline__ float entry_interior(float t, const EntryConst& c) {
+    const float s = __builtin_amdgcn_rsqf(t);
+    const float p = fmaf(fmaf(c.k2f, t, c.e2x2f), t, c.e2f);
+    return p * (s * s * s);
+}
+
+__device__ __forceinline__ float entry_boundary(float t, const EntryConst&) {
+    return t * __builtin_amdgcn_rsqf(t);
+}
+
+// Node record types per evaluation precision.
+template <typename R>
+struct NodeOf;
+template <>
+struct NodeOf<double> {
+    using type = double4;
+};
+template <>
+struct NodeOf<float> {
+    using type = float4;
+};
+
+}  // namespace mqh

@@ -1,0 +1,278 @@
+// gkb_kernels.hip -- vector kernels of the Golub-Kahan bidiagonalisation
+// (Algorithm 1) on gfx950: norms with the breakdown test, scaling, full
+// reorthogonalisation by classical Gram-Schmidt applied twice, and the lift
+// coef = Z y.  All reductions are deterministic (fixed trees, fixed orders).
+//
+// Bases W (n x (ell+1)) and Z (n x ell) are column-major with leading
+// dimension ldn, so every basis vector is contiguous and zero past n.
+#include <float.h>
+
+#include "kernels.hpp"
+
+namespace mqh {
+
+// ---------------------------------------------------------------------------
+// State and small fills
+// ---------------------------------------------------------------------------
+
+__global__ void k_init_state(GkbState* st, int32_t ell, double* alpha, double* beta) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        st->stopped = 0;
+        st->ell_done = ell;
+        st->flag = 0;
+        st->pad = 0;
+        st->scale = 0.0;
+    }
+    if (alpha != nullptr && i < ell) alpha[i] = 0.0;
+    if (beta != nullptr && i <= ell) beta[i] = 0.0;
+}
+
+__global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Norms
+// ---------------------------------------------------------------------------
+
+// partial[b] = sum of x_i^2 over the grid-stride share of block b.
+__global__ __launch_bounds__(kBlock) void k_sumsq_partial(const double* __restrict__ x, int64_t n,
+                                                          double* __restrict__ partial,
+                                                          const GkbState* __restrict__ st) {
+    __shared__ double lds[kBlock / kWave];
+    if (st != nullptr && st->stopped) return;  // uniform over the grid
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        s = fma(x[i], x[i], s);
+    s = block_sum<kBlock>(s, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Sums the partials, takes the square root and applies the breakdown test
+// (kind 0: beta_1 = ||f||; kind 1: alpha_{j+1}; kind 2: beta_{j+2}, 0-based j).
+// The threshold is n * DBL_EPSILON * (running max of alpha, beta_{>=2}).
+__global__ __launch_bounds__(kBlock) void k_norm_finalize(const double* __restrict__ partial, int nparts, int kind,
+                                                          int32_t j, int64_t n, double* __restrict__ alpha,
+                                                          double* __restrict__ beta, GkbState* __restrict__ st) {
+    __shared__ double lds[kBlock / kWave];
+    if (st->stopped) return;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partial[i];
+    s = block_sum<kBlock>(s, lds);
+    if (threadIdx.x != 0) return;
+    const double nrm = sqrt(s);
+    if (kind == 0) {
+        beta[0] = nrm;
+        if (!(nrm > 0.0)) {
+            st->stopped = 1;
+            st->ell_done = 0;
+            st->flag = 2;
+        }
+        return;
+    }
+    const double tau = (double)n * DBL_EPSILON * st->scale;
+    if (kind == 1) {
+        if (!(nrm > tau)) {
+            st->stopped = 1;
+            st->ell_done = j;
+            st->flag = 1;
+            return;
+        }
+        alpha[j] = nrm;
+    } else {
+        if (!(nrm > tau)) {
+            st->stopped = 1;
+            st->ell_done = j + 1;
+            st->flag = 2;
+            beta[j + 1] = 0.0;
+            return;
+        }
+        beta[j + 1] = nrm;
+    }
+    if (nrm > st->scale) st->scale = nrm;
+}
+
+// dst = x / *div  (normalisation of a Krylov vector).
+__global__ __launch_bounds__(kBlock) void k_scale(const double* __restrict__ x, int64_t n,
+                                                  const double* __restrict__ div, double* __restrict__ dst,
+                                                  const GkbState* __restrict__ st) {
+    if (st != nullptr && st->stopped) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) dst[i] = x[i] / *div;
+}
+
+// ---------------------------------------------------------------------------
+// Classical Gram-Schmidt against m orthonormal columns V[:, 0:m]
+// ---------------------------------------------------------------------------
+
+// partial[b * m + k] = sum over rows of block b of V[k][i] x_i.  A block
+// owns 256 rows (4 per lane, held in registers); each wave takes the
+// columns k = wave, wave + 4, ... two at a time and reduces across lanes.
+__global__ __launch_bounds__(kBlock) void k_gemvt_partial(const double* __restrict__ V, int64_t ldn, int64_t n,
+                                                          int32_t m, const double* __restrict__ x,
+                                                          double* __restrict__ partial,
+                                                          const GkbState* __restrict__ st) {
+    if (st != nullptr && st->stopped) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * kBlock + lane;
+    double xv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = r0 + q * kWave;
+        xv[q] = i < n ? x[i] : 0.0;
+    }
+    const int nw = kBlock / kWave;
+    int k = wv;
+    for (; k + nw < m; k += 2 * nw) {
+        const double* v0 = V + (int64_t)k * ldn;
+        const double* v1 = V + (int64_t)(k + nw) * ldn;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = r0 + q * kWave;
+            if (i < ldn) {  // V is zero-padded up to ldn
+                s0 = fma(v0[i], xv[q], s0);
+                s1 = fma(v1[i], xv[q], s1);
+            }
+        }
+        s0 = wave_sum(s0);
+        s1 = wave_sum(s1);
+        if (lane == 0) {
+            partial[(int64_t)blockIdx.x * m + k] = s0;
+            partial[(int64_t)blockIdx.x * m + k + nw] = s1;
+        }
+    }
+    if (k < m) {
+        const double* v0 = V + (int64_t)k * ldn;
+        double s0 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = r0 + q * kWave;
+            if (i < ldn) s0 = fma(v0[i], xv[q], s0);
+        }
+        s0 = wave_sum(s0);
+        if (lane == 0) partial[(int64_t)blockIdx.x * m + k] = s0;
+    }
+}
+
+// c[k] = sum_b partial[b * m + k]; a block takes 64 columns, its four waves
+// take interleaved quarters of the blocks, combined in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restrict__ partial, int nb, int32_t m,
+                                                         double* __restrict__ c,
+                                                         const GkbState* __restrict__ st) {
+    __shared__ double lds[kBlock];
+    if (st != nullptr && st->stopped) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int k = blockIdx.x * kWave + lane;
+    double s = 0.0;
+    if (k < m)
+        for (int b = wv; b < nb; b += kBlock / kWave) s += partial[(int64_t)b * m + k];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    if (wv == 0 && k < m) c[k] = ((lds[lane] + lds[kWave + lane]) + lds[2 * kWave + lane]) + lds[3 * kWave + lane];
+}
+
+// x_i -= sum_k V[k][i] c_k; optionally partial[b] = sum over the block of the updated x_i^2.
+__global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V, int64_t ldn, int64_t n, int32_t m,
+                                                   const double* __restrict__ c, double* __restrict__ x,
+                                                   double* __restrict__ sumsq_partial,
+                                                   const GkbState* __restrict__ st) {
+    __shared__ double lds[kBlock / kWave];
+    if (st != nullptr && st->stopped) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double xi = 0.0;
+    if (i < n) {
+        double s0 = 0.0, s1 = 0.0;
+        int k = 0;
+        for (; k + 1 < m; k += 2) {
+            s0 = fma(V[(int64_t)k * ldn + i], c[k], s0);
+            s1 = fma(V[(int64_t)(k + 1) * ldn + i], c[k + 1], s1);
+        }
+        if (k < m) s0 = fma(V[(int64_t)k * ldn + i], c[k], s0);
+        xi = x[i] - (s0 + s1);
+        x[i] = xi;
+    }
+    if (sumsq_partial != nullptr) {
+        const double s = block_sum<kBlock>(xi * xi, lds);
+        if (threadIdx.x == 0) sumsq_partial[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lift coef = Z y (Algorithm 2 step 5 / Algorithm 4 last step)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_lift(const double* __restrict__ Z, int64_t ldz, int64_t n,
+                                                 int32_t ell, const int32_t* __restrict__ ell_ptr,
+                                                 const double* __restrict__ y, double* __restrict__ coef) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t m = ell_ptr != nullptr ? *ell_ptr : ell;
+    double s0 = 0.0, s1 = 0.0;
+    int k = 0;
+    for (; k + 1 < m; k += 2) {
+        s0 = fma(Z[(int64_t)k * ldz + i], y[k], s0);
+        s1 = fma(Z[(int64_t)(k + 1) * ldz + i], y[k + 1], s1);
+    }
+    if (k < m) s0 = fma(Z[(int64_t)k * ldz + i], y[k], s0);
+    coef[i] = s0 + s1;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+void launch_init_state(GkbState* st, int32_t ell, double* alpha, double* beta, hipStream_t s) {
+    const int nt = 256;
+    k_init_state<<<(ell + 1 + nt) / nt, nt, 0, s>>>(st, ell, alpha, beta);
+}
+
+void launch_fill(double* x, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, v);
+}
+
+int sumsq_blocks(int64_t n) {
+    int64_t nb = (n + kBlock - 1) / kBlock;
+    return (int)(nb < 1024 ? nb : 1024);
+}
+
+void launch_sumsq_partial(const double* x, int64_t n, double* partial, int nb, const GkbState* st, hipStream_t s) {
+    k_sumsq_partial<<<nb, kBlock, 0, s>>>(x, n, partial, st);
+}
+
+void launch_norm_finalize(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
+                          double* beta, GkbState* st, hipStream_t s) {
+    k_norm_finalize<<<1, kBlock, 0, s>>>(partial, nparts, kind, j, n, alpha, beta, st);
+}
+
+void launch_scale(const double* x, int64_t n, const double* div, double* dst, const GkbState* st, hipStream_t s) {
+    k_scale<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, div, dst, st);
+}
+
+int gemvt_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
+                  const GkbState* st, hipStream_t s) {
+    const int nb = gemvt_blocks(n);
+    k_gemvt_partial<<<nb, kBlock, 0, s>>>(V, ldn, n, m, x, partial, st);
+    k_gemvt_reduce<<<(m + kWave - 1) / kWave, kBlock, 0, s>>>(partial, nb, m, c, st);
+}
+
+void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
+                   double* sumsq_partial, const GkbState* st, hipStream_t s) {
+    k_update<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(V, ldn, n, m, c, x, sumsq_partial, st);
+}
+
+int update_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+void launch_lift(const double* Z, int64_t ldz, int64_t n, int32_t ell, const int32_t* ell_ptr, const double* y,
+                 double* coef, hipStream_t s) {
+    k_lift<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(Z, ldz, n, ell, ell_ptr, y, coef);
+}
+
+}  // namespace mqh

@@ -1,0 +1,69 @@
+// kernels.hpp -- host-side launchers of the gfx950 kernels (one stream each;
+// every launch is asynchronous).  Shapes and layouts are documented at the
+// kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace mqh {
+
+constexpr int kMaxEll = 1024;   // largest projected problem (Golub-Kahan steps)
+constexpr int kMaxGrid = 4096;  // largest lambda grid
+
+// Result of the parameter choice, device-resident.
+struct ParamOut {
+    double lambda;
+    double crit;
+    double rho;
+    double eta;
+    int32_t k;
+    uint32_t flags;  // 2 = GCV minimum at a grid end, 4 = L-curve corner next to a grid end
+};
+
+// operator (op_kernels.hip)
+void launch_mf_rows(int prec, const void* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
+                    const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s);
+void launch_mf_cols(int prec, const void* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
+                    const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s);
+void launch_reduce_slices(const double* P, int64_t ldp, int S, int64_t n, const double* shift_ptr,
+                          double shift_val, const double* z, double* y, const GkbState* st, hipStream_t s);
+void launch_assemble(const double4* X, int64_t n, int64_t n_int, int64_t lda, const EntryConst& c, double* A,
+                     hipStream_t s);
+void launch_stored_rows(int rw, const double* A, int64_t lda, int64_t n, const double* x, const double* shift_ptr,
+                        double shift_val, const double* z, double* y, const GkbState* st, hipStream_t s);
+void launch_stored_cols(const double* A, int64_t lda, int64_t n, const double* x, int64_t rows_per_tile, int tiles,
+                        double* P, int64_t ldp, const GkbState* st, hipStream_t s);
+void launch_gen_rows(int prec, const void* X, int64_t n, int64_t n_int, int64_t row0, int64_t count,
+                     const EntryConst& c, double* out, hipStream_t s);
+void launch_eval_partial(const double4* X, const double* coef, int64_t n, const double4* E, int64_t m, int S,
+                         int64_t slice_len, const EntryConst& c, double* P, int64_t ldp, hipStream_t s);
+
+// Golub-Kahan vectors (gkb_kernels.hip)
+void launch_init_state(GkbState* st, int32_t ell, double* alpha, double* beta, hipStream_t s);
+void launch_fill(double* x, int64_t n, double v, hipStream_t s);
+int sumsq_blocks(int64_t n);
+void launch_sumsq_partial(const double* x, int64_t n, double* partial, int nb, const GkbState* st, hipStream_t s);
+void launch_norm_finalize(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
+                          double* beta, GkbState* st, hipStream_t s);
+void launch_scale(const double* x, int64_t n, const double* div, double* dst, const GkbState* st, hipStream_t s);
+int gemvt_blocks(int64_t n);
+void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
+                  const GkbState* st, hipStream_t s);
+int update_blocks(int64_t n);
+void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
+                   double* sumsq_partial, const GkbState* st, hipStream_t s);
+void launch_lift(const double* Z, int64_t ldz, int64_t n, int32_t ell, const int32_t* ell_ptr, const double* y,
+                 double* coef, hipStream_t s);
+
+// projected problem (proj_kernels.hip)
+void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* Vw,
+                       int64_t ldw, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
+                       hipStream_t s);
+void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,
+                         int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double* curve,
+                         ParamOut* out, hipStream_t s);
+void launch_proj_solution(const double* sv, const double* ft, const double* V, int64_t ldv, int32_t l,
+                          const int32_t* l_ptr, int32_t method, double lambda, int32_t k, const ParamOut* po,
+                          double* y, int32_t l_max, hipStream_t s);
+
+}  // namespace mqh

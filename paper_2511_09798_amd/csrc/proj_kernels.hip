@@ -1,0 +1,368 @@
+// proj_kernels.hip -- the projected problem on the device (one workgroup
+// each): SVD of C_l (Algorithm 2 step 2, Algorithm 4 step 2), parameter
+// choice by GCV / L-curve / projected TSVD-GCV (Section 3.2-3.3) and the
+// projected solution y (Algorithm 2 step 5, Algorithm 4 step 8, SVD form).
+#include <float.h>
+
+#include "bidiag_svd.hpp"
+#include "kernels.hpp"
+
+namespace mqh {
+
+constexpr int kProjThreads = 256;
+
+// ---------------------------------------------------------------------------
+// SVD of C_l.  Thread 0 runs the scalar bulge chase; after every sweep all
+// threads apply its right rotations to their rows of the work matrix Vw
+// (column-major, ld = ldw).  Outputs: sv (descending), ftil (l+1), V (ld = ldv).
+// l is taken from *l_ptr when given (steps kept by the Golub-Kahan run).
+// status[0] = 0 on success, -1 if the iteration limit was hit.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kProjThreads) void k_bidiag_svd(const double* __restrict__ alpha,
+                                                             const double* __restrict__ beta, int32_t l_arg,
+                                                             const int32_t* __restrict__ l_ptr,
+                                                             double* __restrict__ Vw, int64_t ldw,
+                                                             double* __restrict__ sv, double* __restrict__ ftil,
+                                                             double* __restrict__ V, int64_t ldv,
+                                                             int32_t* __restrict__ status) {
+    __shared__ double d[kMaxEll], e[kMaxEll], g[kMaxEll], rc[kMaxEll], rs[kMaxEll];
+    __shared__ int rank[kMaxEll];
+    __shared__ int s_ll, s_m, s_res;
+    const int tid = threadIdx.x;
+    const int l = l_ptr != nullptr ? *l_ptr : l_arg;
+    if (l <= 0) {
+        if (tid == 0) {
+            if (status) status[0] = 0;
+            ftil[0] = beta[0];
+        }
+        return;
+    }
+    for (int64_t idx = tid; idx < (int64_t)l * l; idx += kProjThreads) {
+        const int64_t col = idx / l, row = idx % l;
+        Vw[col * ldw + row] = (col == row) ? 1.0 : 0.0;
+    }
+    if (tid == 0) {
+        for (int i = 0; i < l; ++i) e[i] = 0.0;
+        ftil[l] = bsvd::reduce_lower(alpha, beta, l, d, e, g);
+    }
+    __syncthreads();
+    bsvd::Driver dv;
+    if (tid == 0) bsvd::driver_init(dv, l);
+    for (;;) {
+        if (tid == 0) {
+            int ll = 0, m = 0;
+            s_res = bsvd::driver_step(dv, d, e, g, rc, rs, &ll, &m);
+            s_ll = ll;
+            s_m = m;
+        }
+        __syncthreads();
+        const int res = s_res;
+        if (res != 1) break;
+        const int ll = s_ll, m = s_m;
+        for (int row = tid; row < l; row += kProjThreads) bsvd::apply_row(Vw, ldw, row, ll, m, rc, rs);
+        __syncthreads();
+    }
+    if (tid == 0 && status != nullptr) status[0] = s_res == 0 ? 0 : -1;
+    // order descending: rank of |d_i| among all (ties by index), one i per thread
+    for (int i = tid; i < l; i += kProjThreads) {
+        const double si = fabs(d[i]);
+        int rk = 0;
+        for (int j = 0; j < l; ++j) {
+            const double sj = fabs(d[j]);
+            rk += (sj > si || (sj == si && j < i)) ? 1 : 0;
+        }
+        rank[i] = rk;
+    }
+    __syncthreads();
+    for (int i = tid; i < l; i += kProjThreads) {
+        sv[rank[i]] = fabs(d[i]);
+        ftil[rank[i]] = g[i];
+    }
+    for (int64_t idx = tid; idx < (int64_t)l * l; idx += kProjThreads) {
+        const int64_t i = idx / l, row = idx % l;
+        const double sg = d[i] < 0.0 ? -1.0 : 1.0;
+        V[(int64_t)rank[i] * ldv + row] = sg * Vw[i * ldw + row];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Parameter choice
+// ---------------------------------------------------------------------------
+
+// GCV numerator and trace sum for one lambda, evaluated by one thread.
+__device__ inline void gcv_terms(const double* sv, const double* ft, int l, double lam, double& num, double& tr) {
+    const double l2 = lam * lam;
+    double a = 0.0, t = 0.0;
+    for (int i = 0; i < l; ++i) {
+        const double s2 = sv[i] * sv[i];
+        const double den = s2 + l2;
+        const double psi = l2 / den;
+        const double x = psi * ft[i];
+        a = fma(x, x, a);
+        t += s2 / den;
+    }
+    num = fma(ft[l], ft[l], a);
+    tr = t;
+}
+
+__device__ inline double gcv_value(const double* sv, const double* ft, int l, double lam) {
+    double num, tr;
+    gcv_terms(sv, ft, l, lam, num, tr);
+    const double den = (double)(l + 1) - tr;
+    return num / (den * den);
+}
+
+// Signed curvature of (log rho, log eta) in t = log lambda (analytic derivatives,
+// d phi_i / dt = -2 phi_i psi_i).
+__device__ inline double lcurve_kappa(const double* sv, const double* ft, int l, double lam) {
+    const double l2 = lam * lam;
+    double R = ft[l] * ft[l], R1 = 0.0, R2 = 0.0, E = 0.0, E1 = 0.0, E2 = 0.0;
+    for (int i = 0; i < l; ++i) {
+        const double s2 = sv[i] * sv[i];
+        const double den = s2 + l2;
+        const double ph = s2 / den, ps = l2 / den;
+        const double f2 = ft[i] * ft[i];
+        const double g2 = f2 / s2;
+        R += ps * ps * f2;
+        R1 += 4.0 * ph * ps * ps * f2;
+        R2 += 8.0 * f2 * ph * ps * ps * (2.0 * ph - ps);
+        E += ph * ph * g2;
+        E1 += -4.0 * ph * ph * ps * g2;
+        E2 += 8.0 * g2 * ph * ph * ps * (2.0 * ps - ph);
+    }
+    const double x1 = R1 / (2.0 * R), x2 = (R2 * R - R1 * R1) / (2.0 * R * R);
+    const double y1 = E1 / (2.0 * E), y2 = (E2 * E - E1 * E1) / (2.0 * E * E);
+    const double q = x1 * x1 + y1 * y1;
+    return (x1 * y2 - x2 * y1) / (q * sqrt(q));
+}
+
+// Block-parallel GCV for the refinement loop.
+__device__ inline double gcv_block(const double* sv, const double* ft, int l, double lam, double* lds) {
+    const double l2 = lam * lam;
+    double a = 0.0, t = 0.0;
+    for (int i = threadIdx.x; i < l; i += kProjThreads) {
+        const double s2 = sv[i] * sv[i];
+        const double den = s2 + l2;
+        const double x = (l2 / den) * ft[i];
+        a = fma(x, x, a);
+        t += s2 / den;
+    }
+    a = block_sum<kProjThreads>(a, lds);
+    t = block_sum<kProjThreads>(t, lds);
+    const double num = fma(ft[l], ft[l], a);
+    const double den = (double)(l + 1) - t;
+    return num / (den * den);
+}
+
+__global__ __launch_bounds__(kProjThreads) void k_param_choice(const double* __restrict__ sv,
+                                                               const double* __restrict__ ft, int32_t l_arg,
+                                                               const int32_t* __restrict__ l_ptr, int32_t method,
+                                                               int32_t rule, int32_t J, double lambda_fixed,
+                                                               int32_t k_fixed, double* __restrict__ curve,
+                                                               ParamOut* __restrict__ out) {
+    __shared__ double vals[kMaxGrid];
+    __shared__ double lds[kProjThreads / kWave];
+    __shared__ double s_lo, s_hi;
+    const int tid = threadIdx.x;
+    const int l = l_ptr != nullptr ? *l_ptr : l_arg;
+    if (l <= 0) {
+        if (tid == 0) {
+            out->lambda = 0.0;
+            out->k = 0;
+            out->crit = 0.0;
+            out->flags = 0;
+            out->rho = ft[0] >= 0.0 ? ft[0] : -ft[0];
+            out->eta = 0.0;
+        }
+        return;
+    }
+    if (method == 0) {  // Ine-TSVD
+        if (tid == 0) {
+            int k;
+            const int kmax = l / 2 > 1 ? l / 2 : 1;
+            // suffix sums r_k = sum_{i >= k} ft_i^2 over 0-based i in [k, l]
+            double best = 0.0;
+            int bestk = 1;
+            if (rule == 2) {
+                k = k_fixed < 1 ? 1 : (k_fixed > l ? l : k_fixed);
+            } else {
+                double tail = ft[l] * ft[l];
+                for (int i = l - 1; i >= kmax; --i) tail = fma(ft[i], ft[i], tail);
+                // tail now = sum_{i >= kmax} ; walk k downwards to 1
+                double gk = tail / ((double)(l + 1 - kmax) * (double)(l + 1 - kmax));
+                best = gk;
+                bestk = kmax;
+                for (int kk = kmax - 1; kk >= 1; --kk) {
+                    tail = fma(ft[kk], ft[kk], tail);
+                    gk = tail / ((double)(l + 1 - kk) * (double)(l + 1 - kk));
+                    if (gk <= best) {  // ties -> smaller k
+                        best = gk;
+                        bestk = kk;
+                    }
+                }
+                k = bestk;
+            }
+            double res = ft[l] * ft[l], nrm = 0.0;
+            for (int i = k; i < l; ++i) res = fma(ft[i], ft[i], res);
+            for (int i = 0; i < k; ++i) {
+                const double q = ft[i] / sv[i];
+                nrm = fma(q, q, nrm);
+            }
+            out->lambda = 0.0;
+            out->k = k;
+            out->crit = res / ((double)(l + 1 - k) * (double)(l + 1 - k));
+            out->flags = 0;
+            out->rho = sqrt(res);
+            out->eta = sqrt(nrm);
+        }
+        return;
+    }
+    // HKT: lambda
+    double lam = lambda_fixed, crit = 0.0;
+    uint32_t flags = 0;
+    if (rule != 2) {
+        if (tid == 0) {
+            const double hi = sv[0];
+            double lo = sv[l - 1] > 16.0 * DBL_EPSILON * hi ? sv[l - 1] : 16.0 * DBL_EPSILON * hi;
+            if (!(lo < hi)) lo = 16.0 * DBL_EPSILON * hi;
+            s_lo = log(lo);
+            s_hi = log(hi);
+        }
+        __syncthreads();
+        const double t0 = s_lo, t1 = s_hi;
+        const double step = (t1 - t0) / (double)(J - 1);
+        for (int j = tid; j < J; j += kProjThreads) {
+            const double lj = j == J - 1 ? exp(t1) : exp(t0 + step * (double)j);
+            const double v = rule == 0 ? gcv_value(sv, ft, l, lj) : lcurve_kappa(sv, ft, l, lj);
+            vals[j] = v;
+            if (curve != nullptr) curve[j] = v;
+        }
+        __syncthreads();
+        __shared__ int s_k;
+        if (tid == 0) {
+            int kb;
+            if (rule == 0) {  // argmin, ties -> larger lambda
+                kb = 0;
+                for (int j = 1; j < J; ++j)
+                    if (vals[j] <= vals[kb]) kb = j;
+                if (kb == 0 || kb == J - 1) flags |= 2u;
+            } else {  // argmax over inner points, ties -> larger lambda
+                kb = 1;
+                for (int j = 2; j < J - 1; ++j)
+                    if (vals[j] >= vals[kb]) kb = j;
+                if (kb == 1 || kb == J - 2) flags |= 4u;
+            }
+            s_k = kb;
+        }
+        __syncthreads();
+        const int kb = s_k;
+        const double tk = kb == J - 1 ? t1 : t0 + step * (double)kb;
+        lam = exp(tk);
+        crit = vals[kb];
+        if (rule == 0 && kb > 0 && kb < J - 1) {
+            // golden-section search of log(lambda) on the two cells around the grid minimum
+            const double gr = 0.6180339887498949;  // (sqrt(5) - 1) / 2
+            double a = t0 + step * (double)(kb - 1);
+            double b = kb + 1 == J - 1 ? t1 : t0 + step * (double)(kb + 1);
+            double c = b - gr * (b - a), dd = a + gr * (b - a);
+            double fc = gcv_block(sv, ft, l, exp(c), lds), fd = gcv_block(sv, ft, l, exp(dd), lds);
+            int it = 0;
+            while (fabs(b - a) > 1e-10 && it < 200) {
+                if (fc < fd) {
+                    b = dd;
+                    dd = c;
+                    fd = fc;
+                    c = b - gr * (b - a);
+                    fc = gcv_block(sv, ft, l, exp(c), lds);
+                } else {
+                    a = c;
+                    c = dd;
+                    fc = fd;
+                    dd = a + gr * (b - a);
+                    fd = gcv_block(sv, ft, l, exp(dd), lds);
+                }
+                ++it;
+            }
+            const double lr = exp(0.5 * (a + b));
+            const double gv = gcv_block(sv, ft, l, lr, lds);
+            if (!(gv > crit)) {
+                lam = lr;
+                crit = gv;
+            }
+        }
+    }
+    // rho, eta at the chosen lambda
+    {
+        const double l2 = lam * lam;
+        double r = 0.0, e = 0.0;
+        for (int i = tid; i < l; i += kProjThreads) {
+            const double s2 = sv[i] * sv[i];
+            const double den = s2 + l2;
+            const double x = (l2 / den) * ft[i];
+            const double q = (sv[i] / den) * ft[i];
+            r = fma(x, x, r);
+            e = fma(q, q, e);
+        }
+        r = block_sum<kProjThreads>(r, lds);
+        e = block_sum<kProjThreads>(e, lds);
+        if (tid == 0) {
+            out->lambda = lam;
+            out->k = 0;
+            out->crit = rule == 2 ? gcv_value(sv, ft, l, lam) : crit;
+            out->flags = flags;
+            out->rho = sqrt(fma(ft[l], ft[l], r));
+            out->eta = sqrt(e);
+        }
+    }
+}
+
+// y_r = sum_i V[i][r] w_i with w_i = s_i/(s_i^2+lambda^2) f~_i (HKT) or
+// f~_i/s_i for i < k (Ine-TSVD); lambda and k from *po when given.
+__global__ __launch_bounds__(kBlock) void k_proj_solution(const double* __restrict__ sv,
+                                                          const double* __restrict__ ft,
+                                                          const double* __restrict__ V, int64_t ldv, int32_t l_arg,
+                                                          const int32_t* __restrict__ l_ptr, int32_t method,
+                                                          double lambda, int32_t k, const ParamOut* __restrict__ po,
+                                                          double* __restrict__ y) {
+    const int l = l_ptr != nullptr ? *l_ptr : l_arg;
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= l) return;
+    const double lam = po != nullptr ? po->lambda : lambda;
+    const int kk = po != nullptr ? po->k : k;
+    const double l2 = lam * lam;
+    double s = 0.0;
+    if (method == 1) {
+        for (int i = 0; i < l; ++i) {
+            const double w = sv[i] / (sv[i] * sv[i] + l2) * ft[i];
+            s = fma(V[(int64_t)i * ldv + r], w, s);
+        }
+    } else {
+        for (int i = 0; i < kk && i < l; ++i) s = fma(V[(int64_t)i * ldv + r], ft[i] / sv[i], s);
+    }
+    y[r] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* Vw,
+                       int64_t ldw, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
+                       hipStream_t s) {
+    k_bidiag_svd<<<1, kProjThreads, 0, s>>>(alpha, beta, l, l_ptr, Vw, ldw, sv, ftil, V, ldv, status);
+}
+
+void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,
+                         int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double* curve,
+                         ParamOut* out, hipStream_t s) {
+    k_param_choice<<<1, kProjThreads, 0, s>>>(sv, ft, l, l_ptr, method, rule, J, lambda_fixed, k_fixed, curve, out);
+}
+
+void launch_proj_solution(const double* sv, const double* ft, const double* V, int64_t ldv, int32_t l,
+                          const int32_t* l_ptr, int32_t method, double lambda, int32_t k, const ParamOut* po,
+                          double* y, int32_t l_max, hipStream_t s) {
+    k_proj_solution<<<(l_max + kBlock - 1) / kBlock, kBlock, 0, s>>>(sv, ft, V, ldv, l, l_ptr, method, lambda, k,
+                                                                     po, y);
+}
+
+}  // namespace mqh

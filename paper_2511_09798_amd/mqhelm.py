@@ -1,0 +1,371 @@
+"""Python binding of libmqhelm.so (include/mqhelm.h): argument marshalling only.
+
+Every array argument is either a C-contiguous float64 numpy array (host
+pointer) or a contiguous float64 torch tensor on the GPU (device pointer);
+one call never mixes the two kinds.  Every computation runs in the HIP
+library; importing this module fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Any, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmqhelm.so")
+
+# constants (mirror include/mqhelm.h)
+MQH_OK = 0
+MQH_EINVAL = -1
+MQH_ENOMEM = -2
+MQH_EDEVICE = -3
+MQH_WBREAKDOWN = 1
+MQH_WEDGE = 2
+MQH_OP_STORED_FP64 = 0
+MQH_OP_MATFREE_FP64 = 1
+MQH_OP_MATFREE_FP32 = 2
+MQH_METHOD_INE_TSVD = 0
+MQH_METHOD_HKT = 1
+MQH_RULE_GCV = 0
+MQH_RULE_LCURVE = 1
+MQH_RULE_FIXED = 2
+MQH_FLAG_DEVICE_PTRS = 1
+MQH_FLAG_TIME_PRODUCTS = 2
+MQH_INFO_BREAKDOWN = 1
+MQH_INFO_GCV_AT_EDGE = 2
+MQH_INFO_LCURVE_AT_EDGE = 4
+MQH_MAX_ELL = 1024
+
+OP_MODES = {"stored_fp64": MQH_OP_STORED_FP64, "matfree_fp64": MQH_OP_MATFREE_FP64,
+            "matfree_fp32": MQH_OP_MATFREE_FP32}
+
+
+class MQHError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: status {code} ({msg})")
+        self.code = code
+
+
+class mqh_solve_opts(ctypes.Structure):
+    _fields_ = [("ell", ctypes.c_int32), ("reorth", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("rule", ctypes.c_int32), ("k_trunc", ctypes.c_int32), ("n_grid", ctypes.c_int32),
+                ("lambda_fixed", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class mqh_solve_info(ctypes.Structure):
+    _fields_ = [("ell_done", ctypes.c_int32), ("k_chosen", ctypes.c_int32), ("lambda_chosen", ctypes.c_double),
+                ("crit", ctypes.c_double), ("resid_norm", ctypes.c_double), ("sol_norm", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("t_ms", ctypes.c_double * 8)]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_d = ctypes.c_double
+
+_SIGNATURES = {
+    "mqh_version": (ctypes.c_int, []),
+    "mqh_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "mqh_last_error": (ctypes.c_char_p, []),
+    "mqh_problem_create": (ctypes.c_int, [_vp, _i64, _vp, _i64, _d, _d, _i32, _vp, _u32, ctypes.POINTER(_vp)]),
+    "mqh_problem_destroy": (ctypes.c_int, [_vp]),
+    "mqh_problem_size": (_i64, [_vp]),
+    "mqh_apply": (ctypes.c_int, [_vp, _i32, _vp, _d, _vp, _vp, _u32]),
+    "mqh_matrix_rows": (ctypes.c_int, [_vp, _i64, _i64, _vp, _u32]),
+    "mqh_gkb": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), _u32]),
+    "mqh_proj_svd": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _u32]),
+    "mqh_param_choice": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _d, _i32, ctypes.POINTER(_d),
+                                        ctypes.POINTER(_i32), ctypes.POINTER(_d), ctypes.POINTER(_u32), _vp, _vp,
+                                        _u32]),
+    "mqh_proj_solution": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _d, _i32, _vp, _vp, _u32]),
+    "mqh_lift": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _u32]),
+    "mqh_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(mqh_solve_opts), _vp, _vp, _vp, _vp,
+                                 ctypes.POINTER(mqh_solve_info)]),
+    "mqh_eval": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _u32]),
+}
+
+
+def _load():
+    # One HIP runtime per process: torch ships its own libamdhip64 (loaded
+    # under the unversioned name), so when torch is importable it is loaded
+    # first and this library binds to that runtime (its soname matches);
+    # torch streams and device pointers are then valid in every call.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_09798_amd.build` "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def _check(code: int, where: str, warn_ok: bool = True) -> int:
+    if code < 0 or (code > 0 and not warn_ok):
+        raise MQHError(code, where, lib.mqh_last_error().decode() or lib.mqh_status_str(code).decode())
+    return code
+
+
+# --------------------------------------------------------------------------
+# array marshalling
+# --------------------------------------------------------------------------
+
+def _is_torch(a: Any) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a: Any):
+    """(pointer, is_device) of a float64 contiguous array; None -> (None, None)."""
+    if a is None:
+        return None, None
+    if _is_torch(a):
+        if a.dtype.is_floating_point and a.element_size() != 8:
+            raise TypeError("torch tensors must be float64")
+        if not a.is_contiguous():
+            raise TypeError("torch tensors must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), bool(a.is_cuda)
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise TypeError("numpy arrays must be C-contiguous float64")
+    return ctypes.c_void_p(a.ctypes.data), False
+
+
+def _flags(*arrays) -> int:
+    kinds = {d for (_, d) in (_ptr(a) for a in arrays if a is not None)}
+    if len(kinds) > 1:
+        raise TypeError("a call must use only host (numpy) or only device (torch) arrays")
+    return MQH_FLAG_DEVICE_PTRS if kinds == {True} else 0
+
+
+def _empty_like_kind(ref: Any, shape) -> Any:
+    if ref is not None and _is_torch(ref) and ref.is_cuda:
+        import torch
+
+        return torch.empty(shape, dtype=torch.float64, device=ref.device)
+    return np.empty(shape, dtype=np.float64)
+
+
+def _zeros_like_kind(ref: Any, shape) -> Any:
+    if ref is not None and _is_torch(ref) and ref.is_cuda:
+        import torch
+
+        return torch.zeros(shape, dtype=torch.float64, device=ref.device)
+    return np.zeros(shape, dtype=np.float64)
+
+
+def _stream_of(stream: Any) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+# --------------------------------------------------------------------------
+# C-ABI names
+# --------------------------------------------------------------------------
+
+def mqh_version() -> int:
+    return int(lib.mqh_version())
+
+
+def mqh_status_str(code: int) -> str:
+    return lib.mqh_status_str(code).decode()
+
+
+def mqh_last_error() -> str:
+    return lib.mqh_last_error().decode()
+
+
+def mqh_problem_create(x_int, x_bnd, kappa: float, eps: float, op_mode: int, stream=None) -> ctypes.c_void_p:
+    fl = _flags(x_int, x_bnd)
+    pi, _ = _ptr(x_int)
+    pb, _ = _ptr(x_bnd)
+    n_int = 0 if x_int is None else int(x_int.shape[0])
+    n_bnd = 0 if x_bnd is None else int(x_bnd.shape[0])
+    h = ctypes.c_void_p()
+    _check(lib.mqh_problem_create(pi, n_int, pb, n_bnd, float(kappa), float(eps), int(op_mode), _stream_of(stream),
+                                  fl, ctypes.byref(h)), "mqh_problem_create")
+    return h
+
+
+def mqh_problem_destroy(h) -> None:
+    lib.mqh_problem_destroy(h)
+
+
+def mqh_apply(h, trans: int, x, shift: float = 0.0, z=None, y=None):
+    fl = _flags(x, z, y)
+    if y is None:
+        y = _empty_like_kind(x, (x.shape[0],))
+    _check(lib.mqh_apply(h, int(trans), _ptr(x)[0], float(shift), _ptr(z)[0], _ptr(y)[0], fl), "mqh_apply")
+    return y
+
+
+def mqh_matrix_rows(h, row0: int, count: int, out=None, n: Optional[int] = None):
+    if out is None:
+        out = np.empty((count, int(lib.mqh_problem_size(h))), dtype=np.float64)
+    fl = _flags(out)
+    _check(lib.mqh_matrix_rows(h, int(row0), int(count), _ptr(out)[0], fl), "mqh_matrix_rows")
+    return out
+
+
+def mqh_gkb(h, f, ell: int, reorth: int = 1, want_bases: bool = True):
+    n = int(lib.mqh_problem_size(h))
+    W = _empty_like_kind(f, (ell + 1, n)) if want_bases else None  # row k = column k of the n x (ell+1) basis
+    Z = _empty_like_kind(f, (ell, n)) if want_bases else None
+    al = _empty_like_kind(f, (ell,))
+    be = _empty_like_kind(f, (ell + 1,))
+    fl = _flags(f, W, Z, al, be)
+    done = _i32(0)
+    st = _check(lib.mqh_gkb(h, _ptr(f)[0], int(ell), int(reorth), _ptr(W)[0], _ptr(Z)[0], _ptr(al)[0], _ptr(be)[0],
+                            ctypes.byref(done), fl), "mqh_gkb")
+    return dict(W=W, Z=Z, alpha=al, beta=be, ell_done=int(done.value), status=st)
+
+
+def mqh_proj_svd(alpha, beta, want_v: bool = True, stream=None):
+    ell = int(alpha.shape[0])
+    sv = _empty_like_kind(alpha, (ell,))
+    ft = _empty_like_kind(alpha, (ell + 1,))
+    V = _empty_like_kind(alpha, (ell, ell)) if want_v else None  # row i = v~_i
+    fl = _flags(alpha, beta, sv, ft, V)
+    _check(lib.mqh_proj_svd(_ptr(alpha)[0], _ptr(beta)[0], ell, _ptr(sv)[0], _ptr(ft)[0], _ptr(V)[0],
+                            _stream_of(stream), fl), "mqh_proj_svd")
+    return sv, ft, V
+
+
+def mqh_param_choice(sv, ftil, method: int, rule: int, n_grid: int = 200, lambda_fixed: float = 0.0,
+                     k_trunc: int = 0, want_curve: bool = False, stream=None):
+    ell = int(sv.shape[0])
+    J = 200 if n_grid == 0 else n_grid
+    curve = _empty_like_kind(sv, (J,)) if want_curve else None
+    fl = _flags(sv, ftil, curve)
+    lam, k, crit, inf = _d(0), _i32(0), _d(0), _u32(0)
+    st = _check(lib.mqh_param_choice(_ptr(sv)[0], _ptr(ftil)[0], ell, int(method), int(rule), int(n_grid),
+                                     float(lambda_fixed), int(k_trunc), ctypes.byref(lam), ctypes.byref(k),
+                                     ctypes.byref(crit), ctypes.byref(inf), _ptr(curve)[0], _stream_of(stream), fl),
+                "mqh_param_choice")
+    return dict(lambda_=lam.value, k=int(k.value), crit=crit.value, flags=int(inf.value), curve=curve, status=st)
+
+
+def mqh_proj_solution(sv, ftil, V, method: int, lam: float = 0.0, k: int = 0, stream=None):
+    ell = int(sv.shape[0])
+    y = _empty_like_kind(sv, (ell,))
+    fl = _flags(sv, ftil, V, y)
+    _check(lib.mqh_proj_solution(_ptr(sv)[0], _ptr(ftil)[0], _ptr(V)[0], ell, int(method), float(lam), int(k),
+                                 _ptr(y)[0], _stream_of(stream), fl), "mqh_proj_solution")
+    return y
+
+
+def mqh_lift(Z, y, stream=None):
+    """coef = Z y with Z given as an (ell, n) array whose row k is column k."""
+    ell, n = int(Z.shape[0]), int(Z.shape[1])
+    coef = _empty_like_kind(Z, (n,))
+    fl = _flags(Z, y, coef)
+    _check(lib.mqh_lift(_ptr(Z)[0], n, ell, _ptr(y)[0], _ptr(coef)[0], _stream_of(stream), fl), "mqh_lift")
+    return coef
+
+
+@dataclasses.dataclass
+class SolveOutput:
+    coef: Any
+    alpha: Any
+    beta: Any
+    sv: Any
+    status: int
+    ell_done: int
+    k: int
+    lam: float
+    crit: float
+    resid_norm: float
+    sol_norm: float
+    flags: int
+    t_ms: list
+
+
+def mqh_solve(h, f_int, g_bnd, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQH_RULE_GCV,
+              k_trunc: int = 0, lambda_fixed: float = 0.0, n_grid: int = 200, reorth: int = 1,
+              time_products: bool = False, coef=None) -> SolveOutput:
+    n = int(lib.mqh_problem_size(h))
+    ref = f_int if f_int is not None else g_bnd
+    if coef is None:
+        coef = _empty_like_kind(ref, (n,))
+    al = _zeros_like_kind(ref, (ell,))
+    be = _zeros_like_kind(ref, (ell + 1,))
+    sv = _zeros_like_kind(ref, (ell,))
+    fl = _flags(f_int, g_bnd, coef, al, be, sv)
+    opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=int(method), rule=int(rule),
+                          k_trunc=int(k_trunc), n_grid=int(n_grid), lambda_fixed=float(lambda_fixed),
+                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), reserved=0)
+    info = mqh_solve_info()
+    st = _check(lib.mqh_solve(h, _ptr(f_int)[0], _ptr(g_bnd)[0], ctypes.byref(opts), _ptr(coef)[0], _ptr(al)[0],
+                              _ptr(be)[0], _ptr(sv)[0], ctypes.byref(info)), "mqh_solve")
+    return SolveOutput(coef, al, be, sv, st, info.ell_done, info.k_chosen, info.lambda_chosen, info.crit,
+                       info.resid_norm, info.sol_norm, info.flags, list(info.t_ms))
+
+
+def mqh_eval(h, coef, x_eval, u=None):
+    m = int(x_eval.shape[0])
+    if u is None:
+        u = _empty_like_kind(coef, (m,))
+    fl = _flags(coef, x_eval, u)
+    _check(lib.mqh_eval(h, _ptr(coef)[0], _ptr(x_eval)[0], m, _ptr(u)[0], fl), "mqh_eval")
+    return u
+
+
+# --------------------------------------------------------------------------
+# Convenience wrapper
+# --------------------------------------------------------------------------
+
+class Problem:
+    """Owns one mqh_problem handle (nodes, kappa, eps, operator mode, stream)."""
+
+    def __init__(self, x_int, x_bnd, kappa: float, eps: float, op_mode="matfree_fp64", stream=None):
+        mode = OP_MODES[op_mode] if isinstance(op_mode, str) else int(op_mode)
+        self.mode = mode
+        self.n_int = 0 if x_int is None else int(x_int.shape[0])
+        self.n_bnd = 0 if x_bnd is None else int(x_bnd.shape[0])
+        self.n = self.n_int + self.n_bnd
+        self.h = mqh_problem_create(x_int, x_bnd, kappa, eps, mode, stream)
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            mqh_problem_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def apply(self, x, trans=False, shift=0.0, z=None, y=None):
+        return mqh_apply(self.h, int(bool(trans)), x, shift, z, y)
+
+    def matrix_rows(self, row0, count, out=None):
+        return mqh_matrix_rows(self.h, row0, count, out)
+
+    def gkb(self, f, ell, reorth=True, want_bases=True):
+        return mqh_gkb(self.h, f, ell, int(bool(reorth)), want_bases)
+
+    def solve(self, f_int, g_bnd, ell, **kw) -> SolveOutput:
+        return mqh_solve(self.h, f_int, g_bnd, ell, **kw)
+
+    def eval(self, coef, x_eval, u=None):
+        return mqh_eval(self.h, coef, x_eval, u)

@@ -1,0 +1,394 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Rows of the hot path covered here: matrix entries (assembly / generation),
+the products A x and A^T x in all three operator modes, the Golub-Kahan
+bidiagonalisation with full reorthogonalisation, the projected SVD, the
+parameter choice, the projected solution, the lift, the evaluation and the
+whole solve, at small sizes (several tiles plus a ragged tail) element by
+element.
+
+Tolerances (derivations in the design notes):
+* FP64 entries: |dA_ij| <= 4e-15 |A_ij| (both sides evaluate the same closed
+  form with a few roundings each);
+* FP64 products: |dy_i| <= 1e-13 (|A||x|)_i, the natural error scale of a
+  length-n dot product in FP64 with different summation orders;
+* FP32-evaluated entries: |dA_ij| <= 4e-6 |A_ij| (nodes rounded to FP32,
+  one FP32 rsqrt and a few FP32 operations); products |dy_i| <= 4e-6 (|A||x|)_i;
+* leading Ritz values (top 10): relative 1e-12 (spec bar); all Ritz
+  values: absolute 64 l eps s_1 (dense SVD accuracy of the oracle);
+* solution u at the evaluation points: relative 1e-8 at the oracle's lambda;
+  coefficients: relative 1e-6.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2511_09798_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mq():
+    from paper_2511_09798_amd import mqhelm
+
+    return mqhelm
+
+
+def _problem(mq, p, mode):
+    say("create", p.name, "mode", mode, "n", p.n)
+    return mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, mode)
+
+
+SMALL = [
+    ("cube_ragged", lambda: I.cube_scaled(333, 190, kappa=6.0, eps=2.0, ell=40)),
+    ("sphere_ragged", lambda: I.sphere_scaled(517, 260, kappa=9.0, eps=3.0, ell=40)),
+]
+
+
+# ---------------------------------------------------------------------------
+# entries
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,make", SMALL)
+@pytest.mark.parametrize("mode", ["stored_fp64", "matfree_fp64", "matfree_fp32"])
+def test_entries(mq, orc, name, make, mode):
+    p = make()
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    with _problem(mq, p, mode) as pr:
+        say("matrix_rows", name, mode)
+        R = pr.matrix_rows(0, p.n)
+    tol = 4e-6 if mode == "matfree_fp32" else 4e-15
+    assert np.all(np.abs(R - A) <= tol * np.abs(A)), float(np.max(np.abs(R - A) / np.abs(A)))
+
+
+# ---------------------------------------------------------------------------
+# products
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,make", SMALL + [("cube_n1800", I.cube_small)])
+@pytest.mark.parametrize("mode", ["stored_fp64", "matfree_fp64", "matfree_fp32"])
+def test_products(mq, orc, name, make, mode):
+    p = make()
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    x = I.random_vector(p.n, 11)
+    z = I.random_vector(p.n, 12)
+    tol = 4e-6 if mode == "matfree_fp32" else 1e-13
+    with _problem(mq, p, mode) as pr:
+        for trans in (False, True):
+            say("apply", name, mode, "trans", trans)
+            y = pr.apply(x, trans=trans)
+            ref = orc.apply(A, p.nodes, p.n_int, p.kappa, p.eps, x, trans=trans)
+            scale = (np.abs(A.T) if trans else np.abs(A)) @ np.abs(x)
+            assert np.all(np.abs(y - ref) <= tol * scale), float(np.max(np.abs(y - ref) / scale))
+            say("apply shifted", name, mode, "trans", trans)
+            y2 = pr.apply(x, trans=trans, shift=0.75, z=z)
+            scale2 = scale + 0.75 * np.abs(z)
+            assert np.all(np.abs(y2 - (ref - 0.75 * z)) <= tol * scale2)
+
+
+def test_products_device_pointers(mq, orc):
+    import torch
+
+    p = I.cube_scaled(300, 200, kappa=4.0, eps=2.0, ell=10)
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    x = I.random_vector(p.n, 5)
+    with _problem(mq, p, "matfree_fp64") as pr:
+        say("apply device pointers")
+        xd = torch.from_numpy(x).cuda()
+        yd = pr.apply(xd, trans=True)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy()
+    ref = orc.apply(A, p.nodes, p.n_int, p.kappa, p.eps, x, trans=True)
+    assert np.all(np.abs(y - ref) <= 1e-13 * (np.abs(A.T) @ np.abs(x)))
+
+
+# ---------------------------------------------------------------------------
+# Golub-Kahan bidiagonalisation
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["stored_fp64", "matfree_fp64"])
+def test_gkb_against_oracle(mq, orc, mode):
+    p = I.cube_small()
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    g = orc.gkb(A, p.nodes, p.n_int, p.kappa, p.eps, p.rhs, p.ell)
+    with _problem(mq, p, mode) as pr:
+        say("gkb", mode)
+        r = pr.gkb(p.rhs, p.ell)
+    assert r["ell_done"] == g.ell == p.ell and r["status"] == 0
+    W, Z = r["W"].T, r["Z"].T
+    C = orc.bidiag_matrix(r["alpha"], r["beta"])
+    c2 = np.linalg.norm(C, 2)
+    # Krylov relations and orthonormality of the GPU bases
+    assert np.linalg.norm(A @ Z - W @ C) / c2 < 1e-12
+    assert np.max(np.abs(W.T @ W - np.eye(p.ell + 1))) < 1e-12
+    assert np.max(np.abs(Z.T @ Z - np.eye(p.ell))) < 1e-12
+    assert r["beta"][0] == pytest.approx(g.beta[0], rel=1e-14)
+    # leading Ritz values (top 10) and the first Krylov scalars
+    s_gpu = np.linalg.svd(C, compute_uv=False)
+    s_orc = np.linalg.svd(orc.bidiag_matrix(g.alpha, g.beta), compute_uv=False)
+    assert np.max(np.abs(s_gpu[:10] - s_orc[:10]) / s_orc[:10]) < 1e-12
+    assert np.max(np.abs(r["alpha"][:5] - g.alpha[:5]) / g.alpha[:5]) < 1e-12
+
+
+def test_gkb_fp32_entries_close_to_fp64(mq, orc):
+    p = I.cube_small()
+    g = orc.gkb(None, p.nodes, p.n_int, p.kappa, p.eps, p.rhs, 20)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("gkb fp32")
+        r = pr.gkb(p.rhs, 20)
+    s_gpu = np.linalg.svd(orc.bidiag_matrix(r["alpha"], r["beta"]), compute_uv=False)
+    s_orc = np.linalg.svd(orc.bidiag_matrix(g.alpha, g.beta), compute_uv=False)
+    assert np.max(np.abs(s_gpu[:5] - s_orc[:5]) / s_orc[:5]) < 1e-5
+    W, Z = r["W"].T, r["Z"].T
+    assert np.max(np.abs(W.T @ W - np.eye(21))) < 1e-12  # reorthogonalisation stays FP64
+
+
+def test_gkb_breakdown_full_space(mq, orc):
+    n = 16
+    X = I.random_nodes_cube(n, 116)
+    f = I.random_vector(n, 7)
+    say("gkb breakdown l = n")
+    with mq.Problem(X[:8], X[8:], 2.0, 6.0, "stored_fp64") as pr:
+        r = pr.gkb(f, n)
+    g = orc.gkb(None, X, 8, 2.0, 6.0, f, n)
+    assert r["ell_done"] == g.ell == n
+    assert r["status"] == mq.MQH_WBREAKDOWN and r["beta"][n] == 0.0
+    s_gpu = np.linalg.svd(orc.bidiag_matrix(r["alpha"], r["beta"]), compute_uv=False)
+    A = orc.assemble(X, 8, 2.0, 6.0)
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert np.max(np.abs(s_gpu - sv) / sv) < 1e-10
+
+
+def test_gkb_zero_rhs(mq):
+    X = I.random_nodes_cube(40, 3)
+    say("gkb zero rhs")
+    with mq.Problem(X[:20], X[20:], 2.0, 3.0, "matfree_fp64") as pr:
+        r = pr.gkb(np.zeros(40), 5)
+        assert r["ell_done"] == 0 and r["status"] == mq.MQH_WBREAKDOWN
+        out = pr.solve(np.zeros(20), np.zeros(20), 5)
+        assert out.status == mq.MQH_WBREAKDOWN and np.all(out.coef == 0.0)
+
+
+# ---------------------------------------------------------------------------
+# projected problem
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def proj_case(orc):
+    p = I.cube_scaled(400, 240, kappa=3.0, eps=0.7, ell=80)
+    g = orc.gkb(None, p.nodes, p.n_int, p.kappa, p.eps, p.rhs, p.ell)
+    s, ft, V = orc.proj_svd(g.alpha, g.beta)
+    return p, g, s, ft, V
+
+
+def test_proj_svd(mq, orc, proj_case):
+    p, g, s, ft, V = proj_case
+    say("proj_svd l =", g.ell)
+    sv, ftg, Vg = mq.mqh_proj_svd(g.alpha, g.beta)
+    Vg = Vg.T  # columns v~_i
+    assert np.max(np.abs(sv[:10] - s[:10]) / s[:10]) < 1e-12
+    assert np.max(np.abs(sv - s)) < 64 * g.ell * EPS * s[0]
+    assert abs(abs(ftg[-1]) - abs(ft[-1])) < 1e-12 * g.beta[0]
+    assert np.sum(ftg ** 2) == pytest.approx(g.beta[0] ** 2, rel=1e-13)
+    assert np.max(np.abs(Vg.T @ Vg - np.eye(g.ell))) < 1e-12
+    # sign-invariant comparison: projected Tikhonov solutions at a few lambdas
+    for lam in (s[0] * 1e-1, s[5], s[30], s[-1] * 10):
+        y = Vg @ (sv / (sv ** 2 + lam ** 2) * ftg[:-1])
+        yo = orc.y_tikhonov(s, ft, V, lam)
+        assert np.linalg.norm(y - yo) <= 1e-9 * np.linalg.norm(yo)
+
+
+@pytest.mark.parametrize("ell", [1, 2, 7])
+def test_proj_svd_small(mq, orc, ell):
+    rng = np.random.default_rng(ell)
+    a = rng.random(ell) + 0.2
+    b = np.concatenate([[1.5], rng.random(ell) + 0.2])
+    say("proj_svd small", ell)
+    sv, ftg, Vg = mq.mqh_proj_svd(a, b)
+    s, ft, V = orc.proj_svd(a, b)
+    assert np.max(np.abs(sv - s) / s) < 1e-13
+    assert np.max(np.abs(np.abs(ftg) - np.abs(ft))) < 1e-13
+
+
+def test_param_choice(mq, orc, proj_case):
+    p, g, s, ft, V = proj_case
+    say("param_choice gcv")
+    r = mq.mqh_param_choice(s, ft, mq.MQH_METHOD_HKT, mq.MQH_RULE_GCV, want_curve=True)
+    lam, gv, edge, grid, vals = orc.choose_lambda_gcv(s, ft, 200)
+    assert bool(r["flags"] & mq.MQH_INFO_GCV_AT_EDGE) == edge
+    np.testing.assert_allclose(r["curve"], vals, rtol=1e-11)
+    # the GCV minimiser is fixed only to ~sqrt(eps) by rounding (flat minimum)
+    assert r["lambda_"] == pytest.approx(lam, rel=1e-6)
+    assert r["crit"] == pytest.approx(gv, rel=1e-10)
+    say("param_choice lcurve")
+    r = mq.mqh_param_choice(s, ft, mq.MQH_METHOD_HKT, mq.MQH_RULE_LCURVE, want_curve=True)
+    lam, kap, edge, grid, kv = orc.choose_lambda_lcurve(s, ft, 200)
+    np.testing.assert_allclose(r["curve"], kv, rtol=1e-8, atol=1e-10 * np.max(np.abs(kv)))
+    assert r["lambda_"] == pytest.approx(lam, rel=1e-12)
+    say("param_choice tsvd")
+    r = mq.mqh_param_choice(s, ft, mq.MQH_METHOD_INE_TSVD, mq.MQH_RULE_GCV)
+    assert r["k"] == orc.choose_rank(s, ft)
+    r = mq.mqh_param_choice(s, ft, mq.MQH_METHOD_INE_TSVD, mq.MQH_RULE_FIXED, k_trunc=9)
+    assert r["k"] == 9
+
+
+def test_param_choice_gcv_closed_form(mq, orc):
+    s, ft, V = orc.proj_svd(np.array([3.0]), np.array([2.0, 1.0]))
+    say("param_choice l=1")
+    r = mq.mqh_param_choice(s, ft, mq.MQH_METHOD_HKT, mq.MQH_RULE_GCV)
+    assert r["lambda_"] == pytest.approx(math.sqrt(10.0 / 8.0), rel=1e-7)
+
+
+def test_proj_solution_and_lift(mq, orc, proj_case):
+    p, g, s, ft, V = proj_case
+    say("proj_solution")
+    Vt = np.ascontiguousarray(V.T)  # row i = v~_i, the layout of the ABI (column-major V)
+    y = mq.mqh_proj_solution(s, ft, Vt, mq.MQH_METHOD_HKT, lam=s[10])
+    yo = orc.y_tikhonov(s, ft, V, s[10])
+    assert np.linalg.norm(y - yo) <= 1e-13 * np.linalg.norm(yo)
+    y = mq.mqh_proj_solution(s, ft, Vt, mq.MQH_METHOD_INE_TSVD, k=12)
+    yo = orc.y_tsvd(s, ft, V, 12)
+    assert np.linalg.norm(y - yo) <= 1e-13 * np.linalg.norm(yo)
+    say("lift")
+    Zr = np.ascontiguousarray(g.Z.T)
+    c = mq.mqh_lift(Zr, yo)
+    co = orc.lift(g.Z, yo)
+    assert np.all(np.abs(c - co) <= 1e-13 * (np.abs(g.Z) @ np.abs(yo)))
+
+
+def test_eval(mq, orc):
+    p = I.sphere_scaled(700, 300, kappa=5.0, eps=2.5, ell=10)
+    coef = I.random_vector(p.n, 3)
+    with _problem(mq, p, "matfree_fp64") as pr:
+        say("eval")
+        u = pr.eval(coef, p.x_eval)
+    uo = orc.eval_u(p.nodes, p.eps, coef, p.x_eval)
+    B = orc.interp_matrix(p.x_eval, p.nodes, p.eps)
+    assert np.all(np.abs(u - uo) <= 1e-13 * (B @ np.abs(coef)))
+
+
+# ---------------------------------------------------------------------------
+# whole solves
+# ---------------------------------------------------------------------------
+
+def _solve_both(mq, orc, p, mode, **kw):
+    r = orc.solve(p.nodes, p.n_int, p.kappa, p.eps, p.rhs, p.ell, stored=False, **kw)
+    with _problem(mq, p, mode) as pr:
+        say("solve", p.name, mode, kw)
+        out = pr.solve(p.f_int, p.g_bnd, p.ell, **kw)
+        u = pr.eval(out.coef, p.x_eval)
+    uo = orc.eval_u(p.nodes, p.eps, r.coef, p.x_eval)
+    return r, out, u, uo
+
+
+SOLVE_CASES = [
+    ("cube_n1800", I.cube_small),
+    ("cube_interior_lambda", lambda: I.cube_scaled(400, 240, kappa=3.0, eps=0.7, ell=80)),
+]
+
+
+@pytest.mark.parametrize("name,make", SOLVE_CASES)
+@pytest.mark.parametrize("mode", ["stored_fp64", "matfree_fp64"])
+def test_solve_hkt(mq, orc, name, make, mode):
+    p = make()
+    r, out, u, uo = _solve_both(mq, orc, p, mode)
+    assert out.ell_done == r.ell
+    assert np.max(np.abs(out.sv[:10] - r.s[:10]) / r.s[:10]) < 1e-12
+    assert out.lam == pytest.approx(r.lam, rel=1e-6)
+    assert bool(out.flags & mq.MQH_INFO_GCV_AT_EDGE) == bool(r.flags & orc.FLAG_GCV_AT_EDGE)
+    # at the oracle's lambda the solutions agree to the spec bar
+    r2, out2, u2, uo2 = _solve_both(mq, orc, p, mode, rule=mq.MQH_RULE_FIXED, lambda_fixed=r.lam)
+    assert np.linalg.norm(u2 - uo2) <= 1e-8 * np.linalg.norm(uo2)
+    assert np.linalg.norm(out2.coef - r2.coef) <= 1e-6 * np.linalg.norm(r2.coef)
+    assert out2.resid_norm == pytest.approx(r2.resid_norm, rel=1e-9)
+    assert out2.sol_norm == pytest.approx(r2.sol_norm, rel=1e-8)
+
+
+@pytest.mark.parametrize("name,make", SOLVE_CASES)
+def test_solve_ine_tsvd(mq, orc, name, make):
+    p = make()
+    r, out, u, uo = _solve_both(mq, orc, p, "matfree_fp64", method=mq.MQH_METHOD_INE_TSVD)
+    assert out.k == r.k
+    assert np.linalg.norm(u - uo) <= 1e-8 * np.linalg.norm(uo)
+
+
+def test_solve_lcurve(mq, orc):
+    p = I.cube_scaled(400, 240, kappa=3.0, eps=0.7, ell=80)
+    r, out, u, uo = _solve_both(mq, orc, p, "matfree_fp64", rule=mq.MQH_RULE_LCURVE)
+    assert out.lam == pytest.approx(r.lam, rel=1e-10)
+    assert np.linalg.norm(u - uo) <= 1e-8 * np.linalg.norm(uo)
+
+
+def test_solve_fp32_entries(mq, orc):
+    # FP32 entries perturb A by dA with |dA| <~ 1e-6 |A| entrywise; a Tikhonov
+    # solution at lambda moves by about (s_1/lambda) |dA|/|A|, so at
+    # lambda = 1e-3 s_1 the FP32 path stays within ~1e-3 of the FP64 oracle.
+    p = I.cube_scaled(400, 240, kappa=3.0, eps=0.7, ell=80)
+    s1 = orc.solve(p.nodes, p.n_int, p.kappa, p.eps, p.rhs, p.ell, stored=False).s[0]
+    r, out, u, uo = _solve_both(mq, orc, p, "matfree_fp32", rule=mq.MQH_RULE_FIXED, lambda_fixed=1e-3 * s1)
+    assert np.linalg.norm(u - uo) <= 1e-3 * np.linalg.norm(uo)
+    # at the GCV choice the error against the exact solution matches the FP64 path's
+    r, out, u, uo = _solve_both(mq, orc, p, "matfree_fp32")
+    e32, e64 = orc.rel_l2(u, p.u_eval), orc.rel_l2(uo, p.u_eval)
+    assert abs(e32 - e64) <= 0.05 * e64
+
+
+def test_solve_deterministic(mq):
+    p = I.cube_scaled(300, 200, kappa=4.0, eps=1.0, ell=30)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("determinism")
+        a = pr.solve(p.f_int, p.g_bnd, p.ell)
+        b = pr.solve(p.f_int, p.g_bnd, p.ell)
+    assert np.array_equal(a.coef, b.coef) and a.lam == b.lam
+
+
+@pytest.mark.parametrize("n_int,n_bnd", [(1, 0), (0, 1), (0, 37), (37, 0), (2, 1), (63, 2), (64, 1), (1000, 7)])
+def test_edge_sizes(mq, orc, n_int, n_bnd):
+    X = I.random_nodes_cube(n_int + n_bnd, 900 + n_int)
+    f = I.random_vector(n_int + n_bnd, 901)
+    ell = min(5, n_int + n_bnd)
+    for mode in ("stored_fp64", "matfree_fp64"):
+        say("edge sizes", n_int, n_bnd, mode)
+        with mq.Problem(X[:n_int] if n_int else None, X[n_int:] if n_bnd else None, 2.0, 3.0, mode) as pr:
+            y = pr.apply(f, trans=True)
+            out = pr.solve(f[:n_int] if n_int else None, f[n_int:] if n_bnd else None, ell,
+                           rule=mq.MQH_RULE_FIXED, lambda_fixed=1e-2)
+        ref = orc.apply(None, X, n_int, 2.0, 3.0, f, trans=True)
+        A = orc.assemble(X, n_int, 2.0, 3.0)
+        assert np.all(np.abs(y - ref) <= 1e-13 * (np.abs(A.T) @ np.abs(f)))
+        r = orc.solve(X, n_int, 2.0, 3.0, f, ell, rule=orc.RULE_FIXED, lambda_fixed=1e-2)
+        assert out.ell_done == r.ell
+        assert np.linalg.norm(out.coef - r.coef) <= 1e-8 * max(np.linalg.norm(r.coef), 1e-300)
+
+
+def test_duplicate_nodes_finite(mq):
+    X = I.random_nodes_cube(60, 44)
+    X[7] = X[3]
+    say("duplicate nodes")
+    with mq.Problem(X[:30], X[30:], 3.0, 4.0, "matfree_fp64") as pr:
+        out = pr.solve(np.ones(30), np.ones(30), 20)
+    assert np.all(np.isfinite(out.coef))
+
+
+def test_invalid_inputs(mq):
+    X = I.random_nodes_cube(40, 3)
+    with mq.Problem(X[:20], X[20:], 2.0, 3.0, "matfree_fp64") as pr:
+        say("invalid inputs")
+        bad = np.ones(20)
+        bad[3] = math.nan
+        with pytest.raises(mq.MQHError):
+            pr.solve(bad, np.ones(20), 5)
+        with pytest.raises(mq.MQHError):
+            pr.solve(np.ones(20), np.ones(20), 41)  # ell > n
+        with pytest.raises(mq.MQHError):
+            pr.solve(np.ones(20), np.ones(20), 5, method=mq.MQH_METHOD_INE_TSVD, rule=mq.MQH_RULE_FIXED, k_trunc=0)
