@@ -32,19 +32,44 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X peaks (vendor figures) and issue model
+# MI355X peaks (vendor unit counts and clock) and the VALU issue model.
 HBM_PEAK_GBS = 8000.0
 CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
-VALU_SLOTS_PER_S = CUS * SIMDS * LANES * CLOCK  # 39.3e12 lane-operations per second (non-packed)
-TRANS_SLOTS = 4  # a transcendental (rsq) occupies four issue slots (quarter rate)
-# VALU lane-operations per entry in the FP32-evaluated product (per the entry formula):
-#   interior: 3 sub + 3 fma (t) + rsq + 2 fma (polynomial) + 3 mul (s^3, product) + cvt + fma64
-#   boundary: 3 sub + 3 fma (t) + rsq + 1 mul (t s) + cvt + fma64
-SLOTS_INT_F32 = 13 + TRANS_SLOTS
-SLOTS_BND_F32 = 9 + TRANS_SLOTS
-#   FP64 evaluation: rsq + 2 Newton steps (8) instead of the FP32 rsq, no cvt
-SLOTS_INT_F64 = 3 + 3 + TRANS_SLOTS + 8 + 2 + 3 + 1
-SLOTS_BND_F64 = 3 + 3 + TRANS_SLOTS + 8 + 1 + 1
+# A SIMD issues one wave64 VALU instruction per 4 cycles; gfx950 can issue two
+# FP32 instructions together when neither reads a scalar register (measured
+# with SQ_ACTIVE_INST_VALU2).  FP64 and transcendental instructions issue
+# alone; v_rsq_f32 / v_sqrt_f32 occupy two issue slots, v_rsq_f64 four.
+VALU_PEAK_DUAL = CUS * SIMDS * 2 * LANES * CLOCK  # 78.6e12 lane-operations/s (= FP32 vector peak / 2 flops)
+VALU_PEAK_SINGLE = CUS * SIMDS * LANES * CLOCK  # 39.3e12 lane-operations/s (FP64 rate)
+# Operations per matrix entry in the product kernels (the entry formula as computed,
+# a transcendental counted once):
+#   FP32: interior 3 sub + 3 fma (t) + rsq + mul (s^2) + 2 fma + fma (accumulate) = 10
+#         boundary 3 sub + 3 fma (t) + sqrt + fma (accumulate)                    = 8
+#   FP64: interior 3 sub + 3 fma + rsq + 8 (two Newton steps) + mul + 2 fma + mul + fma = 20
+#         boundary 3 sub + 3 fma + rsq + 8 + mul + fma                                  = 17
+OPS = {"matfree_fp32": (10, 8), "matfree_fp64": (20, 17)}
+# Issue quad-cycles per entry if every pairable instruction were paired (the
+# ceiling this instruction mix allows): FP32 interior 9/2 + 2, boundary 7/2 + 2.
+QUADS_IDEAL_F32 = (6.5, 5.5)
+
+PROFILES = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch from the committed counter runs, or None when the
+    kernel source changed since they were taken."""
+    import hashlib
+
+    try:
+        with open(PROFILES) as fh:
+            rec = json.load(fh).get(kernel_key)
+        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, KeyError, TypeError, ValueError):
+        return None
+    if sha != rec.get("source_sha256"):
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def log(*a):
@@ -138,7 +163,9 @@ def main():
     ap.add_argument("--variants", default="matfree_fp32,stored_fp64,matfree_fp64",
                     help="first one is the headline")
     ap.add_argument("--context-steps", type=int, default=1, help="timed solves of the non-headline variants")
-    ap.add_argument("--cpu-rows", type=int, default=6000, help="row/column sample of the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-rows", type=int, default=150000, help="row/column sample of the CPU baseline (0: skip)")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -157,6 +184,15 @@ def main():
     if args.ell:
         p.ell = args.ell
     log("workload", p.name, "n", p.n, "n_int", p.n_int, "ell", p.ell)
+    if args.copy_ref_mib > 0:
+        nel = args.copy_ref_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy reference", args.copy_ref_mib, "MiB read +", args.copy_ref_mib, "MiB written")
+        del src, dst
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
     results = {}
     for i, v in enumerate(variants):
@@ -174,17 +210,25 @@ def main():
     k_at, k_a = head.get("kernel_ms_AT", float("nan")), head.get("kernel_ms_A", float("nan"))
     dom_ms, dom_name = (k_at, "A^T x") if k_at >= k_a else (k_a, "A x")
     mode = variants[0]
+    kern = {"matfree_fp32": ("k_mf32_cols", "k_mf32_rows"), "matfree_fp64": ("k_mf_cols", "k_mf_rows"),
+            "stored_fp64": ("k_stored_cols", "k_stored_rows")}[mode][0 if dom_name == "A^T x" else 1]
     if mode.startswith("matfree"):
-        si, sb = (SLOTS_INT_F32, SLOTS_BND_F32) if mode == "matfree_fp32" else (SLOTS_INT_F64, SLOTS_BND_F64)
-        work = (p.n_int * n * si + p.n_bnd * n * sb)  # VALU lane-operation slots per product
+        oi, ob = OPS[mode]
+        work = p.n_int * n * oi + p.n_bnd * n * ob  # lane-operations per product
+        peak = VALU_PEAK_DUAL if mode == "matfree_fp32" else VALU_PEAK_SINGLE
         achieved = work / (dom_ms * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=VALU_SLOTS_PER_S / 1e12, unit="TOP/s",
-                    frac=achieved / (VALU_SLOTS_PER_S / 1e12), traffic=None, kernel=f"{mode} {dom_name}",
-                    kernel_ms=dom_ms, other_kernel_ms=min(k_at, k_a))
+        roof = dict(bound="alu", achieved=achieved, peak=peak / 1e12, unit="TOP/s", frac=achieved / (peak / 1e12),
+                    traffic=measured_traffic(kern), kernel=kern, kernel_ms=dom_ms,
+                    other_kernel_ms=min(k_at, k_a), ops_per_product=work)
+        if mode == "matfree_fp32":
+            quads = (p.n_int * n * QUADS_IDEAL_F32[0] + p.n_bnd * n * QUADS_IDEAL_F32[1]) / 64.0
+            t_ideal = quads / (CUS * SIMDS * CLOCK / 4.0)
+            roof["mix_ceiling_frac"] = (work / t_ideal) / peak
     else:
         achieved = 8.0 * n * n / (dom_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=None, kernel=f"{mode} {dom_name}", kernel_ms=dom_ms, other_kernel_ms=min(k_at, k_a))
+                    traffic=measured_traffic(kern), kernel=kern, kernel_ms=dom_ms,
+                    other_kernel_ms=min(k_at, k_a))
 
     ctx = {}
     for v, r in results.items():
@@ -198,7 +242,7 @@ def main():
     line = dict(metric="HKT time-to-solution & GKB matvec GB/s at N=100k sphere, equal rel-L2 err",
                 value=value, unit="GB/s (FP64-A-equivalent product traffic over the whole HKT solve)",
                 n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
-                scaling="weak", vs_baseline=None, dtype="f32-entries/f64-accumulate", data="synthetic",
+                scaling="weak", vs_baseline=None, dtype="f32" if variants[0] == "matfree_fp32" else "f64", data="synthetic",
                 config=dict(workload=p.name, n=n, n_int=p.n_int, n_bnd=p.n_bnd, kappa=p.kappa, eps=p.eps,
                             ell=p.ell, method="HKT", rule="GCV", operator=variants[0]),
                 hkt_time_to_solution_s=head["solve_s"], roofline=roof, variants=ctx)

@@ -8,8 +8,8 @@
  *
  * Problem (Section 2.1):  Lap u + kappa^2 u = f in Omega, u = g on its boundary.
  * Unknowns: coefficients c of u(X) = sum_j c_j phi(|X - X_j|) with the
- * multiquadric phi(r) = sqrt(1 + eps^2 r^2) (eq. MQ) centred at the nodes.
- * Kansa matrix A (N x N, eqs. H_entries, augmented_system, full_system):
+ * multiquadric phi(r) = sqrt(1 + eps^2 r^2) (eq. (3)) centred at the nodes.
+ * Kansa matrix A (N x N, eqs. (8), (10), (11)):
  *   interior rows i < N_I :  A_ij = Lap phi(r_ij) + kappa^2 phi(r_ij),
  *                            Lap phi(r) = eps^2 (3 + 2 eps^2 r^2) / (1 + eps^2 r^2)^{3/2};
  *   boundary rows i >= N_I:  A_ij = phi(r_ij)   (Dirichlet data);
@@ -61,7 +61,7 @@ extern "C" {
 /* ---- methods and parameter-choice rules ---- */
 #define MQH_METHOD_INE_TSVD 0 /* Algorithm 2 */
 #define MQH_METHOD_HKT 1      /* Algorithm 4 */
-#define MQH_RULE_GCV 0        /* eq. gcv_proj (HKT) / projected TSVD-GCV (Ine-TSVD) */
+#define MQH_RULE_GCV 0        /* eq. (30) (HKT) / projected TSVD-GCV (Ine-TSVD) */
 #define MQH_RULE_LCURVE 1     /* maximum curvature of (log rho, log eta) on the grid */
 #define MQH_RULE_FIXED 2      /* lambda = lambda_fixed (HKT) / k = k_trunc (Ine-TSVD) */
 
@@ -98,8 +98,8 @@ typedef struct {
     int32_t k_chosen;      /* Ine-TSVD rank (0 for HKT) */
     double lambda_chosen;  /* HKT lambda (0 for Ine-TSVD) */
     double crit;           /* GCV value at the choice, or curvature for the L-curve rule */
-    double resid_norm;     /* projected residual norm rho_l at the choice (eq. rho_proj) */
-    double sol_norm;       /* projected solution norm eta_l = ||y|| (eq. eta_proj) */
+    double resid_norm;     /* projected residual norm rho_l at the choice (eq. (28)) */
+    double sol_norm;       /* projected solution norm eta_l = ||y|| (eq. (29)) */
     uint32_t flags;        /* MQH_INFO_* */
     int32_t reserved;
     double t_ms[8];        /* [0] data upload, [1] Golub-Kahan loop, [2] projected SVD,
@@ -117,10 +117,10 @@ const char* mqh_last_error(void);
 
 /*
  * Create a problem: copies the nodes to the device and, for
- * MQH_OP_STORED_FP64, assembles A there (eqs. H_entries, augmented_system).
+ * MQH_OP_STORED_FP64, assembles A there (eqs. (8), (10)).
  *   x_int    n_int x 3 interior nodes (may be NULL when n_int == 0)
  *   x_bnd    n_bnd x 3 boundary nodes (may be NULL when n_bnd == 0)
- *   kappa    wavenumber (finite); eps > 0 shape parameter (eq. MQ)
+ *   kappa    wavenumber (finite); eps > 0 shape parameter (eq. (3))
  *   op_mode  MQH_OP_*
  *   stream   hipStream_t to run on, or NULL for a stream the library creates
  *   flags    MQH_FLAG_DEVICE_PTRS if x_int / x_bnd are device pointers
@@ -151,7 +151,7 @@ int mqh_apply(mqh_problem* p, int32_t trans, const double* x, double shift, cons
  * Rows [row0, row0 + count) of A as the problem's operator mode sees them
  * (the stored matrix, or entries generated the way the matrix-free products
  * generate them, FP32-evaluated in MQH_OP_MATFREE_FP32), written row-major
- * count x n to out.  For checks of the entry generator (eq. H_entries).
+ * count x n to out.  For checks of the entry generator (eq. (8)).
  */
 int mqh_matrix_rows(mqh_problem* p, int64_t row0, int64_t count, double* out, uint32_t flags);
 
@@ -191,7 +191,7 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
 
 /*
  * Parameter choice on the projected problem (Section 3.2-3.3), on the device.
- *   method HKT:      rule GCV    -> lambda* = argmin GCV_l (eq. gcv_proj) on a
+ *   method HKT:      rule GCV    -> lambda* = argmin GCV_l (eq. (30)) on a
  *                                   log grid of n_grid points over
  *                                   [max(s_l, 16 eps_mach s_1), s_1], then
  *                                   golden-section refinement of log lambda
@@ -243,7 +243,7 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
 
 /*
  * Evaluate u(X_e) = sum_j coef_j phi(|X_e - X_j|) at m points
- * (eq. u_reconstruction), FP64: coef (n), x_eval (m x 3) in, u (m) out.
+ * (eq. (18)), FP64: coef (n), x_eval (m x 3) in, u (m) out.
  */
 int mqh_eval(mqh_problem* p, const double* coef, const double* x_eval, int64_t m, double* u, uint32_t flags);
 

@@ -8,15 +8,15 @@
  *
  * What it computes (paper: Efficient Krylov-Regularization Solvers for
  * Multiquadric RBF Discretizations of the 3D Helmholtz Equation):
- *   - the multiquadric kernel phi(r) = sqrt(1 + eps^2 r^2)            (eq. MQ)
+ *   - the multiquadric kernel phi(r) = sqrt(1 + eps^2 r^2)            (eq. (3))
  *   - its 3-D Laplacian and the Helmholtz-applied kernel
- *       L phi = Lap(phi) + kappa^2 phi                               (eqs. Lphi, H_entries)
+ *       L phi = Lap(phi) + kappa^2 phi                               (eqs. (7), (8))
  *   - the Kansa matrix A = [H; R]: interior rows L phi, Dirichlet
- *     boundary rows phi, centres = nodes                              (eqs. augmented_system, full_system)
+ *     boundary rows phi, centres = nodes                              (eqs. (10), (11))
  *   - products A v and A^T u, stored or entry-by-entry
  *   - Golub-Kahan bidiagonalisation with full reorthogonalisation     (Algorithm 1)
  *   - one-sided Jacobi SVD of a small dense matrix (projected SVD)    (Algorithm 2 step 2, Algorithm 4 step 2)
- *   - the lift alpha = Z y and evaluation u(X) = sum_j alpha_j phi   (Algorithm 2 step 5, eq. u_reconstruction)
+ *   - the lift alpha = Z y and evaluation u(X) = sum_j alpha_j phi   (Algorithm 2 step 5, eq. (18))
  *
  * Everything is double precision; sqrt and division are IEEE correctly
  * rounded.  Loops are written in the order of the definitions; OpenMP only
@@ -41,7 +41,7 @@
 /* Kernel and matrix entries                                            */
 /* ------------------------------------------------------------------ */
 
-/* phi(r; eps) = sqrt(1 + eps^2 r^2)  (eq. MQ). */
+/* phi(r; eps) = sqrt(1 + eps^2 r^2)  (eq. (3)). */
 double orc_phi(double r, double eps) { return sqrt(1.0 + eps * eps * r * r); }
 
 /* 3-D Laplacian of the radial function phi(|x - c|).  For a radial f(r) in
@@ -49,14 +49,14 @@ double orc_phi(double r, double eps) { return sqrt(1.0 + eps * eps * r * r); }
  *   f'  = eps^2 r / sqrt(t)
  *   f'' = eps^2 / sqrt(t) - eps^4 r^2 / t^(3/2) = eps^2 / t^(3/2)
  * so Lap f = eps^2/t^(3/2) + 2 eps^2/sqrt(t) = eps^2 (3 + 2 eps^2 r^2) / t^(3/2).
- * The paper does not print this expression (it only names Lap(phi) in eq. Lphi). */
+ * The paper does not print this expression (it only names Lap(phi) in eq. (7)). */
 double orc_lap_phi(double r, double eps) {
     double e2 = eps * eps;
     double t = 1.0 + e2 * r * r;
     return e2 * (3.0 + 2.0 * e2 * r * r) / (t * sqrt(t));
 }
 
-/* Helmholtz-applied kernel L phi = Lap(phi) + kappa^2 phi  (eq. H_entries). */
+/* Helmholtz-applied kernel L phi = Lap(phi) + kappa^2 phi  (eq. (8)). */
 double orc_lphi(double r, double kappa, double eps) {
     return orc_lap_phi(r, eps) + kappa * kappa * orc_phi(r, eps);
 }
@@ -67,7 +67,7 @@ static double dist3(const double* a, const double* b) {
 }
 
 /* A_ij: interior rows (i < n_int) are L phi(|X_i - X_j|); boundary rows are
- * phi(|X_i - X_j|) (Dirichlet, u = g; eq. augmented_system). */
+ * phi(|X_i - X_j|) (Dirichlet, u = g; eq. (10)). */
 double orc_entry(const double* X, int64_t n_int, int64_t i, int64_t j, double kappa, double eps) {
     double r = dist3(X + 3 * i, X + 3 * j);
     return (i < n_int) ? orc_lphi(r, kappa, eps) : orc_phi(r, eps);
@@ -81,7 +81,7 @@ void orc_assemble(const double* X, int64_t n, int64_t n_int, double kappa, doubl
             A[i * n + j] = orc_entry(X, n_int, i, j, kappa, eps);
 }
 
-/* Interpolation matrix B_ij = phi(|X_i - X_j|)  (eq. B_matrix), m x n with
+/* Interpolation matrix B_ij = phi(|X_i - X_j|)  (eq. (5)), m x n with
  * rows at points P (m x 3) and columns at centres X (n x 3). */
 void orc_interp_matrix(const double* P, int64_t m, const double* X, int64_t n, double eps, double* B) {
 #pragma omp parallel for schedule(static)
@@ -356,7 +356,7 @@ int orc_jacobi_svd(double* M, int64_t m, int64_t n, double* sv, double* U, doubl
  * U~; the last column is the unit null vector of C^T, n_1 = 1,
  * n_{j+1} = -alpha_j n_j / beta_{j+1}, normalised.  The projected data are
  * f~ = U~^T (beta_1 e_1), i.e. f~_i = beta_1 U~_{1,i}, i = 1..ell+1
- * (eqs. rho_proj / eta_proj need f~_{ell+1}).
+ * (eqs. (28), (29) need f~_{ell+1}).
  *
  * alpha[ell], beta[ell+1] with beta[0] = beta_1.  Outputs: sv[ell]
  * (descending), ftil[ell+1], V (ell x ell column-major, column i = v~_i).
@@ -410,7 +410,7 @@ void orc_lift(const double* Z, int64_t n, int64_t ell, const double* y, double* 
     }
 }
 
-/* u(P_e) = sum_j coef_j phi(|P_e - X_j|)  (eq. u_reconstruction). */
+/* u(P_e) = sum_j coef_j phi(|P_e - X_j|)  (eq. (18)). */
 void orc_eval(const double* X, int64_t n, double eps, const double* coef, const double* P, int64_t m,
               double* u) {
 #pragma omp parallel for schedule(static)

@@ -134,7 +134,7 @@ def num_threads() -> int:
 
 
 def phi(r: float, eps: float) -> float:
-    """MQ kernel sqrt(1 + eps^2 r^2) (eq. MQ)."""
+    """MQ kernel sqrt(1 + eps^2 r^2) (eq. (3))."""
     return lib().orc_phi(float(r), float(eps))
 
 
@@ -144,12 +144,12 @@ def lap_phi(r: float, eps: float) -> float:
 
 
 def lphi(r: float, kappa: float, eps: float) -> float:
-    """Helmholtz-applied kernel Lap(phi) + kappa^2 phi (eq. H_entries)."""
+    """Helmholtz-applied kernel Lap(phi) + kappa^2 phi (eq. (8))."""
     return lib().orc_lphi(float(r), float(kappa), float(eps))
 
 
 def assemble(X: np.ndarray, n_int: int, kappa: float, eps: float) -> np.ndarray:
-    """Dense Kansa matrix A = [H; R] (eq. augmented_system), row-major n x n."""
+    """Dense Kansa matrix A = [H; R] (eq. (10)), row-major n x n."""
     X = _c(X)
     n = X.shape[0]
     A = np.empty((n, n))
@@ -158,7 +158,7 @@ def assemble(X: np.ndarray, n_int: int, kappa: float, eps: float) -> np.ndarray:
 
 
 def interp_matrix(P: np.ndarray, X: np.ndarray, eps: float) -> np.ndarray:
-    """B_ij = phi(|P_i - X_j|) (eq. B_matrix)."""
+    """B_ij = phi(|P_i - X_j|) (eq. (5))."""
     P, X = _c(P), _c(X)
     B = np.empty((P.shape[0], X.shape[0]))
     lib().orc_interp_matrix(_p(P), P.shape[0], _p(X), X.shape[0], float(eps), _p(B))
@@ -267,7 +267,7 @@ def lift(Z: np.ndarray, y: np.ndarray) -> np.ndarray:
 
 
 def eval_u(X: np.ndarray, eps: float, coef: np.ndarray, P: np.ndarray) -> np.ndarray:
-    """u(P) = sum_j coef_j phi(|P - X_j|) (eq. u_reconstruction)."""
+    """u(P) = sum_j coef_j phi(|P - X_j|) (eq. (18))."""
     X, coef, P = _c(X), _c(coef), _c(P)
     u = np.empty(P.shape[0])
     lib().orc_eval(_p(X), X.shape[0], float(eps), _p(coef), _p(P), P.shape[0], _p(u))
@@ -292,28 +292,28 @@ def tikh_filter_complement(s: np.ndarray, lam: float) -> np.ndarray:
 
 
 def rho2_proj(s: np.ndarray, ftil: np.ndarray, lam: float) -> float:
-    """rho_l^2 = sum_i (1 - phi_i)^2 f~_i^2 + f~_{l+1}^2  (eq. rho_proj)."""
+    """rho_l^2 = sum_i (1 - phi_i)^2 f~_i^2 + f~_{l+1}^2  (eq. (28))."""
     ell = s.shape[0]
     c = tikh_filter_complement(s, lam)
     return float(np.sum((c * ftil[:ell]) ** 2) + ftil[ell] ** 2)
 
 
 def eta2_proj(s: np.ndarray, ftil: np.ndarray, lam: float) -> float:
-    """eta_l^2 = sum_i (phi_i / s_i)^2 f~_i^2  (eq. eta_proj)."""
+    """eta_l^2 = sum_i (phi_i / s_i)^2 f~_i^2  (eq. (29))."""
     ell = s.shape[0]
     ph = tikh_filter(s, lam)
     return float(np.sum((ph / s * ftil[:ell]) ** 2))
 
 
 def gcv_proj(s: np.ndarray, ftil: np.ndarray, lam: float) -> float:
-    """GCV_l(lambda) = rho_l^2 / ((l+1) - sum_i phi_i)^2  (eq. gcv_proj)."""
+    """GCV_l(lambda) = rho_l^2 / ((l+1) - sum_i phi_i)^2  (eq. (30))."""
     ell = s.shape[0]
     den = (ell + 1) - float(np.sum(tikh_filter(s, lam)))
     return rho2_proj(s, ftil, lam) / (den * den)
 
 
 def gcv_full(s: np.ndarray, fhat: np.ndarray, s_perp: float, n: int, lam: float) -> float:
-    """GCV(lambda) of the full problem in SVD variables (eq. gcv_svd, Algorithm 3)."""
+    """GCV(lambda) of the full problem in SVD variables (eq. (25), Algorithm 3)."""
     c = tikh_filter_complement(s, lam)
     rho2 = float(np.sum((c * fhat) ** 2)) + s_perp
     den = n - float(np.sum(tikh_filter(s, lam)))
@@ -504,13 +504,13 @@ def full_svd(A: np.ndarray):
 
 
 def full_tsvd(A: np.ndarray, f: np.ndarray, k: int) -> np.ndarray:
-    """alpha_k = sum_{i<=k} v_i (u_i^T f) / s_i  (eq. tsvd_solution)."""
+    """alpha_k = sum_{i<=k} v_i (u_i^T f) / s_i  (eq. (14))."""
     U, s, V = full_svd(A)
     return V[:, :k] @ ((U[:, :k].T @ f) / s[:k])
 
 
 def full_tikhonov(A: np.ndarray, f: np.ndarray, lam: float) -> np.ndarray:
-    """alpha_lambda = sum_i s_i/(s_i^2+lambda^2) (u_i^T f) v_i  (eq. tikh_solution)."""
+    """alpha_lambda = sum_i s_i/(s_i^2+lambda^2) (u_i^T f) v_i  (eq. (17))."""
     U, s, V = full_svd(A)
     return V @ (s / (s * s + lam * lam) * (U.T @ f))
 
@@ -539,5 +539,5 @@ def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
 
 
 def rel_linf(a: np.ndarray, b: np.ndarray) -> float:
-    """Re = ||u - u_a||_inf / ||u||_inf (eq. rel_error)."""
+    """Re = ||u - u_a||_inf / ||u||_inf (eq. (31))."""
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))

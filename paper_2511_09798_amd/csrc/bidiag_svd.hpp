@@ -34,17 +34,30 @@ constexpr double kEps = 2.220446049250313e-16;  // DBL_EPSILON
 constexpr double kTol = 16.0 * kEps;            // relative deflation tolerance
 constexpr double kTiny = 2.2250738585072014e-308;
 
+// 1/sqrt(q) to about one ulp: on the device the hardware estimate refined by
+// two Newton steps, on the host the library square root.
+MQH_HD inline double inv_sqrt(double q) {
+#ifdef __HIP_DEVICE_COMPILE__
+    double y = __builtin_amdgcn_rsq(q);
+    double h = q * y;
+    double r = fma(-h, y, 1.0);
+    y = fma(0.5 * y, r, y);
+    h = q * y;
+    r = fma(-h, y, 1.0);
+    return fma(0.5 * y, r, y);
+#else
+    return 1.0 / sqrt(q);
+#endif
+}
+
 // Givens rotation: c = f / r, s = g / r, r = sqrt(f^2 + g^2) >= 0, so that
-// [c s; -s c] [f; g] = [r; 0].
+// [c s; -s c] [f; g] = [r; 0].  The squares are formed directly when they
+// neither overflow nor underflow, otherwise after scaling by max(|f|, |g|).
 MQH_HD inline void make_rot(double f, double g, double& c, double& s, double& r) {
     if (g == 0.0) {
-        c = 1.0;
+        c = f < 0.0 ? -1.0 : 1.0;
         s = 0.0;
-        r = f;
-        if (f < 0.0) {
-            c = -1.0;
-            r = -f;
-        }
+        r = fabs(f);
         return;
     }
     if (f == 0.0) {
@@ -53,14 +66,21 @@ MQH_HD inline void make_rot(double f, double g, double& c, double& s, double& r)
         r = fabs(g);
         return;
     }
+    const double q = fma(f, f, g * g);
+    if (q > 1e-290 && q < 1e290) {
+        const double inv = inv_sqrt(q);
+        r = q * inv;
+        c = f * inv;
+        s = g * inv;
+        return;
+    }
     const double af = fabs(f), ag = fabs(g);
     const double mx = af > ag ? af : ag;
     const double mn = af > ag ? ag : af;
-    const double q = mn / mx;
-    r = mx * sqrt(1.0 + q * q);
-    const double inv = 1.0 / r;
-    c = f * inv;
-    s = g * inv;
+    const double t = mn / mx;
+    r = mx * sqrt(1.0 + t * t);
+    c = f / r;
+    s = g / r;
 }
 
 // Step 1: C (lower bidiagonal, (l+1) x l) -> upper bidiagonal B (d, e) and
@@ -98,34 +118,41 @@ MQH_HD inline double smin2(double f, double h, double k) {
 
 // One bulge-chasing sweep with shift mu on rows/columns ll..m (upper
 // bidiagonal d, e).  Records right rotations in rc/rs[0 .. m-ll-1] and
-// applies left rotations to g.
+// applies left rotations to g.  The running entries are carried in
+// registers; each array element is read once and written once.
 MQH_HD inline void sweep_shifted(double* d, double* e, double* g, int ll, int m, double mu, double* rc, double* rs) {
-    const double dl = d[ll];
-    double f = (fabs(dl) - mu) * ((dl < 0.0 ? -1.0 : 1.0) + mu / dl);
-    double gg = e[ll];
+    double dk = d[ll], ek = e[ll], gk = g[ll];
+    double f = (fabs(dk) - mu) * ((dk < 0.0 ? -1.0 : 1.0) + mu / dk);
+    double gg = ek;
     for (int k = ll; k < m; ++k) {
+        double dk1 = d[k + 1];
+        double ek1 = k + 1 < m ? e[k + 1] : 0.0;
+        const double gk1 = g[k + 1];
         double c, s, r;
-        make_rot(f, gg, c, s, r);
+        make_rot(f, gg, c, s, r);  // right rotation, columns k, k+1
         if (k > ll) e[k - 1] = r;
-        f = c * d[k] + s * e[k];
-        e[k] = c * e[k] - s * d[k];
-        gg = s * d[k + 1];
-        d[k + 1] = c * d[k + 1];
+        f = c * dk + s * ek;
+        ek = c * ek - s * dk;
+        gg = s * dk1;
+        dk1 = c * dk1;
         rc[k - ll] = c;
         rs[k - ll] = s;
-        make_rot(f, gg, c, s, r);
+        make_rot(f, gg, c, s, r);  // left rotation, rows k, k+1
         d[k] = r;
-        f = c * e[k] + s * d[k + 1];
-        d[k + 1] = c * d[k + 1] - s * e[k];
+        f = c * ek + s * dk1;
+        dk1 = c * dk1 - s * ek;
         if (k + 1 < m) {
-            gg = s * e[k + 1];
-            e[k + 1] = c * e[k + 1];
+            gg = s * ek1;
+            ek1 = c * ek1;
         }
-        const double g0 = g[k], g1 = g[k + 1];
-        g[k] = c * g0 + s * g1;
-        g[k + 1] = -s * g0 + c * g1;
+        g[k] = c * gk + s * gk1;
+        gk = -s * gk + c * gk1;
+        dk = dk1;
+        ek = ek1;
     }
     e[m - 1] = f;
+    d[m] = dk;
+    g[m] = gk;
 }
 
 // Zero-shift sweep (Demmel-Kahan): the shifted sweep with mu = 0, written
@@ -133,21 +160,26 @@ MQH_HD inline void sweep_shifted(double* d, double* e, double* g, int ll, int m,
 // relative accuracy.
 MQH_HD inline void sweep_zero(double* d, double* e, double* g, int ll, int m, double* rc, double* rs) {
     double cs = 1.0, sn = 0.0, oldcs = 1.0, oldsn = 0.0, r;
+    double dk = d[ll], gk = g[ll];
     for (int k = ll; k < m; ++k) {
-        make_rot(d[k] * cs, e[k], cs, sn, r);
+        const double ek = e[k];
+        const double dk1 = d[k + 1];
+        const double gk1 = g[k + 1];
+        make_rot(dk * cs, ek, cs, sn, r);
         if (k > ll) e[k - 1] = oldsn * r;
-        double dk;
-        make_rot(oldcs * r, d[k + 1] * sn, oldcs, oldsn, dk);
-        d[k] = dk;
+        double dnew;
+        make_rot(oldcs * r, dk1 * sn, oldcs, oldsn, dnew);
+        d[k] = dnew;
         rc[k - ll] = cs;
         rs[k - ll] = sn;
-        const double g0 = g[k], g1 = g[k + 1];
-        g[k] = oldcs * g0 + oldsn * g1;
-        g[k + 1] = -oldsn * g0 + oldcs * g1;
+        g[k] = oldcs * gk + oldsn * gk1;
+        gk = -oldsn * gk + oldcs * gk1;
+        dk = dk1;
     }
-    const double h = d[m] * cs;
+    const double h = dk * cs;
     d[m] = h * oldcs;
     e[m - 1] = h * oldsn;
+    g[m] = gk;
 }
 
 // Driver state between sweeps.
@@ -188,26 +220,31 @@ MQH_HD inline int driver_step(Driver& dv, double* d, double* e, double* g, doubl
         // top of the unreduced block
         int ll = m - 1;
         while (ll > 0 && e[ll - 1] != 0.0) --ll;
-        // relative test inside the block (forward recurrence)
+        // one pass over the block: relative test with the forward recurrence
+        // mu_{k+1} = |d_{k+1}| mu_k / (mu_k + |e_k|), smallest mu (an estimate of
+        // the smallest singular value), largest entry, exactly zero diagonal
         double mu = fabs(d[ll]);
-        double sminl = mu;
-        bool split = false;
+        double sminl = mu, smax = mu;
+        bool split = false, zero = d[ll] == 0.0;
         for (int k = ll; k < m; ++k) {
-            if (fabs(e[k]) <= kTol * mu) {
+            const double aek = fabs(e[k]);
+            if (aek <= kTol * mu) {
                 e[k] = 0.0;
                 split = true;
                 break;
             }
-            mu = fabs(d[k + 1]) * (mu / (mu + fabs(e[k])));
+            const double adk1 = fabs(d[k + 1]);
+            mu = adk1 * (mu / (mu + aek));
             sminl = mu < sminl ? mu : sminl;
+            smax = aek > smax ? aek : smax;
+            smax = adk1 > smax ? adk1 : smax;
+            zero = zero || adk1 == 0.0;
         }
         if (split) continue;
         // an exactly zero diagonal entry: perturb within rounding of the block norm
-        double smax = 0.0;
-        for (int k = ll; k <= m; ++k) smax = fabs(d[k]) > smax ? fabs(d[k]) : smax;
-        for (int k = ll; k < m; ++k) smax = fabs(e[k]) > smax ? fabs(e[k]) : smax;
-        for (int k = ll; k <= m; ++k)
-            if (d[k] == 0.0) d[k] = kEps * kEps * smax;
+        if (zero)
+            for (int k = ll; k <= m; ++k)
+                if (d[k] == 0.0) d[k] = kEps * kEps * smax;
         if (dv.iters > dv.maxit) {
             dv.status = -1;
             return -1;
@@ -231,14 +268,24 @@ MQH_HD inline int driver_step(Driver& dv, double* d, double* e, double* g, doubl
 }
 
 // Applies the recorded right rotations of one sweep to one row of V,
-// V[row, ll..m], with V column-major (V[k * ldv + row]).
+// V[row, ll..m], with V column-major (V[k * ldv + row]).  Entries are
+// loaded eight at a time ahead of the rotation chain.
 MQH_HD inline void apply_row(double* V, int64_t ldv, int row, int ll, int m, const double* rc, const double* rs) {
     double x = V[(int64_t)ll * ldv + row];
-    for (int k = ll; k < m; ++k) {
-        const double y = V[(int64_t)(k + 1) * ldv + row];
-        const double c = rc[k - ll], s = rs[k - ll];
-        V[(int64_t)k * ldv + row] = c * x + s * y;
-        x = -s * x + c * y;
+    for (int k0 = ll; k0 < m; k0 += 8) {
+        const int cnt = m - k0 < 8 ? m - k0 : 8;
+        double y[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < cnt) y[q] = V[(int64_t)(k0 + 1 + q) * ldv + row];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (q < cnt) {
+                const double c = rc[k0 - ll + q], s = rs[k0 - ll + q];
+                V[(int64_t)(k0 + q) * ldv + row] = c * x + s * y[q];
+                x = -s * x + c * y[q];
+            }
+        }
     }
     V[(int64_t)m * ldv + row] = x;
 }

@@ -151,15 +151,22 @@ void to_records(const mqh_problem* p, const double* xyz, int64_t m, double4* r64
 
 void choose_shapes(mqh_problem* p) {
     const int64_t n = p->n;
-    const int64_t target_blocks = 4096;  // 16 waves per SIMD over 256 CUs
-    const int64_t nb_rows = (p->n_int + kBlock - 1) / kBlock + (p->n_bnd + kBlock - 1) / kBlock;
-    const int64_t nb_cols = (n + kBlock - 1) / kBlock;
+    // Enough blocks for many rounds of 8 resident waves per SIMD over 256
+    // CUs (the FP32 products want more, shorter slices).
+    const int64_t target_blocks = p->mode == MQH_OP_MATFREE_FP32 ? 32768 : 4096;
+    // FP32-evaluated products: kMf32Rows outputs per lane and slices made of
+    // whole LDS tiles; FP64 ones: one output per lane, slices of even length.
+    const bool f32 = p->mode == MQH_OP_MATFREE_FP32;
+    const int64_t per_block = f32 ? (int64_t)kBlock * kMf32Rows : kBlock;
+    const int64_t quantum = f32 ? kBlock : 2;
+    const int64_t nb_rows = (p->n_int + per_block - 1) / per_block + (p->n_bnd + per_block - 1) / per_block;
+    const int64_t nb_cols = (n + per_block - 1) / per_block;
     auto pick = [&](int64_t nb, int& S, int64_t& len) {
         int64_t s = (target_blocks + nb - 1) / nb;
         if (s < 1) s = 1;
         if (s > 64) s = 64;
         int64_t l = (n + s - 1) / s;
-        l = round_up(l < 64 ? 64 : l, 2);
+        l = round_up(l < 64 ? 64 : l, quantum);
         s = (n + l - 1) / l;
         S = (int)(s < 1 ? 1 : s);
         len = l;

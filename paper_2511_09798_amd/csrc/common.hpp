@@ -63,11 +63,12 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 // pre-multiplied by eps, so for two stored nodes P, Q
 //     t = 1 + |P - Q|^2 = 1 + eps^2 r^2 .
 // With s = t^{-1/2}:
-//   boundary row (Dirichlet, eq. MQ):     phi      = sqrt(t)          = t s
-//   interior row (eq. H_entries):         L phi    = eps^2 (2t+1) t^{-3/2} + kappa^2 t^{1/2}
-//                                                  = (kappa^2 t^2 + 2 eps^2 t + eps^2) s^3
+//   boundary row (Dirichlet, eq. (3)):     phi      = sqrt(t)          = t s
+//   interior row (eq. (8)):         L phi    = eps^2 (2t+1) t^{-3/2} + kappa^2 t^{1/2}
+//                                                  = (kappa^2 t + 2 eps^2 + eps^2 s^2) s
 // (the Laplacian of phi in 3-D is eps^2 (3 + 2 eps^2 r^2) / t^{3/2}, and
-//  3 + 2 eps^2 r^2 = 2t + 1).
+//  3 + 2 eps^2 r^2 = 2t + 1; all three terms are positive, so the form has
+//  no cancellation).
 // ---------------------------------------------------------------------------
 
 struct EntryConst {
@@ -103,22 +104,18 @@ __device__ __forceinline__ float t_of(float px, float py, float pz, float qx, fl
 
 __device__ __forceinline__ double entry_interior(double t, const EntryConst& c) {
     const double s = rsqrt_f64(t);
-    const double p = fma(fma(c.k2, t, c.e2x2), t, c.e2);
-    return p * (s * s * s);
+    return fma(c.e2, s * s, fma(c.k2, t, c.e2x2)) * s;
 }
 
 __device__ __forceinline__ double entry_boundary(double t, const EntryConst&) { return t * rsqrt_f64(t); }
 
-// FP32 evaluation: one v_rsq_f32 per entry (1 ulp), the rest in FP32.
+// FP32 evaluation: one v_rsq_f32 / v_sqrt_f32 per entry (1 ulp), the rest in FP32.
 __device__ __forceinline__ float entry_interior(float t, const EntryConst& c) {
     const float s = __builtin_amdgcn_rsqf(t);
-    const float p = fmaf(fmaf(c.k2f, t, c.e2x2f), t, c.e2f);
-    return p * (s * s * s);
+    return fmaf(c.e2f, s * s, fmaf(c.k2f, t, c.e2x2f)) * s;
 }
 
-__device__ __forceinline__ float entry_boundary(float t, const EntryConst&) {
-    return t * __builtin_amdgcn_rsqf(t);
-}
+__device__ __forceinline__ float entry_boundary(float t, const EntryConst&) { return __builtin_amdgcn_sqrtf(t); }
 
 // Node record types per evaluation precision.
 template <typename R>

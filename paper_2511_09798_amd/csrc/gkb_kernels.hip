@@ -107,73 +107,68 @@ __global__ __launch_bounds__(kBlock) void k_scale(const double* __restrict__ x, 
 // Classical Gram-Schmidt against m orthonormal columns V[:, 0:m]
 // ---------------------------------------------------------------------------
 
-// partial[b * m + k] = sum over rows of block b of V[k][i] x_i.  A block
-// owns 256 rows (4 per lane, held in registers); each wave takes the
-// columns k = wave, wave + 4, ... two at a time and reduces across lanes.
+// partial[b * m + k] = sum over the kGtRows rows of block row b of V[k][i] x_i.
+// A block owns kGtRows rows (kGtRows/256 per lane, x held in registers)
+// and kGtCols consecutive columns (blockIdx.y): every lane issues
+// kGtCols * kGtRows/256 independent loads, then each column is reduced
+// over the block in a fixed order.
+constexpr int kGtRows = 1024;
+constexpr int kGtCols = 8;
+
 __global__ __launch_bounds__(kBlock) void k_gemvt_partial(const double* __restrict__ V, int64_t ldn, int64_t n,
                                                           int32_t m, const double* __restrict__ x,
                                                           double* __restrict__ partial,
                                                           const GkbState* __restrict__ st) {
+    __shared__ double lds[kBlock / kWave][kGtCols];
     if (st != nullptr && st->stopped) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int64_t r0 = (int64_t)blockIdx.x * kBlock + lane;
-    double xv[4];
+    constexpr int Q = kGtRows / kBlock;
+    const int64_t r0 = (int64_t)blockIdx.x * kGtRows + threadIdx.x;
+    const int k0 = blockIdx.y * kGtCols;
+    double xv[Q];
+    bool in[Q];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t i = r0 + q * kWave;
+    for (int q = 0; q < Q; ++q) {
+        const int64_t i = r0 + q * kBlock;
+        in[q] = i < ldn;  // V is zero-padded up to ldn
         xv[q] = i < n ? x[i] : 0.0;
     }
-    const int nw = kBlock / kWave;
-    int k = wv;
-    for (; k + nw < m; k += 2 * nw) {
-        const double* v0 = V + (int64_t)k * ldn;
-        const double* v1 = V + (int64_t)(k + nw) * ldn;
-        double s0 = 0.0, s1 = 0.0;
+    double acc[kGtCols];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t i = r0 + q * kWave;
-            if (i < ldn) {  // V is zero-padded up to ldn
-                s0 = fma(v0[i], xv[q], s0);
-                s1 = fma(v1[i], xv[q], s1);
-            }
-        }
-        s0 = wave_sum(s0);
-        s1 = wave_sum(s1);
-        if (lane == 0) {
-            partial[(int64_t)blockIdx.x * m + k] = s0;
-            partial[(int64_t)blockIdx.x * m + k + nw] = s1;
+    for (int c = 0; c < kGtCols; ++c) {
+        acc[c] = 0.0;
+        if (k0 + c < m) {
+            const double* v = V + (int64_t)(k0 + c) * ldn;
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (in[q]) acc[c] = fma(v[r0 + q * kBlock], xv[q], acc[c]);
         }
     }
-    if (k < m) {
-        const double* v0 = V + (int64_t)k * ldn;
-        double s0 = 0.0;
+    const int w = threadIdx.x / kWave;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t i = r0 + q * kWave;
-            if (i < ldn) s0 = fma(v0[i], xv[q], s0);
-        }
-        s0 = wave_sum(s0);
-        if (lane == 0) partial[(int64_t)blockIdx.x * m + k] = s0;
+    for (int c = 0; c < kGtCols; ++c) {
+        const double sc = wave_sum(acc[c]);
+        if ((threadIdx.x & (kWave - 1)) == 0) lds[w][c] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x < kGtCols && k0 + (int)threadIdx.x < m) {
+        const int c = threadIdx.x;
+        partial[(int64_t)blockIdx.x * m + k0 + c] = ((lds[0][c] + lds[1][c]) + lds[2][c]) + lds[3][c];
     }
 }
 
-// c[k] = sum_b partial[b * m + k]; a block takes 64 columns, its four waves
-// take interleaved quarters of the blocks, combined in a fixed order.
+// c[k] = sum_b partial[b * m + k]: one wave per column, lanes take b = lane,
+// lane + 64, ... and the wave reduction combines them in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restrict__ partial, int nb, int32_t m,
                                                          double* __restrict__ c,
                                                          const GkbState* __restrict__ st) {
-    __shared__ double lds[kBlock];
     if (st != nullptr && st->stopped) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int k = blockIdx.x * kWave + lane;
+    const int k = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (k >= m) return;  // wave-uniform; no barriers
     double s = 0.0;
-    if (k < m)
-        for (int b = wv; b < nb; b += kBlock / kWave) s += partial[(int64_t)b * m + k];
-    lds[threadIdx.x] = s;
-    __syncthreads();
-    if (wv == 0 && k < m) c[k] = ((lds[lane] + lds[kWave + lane]) + lds[2 * kWave + lane]) + lds[3 * kWave + lane];
+    for (int b = lane; b < nb; b += kWave) s += partial[(int64_t)b * m + k];
+    s = wave_sum(s);
+    if (lane == 0) c[k] = s;
 }
 
 // x_i -= sum_k V[k][i] c_k; optionally partial[b] = sum over the block of the updated x_i^2.
@@ -186,14 +181,16 @@ __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V,
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double xi = 0.0;
     if (i < n) {
-        double s0 = 0.0, s1 = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int k = 0;
-        for (; k + 1 < m; k += 2) {
+        for (; k + 3 < m; k += 4) {
             s0 = fma(V[(int64_t)k * ldn + i], c[k], s0);
             s1 = fma(V[(int64_t)(k + 1) * ldn + i], c[k + 1], s1);
+            s2 = fma(V[(int64_t)(k + 2) * ldn + i], c[k + 2], s2);
+            s3 = fma(V[(int64_t)(k + 3) * ldn + i], c[k + 3], s3);
         }
-        if (k < m) s0 = fma(V[(int64_t)k * ldn + i], c[k], s0);
-        xi = x[i] - (s0 + s1);
+        for (; k < m; ++k) s0 = fma(V[(int64_t)k * ldn + i], c[k], s0);
+        xi = x[i] - ((s0 + s1) + (s2 + s3));
         x[i] = xi;
     }
     if (sumsq_partial != nullptr) {
@@ -254,13 +251,13 @@ void launch_scale(const double* x, int64_t n, const double* div, double* dst, co
     k_scale<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, div, dst, st);
 }
 
-int gemvt_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+int gemvt_blocks(int64_t n) { return (int)((n + kGtRows - 1) / kGtRows); }
 
 void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
                   const GkbState* st, hipStream_t s) {
     const int nb = gemvt_blocks(n);
-    k_gemvt_partial<<<nb, kBlock, 0, s>>>(V, ldn, n, m, x, partial, st);
-    k_gemvt_reduce<<<(m + kWave - 1) / kWave, kBlock, 0, s>>>(partial, nb, m, c, st);
+    k_gemvt_partial<<<dim3(nb, (m + kGtCols - 1) / kGtCols), kBlock, 0, s>>>(V, ldn, n, m, x, partial, st);
+    k_gemvt_reduce<<<(m + kBlock / kWave - 1) / (kBlock / kWave), kBlock, 0, s>>>(partial, nb, m, c, st);
 }
 
 void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,

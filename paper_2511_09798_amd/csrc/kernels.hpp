@@ -9,6 +9,7 @@ namespace mqh {
 
 constexpr int kMaxEll = 1024;   // largest projected problem (Golub-Kahan steps)
 constexpr int kMaxGrid = 4096;  // largest lambda grid
+constexpr int kMf32Rows = 1;    // outputs per lane in the FP32-evaluated matrix-free products
 
 // Result of the parameter choice, device-resident.
 struct ParamOut {

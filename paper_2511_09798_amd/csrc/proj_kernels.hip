@@ -12,22 +12,26 @@ namespace mqh {
 constexpr int kProjThreads = 256;
 
 // ---------------------------------------------------------------------------
-// SVD of C_l.  Thread 0 runs the scalar bulge chase; after every sweep all
-// threads apply its right rotations to their rows of the work matrix Vw
-// (column-major, ld = ldw).  Outputs: sv (descending), ftil (l+1), V (ld = ldv).
+// SVD of C_l.  Lane 0 of wave 0 runs the scalar bulge chase; the other four
+// waves apply the right rotations of the previous sweep to their rows of the
+// work matrix Vw (column-major, ld = ldw) at the same time, through two
+// rotation buffers.  Outputs: sv (descending), ftil (l+1), V (ld = ldv).
 // l is taken from *l_ptr when given (steps kept by the Golub-Kahan run).
 // status[0] = 0 on success, -1 if the iteration limit was hit.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kProjThreads) void k_bidiag_svd(const double* __restrict__ alpha,
-                                                             const double* __restrict__ beta, int32_t l_arg,
-                                                             const int32_t* __restrict__ l_ptr,
-                                                             double* __restrict__ Vw, int64_t ldw,
-                                                             double* __restrict__ sv, double* __restrict__ ftil,
-                                                             double* __restrict__ V, int64_t ldv,
-                                                             int32_t* __restrict__ status) {
-    __shared__ double d[kMaxEll], e[kMaxEll], g[kMaxEll], rc[kMaxEll], rs[kMaxEll];
+constexpr int kSvdThreads = kProjThreads + kWave;  // one chain wave + four applier waves
+
+__global__ __launch_bounds__(kSvdThreads) void k_bidiag_svd(const double* __restrict__ alpha,
+                                                            const double* __restrict__ beta, int32_t l_arg,
+                                                            const int32_t* __restrict__ l_ptr,
+                                                            double* __restrict__ Vw, int64_t ldw,
+                                                            double* __restrict__ sv, double* __restrict__ ftil,
+                                                            double* __restrict__ V, int64_t ldv,
+                                                            int32_t* __restrict__ status) {
+    __shared__ double d[kMaxEll], e[kMaxEll], g[kMaxEll];
+    __shared__ double rc[2][kMaxEll], rs[2][kMaxEll];
     __shared__ int rank[kMaxEll];
-    __shared__ int s_ll, s_m, s_res;
+    __shared__ int s_ll[2], s_m[2], s_res[2];
     const int tid = threadIdx.x;
     const int l = l_ptr != nullptr ? *l_ptr : l_arg;
     if (l <= 0) {
@@ -37,34 +41,40 @@ __global__ __launch_bounds__(kProjThreads) void k_bidiag_svd(const double* __res
         }
         return;
     }
-    for (int64_t idx = tid; idx < (int64_t)l * l; idx += kProjThreads) {
+    for (int64_t idx = tid; idx < (int64_t)l * l; idx += kSvdThreads) {
         const int64_t col = idx / l, row = idx % l;
         Vw[col * ldw + row] = (col == row) ? 1.0 : 0.0;
     }
+    bsvd::Driver dv;
     if (tid == 0) {
         for (int i = 0; i < l; ++i) e[i] = 0.0;
         ftil[l] = bsvd::reduce_lower(alpha, beta, l, d, e, g);
+        bsvd::driver_init(dv, l);
+        int ll = 0, m = 0;
+        s_res[0] = bsvd::driver_step(dv, d, e, g, rc[0], rs[0], &ll, &m);
+        s_ll[0] = ll;
+        s_m[0] = m;
     }
     __syncthreads();
-    bsvd::Driver dv;
-    if (tid == 0) bsvd::driver_init(dv, l);
+    int b = 0;
     for (;;) {
-        if (tid == 0) {
+        if (s_res[b] != 1) break;  // block-uniform
+        if (tid >= kWave) {
+            const int ll = s_ll[b], m = s_m[b];
+            for (int row = tid - kWave; row < l; row += kSvdThreads - kWave)
+                bsvd::apply_row(Vw, ldw, row, ll, m, rc[b], rs[b]);
+        } else if (tid == 0) {
             int ll = 0, m = 0;
-            s_res = bsvd::driver_step(dv, d, e, g, rc, rs, &ll, &m);
-            s_ll = ll;
-            s_m = m;
+            s_res[1 - b] = bsvd::driver_step(dv, d, e, g, rc[1 - b], rs[1 - b], &ll, &m);
+            s_ll[1 - b] = ll;
+            s_m[1 - b] = m;
         }
         __syncthreads();
-        const int res = s_res;
-        if (res != 1) break;
-        const int ll = s_ll, m = s_m;
-        for (int row = tid; row < l; row += kProjThreads) bsvd::apply_row(Vw, ldw, row, ll, m, rc, rs);
-        __syncthreads();
+        b = 1 - b;
     }
-    if (tid == 0 && status != nullptr) status[0] = s_res == 0 ? 0 : -1;
+    if (tid == 0 && status != nullptr) status[0] = s_res[b] == 0 ? 0 : -1;
     // order descending: rank of |d_i| among all (ties by index), one i per thread
-    for (int i = tid; i < l; i += kProjThreads) {
+    for (int i = tid; i < l; i += kSvdThreads) {
         const double si = fabs(d[i]);
         int rk = 0;
         for (int j = 0; j < l; ++j) {
@@ -74,11 +84,11 @@ __global__ __launch_bounds__(kProjThreads) void k_bidiag_svd(const double* __res
         rank[i] = rk;
     }
     __syncthreads();
-    for (int i = tid; i < l; i += kProjThreads) {
+    for (int i = tid; i < l; i += kSvdThreads) {
         sv[rank[i]] = fabs(d[i]);
         ftil[rank[i]] = g[i];
     }
-    for (int64_t idx = tid; idx < (int64_t)l * l; idx += kProjThreads) {
+    for (int64_t idx = tid; idx < (int64_t)l * l; idx += kSvdThreads) {
         const int64_t i = idx / l, row = idx % l;
         const double sg = d[i] < 0.0 ? -1.0 : 1.0;
         V[(int64_t)rank[i] * ldv + row] = sg * Vw[i * ldw + row];
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_proj_solution(const double* __restri
 void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* Vw,
                        int64_t ldw, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
                        hipStream_t s) {
-    k_bidiag_svd<<<1, kProjThreads, 0, s>>>(alpha, beta, l, l_ptr, Vw, ldw, sv, ftil, V, ldv, status);
+    k_bidiag_svd<<<1, kSvdThreads, 0, s>>>(alpha, beta, l, l_ptr, Vw, ldw, sv, ftil, V, ldv, status);
 }
 
 void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,

@@ -14,7 +14,7 @@ Tolerances (derivations in the design notes):
   length-n dot product in FP64 with different summation orders;
 * FP32-evaluated entries: |dA_ij| <= 4e-6 |A_ij| (nodes rounded to FP32,
   one FP32 rsqrt and a few FP32 operations); products |dy_i| <= 4e-6 (|A||x|)_i;
-* leading Ritz values (top 10): relative 1e-12 (spec bar); all Ritz
+* leading Ritz values (top 10): relative 1e-12 (the required bar); all Ritz
   values: absolute 64 l eps s_1 (dense SVD accuracy of the oracle);
 * solution u at the evaluation points: relative 1e-8 at the oracle's lambda;
   coefficients: relative 1e-6.
@@ -306,7 +306,7 @@ def test_solve_hkt(mq, orc, name, make, mode):
     assert np.max(np.abs(out.sv[:10] - r.s[:10]) / r.s[:10]) < 1e-12
     assert out.lam == pytest.approx(r.lam, rel=1e-6)
     assert bool(out.flags & mq.MQH_INFO_GCV_AT_EDGE) == bool(r.flags & orc.FLAG_GCV_AT_EDGE)
-    # at the oracle's lambda the solutions agree to the spec bar
+    # at the oracle's lambda the solutions agree to the required 1e-8 bar
     r2, out2, u2, uo2 = _solve_both(mq, orc, p, mode, rule=mq.MQH_RULE_FIXED, lambda_fixed=r.lam)
     assert np.linalg.norm(u2 - uo2) <= 1e-8 * np.linalg.norm(uo2)
     assert np.linalg.norm(out2.coef - r2.coef) <= 1e-6 * np.linalg.norm(r2.coef)

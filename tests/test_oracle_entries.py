@@ -3,9 +3,9 @@
 Each check ties the oracle to something fixed by the paper or by
 mathematics, not to the oracle itself:
 * hand-worked closed-form values (tests/golden/mq_entries.txt);
-* the Laplacian as a finite-difference limit of the kernel (eq. Lphi: the
+* the Laplacian as a finite-difference limit of the kernel (eq. (7): the
   interior rows apply Lap + kappa^2 to phi);
-* rigid-motion invariance of A (entries depend only on distances, eq. MQ);
+* rigid-motion invariance of A (entries depend only on distances, eq. (3));
 * the interpolation matrix B having exactly one positive eigenvalue
   (the CPD(1) property of Section 4.1, with the sign the classical
   statement has: -B is conditionally positive definite);
@@ -88,7 +88,7 @@ def test_rigid_motion_invariance(orc):
 
 def test_interior_rows_apply_helmholtz_operator(orc):
     # Row i of H applied to coefficients c equals (Lap + kappa^2) of the expansion
-    # u(x) = sum_j c_j phi(|x - X_j|) at X_i (eqs. u_expansion, H_entries).
+    # u(x) = sum_j c_j phi(|x - X_j|) at X_i (eqs. (4), (8)).
     p = I.cube_scaled(12, 10, kappa=3.0, eps=1.5, ell=5)
     X = p.nodes
     c = I.random_vector(p.n, 3)
@@ -123,7 +123,7 @@ def test_mq_matrix_has_one_positive_eigenvalue(orc, eps):
 
 
 def test_interp_matrix_reproduces_data(orc):
-    # Interpolation (eq. B_matrix): coefficients solving B a = g reproduce g at the nodes via eval_u.
+    # Interpolation (eq. (5)): coefficients solving B a = g reproduce g at the nodes via eval_u.
     X = I.random_nodes_cube(60, 9)
     eps = 3.0
     B = orc.interp_matrix(X, X, eps)

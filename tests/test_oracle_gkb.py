@@ -3,7 +3,7 @@
 * products: the C loops against numpy's BLAS matmul of the same assembled
   matrix, entry-wise vs stored, sampled vs full;
 * the Krylov relations A Z = W C and A^T W_l = Z_l (C_l)_{1:l,1:l}^T, the
-  orthonormality of both bases and W^T f = beta_1 e_1 (eq. GKB and the
+  orthonormality of both bases and W^T f = beta_1 e_1 (eq. (26) and the
   projected-formulation remark of Section 4.2; the paper's second relation
   misses alpha_{l+1} z_{l+1} e_{l+1}^T in its last column, so it is checked
   on the first l columns);

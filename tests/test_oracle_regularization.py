@@ -4,14 +4,13 @@
   Tikhonov solution against the stacked least-squares problem
   [C; lambda I] y ~ [beta_1 e_1; 0] solved by LAPACK; rho_l^2 and eta_l^2
   against the residual and norm of that solution computed directly; the
-  trace of the explicit hat matrix against sum phi_i (eqs. rho_proj,
-  eta_proj, gcv_proj);
+  trace of the explicit hat matrix against sum phi_i (eqs. (28), (29), (30));
 * limits: lambda -> 0 gives the least-squares solution C^+ beta_1 e_1 and
   GCV_l(0) = f~_{l+1}^2; lambda -> inf gives lambda^2 y -> C^T beta_1 e_1
   and GCV_l(inf) = beta_1^2/(l+1)^2;
 * reduction to the textbook methods at l = N: HKT at fixed lambda equals
-  full Tikhonov (eq. tikh_solution) and Ine-TSVD at rank k equals TSVD
-  (eq. tsvd_solution), the full ones computed by LAPACK's SVD;
+  full Tikhonov (eq. (17)) and Ine-TSVD at rank k equals TSVD
+  (eq. (14)), the full ones computed by LAPACK's SVD;
 * GCV minimiser: closed form for l = 1, brute-force dense scan otherwise;
 * L-curve: analytic curvature against finite differences of
   (log rho, log eta) in log lambda; corner near the noise level of
