@@ -56,7 +56,8 @@ extern "C" {
 /* ---- operator modes (how A enters the products) ---- */
 #define MQH_OP_STORED_FP64 0   /* A assembled once in HBM (8 N^2 bytes, row-major), FP64 products */
 #define MQH_OP_MATFREE_FP64 1  /* entries regenerated inside every product, FP64 throughout */
-#define MQH_OP_MATFREE_FP32 2  /* entries evaluated in FP32, accumulated in FP64 */
+#define MQH_OP_MATFREE_FP32 2  /* entries evaluated in FP32 (the squared distances on the matrix
+                                  cores, FP32-accurate), accumulated in FP64 */
 
 /* ---- methods and parameter-choice rules ---- */
 #define MQH_METHOD_INE_TSVD 0 /* Algorithm 2 */
@@ -150,8 +151,9 @@ int mqh_apply(mqh_problem* p, int32_t trans, const double* x, double shift, cons
 /*
  * Rows [row0, row0 + count) of A as the problem's operator mode sees them
  * (the stored matrix, or entries generated the way the matrix-free products
- * generate them, FP32-evaluated in MQH_OP_MATFREE_FP32), written row-major
- * count x n to out.  For checks of the entry generator (eq. (8)).
+ * generate them; in MQH_OP_MATFREE_FP32 the entries by the direct FP32
+ * formula, which the products reproduce up to a few FP32 roundings), written
+ * row-major count x n to out.  For checks of the entry generator (eq. (8)).
  */
 int mqh_matrix_rows(mqh_problem* p, int64_t row0, int64_t count, double* out, uint32_t flags);
 

@@ -26,6 +26,10 @@ FLAGS = [
     "--offload-arch=gfx950",
     "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results straight into VGPRs (the product kernels read every
+    # result with VALU instructions; the accumulator-register form would add
+    # one move per value)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", INCLUDE,
     "-I", CSRC,
 ]

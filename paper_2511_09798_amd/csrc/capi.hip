@@ -7,7 +7,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "kernels.hpp"
@@ -91,6 +93,14 @@ struct mqh_problem {
     EntryConst ec{};
     double4* X64 = nullptr;
     float4* X32 = nullptr;
+    // FP32-evaluated products: nodes in Morton order within each class (FP32
+    // records), perm[q] = original index of sorted node q, one frame centre
+    // per block of kMfmFixed sorted nodes, and the weight-folded coefficients
+    // of the current product in the sorted order
+    float4* XS = nullptr;
+    int32_t* perm = nullptr;
+    float4* frames = nullptr;
+    float4* cf = nullptr;
     double* A = nullptr;
     int64_t lda = 0;
     // length-ldn vectors (zero past n)
@@ -149,18 +159,95 @@ void to_records(const mqh_problem* p, const double* xyz, int64_t m, double4* r64
     }
 }
 
+// Morton (Z-order) code of a point in a box, 10 bits per axis.
+uint32_t spread_bits10(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// Appends to perm the indices [a, b) of r sorted by Morton code over their
+// bounding box (stable, so ties keep the input order).
+void morton_order(const std::vector<double4>& r, int64_t a, int64_t b, std::vector<int32_t>& perm) {
+    if (b <= a) return;
+    double lo[3] = {r[a].x, r[a].y, r[a].z}, hi[3] = {lo[0], lo[1], lo[2]};
+    for (int64_t i = a; i < b; ++i) {
+        const double v[3] = {r[i].x, r[i].y, r[i].z};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = v[d] < lo[d] ? v[d] : lo[d];
+            hi[d] = v[d] > hi[d] ? v[d] : hi[d];
+        }
+    }
+    double ext = hi[0] - lo[0];
+    for (int d = 1; d < 3; ++d) ext = hi[d] - lo[d] > ext ? hi[d] - lo[d] : ext;
+    const double scale = ext > 0.0 ? 1024.0 / ext : 0.0;
+    std::vector<std::pair<uint32_t, int32_t>> key((size_t)(b - a));
+    for (int64_t i = a; i < b; ++i) {
+        const double v[3] = {r[i].x, r[i].y, r[i].z};
+        uint32_t code = 0;
+        for (int d = 0; d < 3; ++d) {
+            double s = (v[d] - lo[d]) * scale;
+            s = s < 0.0 ? 0.0 : (s > 1023.0 ? 1023.0 : s);
+            code |= spread_bits10((uint32_t)s) << d;
+        }
+        key[(size_t)(i - a)] = {code, (int32_t)i};
+    }
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint32_t, int32_t>& u, const std::pair<uint32_t, int32_t>& v) {
+                         return u.first < v.first;
+                     });
+    for (const auto& k : key) perm.push_back(k.second);
+}
+
+// Sorted records and one frame centre (bounding-box midpoint) per block of
+// kMfmFixed sorted nodes, interior blocks first.
+void sorted_layout(const std::vector<double4>& r, int64_t n, int64_t n_int, std::vector<int32_t>& perm,
+                   std::vector<float4>& rs32, std::vector<float4>& frames) {
+    perm.clear();
+    perm.reserve((size_t)n);
+    morton_order(r, 0, n_int, perm);
+    morton_order(r, n_int, n, perm);
+    std::vector<double4> rs((size_t)n);
+    rs32.resize((size_t)n);
+    for (int64_t q = 0; q < n; ++q) {
+        rs[(size_t)q] = r[(size_t)perm[(size_t)q]];
+        rs32[(size_t)q] = make_float4((float)rs[(size_t)q].x, (float)rs[(size_t)q].y, (float)rs[(size_t)q].z, 0.0f);
+    }
+    const int64_t nb_int = (n_int + kMfmFixed - 1) / kMfmFixed;
+    const int64_t nb = mfm_blocks(n, n_int);
+    frames.assign((size_t)nb, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+    for (int64_t b = 0; b < nb; ++b) {
+        const bool fint = b < nb_int;
+        const int64_t f0 = fint ? b * kMfmFixed : n_int + (b - nb_int) * kMfmFixed;
+        const int64_t fe = fint ? n_int : n;
+        const int64_t f1 = f0 + kMfmFixed < fe ? f0 + kMfmFixed : fe;
+        double lo[3] = {rs[f0].x, rs[f0].y, rs[f0].z}, hi[3] = {lo[0], lo[1], lo[2]};
+        for (int64_t i = f0; i < f1; ++i) {
+            const double v[3] = {rs[i].x, rs[i].y, rs[i].z};
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = v[d] < lo[d] ? v[d] : lo[d];
+                hi[d] = v[d] > hi[d] ? v[d] : hi[d];
+            }
+        }
+        frames[(size_t)b] = make_float4((float)(0.5 * (lo[0] + hi[0])), (float)(0.5 * (lo[1] + hi[1])),
+                                        (float)(0.5 * (lo[2] + hi[2])), 0.0f);
+    }
+}
+
 void choose_shapes(mqh_problem* p) {
     const int64_t n = p->n;
-    // Enough blocks for many rounds of 8 resident waves per SIMD over 256
-    // CUs (the FP32 products want more, shorter slices).
-    const int64_t target_blocks = p->mode == MQH_OP_MATFREE_FP32 ? 32768 : 4096;
-    // FP32-evaluated products: kMf32Rows outputs per lane and slices made of
-    // whole LDS tiles; FP64 ones: one output per lane, slices of even length.
+    // Enough blocks for many rounds of resident waves over 256 CUs.
     const bool f32 = p->mode == MQH_OP_MATFREE_FP32;
-    const int64_t per_block = f32 ? (int64_t)kBlock * kMf32Rows : kBlock;
+    const int64_t target_blocks = f32 ? 24576 : 4096;
+    // FP32-evaluated products: blocks of kMfmFixed sorted nodes and slices of
+    // whole LDS chunks; FP64 ones: one output per lane, slices of even length.
     const int64_t quantum = f32 ? kBlock : 2;
-    const int64_t nb_rows = (p->n_int + per_block - 1) / per_block + (p->n_bnd + per_block - 1) / per_block;
-    const int64_t nb_cols = (n + per_block - 1) / per_block;
+    const int64_t nb_rows = f32 ? mfm_blocks(n, p->n_int)
+                                : (p->n_int + kBlock - 1) / kBlock + (p->n_bnd + kBlock - 1) / kBlock;
+    const int64_t nb_cols = f32 ? mfm_blocks(n, p->n_int) : (n + kBlock - 1) / kBlock;
     auto pick = [&](int64_t nb, int& S, int64_t& len) {
         int64_t s = (target_blocks + nb - 1) / nb;
         if (s < 1) s = 1;
@@ -192,6 +279,12 @@ void choose_shapes(mqh_problem* p) {
 int op_product(mqh_problem* p, int trans, const double* x, const double* shift_ptr, double shift_val, const double* z,
                double* y, const GkbState* st, bool timed) {
     hipStream_t s = p->stream;
+    if (p->mode == MQH_OP_MATFREE_FP32) {
+        // x into the sorted node order, folded into the entry coefficients
+        // (outside the timed span)
+        launch_gather_coef(x, p->perm, p->n, p->ec, p->cf, st, s);
+        LAUNCHCHK("gather");
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         size_t k = p->pev.size();
@@ -213,24 +306,28 @@ int op_product(mqh_problem* p, int trans, const double* x, const double* shift_p
             launch_stored_cols(p->A, p->lda, p->n, x, p->stored_tile_rows, p->stored_tiles, p->P, p->ldn, st, s);
             LAUNCHCHK("stored columns product");
             if (timed) HIPCHK(hipEventRecord(e1, s));
-            launch_reduce_slices(p->P, p->ldn, p->stored_tiles, p->n, shift_ptr, shift_val, z, y, st, s);
+            launch_reduce_slices(p->P, p->ldn, p->stored_tiles, p->n, nullptr, shift_ptr, shift_val, z, y, st, s);
             LAUNCHCHK("slice reduction");
         }
         return MQH_OK;
     }
-    const int prec = p->mode == MQH_OP_MATFREE_FP64 ? 64 : 32;
-    const void* X = prec == 64 ? (const void*)p->X64 : (const void*)p->X32;
     int S;
-    if (!trans) {
+    const int32_t* perm = nullptr;
+    if (p->mode == MQH_OP_MATFREE_FP32) {
+        S = trans ? p->S_cols : p->S_rows;
+        launch_mfm_product(trans, p->XS, p->frames, p->cf, p->n, p->n_int, S, trans ? p->slice_cols : p->slice_rows,
+                           p->P, p->ldn, st, s);
+        perm = p->perm;
+    } else if (!trans) {
         S = p->S_rows;
-        launch_mf_rows(prec, X, x, p->n, p->n_int, S, p->slice_rows, p->ec, p->P, p->ldn, st, s);
+        launch_mf_rows(p->X64, x, p->n, p->n_int, S, p->slice_rows, p->ec, p->P, p->ldn, st, s);
     } else {
         S = p->S_cols;
-        launch_mf_cols(prec, X, x, p->n, p->n_int, S, p->slice_cols, p->ec, p->P, p->ldn, st, s);
+        launch_mf_cols(p->X64, x, p->n, p->n_int, S, p->slice_cols, p->ec, p->P, p->ldn, st, s);
     }
     LAUNCHCHK("matrix-free product");
     if (timed) HIPCHK(hipEventRecord(e1, s));
-    launch_reduce_slices(p->P, p->ldn, S, p->n, shift_ptr, shift_val, z, y, st, s);
+    launch_reduce_slices(p->P, p->ldn, S, p->n, perm, shift_ptr, shift_val, z, y, st, s);
     LAUNCHCHK("slice reduction");
     return MQH_OK;
 }
@@ -358,6 +455,10 @@ int mqh_problem_destroy(mqh_problem* p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     dfree(p->X64);
     dfree(p->X32);
+    dfree(p->XS);
+    dfree(p->perm);
+    dfree(p->frames);
+    dfree(p->cf);
     dfree(p->A);
     dfree(p->vx);
     dfree(p->vy);
@@ -476,6 +577,22 @@ int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, 
         (e = hipMemsetAsync(p->vz, 0, (size_t)p->ldn * sizeof(double), p->stream)) ||
         (e = hipMemsetAsync(p->coef, 0, (size_t)p->ldn * sizeof(double), p->stream)))
         return bail(hip_fail(e, "upload"));
+    if (op_mode == MQH_OP_MATFREE_FP32) {
+        std::vector<int32_t> perm;
+        std::vector<float4> rs, frames;
+        sorted_layout(r64, n, n_int, perm, rs, frames);
+        if ((rc = dalloc(&p->XS, (size_t)n))) return bail(rc);
+        if ((rc = dalloc(&p->perm, (size_t)n))) return bail(rc);
+        if ((rc = dalloc(&p->frames, frames.size()))) return bail(rc);
+        if ((rc = dalloc(&p->cf, (size_t)n))) return bail(rc);
+        if ((e = hipMemcpyAsync(p->XS, rs.data(), (size_t)n * sizeof(float4), hipMemcpyHostToDevice, p->stream)) ||
+            (e = hipMemcpyAsync(p->perm, perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice,
+                                p->stream)) ||
+            (e = hipMemcpyAsync(p->frames, frames.data(), frames.size() * sizeof(float4), hipMemcpyHostToDevice,
+                                p->stream)) ||
+            (e = hipStreamSynchronize(p->stream)))
+            return bail(hip_fail(e, "upload of the sorted layout"));
+    }
     if (op_mode == MQH_OP_STORED_FP64) {
         p->lda = p->ldn;
         if ((rc = dalloc(&p->A, (size_t)(n * p->lda)))) return bail(rc);
@@ -715,7 +832,7 @@ int mqh_eval(mqh_problem* p, const double* coef, const double* x_eval, int64_t m
     HIPCHK(hipMemcpyAsync(p->E, rec.data(), (size_t)m * sizeof(double4), hipMemcpyHostToDevice, s));
     launch_eval_partial(p->X64, p->vx, p->n, p->E, m, (int)S, len, p->ec, p->EP, ldm, s);
     LAUNCHCHK("evaluation");
-    launch_reduce_slices(p->EP, ldm, (int)S, m, nullptr, 0.0, nullptr, p->u, nullptr, s);
+    launch_reduce_slices(p->EP, ldm, (int)S, m, nullptr, nullptr, 0.0, nullptr, p->u, nullptr, s);
     LAUNCHCHK("evaluation reduction");
     HIPCHK(hipMemcpyAsync(u, p->u, (size_t)m * sizeof(double), kind_out(flags), s));
     HIPCHK(hipStreamSynchronize(s));

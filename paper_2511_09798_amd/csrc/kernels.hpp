@@ -9,7 +9,8 @@ namespace mqh {
 
 constexpr int kMaxEll = 1024;   // largest projected problem (Golub-Kahan steps)
 constexpr int kMaxGrid = 4096;  // largest lambda grid
-constexpr int kMf32Rows = 1;    // outputs per lane in the FP32-evaluated matrix-free products
+constexpr int kMfmFt = 2;       // 16-node fixed tiles per wave in the FP32-evaluated products
+constexpr int kMfmFixed = (kBlock / kWave) * kMfmFt * 16;  // fixed nodes per block (128)
 
 // Result of the parameter choice, device-resident.
 struct ParamOut {
@@ -22,12 +23,19 @@ struct ParamOut {
 };
 
 // operator (op_kernels.hip)
-void launch_mf_rows(int prec, const void* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
+void launch_mf_rows(const double4* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
                     const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s);
-void launch_mf_cols(int prec, const void* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
+void launch_mf_cols(const double4* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
                     const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s);
-void launch_reduce_slices(const double* P, int64_t ldp, int S, int64_t n, const double* shift_ptr,
-                          double shift_val, const double* z, double* y, const GkbState* st, hipStream_t s);
+int64_t mfm_blocks(int64_t n, int64_t n_int);
+void launch_gather_coef(const double* x, const int32_t* perm, int64_t n, const EntryConst& c, float4* CF,
+                        const GkbState* st, hipStream_t s);
+void launch_mfm_product(int trans, const float4* XS, const float4* frames, const float4* CF, int64_t n,
+                        int64_t n_int, int S, int64_t slice_len, double* P, int64_t ldp, const GkbState* st,
+                        hipStream_t s);
+void launch_reduce_slices(const double* P, int64_t ldp, int S, int64_t n, const int32_t* perm,
+                          const double* shift_ptr, double shift_val, const double* z, double* y,
+                          const GkbState* st, hipStream_t s);
 void launch_assemble(const double4* X, int64_t n, int64_t n_int, int64_t lda, const EntryConst& c, double* A,
                      hipStream_t s);
 void launch_stored_rows(int rw, const double* A, int64_t lda, int64_t n, const double* x, const double* shift_ptr,

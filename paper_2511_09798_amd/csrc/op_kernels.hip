@@ -89,12 +89,13 @@ __global__ __launch_bounds__(kBlock) void k_mf_cols(const typename NodeOf<R>::ty
     if (valid) P[(int64_t)blockIdx.y * ldp + col] = a0 + a1;
 }
 
-// y_i = sum_s P[s][i] - shift * z_i  (shift from *shift_ptr when given);
-// the slices are summed in four interleaved groups combined in a fixed order.
+// y_o = sum_s P[s][i] - shift * z_o with o = perm[i] (o = i when perm is
+// null; shift from *shift_ptr when given); the slices are summed in four
+// interleaved groups combined in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_reduce_slices(const double* __restrict__ P, int64_t ldp, int S,
-                                                          int64_t n, const double* __restrict__ shift_ptr,
-                                                          double shift_val, const double* __restrict__ z,
-                                                          double* __restrict__ y,
+                                                          int64_t n, const int32_t* __restrict__ perm,
+                                                          const double* __restrict__ shift_ptr, double shift_val,
+                                                          const double* __restrict__ z, double* __restrict__ y,
                                                           const GkbState* __restrict__ st) {
     if (st != nullptr && st->stopped) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -109,154 +110,273 @@ __global__ __launch_bounds__(kBlock) void k_reduce_slices(const double* __restri
     }
     for (; k < S; ++k) a0 += P[(int64_t)k * ldp + i];
     double s = (a0 + a1) + (a2 + a3);
+    const int64_t o = perm != nullptr ? (int64_t)perm[i] : i;
     if (z != nullptr) {
         const double sh = shift_ptr != nullptr ? *shift_ptr : shift_val;
-        s -= sh * z[i];
+        s -= sh * z[o];
     }
-    y[i] = s;
+    y[o] = s;
 }
 
 // ---------------------------------------------------------------------------
-// FP32-evaluated matrix-free products.  On gfx950 an FP32 VALU instruction
-// can be issued together with another one only when it reads no scalar
-// register, so the loop nodes are staged through LDS (broadcast reads into
-// vector registers) instead of scalar loads.  Each lane owns R outputs; the
-// weight w_j of a loop node is folded into the entry coefficients
-// (interior: (w kappa^2 t + 2 w eps^2 + w eps^2 s^2) s, boundary: w sqrt(t)),
-// the products are summed in FP32 over blocks of kFlush loop nodes and each
-// block sum is added to an FP64 accumulator.
+// FP32-evaluated matrix-free products on the matrix cores.
+//
+// Nodes are visited in a spatially sorted order (Morton order within each
+// class, interior first) and cut into blocks of kMfmFixed "fixed" nodes (the
+// outputs: rows for A x, columns for A^T x), each with a frame centre c among
+// its nodes.  With d = P - c (P the eps-scaled node, in FP32),
+//     t_ij = 1 + |d_i - d_j|^2 = |d_i|^2 + sum_k a_ik b_kj,
+//     a_i = (-2 d_i, 1),  b_j = (d_j, 1 + |d_j|^2),
+// a K = 4 contraction per 16 x 16 tile of entries.  Each FP32 factor is split
+// exactly into three bf16 parts by truncation (h = top 8 significant bits,
+// m = next 8, l = the last 8), and the eight cross products that matter at
+// FP32 precision (all but l*l, 2^-32 relative) are laid out along K = 32 of
+// one v_mfma_f32_16x16x32_bf16: t comes out with FP32 accuracy at half the
+// matrix-core time of the FP32 MFMA.  Close pairs have small |d_i|, |d_j|
+// (the frame sits among the fixed nodes), so t keeps its relative accuracy
+// where 1 + eps^2 r^2 is near 1.  The entry is evaluated on the VALU from t
+// (interior: (w kappa^2 t + 2 w eps^2 + w eps^2 s^2) s with s = t^(-1/2);
+// boundary: w sqrt(t)), summed in FP32 over the 16 loop nodes a lane sees per
+// chunk, then in FP64.
+//
+// Lane layout of v_mfma_f32_16x16x32_bf16 (wave64): lane l holds A[l%16][k]
+// and B[k][l%16] for k = 8(l/16) .. 8(l/16)+7, and D[4(l/16)+r][l%16],
+// r = 0..3.  Lane group g = l/16 carries coordinate g (g < 3) or the
+// 1 * (1 + |d_j|^2) term (g = 3).
 // ---------------------------------------------------------------------------
 
-constexpr int kTile = kBlock;  // loop nodes staged per round (one per thread)
-constexpr int kFlush = 16;     // FP32 block length before the FP64 accumulation
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Accumulates, for every output r of this lane, sum over loop nodes j in
-// [j0, j1) of w_j * entry(P_r, X_j) with the entry kind INTERIOR.  j0, j1
-// are block-uniform (contains barriers).
-template <int R, bool INTERIOR>
-__device__ __forceinline__ void mf32_span(const float4* __restrict__ X, const double* __restrict__ w, int64_t j0,
-                                          int64_t j1, const float (&px)[R], const float (&py)[R],
-                                          const float (&pz)[R], const EntryConst& c, double (&acc)[R],
-                                          float4* __restrict__ lds0, float2* __restrict__ lds1) {
-    for (int64_t t0 = j0; t0 < j1; t0 += kTile) {
+constexpr int kMfmChunk = kBlock;  // loop nodes staged in LDS per round (one per thread)
+
+// Exact split x = h + m + l of a finite FP32 value into three bf16 values,
+// returned as FP32 bit patterns with zero low halves: h keeps the top 16 bits
+// of x, m those of x - h (exact), l = x - h - m (exact, at most 8 significant
+// bits).
+__device__ __forceinline__ void split_bf16x3(float x, unsigned& h, unsigned& m, unsigned& l) {
+    h = __float_as_uint(x) & 0xFFFF0000u;
+    const float r1 = x - __uint_as_float(h);
+    m = __float_as_uint(r1) & 0xFFFF0000u;
+    l = __float_as_uint(r1 - __uint_as_float(m));
+}
+
+// Two bf16 values in one dword: lo's high half in bits 0..15, hi's in 16..31.
+__device__ __forceinline__ unsigned pack_bf16(unsigned lo, unsigned hi) {
+    return __builtin_amdgcn_perm(hi, lo, 0x07060302u);
+}
+
+// Eight K slots of one coordinate: the cross products
+// (h,h) (h,m) (m,h) (h,l) (l,h) (m,m) (m,l) (l,m) of a (fixed side) and b.
+__device__ __forceinline__ v4u fixed_terms(float a) {
+    unsigned h, m, l;
+    split_bf16x3(a, h, m, l);
+    v4u r;
+    r[0] = pack_bf16(h, h);
+    r[1] = pack_bf16(m, h);
+    r[2] = pack_bf16(l, m);
+    r[3] = pack_bf16(m, l);
+    return r;
+}
+__device__ __forceinline__ v4u loop_terms(float b) {
+    unsigned h, m, l;
+    split_bf16x3(b, h, m, l);
+    v4u r;
+    r[0] = pack_bf16(h, m);
+    r[1] = pack_bf16(h, l);
+    r[2] = pack_bf16(h, m);
+    r[3] = pack_bf16(l, m);
+    return r;
+}
+
+// Accumulates, for the 4 * kMfmFt fixed nodes of this lane, the sum over loop
+// nodes j in [j0, j1) (a lane sees the loop nodes j = l mod 16) of
+// w_j * entry, the entry kind INTERIOR.  CF holds the weight-folded
+// coefficients (w kappa^2, 2 w eps^2, w eps^2, w) of every sorted node.
+// j0, j1 are block-uniform (contains barriers).
+template <bool INTERIOR>
+__device__ __forceinline__ void mfm_span(const float4* __restrict__ XS, const float4* __restrict__ CF, int64_t j0,
+                                         int64_t j1, const float4& fr, const v4u (&a)[kMfmFt],
+                                         const v4f (&C)[kMfmFt], double (&acc)[kMfmFt][4],
+                                         v4u* __restrict__ lds_b, float4* __restrict__ lds_c) {
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15;
+    for (int64_t t0 = j0; t0 < j1; t0 += kMfmChunk) {
+        // stage one loop node per thread: B operand (4 lane groups x 8 bf16)
+        // and its coefficients; nodes past j1 get d = 0, w = 0
         const int64_t j = t0 + threadIdx.x;
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-        float2 b = make_float2(0.f, 0.f);
+        float dx = 0.f, dy = 0.f, dz = 0.f;
+        float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
         if (j < j1) {
-            const float4 q = X[j];
-            const double wj = w[j];
-            if (INTERIOR) {
-                a = make_float4(q.x, q.y, q.z, (float)(wj * c.k2));
-                b = make_float2((float)(wj * c.e2x2), (float)(wj * c.e2));
-            } else {
-                a = make_float4(q.x, q.y, q.z, (float)wj);
-            }
+            const float4 q = XS[j];
+            cf = CF[j];
+            dx = q.x - fr.x;
+            dy = q.y - fr.y;
+            dz = q.z - fr.z;
         }
-        __syncthreads();  // the previous tile has been consumed
-        lds0[threadIdx.x] = a;
-        if (INTERIOR) lds1[threadIdx.x] = b;
+        const v4u b0 = loop_terms(dx), b1 = loop_terms(dy), b2 = loop_terms(dz);
+        unsigned h, m, l;
+        split_bf16x3(fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 1.0f))), h, m, l);
+        v4u b3;
+        b3[0] = pack_bf16(h, m);
+        b3[1] = l >> 16;
+        b3[2] = 0u;
+        b3[3] = 0u;
+        __syncthreads();  // the previous chunk has been consumed
+        lds_b[threadIdx.x * 4 + 0] = b0;
+        lds_b[threadIdx.x * 4 + 1] = b1;
+        lds_b[threadIdx.x * 4 + 2] = b2;
+        lds_b[threadIdx.x * 4 + 3] = b3;
+        lds_c[threadIdx.x] = cf;
         __syncthreads();
-        const int64_t rem = j1 - t0;
-        const int cnt = rem < kTile ? (int)rem : kTile;
-        const int cnt_pad = (cnt + kFlush - 1) / kFlush * kFlush;  // padded nodes carry w = 0
-        for (int k0 = 0; k0 < cnt_pad; k0 += kFlush) {
-            float s32[R];
+        // 16 tiles of 16 loop nodes; the next tile's products are issued
+        // before this tile's entries are evaluated
+        float s32[kMfmFt][4];
 #pragma unroll
-            for (int r = 0; r < R; ++r) s32[r] = 0.f;
+        for (int f = 0; f < kMfmFt; ++f)
 #pragma unroll
-            for (int k = k0; k < k0 + kFlush; ++k) {
-                const float4 q = lds0[k];
-                float2 qb = make_float2(0.f, 0.f);
-                if (INTERIOR) qb = lds1[k];
+            for (int r = 0; r < 4; ++r) s32[f][r] = 0.f;
+        float4 q = lds_c[jj];
+        v4f t[kMfmFt];
+        {
+            const v8bf bk = __builtin_bit_cast(v8bf, lds_b[jj * 4 + g]);
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const float dx = px[r] - q.x, dy = py[r] - q.y, dz = pz[r] - q.z;
-                    const float t = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 1.0f)));
+            for (int f = 0; f < kMfmFt; ++f)
+                t[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[f]), bk, C[f], 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kMfmChunk / 16; ++u) {
+            v4f tn[kMfmFt];
+            float4 qn = q;
+            if (u + 1 < kMfmChunk / 16) {
+                const v8bf bn = __builtin_bit_cast(v8bf, lds_b[((u + 1) * 16 + jj) * 4 + g]);
+                qn = lds_c[(u + 1) * 16 + jj];
+#pragma unroll
+                for (int f = 0; f < kMfmFt; ++f)
+                    tn[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[f]), bn, C[f], 0, 0, 0);
+            }
+#pragma unroll
+            for (int f = 0; f < kMfmFt; ++f) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
                     if (INTERIOR) {
-                        const float s = __builtin_amdgcn_rsqf(t);
-                        const float inner = fmaf(qb.y, s * s, fmaf(q.w, t, qb.x));
-                        s32[r] = fmaf(inner, s, s32[r]);
+                        const float s = __builtin_amdgcn_rsqf(t[f][r]);
+                        const float inner = fmaf(q.z, s * s, fmaf(q.x, t[f][r], q.y));
+                        s32[f][r] = fmaf(inner, s, s32[f][r]);
                     } else {
-                        s32[r] = fmaf(__builtin_amdgcn_sqrtf(t), q.w, s32[r]);
+                        s32[f][r] = fmaf(__builtin_amdgcn_sqrtf(t[f][r]), q.w, s32[f][r]);
                     }
                 }
             }
+            if (u + 1 < kMfmChunk / 16) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += (double)s32[r];
+                for (int f = 0; f < kMfmFt; ++f) t[f] = tn[f];
+                q = qn;
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < kMfmFt; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[f][r] += (double)s32[f][r];
+    }
+}
+
+// Partial products in sorted order: P[slice][q] for fixed node q of block
+// blockIdx.x (blocks [0, nb_int) hold interior nodes, the rest boundary
+// ones).  ROWS: y = A x (entry kind from the fixed row); otherwise
+// y = A^T x (entry kind from the loop row; the loop range is split at n_int).
+template <bool ROWS>
+__global__ __launch_bounds__(kBlock) void k_mfm(const float4* __restrict__ XS, const float4* __restrict__ CF,
+                                                int64_t n, int64_t n_int, int64_t nb_int, int64_t slice_len,
+                                                const float4* __restrict__ frames, double* __restrict__ P,
+                                                int64_t ldp, const GkbState* __restrict__ st) {
+    __shared__ v4u lds_b[4 * kMfmChunk];
+    __shared__ float4 lds_c[kMfmChunk];
+    if (st != nullptr && st->stopped) return;
+    const int64_t b = blockIdx.x;
+    const bool fint = b < nb_int;
+    const int64_t fb0 = fint ? b * kMfmFixed : n_int + (b - nb_int) * kMfmFixed;
+    const int64_t fend = fint ? n_int : n;
+    const int64_t fb1 = fb0 + kMfmFixed < fend ? fb0 + kMfmFixed : fend;
+    const float4 fr = frames[b];
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15, wv = threadIdx.x / kWave;
+    v4u a[kMfmFt];
+    v4f C[kMfmFt];
+    double acc[kMfmFt][4];
+#pragma unroll
+    for (int f = 0; f < kMfmFt; ++f) {
+        const int64_t base = fb0 + (int64_t)(wv * kMfmFt + f) * 16;
+        const int64_t i = base + jj;
+        float d[3] = {0.f, 0.f, 0.f};
+        if (i < fb1) {
+            const float4 q = XS[i];
+            d[0] = q.x - fr.x;
+            d[1] = q.y - fr.y;
+            d[2] = q.z - fr.z;
+        }
+        if (g < 3) {
+            a[f] = fixed_terms(-2.0f * d[g]);
+        } else {
+            const unsigned one = 0x3F80u;  // bf16 1.0
+            a[f][0] = one | (one << 16);
+            a[f][1] = one;
+            a[f][2] = 0u;
+            a[f][3] = 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i2 = base + 4 * g + r;
+            float d2 = 0.f;
+            if (i2 < fb1) {
+                const float4 q = XS[i2];
+                const float ex = q.x - fr.x, ey = q.y - fr.y, ez = q.z - fr.z;
+                d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+            }
+            C[f][r] = d2;
+            acc[f][r] = 0.0;
+        }
+    }
+    const int64_t j0 = (int64_t)blockIdx.y * slice_len;
+    const int64_t j1 = j0 + slice_len < n ? j0 + slice_len : n;
+    if (ROWS) {
+        if (fint)
+            mfm_span<true>(XS, CF, j0, j1, fr, a, C, acc, lds_b, lds_c);
+        else
+            mfm_span<false>(XS, CF, j0, j1, fr, a, C, acc, lds_b, lds_c);
+    } else {
+        const int64_t m1 = j1 < n_int ? j1 : n_int;
+        if (j0 < m1) mfm_span<true>(XS, CF, j0, m1, fr, a, C, acc, lds_b, lds_c);
+        const int64_t m0 = j0 > n_int ? j0 : n_int;
+        if (m0 < j1) mfm_span<false>(XS, CF, m0, j1, fr, a, C, acc, lds_b, lds_c);
+    }
+    // sum each fixed node's 16 lane partials (fixed order) through LDS
+    double* red = reinterpret_cast<double*>(lds_b);  // 64 nodes x 17 (padded) doubles
+#pragma unroll
+    for (int f = 0; f < kMfmFt; ++f) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[(wv * 16 + 4 * g + r) * 17 + jj] = acc[f][r];
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int node = threadIdx.x;
+            double s = 0.0;
+            for (int q = 0; q < 16; ++q) s += red[node * 17 + q];
+            const int64_t i = fb0 + (int64_t)((node >> 4) * kMfmFt + f) * 16 + (node & 15);
+            if (i < fb1) P[(int64_t)blockIdx.y * ldp + i] = s;
         }
     }
 }
 
-// y = A x partials, FP32 entries: a block owns kBlock * R rows of one kind.
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_mf32_rows(const float4* __restrict__ X, const double* __restrict__ x,
-                                                      int64_t n, int64_t n_int, int64_t nb_int, int64_t slice_len,
-                                                      EntryConst c, double* __restrict__ P, int64_t ldp,
-                                                      const GkbState* __restrict__ st) {
-    __shared__ float4 lds0[kTile];
-    __shared__ float2 lds1[kTile];
+// CF[q] = (w kappa^2, 2 w eps^2, w eps^2, w) with w = x[perm[q]]: the
+// weight-folded entry coefficients of the sorted nodes for one product.
+__global__ __launch_bounds__(kBlock) void k_gather_coef(const double* __restrict__ x,
+                                                        const int32_t* __restrict__ perm, int64_t n, EntryConst c,
+                                                        float4* __restrict__ CF, const GkbState* __restrict__ st) {
     if (st != nullptr && st->stopped) return;
-    const int64_t b = blockIdx.x;
-    const bool interior = b < nb_int;
-    const int64_t base = interior ? b * kBlock * R : n_int + (b - nb_int) * kBlock * R;
-    const int64_t row_end = interior ? n_int : n;
-    float px[R], py[R], pz[R];
-    double acc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t row = base + r * kBlock + threadIdx.x;
-        const float4 q = X[row < row_end ? row : 0];
-        px[r] = q.x;
-        py[r] = q.y;
-        pz[r] = q.z;
-        acc[r] = 0.0;
-    }
-    const int64_t j0 = (int64_t)blockIdx.y * slice_len;
-    const int64_t j1 = j0 + slice_len < n ? j0 + slice_len : n;
-    if (interior)
-        mf32_span<R, true>(X, x, j0, j1, px, py, pz, c, acc, lds0, lds1);
-    else
-        mf32_span<R, false>(X, x, j0, j1, px, py, pz, c, acc, lds0, lds1);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t row = base + r * kBlock + threadIdx.x;
-        if (row < row_end) P[(int64_t)blockIdx.y * ldp + row] = acc[r];
-    }
-}
-
-// y = A^T x partials, FP32 entries: a block owns kBlock * R columns; the loop
-// runs over the slice's interior rows, then its boundary rows.
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_mf32_cols(const float4* __restrict__ X, const double* __restrict__ x,
-                                                      int64_t n, int64_t n_int, int64_t slice_len, EntryConst c,
-                                                      double* __restrict__ P, int64_t ldp,
-                                                      const GkbState* __restrict__ st) {
-    __shared__ float4 lds0[kTile];
-    __shared__ float2 lds1[kTile];
-    if (st != nullptr && st->stopped) return;
-    const int64_t base = (int64_t)blockIdx.x * kBlock * R;
-    float px[R], py[R], pz[R];
-    double acc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t col = base + r * kBlock + threadIdx.x;
-        const float4 q = X[col < n ? col : 0];
-        px[r] = q.x;
-        py[r] = q.y;
-        pz[r] = q.z;
-        acc[r] = 0.0;
-    }
-    const int64_t i0 = (int64_t)blockIdx.y * slice_len;
-    const int64_t i1 = i0 + slice_len < n ? i0 + slice_len : n;
-    const int64_t m1 = i1 < n_int ? i1 : n_int;
-    if (i0 < m1) mf32_span<R, true>(X, x, i0, m1, px, py, pz, c, acc, lds0, lds1);
-    const int64_t m0 = i0 > n_int ? i0 : n_int;
-    if (m0 < i1) mf32_span<R, false>(X, x, m0, i1, px, py, pz, c, acc, lds0, lds1);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t col = base + r * kBlock + threadIdx.x;
-        if (col < n) P[(int64_t)blockIdx.y * ldp + col] = acc[r];
-    }
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const double w = x[perm[q]];
+    CF[q] = make_float4((float)(w * c.k2), (float)(w * c.e2x2), (float)(w * c.e2), (float)w);
 }
 
 // ---------------------------------------------------------------------------
@@ -401,33 +521,45 @@ __global__ __launch_bounds__(kBlock) void k_eval_partial(const double4* __restri
 // Host launchers
 // ---------------------------------------------------------------------------
 
-void launch_mf_rows(int prec, const void* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
+void launch_mf_rows(const double4* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
                     const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s) {
-    const int64_t rows_per_block = prec == 64 ? kBlock : (int64_t)kBlock * kMf32Rows;
-    const int64_t nb_int = (n_int + rows_per_block - 1) / rows_per_block;
-    const int64_t nb_bnd = (n - n_int + rows_per_block - 1) / rows_per_block;
+    const int64_t nb_int = (n_int + kBlock - 1) / kBlock;
+    const int64_t nb_bnd = (n - n_int + kBlock - 1) / kBlock;
     dim3 grid((unsigned)(nb_int + nb_bnd), (unsigned)S);
-    if (prec == 64)
-        k_mf_rows<double><<<grid, kBlock, 0, s>>>((const double4*)X, x, n, n_int, nb_int, slice_len, c, P, ldp, st);
-    else
-        k_mf32_rows<kMf32Rows><<<grid, kBlock, 0, s>>>((const float4*)X, x, n, n_int, nb_int, slice_len, c, P, ldp,
-                                                       st);
+    k_mf_rows<double><<<grid, kBlock, 0, s>>>(X, x, n, n_int, nb_int, slice_len, c, P, ldp, st);
 }
 
-void launch_mf_cols(int prec, const void* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
+void launch_mf_cols(const double4* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
                     const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s) {
-    const int64_t cols_per_block = prec == 64 ? kBlock : (int64_t)kBlock * kMf32Rows;
-    dim3 grid((unsigned)((n + cols_per_block - 1) / cols_per_block), (unsigned)S);
-    if (prec == 64)
-        k_mf_cols<double><<<grid, kBlock, 0, s>>>((const double4*)X, x, n, n_int, slice_len, c, P, ldp, st);
-    else
-        k_mf32_cols<kMf32Rows><<<grid, kBlock, 0, s>>>((const float4*)X, x, n, n_int, slice_len, c, P, ldp, st);
+    dim3 grid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)S);
+    k_mf_cols<double><<<grid, kBlock, 0, s>>>(X, x, n, n_int, slice_len, c, P, ldp, st);
 }
 
-void launch_reduce_slices(const double* P, int64_t ldp, int S, int64_t n, const double* shift_ptr,
-                          double shift_val, const double* z, double* y, const GkbState* st, hipStream_t s) {
-    k_reduce_slices<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(P, ldp, S, n, shift_ptr, shift_val, z,
-                                                                            y, st);
+int64_t mfm_blocks(int64_t n, int64_t n_int) {
+    return (n_int + kMfmFixed - 1) / kMfmFixed + (n - n_int + kMfmFixed - 1) / kMfmFixed;
+}
+
+void launch_gather_coef(const double* x, const int32_t* perm, int64_t n, const EntryConst& c, float4* CF,
+                        const GkbState* st, hipStream_t s) {
+    k_gather_coef<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, perm, n, c, CF, st);
+}
+
+void launch_mfm_product(int trans, const float4* XS, const float4* frames, const float4* CF, int64_t n,
+                        int64_t n_int, int S, int64_t slice_len, double* P, int64_t ldp, const GkbState* st,
+                        hipStream_t s) {
+    const int64_t nb_int = (n_int + kMfmFixed - 1) / kMfmFixed;
+    dim3 grid((unsigned)mfm_blocks(n, n_int), (unsigned)S);
+    if (trans)
+        k_mfm<false><<<grid, kBlock, 0, s>>>(XS, CF, n, n_int, nb_int, slice_len, frames, P, ldp, st);
+    else
+        k_mfm<true><<<grid, kBlock, 0, s>>>(XS, CF, n, n_int, nb_int, slice_len, frames, P, ldp, st);
+}
+
+void launch_reduce_slices(const double* P, int64_t ldp, int S, int64_t n, const int32_t* perm,
+                          const double* shift_ptr, double shift_val, const double* z, double* y,
+                          const GkbState* st, hipStream_t s) {
+    k_reduce_slices<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(P, ldp, S, n, perm, shift_ptr,
+                                                                            shift_val, z, y, st);
 }
 
 void launch_assemble(const double4* X, int64_t n, int64_t n_int, int64_t lda, const EntryConst& c, double* A,

@@ -357,6 +357,15 @@ def test_edge_sizes(mq, orc, n_int, n_bnd):
     X = I.random_nodes_cube(n_int + n_bnd, 900 + n_int)
     f = I.random_vector(n_int + n_bnd, 901)
     ell = min(5, n_int + n_bnd)
+    for mode in ("matfree_fp32",):
+        say("edge sizes", n_int, n_bnd, mode)
+        with mq.Problem(X[:n_int] if n_int else None, X[n_int:] if n_bnd else None, 2.0, 3.0, mode) as pr:
+            ys = [pr.apply(f, trans=t) for t in (False, True)]
+        A = orc.assemble(X, n_int, 2.0, 3.0)
+        for t, y in zip((False, True), ys):
+            ref = orc.apply(None, X, n_int, 2.0, 3.0, f, trans=t)
+            scale = (A.T if t else A) @ np.abs(f)  # all entries are positive
+            assert np.all(np.abs(y - ref) <= 4e-6 * scale)
     for mode in ("stored_fp64", "matfree_fp64"):
         say("edge sizes", n_int, n_bnd, mode)
         with mq.Problem(X[:n_int] if n_int else None, X[n_int:] if n_bnd else None, 2.0, 3.0, mode) as pr:
@@ -369,6 +378,61 @@ def test_edge_sizes(mq, orc, n_int, n_bnd):
         r = orc.solve(X, n_int, 2.0, 3.0, f, ell, rule=orc.RULE_FIXED, lambda_fixed=1e-2)
         assert out.ell_done == r.ell
         assert np.linalg.norm(out.coef - r.coef) <= 1e-8 * max(np.linalg.norm(r.coef), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# full size (unit ball, n = 100000), in the launch configuration the
+# benchmark times: sampled outputs against the oracle one by one, and the
+# Golub-Kahan relations on sampled rows
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def sphere_full():
+    return I.sphere_large()
+
+
+@pytest.mark.parametrize("mode", ["matfree_fp32", "matfree_fp64", "stored_fp64"])
+def test_products_full_size_sampled(mq, orc, sphere_full, mode):
+    p = sphere_full
+    x = I.random_vector(p.n, 21)
+    idx = np.unique(np.concatenate([np.arange(0, p.n, 997), [p.n_int - 1, p.n_int, p.n - 1]])).astype(np.int64)
+    tol = 4e-6 if mode == "matfree_fp32" else 1e-13
+    with _problem(mq, p, mode) as pr:
+        for trans in (False, True):
+            say("full-size apply", mode, "trans", trans)
+            y = pr.apply(x, trans=trans)
+            ref = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, x, idx, trans=trans)
+            scale = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, np.abs(x), idx, trans=trans)
+            err = np.abs(y[idx] - ref) / scale
+            assert np.all(err <= tol), float(err.max())
+
+
+def test_gkb_relations_full_size_fp32(mq, orc, sphere_full):
+    # A Z = W C and A^T W_l = Z_l C_l^T hold for the operator the GPU applies;
+    # against the FP64 oracle's A they hold to the FP32 entry error.
+    p = sphere_full
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("full-size gkb fp32, ell", p.ell)
+        r = pr.gkb(p.rhs, p.ell)
+    assert r["ell_done"] == p.ell
+    Wc, Zc, a, b = r["W"], r["Z"], r["alpha"], r["beta"]  # rows are basis vectors
+    l = p.ell
+    WtW = Wc @ Wc.T
+    ZtZ = Zc @ Zc.T
+    assert np.max(np.abs(WtW - np.eye(l + 1))) < 1e-12
+    assert np.max(np.abs(ZtZ - np.eye(l))) < 1e-12
+    assert abs(Wc[0] @ p.rhs - b[0]) <= 1e-12 * b[0]
+    idx = np.arange(5, p.n, 1499).astype(np.int64)
+    for j in (0, l // 2, l - 1):
+        say("relation column", j)
+        azj = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, Zc[j], idx)
+        sc = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, np.abs(Zc[j]), idx)
+        wc = a[j] * Wc[j, idx] + b[j + 1] * Wc[j + 1, idx]
+        assert np.all(np.abs(azj - wc) <= 1e-5 * sc), float(np.max(np.abs(azj - wc) / sc))
+        atw = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, Wc[j], idx, trans=True)
+        sct = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, np.abs(Wc[j]), idx, trans=True)
+        zc = a[j] * Zc[j, idx] + (b[j] * Zc[j - 1, idx] if j > 0 else 0.0)
+        assert np.all(np.abs(atw - zc) <= 1e-5 * sct), float(np.max(np.abs(atw - zc) / sct))
 
 
 def test_duplicate_nodes_finite(mq):
