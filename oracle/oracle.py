@@ -25,7 +25,16 @@ the design notes):
   G(k) = (sum_{i>k} f~_i^2 + f~_{l+1}^2) / ((l+1) - k)^2, k = 1..floor(l/2),
   ties to the smaller k;
 * the final Tikhonov solve of Algorithm 4 is done in the SVD-filter form,
-  equal in exact arithmetic to the normal equations it prints.
+  equal in exact arithmetic to the normal equations it prints;
+* weighted GCV (opt-in): the projected GCV with the trace term scaled by a
+  weight omega, rho_l^2 / ((l+1) - omega sum_i phi_i)^2 (omega = 1 is
+  eq. (30)); for the rank, ((l+1) - omega k)^2;
+* LSQR early stopping (Section 3.4): the k-th iterate is Z_k y_k with
+  y_k = argmin ||C_k y - beta_1 e_1||; the stopping index minimises the
+  GCV function of the Krylov filter, rho_k^2 / (n - k)^2 (its influence
+  matrix is a rank-k orthogonal projector), or sits at the corner of the
+  discrete L-curve (log rho_k, log eta_k): the maximum signed Menger
+  curvature over consecutive triples, traversed from large to small k.
 """
 from __future__ import annotations
 
@@ -51,9 +60,11 @@ FLAG_LCURVE_AT_EDGE = 4
 
 METHOD_INE_TSVD = 0
 METHOD_HKT = 1
+METHOD_LSQR = 2
 RULE_GCV = 0
 RULE_LCURVE = 1
 RULE_FIXED = 2
+RULE_WGCV = 3
 
 
 def build(force: bool = True) -> str:
@@ -312,6 +323,13 @@ def gcv_proj(s: np.ndarray, ftil: np.ndarray, lam: float) -> float:
     return rho2_proj(s, ftil, lam) / (den * den)
 
 
+def gcv_proj_weighted(s: np.ndarray, ftil: np.ndarray, lam: float, omega: float) -> float:
+    """Weighted projected GCV: rho_l^2 / ((l+1) - omega sum_i phi_i)^2 (omega = 1 gives eq. (30))."""
+    ell = s.shape[0]
+    den = (ell + 1) - omega * float(np.sum(tikh_filter(s, lam)))
+    return rho2_proj(s, ftil, lam) / (den * den)
+
+
 def gcv_full(s: np.ndarray, fhat: np.ndarray, s_perp: float, n: int, lam: float) -> float:
     """GCV(lambda) of the full problem in SVD variables (eq. (25), Algorithm 3)."""
     c = tikh_filter_complement(s, lam)
@@ -376,11 +394,16 @@ def golden_min(fun, a: float, b: float, tol: float = 1e-10, max_it: int = 200) -
     return 0.5 * (a + b)
 
 
-def choose_lambda_gcv(s: np.ndarray, ftil: np.ndarray, n_grid: int = 200, refine: bool = True):
-    """lambda* = argmin_{lambda > 0} GCV_l(lambda) (Algorithm 4, GCV branch).
+def choose_lambda_gcv(s: np.ndarray, ftil: np.ndarray, n_grid: int = 200, refine: bool = True,
+                      omega: float = 1.0):
+    """lambda* = argmin_{lambda > 0} GCV_l(lambda) (Algorithm 4, GCV branch); with omega != 1
+    the weighted GCV.
 
     Grid minimum first (ties -> larger lambda), then golden-section refinement
     of log(lambda) on the two cells around it.  Returns (lambda, gcv, at_edge, grid, values)."""
+    def gcv_proj(s_, f_, lam_):  # noqa: F811 - the weighted form, eq. (30) at omega = 1
+        return gcv_proj_weighted(s_, f_, lam_, omega)
+
     grid = lambda_grid(s, n_grid)
     vals = np.array([gcv_proj(s, ftil, lam) for lam in grid])
     k = n_grid - 1 - int(np.argmin(vals[::-1]))
@@ -406,19 +429,95 @@ def choose_lambda_lcurve(s: np.ndarray, ftil: np.ndarray, n_grid: int = 200):
     return float(grid[k]), float(kap[k]), (k == 1 or k == n_grid - 2), grid, kap
 
 
-def tsvd_gcv(s: np.ndarray, ftil: np.ndarray, k: int) -> float:
-    """Projected TSVD-GCV: (sum_{i>k} f~_i^2 + f~_{l+1}^2) / ((l+1) - k)^2."""
+def tsvd_gcv(s: np.ndarray, ftil: np.ndarray, k: int, omega: float = 1.0) -> float:
+    """Projected TSVD-GCV: (sum_{i>k} f~_i^2 + f~_{l+1}^2) / ((l+1) - omega k)^2 (omega = 1 unless weighted)."""
     ell = s.shape[0]
     res = float(np.sum(ftil[k:ell] ** 2) + ftil[ell] ** 2)
-    return res / float((ell + 1 - k) ** 2)
+    den = (ell + 1) - omega * k
+    return res / (den * den)
 
 
-def choose_rank(s: np.ndarray, ftil: np.ndarray) -> int:
+def choose_rank(s: np.ndarray, ftil: np.ndarray, omega: float = 1.0) -> int:
     """Ine-TSVD rank k* (Algorithm 2 step 4): argmin of the projected TSVD-GCV over k = 1..max(1, floor(l/2))."""
     ell = s.shape[0]
     kmax = max(1, ell // 2)
-    vals = [tsvd_gcv(s, ftil, k) for k in range(1, kmax + 1)]
+    vals = [tsvd_gcv(s, ftil, k, omega) for k in range(1, kmax + 1)]
     return 1 + int(np.argmin(vals))
+
+
+# --------------------------------------------------------------------------
+# LSQR iterates and early stopping (Section 3.4)
+# --------------------------------------------------------------------------
+
+
+def lsqr_path(alpha: np.ndarray, beta: np.ndarray):
+    """For k = 1..l: y_k = argmin_y ||C_k y - beta_1 e_1||_2 with C_k the leading (k+1) x k block of
+    C_l, so that Z_k y_k is the k-th LSQR iterate and ||A Z_k y_k - f|| = ||C_k y_k - beta_1 e_1||
+    (Section 3.4; eq. (26)).  Plain definition: one dense least-squares solve per k.
+
+    Returns (rho[l], eta[l], Y) with rho_k = ||C_k y_k - beta_1 e_1||, eta_k = ||y_k|| and row k-1
+    of Y holding y_k padded with zeros to length l."""
+    alpha, beta = _c(alpha), _c(beta)
+    ell = alpha.shape[0]
+    C = bidiag_matrix(alpha, beta)
+    rho = np.empty(ell)
+    eta = np.empty(ell)
+    Y = np.zeros((ell, ell))
+    for k in range(1, ell + 1):
+        Ck = C[: k + 1, :k]
+        rhs = np.zeros(k + 1)
+        rhs[0] = beta[0]
+        y = np.linalg.lstsq(Ck, rhs, rcond=None)[0]
+        rho[k - 1] = float(np.linalg.norm(Ck @ y - rhs))
+        eta[k - 1] = float(np.linalg.norm(y))
+        Y[k - 1, :k] = y
+    return rho, eta, Y
+
+
+def krylov_gcv(rho: np.ndarray, n: int) -> np.ndarray:
+    """G(k) = rho_k^2 / (n - k)^2 for k = 1..len(rho) (trace of the rank-k projector A Z_k C_k^+ W_{k+1}^T is k)."""
+    k = np.arange(1, rho.shape[0] + 1, dtype=np.float64)
+    return rho * rho / ((n - k) ** 2)
+
+
+def choose_k_lsqr_gcv(rho: np.ndarray, n: int) -> int:
+    """Stopping index: argmin_k G(k) over k = 1..min(l, n-1), ties to the smaller k."""
+    kmax = min(rho.shape[0], n - 1)
+    if kmax < 1:
+        return 1
+    return 1 + int(np.argmin(krylov_gcv(rho[:kmax], n)))
+
+
+def menger_curvature(a, b, c) -> float:
+    """Signed curvature of the circle through the points a, b, c (visited in that order)."""
+    ab, bc, ac = b - a, c - b, c - a
+    la, lb, lc = np.linalg.norm(ab), np.linalg.norm(bc), np.linalg.norm(ac)
+    cross = ab[0] * bc[1] - ab[1] * bc[0]
+    return 2.0 * cross / (la * lb * lc)
+
+
+def lcurve_discrete_corner(rho: np.ndarray, eta: np.ndarray):
+    """Corner of the discrete L-curve p_k = (log rho_k, log eta_k): argmax over k = 2..l-1 of the
+    signed curvature of (p_{k+1}, p_k, p_{k-1}), ties to the smaller k.  Triples with a side shorter
+    than 1e-12 times the extent of the point set are skipped.  Returns (k, curvature, at_edge, curvatures)
+    (k = l and at_edge when no triple qualifies)."""
+    ell = rho.shape[0]
+    tiny = np.finfo(np.float64).tiny
+    P = np.stack([np.log(np.maximum(rho, tiny)), np.log(np.maximum(eta, tiny))], axis=1)
+    kap = np.full(ell, -np.inf)
+    if ell < 3:
+        return ell, float("nan"), True, kap
+    ext = float(np.max(np.max(P, axis=0) - np.min(P, axis=0)))
+    tol = 1e-12 * ext
+    for k in range(2, ell):  # 1-based k, inner points
+        a, b, c = P[k], P[k - 1], P[k - 2]  # p_{k+1}, p_k, p_{k-1}
+        if min(np.linalg.norm(b - a), np.linalg.norm(c - b), np.linalg.norm(c - a)) <= tol:
+            continue
+        kap[k - 1] = menger_curvature(a, b, c)
+    if not np.any(np.isfinite(kap)):
+        return ell, float("nan"), True, kap
+    k = 1 + int(np.argmax(kap))
+    return k, float(kap[k - 1]), (k == 2 or k == ell - 1), kap
 
 
 def y_tikhonov(s: np.ndarray, ftil: np.ndarray, V: np.ndarray, lam: float) -> np.ndarray:
@@ -457,8 +556,9 @@ class SolveResult:
 
 def solve(X: np.ndarray, n_int: int, kappa: float, eps: float, f: np.ndarray, ell: int,
           method: int = METHOD_HKT, rule: int = RULE_GCV, k_trunc: int = 0, lambda_fixed: float = 0.0,
-          n_grid: int = 200, stored: bool = True, reorth: bool = True) -> SolveResult:
-    """Ine-TSVD (Algorithm 2) or HKT (Algorithm 4) from nodes and data to RBF coefficients."""
+          n_grid: int = 200, stored: bool = True, reorth: bool = True, gcv_weight: float = 1.0) -> SolveResult:
+    """Ine-TSVD (Algorithm 2), HKT (Algorithm 4) or LSQR with early stopping (Section 3.4) from
+    nodes and data to RBF coefficients."""
     X = _c(X)
     A = assemble(X, n_int, kappa, eps) if stored else None
     g = gkb(A, X, n_int, kappa, eps, f, ell, reorth)
@@ -467,9 +567,26 @@ def solve(X: np.ndarray, n_int: int, kappa: float, eps: float, f: np.ndarray, el
     le = g.ell
     s, ft, V = proj_svd(g.alpha, g.beta)
     lam, k, crit = 0.0, 0, float("nan")
+    omega = float(gcv_weight) if rule == RULE_WGCV else 1.0
+    if method == METHOD_LSQR:
+        rho, eta, Y = lsqr_path(g.alpha, g.beta)
+        if rule == RULE_LCURVE:
+            k, crit, edge, _ = lcurve_discrete_corner(rho, eta)
+            if edge:
+                flags |= FLAG_LCURVE_AT_EDGE
+        elif rule == RULE_FIXED:
+            k = min(max(int(k_trunc), 1), le)
+            crit = float(krylov_gcv(rho, X.shape[0])[k - 1]) if k < X.shape[0] else float("nan")
+        else:
+            k = choose_k_lsqr_gcv(rho, X.shape[0])
+            crit = float(krylov_gcv(rho, X.shape[0])[k - 1])
+        y = Y[k - 1]
+        coef = lift(g.Z, y)
+        return SolveResult(coef, le, k, 0.0, crit, float(rho[k - 1]), float(eta[k - 1]), flags, g.alpha, g.beta,
+                           s, ft, g)
     if method == METHOD_HKT:
-        if rule == RULE_GCV:
-            lam, crit, edge, _, _ = choose_lambda_gcv(s, ft, n_grid)
+        if rule in (RULE_GCV, RULE_WGCV):
+            lam, crit, edge, _, _ = choose_lambda_gcv(s, ft, n_grid, omega=omega)
             if edge:
                 flags |= FLAG_GCV_AT_EDGE
         elif rule == RULE_LCURVE:
@@ -482,9 +599,9 @@ def solve(X: np.ndarray, n_int: int, kappa: float, eps: float, f: np.ndarray, el
         rn = math.sqrt(rho2_proj(s, ft, lam))
         sn = math.sqrt(eta2_proj(s, ft, lam))
     else:
-        k = int(k_trunc) if k_trunc > 0 else choose_rank(s, ft)
+        k = int(k_trunc) if rule == RULE_FIXED and k_trunc > 0 else choose_rank(s, ft, omega)
         k = min(k, le)
-        crit = tsvd_gcv(s, ft, k)
+        crit = tsvd_gcv(s, ft, k, omega)
         y = y_tsvd(s, ft, V, k)
         rn = math.sqrt(float(np.sum(ft[k:] ** 2)))
         sn = float(np.linalg.norm(ft[:k] / s[:k]))
