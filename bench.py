@@ -91,10 +91,30 @@ def rel_linf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def run_variant(mq, torch, p, mode, steps, warmup, dev, want_kernel_times=True):
+def parse_variant(mq, spec):
+    """'mode[:method[:rule[:weight]]]' -> (operator mode, solve keyword arguments).
+
+    method: hkt (Algorithm 4, default), tsvd (Algorithm 2), lsqr (Section 3.4);
+    rule: gcv (default), lcurve, wgcv (weighted GCV, weight default 0.5)."""
+    parts = spec.split(":")
+    mode = parts[0]
+    method = {"hkt": mq.MQH_METHOD_HKT, "tsvd": mq.MQH_METHOD_INE_TSVD,
+              "lsqr": mq.MQH_METHOD_LSQR}[parts[1] if len(parts) > 1 else "hkt"]
+    rule = {"gcv": mq.MQH_RULE_GCV, "lcurve": mq.MQH_RULE_LCURVE,
+            "wgcv": mq.MQH_RULE_WGCV}[parts[2] if len(parts) > 2 else "gcv"]
+    kw = dict(method=method, rule=rule)
+    if rule == mq.MQH_RULE_WGCV:
+        kw["gcv_weight"] = float(parts[3]) if len(parts) > 3 else 0.5
+    if method == mq.MQH_METHOD_LSQR:
+        kw["want_sv"] = False  # the LSQR stop needs no projected SVD
+    return mode, kw
+
+
+def run_variant(mq, torch, p, spec, steps, warmup, dev, want_kernel_times=True):
     """Create the problem, run warmup + timed solves; returns a dict of figures."""
     import numpy as np
 
+    mode, kw = parse_variant(mq, spec)
     stream = torch.cuda.current_stream(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -105,23 +125,24 @@ def run_variant(mq, torch, p, mode, steps, warmup, dev, want_kernel_times=True):
     g_bnd = torch.from_numpy(p.g_bnd).to(dev)
     coef = torch.empty(p.n, dtype=torch.float64, device=dev)
     for w in range(warmup):
-        log(mode, "warmup", w)
-        pr.solve(f_int, g_bnd, p.ell, coef=coef)
+        log(spec, "warmup", w)
+        pr.solve(f_int, g_bnd, p.ell, coef=coef, **kw)
     torch.cuda.synchronize()
     times, outs = [], []
     for k in range(steps):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        out = pr.solve(f_int, g_bnd, p.ell, coef=coef, time_products=want_kernel_times)
+        out = pr.solve(f_int, g_bnd, p.ell, coef=coef, time_products=want_kernel_times, **kw)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
         outs.append(out)
-        log(mode, "step", k, f"{times[-1]:.3f} s", "ell_done", out.ell_done, "lambda", f"{out.lam:.3e}")
+        log(spec, "step", k, f"{times[-1]:.3f} s", "ell_done", out.ell_done, "lambda", f"{out.lam:.3e}",
+            "k", out.k)
     x_eval = torch.from_numpy(p.x_eval).to(dev)
     u = pr.eval(coef, x_eval).cpu().numpy()
     out = outs[-1]
     res = dict(mode=mode, setup_s=setup_s, step_s=times, solve_s=float(np.mean(times)), ell_done=out.ell_done,
-               lam=out.lam, flags=out.flags, rel_l2=rel_l2(u, p.u_eval), rel_linf=rel_linf(u, p.u_eval),
+               lam=out.lam, k=out.k, flags=out.flags, rel_l2=rel_l2(u, p.u_eval), rel_linf=rel_linf(u, p.u_eval),
                phase_ms=dict(upload=out.t_ms[0], gkb=out.t_ms[1], proj_svd=out.t_ms[2], param=out.t_ms[3],
                              lift=out.t_ms[4], total=out.t_ms[5]))
     if want_kernel_times:
@@ -163,8 +184,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sphere_n100000")
     ap.add_argument("--ell", type=int, default=0, help="override the Golub-Kahan steps (0: workload's)")
-    ap.add_argument("--variants", default="matfree_fp32,stored_fp64,matfree_fp64",
-                    help="first one is the headline")
+    ap.add_argument("--variants",
+                    default="matfree_fp32,stored_fp64,matfree_fp64,matfree_fp32:lsqr:gcv,matfree_fp32:lsqr:lcurve,"
+                            "matfree_fp32:hkt:wgcv:0.5",
+                    help="first one is the headline; each is mode[:method[:rule[:weight]]]")
     ap.add_argument("--context-steps", type=int, default=1, help="timed solves of the non-headline variants")
     ap.add_argument("--cpu-rows", type=int, default=150000, help="row/column sample of the CPU baseline (0: skip)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -212,7 +235,7 @@ def main():
     # roofline of the dominant kernel of the headline variant
     k_at, k_a = head.get("kernel_ms_AT", float("nan")), head.get("kernel_ms_A", float("nan"))
     dom_ms, dom_name = (k_at, "A^T x") if k_at >= k_a else (k_a, "A x")
-    mode = variants[0]
+    mode = head["mode"]
     kern = {"matfree_fp32": ("k_mfm<false>", "k_mfm<true>"), "matfree_fp64": ("k_mf_cols", "k_mf_rows"),
             "stored_fp64": ("k_stored_cols", "k_stored_rows")}[mode][0 if dom_name == "A^T x" else 1]
     if mode.startswith("matfree"):
@@ -238,9 +261,9 @@ def main():
 
     ctx = {}
     for v, r in results.items():
-        tts = r["solve_s"] + (r["setup_s"] if v == "stored_fp64" else 0.0)
+        tts = r["solve_s"] + (r["setup_s"] if r["mode"] == "stored_fp64" else 0.0)
         ctx[v] = dict(time_to_solution_s=tts, solve_s=r["solve_s"], setup_s=r["setup_s"], rel_l2=r["rel_l2"],
-                      rel_linf=r["rel_linf"], lam=r["lam"], ell_done=r["ell_done"],
+                      rel_linf=r["rel_linf"], lam=r["lam"], k=r["k"], ell_done=r["ell_done"],
                       product_ms_AT=r.get("kernel_ms_AT"), product_ms_A=r.get("kernel_ms_A"),
                       product_equiv_GBs=(8.0 * n * n / (0.5e-3 * (r["kernel_ms_AT"] + r["kernel_ms_A"])) / 1e9)
                       if "kernel_ms_AT" in r else None,
@@ -248,9 +271,9 @@ def main():
     line = dict(metric="HKT time-to-solution & GKB matvec GB/s at N=100k sphere, equal rel-L2 err",
                 value=value, unit="GB/s (FP64-A-equivalent product traffic over the whole HKT solve)",
                 n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
-                scaling="weak", vs_baseline=None, dtype="f32" if variants[0] == "matfree_fp32" else "f64", data="synthetic",
+                scaling="weak", vs_baseline=None, dtype="f32" if mode == "matfree_fp32" else "f64", data="synthetic",
                 config=dict(workload=p.name, n=n, n_int=p.n_int, n_bnd=p.n_bnd, kappa=p.kappa, eps=p.eps,
-                            ell=p.ell, method="HKT", rule="GCV", operator=variants[0]),
+                            ell=p.ell, method="HKT", rule="GCV", operator=mode),
                 hkt_time_to_solution_s=head["solve_s"], roofline=roof, variants=ctx)
     if args.cpu_rows > 0:
         log("cpu baseline", args.cpu_rows, "rows")

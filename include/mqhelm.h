@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MQH_VERSION 10000 /* 1.0.0 */
+#define MQH_VERSION 10100 /* 1.1.0 */
 
 /* ---- status codes ---- */
 #define MQH_OK 0
@@ -62,9 +62,11 @@ extern "C" {
 /* ---- methods and parameter-choice rules ---- */
 #define MQH_METHOD_INE_TSVD 0 /* Algorithm 2 */
 #define MQH_METHOD_HKT 1      /* Algorithm 4 */
-#define MQH_RULE_GCV 0        /* eq. (30) (HKT) / projected TSVD-GCV (Ine-TSVD) */
-#define MQH_RULE_LCURVE 1     /* maximum curvature of (log rho, log eta) on the grid */
-#define MQH_RULE_FIXED 2      /* lambda = lambda_fixed (HKT) / k = k_trunc (Ine-TSVD) */
+#define MQH_METHOD_LSQR 2     /* LSQR iterate with early stopping (Section 3.4), see mqh_lsqr */
+#define MQH_RULE_GCV 0        /* eq. (30) (HKT) / projected TSVD-GCV (Ine-TSVD) / Krylov GCV (LSQR) */
+#define MQH_RULE_LCURVE 1     /* maximum curvature of (log rho, log eta) on the grid / discrete (LSQR) */
+#define MQH_RULE_FIXED 2      /* lambda = lambda_fixed (HKT) / k = k_trunc (Ine-TSVD, LSQR) */
+#define MQH_RULE_WGCV 3       /* weighted GCV, trace term scaled by gcv_weight (HKT, Ine-TSVD) */
 
 /* ---- call flags ---- */
 #define MQH_FLAG_DEVICE_PTRS 1u     /* array arguments are device pointers */
@@ -86,21 +88,22 @@ typedef struct {
     int32_t reorth;       /* 1: full reorthogonalisation (classical Gram-Schmidt twice); 0: none */
     int32_t method;       /* MQH_METHOD_* */
     int32_t rule;         /* MQH_RULE_* */
-    int32_t k_trunc;      /* Ine-TSVD with MQH_RULE_FIXED: rank k (1..ell) */
+    int32_t k_trunc;      /* Ine-TSVD / LSQR with MQH_RULE_FIXED: rank / iteration k (1..ell) */
     int32_t n_grid;       /* lambda grid size J (>= 3; 0 -> 200) */
     double lambda_fixed;  /* HKT with MQH_RULE_FIXED: lambda >= 0 */
     uint32_t flags;       /* MQH_FLAG_* for this call */
     int32_t reserved;
+    double gcv_weight;    /* MQH_RULE_WGCV: weight omega in (0, 1] of the trace term (1 -> plain GCV) */
 } mqh_solve_opts;
 
 /* Outcome of a solve. */
 typedef struct {
     int32_t ell_done;      /* Golub-Kahan steps kept (< ell after a breakdown) */
-    int32_t k_chosen;      /* Ine-TSVD rank (0 for HKT) */
+    int32_t k_chosen;      /* Ine-TSVD rank / LSQR stopping index (0 for HKT) */
     double lambda_chosen;  /* HKT lambda (0 for Ine-TSVD) */
     double crit;           /* GCV value at the choice, or curvature for the L-curve rule */
-    double resid_norm;     /* projected residual norm rho_l at the choice (eq. (28)) */
-    double sol_norm;       /* projected solution norm eta_l = ||y|| (eq. (29)) */
+    double resid_norm;     /* projected residual norm rho_l at the choice (eq. (28); LSQR: rho_k) */
+    double sol_norm;       /* projected solution norm eta_l = ||y|| (eq. (29); LSQR: eta_k) */
     uint32_t flags;        /* MQH_INFO_* */
     int32_t reserved;
     double t_ms[8];        /* [0] data upload, [1] Golub-Kahan loop, [2] projected SVD,
@@ -198,12 +201,16 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
  *                                   [max(s_l, 16 eps_mach s_1), s_1], then
  *                                   golden-section refinement of log lambda
  *                                   in the bracketing cells;
+ *                    rule WGCV   -> the same with the weighted GCV
+ *                                   rho_l^2 / ((l+1) - w sum_i phi_i)^2,
+ *                                   w = gcv_weight in (0, 1];
  *                    rule LCURVE -> grid point of maximum signed curvature
  *                                   of (log rho_l, log eta_l), end points excluded;
  *                    rule FIXED  -> lambda_fixed.
  *   method INE_TSVD: rule FIXED  -> k = k_trunc; otherwise k* = argmin over
  *                                   k = 1..max(1, ell/2) of
- *                                   (sum_{i>k} f~_i^2 + f~_{l+1}^2)/((l+1)-k)^2.
+ *                                   (sum_{i>k} f~_i^2 + f~_{l+1}^2)/((l+1)-w k)^2
+ *                                   (w = gcv_weight for WGCV, else 1).
  * Inputs sv (ell, descending), ftil (ell+1).  Outputs (host scalars; NULL
  * allowed): lambda, k, crit (GCV value / curvature at the choice),
  * info_flags (MQH_INFO_*); curve (n_grid values of the criterion on the
@@ -211,8 +218,33 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
  * Returns MQH_WEDGE when the choice is at a grid end.
  */
 int mqh_param_choice(const double* sv, const double* ftil, int32_t ell, int32_t method, int32_t rule,
-                     int32_t n_grid, double lambda_fixed, int32_t k_trunc, double* lambda, int32_t* k,
-                     double* crit, uint32_t* info_flags, double* curve, void* stream, uint32_t flags);
+                     int32_t n_grid, double lambda_fixed, int32_t k_trunc, double gcv_weight, double* lambda,
+                     int32_t* k, double* crit, uint32_t* info_flags, double* curve, void* stream, uint32_t flags);
+
+/*
+ * LSQR iterates on the projected problem and their stopping index
+ * (Section 3.4), on the device.  The k-th LSQR iterate is Z_k y_k with
+ * y_k = argmin ||C_k y - beta_1 e_1|| (C_k the leading (k+1) x k block of
+ * C_ell); rho_k = ||C_k y_k - beta_1 e_1|| = ||A Z_k y_k - f|| and
+ * eta_k = ||y_k|| = ||Z_k y_k|| (eq. (26), orthonormal bases).
+ *   rule GCV    -> k* = argmin rho_k^2 / (n - k)^2 over k = 1..min(ell, n-1)
+ *                  (the k-th iterate's influence matrix is a rank-k
+ *                  projector), ties to the smaller k;
+ *   rule LCURVE -> corner of the discrete L-curve p_k = (log rho_k,
+ *                  log eta_k): maximum signed Menger curvature of
+ *                  (p_{k+1}, p_k, p_{k-1}) over k = 2..ell-1, ties to the
+ *                  smaller k; MQH_INFO_LCURVE_AT_EDGE (and MQH_WEDGE) when
+ *                  the corner is k = 2 or ell-1 or no triple qualifies
+ *                  (then k* = ell);
+ *   rule FIXED  -> k* = k_trunc (1..ell).
+ * Inputs alpha (ell), beta (ell+1, beta[0] = beta_1), n = rows of A.
+ * Outputs: k, crit (GCV value / curvature at k*; host scalars, NULL
+ * allowed), info_flags, y (ell entries: y_k* then zeros), rho and eta
+ * (ell entries each, NULL allowed).  1 <= ell <= MQH_MAX_ELL, n > ell - 1.
+ */
+int mqh_lsqr(const double* alpha, const double* beta, int32_t ell, int64_t n, int32_t rule, int32_t k_trunc,
+             int32_t* k, double* crit, uint32_t* info_flags, double* y, double* rho, double* eta, void* stream,
+             uint32_t flags);
 
 /*
  * Projected solution (Algorithm 2 step 5 / Algorithm 4 step 8 in SVD form):
@@ -232,9 +264,11 @@ int mqh_lift(const double* Z, int64_t n, int32_t ell, const double* y, double* c
              uint32_t flags);
 
 /*
- * Whole solve (Algorithm 2 or 4): f = [f_int (n_int); g_bnd (n_bnd)] ->
- * Golub-Kahan (ell steps) -> projected SVD -> parameter choice -> projected
- * solution -> coef = Z y (n).  Optional outputs (NULL allowed): gkb_alpha
+ * Whole solve (Algorithm 2 or 4, or LSQR with early stopping, Section 3.4):
+ * f = [f_int (n_int); g_bnd (n_bnd)] -> Golub-Kahan (ell steps) -> projected
+ * SVD -> parameter choice -> projected solution -> coef = Z y (n).  For
+ * MQH_METHOD_LSQR the SVD runs only when ritz_sv is requested and the
+ * projected steps are those of mqh_lsqr.  Optional outputs (NULL allowed): gkb_alpha
  * (ell), gkb_beta (ell+1), ritz_sv (ell); entries past info->ell_done are 0.
  * info may be NULL.  opts->flags decides the pointer kind of every array.
  * Returns MQH_OK, MQH_WBREAKDOWN, MQH_WEDGE (edge and breakdown: breakdown

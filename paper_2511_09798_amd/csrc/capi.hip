@@ -710,15 +710,19 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
     const int32_t ell = opts->ell;
     if (ell < 1 || ell > p->n || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= min(n, MQH_MAX_ELL)");
     if (opts->reorth != 0 && opts->reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
-    if (opts->method != MQH_METHOD_INE_TSVD && opts->method != MQH_METHOD_HKT) return fail(MQH_EINVAL, "method");
-    if (opts->rule < MQH_RULE_GCV || opts->rule > MQH_RULE_FIXED) return fail(MQH_EINVAL, "rule");
+    if (opts->method != MQH_METHOD_INE_TSVD && opts->method != MQH_METHOD_HKT && opts->method != MQH_METHOD_LSQR)
+        return fail(MQH_EINVAL, "method");
+    if (opts->rule < MQH_RULE_GCV || opts->rule > MQH_RULE_WGCV) return fail(MQH_EINVAL, "rule");
+    if (opts->method == MQH_METHOD_LSQR && opts->rule == MQH_RULE_WGCV)
+        return fail(MQH_EINVAL, "the weighted GCV rule applies to HKT and Ine-TSVD");
+    if (opts->rule == MQH_RULE_WGCV && !(opts->gcv_weight > 0.0 && opts->gcv_weight <= 1.0))
+        return fail(MQH_EINVAL, "gcv_weight must be in (0, 1]");
     const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
     if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
     if (opts->method == MQH_METHOD_HKT && opts->rule == MQH_RULE_FIXED &&
         (!isfinite(opts->lambda_fixed) || opts->lambda_fixed < 0.0))
         return fail(MQH_EINVAL, "lambda_fixed must be finite and >= 0");
-    if (opts->method == MQH_METHOD_INE_TSVD && opts->rule == MQH_RULE_FIXED &&
-        (opts->k_trunc < 1 || opts->k_trunc > ell))
+    if (opts->method != MQH_METHOD_HKT && opts->rule == MQH_RULE_FIXED && (opts->k_trunc < 1 || opts->k_trunc > ell))
         return fail(MQH_EINVAL, "k_trunc must be in [1, ell]");
     const uint32_t flags = opts->flags;
     const bool timed = (flags & MQH_FLAG_TIME_PRODUCTS) != 0;
@@ -735,13 +739,22 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
     if ((rc = run_gkb(p, ell, opts->reorth, timed))) return rc;
     HIPCHK(hipEventRecord(p->ev[2], s));
     const int32_t* lp = &p->st->ell_done;
+    const bool lsqr = opts->method == MQH_METHOD_LSQR;
+    const bool svd_runs = !lsqr || ritz_sv != nullptr;
     launch_fill(p->sv, ell, 0.0, s);
-    launch_bidiag_svd(p->alpha, p->beta, ell, lp, p->Vw, ell, p->sv, p->ftil, p->V, ell, p->svd_status, s);
-    LAUNCHCHK("projected SVD");
+    if (svd_runs) {
+        launch_bidiag_svd(p->alpha, p->beta, ell, lp, p->Vw, ell, p->sv, p->ftil, p->V, ell, p->svd_status, s);
+        LAUNCHCHK("projected SVD");
+    }
     HIPCHK(hipEventRecord(p->ev[3], s));
-    launch_param_choice(p->sv, p->ftil, ell, lp, opts->method, opts->rule, J, opts->lambda_fixed, opts->k_trunc,
-                        nullptr, p->pout, s);
-    launch_proj_solution(p->sv, p->ftil, p->V, ell, ell, lp, opts->method, 0.0, 0, p->pout, p->y, ell, s);
+    if (lsqr) {
+        launch_lsqr(p->alpha, p->beta, ell, lp, p->n, opts->rule, opts->k_trunc, nullptr, nullptr, p->pout, p->y, ell,
+                    s);
+    } else {
+        launch_param_choice(p->sv, p->ftil, ell, lp, opts->method, opts->rule, J, opts->lambda_fixed, opts->k_trunc,
+                            opts->gcv_weight, nullptr, p->pout, s);
+        launch_proj_solution(p->sv, p->ftil, p->V, ell, ell, lp, opts->method, 0.0, 0, p->pout, p->y, ell, s);
+    }
     LAUNCHCHK("parameter choice");
     HIPCHK(hipEventRecord(p->ev[4], s));
     launch_lift(p->Z, p->ldn, p->n, ell, lp, p->y, p->coef, s);
@@ -754,7 +767,7 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
     double b1 = 0.0;
     HIPCHK(hipMemcpy(&b1, p->beta, sizeof(double), hipMemcpyDeviceToHost));
     if (!isfinite(b1)) return fail(MQH_EINVAL, "non-finite right-hand side");
-    if (p->hres->svd_status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    if (svd_runs && p->hres->svd_status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
     const hipMemcpyKind ko = kind_out(flags);
     HIPCHK(hipMemcpyAsync(coef, p->coef, (size_t)p->n * sizeof(double), ko, s));
     if (gkb_alpha) HIPCHK(hipMemcpyAsync(gkb_alpha, p->alpha, (size_t)ell * sizeof(double), ko, s));
@@ -924,12 +937,14 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
 }
 
 int mqh_param_choice(const double* sv, const double* ftil, int32_t ell, int32_t method, int32_t rule, int32_t n_grid,
-                     double lambda_fixed, int32_t k_trunc, double* lambda, int32_t* k, double* crit,
+                     double lambda_fixed, int32_t k_trunc, double gcv_weight, double* lambda, int32_t* k, double* crit,
                      uint32_t* info_flags, double* curve, void* stream, uint32_t flags) {
     if (sv == nullptr || ftil == nullptr) return fail(MQH_EINVAL, "NULL array");
     if (ell < 1 || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= MQH_MAX_ELL");
     if (method != MQH_METHOD_INE_TSVD && method != MQH_METHOD_HKT) return fail(MQH_EINVAL, "method");
-    if (rule < MQH_RULE_GCV || rule > MQH_RULE_FIXED) return fail(MQH_EINVAL, "rule");
+    if (rule < MQH_RULE_GCV || rule > MQH_RULE_WGCV) return fail(MQH_EINVAL, "rule");
+    if (rule == MQH_RULE_WGCV && !(gcv_weight > 0.0 && gcv_weight <= 1.0))
+        return fail(MQH_EINVAL, "gcv_weight must be in (0, 1]");
     const int32_t J = n_grid == 0 ? 200 : n_grid;
     if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
     if (method == MQH_METHOD_HKT && rule == MQH_RULE_FIXED && (!isfinite(lambda_fixed) || lambda_fixed < 0.0))
@@ -948,7 +963,7 @@ int mqh_param_choice(const double* sv, const double* ftil, int32_t ell, int32_t 
     if ((rc = dev_in(t, ftil, (size_t)ell + 1, flags, s, &dft))) return rc;
     if (curve != nullptr && (rc = dev_out(t, curve, (size_t)J, flags, &dcurve))) return rc;
     if ((rc = t.get(&dpo, 1))) return rc;
-    launch_param_choice(dsv, dft, ell, nullptr, method, rule, J, lambda_fixed, k_trunc, dcurve, dpo, s);
+    launch_param_choice(dsv, dft, ell, nullptr, method, rule, J, lambda_fixed, k_trunc, gcv_weight, dcurve, dpo, s);
     LAUNCHCHK("parameter choice");
     ParamOut po;
     HIPCHK(hipMemcpyAsync(&po, dpo, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
@@ -960,6 +975,43 @@ int mqh_param_choice(const double* sv, const double* ftil, int32_t ell, int32_t 
     if (crit) *crit = po.crit;
     if (info_flags) *info_flags = po.flags;
     return (po.flags & (MQH_INFO_GCV_AT_EDGE | MQH_INFO_LCURVE_AT_EDGE)) ? MQH_WEDGE : MQH_OK;
+}
+
+int mqh_lsqr(const double* alpha, const double* beta, int32_t ell, int64_t n, int32_t rule, int32_t k_trunc, int32_t* k,
+             double* crit, uint32_t* info_flags, double* y, double* rho, double* eta, void* stream, uint32_t flags) {
+    if (alpha == nullptr || beta == nullptr || y == nullptr) return fail(MQH_EINVAL, "NULL array");
+    if (ell < 1 || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= MQH_MAX_ELL");
+    if (n < ell) return fail(MQH_EINVAL, "need n >= ell");
+    if (rule < MQH_RULE_GCV || rule > MQH_RULE_FIXED) return fail(MQH_EINVAL, "rule");
+    if (rule == MQH_RULE_FIXED && (k_trunc < 1 || k_trunc > ell)) return fail(MQH_EINVAL, "k_trunc");
+    if (!(flags & MQH_FLAG_DEVICE_PTRS) && (!all_finite(alpha, ell) || !all_finite(beta, ell + 1)))
+        return fail(MQH_EINVAL, "non-finite input");
+    hipStream_t s = (hipStream_t)stream;
+    Tmp t;
+    int rc;
+    const double *da, *db;
+    double *dy, *drho = nullptr, *deta = nullptr;
+    ParamOut* dpo;
+    if ((rc = dev_in(t, alpha, (size_t)ell, flags, s, &da))) return rc;
+    if ((rc = dev_in(t, beta, (size_t)ell + 1, flags, s, &db))) return rc;
+    if ((rc = dev_out(t, y, (size_t)ell, flags, &dy))) return rc;
+    if (rho != nullptr && (rc = dev_out(t, rho, (size_t)ell, flags, &drho))) return rc;
+    if (eta != nullptr && (rc = dev_out(t, eta, (size_t)ell, flags, &deta))) return rc;
+    if ((rc = t.get(&dpo, 1))) return rc;
+    launch_lsqr(da, db, ell, nullptr, n, rule, k_trunc, drho, deta, dpo, dy, ell, s);
+    LAUNCHCHK("LSQR iterates");
+    ParamOut po;
+    HIPCHK(hipMemcpyAsync(&po, dpo, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
+    if (!(flags & MQH_FLAG_DEVICE_PTRS)) {
+        HIPCHK(hipMemcpyAsync(y, dy, (size_t)ell * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (rho) HIPCHK(hipMemcpyAsync(rho, drho, (size_t)ell * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (eta) HIPCHK(hipMemcpyAsync(eta, deta, (size_t)ell * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (k) *k = po.k;
+    if (crit) *crit = po.crit;
+    if (info_flags) *info_flags = po.flags;
+    return (po.flags & MQH_INFO_LCURVE_AT_EDGE) ? MQH_WEDGE : MQH_OK;
 }
 
 int mqh_proj_solution(const double* sv, const double* ftil, const double* V, int32_t ell, int32_t method, double lambda,

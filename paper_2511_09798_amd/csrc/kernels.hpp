@@ -69,8 +69,10 @@ void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const
                        int64_t ldw, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
                        hipStream_t s);
 void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,
-                         int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double* curve,
+                         int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double omega, double* curve,
                          ParamOut* out, hipStream_t s);
+void launch_lsqr(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, int64_t n, int32_t rule,
+                 int32_t k_fixed, double* rho, double* eta, ParamOut* out, double* y, int32_t l_max, hipStream_t s);
 void launch_proj_solution(const double* sv, const double* ft, const double* V, int64_t ldv, int32_t l,
                           const int32_t* l_ptr, int32_t method, double lambda, int32_t k, const ParamOut* po,
                           double* y, int32_t l_max, hipStream_t s);

@@ -1,7 +1,9 @@
 // proj_kernels.hip -- the projected problem on the device (one workgroup
 // each): SVD of C_l (Algorithm 2 step 2, Algorithm 4 step 2), parameter
-// choice by GCV / L-curve / projected TSVD-GCV (Section 3.2-3.3) and the
-// projected solution y (Algorithm 2 step 5, Algorithm 4 step 8, SVD form).
+// choice by GCV (optionally weighted) / L-curve / projected TSVD-GCV
+// (Section 3.2-3.3), the projected solution y (Algorithm 2 step 5,
+// Algorithm 4 step 8, SVD form), and the LSQR iterates with their stopping
+// index (Section 3.4).
 #include <float.h>
 
 #include "bidiag_svd.hpp"
@@ -115,10 +117,12 @@ __device__ inline void gcv_terms(const double* sv, const double* ft, int l, doub
     tr = t;
 }
 
-__device__ inline double gcv_value(const double* sv, const double* ft, int l, double lam) {
+// rho_l^2 / ((l+1) - omega sum_i phi_i)^2: eq. (30) for omega = 1, the
+// weighted GCV otherwise.
+__device__ inline double gcv_value(const double* sv, const double* ft, int l, double lam, double omega) {
     double num, tr;
     gcv_terms(sv, ft, l, lam, num, tr);
-    const double den = (double)(l + 1) - tr;
+    const double den = (double)(l + 1) - omega * tr;
     return num / (den * den);
 }
 
@@ -146,8 +150,8 @@ __device__ inline double lcurve_kappa(const double* sv, const double* ft, int l,
     return (x1 * y2 - x2 * y1) / (q * sqrt(q));
 }
 
-// Block-parallel GCV for the refinement loop.
-__device__ inline double gcv_block(const double* sv, const double* ft, int l, double lam, double* lds) {
+// Block-parallel (weighted) GCV for the refinement loop.
+__device__ inline double gcv_block(const double* sv, const double* ft, int l, double lam, double omega, double* lds) {
     const double l2 = lam * lam;
     double a = 0.0, t = 0.0;
     for (int i = threadIdx.x; i < l; i += kProjThreads) {
@@ -160,7 +164,7 @@ __device__ inline double gcv_block(const double* sv, const double* ft, int l, do
     a = block_sum<kProjThreads>(a, lds);
     t = block_sum<kProjThreads>(t, lds);
     const double num = fma(ft[l], ft[l], a);
-    const double den = (double)(l + 1) - t;
+    const double den = (double)(l + 1) - omega * t;
     return num / (den * den);
 }
 
@@ -168,13 +172,17 @@ __global__ __launch_bounds__(kProjThreads) void k_param_choice(const double* __r
                                                                const double* __restrict__ ft, int32_t l_arg,
                                                                const int32_t* __restrict__ l_ptr, int32_t method,
                                                                int32_t rule, int32_t J, double lambda_fixed,
-                                                               int32_t k_fixed, double* __restrict__ curve,
+                                                               int32_t k_fixed, double omega_arg,
+                                                               double* __restrict__ curve,
                                                                ParamOut* __restrict__ out) {
     __shared__ double vals[kMaxGrid];
     __shared__ double lds[kProjThreads / kWave];
     __shared__ double s_lo, s_hi;
     const int tid = threadIdx.x;
     const int l = l_ptr != nullptr ? *l_ptr : l_arg;
+    // rule 3: weighted GCV (rule 0 with the trace term scaled by omega)
+    const double omega = rule == 3 ? omega_arg : 1.0;
+    if (rule == 3) rule = 0;
     if (l <= 0) {
         if (tid == 0) {
             out->lambda = 0.0;
@@ -199,12 +207,14 @@ __global__ __launch_bounds__(kProjThreads) void k_param_choice(const double* __r
                 double tail = ft[l] * ft[l];
                 for (int i = l - 1; i >= kmax; --i) tail = fma(ft[i], ft[i], tail);
                 // tail now = sum_{i >= kmax} ; walk k downwards to 1
-                double gk = tail / ((double)(l + 1 - kmax) * (double)(l + 1 - kmax));
+                double den = (double)(l + 1) - omega * (double)kmax;
+                double gk = tail / (den * den);
                 best = gk;
                 bestk = kmax;
                 for (int kk = kmax - 1; kk >= 1; --kk) {
                     tail = fma(ft[kk], ft[kk], tail);
-                    gk = tail / ((double)(l + 1 - kk) * (double)(l + 1 - kk));
+                    den = (double)(l + 1) - omega * (double)kk;
+                    gk = tail / (den * den);
                     if (gk <= best) {  // ties -> smaller k
                         best = gk;
                         bestk = kk;
@@ -218,9 +228,10 @@ __global__ __launch_bounds__(kProjThreads) void k_param_choice(const double* __r
                 const double q = ft[i] / sv[i];
                 nrm = fma(q, q, nrm);
             }
+            const double den = (double)(l + 1) - omega * (double)k;
             out->lambda = 0.0;
             out->k = k;
-            out->crit = res / ((double)(l + 1 - k) * (double)(l + 1 - k));
+            out->crit = res / (den * den);
             out->flags = 0;
             out->rho = sqrt(res);
             out->eta = sqrt(nrm);
@@ -243,7 +254,7 @@ __global__ __launch_bounds__(kProjThreads) void k_param_choice(const double* __r
         const double step = (t1 - t0) / (double)(J - 1);
         for (int j = tid; j < J; j += kProjThreads) {
             const double lj = j == J - 1 ? exp(t1) : exp(t0 + step * (double)j);
-            const double v = rule == 0 ? gcv_value(sv, ft, l, lj) : lcurve_kappa(sv, ft, l, lj);
+            const double v = rule == 0 ? gcv_value(sv, ft, l, lj, omega) : lcurve_kappa(sv, ft, l, lj);
             vals[j] = v;
             if (curve != nullptr) curve[j] = v;
         }
@@ -275,7 +286,7 @@ __global__ __launch_bounds__(kProjThreads) void k_param_choice(const double* __r
             double a = t0 + step * (double)(kb - 1);
             double b = kb + 1 == J - 1 ? t1 : t0 + step * (double)(kb + 1);
             double c = b - gr * (b - a), dd = a + gr * (b - a);
-            double fc = gcv_block(sv, ft, l, exp(c), lds), fd = gcv_block(sv, ft, l, exp(dd), lds);
+            double fc = gcv_block(sv, ft, l, exp(c), omega, lds), fd = gcv_block(sv, ft, l, exp(dd), omega, lds);
             int it = 0;
             while (fabs(b - a) > 1e-10 && it < 200) {
                 if (fc < fd) {
@@ -283,18 +294,18 @@ __global__ __launch_bounds__(kProjThreads) void k_param_choice(const double* __r
                     dd = c;
                     fd = fc;
                     c = b - gr * (b - a);
-                    fc = gcv_block(sv, ft, l, exp(c), lds);
+                    fc = gcv_block(sv, ft, l, exp(c), omega, lds);
                 } else {
                     a = c;
                     c = dd;
                     fc = fd;
                     dd = a + gr * (b - a);
-                    fd = gcv_block(sv, ft, l, exp(dd), lds);
+                    fd = gcv_block(sv, ft, l, exp(dd), omega, lds);
                 }
                 ++it;
             }
             const double lr = exp(0.5 * (a + b));
-            const double gv = gcv_block(sv, ft, l, lr, lds);
+            const double gv = gcv_block(sv, ft, l, lr, omega, lds);
             if (!(gv > crit)) {
                 lam = lr;
                 crit = gv;
@@ -318,7 +329,7 @@ __global__ __launch_bounds__(kProjThreads) void k_param_choice(const double* __r
         if (tid == 0) {
             out->lambda = lam;
             out->k = 0;
-            out->crit = rule == 2 ? gcv_value(sv, ft, l, lam) : crit;
+            out->crit = rule == 2 ? gcv_value(sv, ft, l, lam, 1.0) : crit;
             out->flags = flags;
             out->rho = sqrt(fma(ft[l], ft[l], r));
             out->eta = sqrt(e);
@@ -353,6 +364,163 @@ __global__ __launch_bounds__(kBlock) void k_proj_solution(const double* __restri
 }
 
 // ---------------------------------------------------------------------------
+// LSQR iterates on the projected problem (Section 3.4).  The k-th LSQR
+// iterate is Z_k y_k with y_k = argmin ||C_k y - beta_1 e_1||.  Left Givens
+// rotations reduce C_l to upper bidiagonal R (d, e) column by column while
+// carrying beta_1 e_1 (g); after k rotations the leading k x k block of R and
+// g_{1:k} are those of C_k, and the carried remainder is the residual
+// rho_k = ||C_k y_k - beta_1 e_1||.  eta_k = ||y_k|| by back substitution,
+// one k per thread.  Stopping index: rule 0 minimises rho_k^2 / (n - k)^2
+// over k <= min(l, n - 1) (the influence matrix of the k-th iterate is a
+// rank-k projector), ties to the smaller k; rule 1 takes the corner of the
+// discrete L-curve p_k = (log rho_k, log eta_k): the largest signed Menger
+// curvature of (p_{k+1}, p_k, p_{k-1}) over k = 2..l-1 (triples with a side
+// below 1e-12 of the extent of the points skipped; ties to the smaller k;
+// k = l with the edge flag when none qualifies); rule 2 takes k = k_fixed.
+// Outputs: y (l_max entries, y_k then zeros), out (k, crit, rho, eta,
+// flags), and rho / eta for every k when given.
+// ---------------------------------------------------------------------------
+
+__device__ inline double menger(double ax, double ay, double bx, double by, double cx, double cy) {
+    const double ux = bx - ax, uy = by - ay, vx = cx - bx, vy = cy - by, wx = cx - ax, wy = cy - ay;
+    const double la = sqrt(ux * ux + uy * uy), lb = sqrt(vx * vx + vy * vy), lc = sqrt(wx * wx + wy * wy);
+    return 2.0 * (ux * vy - uy * vx) / (la * lb * lc);
+}
+
+__global__ __launch_bounds__(kProjThreads) void k_lsqr(const double* __restrict__ alpha,
+                                                       const double* __restrict__ beta, int32_t l_arg,
+                                                       const int32_t* __restrict__ l_ptr, int64_t n, int32_t rule,
+                                                       int32_t k_fixed, double* __restrict__ rho_out,
+                                                       double* __restrict__ eta_out, ParamOut* __restrict__ out,
+                                                       double* __restrict__ y, int32_t l_max) {
+    __shared__ double d[kMaxEll], e[kMaxEll], g[kMaxEll], rho[kMaxEll], eta[kMaxEll];
+    __shared__ int s_k;
+    const int tid = threadIdx.x;
+    const int l = l_ptr != nullptr ? *l_ptr : l_arg;
+    for (int i = tid; i < l_max; i += kProjThreads) y[i] = 0.0;
+    if (l <= 0) {
+        if (tid == 0) {
+            out->lambda = 0.0;
+            out->k = 0;
+            out->crit = 0.0;
+            out->flags = 0;
+            out->rho = fabs(beta[0]);
+            out->eta = 0.0;
+        }
+        return;
+    }
+    if (tid == 0) {
+        double rhobar = alpha[0], phibar = beta[0];
+        for (int i = 0; i < l; ++i) {
+            double c, s, r;
+            bsvd::make_rot(rhobar, beta[i + 1], c, s, r);
+            d[i] = r;
+            g[i] = c * phibar;
+            phibar = -s * phibar;
+            rho[i] = fabs(phibar);
+            if (i + 1 < l) {
+                e[i] = s * alpha[i + 1];
+                rhobar = c * alpha[i + 1];
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = tid + 1; k <= l; k += kProjThreads) {
+        double yi = g[k - 1] / d[k - 1];
+        double ss = yi * yi;
+        for (int i = k - 2; i >= 0; --i) {
+            yi = (g[i] - e[i] * yi) / d[i];
+            ss = fma(yi, yi, ss);
+        }
+        eta[k - 1] = sqrt(ss);
+    }
+    __syncthreads();
+    for (int i = tid; i < l; i += kProjThreads) {
+        if (rho_out) rho_out[i] = rho[i];
+        if (eta_out) eta_out[i] = eta[i];
+    }
+    if (tid == 0) {
+        int k = l;
+        double crit = 0.0;
+        uint32_t flags = 0;
+        if (rule == 2) {
+            k = k_fixed < 1 ? 1 : (k_fixed > l ? l : k_fixed);
+            const double nk = (double)(n - k);
+            crit = n > k ? rho[k - 1] * rho[k - 1] / (nk * nk) : 0.0;
+        } else if (rule == 0) {
+            const int kmax = (int64_t)l < n - 1 ? l : (int)(n - 1);
+            k = 1;
+            crit = 0.0;
+            if (kmax >= 1) {
+                for (int kk = 1; kk <= kmax; ++kk) {
+                    const double nk = (double)(n - kk);
+                    const double gk = rho[kk - 1] * rho[kk - 1] / (nk * nk);
+                    if (kk == 1 || gk < crit) {
+                        crit = gk;
+                        k = kk;
+                    }
+                }
+            }
+        } else {
+            // discrete L-curve corner
+            k = l;
+            crit = 0.0;
+            flags = 4u;
+            if (l >= 3) {
+                double xlo = 0.0, xhi = 0.0, ylo = 0.0, yhi = 0.0;
+                for (int i = 0; i < l; ++i) {
+                    const double x = log(rho[i] > DBL_MIN ? rho[i] : DBL_MIN);
+                    const double yy = log(eta[i] > DBL_MIN ? eta[i] : DBL_MIN);
+                    xlo = i == 0 || x < xlo ? x : xlo;
+                    xhi = i == 0 || x > xhi ? x : xhi;
+                    ylo = i == 0 || yy < ylo ? yy : ylo;
+                    yhi = i == 0 || yy > yhi ? yy : yhi;
+                }
+                const double ext = xhi - xlo > yhi - ylo ? xhi - xlo : yhi - ylo;
+                const double tol = 1e-12 * ext;
+                bool found = false;
+                for (int kk = 2; kk < l; ++kk) {  // p_{kk+1}, p_kk, p_{kk-1} at 0-based kk, kk-1, kk-2
+                    const double ax = log(rho[kk] > DBL_MIN ? rho[kk] : DBL_MIN);
+                    const double ay = log(eta[kk] > DBL_MIN ? eta[kk] : DBL_MIN);
+                    const double bx = log(rho[kk - 1] > DBL_MIN ? rho[kk - 1] : DBL_MIN);
+                    const double by = log(eta[kk - 1] > DBL_MIN ? eta[kk - 1] : DBL_MIN);
+                    const double cx = log(rho[kk - 2] > DBL_MIN ? rho[kk - 2] : DBL_MIN);
+                    const double cy = log(eta[kk - 2] > DBL_MIN ? eta[kk - 2] : DBL_MIN);
+                    const double lab = sqrt((bx - ax) * (bx - ax) + (by - ay) * (by - ay));
+                    const double lbc = sqrt((cx - bx) * (cx - bx) + (cy - by) * (cy - by));
+                    const double lac = sqrt((cx - ax) * (cx - ax) + (cy - ay) * (cy - ay));
+                    if (!(lab > tol && lbc > tol && lac > tol)) continue;
+                    const double kap = menger(ax, ay, bx, by, cx, cy);
+                    if (!found || kap > crit) {
+                        found = true;
+                        crit = kap;
+                        k = kk;
+                    }
+                }
+                if (found) flags = (k == 2 || k == l - 1) ? 4u : 0u;
+            }
+        }
+        s_k = k;
+        out->lambda = 0.0;
+        out->k = k;
+        out->crit = crit;
+        out->flags = flags;
+        out->rho = rho[k - 1];
+        out->eta = eta[k - 1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int k = s_k;
+        double yi = g[k - 1] / d[k - 1];
+        y[k - 1] = yi;
+        for (int i = k - 2; i >= 0; --i) {
+            yi = (g[i] - e[i] * yi) / d[i];
+            y[i] = yi;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 
@@ -363,9 +531,15 @@ void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const
 }
 
 void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,
-                         int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double* curve,
+                         int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double omega, double* curve,
                          ParamOut* out, hipStream_t s) {
-    k_param_choice<<<1, kProjThreads, 0, s>>>(sv, ft, l, l_ptr, method, rule, J, lambda_fixed, k_fixed, curve, out);
+    k_param_choice<<<1, kProjThreads, 0, s>>>(sv, ft, l, l_ptr, method, rule, J, lambda_fixed, k_fixed, omega, curve,
+                                              out);
+}
+
+void launch_lsqr(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, int64_t n, int32_t rule,
+                 int32_t k_fixed, double* rho, double* eta, ParamOut* out, double* y, int32_t l_max, hipStream_t s) {
+    k_lsqr<<<1, kProjThreads, 0, s>>>(alpha, beta, l, l_ptr, n, rule, k_fixed, rho, eta, out, y, l_max);
 }
 
 void launch_proj_solution(const double* sv, const double* ft, const double* V, int64_t ldv, int32_t l,

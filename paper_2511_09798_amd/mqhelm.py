@@ -29,9 +29,11 @@ MQH_OP_MATFREE_FP64 = 1
 MQH_OP_MATFREE_FP32 = 2
 MQH_METHOD_INE_TSVD = 0
 MQH_METHOD_HKT = 1
+MQH_METHOD_LSQR = 2
 MQH_RULE_GCV = 0
 MQH_RULE_LCURVE = 1
 MQH_RULE_FIXED = 2
+MQH_RULE_WGCV = 3
 MQH_FLAG_DEVICE_PTRS = 1
 MQH_FLAG_TIME_PRODUCTS = 2
 MQH_INFO_BREAKDOWN = 1
@@ -52,7 +54,8 @@ class MQHError(RuntimeError):
 class mqh_solve_opts(ctypes.Structure):
     _fields_ = [("ell", ctypes.c_int32), ("reorth", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("rule", ctypes.c_int32), ("k_trunc", ctypes.c_int32), ("n_grid", ctypes.c_int32),
-                ("lambda_fixed", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("lambda_fixed", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("gcv_weight", ctypes.c_double)]
 
 
 class mqh_solve_info(ctypes.Structure):
@@ -78,9 +81,11 @@ _SIGNATURES = {
     "mqh_matrix_rows": (ctypes.c_int, [_vp, _i64, _i64, _vp, _u32]),
     "mqh_gkb": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), _u32]),
     "mqh_proj_svd": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _u32]),
-    "mqh_param_choice": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _d, _i32, ctypes.POINTER(_d),
+    "mqh_param_choice": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _d, _i32, _d, ctypes.POINTER(_d),
                                         ctypes.POINTER(_i32), ctypes.POINTER(_d), ctypes.POINTER(_u32), _vp, _vp,
                                         _u32]),
+    "mqh_lsqr": (ctypes.c_int, [_vp, _vp, _i32, _i64, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_d),
+                                ctypes.POINTER(_u32), _vp, _vp, _vp, _vp, _u32]),
     "mqh_proj_solution": (ctypes.c_int, [_vp, _vp, _vp, _i32, _i32, _d, _i32, _vp, _vp, _u32]),
     "mqh_lift": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _u32]),
     "mqh_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(mqh_solve_opts), _vp, _vp, _vp, _vp,
@@ -245,17 +250,32 @@ def mqh_proj_svd(alpha, beta, want_v: bool = True, stream=None):
 
 
 def mqh_param_choice(sv, ftil, method: int, rule: int, n_grid: int = 200, lambda_fixed: float = 0.0,
-                     k_trunc: int = 0, want_curve: bool = False, stream=None):
+                     k_trunc: int = 0, want_curve: bool = False, stream=None, gcv_weight: float = 1.0):
     ell = int(sv.shape[0])
     J = 200 if n_grid == 0 else n_grid
     curve = _empty_like_kind(sv, (J,)) if want_curve else None
     fl = _flags(sv, ftil, curve)
     lam, k, crit, inf = _d(0), _i32(0), _d(0), _u32(0)
     st = _check(lib.mqh_param_choice(_ptr(sv)[0], _ptr(ftil)[0], ell, int(method), int(rule), int(n_grid),
-                                     float(lambda_fixed), int(k_trunc), ctypes.byref(lam), ctypes.byref(k),
+                                     float(lambda_fixed), int(k_trunc), float(gcv_weight), ctypes.byref(lam),
+                                     ctypes.byref(k),
                                      ctypes.byref(crit), ctypes.byref(inf), _ptr(curve)[0], _stream_of(stream), fl),
                 "mqh_param_choice")
     return dict(lambda_=lam.value, k=int(k.value), crit=crit.value, flags=int(inf.value), curve=curve, status=st)
+
+
+def mqh_lsqr(alpha, beta, n: int, rule: int = MQH_RULE_GCV, k_trunc: int = 0, want_path: bool = True, stream=None):
+    """LSQR iterates on the projected problem and the stopping index (Section 3.4)."""
+    ell = int(alpha.shape[0])
+    y = _empty_like_kind(alpha, (ell,))
+    rho = _empty_like_kind(alpha, (ell,)) if want_path else None
+    eta = _empty_like_kind(alpha, (ell,)) if want_path else None
+    fl = _flags(alpha, beta, y, rho, eta)
+    k, crit, inf = _i32(0), _d(0), _u32(0)
+    st = _check(lib.mqh_lsqr(_ptr(alpha)[0], _ptr(beta)[0], ell, int(n), int(rule), int(k_trunc), ctypes.byref(k),
+                             ctypes.byref(crit), ctypes.byref(inf), _ptr(y)[0], _ptr(rho)[0], _ptr(eta)[0],
+                             _stream_of(stream), fl), "mqh_lsqr")
+    return dict(k=int(k.value), crit=crit.value, flags=int(inf.value), y=y, rho=rho, eta=eta, status=st)
 
 
 def mqh_proj_solution(sv, ftil, V, method: int, lam: float = 0.0, k: int = 0, stream=None):
@@ -295,18 +315,19 @@ class SolveOutput:
 
 def mqh_solve(h, f_int, g_bnd, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQH_RULE_GCV,
               k_trunc: int = 0, lambda_fixed: float = 0.0, n_grid: int = 200, reorth: int = 1,
-              time_products: bool = False, coef=None) -> SolveOutput:
+              time_products: bool = False, coef=None, gcv_weight: float = 1.0, want_sv: bool = True) -> SolveOutput:
     n = int(lib.mqh_problem_size(h))
     ref = f_int if f_int is not None else g_bnd
     if coef is None:
         coef = _empty_like_kind(ref, (n,))
     al = _zeros_like_kind(ref, (ell,))
     be = _zeros_like_kind(ref, (ell + 1,))
-    sv = _zeros_like_kind(ref, (ell,))
+    sv = _zeros_like_kind(ref, (ell,)) if want_sv else None
     fl = _flags(f_int, g_bnd, coef, al, be, sv)
     opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=int(method), rule=int(rule),
                           k_trunc=int(k_trunc), n_grid=int(n_grid), lambda_fixed=float(lambda_fixed),
-                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), reserved=0)
+                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), reserved=0,
+                          gcv_weight=float(gcv_weight))
     info = mqh_solve_info()
     st = _check(lib.mqh_solve(h, _ptr(f_int)[0], _ptr(g_bnd)[0], ctypes.byref(opts), _ptr(coef)[0], _ptr(al)[0],
                               _ptr(be)[0], _ptr(sv)[0], ctypes.byref(info)), "mqh_solve")

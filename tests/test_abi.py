@@ -5,12 +5,14 @@ import ctypes
 import math
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "mqhelm.h")
+INCLUDE = os.path.join(ROOT, "include")
+HEADER = os.path.join(INCLUDE, "mqhelm.h")
 
 
 @pytest.fixture(scope="module")
@@ -52,11 +54,23 @@ def test_constants_match_header(mq):
     assert mq.mqh_version() == _header_defines()["MQH_VERSION"]
 
 
-def test_struct_layouts(mq):
-    assert ctypes.sizeof(mq.mqh_solve_opts) == 40
-    assert mq.mqh_solve_opts.lambda_fixed.offset == 24
-    assert ctypes.sizeof(mq.mqh_solve_info) == 48 + 64
-    assert mq.mqh_solve_info.t_ms.offset == 48
+def test_struct_layouts(mq, tmp_path):
+    # the binding's ctypes structs against the header as a C compiler lays it out
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "mqhelm.h"\n'
+        'int main(void) {\n'
+        '  printf("%zu %zu %zu %zu %zu\\n", sizeof(mqh_solve_opts), offsetof(mqh_solve_opts, lambda_fixed),\n'
+        '         offsetof(mqh_solve_opts, flags), offsetof(mqh_solve_opts, gcv_weight), sizeof(mqh_solve_info));\n'
+        '  printf("%zu %zu\\n", offsetof(mqh_solve_info, flags), offsetof(mqh_solve_info, t_ms));\n'
+        '  return 0;\n}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", INCLUDE, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    vals = [int(v) for v in out]
+    O, F = mq.mqh_solve_opts, mq.mqh_solve_info
+    assert vals == [ctypes.sizeof(O), O.lambda_fixed.offset, O.flags.offset, O.gcv_weight.offset, ctypes.sizeof(F),
+                    F.flags.offset, F.t_ms.offset]
 
 
 def test_status_strings(mq):
@@ -98,10 +112,26 @@ def test_invalid_projected_arguments(mq):
     assert L.mqh_proj_svd(bad.ctypes.data, b.ctypes.data, 4, out.ctypes.data, out.ctypes.data, None, None, 0) == \
         mq.MQH_EINVAL
     lam = ctypes.c_double()
-    assert L.mqh_param_choice(a.ctypes.data, b.ctypes.data, 4, 1, 0, 2, 0.0, 0, ctypes.byref(lam), None, None, None,
-                              None, None, 0) == mq.MQH_EINVAL  # n_grid = 2 < 3
-    assert L.mqh_param_choice(a.ctypes.data, b.ctypes.data, 4, 0, 2, 0, 0.0, 9, ctypes.byref(lam), None, None, None,
-                              None, None, 0) == mq.MQH_EINVAL  # k_trunc > ell
+    assert L.mqh_param_choice(a.ctypes.data, b.ctypes.data, 4, 1, 0, 2, 0.0, 0, 1.0, ctypes.byref(lam), None, None,
+                              None, None, None, 0) == mq.MQH_EINVAL  # n_grid = 2 < 3
+    assert L.mqh_param_choice(a.ctypes.data, b.ctypes.data, 4, 0, 2, 0, 0.0, 9, 1.0, ctypes.byref(lam), None, None,
+                              None, None, None, 0) == mq.MQH_EINVAL  # k_trunc > ell
+    for w in (0.0, -0.5, 1.5, math.nan):  # weighted GCV needs 0 < w <= 1
+        assert L.mqh_param_choice(a.ctypes.data, b.ctypes.data, 4, 1, mq.MQH_RULE_WGCV, 0, 0.0, 0, w,
+                                  ctypes.byref(lam), None, None, None, None, None, 0) == mq.MQH_EINVAL
+    assert L.mqh_param_choice(a.ctypes.data, b.ctypes.data, 4, 1, 4, 0, 0.0, 0, 1.0, ctypes.byref(lam), None, None,
+                              None, None, None, 0) == mq.MQH_EINVAL  # unknown rule
+    k = ctypes.c_int32()
+    assert L.mqh_lsqr(a.ctypes.data, b.ctypes.data, 4, 3, 0, 0, ctypes.byref(k), None, None, out.ctypes.data, None,
+                      None, None, 0) == mq.MQH_EINVAL  # n < ell
+    assert L.mqh_lsqr(a.ctypes.data, b.ctypes.data, 4, 10, mq.MQH_RULE_WGCV, 0, ctypes.byref(k), None, None,
+                      out.ctypes.data, None, None, None, 0) == mq.MQH_EINVAL  # no weighted rule for LSQR
+    assert L.mqh_lsqr(a.ctypes.data, b.ctypes.data, 4, 10, mq.MQH_RULE_FIXED, 5, ctypes.byref(k), None, None,
+                      out.ctypes.data, None, None, None, 0) == mq.MQH_EINVAL  # k_trunc > ell
+    assert L.mqh_lsqr(bad.ctypes.data, b.ctypes.data, 4, 10, 0, 0, ctypes.byref(k), None, None, out.ctypes.data,
+                      None, None, None, 0) == mq.MQH_EINVAL  # non-finite alpha
+    assert L.mqh_lsqr(a.ctypes.data, b.ctypes.data, 4, 10, 0, 0, ctypes.byref(k), None, None, None, None, None, None,
+                      0) == mq.MQH_EINVAL  # NULL y
     assert L.mqh_proj_solution(a.ctypes.data, b.ctypes.data, a.ctypes.data, 4, 1, -1.0, 0, out.ctypes.data, None,
                                0) == mq.MQH_EINVAL  # negative lambda
     assert L.mqh_problem_destroy(None) == mq.MQH_OK
