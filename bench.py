@@ -153,6 +153,49 @@ def run_variant(mq, torch, p, spec, steps, warmup, dev, want_kernel_times=True):
     return res
 
 
+def learned_context(mq, torch, dev, count: int, n: int = 60000, ell: int = 60, seed: int = 5):
+    """Pump-casing-like solid, n nodes (80% interior), kappa in [5, 35], eps in [2, 8]: the plain
+    method (ell steps, GCV) against the learned solve (predicted steps and lambda, GCV as judge)."""
+    import numpy as np
+
+    from paper_2511_09798_amd import learned as L
+
+    model = L.load_predictor()
+    rng = np.random.default_rng(seed)
+    rows = []
+    for k in range(count):
+        prob = L.sample_problem(rng, kind="casing", n=n, kappa=float(rng.uniform(5, 35)),
+                                eps=float(rng.uniform(2, 8)), n_eval=2000)
+        pred, keep = L.make_device_predictor(mq, torch, model, prob["h"], dev)
+        with mq.Problem(prob["x_int"], prob["x_bnd"], prob["kappa"], prob["eps"], "matfree_fp32") as pr:
+            fi = torch.from_numpy(prob["f_int"]).to(dev)
+            gb = torch.from_numpy(prob["g_bnd"]).to(dev)
+            xe = torch.from_numpy(prob["x_eval"]).to(dev)
+            pr.solve(fi, gb, ell)  # warm
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            base = pr.solve(fi, gb, ell)
+            torch.cuda.synchronize()
+            t_base = time.perf_counter() - t
+            t = time.perf_counter()
+            out = pr.solve_learned(fi, gb, ell, pred)
+            torch.cuda.synchronize()
+            t_net = time.perf_counter() - t
+            ub = pr.eval(base.coef, xe).cpu().numpy()
+            un = pr.eval(out.coef, xe).cpu().numpy()
+        rows.append(dict(kappa=prob["kappa"], eps=prob["eps"], steps=out.ell_pred, used_net=out.used_net_lambda,
+                         t_gcv=t_base, t_learned=t_net, err_gcv=rel_l2(ub, prob["u_eval"]),
+                         err_learned=rel_l2(un, prob["u_eval"]), lam_gcv=base.lam, lam_learned=out.lam))
+        log("learned casing", k, json.dumps(rows[-1]))
+    eg = np.array([r["err_gcv"] for r in rows])
+    en = np.array([r["err_learned"] for r in rows])
+    return dict(workload=f"casing_n{n}", problems=count, ell=ell, mean_steps_learned=float(np.mean([r["steps"] for r in rows])),
+                steps_gcv=ell, mean_time_gcv_s=float(np.mean([r["t_gcv"] for r in rows])),
+                mean_time_learned_s=float(np.mean([r["t_learned"] for r in rows])),
+                median_rel_l2_gcv=float(np.median(eg)), median_rel_l2_learned=float(np.median(en)),
+                net_lambda_used=int(sum(r["used_net"] for r in rows)), cases=rows)
+
+
 def cpu_baseline(p, rows):
     """The oracle's entry-by-entry FP64 products on a row / column sample."""
     import numpy as np
@@ -190,6 +233,8 @@ def main():
                     help="first one is the headline; each is mode[:method[:rule[:weight]]]")
     ap.add_argument("--context-steps", type=int, default=1, help="timed solves of the non-headline variants")
     ap.add_argument("--cpu-rows", type=int, default=150000, help="row/column sample of the CPU baseline (0: skip)")
+    ap.add_argument("--learned", type=int, default=8,
+                    help="pump-casing problems for the learned-solve comparison (0: skip)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -275,6 +320,13 @@ def main():
                 config=dict(workload=p.name, n=n, n_int=p.n_int, n_bnd=p.n_bnd, kappa=p.kappa, eps=p.eps,
                             ell=p.ell, method="HKT", rule="GCV", operator=mode),
                 hkt_time_to_solution_s=head["solve_s"], roofline=roof, variants=ctx)
+    if args.learned > 0:
+        from paper_2511_09798_amd import learned as L
+
+        if os.path.exists(L.MODEL_PATH):
+            line["learned"] = learned_context(mq, torch, dev, args.learned)
+        else:
+            log("no trained predictor at", L.MODEL_PATH, "- learned comparison skipped")
     if args.cpu_rows > 0:
         log("cpu baseline", args.cpu_rows, "rows")
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_rows)

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MQH_VERSION 10100 /* 1.1.0 */
+#define MQH_VERSION 10200 /* 1.2.0 */
 
 /* ---- status codes ---- */
 #define MQH_OK 0
@@ -80,6 +80,13 @@ extern "C" {
 /* Largest number of Golub-Kahan steps a solve accepts (projected problem size). */
 #define MQH_MAX_ELL 1024
 
+/* ---- learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs ---- */
+#define MQH_MLP_IN 24
+#define MQH_MLP_WIDTH 128
+#define MQH_MLP_OUT 2
+#define MQH_MLP_PROBE 10      /* Golub-Kahan steps read by the features */
+#define MQH_MLP_NPARAMS 36482 /* 24*128+128 + 2*(128*128+128) + 128*2+2 */
+
 typedef struct mqh_problem mqh_problem;
 
 /* Options of a solve (Algorithms 2 and 4; Section 3). */
@@ -114,6 +121,35 @@ typedef struct {
                               ([6],[7] only with MQH_FLAG_TIME_PRODUCTS; the split-K
                               reduction that follows a product is not included) */
 } mqh_solve_info;
+
+/* Learned predictor of the regularisation parameter and the stopping index
+ * (used by mqh_solve_learned).  The network reads the standardised features
+ *   (log alpha_1..alpha_10, log beta_2..beta_11, log kappa, log eps, log n, log h)
+ * and predicts, after de-standardisation (out = y * out_std + out_mean),
+ *   out[0] = log(lambda / alpha_1)   out[1] = ell_stop / ell. */
+typedef struct {
+    const float* params;          /* MQH_MLP_NPARAMS device floats, layer by layer: W (out x in, row-major), b */
+    float in_mean[MQH_MLP_IN];    /* feature standardisation: (x - in_mean) / in_std */
+    float in_std[MQH_MLP_IN];
+    float out_mean[MQH_MLP_OUT];
+    float out_std[MQH_MLP_OUT];
+    double h;                     /* fill distance of the node set, (domain volume / n)^(1/3) */
+    int32_t ell_step;             /* the predicted stop index is rounded up to a multiple of this (>= 1) */
+    int32_t reserved;
+    double judge_ratio;           /* 0: GCV only reports; >= 1: also veto lambda_net when
+                                     GCV(lambda_net) > judge_ratio * min GCV */
+} mqh_predictor;
+
+/* What the learned solve did. */
+typedef struct {
+    int32_t ell_pred;             /* Golub-Kahan steps run (predicted stop index) */
+    int32_t used_net_lambda;      /* 1: the network's lambda, 0: the GCV fallback */
+    double lambda_net;            /* alpha_1 exp(out[0]) */
+    double lambda_gcv;            /* the GCV choice at ell_pred (the judge) */
+    double gcv_net;               /* GCV_l(lambda_net) */
+    double gcv_min;               /* GCV_l(lambda_gcv) */
+    double out[MQH_MLP_OUT];      /* de-standardised network outputs */
+} mqh_learned_info;
 
 int mqh_version(void);
 const char* mqh_status_str(int status);
@@ -276,6 +312,45 @@ int mqh_lift(const double* Z, int64_t n, int32_t ell, const double* y, double* c
  */
 int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts, double* coef,
               double* gkb_alpha, double* gkb_beta, double* ritz_sv, mqh_solve_info* info);
+
+/*
+ * The predictor network's kernels (FP32; every array is a device pointer and
+ * flags must contain MQH_FLAG_DEVICE_PTRS).  Batches are row-major.
+ *   mqh_mlp_forward:  y (batch x 2) from x (batch x 24); hidden receives the
+ *                     tanh outputs, 3 blocks of batch x 128 (kept for backward).
+ *   mqh_mlp_backward: grad (MQH_MLP_NPARAMS) of a loss from dy = dL/dy
+ *                     (batch x 2), x and hidden; work: 2 x batch x 128 floats.
+ *   mqh_mlp_loss:     loss = sum_b sum_k w_k (y - t)^2 / batch (one float,
+ *                     NULL allowed) and dy = dloss/dy (NULL allowed); w has 2 entries.
+ *   mqh_mlp_adam:     one Adam step (bias-corrected moments, step >= 1) on n parameters.
+ * Reductions run in a fixed order (deterministic).
+ */
+int mqh_mlp_forward(const float* params, const float* x, int32_t batch, float* y, float* hidden, void* stream,
+                    uint32_t flags);
+int mqh_mlp_backward(const float* params, const float* x, const float* hidden, const float* dy, int32_t batch,
+                     float* grad, float* work, void* stream, uint32_t flags);
+int mqh_mlp_loss(const float* y, const float* t, const float* w, int32_t batch, float* loss, float* dy, void* stream,
+                 uint32_t flags);
+int mqh_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                 float eps, int32_t step, void* stream, uint32_t flags);
+
+/*
+ * HKT with a learned stopping index and regularisation parameter, GCV as
+ * judge and fallback (Algorithm 4 with an early stop).  Runs MQH_MLP_PROBE
+ * Golub-Kahan steps, evaluates the predictor on the device, continues to
+ * ell_pred = the predicted stop index (rounded up to a multiple of
+ * pred->ell_step, within [MQH_MLP_PROBE, opts->ell]), computes the projected
+ * SVD and the GCV choice lambda_gcv at ell_pred (the judge: linfo reports
+ * lambda_gcv, GCV(lambda_net) and min GCV), and solves with the network's
+ * lambda_net = alpha_1 exp(out[0]) unless it falls back to lambda_gcv:
+ * lambda_net not finite or positive, more than a factor 10 outside GCV's
+ * search range [max(s_l, 16 eps_mach s_1), s_1], or (judge_ratio >= 1)
+ * GCV(lambda_net) > judge_ratio * GCV(lambda_gcv).
+ * opts: method HKT, rule GCV, ell >= MQH_MLP_PROBE; kappa > 0.
+ * coef (n) out; info and linfo may be NULL.
+ */
+int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts,
+                      const mqh_predictor* pred, double* coef, mqh_solve_info* info, mqh_learned_info* linfo);
 
 /*
  * Evaluate u(X_e) = sum_j coef_j phi(|X_e - X_j|) at m points

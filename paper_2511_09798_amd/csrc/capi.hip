@@ -4,6 +4,7 @@
 // Every call enqueues its kernels on the problem's stream, keeps all
 // Golub-Kahan scalars on the device (no host synchronisation inside the
 // loop) and synchronises once before it returns.
+#include <float.h>
 #include <math.h>
 #include <string.h>
 
@@ -142,6 +143,10 @@ struct mqh_problem {
     double* EP = nullptr;
     int64_t EP_cap = 0;
     double* u = nullptr;
+    // learned predictor: features (kMlpIn), outputs (kMlpOut), hidden
+    // activations (3 x kMlpWidth), standardisation (2 kMlpIn), FP32
+    float* mlp = nullptr;
+    ParamOut* pout2 = nullptr;
     // timing
     hipEvent_t ev[8] = {};
     std::vector<hipEvent_t> pev;
@@ -366,17 +371,23 @@ int ensure_gkb(mqh_problem* p, int32_t ell) {
 }
 
 // f must be staged in p->vx.  Runs Algorithm 1 with ell steps; everything stays on the device.
-int run_gkb(mqh_problem* p, int32_t ell, int32_t reorth, bool timed) {
+// Golub-Kahan steps [j0, j1) of a run of at most ell steps (j1 < 0: ell);
+// j0 = 0 starts the run from p->vx (beta_1 w_1 = f).  Steps after a
+// breakdown are no-ops on the device, so a run may be enqueued in pieces.
+int run_gkb(mqh_problem* p, int32_t ell, int32_t reorth, bool timed, int32_t j0 = 0, int32_t j1 = -1) {
     hipStream_t s = p->stream;
     const int64_t n = p->n, ldn = p->ldn;
     const int nbq = sumsq_blocks(n);
     const int nbu = update_blocks(n);
-    launch_init_state(p->st, ell, p->alpha, p->beta, s);
-    LAUNCHCHK("init state");
-    launch_sumsq_partial(p->vx, n, p->npart, nbq, p->st, s);
-    launch_norm_finalize(p->npart, nbq, 0, 0, n, p->alpha, p->beta, p->st, s);
-    launch_scale(p->vx, n, p->beta, p->W, p->st, s);
-    LAUNCHCHK("initial normalisation");
+    if (j1 < 0) j1 = ell;
+    if (j0 == 0) {
+        launch_init_state(p->st, ell, p->alpha, p->beta, s);
+        LAUNCHCHK("init state");
+        launch_sumsq_partial(p->vx, n, p->npart, nbq, p->st, s);
+        launch_norm_finalize(p->npart, nbq, 0, 0, n, p->alpha, p->beta, p->st, s);
+        launch_scale(p->vx, n, p->beta, p->W, p->st, s);
+        LAUNCHCHK("initial normalisation");
+    }
     auto orthonormalize = [&](double* v, const double* V, int32_t m, int kind, int32_t j, double* dst) -> int {
         int nparts;
         if (reorth && m > 0) {
@@ -396,7 +407,7 @@ int run_gkb(mqh_problem* p, int32_t ell, int32_t reorth, bool timed) {
         return MQH_OK;
     };
     int rc;
-    for (int32_t j = 0; j < ell; ++j) {
+    for (int32_t j = j0; j < j1; ++j) {
         double* Wj = p->W + (int64_t)j * ldn;
         double* Zj = p->Z + (int64_t)j * ldn;
         // r = A^T w_j - beta_j z_{j-1}
@@ -455,6 +466,8 @@ int mqh_problem_destroy(mqh_problem* p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     dfree(p->X64);
     dfree(p->X32);
+    dfree(p->mlp);
+    dfree(p->pout2);
     dfree(p->XS);
     dfree(p->perm);
     dfree(p->frames);
@@ -1054,6 +1067,193 @@ int mqh_lift(const double* Z, int64_t n, int32_t ell, const double* y, double* c
     if (!(flags & MQH_FLAG_DEVICE_PTRS))
         HIPCHK(hipMemcpyAsync(coef, dc, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    return MQH_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Predictor network (device pointers only) and the learned solve
+// ---------------------------------------------------------------------------
+
+int mqh_mlp_forward(const float* params, const float* x, int32_t batch, float* y, float* hidden, void* stream,
+                    uint32_t flags) {
+    if (!(flags & MQH_FLAG_DEVICE_PTRS)) return fail(MQH_EINVAL, "the network calls take device pointers only");
+    if (params == nullptr || x == nullptr || y == nullptr || hidden == nullptr) return fail(MQH_EINVAL, "NULL array");
+    if (batch < 1) return fail(MQH_EINVAL, "batch must be >= 1");
+    launch_mlp_forward(params, x, batch, y, hidden, (hipStream_t)stream);
+    LAUNCHCHK("network forward");
+    return MQH_OK;
+}
+
+int mqh_mlp_backward(const float* params, const float* x, const float* hidden, const float* dy, int32_t batch,
+                     float* grad, float* work, void* stream, uint32_t flags) {
+    if (!(flags & MQH_FLAG_DEVICE_PTRS)) return fail(MQH_EINVAL, "the network calls take device pointers only");
+    if (params == nullptr || x == nullptr || hidden == nullptr || dy == nullptr || grad == nullptr || work == nullptr)
+        return fail(MQH_EINVAL, "NULL array");
+    if (batch < 1) return fail(MQH_EINVAL, "batch must be >= 1");
+    launch_mlp_backward(params, x, hidden, dy, batch, grad, work, (hipStream_t)stream);
+    LAUNCHCHK("network backward");
+    return MQH_OK;
+}
+
+int mqh_mlp_loss(const float* y, const float* t, const float* w, int32_t batch, float* loss, float* dy, void* stream,
+                 uint32_t flags) {
+    if (!(flags & MQH_FLAG_DEVICE_PTRS)) return fail(MQH_EINVAL, "the network calls take device pointers only");
+    if (y == nullptr || t == nullptr || w == nullptr || (loss == nullptr && dy == nullptr))
+        return fail(MQH_EINVAL, "NULL array");
+    if (batch < 1) return fail(MQH_EINVAL, "batch must be >= 1");
+    launch_mse(y, t, w, batch, loss, dy, (hipStream_t)stream);
+    LAUNCHCHK("network loss");
+    return MQH_OK;
+}
+
+int mqh_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t n, float lr, float beta1, float beta2,
+                 float eps, int32_t step, void* stream, uint32_t flags) {
+    if (!(flags & MQH_FLAG_DEVICE_PTRS)) return fail(MQH_EINVAL, "the network calls take device pointers only");
+    if (params == nullptr || grad == nullptr || m == nullptr || v == nullptr) return fail(MQH_EINVAL, "NULL array");
+    if (n < 1 || step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps > 0.0f))
+        return fail(MQH_EINVAL, "bad Adam arguments");
+    launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream);
+    LAUNCHCHK("Adam step");
+    return MQH_OK;
+}
+
+int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts,
+                      const mqh_predictor* pred, double* coef, mqh_solve_info* info, mqh_learned_info* linfo) {
+    clear_info(info);
+    if (linfo) memset(linfo, 0, sizeof(*linfo));
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (opts == nullptr || pred == nullptr || pred->params == nullptr) return fail(MQH_EINVAL, "NULL opts / predictor");
+    if (coef == nullptr) return fail(MQH_EINVAL, "NULL coef");
+    if ((p->n_int > 0 && f_int == nullptr) || (p->n_bnd > 0 && g_bnd == nullptr)) return fail(MQH_EINVAL, "NULL data");
+    const int32_t ell = opts->ell;
+    if (ell < kMlpProbe || ell > p->n || ell > kMaxEll)
+        return fail(MQH_EINVAL, "need MQH_MLP_PROBE <= ell <= min(n, MQH_MAX_ELL)");
+    if (opts->reorth != 0 && opts->reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
+    if (opts->method != MQH_METHOD_HKT || opts->rule != MQH_RULE_GCV)
+        return fail(MQH_EINVAL, "the learned solve is HKT with GCV as judge and fallback");
+    const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
+    if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
+    if (!(pred->h > 0.0) || !isfinite(pred->h) || pred->ell_step < 1 ||
+        !(pred->judge_ratio == 0.0 || pred->judge_ratio >= 1.0))
+        return fail(MQH_EINVAL, "predictor needs h > 0, ell_step >= 1, judge_ratio 0 or >= 1");
+    if (!(p->kappa > 0.0)) return fail(MQH_EINVAL, "the predictor's features need kappa > 0");
+    for (int i = 0; i < kMlpIn; ++i)
+        if (!(pred->in_std[i] > 0.0f) || !isfinite(pred->in_mean[i])) return fail(MQH_EINVAL, "bad standardisation");
+    for (int i = 0; i < kMlpOut; ++i)
+        if (!(pred->out_std[i] > 0.0f) || !isfinite(pred->out_mean[i])) return fail(MQH_EINVAL, "bad standardisation");
+    const uint32_t flags = opts->flags;
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t s = p->stream;
+    if ((rc = ensure_gkb(p, ell))) return rc;
+    const size_t mlp_floats = kMlpIn + kMlpOut + 3 * kMlpWidth + 2 * kMlpIn;
+    if (p->mlp == nullptr && (rc = dalloc(&p->mlp, mlp_floats))) return rc;
+    if (p->pout2 == nullptr && (rc = dalloc(&p->pout2, 1))) return rc;
+    float* dx = p->mlp;
+    float* dyv = dx + kMlpIn;
+    float* dhid = dyv + kMlpOut;
+    float* dmean = dhid + 3 * kMlpWidth;
+    float* dstd = dmean + kMlpIn;
+    for (auto& e : p->pev) (void)hipEventDestroy(e);
+    p->pev.clear();
+    HIPCHK(hipEventRecord(p->ev[0], s));
+    HIPCHK(hipMemcpyAsync(dmean, pred->in_mean, kMlpIn * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dstd, pred->in_std, kMlpIn * sizeof(float), hipMemcpyHostToDevice, s));
+    if ((rc = stage_in(p->vx, f_int, p->n_int, flags, s))) return rc;
+    if ((rc = stage_in(p->vx + p->n_int, g_bnd, p->n_bnd, flags, s))) return rc;
+    HIPCHK(hipEventRecord(p->ev[1], s));
+    // probe: the first kMlpProbe steps, then the network
+    if ((rc = run_gkb(p, ell, opts->reorth, false, 0, kMlpProbe))) return rc;
+    launch_mlp_features(p->alpha, p->beta, p->kappa, p->eps, (double)p->n, pred->h, dmean, dstd, dx, s);
+    launch_mlp_forward(pred->params, dx, 1, dyv, dhid, s);
+    LAUNCHCHK("predictor");
+    float yo[kMlpOut];
+    double a1 = 0.0;
+    HIPCHK(hipMemcpyAsync(yo, dyv, sizeof(yo), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&a1, p->alpha, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&p->hres->st, p->st, sizeof(GkbState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double t0 = (double)yo[0] * pred->out_std[0] + pred->out_mean[0];
+    const double t1 = (double)yo[1] * pred->out_std[1] + pred->out_mean[1];
+    int32_t ell_pred = ell;
+    if (isfinite(t1)) {
+        const double want = t1 * (double)ell;
+        const double q = ceil(want / (double)pred->ell_step) * (double)pred->ell_step;
+        ell_pred = q < (double)kMlpProbe ? kMlpProbe : (q > (double)ell ? ell : (int32_t)q);
+    }
+    if (p->hres->st.stopped) ell_pred = p->hres->st.ell_done > kMlpProbe ? kMlpProbe : p->hres->st.ell_done;
+    const double lam_net = isfinite(t0) && a1 > 0.0 ? a1 * exp(t0) : 0.0;
+    // the rest of the run, then the projected problem with GCV as judge
+    if ((rc = run_gkb(p, ell, opts->reorth, false, kMlpProbe, ell_pred))) return rc;
+    launch_cap_ell(p->st, ell_pred, s);
+    HIPCHK(hipEventRecord(p->ev[2], s));
+    const int32_t* lp = &p->st->ell_done;
+    launch_fill(p->sv, ell, 0.0, s);
+    launch_bidiag_svd(p->alpha, p->beta, ell, lp, p->Vw, ell, p->sv, p->ftil, p->V, ell, p->svd_status, s);
+    LAUNCHCHK("projected SVD");
+    HIPCHK(hipEventRecord(p->ev[3], s));
+    launch_param_choice(p->sv, p->ftil, ell, lp, MQH_METHOD_HKT, MQH_RULE_GCV, J, 0.0, 0, 1.0, nullptr, p->pout, s);
+    launch_param_choice(p->sv, p->ftil, ell, lp, MQH_METHOD_HKT, MQH_RULE_FIXED, J, lam_net, 0, 1.0, nullptr, p->pout2,
+                        s);
+    LAUNCHCHK("parameter choice");
+    ParamOut po_gcv, po_net;
+    std::vector<double> svh((size_t)ell);
+    HIPCHK(hipMemcpyAsync(&po_gcv, p->pout, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&po_net, p->pout2, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&p->hres->svd_status, p->svd_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&p->hres->st, p->st, sizeof(GkbState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(svh.data(), p->sv, (size_t)ell * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (p->hres->svd_status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    // GCV's search range at ell_pred: a network lambda more than 10x outside it is an extrapolation
+    const int32_t le = p->hres->st.ell_done;
+    bool use_net = lam_net > 0.0 && isfinite(lam_net) && le >= 1;
+    if (use_net) {
+        const double hi = svh[0];
+        const double lo = svh[le - 1] > 16.0 * DBL_EPSILON * hi ? svh[le - 1] : 16.0 * DBL_EPSILON * hi;
+        use_net = lam_net >= 0.1 * lo && lam_net <= 10.0 * hi;
+    }
+    if (use_net && pred->judge_ratio >= 1.0) use_net = isfinite(po_net.crit) && po_net.crit <= pred->judge_ratio * po_gcv.crit;
+    const ParamOut& po = use_net ? po_net : po_gcv;
+    launch_proj_solution(p->sv, p->ftil, p->V, ell, ell, lp, MQH_METHOD_HKT, po.lambda, 0, nullptr, p->y, ell, s);
+    HIPCHK(hipEventRecord(p->ev[4], s));
+    launch_lift(p->Z, p->ldn, p->n, ell, lp, p->y, p->coef, s);
+    LAUNCHCHK("lift");
+    HIPCHK(hipEventRecord(p->ev[5], s));
+    HIPCHK(hipMemcpyAsync(&p->hres->st, p->st, sizeof(GkbState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(coef, p->coef, (size_t)p->n * sizeof(double), kind_out(flags), s));
+    HIPCHK(hipEventRecord(p->ev[6], s));
+    HIPCHK(hipStreamSynchronize(s));
+    const GkbState& st = p->hres->st;
+    uint32_t iflags = use_net ? 0u : po_gcv.flags;
+    if (st.flag != 0) iflags |= MQH_INFO_BREAKDOWN;
+    if (info) {
+        info->ell_done = st.ell_done;
+        info->k_chosen = 0;
+        info->lambda_chosen = po.lambda;
+        info->crit = po.crit;
+        info->resid_norm = po.rho;
+        info->sol_norm = po.eta;
+        info->flags = iflags;
+        float ms = 0.f;
+        const int pairs[6][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {0, 6}};
+        for (int q = 0; q < 6; ++q)
+            if (hipEventElapsedTime(&ms, p->ev[pairs[q][0]], p->ev[pairs[q][1]]) == hipSuccess) info->t_ms[q] = ms;
+    }
+    if (linfo) {
+        linfo->ell_pred = ell_pred;
+        linfo->used_net_lambda = use_net ? 1 : 0;
+        linfo->lambda_net = lam_net;
+        linfo->lambda_gcv = po_gcv.lambda;
+        linfo->gcv_net = po_net.crit;
+        linfo->gcv_min = po_gcv.crit;
+        linfo->out[0] = t0;
+        linfo->out[1] = t1;
+    }
+    if (st.flag != 0) return MQH_WBREAKDOWN;
+    if (iflags & MQH_INFO_GCV_AT_EDGE) return MQH_WEDGE;
     return MQH_OK;
 }
 

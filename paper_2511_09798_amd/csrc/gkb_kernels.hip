@@ -28,6 +28,11 @@ __global__ void k_init_state(GkbState* st, int32_t ell, double* alpha, double* b
     if (beta != nullptr && i <= ell) beta[i] = 0.0;
 }
 
+// Keep at most ell steps (a run stopped early by a breakdown keeps fewer).
+__global__ void k_cap_ell(GkbState* st, int32_t ell) {
+    if (threadIdx.x == 0 && st->ell_done > ell) st->ell_done = ell;
+}
+
 __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = v;
@@ -227,6 +232,8 @@ void launch_init_state(GkbState* st, int32_t ell, double* alpha, double* beta, h
     const int nt = 256;
     k_init_state<<<(ell + 1 + nt) / nt, nt, 0, s>>>(st, ell, alpha, beta);
 }
+
+void launch_cap_ell(GkbState* st, int32_t ell, hipStream_t s) { k_cap_ell<<<1, 64, 0, s>>>(st, ell); }
 
 void launch_fill(double* x, int64_t n, double v, hipStream_t s) {
     if (n <= 0) return;

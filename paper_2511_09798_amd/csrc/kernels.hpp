@@ -12,6 +12,15 @@ constexpr int kMaxGrid = 4096;  // largest lambda grid
 constexpr int kMfmFt = 2;       // 16-node fixed tiles per wave in the FP32-evaluated products
 constexpr int kMfmFixed = (kBlock / kWave) * kMfmFt * 16;  // fixed nodes per block (128)
 
+// Learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs.
+constexpr int kMlpIn = 24;
+constexpr int kMlpWidth = 128;
+constexpr int kMlpOut = 2;
+constexpr int kMlpLayers = 4;
+constexpr int kMlpProbe = 10;  // Golub-Kahan steps read by the features (alpha_1..10, beta_2..11)
+constexpr int64_t kMlpParams = (int64_t)kMlpIn * kMlpWidth + kMlpWidth + 2 * ((int64_t)kMlpWidth * kMlpWidth + kMlpWidth) +
+                               (int64_t)kMlpWidth * kMlpOut + kMlpOut;
+
 // Result of the parameter choice, device-resident.
 struct ParamOut {
     double lambda;
@@ -47,7 +56,19 @@ void launch_gen_rows(int prec, const void* X, int64_t n, int64_t n_int, int64_t 
 void launch_eval_partial(const double4* X, const double* coef, int64_t n, const double4* E, int64_t m, int S,
                          int64_t slice_len, const EntryConst& c, double* P, int64_t ldp, hipStream_t s);
 
+// predictor network (mlp_kernels.hip)
+int64_t mlp_param_offset(int layer);
+void launch_mlp_forward(const float* params, const float* x, int B, float* y, float* hidden, hipStream_t s);
+void launch_mlp_backward(const float* params, const float* x, const float* hidden, const float* dy, int B,
+                         float* grad, float* work, hipStream_t s);
+void launch_mse(const float* y, const float* t, const float* w, int B, float* loss, float* dy, hipStream_t s);
+void launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                 int32_t t, hipStream_t s);
+void launch_mlp_features(const double* alpha, const double* beta, double kappa, double eps, double n, double h,
+                         const float* mean, const float* stdv, float* x, hipStream_t s);
+
 // Golub-Kahan vectors (gkb_kernels.hip)
+void launch_cap_ell(GkbState* st, int32_t ell, hipStream_t s);
 void launch_init_state(GkbState* st, int32_t ell, double* alpha, double* beta, hipStream_t s);
 void launch_fill(double* x, int64_t n, double v, hipStream_t s);
 int sumsq_blocks(int64_t n);

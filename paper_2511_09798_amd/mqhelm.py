@@ -40,6 +40,11 @@ MQH_INFO_BREAKDOWN = 1
 MQH_INFO_GCV_AT_EDGE = 2
 MQH_INFO_LCURVE_AT_EDGE = 4
 MQH_MAX_ELL = 1024
+MQH_MLP_IN = 24
+MQH_MLP_WIDTH = 128
+MQH_MLP_OUT = 2
+MQH_MLP_PROBE = 10
+MQH_MLP_NPARAMS = 36482
 
 OP_MODES = {"stored_fp64": MQH_OP_STORED_FP64, "matfree_fp64": MQH_OP_MATFREE_FP64,
             "matfree_fp32": MQH_OP_MATFREE_FP32}
@@ -62,6 +67,18 @@ class mqh_solve_info(ctypes.Structure):
     _fields_ = [("ell_done", ctypes.c_int32), ("k_chosen", ctypes.c_int32), ("lambda_chosen", ctypes.c_double),
                 ("crit", ctypes.c_double), ("resid_norm", ctypes.c_double), ("sol_norm", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("t_ms", ctypes.c_double * 8)]
+
+
+class mqh_predictor(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("in_mean", ctypes.c_float * 24), ("in_std", ctypes.c_float * 24),
+                ("out_mean", ctypes.c_float * 2), ("out_std", ctypes.c_float * 2), ("h", ctypes.c_double),
+                ("ell_step", ctypes.c_int32), ("reserved", ctypes.c_int32), ("judge_ratio", ctypes.c_double)]
+
+
+class mqh_learned_info(ctypes.Structure):
+    _fields_ = [("ell_pred", ctypes.c_int32), ("used_net_lambda", ctypes.c_int32), ("lambda_net", ctypes.c_double),
+                ("lambda_gcv", ctypes.c_double), ("gcv_net", ctypes.c_double), ("gcv_min", ctypes.c_double),
+                ("out", ctypes.c_double * 2)]
 
 
 _vp = ctypes.c_void_p
@@ -91,6 +108,13 @@ _SIGNATURES = {
     "mqh_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(mqh_solve_opts), _vp, _vp, _vp, _vp,
                                  ctypes.POINTER(mqh_solve_info)]),
     "mqh_eval": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _u32]),
+    "mqh_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _u32]),
+    "mqh_mlp_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _u32]),
+    "mqh_mlp_loss": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _u32]),
+    "mqh_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, _i32, _vp, _u32]),
+    "mqh_solve_learned": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(mqh_solve_opts), ctypes.POINTER(mqh_predictor),
+                                         _vp, ctypes.POINTER(mqh_solve_info), ctypes.POINTER(mqh_learned_info)]),
 }
 
 
@@ -345,6 +369,90 @@ def mqh_eval(h, coef, x_eval, u=None):
 
 
 # --------------------------------------------------------------------------
+# Predictor network (FP32 torch tensors on the GPU)
+# --------------------------------------------------------------------------
+
+def _fptr(t) -> ctypes.c_void_p:
+    """Device pointer of a contiguous float32 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not (_is_torch(t) and t.is_cuda and t.dtype.itemsize == 4 and t.dtype.is_floating_point and t.is_contiguous()):
+        raise TypeError("the network calls take contiguous float32 GPU tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mqh_mlp_forward(params, x, y, hidden, stream=None):
+    _check(lib.mqh_mlp_forward(_fptr(params), _fptr(x), int(x.shape[0]), _fptr(y), _fptr(hidden), _stream_of(stream),
+                               MQH_FLAG_DEVICE_PTRS), "mqh_mlp_forward")
+
+
+def mqh_mlp_backward(params, x, hidden, dy, grad, work, stream=None):
+    _check(lib.mqh_mlp_backward(_fptr(params), _fptr(x), _fptr(hidden), _fptr(dy), int(x.shape[0]), _fptr(grad),
+                                _fptr(work), _stream_of(stream), MQH_FLAG_DEVICE_PTRS), "mqh_mlp_backward")
+
+
+def mqh_mlp_loss(y, t, w, loss=None, dy=None, stream=None):
+    _check(lib.mqh_mlp_loss(_fptr(y), _fptr(t), _fptr(w), int(y.shape[0]), _fptr(loss), _fptr(dy), _stream_of(stream),
+                            MQH_FLAG_DEVICE_PTRS), "mqh_mlp_loss")
+
+
+def mqh_mlp_adam(params, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, stream=None):
+    _check(lib.mqh_mlp_adam(_fptr(params), _fptr(grad), _fptr(m), _fptr(v), int(params.numel()), float(lr),
+                            float(beta1), float(beta2), float(eps), int(step), _stream_of(stream),
+                            MQH_FLAG_DEVICE_PTRS), "mqh_mlp_adam")
+
+
+def make_predictor(params, in_mean, in_std, out_mean, out_std, h: float, ell_step: int = 5,
+                   judge_ratio: float = 0.0) -> mqh_predictor:
+    pr = mqh_predictor()
+    pr.params = _fptr(params)
+    for i in range(MQH_MLP_IN):
+        pr.in_mean[i] = float(in_mean[i])
+        pr.in_std[i] = float(in_std[i])
+    for i in range(MQH_MLP_OUT):
+        pr.out_mean[i] = float(out_mean[i])
+        pr.out_std[i] = float(out_std[i])
+    pr.h = float(h)
+    pr.ell_step = int(ell_step)
+    pr.judge_ratio = float(judge_ratio)
+    return pr
+
+
+@dataclasses.dataclass
+class LearnedOutput:
+    coef: Any
+    status: int
+    ell_done: int
+    lam: float
+    ell_pred: int
+    used_net_lambda: bool
+    lambda_net: float
+    lambda_gcv: float
+    gcv_net: float
+    gcv_min: float
+    out: tuple
+    t_ms: list
+
+
+def mqh_solve_learned(h, f_int, g_bnd, ell: int, predictor: mqh_predictor, coef=None, n_grid: int = 200,
+                      reorth: int = 1) -> LearnedOutput:
+    n = int(lib.mqh_problem_size(h))
+    ref = f_int if f_int is not None else g_bnd
+    if coef is None:
+        coef = _empty_like_kind(ref, (n,))
+    fl = _flags(f_int, g_bnd, coef)
+    opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=MQH_METHOD_HKT, rule=MQH_RULE_GCV, k_trunc=0,
+                          n_grid=int(n_grid), lambda_fixed=0.0, flags=fl, reserved=0, gcv_weight=1.0)
+    info, li = mqh_solve_info(), mqh_learned_info()
+    st = _check(lib.mqh_solve_learned(h, _ptr(f_int)[0], _ptr(g_bnd)[0], ctypes.byref(opts), ctypes.byref(predictor),
+                                      _ptr(coef)[0], ctypes.byref(info), ctypes.byref(li)), "mqh_solve_learned")
+    return LearnedOutput(coef, st, info.ell_done, info.lambda_chosen, li.ell_pred, bool(li.used_net_lambda),
+                         li.lambda_net, li.lambda_gcv, li.gcv_net, li.gcv_min, (li.out[0], li.out[1]),
+                         list(info.t_ms))
+
+
+# --------------------------------------------------------------------------
 # Convenience wrapper
 # --------------------------------------------------------------------------
 
@@ -384,6 +492,9 @@ class Problem:
 
     def gkb(self, f, ell, reorth=True, want_bases=True):
         return mqh_gkb(self.h, f, ell, int(bool(reorth)), want_bases)
+
+    def solve_learned(self, f_int, g_bnd, ell, predictor, **kw) -> LearnedOutput:
+        return mqh_solve_learned(self.h, f_int, g_bnd, ell, predictor, **kw)
 
     def solve(self, f_int, g_bnd, ell, **kw) -> SolveOutput:
         return mqh_solve(self.h, f_int, g_bnd, ell, **kw)

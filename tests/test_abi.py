@@ -63,14 +63,18 @@ def test_struct_layouts(mq, tmp_path):
         '  printf("%zu %zu %zu %zu %zu\\n", sizeof(mqh_solve_opts), offsetof(mqh_solve_opts, lambda_fixed),\n'
         '         offsetof(mqh_solve_opts, flags), offsetof(mqh_solve_opts, gcv_weight), sizeof(mqh_solve_info));\n'
         '  printf("%zu %zu\\n", offsetof(mqh_solve_info, flags), offsetof(mqh_solve_info, t_ms));\n'
+        '  printf("%zu %zu %zu %zu\\n", sizeof(mqh_predictor), offsetof(mqh_predictor, h),\n'
+        '         offsetof(mqh_predictor, ell_step), offsetof(mqh_predictor, judge_ratio));\n'
+        '  printf("%zu %zu\\n", sizeof(mqh_learned_info), offsetof(mqh_learned_info, out));\n'
         '  return 0;\n}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", INCLUDE, str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     vals = [int(v) for v in out]
-    O, F = mq.mqh_solve_opts, mq.mqh_solve_info
+    O, F, P, L = mq.mqh_solve_opts, mq.mqh_solve_info, mq.mqh_predictor, mq.mqh_learned_info
     assert vals == [ctypes.sizeof(O), O.lambda_fixed.offset, O.flags.offset, O.gcv_weight.offset, ctypes.sizeof(F),
-                    F.flags.offset, F.t_ms.offset]
+                    F.flags.offset, F.t_ms.offset, ctypes.sizeof(P), P.h.offset, P.ell_step.offset,
+                    P.judge_ratio.offset, ctypes.sizeof(L), L.out.offset]
 
 
 def test_status_strings(mq):
@@ -143,3 +147,11 @@ def test_binding_rejects_mixed_and_wrong_arrays(mq):
         mq._ptr(np.ones(3, dtype=np.float32))
     with pytest.raises(TypeError):
         mq._ptr(np.ones((3, 3))[:, 0])
+
+
+def test_network_size_matches_oracle():
+    from oracle import mlp as M
+
+    d = _header_defines()
+    assert d["MQH_MLP_NPARAMS"] == M.n_params()
+    assert (d["MQH_MLP_IN"], d["MQH_MLP_WIDTH"], d["MQH_MLP_OUT"]) == (M.SIZES[0], M.SIZES[1], M.SIZES[-1])

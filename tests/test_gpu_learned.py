@@ -1,0 +1,198 @@
+"""GPU parity of the learned predictor's kernels against the FP64 oracle, and
+what the trained predictor gains over the method without it.
+
+Tolerances: the kernels run in FP32 (products of 24..128 terms, tanh);
+outputs and gradients are compared with the FP64 oracle evaluated on the
+same FP32 parameters and inputs, relative to the largest magnitude of the
+compared array: 2e-5 for activations and outputs, 1e-4 for gradients (one
+more product chain), 1e-6 relative for an Adam step.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2511_09798_amd import mqhelm
+
+    return mqhelm, torch, torch.device("cuda:0")
+
+
+def _f32(torch, dev, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+@pytest.mark.parametrize("batch", [1, 37, 300])
+def test_mlp_forward_backward_loss(env, batch):
+    mq, torch, dev = env
+    rng = np.random.default_rng(batch)
+    P = M.n_params()
+    params = (rng.normal(scale=0.15, size=P)).astype(np.float32)
+    X = rng.normal(size=(batch, 24)).astype(np.float32)
+    T = rng.normal(size=(batch, 2)).astype(np.float32)
+    w = np.array([1.0, 0.7], dtype=np.float32)
+    p_d, x_d, t_d, w_d = (_f32(torch, dev, a) for a in (params, X, T, w))
+    y_d = torch.empty((batch, 2), dtype=torch.float32, device=dev)
+    hid = torch.empty(3 * batch * 128, dtype=torch.float32, device=dev)
+    say("mlp forward", batch)
+    mq.mqh_mlp_forward(p_d, x_d, y_d, hid)
+    Y, H = M.forward(params.astype(np.float64), X.astype(np.float64))
+    y = y_d.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(y - Y)) <= 2e-5 * np.max(np.abs(Y))
+    h = hid.cpu().numpy().reshape(3, batch, 128).astype(np.float64)
+    for l in range(3):
+        assert np.max(np.abs(h[l] - H[l + 1])) <= 2e-5
+    say("mlp loss", batch)
+    loss_d = torch.empty(1, dtype=torch.float32, device=dev)
+    dy_d = torch.empty((batch, 2), dtype=torch.float32, device=dev)
+    mq.mqh_mlp_loss(y_d, t_d, w_d, loss_d, dy_d)
+    loss, dY = M.mse_loss(y, T.astype(np.float64), w.astype(np.float64))
+    assert float(loss_d.cpu()) == pytest.approx(loss, rel=1e-5)
+    assert np.max(np.abs(dy_d.cpu().numpy() - dY)) <= 1e-6 * np.max(np.abs(dY))
+    say("mlp backward", batch)
+    g_d = torch.empty(P, dtype=torch.float32, device=dev)
+    work = torch.empty(2 * batch * 128, dtype=torch.float32, device=dev)
+    mq.mqh_mlp_backward(p_d, x_d, hid, dy_d, g_d, work)
+    G = M.backward(params.astype(np.float64), H, dy_d.cpu().numpy().astype(np.float64))
+    g = g_d.cpu().numpy().astype(np.float64)
+    off = 0
+    for l in range(4):  # per layer, relative to the layer's largest gradient
+        o, i = M.SIZES[l + 1], M.SIZES[l]
+        sl = slice(off, off + o * i + o)
+        assert np.max(np.abs(g[sl] - G[sl])) <= 1e-4 * np.max(np.abs(G[sl])), l
+        off += o * i + o
+
+
+def test_mlp_adam(env):
+    mq, torch, dev = env
+    rng = np.random.default_rng(3)
+    n = M.n_params()
+    p = rng.normal(size=n).astype(np.float32)
+    g = rng.normal(size=n).astype(np.float32)
+    m = (0.1 * rng.normal(size=n)).astype(np.float32)
+    v = (0.1 * rng.random(size=n)).astype(np.float32)
+    p_d, g_d, m_d, v_d = (_f32(torch, dev, a) for a in (p, g, m, v))
+    say("adam")
+    mq.mqh_mlp_adam(p_d, g_d, m_d, v_d, 7, 1e-3)
+    # the oracle gets the hyperparameters as the kernel holds them (FP32-rounded)
+    f = lambda a: float(np.float32(a))  # noqa: E731
+    po, mo, vo = M.adam_step(p, g, m, v, 7, f(1e-3), f(0.9), f(0.999), f(1e-8))
+    np.testing.assert_allclose(p_d.cpu().numpy(), po, rtol=1e-6, atol=1e-7)
+    # the moments are one FMA each in FP32: a few ulps of the terms' magnitude
+    u32 = 2.0 ** -24
+    tm = 0.9 * np.abs(m) + 0.1 * np.abs(g)
+    tv = 0.999 * np.abs(v) + 0.001 * g * g
+    assert np.all(np.abs(m_d.cpu().numpy() - mo) <= 4 * u32 * tm)
+    assert np.all(np.abs(v_d.cpu().numpy() - vo) <= 4 * u32 * tv)
+
+
+def test_training_decreases_loss(env):
+    # a few hundred steps of the library's kernels fit a smooth synthetic map
+    mq, torch, dev = env
+    from paper_2511_09798_amd import learned as L
+
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(1024, 24)).astype(np.float32)
+    T = np.stack([np.tanh(X[:, 0] - 0.5 * X[:, 3]), 0.3 * X[:, 5] * X[:, 6]], axis=1).astype(np.float32)
+    tr = L.Trainer(mq, torch, L.init_params(0), 128, dev)
+    xt, tt = _f32(torch, dev, X), _f32(torch, dev, T)
+
+    def mse():
+        return float(np.mean((tr.predict(xt).cpu().numpy() - T) ** 2))
+
+    before = mse()
+    say("training steps")
+    for ep in range(40):
+        for b in range(8):
+            tr.step(xt[b * 128:(b + 1) * 128].contiguous(), tt[b * 128:(b + 1) * 128].contiguous(), 3e-3)
+    after = mse()
+    assert after < 0.1 * before, (before, after)
+
+
+# ---------------------------------------------------------------------------
+# the learned solve with the trained predictor
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def model():
+    from paper_2511_09798_amd import learned as L
+
+    return L.load_predictor()
+
+
+def _heldout(L, seed, count):
+    rng = np.random.default_rng(seed)
+    return [L.sample_problem(rng) for _ in range(count)]
+
+
+def test_learned_solve_matches_oracle_network(env, model, orc):
+    mq, torch, dev = env
+    from paper_2511_09798_amd import learned as L
+
+    prob = L.sample_problem(np.random.default_rng(4242), kind="cube", n=1500, kappa=2.0, eps=0.6)
+    X = np.concatenate([prob["x_int"], prob["x_bnd"]])
+    f = np.concatenate([prob["f_int"], prob["g_bnd"]])
+    ni = prob["x_int"].shape[0]
+    pred, keep = L.make_device_predictor(mq, torch, model, prob["h"], dev)
+    with mq.Problem(prob["x_int"], prob["x_bnd"], prob["kappa"], prob["eps"], "matfree_fp64") as pr:
+        say("learned solve")
+        out = pr.solve_learned(prob["f_int"], prob["g_bnd"], 60, pred)
+        g = pr.gkb(f, 10)
+    # the network on the oracle's features of the same first scalars
+    x = M.features(g["alpha"], g["beta"], prob["kappa"], prob["eps"], X.shape[0], prob["h"],
+                   model["in_mean"], model["in_std"])
+    y, _ = M.forward(model["params"].astype(np.float64), x[None, :])
+    t = y[0] * model["out_std"] + model["out_mean"]
+    assert abs(out.out[0] - t[0]) <= 1e-3 and abs(out.out[1] - t[1]) <= 1e-4
+    want = int(math.ceil(out.out[1] * 60 / 5) * 5)
+    assert out.ell_pred == min(max(want, 10), 60)
+    assert out.lambda_net == pytest.approx(g["alpha"][0] * math.exp(out.out[0]), rel=1e-12)
+    # the coefficients are the HKT solution at (ell_pred, the lambda used)
+    r = orc.solve(X, ni, prob["kappa"], prob["eps"], f, out.ell_pred, rule=orc.RULE_FIXED, lambda_fixed=out.lam,
+                  stored=False)
+    u = orc.eval_u(X, prob["eps"], out.coef, prob["x_eval"])
+    uo = orc.eval_u(X, prob["eps"], r.coef, prob["x_eval"])
+    assert np.linalg.norm(u - uo) <= 1e-8 * np.linalg.norm(uo)
+    assert keep is not None
+
+
+def test_learned_solve_falls_back_to_gcv(env, model):
+    mq, torch, dev = env
+    from paper_2511_09798_amd import learned as L
+
+    prob = L.sample_problem(np.random.default_rng(77), kind="sphere", n=1200)
+    bad = dict(model)
+    bad["out_mean"] = np.array([60.0, model["out_mean"][1]], dtype=np.float32)  # lambda_net ~ e^60 alpha_1
+    pred, keep = L.make_device_predictor(mq, torch, bad, prob["h"], dev)
+    with mq.Problem(prob["x_int"], prob["x_bnd"], prob["kappa"], prob["eps"], "matfree_fp32") as pr:
+        say("learned fallback")
+        out = pr.solve_learned(prob["f_int"], prob["g_bnd"], 60, pred)
+    assert not out.used_net_lambda and out.lam == out.lambda_gcv
+    assert keep is not None
+
+
+def test_learned_gain_over_gcv(env, model):
+    # held-out problems of the training distribution (a seed the training data did not use):
+    # the plain method (60 steps, GCV) against the learned solve (predicted steps and lambda)
+    mq, torch, dev = env
+    from paper_2511_09798_amd import learned as L
+
+    rep = L.compare(_heldout(L, 909, 48), model, log=lambda k, r: say("gain case", k, r["kind"], r["n"]))
+    say("report", {k: v for k, v in rep.items() if k != "cases"})
+    assert rep["median_err_learned"] < rep["median_err_gcv"]
+    assert rep["frac_err_below_0_5"]["learned"] > rep["frac_err_below_0_5"]["gcv"]
+    assert rep["mean_steps_learned"] < 60
