@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MQH_VERSION 10200 /* 1.2.0 */
+#define MQH_VERSION 10300 /* 1.3.0 */
 
 /* ---- status codes ---- */
 #define MQH_OK 0
@@ -79,6 +79,7 @@ extern "C" {
 
 /* Largest number of Golub-Kahan steps a solve accepts (projected problem size). */
 #define MQH_MAX_ELL 1024
+#define MQH_BLOCK_RHS 16 /* right-hand sides run in lockstep per group (mqh_gkb_multi, mqh_solve_multi) */
 
 /* ---- learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs ---- */
 #define MQH_MLP_IN 24
@@ -312,6 +313,46 @@ int mqh_lift(const double* Z, int64_t n, int32_t ell, const double* y, double* c
  */
 int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts, double* coef,
               double* gkb_alpha, double* gkb_beta, double* ritz_sv, mqh_solve_info* info);
+
+/*
+ * Several right-hand sides on the same A (Algorithm 1, one independent run
+ * per right-hand side; Algorithm 4 for the solve).  The runs go in groups of
+ * MQH_BLOCK_RHS in lockstep: step j of every run of a group is enqueued
+ * together, so one pass over A serves the whole group.  In
+ * MQH_OP_MATFREE_FP32 a group of two or more shares a block product: the
+ * FP32-evaluated entries of a tile multiply all the group's vectors on the
+ * matrix cores (FP32 products, FP32 sums over 256 nodes, FP64 across
+ * chunks and slices); a group of one, and the FP64 forms, run one product
+ * per run, bit-identical to mqh_gkb / mqh_solve.  Everything else (norms,
+ * reorthogonalisation, scalars, breakdown tests, projected SVD, parameter
+ * choice, lift) is per run in FP64 as in the single-run calls.
+ *
+ * mqh_apply_multi: Y_k = op(A) X_k - shifts[k] Z_k for k < nrhs, the
+ * products of Algorithm 1 (steps 3 and 5) for a group; X_k at X + k * ldx,
+ * Z_k at Zs + k * ldz (Zs NULL: no shift term), Y_k at Y + k * ldy, all
+ * leading dimensions >= n; shifts is a host array of nrhs values (NULL:
+ * zeros); Y must not alias X or Zs.
+ *
+ * F: nrhs right-hand sides [f_int; g_bnd] of length n, column k at
+ *    F + k * ldf (ldf >= n).
+ * mqh_gkb_multi outputs (any may be NULL), run k's block after those of
+ * runs 0..k-1, each laid out as in mqh_gkb:
+ *   W (ell+1) n doubles per run, Z ell n, alpha ell, beta ell+1, ell_done 1.
+ * mqh_solve_multi: opts as in mqh_solve (MQH_FLAG_TIME_PRODUCTS sums the
+ * product kernels of each group: t_ms[6], t_ms[7] report the group's
+ * totals, as do the other t_ms); coef column k at coef + k * ldc
+ * (ldc >= n); info: nrhs records (NULL allowed).
+ * Returns MQH_WBREAKDOWN if any run broke down, else MQH_WEDGE if any
+ * choice sits at the edge of its range, else MQH_OK; errors as mqh_solve.
+ * Workspace: per group 2 (ell+1) n doubles of bases per run (grown on
+ * demand, kept with the problem).
+ */
+int mqh_apply_multi(mqh_problem* p, int32_t trans, const double* X, int64_t ldx, int32_t nrhs, const double* shifts,
+                    const double* Zs, int64_t ldz, double* Y, int64_t ldy, uint32_t flags);
+int mqh_gkb_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, int32_t ell, int32_t reorth, double* W,
+                  double* Z, double* alpha, double* beta, int32_t* ell_done, uint32_t flags);
+int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, const mqh_solve_opts* opts,
+                    double* coef, int64_t ldc, mqh_solve_info* info);
 
 /*
  * The predictor network's kernels (FP32; every array is a device pointer and

@@ -18,6 +18,8 @@
 
 using namespace mqh;
 
+static_assert(MQH_BLOCK_RHS == kBlkRhs, "block size of the lockstep runs");
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -83,6 +85,40 @@ struct HostResults {
 
 }  // namespace
 
+// Workspace of the lockstep multi-right-hand-side Golub-Kahan runs: up to
+// kBlkRhs runs side by side, run k's arrays at base + k * stride.
+struct MultiWs {
+    int32_t nz_cap = 0, ell_cap = 0;
+    int64_t vstr = 0;     // stride of the length-(ell + 2) arrays (alpha, beta, sv, ftil, y, cvec)
+    int64_t bstr = 0;     // stride of a basis, (ell_cap + 1) x ldn
+    int64_t gstr = 0;     // stride of the reorthogonalisation partials
+    int64_t nstr = 0;     // stride of the norm partials
+    double* W = nullptr;  // bases, ldn-padded columns
+    double* Z = nullptr;
+    double* alpha = nullptr;
+    double* beta = nullptr;
+    double* sv = nullptr;
+    double* ftil = nullptr;
+    double* y = nullptr;
+    double* cvec = nullptr;
+    double* gpart = nullptr;
+    double* npart = nullptr;
+    double* Vw = nullptr;  // ell_cap x ell_cap per run
+    double* V = nullptr;
+    GkbState* st = nullptr;
+    ParamOut* pout = nullptr;
+    int32_t* status = nullptr;
+    double* X = nullptr;     // staged right-hand sides, ldn each
+    double* Y = nullptr;     // product outputs, ldn each
+    double* coef = nullptr;  // coefficients, ldn each
+    // block products (FP32-evaluated entries): right-hand sides in the sorted
+    // node order, n x kBlkRhs FP32, and split-K partials S x kBlkRhs x ldn
+    float* Vg = nullptr;
+    double* PB = nullptr;
+    int S_rows = 1, S_cols = 1;
+    int64_t slice_rows = 0, slice_cols = 0;
+};
+
 struct mqh_problem {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -147,6 +183,8 @@ struct mqh_problem {
     // activations (3 x kMlpWidth), standardisation (2 kMlpIn), FP32
     float* mlp = nullptr;
     ParamOut* pout2 = nullptr;
+    // multi-right-hand-side runs
+    MultiWs mw;
     // timing
     hipEvent_t ev[8] = {};
     std::vector<hipEvent_t> pev;
@@ -422,6 +460,204 @@ int run_gkb(mqh_problem* p, int32_t ell, int32_t reorth, bool timed, int32_t j0 
     return MQH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Lockstep multi-right-hand-side Golub-Kahan runs: up to kBlkRhs independent
+// runs of Algorithm 1 on the same A, step j of every run enqueued together so
+// that each pass over A serves all of them (a block product with the
+// FP32-evaluated entries; one product per run for the FP64 forms).  Each run
+// keeps its own scalars, bases and breakdown state, exactly as a single run.
+// ---------------------------------------------------------------------------
+
+void multi_free(MultiWs& w) {
+    dfree(w.W);
+    dfree(w.Z);
+    dfree(w.alpha);
+    dfree(w.beta);
+    dfree(w.sv);
+    dfree(w.ftil);
+    dfree(w.y);
+    dfree(w.cvec);
+    dfree(w.gpart);
+    dfree(w.npart);
+    dfree(w.Vw);
+    dfree(w.V);
+    dfree(w.st);
+    dfree(w.pout);
+    dfree(w.status);
+    dfree(w.X);
+    dfree(w.Y);
+    dfree(w.coef);
+    dfree(w.Vg);
+    dfree(w.PB);
+    w.nz_cap = 0;
+    w.ell_cap = 0;
+}
+
+// Slices of a block product: enough workgroups for a few rounds over the
+// chip, slices of whole LDS chunks.
+void block_shapes(mqh_problem* p, MultiWs& w) {
+    const int64_t n = p->n, nb = mfm_blocks(n, p->n_int);
+    const int64_t target_blocks = 4096;
+    int64_t s = (target_blocks + nb - 1) / nb;
+    if (s < 1) s = 1;
+    if (s > 64) s = 64;
+    int64_t l = (n + s - 1) / s;
+    l = round_up(l < kMfmChunk ? kMfmChunk : l, kMfmChunk);
+    s = (n + l - 1) / l;
+    w.S_rows = w.S_cols = (int)(s < 1 ? 1 : s);
+    w.slice_rows = w.slice_cols = l;
+}
+
+int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
+    MultiWs& w = p->mw;
+    if (nz <= w.nz_cap && ell <= w.ell_cap) return MQH_OK;
+    const int zc = nz > w.nz_cap ? nz : w.nz_cap;
+    const int32_t lc = ell > w.ell_cap ? ell : w.ell_cap;
+    multi_free(w);
+    const int64_t n = p->n, ldn = p->ldn, cols = (int64_t)lc + 1;
+    w.vstr = (int64_t)lc + 2;
+    w.bstr = cols * ldn;
+    w.gstr = (int64_t)gemvt_blocks(n) * cols;
+    w.nstr = update_blocks(n) > 1024 ? update_blocks(n) : 1024;
+    const size_t Z = (size_t)zc;
+    int rc;
+    if ((rc = dalloc(&w.W, Z * (size_t)w.bstr)) || (rc = dalloc(&w.Z, Z * (size_t)w.bstr)) ||
+        (rc = dalloc(&w.alpha, Z * (size_t)w.vstr)) || (rc = dalloc(&w.beta, Z * (size_t)w.vstr)) ||
+        (rc = dalloc(&w.sv, Z * (size_t)w.vstr)) || (rc = dalloc(&w.ftil, Z * (size_t)w.vstr)) ||
+        (rc = dalloc(&w.y, Z * (size_t)w.vstr)) || (rc = dalloc(&w.cvec, Z * (size_t)w.vstr)) ||
+        (rc = dalloc(&w.gpart, Z * (size_t)w.gstr)) || (rc = dalloc(&w.npart, Z * (size_t)w.nstr)) ||
+        (rc = dalloc(&w.Vw, Z * (size_t)lc * (size_t)lc)) || (rc = dalloc(&w.V, Z * (size_t)lc * (size_t)lc)) ||
+        (rc = dalloc(&w.st, Z)) || (rc = dalloc(&w.pout, Z)) || (rc = dalloc(&w.status, Z)) ||
+        (rc = dalloc(&w.X, Z * (size_t)ldn)) || (rc = dalloc(&w.Y, Z * (size_t)ldn)) ||
+        (rc = dalloc(&w.coef, Z * (size_t)ldn))) {
+        multi_free(w);
+        return rc;
+    }
+    hipStream_t s = p->stream;
+    // zero padding past n and unused basis columns
+    hipError_t e;
+    if ((e = hipMemsetAsync(w.W, 0, Z * (size_t)w.bstr * sizeof(double), s)) ||
+        (e = hipMemsetAsync(w.Z, 0, Z * (size_t)w.bstr * sizeof(double), s)) ||
+        (e = hipMemsetAsync(w.X, 0, Z * (size_t)ldn * sizeof(double), s)) ||
+        (e = hipMemsetAsync(w.Y, 0, Z * (size_t)ldn * sizeof(double), s))) {
+        multi_free(w);
+        return hip_fail(e, "workspace clear");
+    }
+    if (p->mode == MQH_OP_MATFREE_FP32) {
+        block_shapes(p, w);
+        const int S = w.S_rows > w.S_cols ? w.S_rows : w.S_cols;
+        if ((rc = dalloc(&w.Vg, (size_t)n * kBlkRhs)) ||
+            (rc = dalloc(&w.PB, (size_t)S * kBlkRhs * (size_t)ldn))) {
+            multi_free(w);
+            return rc;
+        }
+    }
+    w.nz_cap = zc;
+    w.ell_cap = lc;
+    return MQH_OK;
+}
+
+// Y_k = op(A) X_k - shift_k Zs_k for runs k < nz (run k's vectors at
+// base + k * stride; shift_k = shift[k * sstr]; no shift term when Zs is
+// null).  Stopped runs are skipped.
+int block_product(mqh_problem* p, int nz, int trans, const double* X, int64_t xstr, const double* shift,
+                  int64_t sstr, const double* Zs, int64_t zstr, double* Y, const GkbState* st, bool timed) {
+    MultiWs& w = p->mw;
+    hipStream_t s = p->stream;
+    if (p->mode != MQH_OP_MATFREE_FP32 || nz < 2) {
+        for (int k = 0; k < nz; ++k) {
+            int rc = op_product(p, trans, X + k * xstr, shift + k * sstr, 0.0, Zs ? Zs + k * zstr : nullptr,
+                                Y + k * p->ldn, st ? st + k : nullptr, timed);
+            if (rc) return rc;
+        }
+        return MQH_OK;
+    }
+    launch_gather_block(X, xstr, nz, p->perm, p->n, st, w.Vg, s);
+    LAUNCHCHK("block gather");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        for (int q = 0; q < 2; ++q) {
+            hipEvent_t ev;
+            HIPCHK(hipEventCreate(&ev));
+            p->pev.push_back(ev);
+        }
+        e0 = p->pev[p->pev.size() - 2];
+        e1 = p->pev[p->pev.size() - 1];
+        HIPCHK(hipEventRecord(e0, s));
+    }
+    const int S = trans ? w.S_cols : w.S_rows;
+    launch_mfm_block(trans, p->XS, p->frames, w.Vg, p->n, p->n_int, S, trans ? w.slice_cols : w.slice_rows, p->ec,
+                     w.PB, p->ldn, s);
+    LAUNCHCHK("block product");
+    if (timed) HIPCHK(hipEventRecord(e1, s));
+    launch_reduce_block(w.PB, p->ldn, S, p->n, nz, p->perm, shift, sstr, Zs, zstr, Y, p->ldn, st, s);
+    LAUNCHCHK("block reduction");
+    return MQH_OK;
+}
+
+// Runs k < nz start from w.X + k ldn (beta_1 w_1 = f).
+int run_gkb_multi(mqh_problem* p, int nz, int32_t ell, int32_t reorth, bool timed) {
+    MultiWs& w = p->mw;
+    hipStream_t s = p->stream;
+    const int64_t n = p->n, ldn = p->ldn;
+    const int nbq = sumsq_blocks(n);
+    const int nbu = update_blocks(n);
+    launch_init_state_b(w.st, ell, w.alpha, w.beta, nz, Bz{w.vstr, w.vstr}, s);
+    LAUNCHCHK("init state");
+    launch_sumsq_partial_b(w.X, n, w.npart, nbq, w.st, nz, Bz{ldn, w.nstr}, s);
+    launch_norm_finalize_b(w.npart, nbq, 0, 0, n, w.alpha, w.beta, w.st, nz, Bz{w.nstr, w.vstr, w.vstr}, s);
+    launch_scale_b(w.X, n, w.beta, w.W, w.st, nz, Bz{ldn, w.vstr, w.bstr}, s);
+    LAUNCHCHK("initial normalisation");
+    auto orthonormalize = [&](const double* V, int32_t m, int kind, int32_t j, double* dst) -> int {
+        int nparts;
+        if (reorth && m > 0) {
+            const Bz ub{w.bstr, w.vstr, ldn, w.nstr};
+            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.cvec, w.st, nz, w.bstr, ldn, w.gstr, w.vstr, s);
+            launch_update_b(V, ldn, n, m, w.cvec, w.Y, nullptr, w.st, nz, ub, s);
+            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.cvec, w.st, nz, w.bstr, ldn, w.gstr, w.vstr, s);
+            launch_update_b(V, ldn, n, m, w.cvec, w.Y, w.npart, w.st, nz, ub, s);
+            nparts = nbu;
+        } else {
+            launch_sumsq_partial_b(w.Y, n, w.npart, nbq, w.st, nz, Bz{ldn, w.nstr}, s);
+            nparts = nbq;
+        }
+        launch_norm_finalize_b(w.npart, nparts, kind, j, n, w.alpha, w.beta, w.st, nz, Bz{w.nstr, w.vstr, w.vstr},
+                               s);
+        const double* div = kind == 1 ? w.alpha + j : w.beta + j + 1;
+        launch_scale_b(w.Y, n, div, dst, w.st, nz, Bz{ldn, w.vstr, w.bstr}, s);
+        LAUNCHCHK("reorthogonalisation / normalisation");
+        return MQH_OK;
+    };
+    int rc;
+    for (int32_t j = 0; j < ell; ++j) {
+        double* Wj = w.W + (int64_t)j * ldn;
+        double* Zj = w.Z + (int64_t)j * ldn;
+        // r = A^T w_j - beta_j z_{j-1}
+        if ((rc = block_product(p, nz, 1, Wj, w.bstr, w.beta + j, w.vstr,
+                                j > 0 ? w.Z + (int64_t)(j - 1) * ldn : nullptr, w.bstr, w.Y, w.st, timed)))
+            return rc;
+        if ((rc = orthonormalize(w.Z, j, 1, j, Zj))) return rc;
+        // p = A z_j - alpha_j w_j
+        if ((rc = block_product(p, nz, 0, Zj, w.bstr, w.alpha + j, w.vstr, Wj, w.bstr, w.Y, w.st, timed)))
+            return rc;
+        if ((rc = orthonormalize(w.W, j + 1, 2, j, w.W + (int64_t)(j + 1) * ldn))) return rc;
+    }
+    return MQH_OK;
+}
+
+// Stage right-hand sides k0 .. k0 + nz - 1 (columns of F, leading dimension
+// ldf) into w.X.
+int stage_multi(mqh_problem* p, const double* F, int64_t ldf, int k0, int nz, uint32_t flags) {
+    MultiWs& w = p->mw;
+    const int64_t n = p->n;
+    if (!(flags & MQH_FLAG_DEVICE_PTRS))
+        for (int k = 0; k < nz; ++k)
+            if (!all_finite(F + (int64_t)(k0 + k) * ldf, n)) return fail(MQH_EINVAL, "non-finite right-hand side");
+    HIPCHK(hipMemcpy2DAsync(w.X, (size_t)p->ldn * sizeof(double), F + (int64_t)k0 * ldf, (size_t)ldf * sizeof(double),
+                            (size_t)n * sizeof(double), (size_t)nz, kind_in(flags), p->stream));
+    return MQH_OK;
+}
+
 int stage_in(double* dst, const double* src, int64_t count, uint32_t flags, hipStream_t s) {
     if (count <= 0) return MQH_OK;
     if (!(flags & MQH_FLAG_DEVICE_PTRS) && !all_finite(src, count)) return fail(MQH_EINVAL, "non-finite input");
@@ -431,6 +667,27 @@ int stage_in(double* dst, const double* src, int64_t count, uint32_t flags, hipS
 
 int check_problem(const mqh_problem* p) {
     if (p == nullptr) return fail(MQH_EINVAL, "NULL problem");
+    return MQH_OK;
+}
+
+int check_opts(const mqh_problem* p, const mqh_solve_opts* opts) {
+    const int32_t ell = opts->ell;
+    if (ell < 1 || ell > p->n || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= min(n, MQH_MAX_ELL)");
+    if (opts->reorth != 0 && opts->reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
+    if (opts->method != MQH_METHOD_INE_TSVD && opts->method != MQH_METHOD_HKT && opts->method != MQH_METHOD_LSQR)
+        return fail(MQH_EINVAL, "method");
+    if (opts->rule < MQH_RULE_GCV || opts->rule > MQH_RULE_WGCV) return fail(MQH_EINVAL, "rule");
+    if (opts->method == MQH_METHOD_LSQR && opts->rule == MQH_RULE_WGCV)
+        return fail(MQH_EINVAL, "the weighted GCV rule applies to HKT and Ine-TSVD");
+    if (opts->rule == MQH_RULE_WGCV && !(opts->gcv_weight > 0.0 && opts->gcv_weight <= 1.0))
+        return fail(MQH_EINVAL, "gcv_weight must be in (0, 1]");
+    const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
+    if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
+    if (opts->method == MQH_METHOD_HKT && opts->rule == MQH_RULE_FIXED &&
+        (!isfinite(opts->lambda_fixed) || opts->lambda_fixed < 0.0))
+        return fail(MQH_EINVAL, "lambda_fixed must be finite and >= 0");
+    if (opts->method != MQH_METHOD_HKT && opts->rule == MQH_RULE_FIXED && (opts->k_trunc < 1 || opts->k_trunc > ell))
+        return fail(MQH_EINVAL, "k_trunc must be in [1, ell]");
     return MQH_OK;
 }
 
@@ -496,6 +753,7 @@ int mqh_problem_destroy(mqh_problem* p) {
     dfree(p->E);
     dfree(p->EP);
     dfree(p->u);
+    multi_free(p->mw);
     if (p->hres) (void)hipHostFree(p->hres);
     for (auto& e : p->ev)
         if (e) (void)hipEventDestroy(e);
@@ -720,23 +978,9 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
     if (opts == nullptr) return fail(MQH_EINVAL, "NULL opts");
     if (coef == nullptr) return fail(MQH_EINVAL, "NULL coef");
     if ((p->n_int > 0 && f_int == nullptr) || (p->n_bnd > 0 && g_bnd == nullptr)) return fail(MQH_EINVAL, "NULL data");
+    if ((rc = check_opts(p, opts))) return rc;
     const int32_t ell = opts->ell;
-    if (ell < 1 || ell > p->n || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= min(n, MQH_MAX_ELL)");
-    if (opts->reorth != 0 && opts->reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
-    if (opts->method != MQH_METHOD_INE_TSVD && opts->method != MQH_METHOD_HKT && opts->method != MQH_METHOD_LSQR)
-        return fail(MQH_EINVAL, "method");
-    if (opts->rule < MQH_RULE_GCV || opts->rule > MQH_RULE_WGCV) return fail(MQH_EINVAL, "rule");
-    if (opts->method == MQH_METHOD_LSQR && opts->rule == MQH_RULE_WGCV)
-        return fail(MQH_EINVAL, "the weighted GCV rule applies to HKT and Ine-TSVD");
-    if (opts->rule == MQH_RULE_WGCV && !(opts->gcv_weight > 0.0 && opts->gcv_weight <= 1.0))
-        return fail(MQH_EINVAL, "gcv_weight must be in (0, 1]");
     const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
-    if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
-    if (opts->method == MQH_METHOD_HKT && opts->rule == MQH_RULE_FIXED &&
-        (!isfinite(opts->lambda_fixed) || opts->lambda_fixed < 0.0))
-        return fail(MQH_EINVAL, "lambda_fixed must be finite and >= 0");
-    if (opts->method != MQH_METHOD_HKT && opts->rule == MQH_RULE_FIXED && (opts->k_trunc < 1 || opts->k_trunc > ell))
-        return fail(MQH_EINVAL, "k_trunc must be in [1, ell]");
     const uint32_t flags = opts->flags;
     const bool timed = (flags & MQH_FLAG_TIME_PRODUCTS) != 0;
     HIPCHK(hipSetDevice(p->device));
@@ -816,6 +1060,225 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
     }
     if (st.flag != 0) return MQH_WBREAKDOWN;
     if (iflags & (MQH_INFO_GCV_AT_EDGE | MQH_INFO_LCURVE_AT_EDGE)) return MQH_WEDGE;
+    return MQH_OK;
+}
+
+int mqh_apply_multi(mqh_problem* p, int32_t trans, const double* X, int64_t ldx, int32_t nrhs, const double* shifts,
+                    const double* Zs, int64_t ldz, double* Y, int64_t ldy, uint32_t flags) {
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (X == nullptr || Y == nullptr) return fail(MQH_EINVAL, "NULL X or Y");
+    if (trans != 0 && trans != 1) return fail(MQH_EINVAL, "trans must be 0 or 1");
+    if (nrhs < 1) return fail(MQH_EINVAL, "need nrhs >= 1");
+    if (ldx < p->n || ldy < p->n || (Zs != nullptr && ldz < p->n))
+        return fail(MQH_EINVAL, "need leading dimensions >= n");
+    if (shifts != nullptr)
+        for (int32_t k = 0; k < nrhs; ++k)
+            if (!isfinite(shifts[k])) return fail(MQH_EINVAL, "non-finite shift");
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t s = p->stream;
+    for (int k0 = 0; k0 < nrhs; k0 += kBlkRhs) {
+        const int nz = nrhs - k0 < kBlkRhs ? nrhs - k0 : kBlkRhs;
+        if ((rc = ensure_multi(p, nz, 1))) return rc;
+        MultiWs& w = p->mw;
+        if ((rc = stage_multi(p, X, ldx, k0, nz, flags))) return rc;
+        const double* zs = nullptr;
+        if (Zs != nullptr) {
+            if (!(flags & MQH_FLAG_DEVICE_PTRS))
+                for (int k = 0; k < nz; ++k)
+                    if (!all_finite(Zs + (int64_t)(k0 + k) * ldz, p->n)) return fail(MQH_EINVAL, "non-finite z");
+            HIPCHK(hipMemcpy2DAsync(w.Z, (size_t)w.bstr * sizeof(double), Zs + (int64_t)k0 * ldz,
+                                    (size_t)ldz * sizeof(double), (size_t)p->n * sizeof(double), (size_t)nz,
+                                    kind_in(flags), s));
+            zs = w.Z;
+        }
+        // the shifts go in column 0 of the run's alpha
+        std::vector<double> sh((size_t)nz * (size_t)w.vstr, 0.0);
+        if (shifts != nullptr)
+            for (int k = 0; k < nz; ++k) sh[(size_t)k * (size_t)w.vstr] = shifts[k0 + k];
+        HIPCHK(hipMemcpyAsync(w.alpha, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        if ((rc = block_product(p, nz, trans, w.X, p->ldn, w.alpha, w.vstr, zs, w.bstr, w.Y, nullptr, false)))
+            return rc;
+        HIPCHK(hipMemcpy2DAsync(Y + (int64_t)k0 * ldy, (size_t)ldy * sizeof(double), w.Y,
+                                (size_t)p->ldn * sizeof(double), (size_t)p->n * sizeof(double), (size_t)nz,
+                                kind_out(flags), s));
+        HIPCHK(hipStreamSynchronize(s));  // sh lives until the copy has run
+    }
+    return MQH_OK;
+}
+
+int mqh_gkb_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, int32_t ell, int32_t reorth, double* W,
+                  double* Z, double* alpha, double* beta, int32_t* ell_done, uint32_t flags) {
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (F == nullptr) return fail(MQH_EINVAL, "NULL F");
+    if (nrhs < 1) return fail(MQH_EINVAL, "need nrhs >= 1");
+    if (ldf < p->n) return fail(MQH_EINVAL, "need ldf >= n");
+    if (ell < 1 || ell > p->n || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= min(n, MQH_MAX_ELL)");
+    if (reorth != 0 && reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t s = p->stream;
+    const int64_t n = p->n;
+    const hipMemcpyKind ko = kind_out(flags);
+    const bool dev = (flags & MQH_FLAG_DEVICE_PTRS) != 0;
+    bool broke = false;
+    for (int k0 = 0; k0 < nrhs; k0 += kBlkRhs) {
+        const int nz = nrhs - k0 < kBlkRhs ? nrhs - k0 : kBlkRhs;
+        if ((rc = ensure_multi(p, nz, ell))) return rc;
+        MultiWs& w = p->mw;
+        if ((rc = stage_multi(p, F, ldf, k0, nz, flags))) return rc;
+        if ((rc = run_gkb_multi(p, nz, ell, reorth, false))) return rc;
+        std::vector<GkbState> st((size_t)nz);
+        std::vector<double> b1((size_t)nz);
+        HIPCHK(hipMemcpyAsync(st.data(), w.st, (size_t)nz * sizeof(GkbState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpy2DAsync(b1.data(), sizeof(double), w.beta, (size_t)w.vstr * sizeof(double), sizeof(double),
+                                (size_t)nz, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < nz; ++k)
+            if (!isfinite(b1[(size_t)k])) return fail(MQH_EINVAL, "non-finite right-hand side");
+        for (int k = 0; k < nz; ++k) {
+            const int64_t r = k0 + k;
+            const int32_t done = st[(size_t)k].ell_done;
+            broke = broke || done < ell || st[(size_t)k].flag != 0;
+            auto copy_cols = [&](double* dst, const double* src, int32_t total, int32_t valid) -> int {
+                if (dst == nullptr) return MQH_OK;
+                if (valid > 0)
+                    HIPCHK(hipMemcpy2DAsync(dst, (size_t)n * sizeof(double), src, (size_t)p->ldn * sizeof(double),
+                                            (size_t)n * sizeof(double), (size_t)valid, ko, s));
+                if (total > valid) {
+                    if (dev) {
+                        launch_fill(dst + (int64_t)valid * n, (int64_t)(total - valid) * n, 0.0, s);
+                        LAUNCHCHK("fill");
+                    } else {
+                        memset(dst + (int64_t)valid * n, 0, (size_t)(total - valid) * n * sizeof(double));
+                    }
+                }
+                return MQH_OK;
+            };
+            const int32_t wcols = st[(size_t)k].flag == 2 ? done : done + 1;
+            if ((rc = copy_cols(W ? W + r * (ell + 1) * n : nullptr, w.W + k * w.bstr, ell + 1, wcols))) return rc;
+            if ((rc = copy_cols(Z ? Z + r * ell * n : nullptr, w.Z + k * w.bstr, ell, done))) return rc;
+            if (alpha)
+                HIPCHK(hipMemcpyAsync(alpha + r * ell, w.alpha + k * w.vstr, (size_t)ell * sizeof(double), ko, s));
+            if (beta)
+                HIPCHK(hipMemcpyAsync(beta + r * (ell + 1), w.beta + k * w.vstr, (size_t)(ell + 1) * sizeof(double),
+                                      ko, s));
+            if (ell_done) ell_done[r] = done;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return broke ? MQH_WBREAKDOWN : MQH_OK;
+}
+
+int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, const mqh_solve_opts* opts,
+                    double* coef, int64_t ldc, mqh_solve_info* info) {
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (opts == nullptr) return fail(MQH_EINVAL, "NULL opts");
+    if (F == nullptr || coef == nullptr) return fail(MQH_EINVAL, "NULL F or coef");
+    if (nrhs < 1) return fail(MQH_EINVAL, "need nrhs >= 1");
+    if (ldf < p->n || ldc < p->n) return fail(MQH_EINVAL, "need ldf >= n and ldc >= n");
+    if (info)
+        for (int32_t k = 0; k < nrhs; ++k) clear_info(info + k);
+    if ((rc = check_opts(p, opts))) return rc;
+    const int32_t ell = opts->ell;
+    const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
+    const uint32_t flags = opts->flags;
+    const bool timed = (flags & MQH_FLAG_TIME_PRODUCTS) != 0;
+    const bool lsqr = opts->method == MQH_METHOD_LSQR;
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t s = p->stream;
+    const hipMemcpyKind ko = kind_out(flags);
+    bool broke = false, edge = false;
+    for (int k0 = 0; k0 < nrhs; k0 += kBlkRhs) {
+        const int nz = nrhs - k0 < kBlkRhs ? nrhs - k0 : kBlkRhs;
+        if ((rc = ensure_multi(p, nz, ell))) return rc;
+        MultiWs& w = p->mw;
+        for (auto& e : p->pev) (void)hipEventDestroy(e);
+        p->pev.clear();
+        if (timed) p->pev.reserve((size_t)ell * 4 * (size_t)nz);
+        HIPCHK(hipEventRecord(p->ev[0], s));
+        if ((rc = stage_multi(p, F, ldf, k0, nz, flags))) return rc;
+        HIPCHK(hipEventRecord(p->ev[1], s));
+        if ((rc = run_gkb_multi(p, nz, ell, opts->reorth, timed))) return rc;
+        HIPCHK(hipEventRecord(p->ev[2], s));
+        const int32_t* lp = &w.st->ell_done;
+        const ProjBatch pb{w.vstr, (int64_t)w.ell_cap * w.ell_cap, (int64_t)(sizeof(GkbState) / sizeof(int32_t)), 0};
+        launch_fill(w.sv, (int64_t)nz * w.vstr, 0.0, s);
+        if (!lsqr) {
+            launch_bidiag_svd(w.alpha, w.beta, ell, lp, w.Vw, ell, w.sv, w.ftil, w.V, ell, w.status, s, nz, pb);
+            LAUNCHCHK("projected SVD");
+        }
+        HIPCHK(hipEventRecord(p->ev[3], s));
+        if (lsqr) {
+            launch_lsqr(w.alpha, w.beta, ell, lp, p->n, opts->rule, opts->k_trunc, nullptr, nullptr, w.pout, w.y, ell,
+                        s, nz, pb);
+        } else {
+            launch_param_choice(w.sv, w.ftil, ell, lp, opts->method, opts->rule, J, opts->lambda_fixed, opts->k_trunc,
+                                opts->gcv_weight, nullptr, w.pout, s, nz, pb);
+            launch_proj_solution(w.sv, w.ftil, w.V, ell, ell, lp, opts->method, 0.0, 0, w.pout, w.y, ell, s, nz, pb);
+        }
+        LAUNCHCHK("parameter choice");
+        HIPCHK(hipEventRecord(p->ev[4], s));
+        launch_lift(w.Z, p->ldn, p->n, ell, lp, w.y, w.coef, s, nz,
+                    Bz{w.bstr, w.vstr, p->ldn, (int64_t)(sizeof(GkbState) / sizeof(int32_t))});
+        LAUNCHCHK("lift");
+        HIPCHK(hipEventRecord(p->ev[5], s));
+        std::vector<GkbState> st((size_t)nz);
+        std::vector<ParamOut> po((size_t)nz);
+        std::vector<int32_t> svs((size_t)nz, 0);
+        std::vector<double> b1((size_t)nz);
+        HIPCHK(hipMemcpyAsync(st.data(), w.st, (size_t)nz * sizeof(GkbState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(po.data(), w.pout, (size_t)nz * sizeof(ParamOut), hipMemcpyDeviceToHost, s));
+        if (!lsqr) HIPCHK(hipMemcpyAsync(svs.data(), w.status, (size_t)nz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpy2DAsync(b1.data(), sizeof(double), w.beta, (size_t)w.vstr * sizeof(double), sizeof(double),
+                                (size_t)nz, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int k = 0; k < nz; ++k) {
+            if (!isfinite(b1[(size_t)k])) return fail(MQH_EINVAL, "non-finite right-hand side");
+            if (svs[(size_t)k] != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+        }
+        HIPCHK(hipMemcpy2DAsync(coef + (int64_t)k0 * ldc, (size_t)ldc * sizeof(double), w.coef,
+                                (size_t)p->ldn * sizeof(double), (size_t)p->n * sizeof(double), (size_t)nz, ko, s));
+        HIPCHK(hipEventRecord(p->ev[6], s));
+        HIPCHK(hipStreamSynchronize(s));
+        float t_ms[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        {
+            float ms = 0.f;
+            const int pairs[6][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {0, 6}};
+            for (int q = 0; q < 6; ++q)
+                if (hipEventElapsedTime(&ms, p->ev[pairs[q][0]], p->ev[pairs[q][1]]) == hipSuccess) t_ms[q] = ms;
+            if (timed) {
+                // products alternate A^T (even pairs) and A (odd pairs) when
+                // they are block products; one per run otherwise
+                const size_t per = (p->mode == MQH_OP_MATFREE_FP32 && nz >= 2) ? 1 : (size_t)nz;
+                for (size_t q = 0; q + 1 < p->pev.size(); q += 2)
+                    if (hipEventElapsedTime(&ms, p->pev[q], p->pev[q + 1]) == hipSuccess)
+                        t_ms[((q / 2) / per) % 2 == 0 ? 6 : 7] += ms;
+            }
+        }
+        for (int k = 0; k < nz; ++k) {
+            const GkbState& g = st[(size_t)k];
+            const ParamOut& o = po[(size_t)k];
+            uint32_t iflags = o.flags;
+            if (g.flag != 0) iflags |= MQH_INFO_BREAKDOWN;
+            broke = broke || g.flag != 0;
+            edge = edge || (iflags & (MQH_INFO_GCV_AT_EDGE | MQH_INFO_LCURVE_AT_EDGE)) != 0;
+            if (info) {
+                mqh_solve_info* in = info + k0 + k;
+                in->ell_done = g.ell_done;
+                in->k_chosen = o.k;
+                in->lambda_chosen = o.lambda;
+                in->crit = o.crit;
+                in->resid_norm = o.rho;
+                in->sol_norm = o.eta;
+                in->flags = iflags;
+                for (int q = 0; q < 8; ++q) in->t_ms[q] = t_ms[q];
+            }
+        }
+    }
+    if (broke) return MQH_WBREAKDOWN;
+    if (edge) return MQH_WEDGE;
     return MQH_OK;
 }
 

@@ -22,6 +22,23 @@ struct GkbState {
     double scale;      // running max of alpha_j, beta_{j+1}: the operator scale
 };
 
+// Per-batch-slice strides of a kernel's pointer arguments (in elements):
+// slice z of a batched launch uses pointer + z * stride; which argument
+// takes which stride is stated at each kernel.  Zero strides with one slice
+// are the unbatched call.
+struct Bz {
+    int64_t a = 0, b = 0, c = 0, d = 0;
+};
+
+// Per-problem strides (in elements) of a batched launch of the projected-
+// problem kernels, one workgroup (row of workgroups) per problem z:
+// vec for alpha, beta, sv, ftil, y, rho, eta; mat for Vw and V; lstr for
+// the step-count pointer (int32 elements); curve for the criterion curve;
+// ParamOut and the status word advance by one per problem.
+struct ProjBatch {
+    int64_t vec = 0, mat = 0, lstr = 0, curve = 0;
+};
+
 // Native 2 x FP64 vector for 16-byte (non-temporal) loads and stores.
 typedef double v2d __attribute__((ext_vector_type(2)));
 

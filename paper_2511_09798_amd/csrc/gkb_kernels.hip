@@ -15,7 +15,11 @@ namespace mqh {
 // State and small fills
 // ---------------------------------------------------------------------------
 
-__global__ void k_init_state(GkbState* st, int32_t ell, double* alpha, double* beta) {
+__global__ void k_init_state(GkbState* st, int32_t ell, double* alpha, double* beta, Bz bz) {
+    const int64_t z = blockIdx.y;  // batch: state z, alpha + z bz.a, beta + z bz.b
+    st += z;
+    if (alpha != nullptr) alpha += z * bz.a;
+    if (beta != nullptr) beta += z * bz.b;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         st->stopped = 0;
@@ -45,8 +49,12 @@ __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
 // partial[b] = sum of x_i^2 over the grid-stride share of block b.
 __global__ __launch_bounds__(kBlock) void k_sumsq_partial(const double* __restrict__ x, int64_t n,
                                                           double* __restrict__ partial,
-                                                          const GkbState* __restrict__ st) {
+                                                          const GkbState* __restrict__ st, Bz bz) {
     __shared__ double lds[kBlock / kWave];
+    const int64_t z = blockIdx.z;  // batch: x + z bz.a, partial + z bz.b, state z
+    x += z * bz.a;
+    partial += z * bz.b;
+    if (st != nullptr) st += z;
     if (st != nullptr && st->stopped) return;  // uniform over the grid
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
@@ -60,8 +68,14 @@ __global__ __launch_bounds__(kBlock) void k_sumsq_partial(const double* __restri
 // The threshold is n * DBL_EPSILON * (running max of alpha, beta_{>=2}).
 __global__ __launch_bounds__(kBlock) void k_norm_finalize(const double* __restrict__ partial, int nparts, int kind,
                                                           int32_t j, int64_t n, double* __restrict__ alpha,
-                                                          double* __restrict__ beta, GkbState* __restrict__ st) {
+                                                          double* __restrict__ beta, GkbState* __restrict__ st,
+                                                          Bz bz) {
     __shared__ double lds[kBlock / kWave];
+    const int64_t z = blockIdx.x;  // batch: partial + z bz.a, alpha + z bz.b, beta + z bz.c, state z
+    partial += z * bz.a;
+    alpha += z * bz.b;
+    beta += z * bz.c;
+    st += z;
     if (st->stopped) return;
     double s = 0.0;
     for (int i = threadIdx.x; i < nparts; i += kBlock) s += partial[i];
@@ -102,7 +116,12 @@ __global__ __launch_bounds__(kBlock) void k_norm_finalize(const double* __restri
 // dst = x / *div  (normalisation of a Krylov vector).
 __global__ __launch_bounds__(kBlock) void k_scale(const double* __restrict__ x, int64_t n,
                                                   const double* __restrict__ div, double* __restrict__ dst,
-                                                  const GkbState* __restrict__ st) {
+                                                  const GkbState* __restrict__ st, Bz bz) {
+    const int64_t z = blockIdx.z;  // batch: x + z bz.a, div + z bz.b, dst + z bz.c, state z
+    x += z * bz.a;
+    div += z * bz.b;
+    dst += z * bz.c;
+    if (st != nullptr) st += z;
     if (st != nullptr && st->stopped) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) dst[i] = x[i] / *div;
@@ -123,8 +142,13 @@ constexpr int kGtCols = 8;
 __global__ __launch_bounds__(kBlock) void k_gemvt_partial(const double* __restrict__ V, int64_t ldn, int64_t n,
                                                           int32_t m, const double* __restrict__ x,
                                                           double* __restrict__ partial,
-                                                          const GkbState* __restrict__ st) {
+                                                          const GkbState* __restrict__ st, Bz bz) {
     __shared__ double lds[kBlock / kWave][kGtCols];
+    const int64_t z = blockIdx.z;  // batch: V + z bz.a, x + z bz.b, partial + z bz.c, state z
+    V += z * bz.a;
+    x += z * bz.b;
+    partial += z * bz.c;
+    if (st != nullptr) st += z;
     if (st != nullptr && st->stopped) return;
     constexpr int Q = kGtRows / kBlock;
     const int64_t r0 = (int64_t)blockIdx.x * kGtRows + threadIdx.x;
@@ -165,7 +189,11 @@ __global__ __launch_bounds__(kBlock) void k_gemvt_partial(const double* __restri
 // lane + 64, ... and the wave reduction combines them in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restrict__ partial, int nb, int32_t m,
                                                          double* __restrict__ c,
-                                                         const GkbState* __restrict__ st) {
+                                                         const GkbState* __restrict__ st, Bz bz) {
+    const int64_t z = blockIdx.y;  // batch: partial + z bz.a, c + z bz.b, state z
+    partial += z * bz.a;
+    c += z * bz.b;
+    if (st != nullptr) st += z;
     if (st != nullptr && st->stopped) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int k = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
@@ -180,8 +208,14 @@ __global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restric
 __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V, int64_t ldn, int64_t n, int32_t m,
                                                    const double* __restrict__ c, double* __restrict__ x,
                                                    double* __restrict__ sumsq_partial,
-                                                   const GkbState* __restrict__ st) {
+                                                   const GkbState* __restrict__ st, Bz bz) {
     __shared__ double lds[kBlock / kWave];
+    const int64_t z = blockIdx.z;  // batch: V + z bz.a, c + z bz.b, x + z bz.c, partial + z bz.d, state z
+    V += z * bz.a;
+    c += z * bz.b;
+    x += z * bz.c;
+    if (sumsq_partial != nullptr) sumsq_partial += z * bz.d;
+    if (st != nullptr) st += z;
     if (st != nullptr && st->stopped) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double xi = 0.0;
@@ -210,7 +244,14 @@ __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V,
 
 __global__ __launch_bounds__(kBlock) void k_lift(const double* __restrict__ Z, int64_t ldz, int64_t n,
                                                  int32_t ell, const int32_t* __restrict__ ell_ptr,
-                                                 const double* __restrict__ y, double* __restrict__ coef) {
+                                                 const double* __restrict__ y, double* __restrict__ coef, Bz bz) {
+    {
+        const int64_t z = blockIdx.y;  // batch: Z + z bz.a, y + z bz.b, coef + z bz.c, ell_ptr + z bz.d
+        Z += z * bz.a;
+        y += z * bz.b;
+        coef += z * bz.c;
+        if (ell_ptr != nullptr) ell_ptr += z * bz.d;
+    }
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int32_t m = ell_ptr != nullptr ? *ell_ptr : ell;
@@ -229,8 +270,12 @@ __global__ __launch_bounds__(kBlock) void k_lift(const double* __restrict__ Z, i
 // ---------------------------------------------------------------------------
 
 void launch_init_state(GkbState* st, int32_t ell, double* alpha, double* beta, hipStream_t s) {
+    launch_init_state_b(st, ell, alpha, beta, 1, Bz{}, s);
+}
+
+void launch_init_state_b(GkbState* st, int32_t ell, double* alpha, double* beta, int nz, Bz bz, hipStream_t s) {
     const int nt = 256;
-    k_init_state<<<(ell + 1 + nt) / nt, nt, 0, s>>>(st, ell, alpha, beta);
+    k_init_state<<<dim3((ell + 1 + nt) / nt, nz), nt, 0, s>>>(st, ell, alpha, beta, bz);
 }
 
 void launch_cap_ell(GkbState* st, int32_t ell, hipStream_t s) { k_cap_ell<<<1, 64, 0, s>>>(st, ell); }
@@ -246,37 +291,65 @@ int sumsq_blocks(int64_t n) {
 }
 
 void launch_sumsq_partial(const double* x, int64_t n, double* partial, int nb, const GkbState* st, hipStream_t s) {
-    k_sumsq_partial<<<nb, kBlock, 0, s>>>(x, n, partial, st);
+    launch_sumsq_partial_b(x, n, partial, nb, st, 1, Bz{}, s);
+}
+
+void launch_sumsq_partial_b(const double* x, int64_t n, double* partial, int nb, const GkbState* st, int nz, Bz bz,
+                            hipStream_t s) {
+    k_sumsq_partial<<<dim3(nb, 1, nz), kBlock, 0, s>>>(x, n, partial, st, bz);
 }
 
 void launch_norm_finalize(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
                           double* beta, GkbState* st, hipStream_t s) {
-    k_norm_finalize<<<1, kBlock, 0, s>>>(partial, nparts, kind, j, n, alpha, beta, st);
+    launch_norm_finalize_b(partial, nparts, kind, j, n, alpha, beta, st, 1, Bz{}, s);
+}
+
+void launch_norm_finalize_b(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
+                            double* beta, GkbState* st, int nz, Bz bz, hipStream_t s) {
+    k_norm_finalize<<<nz, kBlock, 0, s>>>(partial, nparts, kind, j, n, alpha, beta, st, bz);
 }
 
 void launch_scale(const double* x, int64_t n, const double* div, double* dst, const GkbState* st, hipStream_t s) {
-    k_scale<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, div, dst, st);
+    launch_scale_b(x, n, div, dst, st, 1, Bz{}, s);
+}
+
+void launch_scale_b(const double* x, int64_t n, const double* div, double* dst, const GkbState* st, int nz, Bz bz,
+                    hipStream_t s) {
+    k_scale<<<dim3((unsigned)((n + kBlock - 1) / kBlock), 1, nz), kBlock, 0, s>>>(x, n, div, dst, st, bz);
 }
 
 int gemvt_blocks(int64_t n) { return (int)((n + kGtRows - 1) / kGtRows); }
 
 void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
                   const GkbState* st, hipStream_t s) {
+    launch_gemvt_b(V, ldn, n, m, x, partial, c, st, 1, 0, 0, 0, 0, s);
+}
+
+void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
+                    const GkbState* st, int nz, int64_t sV, int64_t sx, int64_t sp, int64_t sc, hipStream_t s) {
     const int nb = gemvt_blocks(n);
-    k_gemvt_partial<<<dim3(nb, (m + kGtCols - 1) / kGtCols), kBlock, 0, s>>>(V, ldn, n, m, x, partial, st);
-    k_gemvt_reduce<<<(m + kBlock / kWave - 1) / (kBlock / kWave), kBlock, 0, s>>>(partial, nb, m, c, st);
+    k_gemvt_partial<<<dim3(nb, (m + kGtCols - 1) / kGtCols, nz), kBlock, 0, s>>>(V, ldn, n, m, x, partial, st,
+                                                                                 Bz{sV, sx, sp, 0});
+    k_gemvt_reduce<<<dim3((m + kBlock / kWave - 1) / (kBlock / kWave), nz), kBlock, 0, s>>>(partial, nb, m, c, st,
+                                                                                           Bz{sp, sc, 0, 0});
 }
 
 void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
                    double* sumsq_partial, const GkbState* st, hipStream_t s) {
-    k_update<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(V, ldn, n, m, c, x, sumsq_partial, st);
+    launch_update_b(V, ldn, n, m, c, x, sumsq_partial, st, 1, Bz{}, s);
+}
+
+void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
+                     double* sumsq_partial, const GkbState* st, int nz, Bz bz, hipStream_t s) {
+    k_update<<<dim3((unsigned)((n + kBlock - 1) / kBlock), 1, nz), kBlock, 0, s>>>(V, ldn, n, m, c, x, sumsq_partial,
+                                                                                 st, bz);
 }
 
 int update_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 void launch_lift(const double* Z, int64_t ldz, int64_t n, int32_t ell, const int32_t* ell_ptr, const double* y,
-                 double* coef, hipStream_t s) {
-    k_lift<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(Z, ldz, n, ell, ell_ptr, y, coef);
+                 double* coef, hipStream_t s, int nz, Bz bz) {
+    k_lift<<<dim3((unsigned)((n + kBlock - 1) / kBlock), nz), kBlock, 0, s>>>(Z, ldz, n, ell, ell_ptr, y, coef, bz);
 }
 
 }  // namespace mqh

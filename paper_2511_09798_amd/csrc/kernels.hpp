@@ -11,6 +11,8 @@ constexpr int kMaxEll = 1024;   // largest projected problem (Golub-Kahan steps)
 constexpr int kMaxGrid = 4096;  // largest lambda grid
 constexpr int kMfmFt = 2;       // 16-node fixed tiles per wave in the FP32-evaluated products
 constexpr int kMfmFixed = (kBlock / kWave) * kMfmFt * 16;  // fixed nodes per block (128)
+constexpr int kMfmChunk = kBlock;  // loop nodes staged in LDS per round (one per thread)
+constexpr int kBlkRhs = 16;        // right-hand sides of a block product (lockstep Golub-Kahan runs)
 
 // Learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs.
 constexpr int kMlpIn = 24;
@@ -42,6 +44,13 @@ void launch_gather_coef(const double* x, const int32_t* perm, int64_t n, const E
 void launch_mfm_product(int trans, const float4* XS, const float4* frames, const float4* CF, int64_t n,
                         int64_t n_int, int S, int64_t slice_len, double* P, int64_t ldp, const GkbState* st,
                         hipStream_t s);
+void launch_mfm_block(int trans, const float4* XS, const float4* frames, const float* Vg, int64_t n, int64_t n_int,
+                      int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp, hipStream_t s);
+void launch_gather_block(const double* X, int64_t ldx, int nrhs, const int32_t* perm, int64_t n,
+                         const GkbState* st, float* Vg, hipStream_t s);
+void launch_reduce_block(const double* P, int64_t ldp, int S, int64_t n, int nrhs, const int32_t* perm,
+                         const double* shift, int64_t sstride, const double* z, int64_t ldz, double* y, int64_t ldy,
+                         const GkbState* st, hipStream_t s);
 void launch_reduce_slices(const double* P, int64_t ldp, int S, int64_t n, const int32_t* perm,
                           const double* shift_ptr, double shift_val, const double* z, double* y,
                           const GkbState* st, hipStream_t s);
@@ -83,19 +92,31 @@ int update_blocks(int64_t n);
 void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
                    double* sumsq_partial, const GkbState* st, hipStream_t s);
 void launch_lift(const double* Z, int64_t ldz, int64_t n, int32_t ell, const int32_t* ell_ptr, const double* y,
-                 double* coef, hipStream_t s);
+                 double* coef, hipStream_t s, int nz = 1, Bz bz = Bz{});
+// batched forms: nz slices, strides per slice as stated at the kernels
+void launch_init_state_b(GkbState* st, int32_t ell, double* alpha, double* beta, int nz, Bz bz, hipStream_t s);
+void launch_sumsq_partial_b(const double* x, int64_t n, double* partial, int nb, const GkbState* st, int nz, Bz bz,
+                            hipStream_t s);
+void launch_norm_finalize_b(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
+                            double* beta, GkbState* st, int nz, Bz bz, hipStream_t s);
+void launch_scale_b(const double* x, int64_t n, const double* div, double* dst, const GkbState* st, int nz, Bz bz,
+                    hipStream_t s);
+void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
+                    const GkbState* st, int nz, int64_t sV, int64_t sx, int64_t sp, int64_t sc, hipStream_t s);
+void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
+                     double* sumsq_partial, const GkbState* st, int nz, Bz bz, hipStream_t s);
 
 // projected problem (proj_kernels.hip)
 void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* Vw,
                        int64_t ldw, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
-                       hipStream_t s);
+                       hipStream_t s, int nz = 1, ProjBatch pb = ProjBatch{});
 void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,
                          int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double omega, double* curve,
-                         ParamOut* out, hipStream_t s);
+                         ParamOut* out, hipStream_t s, int nz = 1, ProjBatch pb = ProjBatch{});
 void launch_lsqr(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, int64_t n, int32_t rule,
-                 int32_t k_fixed, double* rho, double* eta, ParamOut* out, double* y, int32_t l_max, hipStream_t s);
+                 int32_t k_fixed, double* rho, double* eta, ParamOut* out, double* y, int32_t l_max, hipStream_t s, int nz = 1, ProjBatch pb = ProjBatch{});
 void launch_proj_solution(const double* sv, const double* ft, const double* V, int64_t ldv, int32_t l,
                           const int32_t* l_ptr, int32_t method, double lambda, int32_t k, const ParamOut* po,
-                          double* y, int32_t l_max, hipStream_t s);
+                          double* y, int32_t l_max, hipStream_t s, int nz = 1, ProjBatch pb = ProjBatch{});
 
 }  // namespace mqh

@@ -149,7 +149,6 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmChunk = kBlock;  // loop nodes staged in LDS per round (one per thread)
 
 // Exact split x = h + m + l of a finite FP32 value into three bf16 values,
 // returned as FP32 bit patterns with zero low halves: h keeps the top 16 bits
@@ -380,6 +379,218 @@ __global__ __launch_bounds__(kBlock) void k_gather_coef(const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Block products for kBlkRhs right-hand sides at once (lockstep Golub-Kahan
+// runs sharing each pass over A): P[slice][k][q] = sum over the slice's loop
+// nodes j of A(q, j) V[j][k] (rows) or A(j, q) V[j][k] (columns), V the
+// kBlkRhs vectors in FP32, sorted node order.
+//
+// Per 16 x 16 tile the squared distances come from the same bf16x3 MFMA as
+// in k_mfm with the operands swapped (A = loop nodes, B = fixed nodes), so a
+// lane holds t for 4 loop nodes j = 4g + r and one fixed node; the lane
+// evaluates the (unweighted) entries and they enter, as they are, the A
+// operand of four v_mfma_f32_16x16x4_f32 against the staged right-hand sides
+// (K = the 4 loop nodes {r, 4 + r, 8 + r, 12 + r}): the contraction
+// E (16 fixed x 16 loop) V (16 loop x 16 rhs) on the matrix cores, FP32,
+// summed over the 256 loop nodes of a chunk, then added in FP64.  Each lane
+// ends with its own outputs (4 fixed nodes x 1 right-hand side).
+// ---------------------------------------------------------------------------
+
+constexpr int kBlkVs = kBlkRhs + 4;  // LDS row of the staged right-hand sides (padded against bank conflicts)
+
+template <bool INTERIOR>
+__device__ __forceinline__ void mfb_span(const float4* __restrict__ XS, const float* __restrict__ Vg, int64_t j0,
+                                         int64_t j1, const float4& fr, const EntryConst& c,
+                                         const v4u (&bf)[kMfmFt], const v4f (&Cf)[kMfmFt],
+                                         double (&acc)[kMfmFt][4], v4u* __restrict__ lds_a,
+                                         float* __restrict__ lds_v) {
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15;
+    const float k2 = c.k2f, e2x2 = c.e2x2f, e2 = c.e2f;
+    for (int64_t t0 = j0; t0 < j1; t0 += kMfmChunk) {
+        const int64_t j = t0 + threadIdx.x;
+        float dx = 0.f, dy = 0.f, dz = 0.f;
+        float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0, v2 = v0, v3 = v0;
+        if (j < j1) {
+            const float4 q = XS[j];
+            dx = q.x - fr.x;
+            dy = q.y - fr.y;
+            dz = q.z - fr.z;
+            const float4* vr = reinterpret_cast<const float4*>(Vg + j * kBlkRhs);
+            v0 = vr[0];
+            v1 = vr[1];
+            v2 = vr[2];
+            v3 = vr[3];
+        }
+        const v4u a0 = loop_terms(dx), a1 = loop_terms(dy), a2 = loop_terms(dz);
+        unsigned h, m, l;
+        split_bf16x3(fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 1.0f))), h, m, l);
+        v4u a3;
+        a3[0] = pack_bf16(h, m);
+        a3[1] = l >> 16;
+        a3[2] = 0u;
+        a3[3] = 0u;
+        __syncthreads();  // the previous chunk has been consumed
+        lds_a[threadIdx.x * 4 + 0] = a0;
+        lds_a[threadIdx.x * 4 + 1] = a1;
+        lds_a[threadIdx.x * 4 + 2] = a2;
+        lds_a[threadIdx.x * 4 + 3] = a3;
+        float4* vrow = reinterpret_cast<float4*>(lds_v + threadIdx.x * kBlkVs);
+        vrow[0] = v0;
+        vrow[1] = v1;
+        vrow[2] = v2;
+        vrow[3] = v3;
+        __syncthreads();
+        v4f d2[kMfmFt];
+#pragma unroll
+        for (int f = 0; f < kMfmFt; ++f) d2[f] = v4f{0.f, 0.f, 0.f, 0.f};
+        v4f t[kMfmFt];
+        {
+            const v8bf ak = __builtin_bit_cast(v8bf, lds_a[jj * 4 + g]);
+#pragma unroll
+            for (int f = 0; f < kMfmFt; ++f)
+                t[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ak, __builtin_bit_cast(v8bf, bf[f]), Cf[f], 0, 0, 0);
+        }
+#pragma unroll 2
+        for (int u = 0; u < kMfmChunk / 16; ++u) {
+            v4f tn[kMfmFt];
+            if (u + 1 < kMfmChunk / 16) {
+                const v8bf an = __builtin_bit_cast(v8bf, lds_a[((u + 1) * 16 + jj) * 4 + g]);
+#pragma unroll
+                for (int f = 0; f < kMfmFt; ++f)
+                    tn[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(an, __builtin_bit_cast(v8bf, bf[f]), Cf[f], 0, 0, 0);
+            }
+            float vb[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) vb[r] = lds_v[(u * 16 + 4 * g + r) * kBlkVs + jj];
+#pragma unroll
+            for (int f = 0; f < kMfmFt; ++f) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float e;
+                    if (INTERIOR) {
+                        const float sv = __builtin_amdgcn_rsqf(t[f][r]);
+                        e = fmaf(e2, sv * sv, fmaf(k2, t[f][r], e2x2)) * sv;
+                    } else {
+                        e = __builtin_amdgcn_sqrtf(t[f][r]);
+                    }
+                    d2[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, vb[r], d2[f], 0, 0, 0);
+                }
+            }
+            if (u + 1 < kMfmChunk / 16) {
+#pragma unroll
+                for (int f = 0; f < kMfmFt; ++f) t[f] = tn[f];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < kMfmFt; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[f][r] += (double)d2[f][r];
+    }
+}
+
+template <bool ROWS>
+__global__ __launch_bounds__(kBlock) void k_mfm_block(const float4* __restrict__ XS, const float* __restrict__ Vg,
+                                                      int64_t n, int64_t n_int, int64_t nb_int, int64_t slice_len,
+                                                      const float4* __restrict__ frames, EntryConst c,
+                                                      double* __restrict__ P, int64_t ldp) {
+    __shared__ v4u lds_a[4 * kMfmChunk];
+    __shared__ float lds_v[kMfmChunk * kBlkVs];
+    const int64_t b = blockIdx.x;
+    const bool fint = b < nb_int;
+    const int64_t fb0 = fint ? b * kMfmFixed : n_int + (b - nb_int) * kMfmFixed;
+    const int64_t fend = fint ? n_int : n;
+    const int64_t fb1 = fb0 + kMfmFixed < fend ? fb0 + kMfmFixed : fend;
+    const float4 fr = frames[b];
+    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15, wv = threadIdx.x / kWave;
+    v4u bf[kMfmFt];
+    v4f Cf[kMfmFt];
+    double acc[kMfmFt][4];
+#pragma unroll
+    for (int f = 0; f < kMfmFt; ++f) {
+        const int64_t i = fb0 + (int64_t)(wv * kMfmFt + f) * 16 + jj;
+        float d[3] = {0.f, 0.f, 0.f};
+        if (i < fb1) {
+            const float4 q = XS[i];
+            d[0] = q.x - fr.x;
+            d[1] = q.y - fr.y;
+            d[2] = q.z - fr.z;
+        }
+        if (g < 3) {
+            bf[f] = fixed_terms(-2.0f * d[g]);
+        } else {
+            const unsigned one = 0x3F80u;  // bf16 1.0
+            bf[f][0] = one | (one << 16);
+            bf[f][1] = one;
+            bf[f][2] = 0u;
+            bf[f][3] = 0u;
+        }
+        const float d2 = fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
+        Cf[f] = v4f{d2, d2, d2, d2};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[f][r] = 0.0;
+    }
+    const int64_t j0 = (int64_t)blockIdx.y * slice_len;
+    const int64_t j1 = j0 + slice_len < n ? j0 + slice_len : n;
+    if (ROWS) {
+        if (fint)
+            mfb_span<true>(XS, Vg, j0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
+        else
+            mfb_span<false>(XS, Vg, j0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
+    } else {
+        const int64_t m1 = j1 < n_int ? j1 : n_int;
+        if (j0 < m1) mfb_span<true>(XS, Vg, j0, m1, fr, c, bf, Cf, acc, lds_a, lds_v);
+        const int64_t m0 = j0 > n_int ? j0 : n_int;
+        if (m0 < j1) mfb_span<false>(XS, Vg, m0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
+    }
+#pragma unroll
+    for (int f = 0; f < kMfmFt; ++f) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = fb0 + (int64_t)(wv * kMfmFt + f) * 16 + 4 * g + r;
+            if (i < fb1) P[((int64_t)blockIdx.y * kBlkRhs + jj) * ldp + i] = acc[f][r];
+        }
+    }
+}
+
+// Vg[q][k] = x_k[perm[q]] in FP32 for k < s (zero for s <= k < kBlkRhs and
+// for stopped runs); x_k = X + k * ldx.
+__global__ __launch_bounds__(kBlock) void k_gather_block(const double* __restrict__ X, int64_t ldx, int s,
+                                                         const int32_t* __restrict__ perm, int64_t n,
+                                                         const GkbState* __restrict__ st, float* __restrict__ Vg) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n * kBlkRhs) return;
+    const int64_t q = e / kBlkRhs;
+    const int k = (int)(e % kBlkRhs);
+    const bool live = k < s && (st == nullptr || !st[k].stopped);
+    Vg[e] = live ? (float)X[k * ldx + perm[q]] : 0.f;
+}
+
+// y_k[perm[i]] = sum_slices P[slice][k][i] - shift_k z_k[perm[i]] for right-hand
+// side k = blockIdx.y (shift_k = shift[k * sstride], z_k = z + k * ldz,
+// y_k = y + k * ldy); skipped when state k has stopped.
+__global__ __launch_bounds__(kBlock) void k_reduce_block(const double* __restrict__ P, int64_t ldp, int S, int64_t n,
+                                                         const int32_t* __restrict__ perm,
+                                                         const double* __restrict__ shift, int64_t sstride,
+                                                         const double* __restrict__ z, int64_t ldz,
+                                                         double* __restrict__ y, int64_t ldy,
+                                                         const GkbState* __restrict__ st) {
+    const int k = blockIdx.y;
+    if (st != nullptr && st[k].stopped) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double a0 = 0.0, a1 = 0.0;
+    int sl = 0;
+    for (; sl + 1 < S; sl += 2) {
+        a0 += P[((int64_t)sl * kBlkRhs + k) * ldp + i];
+        a1 += P[((int64_t)(sl + 1) * kBlkRhs + k) * ldp + i];
+    }
+    if (sl < S) a0 += P[((int64_t)sl * kBlkRhs + k) * ldp + i];
+    double v = a0 + a1;
+    const int64_t o = perm[i];
+    if (z != nullptr) v -= shift[k * sstride] * z[k * ldz + o];
+    y[k * ldy + o] = v;
+}
+
+// ---------------------------------------------------------------------------
 // Stored FP64 operator
 // ---------------------------------------------------------------------------
 
@@ -553,6 +764,28 @@ void launch_mfm_product(int trans, const float4* XS, const float4* frames, const
         k_mfm<false><<<grid, kBlock, 0, s>>>(XS, CF, n, n_int, nb_int, slice_len, frames, P, ldp, st);
     else
         k_mfm<true><<<grid, kBlock, 0, s>>>(XS, CF, n, n_int, nb_int, slice_len, frames, P, ldp, st);
+}
+
+void launch_mfm_block(int trans, const float4* XS, const float4* frames, const float* Vg, int64_t n, int64_t n_int,
+                      int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp, hipStream_t s) {
+    const int64_t nb_int = (n_int + kMfmFixed - 1) / kMfmFixed;
+    dim3 grid((unsigned)mfm_blocks(n, n_int), (unsigned)S);
+    if (trans)
+        k_mfm_block<false><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+    else
+        k_mfm_block<true><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+}
+
+void launch_gather_block(const double* X, int64_t ldx, int nrhs, const int32_t* perm, int64_t n,
+                         const GkbState* st, float* Vg, hipStream_t s) {
+    k_gather_block<<<(unsigned)((n * kBlkRhs + kBlock - 1) / kBlock), kBlock, 0, s>>>(X, ldx, nrhs, perm, n, st, Vg);
+}
+
+void launch_reduce_block(const double* P, int64_t ldp, int S, int64_t n, int nrhs, const int32_t* perm,
+                         const double* shift, int64_t sstride, const double* z, int64_t ldz, double* y, int64_t ldy,
+                         const GkbState* st, hipStream_t s) {
+    k_reduce_block<<<dim3((unsigned)((n + kBlock - 1) / kBlock), nrhs), kBlock, 0, s>>>(P, ldp, S, n, perm, shift,
+                                                                                       sstride, z, ldz, y, ldy, st);
 }
 
 void launch_reduce_slices(const double* P, int64_t ldp, int S, int64_t n, const int32_t* perm,

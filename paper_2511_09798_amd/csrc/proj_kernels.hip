@@ -29,7 +29,18 @@ __global__ __launch_bounds__(kSvdThreads) void k_bidiag_svd(const double* __rest
                                                             double* __restrict__ Vw, int64_t ldw,
                                                             double* __restrict__ sv, double* __restrict__ ftil,
                                                             double* __restrict__ V, int64_t ldv,
-                                                            int32_t* __restrict__ status) {
+                                                            int32_t* __restrict__ status, ProjBatch pb) {
+    {
+        const int64_t z = blockIdx.x;  // batch: problem z
+        alpha += z * pb.vec;
+        beta += z * pb.vec;
+        if (l_ptr != nullptr) l_ptr += z * pb.lstr;
+        Vw += z * pb.mat;
+        sv += z * pb.vec;
+        ftil += z * pb.vec;
+        V += z * pb.mat;
+        if (status != nullptr) status += z;
+    }
     __shared__ double d[kMaxEll], e[kMaxEll], g[kMaxEll];
     __shared__ double rc[2][kMaxEll], rs[2][kMaxEll];
     __shared__ int rank[kMaxEll];
@@ -174,7 +185,15 @@ __global__ __launch_bounds__(kProjThreads) void k_param_choice(const double* __r
                                                                int32_t rule, int32_t J, double lambda_fixed,
                                                                int32_t k_fixed, double omega_arg,
                                                                double* __restrict__ curve,
-                                                               ParamOut* __restrict__ out) {
+                                                               ParamOut* __restrict__ out, ProjBatch pb) {
+    {
+        const int64_t z = blockIdx.x;  // batch: problem z
+        sv += z * pb.vec;
+        ft += z * pb.vec;
+        if (l_ptr != nullptr) l_ptr += z * pb.lstr;
+        if (curve != nullptr) curve += z * pb.curve;
+        out += z;
+    }
     __shared__ double vals[kMaxGrid];
     __shared__ double lds[kProjThreads / kWave];
     __shared__ double s_lo, s_hi;
@@ -344,7 +363,16 @@ __global__ __launch_bounds__(kBlock) void k_proj_solution(const double* __restri
                                                           const double* __restrict__ V, int64_t ldv, int32_t l_arg,
                                                           const int32_t* __restrict__ l_ptr, int32_t method,
                                                           double lambda, int32_t k, const ParamOut* __restrict__ po,
-                                                          double* __restrict__ y) {
+                                                          double* __restrict__ y, ProjBatch pb) {
+    {
+        const int64_t z = blockIdx.y;  // batch: problem z
+        sv += z * pb.vec;
+        ft += z * pb.vec;
+        V += z * pb.mat;
+        if (l_ptr != nullptr) l_ptr += z * pb.lstr;
+        if (po != nullptr) po += z;
+        y += z * pb.vec;
+    }
     const int l = l_ptr != nullptr ? *l_ptr : l_arg;
     const int r = blockIdx.x * kBlock + threadIdx.x;
     if (r >= l) return;
@@ -392,7 +420,17 @@ __global__ __launch_bounds__(kProjThreads) void k_lsqr(const double* __restrict_
                                                        const int32_t* __restrict__ l_ptr, int64_t n, int32_t rule,
                                                        int32_t k_fixed, double* __restrict__ rho_out,
                                                        double* __restrict__ eta_out, ParamOut* __restrict__ out,
-                                                       double* __restrict__ y, int32_t l_max) {
+                                                       double* __restrict__ y, int32_t l_max, ProjBatch pb) {
+    {
+        const int64_t z = blockIdx.x;  // batch: problem z
+        alpha += z * pb.vec;
+        beta += z * pb.vec;
+        if (l_ptr != nullptr) l_ptr += z * pb.lstr;
+        if (rho_out != nullptr) rho_out += z * pb.vec;
+        if (eta_out != nullptr) eta_out += z * pb.vec;
+        out += z;
+        y += z * pb.vec;
+    }
     __shared__ double d[kMaxEll], e[kMaxEll], g[kMaxEll], rho[kMaxEll], eta[kMaxEll];
     __shared__ int s_k;
     const int tid = threadIdx.x;
@@ -526,27 +564,28 @@ __global__ __launch_bounds__(kProjThreads) void k_lsqr(const double* __restrict_
 
 void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* Vw,
                        int64_t ldw, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
-                       hipStream_t s) {
-    k_bidiag_svd<<<1, kSvdThreads, 0, s>>>(alpha, beta, l, l_ptr, Vw, ldw, sv, ftil, V, ldv, status);
+                       hipStream_t s, int nz, ProjBatch pb) {
+    k_bidiag_svd<<<nz, kSvdThreads, 0, s>>>(alpha, beta, l, l_ptr, Vw, ldw, sv, ftil, V, ldv, status, pb);
 }
 
 void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,
                          int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double omega, double* curve,
-                         ParamOut* out, hipStream_t s) {
-    k_param_choice<<<1, kProjThreads, 0, s>>>(sv, ft, l, l_ptr, method, rule, J, lambda_fixed, k_fixed, omega, curve,
-                                              out);
+                         ParamOut* out, hipStream_t s, int nz, ProjBatch pb) {
+    k_param_choice<<<nz, kProjThreads, 0, s>>>(sv, ft, l, l_ptr, method, rule, J, lambda_fixed, k_fixed, omega, curve,
+                                               out, pb);
 }
 
 void launch_lsqr(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, int64_t n, int32_t rule,
-                 int32_t k_fixed, double* rho, double* eta, ParamOut* out, double* y, int32_t l_max, hipStream_t s) {
-    k_lsqr<<<1, kProjThreads, 0, s>>>(alpha, beta, l, l_ptr, n, rule, k_fixed, rho, eta, out, y, l_max);
+                 int32_t k_fixed, double* rho, double* eta, ParamOut* out, double* y, int32_t l_max, hipStream_t s,
+                 int nz, ProjBatch pb) {
+    k_lsqr<<<nz, kProjThreads, 0, s>>>(alpha, beta, l, l_ptr, n, rule, k_fixed, rho, eta, out, y, l_max, pb);
 }
 
 void launch_proj_solution(const double* sv, const double* ft, const double* V, int64_t ldv, int32_t l,
                           const int32_t* l_ptr, int32_t method, double lambda, int32_t k, const ParamOut* po,
-                          double* y, int32_t l_max, hipStream_t s) {
-    k_proj_solution<<<(l_max + kBlock - 1) / kBlock, kBlock, 0, s>>>(sv, ft, V, ldv, l, l_ptr, method, lambda, k,
-                                                                     po, y);
+                          double* y, int32_t l_max, hipStream_t s, int nz, ProjBatch pb) {
+    k_proj_solution<<<dim3((l_max + kBlock - 1) / kBlock, nz), kBlock, 0, s>>>(sv, ft, V, ldv, l, l_ptr, method,
+                                                                               lambda, k, po, y, pb);
 }
 
 }  // namespace mqh

@@ -234,6 +234,90 @@ WORKLOADS: Dict[str, Callable[[], Problem]] = {
 }
 
 
+# --------------------------------------------------------------------------
+# Several right-hand sides per problem: a frequency sweep over cubes with
+# Gaussian-blob sources (no manufactured solution; results are compared with
+# the FP64 oracle)
+# --------------------------------------------------------------------------
+
+
+def blob_sources(x: np.ndarray, centres: np.ndarray, width: float = 0.1) -> np.ndarray:
+    """Rows exp(-|x - c_k|^2 / (2 width^2)) for each centre c_k: (len(centres), len(x))."""
+    d2 = ((x[None, :, :] - centres[:, None, :]) ** 2).sum(axis=2)
+    return np.exp(-d2 / (2.0 * width * width))
+
+
+@dataclasses.dataclass
+class MultiProblem:
+    """One problem with several right-hand sides F (rows [f_int; g_bnd])."""
+
+    name: str
+    x_int: np.ndarray
+    x_bnd: np.ndarray
+    kappa: float
+    eps: float
+    F: np.ndarray  # nrhs x n
+    ell: int
+
+    @property
+    def n_int(self) -> int:
+        return self.x_int.shape[0]
+
+    @property
+    def n_bnd(self) -> int:
+        return self.x_bnd.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.n_int + self.n_bnd
+
+    @property
+    def nrhs(self) -> int:
+        return self.F.shape[0]
+
+    @property
+    def nodes(self) -> np.ndarray:
+        return np.ascontiguousarray(np.concatenate([self.x_int, self.x_bnd], axis=0))
+
+
+SWEEP_COUNT = 64
+SWEEP_NRHS = 16
+SWEEP_ELL = 100
+SWEEP_SEED = 41
+
+
+def multi_cube(n_int: int, n_bnd: int, kappa: float, eps: float, nrhs: int, ell: int, seed: int,
+               width: float = 0.1) -> MultiProblem:
+    """Unit cube (Halton interior, uniform faces) with nrhs blob sources at uniform random
+    centres in the cube, g = 0 on the boundary."""
+    x_int = halton_cube(n_int)
+    x_bnd = cube_faces_uniform(split_counts(n_bnd, 6), seed)
+    centres = np.random.default_rng(seed + 1).random((nrhs, 3))
+    F = np.zeros((nrhs, n_int + n_bnd))
+    F[:, :n_int] = blob_sources(x_int, centres, width)
+    return MultiProblem(f"cube_n{n_int + n_bnd}_s{nrhs}", x_int, x_bnd, kappa, eps, F, ell)
+
+
+def sweep_sizes(count: int = SWEEP_COUNT, seed: int = SWEEP_SEED) -> np.ndarray:
+    """Problem sizes of the sweep: N uniform on [2000, 30000]."""
+    return np.random.default_rng(seed).integers(2000, 30001, size=count)
+
+
+def sweep_kappa(k: int, count: int = SWEEP_COUNT) -> float:
+    """kappa evenly spaced on [2, 40]."""
+    return 2.0 + 38.0 * k / (count - 1)
+
+
+def sweep_member(k: int, count: int = SWEEP_COUNT, nrhs: int = SWEEP_NRHS, ell: int = SWEEP_ELL,
+                 seed: int = SWEEP_SEED) -> MultiProblem:
+    """Member k of the frequency sweep: N from sweep_sizes (80 % interior Halton nodes,
+    20 % uniform face nodes), kappa from sweep_kappa, eps = 0.2 kappa + 1, nrhs blob sources."""
+    n = int(sweep_sizes(count, seed)[k])
+    n_int = int(round(0.8 * n))
+    kappa = sweep_kappa(k, count)
+    return multi_cube(n_int, n - n_int, kappa, 0.2 * kappa + 1.0, nrhs, ell, seed + 1000 + 2 * k)
+
+
 def random_vector(n: int, seed: int) -> np.ndarray:
     """Seeded standard-normal float64 vector (test operands)."""
     return np.random.default_rng(seed).standard_normal(n)

@@ -40,6 +40,7 @@ MQH_INFO_BREAKDOWN = 1
 MQH_INFO_GCV_AT_EDGE = 2
 MQH_INFO_LCURVE_AT_EDGE = 4
 MQH_MAX_ELL = 1024
+MQH_BLOCK_RHS = 16
 MQH_MLP_IN = 24
 MQH_MLP_WIDTH = 128
 MQH_MLP_OUT = 2
@@ -107,6 +108,10 @@ _SIGNATURES = {
     "mqh_lift": (ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _u32]),
     "mqh_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(mqh_solve_opts), _vp, _vp, _vp, _vp,
                                  ctypes.POINTER(mqh_solve_info)]),
+    "mqh_apply_multi": (ctypes.c_int, [_vp, _i32, _vp, _i64, _i32, _vp, _vp, _i64, _vp, _i64, _u32]),
+    "mqh_gkb_multi": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _u32]),
+    "mqh_solve_multi": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(mqh_solve_opts), _vp, _i64,
+                                       ctypes.POINTER(mqh_solve_info)]),
     "mqh_eval": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _u32]),
     "mqh_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _u32]),
     "mqh_mlp_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _u32]),
@@ -359,6 +364,80 @@ def mqh_solve(h, f_int, g_bnd, ell: int, method: int = MQH_METHOD_HKT, rule: int
                        info.resid_norm, info.sol_norm, info.flags, list(info.t_ms))
 
 
+def mqh_apply_multi(h, trans: int, X, shifts=None, Z=None, Y=None):
+    """Rows of Y (nrhs x n): Y[k] = op(A) X[k] - shifts[k] Z[k]."""
+    n = int(lib.mqh_problem_size(h))
+    nrhs = int(X.shape[0])
+    if X.shape[1] != n or (Z is not None and tuple(Z.shape) != tuple(X.shape)):
+        raise ValueError("X and Z must be nrhs x n")
+    if Y is None:
+        Y = _empty_like_kind(X, (nrhs, n))
+    fl = _flags(X, Z, Y)
+    sh = None
+    if shifts is not None:
+        sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64).reshape(nrhs))
+    _check(lib.mqh_apply_multi(h, int(trans), _ptr(X)[0], n, nrhs, None if sh is None else ctypes.c_void_p(sh.ctypes.data),
+                               _ptr(Z)[0], n, _ptr(Y)[0], n, fl), "mqh_apply_multi", warn_ok=False)
+    return Y
+
+
+def mqh_gkb_multi(h, F, ell: int, reorth: int = 1, want_bases: bool = True):
+    """Lockstep runs of Algorithm 1 for the rows of F (nrhs x n): per run k,
+    W[k] (ell+1 x n, row j = w_{j+1}), Z[k], alpha[k], beta[k], ell_done[k]."""
+    n = int(lib.mqh_problem_size(h))
+    nrhs = int(F.shape[0])
+    if F.shape[1] != n:
+        raise ValueError("F must be nrhs x n")
+    W = _empty_like_kind(F, (nrhs, ell + 1, n)) if want_bases else None
+    Z = _empty_like_kind(F, (nrhs, ell, n)) if want_bases else None
+    al = _empty_like_kind(F, (nrhs, ell))
+    be = _empty_like_kind(F, (nrhs, ell + 1))
+    fl = _flags(F, W, Z, al, be)
+    done = np.zeros(nrhs, dtype=np.int32)
+    st = _check(lib.mqh_gkb_multi(h, _ptr(F)[0], n, nrhs, int(ell), int(reorth), _ptr(W)[0], _ptr(Z)[0], _ptr(al)[0],
+                                  _ptr(be)[0], ctypes.c_void_p(done.ctypes.data), fl), "mqh_gkb_multi")
+    return dict(W=W, Z=Z, alpha=al, beta=be, ell_done=done, status=st)
+
+
+@dataclasses.dataclass
+class MultiSolveOutput:
+    coef: Any          # nrhs x n
+    status: int
+    ell_done: np.ndarray
+    k: np.ndarray
+    lam: np.ndarray
+    crit: np.ndarray
+    resid_norm: np.ndarray
+    sol_norm: np.ndarray
+    flags: np.ndarray
+    t_ms: np.ndarray   # nrhs x 8 (each run reports its group's times)
+
+
+def mqh_solve_multi(h, F, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQH_RULE_GCV, k_trunc: int = 0,
+                    lambda_fixed: float = 0.0, n_grid: int = 200, reorth: int = 1, time_products: bool = False,
+                    coef=None, gcv_weight: float = 1.0) -> MultiSolveOutput:
+    """Algorithm 4 for every row of F (nrhs x n, rows [f_int; g_bnd])."""
+    n = int(lib.mqh_problem_size(h))
+    nrhs = int(F.shape[0])
+    if F.shape[1] != n:
+        raise ValueError("F must be nrhs x n")
+    if coef is None:
+        coef = _empty_like_kind(F, (nrhs, n))
+    fl = _flags(F, coef)
+    opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=int(method), rule=int(rule),
+                          k_trunc=int(k_trunc), n_grid=int(n_grid), lambda_fixed=float(lambda_fixed),
+                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), reserved=0,
+                          gcv_weight=float(gcv_weight))
+    infos = (mqh_solve_info * nrhs)()
+    st = _check(lib.mqh_solve_multi(h, _ptr(F)[0], n, nrhs, ctypes.byref(opts), _ptr(coef)[0], n, infos),
+                "mqh_solve_multi")
+    get = lambda f, dt: np.array([getattr(i, f) for i in infos], dtype=dt)  # noqa: E731
+    return MultiSolveOutput(coef, st, get("ell_done", np.int32), get("k_chosen", np.int32),
+                            get("lambda_chosen", np.float64), get("crit", np.float64),
+                            get("resid_norm", np.float64), get("sol_norm", np.float64), get("flags", np.uint32),
+                            np.array([list(i.t_ms) for i in infos], dtype=np.float64))
+
+
 def mqh_eval(h, coef, x_eval, u=None):
     m = int(x_eval.shape[0])
     if u is None:
@@ -492,6 +571,15 @@ class Problem:
 
     def gkb(self, f, ell, reorth=True, want_bases=True):
         return mqh_gkb(self.h, f, ell, int(bool(reorth)), want_bases)
+
+    def apply_multi(self, X, trans=False, shifts=None, Z=None, Y=None):
+        return mqh_apply_multi(self.h, int(bool(trans)), X, shifts, Z, Y)
+
+    def gkb_multi(self, F, ell, reorth=True, want_bases=True):
+        return mqh_gkb_multi(self.h, F, ell, int(bool(reorth)), want_bases)
+
+    def solve_multi(self, F, ell, **kw) -> MultiSolveOutput:
+        return mqh_solve_multi(self.h, F, ell, **kw)
 
     def solve_learned(self, f_int, g_bnd, ell, predictor, **kw) -> LearnedOutput:
         return mqh_solve_learned(self.h, f_int, g_bnd, ell, predictor, **kw)

@@ -102,6 +102,18 @@ def test_invalid_create_arguments(mq):
     assert "non-finite" in mq.mqh_last_error()
 
 
+def test_multi_entry_points_reject_null_problem(mq):
+    # argument checks run before any device work
+    L = mq.lib
+    F = np.zeros((2, 8))
+    fp = F.ctypes.data
+    opts = mq.mqh_solve_opts(ell=3, reorth=1, method=mq.MQH_METHOD_HKT, rule=mq.MQH_RULE_GCV)
+    assert L.mqh_apply_multi(None, 0, fp, 8, 2, None, None, 8, fp, 8, 0) == mq.MQH_EINVAL
+    assert L.mqh_gkb_multi(None, fp, 8, 2, 3, 1, None, None, None, None, None, 0) == mq.MQH_EINVAL
+    assert L.mqh_solve_multi(None, fp, 8, 2, ctypes.byref(opts), fp, 8, None) == mq.MQH_EINVAL
+    assert "NULL problem" in mq.mqh_last_error()
+
+
 def test_invalid_projected_arguments(mq):
     a = np.ones(4)
     b = np.ones(5)

@@ -1,0 +1,260 @@
+"""GPU parity of the multi-right-hand-side path (lockstep Golub-Kahan runs
+sharing each pass over A) against the FP64 oracle, run by run.
+
+The method for several right-hand sides is one independent run of
+Algorithm 1 (and of Algorithm 4 for the solve) per right-hand side, so the
+oracle is the single-run oracle applied to each column.
+
+Tolerances:
+* FP64 forms and groups of one: the multi path performs, per run, exactly
+  the operations of the single-run path (same kernels, same reduction
+  orders), so its outputs are compared bit for bit with mqh_gkb / mqh_solve.
+* Block products (FP32-evaluated entries, FP32 matrix-core products, FP32
+  sums over one 256-node chunk, FP64 across chunks and slices):
+  |dy_i| <= 4e-6 (|A||x|)_i against the oracle, the bar of the single FP32
+  product (entries to ~1e-6 relative; a 256-term FP32 sum adds at most
+  ~256 u32 / 2 of its absolute sum in the worst case, ~1e-6 typically).
+* Golub-Kahan scalars with FP32 entries: leading Ritz values to 1e-5
+  relative, bases orthonormal to 1e-12 (reorthogonalisation stays FP64).
+* Runs in a group do not interact: a run's outputs are bit-identical
+  whichever runs share its group (each output column of a block product is
+  its own dot products over the same entries).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2511_09798_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mq():
+    from paper_2511_09798_amd import mqhelm
+
+    return mqhelm
+
+
+def _problem(mq, p, mode):
+    say("create", p.name, "mode", mode, "n", p.n)
+    return mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, mode)
+
+
+# ragged sizes: several 128-node blocks and 256-node chunks plus tails in both classes
+RAGGED = [
+    ("cube_523", lambda s: I.multi_cube(333, 190, 6.0, 2.0, s, 30, seed=5)),
+    ("cube_1800", lambda s: I.multi_cube(1200, 600, 5.0, 2.0, s, 30, seed=9)),
+]
+
+
+def _scale_rows(orc, p, X, trans):
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    Aop = A.T if trans else A
+    return Aop @ X.T, np.abs(Aop) @ np.abs(X.T)
+
+
+# ---------------------------------------------------------------------------
+# block products
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,make", RAGGED)
+@pytest.mark.parametrize("nrhs", [2, 5, 16, 19])
+@pytest.mark.parametrize("mode", ["matfree_fp32", "matfree_fp64"])
+def test_apply_multi_against_oracle(mq, orc, name, make, nrhs, mode):
+    p = make(nrhs)
+    rng = np.random.default_rng(nrhs)
+    X = rng.standard_normal((nrhs, p.n))
+    Zs = rng.standard_normal((nrhs, p.n))
+    shifts = rng.standard_normal(nrhs)
+    tol = 4e-6 if mode == "matfree_fp32" else 1e-13
+    with _problem(mq, p, mode) as pr:
+        for trans in (False, True):
+            say("apply_multi", name, nrhs, mode, "trans", trans)
+            Y = pr.apply_multi(X, trans=trans)
+            ref, scale = _scale_rows(orc, p, X, trans)
+            err = np.abs(Y.T - ref) / scale
+            assert np.all(err <= tol), float(err.max())
+            say("apply_multi shifted", name, nrhs, mode, "trans", trans)
+            Y2 = pr.apply_multi(X, trans=trans, shifts=shifts, Z=Zs)
+            ref2 = ref - shifts[None, :] * Zs.T
+            scale2 = scale + np.abs(shifts[None, :] * Zs.T)
+            err2 = np.abs(Y2.T - ref2) / scale2
+            assert np.all(err2 <= tol), float(err2.max())
+
+
+def test_apply_multi_columns_independent(mq):
+    # a column's block product does not depend on the other columns of its group
+    p = I.multi_cube(700, 300, 4.0, 1.5, 16, 10, seed=3)
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((16, p.n))
+    X2 = X.copy()
+    X2[5:] = rng.standard_normal((11, p.n)) * 1e3
+    X2[9] = 0.0
+    with _problem(mq, p, "matfree_fp32") as pr:
+        for trans in (False, True):
+            say("independence", trans)
+            Y = pr.apply_multi(X, trans=trans)
+            Y2 = pr.apply_multi(X2, trans=trans)
+            assert np.array_equal(Y[:5], Y2[:5])
+            assert np.all(Y2[9] == 0.0)
+
+
+def test_apply_multi_single_group_of_one_is_single_product(mq):
+    p = I.multi_cube(333, 190, 6.0, 2.0, 1, 10, seed=5)
+    x = I.random_vector(p.n, 4)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("group of one")
+        for trans in (False, True):
+            assert np.array_equal(pr.apply_multi(x[None, :], trans=trans)[0], pr.apply(x, trans=trans))
+
+
+# ---------------------------------------------------------------------------
+# lockstep Golub-Kahan runs
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["stored_fp64", "matfree_fp64"])
+def test_gkb_multi_bitwise_single_fp64(mq, mode):
+    p = I.multi_cube(333, 190, 6.0, 2.0, 5, 30, seed=5)
+    with _problem(mq, p, mode) as pr:
+        say("gkb_multi fp64 vs single", mode)
+        r = pr.gkb_multi(p.F, p.ell)
+        for k in range(p.nrhs):
+            s = pr.gkb(p.F[k], p.ell)
+            assert r["ell_done"][k] == s["ell_done"]
+            for key in ("alpha", "beta", "W", "Z"):
+                assert np.array_equal(r[key][k], s[key]), (k, key)
+
+
+def test_gkb_multi_group_of_one_fp32_bitwise_single(mq):
+    p = I.multi_cube(333, 190, 6.0, 2.0, 1, 30, seed=5)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("gkb_multi fp32 group of one")
+        r = pr.gkb_multi(p.F, p.ell)
+        s = pr.gkb(p.F[0], p.ell)
+    for key in ("alpha", "beta", "W", "Z"):
+        assert np.array_equal(r[key][0], s[key]), key
+
+
+@pytest.mark.parametrize("name,make", RAGGED)
+@pytest.mark.parametrize("nrhs", [16, 19])
+def test_gkb_multi_block_against_oracle(mq, orc, name, make, nrhs):
+    p = make(nrhs)
+    ell = 20
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("gkb_multi block", name, nrhs)
+        r = pr.gkb_multi(p.F, ell)
+    assert np.all(r["ell_done"] == ell) and r["status"] == 0
+    for k in range(nrhs):
+        g = orc.gkb(A, p.nodes, p.n_int, p.kappa, p.eps, p.F[k], ell)
+        C = orc.bidiag_matrix(r["alpha"][k], r["beta"][k])
+        s_gpu = np.linalg.svd(C, compute_uv=False)
+        s_orc = np.linalg.svd(orc.bidiag_matrix(g.alpha, g.beta), compute_uv=False)
+        assert np.max(np.abs(s_gpu[:5] - s_orc[:5]) / s_orc[:5]) < 1e-5, k
+        assert r["beta"][k][0] == pytest.approx(g.beta[0], rel=1e-14)
+        W, Z = r["W"][k].T, r["Z"][k].T
+        assert np.max(np.abs(W.T @ W - np.eye(ell + 1))) < 1e-12
+        assert np.max(np.abs(Z.T @ Z - np.eye(ell))) < 1e-12
+        # A Z = W C with the oracle's A, to the FP32 entry error
+        R = A @ Z - W @ C
+        S = np.abs(A) @ np.abs(Z) + np.abs(W) @ np.abs(C)
+        assert np.max(np.abs(R) / S) < 1e-5, k
+
+
+def test_gkb_multi_runs_independent_and_breakdown(mq):
+    # a zero right-hand side stops at once (beta_1 = 0); the other runs of its
+    # group are bit-identical to a group without it; identical columns give
+    # identical runs
+    p = I.multi_cube(700, 300, 4.0, 1.5, 6, 15, seed=3)
+    F = p.F
+    G = np.concatenate([F[:3], np.zeros((1, p.n)), F[3:], F[1:2]], axis=0)  # 8 runs
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("gkb_multi independence")
+        r = pr.gkb_multi(F, p.ell)
+        q = pr.gkb_multi(G, p.ell)
+    assert q["status"] == 1  # MQH_WBREAKDOWN
+    assert q["ell_done"][3] == 0 and q["beta"][3][0] == 0.0
+    assert np.all(q["W"][3] == 0.0) and np.all(q["Z"][3] == 0.0)
+    for k, kg in ((0, 0), (1, 1), (2, 2), (3, 4), (4, 5), (5, 6)):
+        for key in ("alpha", "beta", "W", "Z"):
+            assert np.array_equal(r[key][k], q[key][kg]), (k, key)
+    for key in ("alpha", "beta", "W", "Z"):
+        assert np.array_equal(q[key][7], q[key][1]), key
+
+
+# ---------------------------------------------------------------------------
+# whole solves
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", ["hkt", "ine_tsvd", "lsqr"])
+def test_solve_multi_bitwise_single_fp64(mq, method):
+    p = I.multi_cube(333, 190, 6.0, 2.0, 4, 30, seed=5)
+    m = {"hkt": mq.MQH_METHOD_HKT, "ine_tsvd": mq.MQH_METHOD_INE_TSVD, "lsqr": mq.MQH_METHOD_LSQR}[method]
+    with _problem(mq, p, "matfree_fp64") as pr:
+        say("solve_multi vs single", method)
+        r = pr.solve_multi(p.F, p.ell, method=m)
+        for k in range(p.nrhs):
+            s = pr.solve(p.F[k, :p.n_int], p.F[k, p.n_int:], p.ell, method=m)
+            assert np.array_equal(r.coef[k], s.coef), k
+            assert r.lam[k] == s.lam and r.k[k] == s.k and r.ell_done[k] == s.ell_done
+            assert r.crit[k] == s.crit and r.flags[k] == s.flags
+
+
+def test_solve_multi_against_oracle(mq, orc):
+    # FP64 form: each run's GCV lambda to 1e-6 of the oracle's, and at a
+    # fixed lambda u to 1e-8; block form: at lambda = 1e-3 max_k s_1 u
+    # within 1e-3 of the oracle (the single FP32 solve's bar)
+    p = I.multi_cube(400, 240, 3.0, 0.7, 17, 60, seed=11)
+    x_eval = I.cube_interior_uniform(500, 12)
+    refs = [orc.solve(p.nodes, p.n_int, p.kappa, p.eps, p.F[k], p.ell, stored=False) for k in range(p.nrhs)]
+    lam = np.array([ro.lam for ro in refs])
+    s1 = max(float(ro.s[0]) for ro in refs)
+    for mode, lam_c, tol in (("matfree_fp64", float(np.median(lam)), 1e-8), ("matfree_fp32", 1e-3 * s1, 1e-3)):
+        with _problem(mq, p, mode) as pr:
+            if mode == "matfree_fp64":
+                say("solve_multi gcv", mode)
+                r = pr.solve_multi(p.F, p.ell)
+                for k in range(p.nrhs):
+                    assert r.lam[k] == pytest.approx(lam[k], rel=1e-6), k
+            say("solve_multi fixed lambda", mode, lam_c)
+            rr = pr.solve_multi(p.F, p.ell, rule=mq.MQH_RULE_FIXED, lambda_fixed=lam_c)
+            for k in range(p.nrhs):
+                ro = orc.solve(p.nodes, p.n_int, p.kappa, p.eps, p.F[k], p.ell, stored=False,
+                               rule=orc.RULE_FIXED, lambda_fixed=lam_c)
+                u = pr.eval(rr.coef[k], x_eval)
+                uo = orc.eval_u(p.nodes, p.eps, ro.coef, x_eval)
+                assert np.linalg.norm(u - uo) <= tol * np.linalg.norm(uo), (mode, k)
+
+
+def test_multi_invalid_arguments(mq):
+    p = I.multi_cube(50, 30, 3.0, 1.0, 2, 5, seed=1)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("multi invalid args")
+        L = mq.lib
+        n = p.n
+        F = np.ascontiguousarray(p.F)
+        fp = F.ctypes.data_as(mq.ctypes.c_void_p)
+        assert L.mqh_gkb_multi(pr.h, fp, n, 0, 5, 1, None, None, None, None, None, 0) == mq.MQH_EINVAL
+        assert L.mqh_gkb_multi(pr.h, fp, n - 1, 2, 5, 1, None, None, None, None, None, 0) == mq.MQH_EINVAL
+        assert L.mqh_gkb_multi(pr.h, fp, n, 2, n + 1, 1, None, None, None, None, None, 0) == mq.MQH_EINVAL
+        assert L.mqh_gkb_multi(pr.h, None, n, 2, 5, 1, None, None, None, None, None, 0) == mq.MQH_EINVAL
+        bad = F.copy()
+        bad[1, 3] = np.nan
+        assert L.mqh_gkb_multi(pr.h, bad.ctypes.data_as(mq.ctypes.c_void_p), n, 2, 5, 1, None, None, None, None,
+                               None, 0) == mq.MQH_EINVAL
+        Y = np.empty_like(F)
+        yp = Y.ctypes.data_as(mq.ctypes.c_void_p)
+        assert L.mqh_apply_multi(pr.h, 2, fp, n, 2, None, None, n, yp, n, 0) == mq.MQH_EINVAL
+        assert L.mqh_apply_multi(pr.h, 0, fp, n, 2, None, None, n, yp, n - 1, 0) == mq.MQH_EINVAL
+        with pytest.raises(mq.MQHError):
+            pr.solve_multi(F, 5, method=7)
+        # the problem is still usable after rejected calls
+        r = pr.gkb_multi(F, 5)
+        assert np.all(r["ell_done"] == 5)
