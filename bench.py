@@ -41,6 +41,7 @@ CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
 # alone; v_rsq_f32 / v_sqrt_f32 occupy two issue slots, v_rsq_f64 four.
 VALU_PEAK_DUAL = CUS * SIMDS * 2 * LANES * CLOCK  # 78.6e12 lane-operations/s (= FP32 vector peak / 2 flops)
 VALU_PEAK_SINGLE = CUS * SIMDS * LANES * CLOCK  # 39.3e12 lane-operations/s (FP64 rate)
+MFMA_F32_PEAK = 157.3e12  # dense FP32 matrix-core flop/s
 # Algorithmic operations per matrix entry (the entry formula evaluated
 # directly, a transcendental counted once):
 #   FP32: interior 3 sub + 3 fma (t) + rsq + mul (s^2) + 2 fma + fma (accumulate) = 11
@@ -196,6 +197,115 @@ def learned_context(mq, torch, dev, count: int, n: int = 60000, ell: int = 60, s
                 net_lambda_used=int(sum(r["used_net"] for r in rows)), cases=rows)
 
 
+def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, workers: int):
+    """Frequency sweep over cubes: count problems (N uniform on [2000, 30000], kappa evenly spaced
+    on [2, 40], eps = 0.2 kappa + 1), 16 Gaussian-blob sources each, ell = 100, HKT with GCV for
+    every source through the lockstep runs with block products (FP32 entries).  All problems and
+    sources are resident on the device; the sweep runs once one problem at a time (kernel timing)
+    and once with `workers` problems side by side, each on its own stream (the sweep time)."""
+    import numpy as np
+
+    from paper_2511_09798_amd import inputs as I
+
+    ns = I.sweep_sizes()[:count]
+    probs, handles, Fs, coefs = [], [], [], []
+    t = time.perf_counter()
+    for k in range(count):
+        p = I.sweep_member(k)
+        probs.append(p)
+        handles.append(mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, "matfree_fp32"))
+        Fs.append(torch.from_numpy(p.F).to(dev))
+        coefs.append(torch.empty_like(Fs[-1]))
+    torch.cuda.synchronize()
+    log("sweep setup", f"{time.perf_counter() - t:.1f} s")
+    ell = probs[0].ell
+    mq.mqh_solve_sweep(handles, Fs, ell, workers=workers, coefs=coefs)  # warmup (workspaces)
+    torch.cuda.synchronize()
+    # one problem at a time, product kernels timed
+    t = time.perf_counter()
+    outs = mq.mqh_solve_sweep(handles, Fs, ell, workers=1, coefs=coefs, time_products=True)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t
+    kern_ms = gkb_ms = svd_ms = par_ms = lift_ms = flops = 0.0
+    solves = 0
+    for p, o in zip(probs, outs):
+        tm = o.t_ms[0]
+        kern_ms += tm[6] + tm[7]
+        gkb_ms += tm[1]
+        svd_ms += tm[2]
+        par_ms += tm[3]
+        lift_ms += tm[4]
+        flops += 2.0 * 2.0 * p.ell * p.n * p.n * p.nrhs * (int(o.ell_done.min()) / p.ell)
+        solves += p.nrhs
+    log("sweep one problem at a time", f"{seq_s:.3f} s", "block kernels", f"{kern_ms / 1e3:.3f} s")
+    # side by side
+    reps = []
+    for r in range(2):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        outs_p = mq.mqh_solve_sweep(handles, Fs, ell, workers=workers, coefs=coefs)
+        torch.cuda.synchronize()
+        reps.append(time.perf_counter() - t)
+        log("sweep", workers, "workers", f"{reps[-1]:.3f} s")
+    par_s = min(reps)
+    same = all(np.array_equal(a.lam, b.lam) for a, b in zip(outs, outs_p))
+    res = dict(workload=f"cube frequency sweep: {count} problems, N uniform on [2000, 30000], kappa evenly "
+                        "spaced on [2, 40], eps = 0.2 kappa + 1, 16 Gaussian-blob sources (width 0.1), g = 0, "
+                        "ell = 100, HKT + GCV per source, FP32 entries, block products",
+               problems=count, sources=solves, sum_n2=float((ns.astype(np.float64) ** 2).sum()),
+               time_s=par_s, workers=workers, source_solves_per_s=solves / par_s,
+               time_one_at_a_time_s=seq_s, same_choices_side_by_side=bool(same),
+               phase_ms_one_at_a_time=dict(gkb=gkb_ms, proj_svd=svd_ms, param=par_ms, lift=lift_ms),
+               block_product_ms=kern_ms,
+               roofline=dict(bound="mfma", achieved=flops / (kern_ms * 1e-3) / 1e12, peak=MFMA_F32_PEAK / 1e12,
+                             unit="TFLOP/s", frac=flops / (kern_ms * 1e-3) / MFMA_F32_PEAK,
+                             kernel="k_mfm_block", flops=flops,
+                             note="2 n^2 s flops per block product (the dense n x n by n x s contraction); "
+                                  "entries and squared distances are extra issue on the same SIMDs"))
+    seq = []
+    for k in range(min(compare, count)):
+        p, h, F = probs[k], handles[k], Fs[k]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        h.solve_multi(F, p.ell, coef=coefs[k])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        for r in range(p.nrhs):  # warmup of the single-source path
+            h.solve(F[r, :p.n_int].contiguous(), F[r, p.n_int:].contiguous(), p.ell)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for r in range(p.nrhs):
+            h.solve(F[r, :p.n_int].contiguous(), F[r, p.n_int:].contiguous(), p.ell)
+        torch.cuda.synchronize()
+        seq.append((p.n, dt, time.perf_counter() - t))
+        log("sweep", k, "lockstep", f"{dt * 1e3:.1f} ms", "one source at a time", f"{seq[-1][2] * 1e3:.1f} ms")
+    if seq:
+        res["vs_sequential_single"] = dict(problems=len(seq), n=[q[0] for q in seq],
+                                           lockstep_s=sum(q[1] for q in seq), sequential_s=sum(q[2] for q in seq),
+                                           speedup=sum(q[2] for q in seq) / sum(q[1] for q in seq))
+    if oracle_check:
+        from oracle import oracle as O
+
+        k = int(np.argmin(ns))
+        p = probs[k]
+        x_eval = I.cube_interior_uniform(1000, 77)
+        cg = coefs[k].cpu().numpy()
+        e = []
+        for r in range(p.nrhs):
+            ro = O.solve(p.nodes, p.n_int, p.kappa, p.eps, p.F[r], p.ell, stored=True)
+            u = O.eval_u(p.nodes, p.eps, cg[r], x_eval)
+            uo = O.eval_u(p.nodes, p.eps, ro.coef, x_eval)
+            e.append(rel_l2(u, uo))
+        res["oracle_check"] = dict(problem=k, n=p.n, kappa=p.kappa, max_rel_l2_vs_oracle=float(max(e)),
+                                   median_rel_l2_vs_oracle=float(np.median(e)))
+        log("sweep oracle check", json.dumps(res["oracle_check"]))
+    for h in handles:
+        h.close()
+    del Fs, coefs
+    torch.cuda.synchronize()
+    return res
+
+
 def cpu_baseline(p, rows):
     """The oracle's entry-by-entry FP64 products on a row / column sample."""
     import numpy as np
@@ -235,6 +345,11 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=150000, help="row/column sample of the CPU baseline (0: skip)")
     ap.add_argument("--learned", type=int, default=8,
                     help="pump-casing problems for the learned-solve comparison (0: skip)")
+    ap.add_argument("--sweep", type=int, default=64, help="problems of the multi-source frequency sweep (0: skip)")
+    ap.add_argument("--sweep-compare", type=int, default=2,
+                    help="sweep problems also solved one source at a time for comparison")
+    ap.add_argument("--sweep-oracle", type=int, default=1, help="check the smallest sweep problem against the oracle")
+    ap.add_argument("--sweep-workers", type=int, default=4, help="sweep problems run side by side")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -327,6 +442,9 @@ def main():
             line["learned"] = learned_context(mq, torch, dev, args.learned)
         else:
             log("no trained predictor at", L.MODEL_PATH, "- learned comparison skipped")
+    if args.sweep > 0:
+        line["sweep"] = sweep_context(mq, torch, dev, args.sweep, args.sweep_compare, bool(args.sweep_oracle),
+                                      args.sweep_workers)
     if args.cpu_rows > 0:
         log("cpu baseline", args.cpu_rows, "rows")
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_rows)

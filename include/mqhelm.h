@@ -355,6 +355,33 @@ int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
                     double* coef, int64_t ldc, mqh_solve_info* info);
 
 /*
+ * A sweep of independent problems (a frequency sweep: one problem per
+ * wavenumber), each solved as by mqh_solve_multi with the same opts.
+ * `workers` host threads take the items in order and run them side by
+ * side, each problem on its own stream, so that the kernels of one problem
+ * overlap those of another (problems created with stream = NULL each own a
+ * stream; problems sharing a stream run one after the other).  A problem
+ * may appear once.  Per item: status receives mqh_solve_multi's return
+ * value; F, coef, info as there (opts->flags applies to every item).
+ * Returns the first error met (mqh_last_error has its message; items not
+ * yet started keep MQH_EINVAL), else MQH_WBREAKDOWN if any item broke
+ * down, else MQH_WEDGE if any choice sits at an edge, else MQH_OK.
+ * Items must not be touched while the call runs.
+ */
+typedef struct {
+    mqh_problem* p;
+    const double* F;        /* nrhs right-hand sides, leading dimension ldf */
+    int64_t ldf;
+    int32_t nrhs;
+    int32_t status;         /* out */
+    double* coef;           /* out: nrhs coefficient vectors, leading dimension ldc */
+    int64_t ldc;
+    mqh_solve_info* info;   /* out: nrhs records, or NULL */
+} mqh_sweep_item;
+
+int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* opts, int32_t workers);
+
+/*
  * The predictor network's kernels (FP32; every array is a device pointer and
  * flags must contain MQH_FLAG_DEVICE_PTRS).  Batches are row-major.
  *   mqh_mlp_forward:  y (batch x 2) from x (batch x 24); hidden receives the

@@ -9,7 +9,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -89,7 +92,7 @@ struct HostResults {
 // kBlkRhs runs side by side, run k's arrays at base + k * stride.
 struct MultiWs {
     int32_t nz_cap = 0, ell_cap = 0;
-    int64_t vstr = 0;     // stride of the length-(ell + 2) arrays (alpha, beta, sv, ftil, y, cvec)
+    int64_t vstr = 0;     // stride of the length-(ell + 2) arrays (alpha, beta, sv, ftil, y)
     int64_t bstr = 0;     // stride of a basis, (ell_cap + 1) x ldn
     int64_t gstr = 0;     // stride of the reorthogonalisation partials
     int64_t nstr = 0;     // stride of the norm partials
@@ -100,7 +103,6 @@ struct MultiWs {
     double* sv = nullptr;
     double* ftil = nullptr;
     double* y = nullptr;
-    double* cvec = nullptr;
     double* gpart = nullptr;
     double* npart = nullptr;
     double* Vw = nullptr;  // ell_cap x ell_cap per run
@@ -136,6 +138,7 @@ struct mqh_problem {
     // of the current product in the sorted order
     float4* XS = nullptr;
     int32_t* perm = nullptr;
+    int32_t* iperm = nullptr;  // iperm[perm[q]] = q
     float4* frames = nullptr;
     float4* cf = nullptr;
     double* A = nullptr;
@@ -161,7 +164,6 @@ struct mqh_problem {
     double* beta = nullptr;
     GkbState* st = nullptr;
     double* gpart = nullptr;
-    double* cvec = nullptr;
     double* npart = nullptr;
     // projected problem
     double* sv = nullptr;
@@ -382,7 +384,6 @@ int ensure_gkb(mqh_problem* p, int32_t ell) {
     dfree(p->alpha);
     dfree(p->beta);
     dfree(p->gpart);
-    dfree(p->cvec);
     dfree(p->sv);
     dfree(p->ftil);
     dfree(p->Vw);
@@ -398,7 +399,6 @@ int ensure_gkb(mqh_problem* p, int32_t ell) {
     if ((rc = dalloc(&p->alpha, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->beta, (size_t)cols + 1))) return rc;
     if ((rc = dalloc(&p->gpart, (size_t)gemvt_blocks(p->n) * (size_t)cols))) return rc;
-    if ((rc = dalloc(&p->cvec, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->sv, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->ftil, (size_t)cols + 1))) return rc;
     if ((rc = dalloc(&p->Vw, (size_t)ell * (size_t)ell))) return rc;
@@ -422,25 +422,22 @@ int run_gkb(mqh_problem* p, int32_t ell, int32_t reorth, bool timed, int32_t j0 
         launch_init_state(p->st, ell, p->alpha, p->beta, s);
         LAUNCHCHK("init state");
         launch_sumsq_partial(p->vx, n, p->npart, nbq, p->st, s);
-        launch_norm_finalize(p->npart, nbq, 0, 0, n, p->alpha, p->beta, p->st, s);
-        launch_scale(p->vx, n, p->beta, p->W, p->st, s);
+        launch_finalize_scale(p->npart, nbq, 0, 0, n, p->alpha, p->beta, p->st, p->vx, p->W, s);
         LAUNCHCHK("initial normalisation");
     }
     auto orthonormalize = [&](double* v, const double* V, int32_t m, int kind, int32_t j, double* dst) -> int {
         int nparts;
         if (reorth && m > 0) {
-            launch_gemvt(V, ldn, n, m, v, p->gpart, p->cvec, p->st, s);
-            launch_update(V, ldn, n, m, p->cvec, v, nullptr, p->st, s);
-            launch_gemvt(V, ldn, n, m, v, p->gpart, p->cvec, p->st, s);
-            launch_update(V, ldn, n, m, p->cvec, v, p->npart, p->st, s);
+            launch_gemvt(V, ldn, n, m, v, p->gpart, p->st, s);
+            launch_update(V, ldn, n, m, p->gpart, v, nullptr, p->st, s);
+            launch_gemvt(V, ldn, n, m, v, p->gpart, p->st, s);
+            launch_update(V, ldn, n, m, p->gpart, v, p->npart, p->st, s);
             nparts = nbu;
         } else {
             launch_sumsq_partial(v, n, p->npart, nbq, p->st, s);
             nparts = nbq;
         }
-        launch_norm_finalize(p->npart, nparts, kind, j, n, p->alpha, p->beta, p->st, s);
-        const double* div = kind == 1 ? p->alpha + j : p->beta + j + 1;
-        launch_scale(v, n, div, dst, p->st, s);
+        launch_finalize_scale(p->npart, nparts, kind, j, n, p->alpha, p->beta, p->st, v, dst, s);
         LAUNCHCHK("reorthogonalisation / normalisation");
         return MQH_OK;
     };
@@ -476,7 +473,6 @@ void multi_free(MultiWs& w) {
     dfree(w.sv);
     dfree(w.ftil);
     dfree(w.y);
-    dfree(w.cvec);
     dfree(w.gpart);
     dfree(w.npart);
     dfree(w.Vw);
@@ -524,7 +520,7 @@ int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
     if ((rc = dalloc(&w.W, Z * (size_t)w.bstr)) || (rc = dalloc(&w.Z, Z * (size_t)w.bstr)) ||
         (rc = dalloc(&w.alpha, Z * (size_t)w.vstr)) || (rc = dalloc(&w.beta, Z * (size_t)w.vstr)) ||
         (rc = dalloc(&w.sv, Z * (size_t)w.vstr)) || (rc = dalloc(&w.ftil, Z * (size_t)w.vstr)) ||
-        (rc = dalloc(&w.y, Z * (size_t)w.vstr)) || (rc = dalloc(&w.cvec, Z * (size_t)w.vstr)) ||
+        (rc = dalloc(&w.y, Z * (size_t)w.vstr)) ||
         (rc = dalloc(&w.gpart, Z * (size_t)w.gstr)) || (rc = dalloc(&w.npart, Z * (size_t)w.nstr)) ||
         (rc = dalloc(&w.Vw, Z * (size_t)lc * (size_t)lc)) || (rc = dalloc(&w.V, Z * (size_t)lc * (size_t)lc)) ||
         (rc = dalloc(&w.st, Z)) || (rc = dalloc(&w.pout, Z)) || (rc = dalloc(&w.status, Z)) ||
@@ -559,9 +555,11 @@ int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
 
 // Y_k = op(A) X_k - shift_k Zs_k for runs k < nz (run k's vectors at
 // base + k * stride; shift_k = shift[k * sstr]; no shift term when Zs is
-// null).  Stopped runs are skipped.
+// null).  Stopped runs are skipped.  staged: w.Vg already holds X in the
+// sorted FP32 layout (written by the normalisation that produced X).
 int block_product(mqh_problem* p, int nz, int trans, const double* X, int64_t xstr, const double* shift,
-                  int64_t sstr, const double* Zs, int64_t zstr, double* Y, const GkbState* st, bool timed) {
+                  int64_t sstr, const double* Zs, int64_t zstr, double* Y, const GkbState* st, bool timed,
+                  bool staged = false) {
     MultiWs& w = p->mw;
     hipStream_t s = p->stream;
     if (p->mode != MQH_OP_MATFREE_FP32 || nz < 2) {
@@ -572,8 +570,10 @@ int block_product(mqh_problem* p, int nz, int trans, const double* X, int64_t xs
         }
         return MQH_OK;
     }
-    launch_gather_block(X, xstr, nz, p->perm, p->n, st, w.Vg, s);
-    LAUNCHCHK("block gather");
+    if (!staged) {
+        launch_gather_block(X, xstr, nz, p->perm, p->n, st, w.Vg, s);
+        LAUNCHCHK("block gather");
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         for (int q = 0; q < 2; ++q) {
@@ -604,27 +604,32 @@ int run_gkb_multi(mqh_problem* p, int nz, int32_t ell, int32_t reorth, bool time
     const int nbu = update_blocks(n);
     launch_init_state_b(w.st, ell, w.alpha, w.beta, nz, Bz{w.vstr, w.vstr}, s);
     LAUNCHCHK("init state");
+    // block products read their operand from w.Vg, which the normalisation
+    // writes (columns past nz stay zero)
+    const bool blk = p->mode == MQH_OP_MATFREE_FP32 && nz >= 2;
+    const int32_t* ip = blk ? p->iperm : nullptr;
+    float* vg = blk ? w.Vg : nullptr;
+    if (blk) launch_fill_f32(w.Vg, n * kBlkRhs, 0.f, s);
     launch_sumsq_partial_b(w.X, n, w.npart, nbq, w.st, nz, Bz{ldn, w.nstr}, s);
-    launch_norm_finalize_b(w.npart, nbq, 0, 0, n, w.alpha, w.beta, w.st, nz, Bz{w.nstr, w.vstr, w.vstr}, s);
-    launch_scale_b(w.X, n, w.beta, w.W, w.st, nz, Bz{ldn, w.vstr, w.bstr}, s);
+    launch_finalize_scale_b(w.npart, nbq, 0, 0, n, w.alpha, w.beta, w.st, w.X, w.W, ip, vg, nz,
+                            Bz{w.nstr, w.vstr, ldn, w.bstr}, s);
     LAUNCHCHK("initial normalisation");
     auto orthonormalize = [&](const double* V, int32_t m, int kind, int32_t j, double* dst) -> int {
         int nparts;
         if (reorth && m > 0) {
-            const Bz ub{w.bstr, w.vstr, ldn, w.nstr};
-            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.cvec, w.st, nz, w.bstr, ldn, w.gstr, w.vstr, s);
-            launch_update_b(V, ldn, n, m, w.cvec, w.Y, nullptr, w.st, nz, ub, s);
-            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.cvec, w.st, nz, w.bstr, ldn, w.gstr, w.vstr, s);
-            launch_update_b(V, ldn, n, m, w.cvec, w.Y, w.npart, w.st, nz, ub, s);
+            const Bz gb{w.bstr, ldn, w.gstr, 0};
+            const Bz ub{w.bstr, w.gstr, ldn, w.nstr};
+            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.st, nz, gb, s);
+            launch_update_b(V, ldn, n, m, w.gpart, w.Y, nullptr, w.st, nz, ub, s);
+            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.st, nz, gb, s);
+            launch_update_b(V, ldn, n, m, w.gpart, w.Y, w.npart, w.st, nz, ub, s);
             nparts = nbu;
         } else {
             launch_sumsq_partial_b(w.Y, n, w.npart, nbq, w.st, nz, Bz{ldn, w.nstr}, s);
             nparts = nbq;
         }
-        launch_norm_finalize_b(w.npart, nparts, kind, j, n, w.alpha, w.beta, w.st, nz, Bz{w.nstr, w.vstr, w.vstr},
-                               s);
-        const double* div = kind == 1 ? w.alpha + j : w.beta + j + 1;
-        launch_scale_b(w.Y, n, div, dst, w.st, nz, Bz{ldn, w.vstr, w.bstr}, s);
+        launch_finalize_scale_b(w.npart, nparts, kind, j, n, w.alpha, w.beta, w.st, w.Y, dst, ip, vg, nz,
+                                Bz{w.nstr, w.vstr, ldn, w.bstr}, s);
         LAUNCHCHK("reorthogonalisation / normalisation");
         return MQH_OK;
     };
@@ -634,11 +639,11 @@ int run_gkb_multi(mqh_problem* p, int nz, int32_t ell, int32_t reorth, bool time
         double* Zj = w.Z + (int64_t)j * ldn;
         // r = A^T w_j - beta_j z_{j-1}
         if ((rc = block_product(p, nz, 1, Wj, w.bstr, w.beta + j, w.vstr,
-                                j > 0 ? w.Z + (int64_t)(j - 1) * ldn : nullptr, w.bstr, w.Y, w.st, timed)))
+                                j > 0 ? w.Z + (int64_t)(j - 1) * ldn : nullptr, w.bstr, w.Y, w.st, timed, blk)))
             return rc;
         if ((rc = orthonormalize(w.Z, j, 1, j, Zj))) return rc;
         // p = A z_j - alpha_j w_j
-        if ((rc = block_product(p, nz, 0, Zj, w.bstr, w.alpha + j, w.vstr, Wj, w.bstr, w.Y, w.st, timed)))
+        if ((rc = block_product(p, nz, 0, Zj, w.bstr, w.alpha + j, w.vstr, Wj, w.bstr, w.Y, w.st, timed, blk)))
             return rc;
         if ((rc = orthonormalize(w.W, j + 1, 2, j, w.W + (int64_t)(j + 1) * ldn))) return rc;
     }
@@ -727,6 +732,7 @@ int mqh_problem_destroy(mqh_problem* p) {
     dfree(p->pout2);
     dfree(p->XS);
     dfree(p->perm);
+    dfree(p->iperm);
     dfree(p->frames);
     dfree(p->cf);
     dfree(p->A);
@@ -740,7 +746,6 @@ int mqh_problem_destroy(mqh_problem* p) {
     dfree(p->beta);
     dfree(p->st);
     dfree(p->gpart);
-    dfree(p->cvec);
     dfree(p->npart);
     dfree(p->sv);
     dfree(p->ftil);
@@ -854,10 +859,15 @@ int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, 
         sorted_layout(r64, n, n_int, perm, rs, frames);
         if ((rc = dalloc(&p->XS, (size_t)n))) return bail(rc);
         if ((rc = dalloc(&p->perm, (size_t)n))) return bail(rc);
+        if ((rc = dalloc(&p->iperm, (size_t)n))) return bail(rc);
+        std::vector<int32_t> iperm((size_t)n);
+        for (int64_t q = 0; q < n; ++q) iperm[(size_t)perm[(size_t)q]] = (int32_t)q;
         if ((rc = dalloc(&p->frames, frames.size()))) return bail(rc);
         if ((rc = dalloc(&p->cf, (size_t)n))) return bail(rc);
         if ((e = hipMemcpyAsync(p->XS, rs.data(), (size_t)n * sizeof(float4), hipMemcpyHostToDevice, p->stream)) ||
             (e = hipMemcpyAsync(p->perm, perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice,
+                                p->stream)) ||
+            (e = hipMemcpyAsync(p->iperm, iperm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice,
                                 p->stream)) ||
             (e = hipMemcpyAsync(p->frames, frames.data(), frames.size() * sizeof(float4), hipMemcpyHostToDevice,
                                 p->stream)) ||
@@ -1280,6 +1290,48 @@ int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     if (broke) return MQH_WBREAKDOWN;
     if (edge) return MQH_WEDGE;
     return MQH_OK;
+}
+
+int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* opts, int32_t workers) {
+    if (items == nullptr || count < 1) return fail(MQH_EINVAL, "need items and count >= 1");
+    if (opts == nullptr) return fail(MQH_EINVAL, "NULL opts");
+    for (int32_t k = 0; k < count; ++k) {
+        items[k].status = MQH_EINVAL;
+        if (items[k].p == nullptr) return fail(MQH_EINVAL, "NULL problem in the sweep");
+        for (int32_t q = 0; q < k; ++q)
+            if (items[q].p == items[k].p) return fail(MQH_EINVAL, "a problem appears twice in the sweep");
+    }
+    if (workers < 1) workers = 1;
+    if (workers > count) workers = count;
+    std::atomic<int32_t> next{0};
+    std::mutex mu;
+    std::string first_error;
+    int first_code = MQH_OK;
+    auto work = [&]() {
+        for (;;) {
+            const int32_t k = next.fetch_add(1);
+            if (k >= count) return;
+            mqh_sweep_item& it = items[k];
+            it.status = mqh_solve_multi(it.p, it.F, it.ldf, it.nrhs, opts, it.coef, it.ldc, it.info);
+            if (it.status < 0) {
+                std::lock_guard<std::mutex> lock(mu);
+                if (first_code == MQH_OK) {
+                    first_code = it.status;
+                    first_error = g_last_error;
+                }
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    pool.reserve((size_t)workers - 1);
+    for (int32_t t = 1; t < workers; ++t) pool.emplace_back(work);
+    work();
+    for (auto& t : pool) t.join();
+    if (first_code != MQH_OK) return fail(first_code, first_error);
+    int worst = MQH_OK;
+    for (int32_t k = 0; k < count; ++k)
+        if (items[k].status == MQH_WBREAKDOWN || (items[k].status == MQH_WEDGE && worst == MQH_OK)) worst = items[k].status;
+    return worst;
 }
 
 int mqh_eval(mqh_problem* p, const double* coef, const double* x_eval, int64_t m, double* u, uint32_t flags) {

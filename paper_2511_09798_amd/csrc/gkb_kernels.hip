@@ -63,68 +63,87 @@ __global__ __launch_bounds__(kBlock) void k_sumsq_partial(const double* __restri
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// Sums the partials, takes the square root and applies the breakdown test
-// (kind 0: beta_1 = ||f||; kind 1: alpha_{j+1}; kind 2: beta_{j+2}, 0-based j).
-// The threshold is n * DBL_EPSILON * (running max of alpha, beta_{>=2}).
-__global__ __launch_bounds__(kBlock) void k_norm_finalize(const double* __restrict__ partial, int nparts, int kind,
-                                                          int32_t j, int64_t n, double* __restrict__ alpha,
-                                                          double* __restrict__ beta, GkbState* __restrict__ st,
-                                                          Bz bz) {
+// Norm of a Krylov vector from its partial sums of squares, breakdown test
+// and normalisation dst = x / norm (kind 0: beta_1 = ||f||; kind 1:
+// alpha_{j+1}; kind 2: beta_{j+2}, 0-based j).  The threshold is
+// n * DBL_EPSILON * (running max of alpha, beta_{>=2}).  Every block sums the
+// partials in the same order (thread t takes t, t + 256, ..., then the block
+// reduction), so all blocks hold the same norm and take the same decision;
+// block 0 records it.  Block 0 may raise the running scale to this norm while
+// other blocks read it, but a norm above the old threshold is also above the
+// raised one (n DBL_EPSILON < 1), and after a breakdown the scale is left as
+// it was, so the decision does not depend on that order.  With Vg, the
+// normalised vector also goes, in FP32, to column z of the sorted
+// block-product operand, Vg[iperm[i]][z] (zeros for a stopped run).
+__global__ __launch_bounds__(kBlock) void k_finalize_scale(const double* __restrict__ partial, int nparts, int kind,
+                                                           int32_t j, int64_t n, double* __restrict__ alpha,
+                                                           double* __restrict__ beta, GkbState* __restrict__ st,
+                                                           const double* __restrict__ x, double* __restrict__ dst,
+                                                           const int32_t* __restrict__ iperm, float* __restrict__ Vg,
+                                                           Bz bz) {
     __shared__ double lds[kBlock / kWave];
-    const int64_t z = blockIdx.x;  // batch: partial + z bz.a, alpha + z bz.b, beta + z bz.c, state z
+    __shared__ int s_stopped;
+    const int64_t z = blockIdx.y;  // batch: partial + z bz.a, alpha, beta + z bz.b, x + z bz.c, dst + z bz.d, state z
     partial += z * bz.a;
     alpha += z * bz.b;
-    beta += z * bz.c;
+    beta += z * bz.b;
+    x += z * bz.c;
+    dst += z * bz.d;
     st += z;
-    if (st->stopped) return;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += kBlock) s += partial[i];
-    s = block_sum<kBlock>(s, lds);
-    if (threadIdx.x != 0) return;
-    const double nrm = sqrt(s);
-    if (kind == 0) {
-        beta[0] = nrm;
-        if (!(nrm > 0.0)) {
-            st->stopped = 1;
-            st->ell_done = 0;
-            st->flag = 2;
-        }
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (threadIdx.x == 0) s_stopped = st->stopped;
+    __syncthreads();
+    if (s_stopped) {  // block-uniform
+        if (Vg != nullptr && i < n) Vg[(int64_t)iperm[i] * kBlkRhs + z] = 0.f;
         return;
     }
-    const double tau = (double)n * DBL_EPSILON * st->scale;
-    if (kind == 1) {
-        if (!(nrm > tau)) {
-            st->stopped = 1;
-            st->ell_done = j;
-            st->flag = 1;
-            return;
-        }
-        alpha[j] = nrm;
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nparts; q += kBlock) s += partial[q];
+    s = block_sum<kBlock>(s, lds);
+    const double nrm = sqrt(s);
+    bool ok;
+    if (kind == 0) {
+        ok = nrm > 0.0;
     } else {
-        if (!(nrm > tau)) {
-            st->stopped = 1;
-            st->ell_done = j + 1;
-            st->flag = 2;
-            beta[j + 1] = 0.0;
-            return;
-        }
-        beta[j + 1] = nrm;
+        const double tau = (double)n * DBL_EPSILON * st->scale;
+        ok = nrm > tau;
     }
-    if (nrm > st->scale) st->scale = nrm;
-}
-
-// dst = x / *div  (normalisation of a Krylov vector).
-__global__ __launch_bounds__(kBlock) void k_scale(const double* __restrict__ x, int64_t n,
-                                                  const double* __restrict__ div, double* __restrict__ dst,
-                                                  const GkbState* __restrict__ st, Bz bz) {
-    const int64_t z = blockIdx.z;  // batch: x + z bz.a, div + z bz.b, dst + z bz.c, state z
-    x += z * bz.a;
-    div += z * bz.b;
-    dst += z * bz.c;
-    if (st != nullptr) st += z;
-    if (st != nullptr && st->stopped) return;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) dst[i] = x[i] / *div;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (kind == 0) {
+            beta[0] = nrm;
+            if (!ok) {
+                st->stopped = 1;
+                st->ell_done = 0;
+                st->flag = 2;
+            }
+        } else if (kind == 1) {
+            if (!ok) {
+                st->stopped = 1;
+                st->ell_done = j;
+                st->flag = 1;
+            } else {
+                alpha[j] = nrm;
+            }
+        } else {
+            if (!ok) {
+                st->stopped = 1;
+                st->ell_done = j + 1;
+                st->flag = 2;
+                beta[j + 1] = 0.0;
+            } else {
+                beta[j + 1] = nrm;
+            }
+        }
+        if (ok && kind != 0 && nrm > st->scale) st->scale = nrm;
+    }
+    if (i >= n) return;
+    if (!ok) {
+        if (Vg != nullptr) Vg[(int64_t)iperm[i] * kBlkRhs + z] = 0.f;
+        return;
+    }
+    const double d = x[i] / nrm;
+    dst[i] = d;
+    if (Vg != nullptr) Vg[(int64_t)iperm[i] * kBlkRhs + z] = (float)d;
 }
 
 // ---------------------------------------------------------------------------
@@ -185,38 +204,34 @@ __global__ __launch_bounds__(kBlock) void k_gemvt_partial(const double* __restri
     }
 }
 
-// c[k] = sum_b partial[b * m + k]: one wave per column, lanes take b = lane,
-// lane + 64, ... and the wave reduction combines them in a fixed order.
-__global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restrict__ partial, int nb, int32_t m,
-                                                         double* __restrict__ c,
-                                                         const GkbState* __restrict__ st, Bz bz) {
-    const int64_t z = blockIdx.y;  // batch: partial + z bz.a, c + z bz.b, state z
-    partial += z * bz.a;
-    c += z * bz.b;
-    if (st != nullptr) st += z;
-    if (st != nullptr && st->stopped) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int k = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (k >= m) return;  // wave-uniform; no barriers
-    double s = 0.0;
-    for (int b = lane; b < nb; b += kWave) s += partial[(int64_t)b * m + k];
-    s = wave_sum(s);
-    if (lane == 0) c[k] = s;
-}
-
-// x_i -= sum_k V[k][i] c_k; optionally partial[b] = sum over the block of the updated x_i^2.
+// x_i -= sum_k V[k][i] c_k with c_k = sum_b partial[b * m + k], the column
+// sums of the k_gemvt_partial partials (nb row blocks).  Every block forms c
+// in LDS itself, one wave per column (lanes take b = lane, lane + 64, ...,
+// then the wave reduction: one fixed order).  Optionally partial[b] = sum
+// over the block of the updated x_i^2.
 __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V, int64_t ldn, int64_t n, int32_t m,
-                                                   const double* __restrict__ c, double* __restrict__ x,
-                                                   double* __restrict__ sumsq_partial,
+                                                   const double* __restrict__ partial, int nb,
+                                                   double* __restrict__ x, double* __restrict__ sumsq_partial,
                                                    const GkbState* __restrict__ st, Bz bz) {
     __shared__ double lds[kBlock / kWave];
-    const int64_t z = blockIdx.z;  // batch: V + z bz.a, c + z bz.b, x + z bz.c, partial + z bz.d, state z
+    __shared__ double c[kMaxEll];
+    const int64_t z = blockIdx.z;  // batch: V + z bz.a, partial + z bz.b, x + z bz.c, sumsq + z bz.d, state z
     V += z * bz.a;
-    c += z * bz.b;
+    partial += z * bz.b;
     x += z * bz.c;
     if (sumsq_partial != nullptr) sumsq_partial += z * bz.d;
     if (st != nullptr) st += z;
-    if (st != nullptr && st->stopped) return;
+    if (st != nullptr && st->stopped) return;  // uniform over the grid
+    {
+        const int lane = threadIdx.x & (kWave - 1);
+        for (int k = threadIdx.x / kWave; k < m; k += kBlock / kWave) {
+            double sk = 0.0;
+            for (int b = lane; b < nb; b += kWave) sk += partial[(int64_t)b * m + k];
+            sk = wave_sum(sk);
+            if (lane == 0) c[k] = sk;
+        }
+    }
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double xi = 0.0;
     if (i < n) {
@@ -280,6 +295,16 @@ void launch_init_state_b(GkbState* st, int32_t ell, double* alpha, double* beta,
 
 void launch_cap_ell(GkbState* st, int32_t ell, hipStream_t s) { k_cap_ell<<<1, 64, 0, s>>>(st, ell); }
 
+__global__ void k_fill_f32(float* __restrict__ x, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_f32<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, v);
+}
+
 void launch_fill(double* x, int64_t n, double v, hipStream_t s) {
     if (n <= 0) return;
     k_fill<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, v);
@@ -299,50 +324,40 @@ void launch_sumsq_partial_b(const double* x, int64_t n, double* partial, int nb,
     k_sumsq_partial<<<dim3(nb, 1, nz), kBlock, 0, s>>>(x, n, partial, st, bz);
 }
 
-void launch_norm_finalize(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
-                          double* beta, GkbState* st, hipStream_t s) {
-    launch_norm_finalize_b(partial, nparts, kind, j, n, alpha, beta, st, 1, Bz{}, s);
+void launch_finalize_scale(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
+                           double* beta, GkbState* st, const double* x, double* dst, hipStream_t s) {
+    launch_finalize_scale_b(partial, nparts, kind, j, n, alpha, beta, st, x, dst, nullptr, nullptr, 1, Bz{}, s);
 }
 
-void launch_norm_finalize_b(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
-                            double* beta, GkbState* st, int nz, Bz bz, hipStream_t s) {
-    k_norm_finalize<<<nz, kBlock, 0, s>>>(partial, nparts, kind, j, n, alpha, beta, st, bz);
-}
-
-void launch_scale(const double* x, int64_t n, const double* div, double* dst, const GkbState* st, hipStream_t s) {
-    launch_scale_b(x, n, div, dst, st, 1, Bz{}, s);
-}
-
-void launch_scale_b(const double* x, int64_t n, const double* div, double* dst, const GkbState* st, int nz, Bz bz,
-                    hipStream_t s) {
-    k_scale<<<dim3((unsigned)((n + kBlock - 1) / kBlock), 1, nz), kBlock, 0, s>>>(x, n, div, dst, st, bz);
+void launch_finalize_scale_b(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
+                             double* beta, GkbState* st, const double* x, double* dst, const int32_t* iperm,
+                             float* Vg, int nz, Bz bz, hipStream_t s) {
+    k_finalize_scale<<<dim3((unsigned)((n + kBlock - 1) / kBlock), nz), kBlock, 0, s>>>(
+        partial, nparts, kind, j, n, alpha, beta, st, x, dst, iperm, Vg, bz);
 }
 
 int gemvt_blocks(int64_t n) { return (int)((n + kGtRows - 1) / kGtRows); }
 
-void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
+void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial,
                   const GkbState* st, hipStream_t s) {
-    launch_gemvt_b(V, ldn, n, m, x, partial, c, st, 1, 0, 0, 0, 0, s);
+    launch_gemvt_b(V, ldn, n, m, x, partial, st, 1, Bz{}, s);
 }
 
-void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
-                    const GkbState* st, int nz, int64_t sV, int64_t sx, int64_t sp, int64_t sc, hipStream_t s) {
-    const int nb = gemvt_blocks(n);
-    k_gemvt_partial<<<dim3(nb, (m + kGtCols - 1) / kGtCols, nz), kBlock, 0, s>>>(V, ldn, n, m, x, partial, st,
-                                                                                 Bz{sV, sx, sp, 0});
-    k_gemvt_reduce<<<dim3((m + kBlock / kWave - 1) / (kBlock / kWave), nz), kBlock, 0, s>>>(partial, nb, m, c, st,
-                                                                                           Bz{sp, sc, 0, 0});
+void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial,
+                    const GkbState* st, int nz, Bz bz, hipStream_t s) {
+    k_gemvt_partial<<<dim3(gemvt_blocks(n), (m + kGtCols - 1) / kGtCols, nz), kBlock, 0, s>>>(V, ldn, n, m, x,
+                                                                                             partial, st, bz);
 }
 
-void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
+void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* partial, double* x,
                    double* sumsq_partial, const GkbState* st, hipStream_t s) {
-    launch_update_b(V, ldn, n, m, c, x, sumsq_partial, st, 1, Bz{}, s);
+    launch_update_b(V, ldn, n, m, partial, x, sumsq_partial, st, 1, Bz{}, s);
 }
 
-void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
+void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* partial, double* x,
                      double* sumsq_partial, const GkbState* st, int nz, Bz bz, hipStream_t s) {
-    k_update<<<dim3((unsigned)((n + kBlock - 1) / kBlock), 1, nz), kBlock, 0, s>>>(V, ldn, n, m, c, x, sumsq_partial,
-                                                                                 st, bz);
+    k_update<<<dim3((unsigned)((n + kBlock - 1) / kBlock), 1, nz), kBlock, 0, s>>>(
+        V, ldn, n, m, partial, gemvt_blocks(n), x, sumsq_partial, st, bz);
 }
 
 int update_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }

@@ -397,6 +397,37 @@ __global__ __launch_bounds__(kBlock) void k_gather_coef(const double* __restrict
 
 constexpr int kBlkVs = kBlkRhs + 4;  // LDS row of the staged right-hand sides (padded against bank conflicts)
 
+// Entries of the lane's 4 loop nodes x kMfmFt fixed nodes from their
+// squared distances t (unweighted; INTERIOR selects the formula).
+template <bool INTERIOR>
+__device__ __forceinline__ void block_entries(const v4f (&t)[kMfmFt], const EntryConst& c, float (&e)[kMfmFt][4]) {
+#pragma unroll
+    for (int f = 0; f < kMfmFt; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (INTERIOR) {
+                const float sv = __builtin_amdgcn_rsqf(t[f][r]);
+                e[f][r] = fmaf(c.e2f, sv * sv, fmaf(c.k2f, t[f][r], c.e2x2f)) * sv;
+            } else {
+                e[f][r] = __builtin_amdgcn_sqrtf(t[f][r]);
+            }
+        }
+}
+
+// Squared distances of tile u (16 staged loop nodes) to the lane's fixed nodes.
+__device__ __forceinline__ void block_tdist(const v4u* __restrict__ lds_a, int u, int jj, int g,
+                                            const v4u (&bf)[kMfmFt], const v4f (&Cf)[kMfmFt], v4f (&t)[kMfmFt]) {
+    const v8bf ak = __builtin_bit_cast(v8bf, lds_a[(u * 16 + jj) * 4 + g]);
+#pragma unroll
+    for (int f = 0; f < kMfmFt; ++f)
+        t[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ak, __builtin_bit_cast(v8bf, bf[f]), Cf[f], 0, 0, 0);
+}
+
+// One slice [j0, j1) of loop nodes (block-uniform; contains barriers).  The
+// chunk's 16 tiles run as a three-stage pipeline, fully unrolled: the
+// squared distances of tile u + 2, the entries of tile u + 1 and the
+// contraction of tile u are in flight together, so no stage waits on the
+// one before it.
 template <bool INTERIOR>
 __device__ __forceinline__ void mfb_span(const float4* __restrict__ XS, const float* __restrict__ Vg, int64_t j0,
                                          int64_t j1, const float4& fr, const EntryConst& c,
@@ -404,7 +435,7 @@ __device__ __forceinline__ void mfb_span(const float4* __restrict__ XS, const fl
                                          double (&acc)[kMfmFt][4], v4u* __restrict__ lds_a,
                                          float* __restrict__ lds_v) {
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15;
-    const float k2 = c.k2f, e2x2 = c.e2x2f, e2 = c.e2f;
+    constexpr int kTiles = kMfmChunk / 16;
     for (int64_t t0 = j0; t0 < j1; t0 += kMfmChunk) {
         const int64_t j = t0 + threadIdx.x;
         float dx = 0.f, dy = 0.f, dz = 0.f;
@@ -442,42 +473,33 @@ __device__ __forceinline__ void mfb_span(const float4* __restrict__ XS, const fl
         v4f d2[kMfmFt];
 #pragma unroll
         for (int f = 0; f < kMfmFt; ++f) d2[f] = v4f{0.f, 0.f, 0.f, 0.f};
-        v4f t[kMfmFt];
-        {
-            const v8bf ak = __builtin_bit_cast(v8bf, lds_a[jj * 4 + g]);
+        v4f tc[kMfmFt], tn[kMfmFt];
+        float ec[kMfmFt][4];
+        block_tdist(lds_a, 0, jj, g, bf, Cf, tc);
+        block_tdist(lds_a, 1, jj, g, bf, Cf, tn);
+        block_entries<INTERIOR>(tc, c, ec);
 #pragma unroll
-            for (int f = 0; f < kMfmFt; ++f)
-                t[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ak, __builtin_bit_cast(v8bf, bf[f]), Cf[f], 0, 0, 0);
-        }
-#pragma unroll 2
-        for (int u = 0; u < kMfmChunk / 16; ++u) {
-            v4f tn[kMfmFt];
-            if (u + 1 < kMfmChunk / 16) {
-                const v8bf an = __builtin_bit_cast(v8bf, lds_a[((u + 1) * 16 + jj) * 4 + g]);
-#pragma unroll
-                for (int f = 0; f < kMfmFt; ++f)
-                    tn[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(an, __builtin_bit_cast(v8bf, bf[f]), Cf[f], 0, 0, 0);
-            }
+        for (int u = 0; u < kTiles; ++u) {
             float vb[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) vb[r] = lds_v[(u * 16 + 4 * g + r) * kBlkVs + jj];
+            v4f tnn[kMfmFt];
+            if (u + 2 < kTiles) block_tdist(lds_a, u + 2, jj, g, bf, Cf, tnn);
+            float en[kMfmFt][4];
+            if (u + 1 < kTiles) block_entries<INTERIOR>(tn, c, en);
+            // the entries enter the A operand as they are: K = loop nodes r, 4 + r, 8 + r, 12 + r
 #pragma unroll
-            for (int f = 0; f < kMfmFt; ++f) {
+            for (int f = 0; f < kMfmFt; ++f)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float e;
-                    if (INTERIOR) {
-                        const float sv = __builtin_amdgcn_rsqf(t[f][r]);
-                        e = fmaf(e2, sv * sv, fmaf(k2, t[f][r], e2x2)) * sv;
-                    } else {
-                        e = __builtin_amdgcn_sqrtf(t[f][r]);
-                    }
-                    d2[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(e, vb[r], d2[f], 0, 0, 0);
+                for (int r = 0; r < 4; ++r)
+                    d2[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(ec[f][r], vb[r], d2[f], 0, 0, 0);
+            if (u + 1 < kTiles) {
+#pragma unroll
+                for (int f = 0; f < kMfmFt; ++f) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) ec[f][r] = en[f][r];
+                    tn[f] = tnn[f];
                 }
-            }
-            if (u + 1 < kMfmChunk / 16) {
-#pragma unroll
-                for (int f = 0; f < kMfmFt; ++f) t[f] = tn[f];
             }
         }
 #pragma unroll

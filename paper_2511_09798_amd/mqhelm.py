@@ -70,6 +70,12 @@ class mqh_solve_info(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32), ("t_ms", ctypes.c_double * 8)]
 
 
+class mqh_sweep_item(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_void_p), ("F", ctypes.c_void_p), ("ldf", ctypes.c_int64), ("nrhs", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("coef", ctypes.c_void_p), ("ldc", ctypes.c_int64),
+                ("info", ctypes.c_void_p)]
+
+
 class mqh_predictor(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("in_mean", ctypes.c_float * 24), ("in_std", ctypes.c_float * 24),
                 ("out_mean", ctypes.c_float * 2), ("out_std", ctypes.c_float * 2), ("h", ctypes.c_double),
@@ -112,6 +118,7 @@ _SIGNATURES = {
     "mqh_gkb_multi": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _u32]),
     "mqh_solve_multi": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(mqh_solve_opts), _vp, _i64,
                                        ctypes.POINTER(mqh_solve_info)]),
+    "mqh_solve_sweep": (ctypes.c_int, [ctypes.POINTER(mqh_sweep_item), _i32, ctypes.POINTER(mqh_solve_opts), _i32]),
     "mqh_eval": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _u32]),
     "mqh_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _u32]),
     "mqh_mlp_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _u32]),
@@ -436,6 +443,41 @@ def mqh_solve_multi(h, F, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQ
                             get("lambda_chosen", np.float64), get("crit", np.float64),
                             get("resid_norm", np.float64), get("sol_norm", np.float64), get("flags", np.uint32),
                             np.array([list(i.t_ms) for i in infos], dtype=np.float64))
+
+
+def mqh_solve_sweep(problems, Fs, ell: int, workers: int = 2, coefs=None, method: int = MQH_METHOD_HKT,
+                    rule: int = MQH_RULE_GCV, k_trunc: int = 0, lambda_fixed: float = 0.0, n_grid: int = 200,
+                    reorth: int = 1, time_products: bool = False, gcv_weight: float = 1.0):
+    """Solve every problem of a sweep (Problem objects, each with its own right-hand sides Fs[i],
+    nrhs_i x n_i) side by side on `workers` host threads; returns a list of MultiSolveOutput."""
+    if len(problems) != len(Fs) or not problems:
+        raise ValueError("one F per problem")
+    count = len(problems)
+    if coefs is None:
+        coefs = [_empty_like_kind(F, tuple(F.shape)) for F in Fs]
+    fl = _flags(*Fs, *coefs)
+    infos = [(mqh_solve_info * int(F.shape[0]))() for F in Fs]
+    items = (mqh_sweep_item * count)()
+    for i, (pr, F, C) in enumerate(zip(problems, Fs, coefs)):
+        if F.shape[1] != pr.n or tuple(C.shape) != tuple(F.shape):
+            raise ValueError("F and coef must be nrhs x n of their problem")
+        items[i] = mqh_sweep_item(p=pr.h.value, F=_ptr(F)[0].value, ldf=pr.n, nrhs=int(F.shape[0]), status=0,
+                                  coef=_ptr(C)[0].value, ldc=pr.n, info=ctypes.cast(infos[i], ctypes.c_void_p).value)
+    opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=int(method), rule=int(rule),
+                          k_trunc=int(k_trunc), n_grid=int(n_grid), lambda_fixed=float(lambda_fixed),
+                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), reserved=0,
+                          gcv_weight=float(gcv_weight))
+    _check(lib.mqh_solve_sweep(items, count, ctypes.byref(opts), int(workers)), "mqh_solve_sweep")
+    outs = []
+    for i in range(count):
+        inf = infos[i]
+        get = lambda f, dt: np.array([getattr(x, f) for x in inf], dtype=dt)  # noqa: E731
+        outs.append(MultiSolveOutput(coefs[i], int(items[i].status), get("ell_done", np.int32),
+                                     get("k_chosen", np.int32), get("lambda_chosen", np.float64),
+                                     get("crit", np.float64), get("resid_norm", np.float64),
+                                     get("sol_norm", np.float64), get("flags", np.uint32),
+                                     np.array([list(x.t_ms) for x in inf], dtype=np.float64)))
+    return outs
 
 
 def mqh_eval(h, coef, x_eval, u=None):

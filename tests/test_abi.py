@@ -66,15 +66,19 @@ def test_struct_layouts(mq, tmp_path):
         '  printf("%zu %zu %zu %zu\\n", sizeof(mqh_predictor), offsetof(mqh_predictor, h),\n'
         '         offsetof(mqh_predictor, ell_step), offsetof(mqh_predictor, judge_ratio));\n'
         '  printf("%zu %zu\\n", sizeof(mqh_learned_info), offsetof(mqh_learned_info, out));\n'
+        '  printf("%zu %zu %zu %zu\\n", sizeof(mqh_sweep_item), offsetof(mqh_sweep_item, status),\n'
+        '         offsetof(mqh_sweep_item, coef), offsetof(mqh_sweep_item, info));\n'
         '  return 0;\n}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", INCLUDE, str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     vals = [int(v) for v in out]
     O, F, P, L = mq.mqh_solve_opts, mq.mqh_solve_info, mq.mqh_predictor, mq.mqh_learned_info
+    S = mq.mqh_sweep_item
     assert vals == [ctypes.sizeof(O), O.lambda_fixed.offset, O.flags.offset, O.gcv_weight.offset, ctypes.sizeof(F),
                     F.flags.offset, F.t_ms.offset, ctypes.sizeof(P), P.h.offset, P.ell_step.offset,
-                    P.judge_ratio.offset, ctypes.sizeof(L), L.out.offset]
+                    P.judge_ratio.offset, ctypes.sizeof(L), L.out.offset, ctypes.sizeof(S), S.status.offset,
+                    S.coef.offset, S.info.offset]
 
 
 def test_status_strings(mq):
@@ -112,6 +116,10 @@ def test_multi_entry_points_reject_null_problem(mq):
     assert L.mqh_gkb_multi(None, fp, 8, 2, 3, 1, None, None, None, None, None, 0) == mq.MQH_EINVAL
     assert L.mqh_solve_multi(None, fp, 8, 2, ctypes.byref(opts), fp, 8, None) == mq.MQH_EINVAL
     assert "NULL problem" in mq.mqh_last_error()
+    items = (mq.mqh_sweep_item * 2)()
+    assert L.mqh_solve_sweep(items, 2, ctypes.byref(opts), 2) == mq.MQH_EINVAL
+    assert "NULL problem" in mq.mqh_last_error()
+    assert L.mqh_solve_sweep(items, 0, ctypes.byref(opts), 2) == mq.MQH_EINVAL
 
 
 def test_invalid_projected_arguments(mq):

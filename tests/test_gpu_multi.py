@@ -258,3 +258,33 @@ def test_multi_invalid_arguments(mq):
         # the problem is still usable after rejected calls
         r = pr.gkb_multi(F, 5)
         assert np.all(r["ell_done"] == 5)
+
+
+# ---------------------------------------------------------------------------
+# sweeps of independent problems run side by side
+# ---------------------------------------------------------------------------
+
+def test_solve_sweep_matches_one_by_one(mq):
+    # each problem on its own stream and host thread: results bit-identical to
+    # solving the problems one at a time
+    probs = [I.multi_cube(300 + 97 * k, 120 + 31 * k, 2.0 + 3.0 * k, 1.0 + 0.6 * k, 3 + (k % 3) * 7, 25, seed=50 + k)
+             for k in range(5)]
+    handles = []
+    try:
+        for p in probs:
+            say("sweep create", p.name)
+            handles.append(mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, "matfree_fp32"))
+        say("sweep one by one")
+        ref = [h.solve_multi(p.F, p.ell) for h, p in zip(handles, probs)]
+        for workers in (1, 3):
+            say("sweep workers", workers)
+            outs = mq.mqh_solve_sweep(handles, [p.F for p in probs], 25, workers=workers)
+            for k, (o, r) in enumerate(zip(outs, ref)):
+                assert o.status == r.status
+                assert np.array_equal(o.coef, r.coef), (workers, k)
+                assert np.array_equal(o.lam, r.lam) and np.array_equal(o.ell_done, r.ell_done)
+        with pytest.raises(mq.MQHError):
+            mq.mqh_solve_sweep([handles[0], handles[0]], [probs[0].F, probs[0].F], 25)
+    finally:
+        for h in handles:
+            h.close()
