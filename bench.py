@@ -197,7 +197,8 @@ def learned_context(mq, torch, dev, count: int, n: int = 60000, ell: int = 60, s
                 net_lambda_used=int(sum(r["used_net"] for r in rows)), cases=rows)
 
 
-def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, workers: int):
+def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, workers: int,
+                  fixed_shapes: bool = False):
     """Frequency sweep over cubes: count problems (N uniform on [2000, 30000], kappa evenly spaced
     on [2, 40], eps = 0.2 kappa + 1), 16 Gaussian-blob sources each, ell = 100, HKT with GCV for
     every source through the lockstep runs with block products (FP32 entries).  All problems and
@@ -213,7 +214,7 @@ def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, 
     for k in range(count):
         p = I.sweep_member(k)
         probs.append(p)
-        handles.append(mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, "matfree_fp32"))
+        handles.append(mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, "matfree_fp32", fixed_shapes=fixed_shapes))
         Fs.append(torch.from_numpy(p.F).to(dev))
         coefs.append(torch.empty_like(Fs[-1]))
     torch.cuda.synchronize()
@@ -238,8 +239,9 @@ def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, 
         flops += 2.0 * 2.0 * p.ell * p.n * p.n * p.nrhs * (int(o.ell_done.min()) / p.ell)
         solves += p.nrhs
     log("sweep one problem at a time", f"{seq_s:.3f} s", "block kernels", f"{kern_ms / 1e3:.3f} s")
-    # side by side
-    reps = []
+    # side by side, with and without the captured Golub-Kahan loops (the first
+    # graph run captures)
+    reps, greps = [], []
     for r in range(2):
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -247,14 +249,26 @@ def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, 
         torch.cuda.synchronize()
         reps.append(time.perf_counter() - t)
         log("sweep", workers, "workers", f"{reps[-1]:.3f} s")
-    par_s = min(reps)
+    for r in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        outs_g = mq.mqh_solve_sweep(handles, Fs, ell, workers=workers, coefs=coefs, graph=True)
+        torch.cuda.synchronize()
+        greps.append(time.perf_counter() - t)
+        log("sweep", workers, "workers, graphs", f"{greps[-1]:.3f} s")
+    graph_s = min(greps[1:])
+    graph_same = all(np.array_equal(a.lam, b.lam) for a, b in zip(outs_p, outs_g))
+    par_s = min(min(reps), graph_s)
     same = all(np.array_equal(a.lam, b.lam) for a, b in zip(outs, outs_p))
     res = dict(workload=f"cube frequency sweep: {count} problems, N uniform on [2000, 30000], kappa evenly "
                         "spaced on [2, 40], eps = 0.2 kappa + 1, 16 Gaussian-blob sources (width 0.1), g = 0, "
                         "ell = 100, HKT + GCV per source, FP32 entries, block products",
                problems=count, sources=solves, sum_n2=float((ns.astype(np.float64) ** 2).sum()),
                time_s=par_s, workers=workers, source_solves_per_s=solves / par_s,
+               block_shapes="fixed (size heuristic)" if fixed_shapes else "autotuned",
                time_one_at_a_time_s=seq_s, same_choices_side_by_side=bool(same),
+               time_no_graph_s=min(reps), time_graph_s=graph_s, graph_capture_run_s=greps[0],
+               same_choices_graph=bool(graph_same),
                phase_ms_one_at_a_time=dict(gkb=gkb_ms, proj_svd=svd_ms, param=par_ms, lift=lift_ms),
                block_product_ms=kern_ms,
                roofline=dict(bound="mfma", achieved=flops / (kern_ms * 1e-3) / 1e12, peak=MFMA_F32_PEAK / 1e12,
@@ -350,6 +364,7 @@ def main():
                     help="sweep problems also solved one source at a time for comparison")
     ap.add_argument("--sweep-oracle", type=int, default=1, help="check the smallest sweep problem against the oracle")
     ap.add_argument("--sweep-workers", type=int, default=4, help="sweep problems run side by side")
+    ap.add_argument("--sweep-fixed-shapes", type=int, default=0, help="block-product shapes from the size heuristic")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -444,7 +459,7 @@ def main():
             log("no trained predictor at", L.MODEL_PATH, "- learned comparison skipped")
     if args.sweep > 0:
         line["sweep"] = sweep_context(mq, torch, dev, args.sweep, args.sweep_compare, bool(args.sweep_oracle),
-                                      args.sweep_workers)
+                                      args.sweep_workers, bool(args.sweep_fixed_shapes))
     if args.cpu_rows > 0:
         log("cpu baseline", args.cpu_rows, "rows")
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_rows)

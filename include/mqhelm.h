@@ -71,6 +71,13 @@ extern "C" {
 /* ---- call flags ---- */
 #define MQH_FLAG_DEVICE_PTRS 1u     /* array arguments are device pointers */
 #define MQH_FLAG_TIME_PRODUCTS 2u   /* mqh_solve: time every product kernel with HIP events on the problem's stream */
+#define MQH_FLAG_FIXED_SHAPES 4u    /* mqh_problem_create: launch shapes of the block products from the size
+                                       alone instead of timing the candidates on first use (results then
+                                       do not depend on timing noise; see mqh_gkb_multi) */
+#define MQH_FLAG_GRAPH 8u           /* mqh_solve_multi / mqh_solve_sweep: run each group's Golub-Kahan loop
+                                       as a captured HIP graph, kept with the problem and replayed while
+                                       the group size, ell and reorth stay the same (ignored with
+                                       MQH_FLAG_TIME_PRODUCTS) */
 
 /* ---- info flags ---- */
 #define MQH_INFO_BREAKDOWN 1u
@@ -164,7 +171,8 @@ const char* mqh_last_error(void);
  *   kappa    wavenumber (finite); eps > 0 shape parameter (eq. (3))
  *   op_mode  MQH_OP_*
  *   stream   hipStream_t to run on, or NULL for a stream the library creates
- *   flags    MQH_FLAG_DEVICE_PTRS if x_int / x_bnd are device pointers
+ *   flags    MQH_FLAG_DEVICE_PTRS if x_int / x_bnd are device pointers,
+ *            MQH_FLAG_FIXED_SHAPES (see there)
  * Errors: MQH_EINVAL (n_int < 0, n_bnd < 0, n = 0, non-finite input,
  * eps <= 0, unknown mode), MQH_ENOMEM (stored matrix or buffers do not fit),
  * MQH_EDEVICE.  On error *out is set to NULL.
@@ -323,7 +331,11 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
  * FP32-evaluated entries of a tile multiply all the group's vectors on the
  * matrix cores (FP32 products, FP32 sums over 256 nodes, FP64 across
  * chunks and slices); a group of one, and the FP64 forms, run one product
- * per run, bit-identical to mqh_gkb / mqh_solve.  Everything else (norms,
+ * per run, bit-identical to mqh_gkb / mqh_solve.  The slice count of the
+ * block products (the split of the sum over nodes, so the order of the FP64
+ * additions) is picked on the first block product of a problem by timing a
+ * few candidates, unless the problem was created with MQH_FLAG_FIXED_SHAPES;
+ * results are bit-reproducible for a given problem handle either way.  Everything else (norms,
  * reorthogonalisation, scalars, breakdown tests, projected SVD, parameter
  * choice, lift) is per run in FP64 as in the single-run calls.
  *

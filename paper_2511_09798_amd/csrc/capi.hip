@@ -119,6 +119,10 @@ struct MultiWs {
     double* PB = nullptr;
     int S_rows = 1, S_cols = 1;
     int64_t slice_rows = 0, slice_cols = 0;
+    // the Golub-Kahan loop of one group as a captured graph, and its key
+    hipGraphExec_t graph = nullptr;
+    int g_nz = 0;
+    int32_t g_ell = 0, g_reorth = -1;
 };
 
 struct mqh_problem {
@@ -128,6 +132,7 @@ struct mqh_problem {
     int64_t n = 0, n_int = 0, n_bnd = 0, ldn = 0;
     double kappa = 0.0, eps = 1.0;
     int32_t mode = 0;
+    bool fixed_shapes = false;
     double center[3] = {0.0, 0.0, 0.0};
     EntryConst ec{};
     double4* X64 = nullptr;
@@ -466,6 +471,10 @@ int run_gkb(mqh_problem* p, int32_t ell, int32_t reorth, bool timed, int32_t j0 
 // ---------------------------------------------------------------------------
 
 void multi_free(MultiWs& w) {
+    if (w.graph != nullptr) (void)hipGraphExecDestroy(w.graph);
+    w.graph = nullptr;
+    w.g_nz = 0;
+    w.g_reorth = -1;
     dfree(w.W);
     dfree(w.Z);
     dfree(w.alpha);
@@ -489,19 +498,85 @@ void multi_free(MultiWs& w) {
     w.ell_cap = 0;
 }
 
-// Slices of a block product: enough workgroups for a few rounds over the
-// chip, slices of whole LDS chunks.
-void block_shapes(mqh_problem* p, MultiWs& w) {
+// Slice count S and length (whole LDS chunks) of a block product aiming at
+// target_blocks workgroups.
+void block_slices(const mqh_problem* p, int64_t target_blocks, int& S, int64_t& len) {
     const int64_t n = p->n, nb = mfm_blocks(n, p->n_int);
-    const int64_t target_blocks = 4096;
     int64_t s = (target_blocks + nb - 1) / nb;
     if (s < 1) s = 1;
-    if (s > 64) s = 64;
+    if (s > kMaxSlices) s = kMaxSlices;
     int64_t l = (n + s - 1) / s;
     l = round_up(l < kMfmChunk ? kMfmChunk : l, kMfmChunk);
     s = (n + l - 1) / l;
-    w.S_rows = w.S_cols = (int)(s < 1 ? 1 : s);
-    w.slice_rows = w.slice_cols = l;
+    S = (int)(s < 1 ? 1 : s);
+    len = l;
+}
+
+// Heuristic shapes: a few rounds of resident workgroups over the chip.
+void block_shapes(mqh_problem* p, MultiWs& w) {
+    block_slices(p, 4096, w.S_rows, w.slice_rows);
+    w.S_cols = w.S_rows;
+    w.slice_cols = w.slice_rows;
+}
+
+// Autotuner of the block products: the candidates aim at 1024 .. 16384
+// workgroups (about one to sixteen rounds of resident workgroups).  Each is
+// timed as the whole product (the slice kernel and the reduction of its
+// nz-column partials) on a pseudo-random operand, once untimed and then five
+// times between event pairs on the problem's stream; the best of the five
+// decides, per direction.  w.PB must hold kMaxSlices slices.
+int tune_block_shapes(mqh_problem* p, MultiWs& w, int nz) {
+    hipStream_t s = p->stream;
+    launch_fill_hash(w.Vg, p->n * kBlkRhs, s);
+    LAUNCHCHK("tuning operand");
+    std::vector<std::pair<int, int64_t>> cand;
+    for (int64_t target = 1024; target <= 16384; target *= 2) {
+        int S;
+        int64_t len;
+        block_slices(p, target, S, len);
+        bool seen = false;
+        for (auto& c : cand) seen = seen || c.first == S;
+        if (!seen) cand.emplace_back(S, len);
+    }
+    constexpr int kReps = 5;
+    hipEvent_t ev[kReps + 1] = {};
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    int rc = MQH_OK;
+    auto product = [&](int trans, const std::pair<int, int64_t>& c) {
+        launch_mfm_block(trans, p->XS, p->frames, w.Vg, p->n, p->n_int, c.first, c.second, p->ec, w.PB, p->ldn, s);
+        launch_reduce_block(w.PB, p->ldn, c.first, p->n, nz, p->perm, nullptr, 0, nullptr, 0, w.Y, p->ldn, nullptr,
+                            s);
+    };
+    for (int trans = 0; trans < 2 && rc == MQH_OK; ++trans) {
+        float best = 0.f;
+        for (auto& c : cand) {
+            product(trans, c);
+            hipError_t e = hipEventRecord(ev[0], s);
+            for (int r = 0; r < kReps && e == hipSuccess; ++r) {
+                product(trans, c);
+                e = hipGetLastError();
+                if (e == hipSuccess) e = hipEventRecord(ev[r + 1], s);
+            }
+            if (e == hipSuccess) e = hipEventSynchronize(ev[kReps]);
+            float t = 0.f;
+            for (int r = 0; r < kReps && e == hipSuccess; ++r) {
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, ev[r], ev[r + 1]);
+                if (r == 0 || ms < t) t = ms;
+            }
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "block-product tuning");
+                break;
+            }
+            if (best == 0.f || t < best) {
+                best = t;
+                (trans ? w.S_cols : w.S_rows) = c.first;
+                (trans ? w.slice_cols : w.slice_rows) = c.second;
+            }
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return rc;
 }
 
 int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
@@ -541,11 +616,27 @@ int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
     }
     if (p->mode == MQH_OP_MATFREE_FP32) {
         block_shapes(p, w);
-        const int S = w.S_rows > w.S_cols ? w.S_rows : w.S_cols;
+        const int S = p->fixed_shapes ? (w.S_rows > w.S_cols ? w.S_rows : w.S_cols) : kMaxSlices;
         if ((rc = dalloc(&w.Vg, (size_t)n * kBlkRhs)) ||
             (rc = dalloc(&w.PB, (size_t)S * kBlkRhs * (size_t)ldn))) {
             multi_free(w);
             return rc;
+        }
+        if (!p->fixed_shapes) {
+            if ((rc = tune_block_shapes(p, w, zc))) {
+                multi_free(w);
+                return rc;
+            }
+            // keep only the partials the chosen shapes use (the tuning
+            // launches have completed: its last event was waited for)
+            const int Sm = w.S_rows > w.S_cols ? w.S_rows : w.S_cols;
+            if (Sm < kMaxSlices) {
+                dfree(w.PB);
+                if ((rc = dalloc(&w.PB, (size_t)Sm * kBlkRhs * (size_t)ldn))) {
+                    multi_free(w);
+                    return rc;
+                }
+            }
         }
     }
     w.nz_cap = zc;
@@ -647,6 +738,41 @@ int run_gkb_multi(mqh_problem* p, int nz, int32_t ell, int32_t reorth, bool time
             return rc;
         if ((rc = orthonormalize(w.W, j + 1, 2, j, w.W + (int64_t)(j + 1) * ldn))) return rc;
     }
+    return MQH_OK;
+}
+
+// The Golub-Kahan loop of a group (run_gkb_multi) as a graph: captured on
+// the problem's stream at the first call with this group size, ell and
+// reorth, replayed after that.  The captured launches hold workspace
+// addresses, so a workspace reallocation drops the graph (multi_free).
+int run_gkb_multi_graph(mqh_problem* p, int nz, int32_t ell, int32_t reorth) {
+    MultiWs& w = p->mw;
+    hipStream_t s = p->stream;
+    if (w.graph != nullptr && (w.g_nz != nz || w.g_ell != ell || w.g_reorth != reorth)) {
+        HIPCHK(hipGraphExecDestroy(w.graph));
+        w.graph = nullptr;
+    }
+    if (w.graph == nullptr) {
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const int rc = run_gkb_multi(p, nz, ell, reorth, false);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc != MQH_OK) {
+            if (g != nullptr) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "graph capture");
+        const hipError_t ei = hipGraphInstantiate(&w.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            w.graph = nullptr;
+            return hip_fail(ei, "graph instantiation");
+        }
+        w.g_nz = nz;
+        w.g_ell = ell;
+        w.g_reorth = reorth;
+    }
+    HIPCHK(hipGraphLaunch(w.graph, s));
     return MQH_OK;
 }
 
@@ -803,6 +929,7 @@ int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, 
     p->kappa = kappa;
     p->eps = eps;
     p->mode = op_mode;
+    p->fixed_shapes = (flags & MQH_FLAG_FIXED_SHAPES) != 0;
     p->ec.k2 = kappa * kappa;
     p->ec.e2 = eps * eps;
     p->ec.e2x2 = 2.0 * eps * eps;
@@ -1210,7 +1337,11 @@ int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
         HIPCHK(hipEventRecord(p->ev[0], s));
         if ((rc = stage_multi(p, F, ldf, k0, nz, flags))) return rc;
         HIPCHK(hipEventRecord(p->ev[1], s));
-        if ((rc = run_gkb_multi(p, nz, ell, opts->reorth, timed))) return rc;
+        if ((flags & MQH_FLAG_GRAPH) && !timed) {
+            if ((rc = run_gkb_multi_graph(p, nz, ell, opts->reorth))) return rc;
+        } else {
+            if ((rc = run_gkb_multi(p, nz, ell, opts->reorth, timed))) return rc;
+        }
         HIPCHK(hipEventRecord(p->ev[2], s));
         const int32_t* lp = &w.st->ell_done;
         const ProjBatch pb{w.vstr, (int64_t)w.ell_cap * w.ell_cap, (int64_t)(sizeof(GkbState) / sizeof(int32_t)), 0};

@@ -13,6 +13,7 @@ constexpr int kMfmFt = 2;       // 16-node fixed tiles per wave in the FP32-eval
 constexpr int kMfmFixed = (kBlock / kWave) * kMfmFt * 16;  // fixed nodes per block (128)
 constexpr int kMfmChunk = kBlock;  // loop nodes staged in LDS per round (one per thread)
 constexpr int kBlkRhs = 16;        // right-hand sides of a block product (lockstep Golub-Kahan runs)
+constexpr int kMaxSlices = 64;     // largest split of a product's sum over nodes
 
 // Learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs.
 constexpr int kMlpIn = 24;
@@ -46,6 +47,7 @@ void launch_mfm_product(int trans, const float4* XS, const float4* frames, const
                         hipStream_t s);
 void launch_mfm_block(int trans, const float4* XS, const float4* frames, const float* Vg, int64_t n, int64_t n_int,
                       int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp, hipStream_t s);
+void launch_fill_hash(float* Vg, int64_t count, hipStream_t s);
 void launch_gather_block(const double* X, int64_t ldx, int nrhs, const int32_t* perm, int64_t n,
                          const GkbState* st, float* Vg, hipStream_t s);
 void launch_reduce_block(const double* P, int64_t ldp, int S, int64_t n, int nrhs, const int32_t* perm,

@@ -586,6 +586,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_block(const double* __restric
     Vg[e] = live ? (float)X[k * ldx + perm[q]] : 0.f;
 }
 
+// Vg[e] = a fixed pseudo-random value in [-0.5, 0.5) (an operand for timing
+// runs: finite, with the spread of real data).
+__global__ __launch_bounds__(kBlock) void k_fill_hash(float* __restrict__ Vg, int64_t count) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= count) return;
+    uint32_t h = (uint32_t)e * 0x9E3779B1u;
+    h ^= h >> 15;
+    h *= 0x85EBCA77u;
+    h ^= h >> 13;
+    Vg[e] = (float)(h >> 8) * (1.0f / 16777216.0f) - 0.5f;
+}
+
 // y_k[perm[i]] = sum_slices P[slice][k][i] - shift_k z_k[perm[i]] for right-hand
 // side k = blockIdx.y (shift_k = shift[k * sstride], z_k = z + k * ldz,
 // y_k = y + k * ldy); skipped when state k has stopped.
@@ -796,6 +808,11 @@ void launch_mfm_block(int trans, const float4* XS, const float4* frames, const f
         k_mfm_block<false><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
     else
         k_mfm_block<true><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+}
+
+void launch_fill_hash(float* Vg, int64_t count, hipStream_t s) {
+    if (count <= 0) return;
+    k_fill_hash<<<(unsigned)((count + kBlock - 1) / kBlock), kBlock, 0, s>>>(Vg, count);
 }
 
 void launch_gather_block(const double* X, int64_t ldx, int nrhs, const int32_t* perm, int64_t n,

@@ -36,6 +36,8 @@ MQH_RULE_FIXED = 2
 MQH_RULE_WGCV = 3
 MQH_FLAG_DEVICE_PTRS = 1
 MQH_FLAG_TIME_PRODUCTS = 2
+MQH_FLAG_FIXED_SHAPES = 4
+MQH_FLAG_GRAPH = 8
 MQH_INFO_BREAKDOWN = 1
 MQH_INFO_GCV_AT_EDGE = 2
 MQH_INFO_LCURVE_AT_EDGE = 4
@@ -229,8 +231,9 @@ def mqh_last_error() -> str:
     return lib.mqh_last_error().decode()
 
 
-def mqh_problem_create(x_int, x_bnd, kappa: float, eps: float, op_mode: int, stream=None) -> ctypes.c_void_p:
-    fl = _flags(x_int, x_bnd)
+def mqh_problem_create(x_int, x_bnd, kappa: float, eps: float, op_mode: int, stream=None,
+                       fixed_shapes: bool = False) -> ctypes.c_void_p:
+    fl = _flags(x_int, x_bnd) | (MQH_FLAG_FIXED_SHAPES if fixed_shapes else 0)
     pi, _ = _ptr(x_int)
     pb, _ = _ptr(x_bnd)
     n_int = 0 if x_int is None else int(x_int.shape[0])
@@ -422,7 +425,7 @@ class MultiSolveOutput:
 
 def mqh_solve_multi(h, F, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQH_RULE_GCV, k_trunc: int = 0,
                     lambda_fixed: float = 0.0, n_grid: int = 200, reorth: int = 1, time_products: bool = False,
-                    coef=None, gcv_weight: float = 1.0) -> MultiSolveOutput:
+                    coef=None, gcv_weight: float = 1.0, graph: bool = False) -> MultiSolveOutput:
     """Algorithm 4 for every row of F (nrhs x n, rows [f_int; g_bnd])."""
     n = int(lib.mqh_problem_size(h))
     nrhs = int(F.shape[0])
@@ -430,7 +433,7 @@ def mqh_solve_multi(h, F, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQ
         raise ValueError("F must be nrhs x n")
     if coef is None:
         coef = _empty_like_kind(F, (nrhs, n))
-    fl = _flags(F, coef)
+    fl = _flags(F, coef) | (MQH_FLAG_GRAPH if graph else 0)
     opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=int(method), rule=int(rule),
                           k_trunc=int(k_trunc), n_grid=int(n_grid), lambda_fixed=float(lambda_fixed),
                           flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), reserved=0,
@@ -447,7 +450,7 @@ def mqh_solve_multi(h, F, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQ
 
 def mqh_solve_sweep(problems, Fs, ell: int, workers: int = 2, coefs=None, method: int = MQH_METHOD_HKT,
                     rule: int = MQH_RULE_GCV, k_trunc: int = 0, lambda_fixed: float = 0.0, n_grid: int = 200,
-                    reorth: int = 1, time_products: bool = False, gcv_weight: float = 1.0):
+                    reorth: int = 1, time_products: bool = False, gcv_weight: float = 1.0, graph: bool = False):
     """Solve every problem of a sweep (Problem objects, each with its own right-hand sides Fs[i],
     nrhs_i x n_i) side by side on `workers` host threads; returns a list of MultiSolveOutput."""
     if len(problems) != len(Fs) or not problems:
@@ -455,7 +458,7 @@ def mqh_solve_sweep(problems, Fs, ell: int, workers: int = 2, coefs=None, method
     count = len(problems)
     if coefs is None:
         coefs = [_empty_like_kind(F, tuple(F.shape)) for F in Fs]
-    fl = _flags(*Fs, *coefs)
+    fl = _flags(*Fs, *coefs) | (MQH_FLAG_GRAPH if graph else 0)
     infos = [(mqh_solve_info * int(F.shape[0]))() for F in Fs]
     items = (mqh_sweep_item * count)()
     for i, (pr, F, C) in enumerate(zip(problems, Fs, coefs)):
@@ -580,13 +583,14 @@ def mqh_solve_learned(h, f_int, g_bnd, ell: int, predictor: mqh_predictor, coef=
 class Problem:
     """Owns one mqh_problem handle (nodes, kappa, eps, operator mode, stream)."""
 
-    def __init__(self, x_int, x_bnd, kappa: float, eps: float, op_mode="matfree_fp64", stream=None):
+    def __init__(self, x_int, x_bnd, kappa: float, eps: float, op_mode="matfree_fp64", stream=None,
+                 fixed_shapes: bool = False):
         mode = OP_MODES[op_mode] if isinstance(op_mode, str) else int(op_mode)
         self.mode = mode
         self.n_int = 0 if x_int is None else int(x_int.shape[0])
         self.n_bnd = 0 if x_bnd is None else int(x_bnd.shape[0])
         self.n = self.n_int + self.n_bnd
-        self.h = mqh_problem_create(x_int, x_bnd, kappa, eps, mode, stream)
+        self.h = mqh_problem_create(x_int, x_bnd, kappa, eps, mode, stream, fixed_shapes)
 
     def close(self):
         if self.h is not None and self.h.value:

@@ -288,3 +288,36 @@ def test_solve_sweep_matches_one_by_one(mq):
     finally:
         for h in handles:
             h.close()
+
+
+def test_graph_replays_match_eager(mq):
+    # the captured Golub-Kahan loop, replayed several times with other work on
+    # the stream in between, gives the eager results bit for bit; a new group
+    # size or ell recaptures
+    p = I.multi_cube(600, 260, 5.0, 1.8, 12, 30, seed=21)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("graph eager reference")
+        ref = pr.solve_multi(p.F, p.ell)
+        ref5 = pr.solve_multi(p.F[:5], 20)
+        for rep in range(3):
+            say("graph replay", rep)
+            out = pr.solve_multi(p.F, p.ell, graph=True)
+            assert np.array_equal(out.coef, ref.coef), rep
+            assert np.array_equal(out.lam, ref.lam)
+            pr.apply_multi(p.F[:3], trans=True)  # eager work between the replays
+            out5 = pr.solve_multi(p.F[:5], 20, graph=True)  # other shape: recapture
+            assert np.array_equal(out5.coef, ref5.coef), rep
+
+
+def test_fixed_shapes_against_oracle(mq, orc):
+    p = I.multi_cube(333, 190, 6.0, 2.0, 7, 30, seed=5)
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((7, p.n))
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    say("fixed shapes")
+    with mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, "matfree_fp32", fixed_shapes=True) as pr:
+        for trans in (False, True):
+            Y = pr.apply_multi(X, trans=trans)
+            Aop = A.T if trans else A
+            err = np.abs(Y.T - Aop @ X.T) / (np.abs(Aop) @ np.abs(X.T))
+            assert np.all(err <= 4e-6), float(err.max())
