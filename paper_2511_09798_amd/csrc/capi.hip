@@ -92,7 +92,7 @@ struct HostResults {
 // kBlkRhs runs side by side, run k's arrays at base + k * stride.
 struct MultiWs {
     int32_t nz_cap = 0, ell_cap = 0;
-    int64_t vstr = 0;     // stride of the length-(ell + 2) arrays (alpha, beta, sv, ftil, y)
+    int64_t vstr = 0;     // stride of the length-(ell + 2) arrays (alpha, beta, sv, ftil, y, cvec)
     int64_t bstr = 0;     // stride of a basis, (ell_cap + 1) x ldn
     int64_t gstr = 0;     // stride of the reorthogonalisation partials
     int64_t nstr = 0;     // stride of the norm partials
@@ -103,6 +103,7 @@ struct MultiWs {
     double* sv = nullptr;
     double* ftil = nullptr;
     double* y = nullptr;
+    double* cvec = nullptr;
     double* gpart = nullptr;
     double* npart = nullptr;
     double* Vw = nullptr;  // ell_cap x ell_cap per run
@@ -169,6 +170,7 @@ struct mqh_problem {
     double* beta = nullptr;
     GkbState* st = nullptr;
     double* gpart = nullptr;
+    double* cvec = nullptr;
     double* npart = nullptr;
     // projected problem
     double* sv = nullptr;
@@ -389,6 +391,7 @@ int ensure_gkb(mqh_problem* p, int32_t ell) {
     dfree(p->alpha);
     dfree(p->beta);
     dfree(p->gpart);
+    dfree(p->cvec);
     dfree(p->sv);
     dfree(p->ftil);
     dfree(p->Vw);
@@ -404,6 +407,7 @@ int ensure_gkb(mqh_problem* p, int32_t ell) {
     if ((rc = dalloc(&p->alpha, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->beta, (size_t)cols + 1))) return rc;
     if ((rc = dalloc(&p->gpart, (size_t)gemvt_blocks(p->n) * (size_t)cols))) return rc;
+    if ((rc = dalloc(&p->cvec, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->sv, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->ftil, (size_t)cols + 1))) return rc;
     if ((rc = dalloc(&p->Vw, (size_t)ell * (size_t)ell))) return rc;
@@ -433,10 +437,10 @@ int run_gkb(mqh_problem* p, int32_t ell, int32_t reorth, bool timed, int32_t j0 
     auto orthonormalize = [&](double* v, const double* V, int32_t m, int kind, int32_t j, double* dst) -> int {
         int nparts;
         if (reorth && m > 0) {
-            launch_gemvt(V, ldn, n, m, v, p->gpart, p->st, s);
-            launch_update(V, ldn, n, m, p->gpart, v, nullptr, p->st, s);
-            launch_gemvt(V, ldn, n, m, v, p->gpart, p->st, s);
-            launch_update(V, ldn, n, m, p->gpart, v, p->npart, p->st, s);
+            launch_gemvt(V, ldn, n, m, v, p->gpart, p->cvec, p->st, s);
+            launch_update(V, ldn, n, m, p->cvec, v, nullptr, p->st, s);
+            launch_gemvt(V, ldn, n, m, v, p->gpart, p->cvec, p->st, s);
+            launch_update(V, ldn, n, m, p->cvec, v, p->npart, p->st, s);
             nparts = nbu;
         } else {
             launch_sumsq_partial(v, n, p->npart, nbq, p->st, s);
@@ -482,6 +486,7 @@ void multi_free(MultiWs& w) {
     dfree(w.sv);
     dfree(w.ftil);
     dfree(w.y);
+    dfree(w.cvec);
     dfree(w.gpart);
     dfree(w.npart);
     dfree(w.Vw);
@@ -595,7 +600,7 @@ int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
     if ((rc = dalloc(&w.W, Z * (size_t)w.bstr)) || (rc = dalloc(&w.Z, Z * (size_t)w.bstr)) ||
         (rc = dalloc(&w.alpha, Z * (size_t)w.vstr)) || (rc = dalloc(&w.beta, Z * (size_t)w.vstr)) ||
         (rc = dalloc(&w.sv, Z * (size_t)w.vstr)) || (rc = dalloc(&w.ftil, Z * (size_t)w.vstr)) ||
-        (rc = dalloc(&w.y, Z * (size_t)w.vstr)) ||
+        (rc = dalloc(&w.y, Z * (size_t)w.vstr)) || (rc = dalloc(&w.cvec, Z * (size_t)w.vstr)) ||
         (rc = dalloc(&w.gpart, Z * (size_t)w.gstr)) || (rc = dalloc(&w.npart, Z * (size_t)w.nstr)) ||
         (rc = dalloc(&w.Vw, Z * (size_t)lc * (size_t)lc)) || (rc = dalloc(&w.V, Z * (size_t)lc * (size_t)lc)) ||
         (rc = dalloc(&w.st, Z)) || (rc = dalloc(&w.pout, Z)) || (rc = dalloc(&w.status, Z)) ||
@@ -708,12 +713,11 @@ int run_gkb_multi(mqh_problem* p, int nz, int32_t ell, int32_t reorth, bool time
     auto orthonormalize = [&](const double* V, int32_t m, int kind, int32_t j, double* dst) -> int {
         int nparts;
         if (reorth && m > 0) {
-            const Bz gb{w.bstr, ldn, w.gstr, 0};
-            const Bz ub{w.bstr, w.gstr, ldn, w.nstr};
-            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.st, nz, gb, s);
-            launch_update_b(V, ldn, n, m, w.gpart, w.Y, nullptr, w.st, nz, ub, s);
-            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.st, nz, gb, s);
-            launch_update_b(V, ldn, n, m, w.gpart, w.Y, w.npart, w.st, nz, ub, s);
+            const Bz ub{w.bstr, w.vstr, ldn, w.nstr};
+            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.cvec, w.st, nz, w.bstr, ldn, w.gstr, w.vstr, s);
+            launch_update_b(V, ldn, n, m, w.cvec, w.Y, nullptr, w.st, nz, ub, s);
+            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.cvec, w.st, nz, w.bstr, ldn, w.gstr, w.vstr, s);
+            launch_update_b(V, ldn, n, m, w.cvec, w.Y, w.npart, w.st, nz, ub, s);
             nparts = nbu;
         } else {
             launch_sumsq_partial_b(w.Y, n, w.npart, nbq, w.st, nz, Bz{ldn, w.nstr}, s);
@@ -872,6 +876,7 @@ int mqh_problem_destroy(mqh_problem* p) {
     dfree(p->beta);
     dfree(p->st);
     dfree(p->gpart);
+    dfree(p->cvec);
     dfree(p->npart);
     dfree(p->sv);
     dfree(p->ftil);

@@ -204,34 +204,38 @@ __global__ __launch_bounds__(kBlock) void k_gemvt_partial(const double* __restri
     }
 }
 
-// x_i -= sum_k V[k][i] c_k with c_k = sum_b partial[b * m + k], the column
-// sums of the k_gemvt_partial partials (nb row blocks).  Every block forms c
-// in LDS itself, one wave per column (lanes take b = lane, lane + 64, ...,
-// then the wave reduction: one fixed order).  Optionally partial[b] = sum
-// over the block of the updated x_i^2.
+// c[k] = sum_b partial[b * m + k]: one wave per column, lanes take b = lane,
+// lane + 64, ... and the wave reduction combines them in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restrict__ partial, int nb, int32_t m,
+                                                         double* __restrict__ c,
+                                                         const GkbState* __restrict__ st, Bz bz) {
+    const int64_t z = blockIdx.y;  // batch: partial + z bz.a, c + z bz.b, state z
+    partial += z * bz.a;
+    c += z * bz.b;
+    if (st != nullptr) st += z;
+    if (st != nullptr && st->stopped) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int k = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (k >= m) return;  // wave-uniform; no barriers
+    double s = 0.0;
+    for (int b = lane; b < nb; b += kWave) s += partial[(int64_t)b * m + k];
+    s = wave_sum(s);
+    if (lane == 0) c[k] = s;
+}
+
+// x_i -= sum_k V[k][i] c_k; optionally partial[b] = sum over the block of the updated x_i^2.
 __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V, int64_t ldn, int64_t n, int32_t m,
-                                                   const double* __restrict__ partial, int nb,
-                                                   double* __restrict__ x, double* __restrict__ sumsq_partial,
+                                                   const double* __restrict__ c, double* __restrict__ x,
+                                                   double* __restrict__ sumsq_partial,
                                                    const GkbState* __restrict__ st, Bz bz) {
     __shared__ double lds[kBlock / kWave];
-    __shared__ double c[kMaxEll];
-    const int64_t z = blockIdx.z;  // batch: V + z bz.a, partial + z bz.b, x + z bz.c, sumsq + z bz.d, state z
+    const int64_t z = blockIdx.z;  // batch: V + z bz.a, c + z bz.b, x + z bz.c, sumsq + z bz.d, state z
     V += z * bz.a;
-    partial += z * bz.b;
+    c += z * bz.b;
     x += z * bz.c;
     if (sumsq_partial != nullptr) sumsq_partial += z * bz.d;
     if (st != nullptr) st += z;
     if (st != nullptr && st->stopped) return;  // uniform over the grid
-    {
-        const int lane = threadIdx.x & (kWave - 1);
-        for (int k = threadIdx.x / kWave; k < m; k += kBlock / kWave) {
-            double sk = 0.0;
-            for (int b = lane; b < nb; b += kWave) sk += partial[(int64_t)b * m + k];
-            sk = wave_sum(sk);
-            if (lane == 0) c[k] = sk;
-        }
-    }
-    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double xi = 0.0;
     if (i < n) {
@@ -338,26 +342,29 @@ void launch_finalize_scale_b(const double* partial, int nparts, int kind, int32_
 
 int gemvt_blocks(int64_t n) { return (int)((n + kGtRows - 1) / kGtRows); }
 
-void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial,
+void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
                   const GkbState* st, hipStream_t s) {
-    launch_gemvt_b(V, ldn, n, m, x, partial, st, 1, Bz{}, s);
+    launch_gemvt_b(V, ldn, n, m, x, partial, c, st, 1, 0, 0, 0, 0, s);
 }
 
-void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial,
-                    const GkbState* st, int nz, Bz bz, hipStream_t s) {
-    k_gemvt_partial<<<dim3(gemvt_blocks(n), (m + kGtCols - 1) / kGtCols, nz), kBlock, 0, s>>>(V, ldn, n, m, x,
-                                                                                             partial, st, bz);
+void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
+                    const GkbState* st, int nz, int64_t sV, int64_t sx, int64_t sp, int64_t sc, hipStream_t s) {
+    const int nb = gemvt_blocks(n);
+    k_gemvt_partial<<<dim3(nb, (m + kGtCols - 1) / kGtCols, nz), kBlock, 0, s>>>(V, ldn, n, m, x, partial, st,
+                                                                                 Bz{sV, sx, sp, 0});
+    k_gemvt_reduce<<<dim3((m + kBlock / kWave - 1) / (kBlock / kWave), nz), kBlock, 0, s>>>(partial, nb, m, c, st,
+                                                                                           Bz{sp, sc, 0, 0});
 }
 
-void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* partial, double* x,
+void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
                    double* sumsq_partial, const GkbState* st, hipStream_t s) {
-    launch_update_b(V, ldn, n, m, partial, x, sumsq_partial, st, 1, Bz{}, s);
+    launch_update_b(V, ldn, n, m, c, x, sumsq_partial, st, 1, Bz{}, s);
 }
 
-void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* partial, double* x,
+void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
                      double* sumsq_partial, const GkbState* st, int nz, Bz bz, hipStream_t s) {
-    k_update<<<dim3((unsigned)((n + kBlock - 1) / kBlock), 1, nz), kBlock, 0, s>>>(
-        V, ldn, n, m, partial, gemvt_blocks(n), x, sumsq_partial, st, bz);
+    k_update<<<dim3((unsigned)((n + kBlock - 1) / kBlock), 1, nz), kBlock, 0, s>>>(V, ldn, n, m, c, x, sumsq_partial,
+                                                                                 st, bz);
 }
 
 int update_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }

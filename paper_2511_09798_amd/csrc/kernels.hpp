@@ -88,12 +88,11 @@ void launch_sumsq_partial(const double* x, int64_t n, double* partial, int nb, c
 void launch_finalize_scale(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
                            double* beta, GkbState* st, const double* x, double* dst, hipStream_t s);
 int gemvt_blocks(int64_t n);
-// partial (gemvt_blocks(n) x m) of V^T x; launch_update subtracts V c with c
-// the column sums of those partials
-void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial,
+// c = V^T x through block partials (gemvt_blocks(n) x m); x -= V c
+void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
                   const GkbState* st, hipStream_t s);
 int update_blocks(int64_t n);
-void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* partial, double* x,
+void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
                    double* sumsq_partial, const GkbState* st, hipStream_t s);
 void launch_lift(const double* Z, int64_t ldz, int64_t n, int32_t ell, const int32_t* ell_ptr, const double* y,
                  double* coef, hipStream_t s, int nz = 1, Bz bz = Bz{});
@@ -106,9 +105,9 @@ void launch_sumsq_partial_b(const double* x, int64_t n, double* partial, int nb,
 void launch_finalize_scale_b(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
                              double* beta, GkbState* st, const double* x, double* dst, const int32_t* iperm,
                              float* Vg, int nz, Bz bz, hipStream_t s);
-void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial,
-                    const GkbState* st, int nz, Bz bz, hipStream_t s);
-void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* partial, double* x,
+void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
+                    const GkbState* st, int nz, int64_t sV, int64_t sx, int64_t sp, int64_t sc, hipStream_t s);
+void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
                      double* sumsq_partial, const GkbState* st, int nz, Bz bz, hipStream_t s);
 void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
 
