@@ -651,6 +651,31 @@ def full_tikh_gcv(A: np.ndarray, f: np.ndarray, n_grid: int = 200):
     return alpha, lam
 
 
+def gcv_tsvd_full(s: np.ndarray, fhat: np.ndarray, s_perp: float, n: int, k: int) -> float:
+    """GCV of the full-problem TSVD solution of rank k: eq. (25) with the filter factors
+    phi_i = 1 for i <= k and 0 otherwise, i.e. (sum_{i>k} fhat_i^2 + s_perp) / (n - k)^2."""
+    d = n - k
+    return (float(np.sum(fhat[k:] ** 2)) + s_perp) / (d * d)
+
+
+def full_tsvd_gcv(A: np.ndarray, f: np.ndarray):
+    """Full TSVD (eq. (14)) with the rank chosen by the full-problem GCV: k over 1 .. min(r, n - 1),
+    r the number of non-zero singular values, ties to the smaller k; returns (alpha, k)."""
+    U, s, V = full_svd(A)
+    n = A.shape[0]
+    fhat = U.T @ f
+    s_perp = max(0.0, float(f @ f) - float(fhat @ fhat))
+    r = int(np.count_nonzero(s > 0.0))
+    kmax = min(r, n - 1)
+    best, kb = None, 1
+    for k in range(1, kmax + 1):
+        g = gcv_tsvd_full(s[:r], fhat[:r], s_perp, n, k)
+        if best is None or g < best:
+            best, kb = g, k
+    alpha = V[:, :kb] @ (fhat[:kb] / s[:kb])
+    return alpha, kb
+
+
 def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
