@@ -632,12 +632,10 @@ def full_tikhonov(A: np.ndarray, f: np.ndarray, lam: float) -> np.ndarray:
     return V @ (s / (s * s + lam * lam) * (U.T @ f))
 
 
-def full_tikh_gcv(A: np.ndarray, f: np.ndarray, n_grid: int = 200):
-    """Tikh-Reg via GCV (Algorithm 3) with grid refinement; returns (alpha, lambda)."""
-    U, s, V = full_svd(A)
-    n = A.shape[0]
-    fhat = U.T @ f
-    s_perp = max(0.0, float(f @ f) - float(fhat @ fhat))
+def choose_lambda_full(s: np.ndarray, fhat: np.ndarray, s_perp: float, n: int, n_grid: int = 200) -> float:
+    """Algorithm 3's lambda: the minimiser of the full-problem GCV (eq. (25)) over a log grid on
+    [max(s_min, 16 eps_mach s_1), s_1], refined by golden section over the two cells around the
+    grid minimum (ties to the larger lambda; a minimum at a grid end is kept)."""
     grid = lambda_grid(s, n_grid)
     vals = np.array([gcv_full(s, fhat, s_perp, n, lam) for lam in grid])
     k = n_grid - 1 - int(np.argmin(vals[::-1]))
@@ -647,6 +645,16 @@ def full_tikh_gcv(A: np.ndarray, f: np.ndarray, n_grid: int = 200):
                        math.log(grid[k + 1]))
         if gcv_full(s, fhat, s_perp, n, math.exp(t)) <= vals[k]:
             lam = math.exp(t)
+    return lam
+
+
+def full_tikh_gcv(A: np.ndarray, f: np.ndarray, n_grid: int = 200):
+    """Tikh-Reg via GCV (Algorithm 3) with grid refinement; returns (alpha, lambda)."""
+    U, s, V = full_svd(A)
+    n = A.shape[0]
+    fhat = U.T @ f
+    s_perp = max(0.0, float(f @ f) - float(fhat @ fhat))
+    lam = choose_lambda_full(s, fhat, s_perp, n, n_grid)
     alpha = V @ (s / (s * s + lam * lam) * fhat)
     return alpha, lam
 
@@ -658,13 +666,9 @@ def gcv_tsvd_full(s: np.ndarray, fhat: np.ndarray, s_perp: float, n: int, k: int
     return (float(np.sum(fhat[k:] ** 2)) + s_perp) / (d * d)
 
 
-def full_tsvd_gcv(A: np.ndarray, f: np.ndarray):
-    """Full TSVD (eq. (14)) with the rank chosen by the full-problem GCV: k over 1 .. min(r, n - 1),
-    r the number of non-zero singular values, ties to the smaller k; returns (alpha, k)."""
-    U, s, V = full_svd(A)
-    n = A.shape[0]
-    fhat = U.T @ f
-    s_perp = max(0.0, float(f @ f) - float(fhat @ fhat))
+def choose_rank_full(s: np.ndarray, fhat: np.ndarray, s_perp: float, n: int) -> int:
+    """The TSVD rank minimising the full-problem GCV with 0/1 filter factors over
+    k = 1 .. min(r, n - 1), r the number of non-zero singular values, ties to the smaller k."""
     r = int(np.count_nonzero(s > 0.0))
     kmax = min(r, n - 1)
     best, kb = None, 1
@@ -672,6 +676,17 @@ def full_tsvd_gcv(A: np.ndarray, f: np.ndarray):
         g = gcv_tsvd_full(s[:r], fhat[:r], s_perp, n, k)
         if best is None or g < best:
             best, kb = g, k
+    return kb
+
+
+def full_tsvd_gcv(A: np.ndarray, f: np.ndarray):
+    """Full TSVD (eq. (14)) with the rank chosen by the full-problem GCV (choose_rank_full);
+    returns (alpha, k)."""
+    U, s, V = full_svd(A)
+    n = A.shape[0]
+    fhat = U.T @ f
+    s_perp = max(0.0, float(f @ f) - float(fhat @ fhat))
+    kb = choose_rank_full(s, fhat, s_perp, n)
     alpha = V[:, :kb] @ (fhat[:kb] / s[:kb])
     return alpha, kb
 
