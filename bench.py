@@ -320,6 +320,47 @@ def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, 
     return res
 
 
+def full_context(mq, torch, dev, level: int):
+    """Classical Tikhonov with GCV on the full SVD (Algorithm 3) on the 20 000-node cube, stored FP64 A,
+    against HKT (ell = 200, GCV) on the same problem: time to solution and error against the manufactured u."""
+    import numpy as np
+
+    from paper_2511_09798_amd import inputs as I
+
+    p = I.cube_medium()
+    res = dict(workload=f"{p.name}: kappa {p.kappa}, eps {p.eps}, stored FP64 A")
+    with mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, "stored_fp64") as pr:
+        f_int = torch.from_numpy(p.f_int).to(dev)
+        g_bnd = torch.from_numpy(p.g_bnd).to(dev)
+        x_eval = torch.from_numpy(p.x_eval).to(dev)
+        runs = [("tikh_reg_full_svd", dict(method=mq.MQH_METHOD_HKT))]
+        if level >= 2:
+            runs.append(("tsvd_full_svd", dict(method=mq.MQH_METHOD_INE_TSVD)))
+        for name, kw in runs:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = pr.full_solve(f_int, g_bnd, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            u = pr.eval(out.coef, x_eval).cpu().numpy()
+            res[name] = dict(time_s=dt, sweeps=out.ell_done, off=out.t_ms[6], lam=out.lam, k=out.k,
+                             rel_l2=rel_l2(u, p.u_eval), rel_linf=rel_linf(u, p.u_eval),
+                             phase_ms=dict(assembly=out.t_ms[0], jacobi=out.t_ms[1], order=out.t_ms[2],
+                                           param=out.t_ms[3], solution=out.t_ms[4]),
+                             cg_iterations=int(out.t_ms[7]))
+            log("full", name, json.dumps(res[name]))
+        pr.solve(f_int, g_bnd, p.ell)  # warmup
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = pr.solve(f_int, g_bnd, p.ell)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        u = pr.eval(out.coef, x_eval).cpu().numpy()
+        res["hkt"] = dict(time_s=dt, ell=p.ell, lam=out.lam, rel_l2=rel_l2(u, p.u_eval), rel_linf=rel_linf(u, p.u_eval))
+        log("full hkt", json.dumps(res["hkt"]))
+    return res
+
+
 def cpu_baseline(p, rows):
     """The oracle's entry-by-entry FP64 products on a row / column sample."""
     import numpy as np
@@ -365,6 +406,9 @@ def main():
     ap.add_argument("--sweep-oracle", type=int, default=1, help="check the smallest sweep problem against the oracle")
     ap.add_argument("--sweep-workers", type=int, default=4, help="sweep problems run side by side")
     ap.add_argument("--sweep-fixed-shapes", type=int, default=0, help="block-product shapes from the size heuristic")
+    ap.add_argument("--full", type=int, default=0,
+                    help="full-SVD reference on the 20 000-node cube beside HKT: 1 Tikh-Reg, 2 also TSVD "
+                         "(minutes each; 0: skip)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -460,6 +504,8 @@ def main():
     if args.sweep > 0:
         line["sweep"] = sweep_context(mq, torch, dev, args.sweep, args.sweep_compare, bool(args.sweep_oracle),
                                       args.sweep_workers, bool(args.sweep_fixed_shapes))
+    if args.full > 0:
+        line["full_svd_reference"] = full_context(mq, torch, dev, args.full)
     if args.cpu_rows > 0:
         log("cpu baseline", args.cpu_rows, "rows")
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_rows)

@@ -52,6 +52,7 @@ extern "C" {
 #define MQH_EDEVICE (-3)  /* a HIP runtime call or kernel launch failed */
 #define MQH_WBREAKDOWN 1  /* Golub-Kahan stopped early (ell_done < ell); outputs valid for ell_done steps */
 #define MQH_WEDGE 2       /* chosen lambda sits at an end of the search grid */
+#define MQH_WNOCONV 3     /* full SVD: the Jacobi sweeps stopped at their limit (results of the last sweep) */
 
 /* ---- operator modes (how A enters the products) ---- */
 #define MQH_OP_STORED_FP64 0   /* A assembled once in HBM (8 N^2 bytes, row-major), FP64 products */
@@ -86,6 +87,7 @@ extern "C" {
 
 /* Largest number of Golub-Kahan steps a solve accepts (projected problem size). */
 #define MQH_MAX_ELL 1024
+#define MQH_FULL_MAX_N 32768 /* largest n of the full-SVD reference path (8.6 GB work matrix) */
 #define MQH_BLOCK_RHS 16 /* right-hand sides run in lockstep per group (mqh_gkb_multi, mqh_solve_multi) */
 
 /* ---- learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs ---- */
@@ -392,6 +394,51 @@ typedef struct {
 } mqh_sweep_item;
 
 int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* opts, int32_t workers);
+
+/*
+ * Reference path: the full SVD of A and the classical regularised solutions
+ * built on it, for n <= MQH_FULL_MAX_N (every call assembles A in FP64 into
+ * its own n x (n + 1) work matrix, 8 n^2 bytes, freed on return).
+ *
+ * The SVD is one-sided block Jacobi on the rows of [A | f]: row rotations Q
+ * (each sweep orders the rows by decreasing norm and pairs 32-row blocks in
+ * a round-robin order; per pair the eigenvectors of the 64 x 64 Gram matrix
+ * of their rows) until, in a whole sweep, every pair of rows has the
+ * component of the smaller along the larger at most 16 sqrt(n) DBL_EPSILON
+ * ||A||_F (backward stable: singular values to that absolute level).  Then
+ * A = Q^T Sigma Ubar^T: sigma_i are the row norms of Q A, U^T f = Q f is the
+ * rotated f column, and the solutions are combinations of the rows of Q A
+ * (U and V are never formed).
+ *
+ * mqh_full_svd: sv (n, descending); fhat (n, NULL allowed) = U^T f in the
+ *   same order (f NULL: fhat = 0); sweeps (host, NULL allowed) = Jacobi
+ *   sweeps run; off (host, NULL allowed) = the last sweep's largest
+ *   off-diagonal measure.  MQH_WNOCONV if 100 sweeps did not reach the
+ *   tolerance.
+ * mqh_full_solve: Algorithm 3 (Tikh-Reg: opts->method = MQH_METHOD_HKT,
+ *   the Tikhonov filter, eq. (17)) or the TSVD solution of eq. (14)
+ *   (opts->method = MQH_METHOD_INE_TSVD, the TSVD filter on the full SVD);
+ *   opts->rule MQH_RULE_GCV (eq. (25): N in the denominator; lambda on
+ *   opts->n_grid log-spaced points on [max(sigma_r, 16 eps sigma_1), sigma_1]
+ *   with golden-section refinement; TSVD rank k over 1 .. min(r, n - 1),
+ *   ties to the smaller k) or MQH_RULE_FIXED (lambda_fixed / k_trunc);
+ *   opts->ell and reorth are ignored.  coef (n) out; sv (n, NULL allowed)
+ *   out; info: ell_done = Jacobi sweeps, k_chosen, lambda_chosen, crit =
+ *   GCV at the choice, resid_norm = ||A coef - f|| and sol_norm = ||coef||
+ *   of the returned coef (computed from it, not from the filter formula),
+ *   flags (MQH_INFO_GCV_AT_EDGE), t_ms [0] assembly, [1] Jacobi sweeps,
+ *   [2] singular values and order, [3] parameter choice, [4] solution,
+ *   [5] total, [6] the last sweep's largest off-diagonal measure, [7] the
+ *   conjugate-gradient iterations of the solution.  The solution is
+ *   x = G^T y, G = Q A the rotated rows, with (G G^T + lambda^2 I) y = Q f
+ *   (Tikhonov) or G_k G_k^T y = (Q f)_k on the k rows of the largest sigma
+ *   (TSVD), solved by conjugate gradients preconditioned with the diagonal:
+ *   exact for any orthogonal Q, whether or not the rows are orthogonal.
+ */
+int mqh_full_svd(mqh_problem* p, const double* f, double* sv, double* fhat, int32_t* sweeps, double* off,
+                 uint32_t flags);
+int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts, double* coef,
+                   double* sv, mqh_solve_info* info);
 
 /*
  * The predictor network's kernels (FP32; every array is a device pointer and

@@ -793,6 +793,220 @@ int stage_multi(mqh_problem* p, const double* F, int64_t ldf, int k0, int nz, ui
     return MQH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Full SVD (one-sided block Jacobi on the rows of [A | f]) and the classical
+// regularised solutions on it (Algorithm 3; eq. (14)).  Reference path for
+// n <= MQH_FULL_MAX_N: every call assembles A in FP64 into its own work
+// matrix (n x (n + 1), rows padded to whole 32-row blocks) and frees it.
+// ---------------------------------------------------------------------------
+
+struct FullRun {
+    int64_t n = 0, ldg = 0, nrow = 0;
+    int nblk = 0, npairs = 0, rounds = 0, S = 1;
+    int64_t chunk = 0;
+    double* G = nullptr;
+    int2* pairs = nullptr;
+    double* Pg = nullptr;
+    double* Pout = nullptr;
+    int32_t* flag = nullptr;
+    double* off = nullptr;
+    double* maxoff = nullptr;
+    double* sig = nullptr;
+    double* fh = nullptr;
+    int32_t* rank = nullptr;
+    double* sv = nullptr;
+    double* fs = nullptr;
+    int32_t* order = nullptr;
+    double* tail = nullptr;
+    ParamOut* po = nullptr;
+    double* coef = nullptr;
+    double* f = nullptr;
+    int32_t* rowidx = nullptr;  // the sweep's row order (blocks = runs of 32)
+    double* rnorm = nullptr;    // row norms of all nrow rows
+    double* rtmp = nullptr;
+    double* cq = nullptr;       // conjugate-gradient direction, B q, dot-product terms, G^T q partials, scalars
+    double* cw = nullptr;
+    double* ct = nullptr;
+    double* cpart = nullptr;
+    double* cpc = nullptr;
+    int sweeps = 0;
+    double final_off = 0.0;
+    ~FullRun() {
+        dfree(rowidx);
+        dfree(rnorm);
+        dfree(rtmp);
+        dfree(cq);
+        dfree(cw);
+        dfree(ct);
+        dfree(cpart);
+        dfree(cpc);
+        dfree(G);
+        dfree(pairs);
+        dfree(Pg);
+        dfree(Pout);
+        dfree(flag);
+        dfree(off);
+        dfree(maxoff);
+        dfree(sig);
+        dfree(fh);
+        dfree(rank);
+        dfree(sv);
+        dfree(fs);
+        dfree(order);
+        dfree(tail);
+        dfree(po);
+        dfree(coef);
+        dfree(f);
+    }
+};
+
+constexpr int kFullMaxSweeps = 100;
+constexpr int kFullMaxInner = 15;
+constexpr int kFullCgMax = 64;        // conjugate-gradient iterations of the solutions' dual system
+constexpr double kFullCgTol = 1e-15;  // stop when sqrt(r^T D^-1 r) falls below this fraction of its start
+
+// Assembles [A | f] (f already staged in r.f, or zero) and runs Jacobi
+// sweeps, each on the rows ordered by decreasing norm, until in a whole sweep
+// every pair of rows has the component of the smaller along the larger at
+// most 16 sqrt(n) DBL_EPSILON ||A||_F (or kFullMaxSweeps); then sigma, f^
+// (input row order) and their descending order.
+int full_svd_run(mqh_problem* p, FullRun& r) {
+    hipStream_t s = p->stream;
+    const int64_t n = p->n;
+    r.n = n;
+    r.ldg = round_up(n + 1, 64);
+    r.nblk = (int)((n + kFsBlock - 1) / kFsBlock);
+    if (r.nblk % 2) ++r.nblk;
+    r.nrow = (int64_t)r.nblk * kFsBlock;
+    r.npairs = r.nblk / 2;
+    r.rounds = r.nblk - 1;
+    {
+        int64_t S = (2048 + r.npairs - 1) / r.npairs;
+        const int64_t smax = (n + 63) / 64;
+        if (S > smax) S = smax;
+        if (S < 1) S = 1;
+        r.chunk = round_up((n + S - 1) / S, 64);
+        r.S = (int)((n + r.chunk - 1) / r.chunk);
+    }
+    int rc;
+    if ((rc = dalloc(&r.G, (size_t)(r.nrow * r.ldg))) || (rc = dalloc(&r.pairs, (size_t)r.rounds * r.npairs)) ||
+        (rc = dalloc(&r.Pg, (size_t)r.npairs * r.S * 4096)) || (rc = dalloc(&r.Pout, (size_t)r.npairs * 4096)) ||
+        (rc = dalloc(&r.flag, (size_t)r.npairs)) || (rc = dalloc(&r.off, (size_t)r.rounds * r.npairs)) ||
+        (rc = dalloc(&r.maxoff, 1)) || (rc = dalloc(&r.sig, (size_t)n)) || (rc = dalloc(&r.fh, (size_t)n)) ||
+        (rc = dalloc(&r.rank, (size_t)n)) || (rc = dalloc(&r.sv, (size_t)n)) || (rc = dalloc(&r.fs, (size_t)n)) ||
+        (rc = dalloc(&r.order, (size_t)n)) || (rc = dalloc(&r.tail, (size_t)n + 1)) || (rc = dalloc(&r.po, 1)) ||
+        (rc = dalloc(&r.coef, (size_t)n)) || (rc = dalloc(&r.rowidx, (size_t)r.nrow)) ||
+        (rc = dalloc(&r.rnorm, (size_t)r.nrow)) || (rc = dalloc(&r.rtmp, (size_t)r.nrow)))
+        return rc;
+    // round-robin tournament of the blocks: block 0 stays, the others rotate
+    std::vector<int2> pr((size_t)r.rounds * r.npairs);
+    std::vector<int> pos((size_t)r.nblk);
+    for (int k = 0; k < r.nblk; ++k) pos[(size_t)k] = k;
+    for (int rd = 0; rd < r.rounds; ++rd) {
+        for (int k = 0; k < r.npairs; ++k) {
+            const int a = pos[(size_t)k], b = pos[(size_t)(r.nblk - 1 - k)];
+            pr[(size_t)rd * r.npairs + k] = make_int2(a, b);
+        }
+        const int last = pos[(size_t)(r.nblk - 1)];
+        for (int k = r.nblk - 1; k > 1; --k) pos[(size_t)k] = pos[(size_t)(k - 1)];
+        pos[1] = last;
+    }
+    HIPCHK(hipMemcpyAsync(r.pairs, pr.data(), pr.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(r.G, 0, (size_t)(r.nrow * r.ldg) * sizeof(double), s));
+    launch_assemble(p->X64, n, p->n_int, r.ldg, p->ec, r.G, s);
+    LAUNCHCHK("full SVD: assembly");
+    launch_fs_setf(r.G, r.ldg, n, r.f, s);
+    LAUNCHCHK("full SVD: data column");
+    HIPCHK(hipEventRecord(p->ev[1], s));
+    const double tol = 16.0 * sqrt((double)n) * DBL_EPSILON;
+    std::vector<double> rn((size_t)r.nrow);
+    std::vector<int32_t> idx((size_t)r.nrow);
+    double inv_f = 0.0;
+    r.sweeps = 0;
+    for (int sw = 0; sw < kFullMaxSweeps; ++sw) {
+        // de Rijk's ordering: rows by decreasing norm (stable), blocks of 32
+        launch_fs_norms(r.G, r.ldg, r.nrow, n, r.rnorm, r.rtmp, s);
+        LAUNCHCHK("full SVD: row norms");
+        HIPCHK(hipMemcpyAsync(rn.data(), r.rnorm, (size_t)r.nrow * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (sw == 0) {
+            // ||A||_F (invariant under the rotations)
+            double fro2 = 0.0;
+            for (double v : rn) fro2 += v * v;
+            if (!(fro2 > 0.0) || !isfinite(fro2)) return fail(MQH_EDEVICE, "full SVD: zero or non-finite matrix");
+            inv_f = 1.0 / sqrt(fro2);
+        }
+        for (int64_t i = 0; i < r.nrow; ++i) idx[(size_t)i] = (int32_t)i;
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return rn[(size_t)a] > rn[(size_t)b]; });
+        HIPCHK(hipMemcpyAsync(r.rowidx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        for (int rd = 0; rd < r.rounds; ++rd) {
+            const int2* prd = r.pairs + (int64_t)rd * r.npairs;
+            launch_fs_gram(r.G, r.ldg, n, r.rowidx, prd, r.npairs, r.S, r.chunk, r.Pg, s);
+            launch_fs_eig(r.Pg, r.S, r.npairs, tol, inv_f, kFullMaxInner, r.Pout, r.flag,
+                          r.off + (int64_t)rd * r.npairs, s);
+            launch_fs_update(r.G, r.ldg, n + 1, r.rowidx, prd, r.npairs, r.Pout, r.flag, s);
+        }
+        LAUNCHCHK("full SVD: Jacobi sweep");
+        launch_fs_maxoff(r.off, (int64_t)r.rounds * r.npairs, r.maxoff, s);
+        double mo = 0.0;
+        HIPCHK(hipMemcpyAsync(&mo, r.maxoff, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        r.sweeps = sw + 1;
+        r.final_off = mo;
+        if (!(mo > tol)) break;
+    }
+    HIPCHK(hipEventRecord(p->ev[2], s));
+    launch_fs_norms(r.G, r.ldg, n, n, r.sig, r.fh, s);
+    launch_fs_rank(r.sig, r.fh, n, r.rank, r.sv, r.fs, r.order, s);
+    LAUNCHCHK("full SVD: singular values");
+    HIPCHK(hipEventRecord(p->ev[3], s));
+    return MQH_OK;
+}
+
+// The solution x = G^T y of the Tikhonov (method 1) or TSVD (method 0) dual
+// system by preconditioned conjugate gradients (the kernels' comment gives
+// the system); y in r.rnorm, the residual in r.rtmp, x in r.coef; then
+// po->rho = ||A x - f|| and po->eta = ||x|| of that x.
+int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters) {
+    hipStream_t s = p->stream;
+    const int64_t n = p->n;
+    int rc;
+    const int chunks = fs_gemvt_chunks(n);
+    if ((rc = dalloc(&r.cq, (size_t)n)) || (rc = dalloc(&r.cw, (size_t)n)) || (rc = dalloc(&r.ct, (size_t)n)) ||
+        (rc = dalloc(&r.cpart, (size_t)chunks * (size_t)n)) || (rc = dalloc(&r.cpc, 4)))
+        return rc;
+    double* y = r.rnorm;
+    double* res = r.rtmp;
+    launch_fs_pcg_start(r.sig, r.fh, r.rank, n, method, r.po, y, res, r.cq, r.ct, r.cpc, 2, s);
+    LAUNCHCHK("full problem: solution start");
+    double rz0 = 0.0;
+    HIPCHK(hipMemcpyAsync(&rz0, r.cpc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!isfinite(rz0)) return fail(MQH_EDEVICE, "full problem: non-finite right-hand side of the solution");
+    int it = 0;
+    if (rz0 > 0.0) {
+        const double stop = kFullCgTol * kFullCgTol * rz0;
+        while (it < kFullCgMax) {
+            const int cur = 2 + (it & 1), nxt = 2 + ((it + 1) & 1);
+            launch_fs_pcg_iter(r.G, r.ldg, n, r.sig, r.rank, method, r.po, r.cpc, cur, nxt, y, res, r.cq, r.cw, r.ct,
+                               r.cpart, r.coef, s);
+            LAUNCHCHK("full problem: solution iteration");
+            double rz = 0.0;
+            HIPCHK(hipMemcpyAsync(&rz, r.cpc + nxt, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ++it;
+            if (!isfinite(rz)) return fail(MQH_EDEVICE, "full problem: non-finite solution iterate");
+            if (!(rz > stop)) break;
+            launch_fs_pcg_dir(r.sig, r.rank, n, method, r.po, r.cpc, cur, nxt, res, r.cq, s);
+        }
+    }
+    launch_fs_gemvt(r.G, r.ldg, n, y, r.cpart, r.coef, s);
+    launch_fs_solution_norms(r.G, r.ldg, n, r.coef, r.fh, r.ct, r.cw, r.cpc, r.po, s);
+    LAUNCHCHK("full problem: solution");
+    *iters = it;
+    return MQH_OK;
+}
+
 int stage_in(double* dst, const double* src, int64_t count, uint32_t flags, hipStream_t s) {
     if (count <= 0) return MQH_OK;
     if (!(flags & MQH_FLAG_DEVICE_PTRS) && !all_finite(src, count)) return fail(MQH_EINVAL, "non-finite input");
@@ -844,6 +1058,7 @@ const char* mqh_status_str(int status) {
         case MQH_EDEVICE: return "device error";
         case MQH_WBREAKDOWN: return "Golub-Kahan breakdown (fewer steps kept)";
         case MQH_WEDGE: return "parameter at the end of the search grid";
+        case MQH_WNOCONV: return "full SVD: Jacobi sweeps stopped at their limit";
         default: return "unknown status";
     }
 }
@@ -1468,6 +1683,101 @@ int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* 
     for (int32_t k = 0; k < count; ++k)
         if (items[k].status == MQH_WBREAKDOWN || (items[k].status == MQH_WEDGE && worst == MQH_OK)) worst = items[k].status;
     return worst;
+}
+
+int mqh_full_svd(mqh_problem* p, const double* f, double* sv, double* fhat, int32_t* sweeps, double* off,
+                 uint32_t flags) {
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (sv == nullptr) return fail(MQH_EINVAL, "NULL sv");
+    if (p->n > MQH_FULL_MAX_N) return fail(MQH_EINVAL, "the full SVD takes n <= MQH_FULL_MAX_N");
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t s = p->stream;
+    FullRun r;
+    if (f != nullptr) {
+        if ((rc = dalloc(&r.f, (size_t)p->n))) return rc;
+        if ((rc = stage_in(r.f, f, p->n, flags, s))) return rc;
+    }
+    HIPCHK(hipEventRecord(p->ev[0], s));
+    if ((rc = full_svd_run(p, r))) return rc;
+    const hipMemcpyKind ko = kind_out(flags);
+    HIPCHK(hipMemcpyAsync(sv, r.sv, (size_t)p->n * sizeof(double), ko, s));
+    if (fhat) HIPCHK(hipMemcpyAsync(fhat, r.fs, (size_t)p->n * sizeof(double), ko, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (sweeps) *sweeps = r.sweeps;
+    if (off) *off = r.final_off;
+    return r.final_off > 16.0 * sqrt((double)p->n) * DBL_EPSILON ? MQH_WNOCONV : MQH_OK;
+}
+
+int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts, double* coef,
+                   double* sv, mqh_solve_info* info) {
+    clear_info(info);
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (opts == nullptr) return fail(MQH_EINVAL, "NULL opts");
+    if (coef == nullptr) return fail(MQH_EINVAL, "NULL coef");
+    if ((p->n_int > 0 && f_int == nullptr) || (p->n_bnd > 0 && g_bnd == nullptr)) return fail(MQH_EINVAL, "NULL data");
+    if (p->n > MQH_FULL_MAX_N) return fail(MQH_EINVAL, "the full SVD takes n <= MQH_FULL_MAX_N");
+    if (opts->method != MQH_METHOD_HKT && opts->method != MQH_METHOD_INE_TSVD)
+        return fail(MQH_EINVAL, "method: MQH_METHOD_HKT (Tikhonov filter) or MQH_METHOD_INE_TSVD (TSVD filter)");
+    if (opts->rule != MQH_RULE_GCV && opts->rule != MQH_RULE_FIXED)
+        return fail(MQH_EINVAL, "rule: MQH_RULE_GCV or MQH_RULE_FIXED");
+    const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
+    if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
+    const bool tikh = opts->method == MQH_METHOD_HKT;
+    if (tikh && opts->rule == MQH_RULE_FIXED && (!isfinite(opts->lambda_fixed) || opts->lambda_fixed < 0.0))
+        return fail(MQH_EINVAL, "lambda_fixed must be finite and >= 0");
+    if (!tikh && opts->rule == MQH_RULE_FIXED && (opts->k_trunc < 1 || opts->k_trunc > p->n))
+        return fail(MQH_EINVAL, "k_trunc must be in [1, n]");
+    const uint32_t flags = opts->flags;
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t s = p->stream;
+    FullRun r;
+    if ((rc = dalloc(&r.f, (size_t)p->n))) return rc;
+    if ((rc = stage_in(r.f, f_int, p->n_int, flags, s))) return rc;
+    if ((rc = stage_in(r.f + p->n_int, g_bnd, p->n_bnd, flags, s))) return rc;
+    HIPCHK(hipEventRecord(p->ev[0], s));
+    // ||f||^2 for s_perp (on the host from the staged copy: one read of n values)
+    std::vector<double> fh((size_t)p->n);
+    HIPCHK(hipMemcpyAsync(fh.data(), r.f, (size_t)p->n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double fn2 = 0.0;
+    for (double v : fh) fn2 += v * v;
+    if (!isfinite(fn2)) return fail(MQH_EINVAL, "non-finite right-hand side");
+    if ((rc = full_svd_run(p, r))) return rc;
+    launch_full_param(r.sv, r.fs, p->n, fn2, tikh ? 1 : 0, opts->rule == MQH_RULE_FIXED ? 2 : 0, J,
+                      opts->lambda_fixed, opts->k_trunc, r.tail, r.po, s);
+    LAUNCHCHK("full problem: parameter choice");
+    HIPCHK(hipEventRecord(p->ev[4], s));
+    int cg_iters = 0;
+    if ((rc = full_solution(p, r, tikh ? 1 : 0, &cg_iters))) return rc;
+    HIPCHK(hipEventRecord(p->ev[5], s));
+    ParamOut po;
+    HIPCHK(hipMemcpyAsync(&po, r.po, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
+    const hipMemcpyKind ko = kind_out(flags);
+    HIPCHK(hipMemcpyAsync(coef, r.coef, (size_t)p->n * sizeof(double), ko, s));
+    if (sv) HIPCHK(hipMemcpyAsync(sv, r.sv, (size_t)p->n * sizeof(double), ko, s));
+    HIPCHK(hipEventRecord(p->ev[6], s));
+    HIPCHK(hipStreamSynchronize(s));
+    const bool noconv = r.final_off > 16.0 * sqrt((double)p->n) * DBL_EPSILON;
+    if (info) {
+        info->ell_done = r.sweeps;
+        info->k_chosen = po.k;
+        info->lambda_chosen = po.lambda;
+        info->crit = po.crit;
+        info->resid_norm = po.rho;
+        info->sol_norm = po.eta;
+        info->flags = po.flags;
+        float ms = 0.f;
+        const int pairs[6][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {0, 6}};
+        for (int q = 0; q < 6; ++q)
+            if (hipEventElapsedTime(&ms, p->ev[pairs[q][0]], p->ev[pairs[q][1]]) == hipSuccess) info->t_ms[q] = ms;
+        info->t_ms[6] = (float)r.final_off;
+        info->t_ms[7] = cg_iters;
+    }
+    if (noconv) return MQH_WNOCONV;
+    if (po.flags & MQH_INFO_GCV_AT_EDGE) return MQH_WEDGE;
+    return MQH_OK;
 }
 
 int mqh_eval(mqh_problem* p, const double* coef, const double* x_eval, int64_t m, double* u, uint32_t flags) {

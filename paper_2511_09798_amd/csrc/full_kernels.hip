@@ -1,0 +1,757 @@
+// full_kernels.hip -- full SVD of the collocation matrix on gfx950 (FP64) and
+// the classical regularised solutions built on it: Tikhonov with the GCV of
+// the full problem (Algorithm 3, eq. (25)) and truncated SVD (eq. (14)).
+//
+// One-sided block Jacobi on the rows of the work matrix G = [A | f]
+// (row-major, leading dimension ldg >= n + 1, rows padded with zero rows to a
+// whole number of 32-row blocks).  Each sweep first orders the rows by
+// decreasing norm (de Rijk's ordering; blocks are runs of 32 rows in that
+// order, through an index, the rows stay in place); a round pairs the blocks
+// (a round-robin tournament, so a sweep meets every pair once); for a pair, X = the 64 rows
+// of its two blocks, M = X_A X_A^T is their Gram matrix over the A columns,
+// M = P diag P^T its eigendecomposition (cyclic Jacobi in LDS), and X <- P^T X
+// makes the 64 rows mutually orthogonal.  The rotations act on the f column
+// too.  At convergence G = Q [A | f] with Q orthogonal and the rows of Q A
+// orthogonal: A = Q^T Sigma Ubar^T, so the singular values are the row norms
+// sigma_i of Q A, U^T f = Q f is the last column (f^_i), and the Tikhonov
+// solution is sum_i f^_i / (sigma_i^2 + lambda^2) (row i of Q A)^T: neither U
+// nor V is ever formed.
+//
+// The two products of a round (the Gram matrices and the update) run on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] and receives D[4r + l/16][l%16], r = 0..3).
+#include <float.h>
+#include <math.h>
+
+#include "kernels.hpp"
+
+namespace mqh {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kFsRows = 2 * kFsBlock;  // rows of a pair (64)
+constexpr int kFsLd = kFsRows + 1;     // LDS row of a 64 x 64 FP64 tile (padded)
+
+// Row of the work matrix holding row r (0..63) of pair (bi, bj): block b
+// consists of the rows rowidx[32 b .. 32 b + 31] (the sweep's order).
+__device__ __forceinline__ int64_t pair_row(const int32_t* __restrict__ rowidx, int2 pr, int r) {
+    return rowidx[r < kFsBlock ? pr.x * kFsBlock + r : pr.y * kFsBlock + (r - kFsBlock)];
+}
+
+// Columns [c0, c0 + 64) of the pair's 64 rows into an LDS tile (zeros past cend).
+__device__ __forceinline__ void load_tile(const double* __restrict__ G, int64_t ldg, const int32_t* __restrict__ rowidx,
+                                          int2 pr, int64_t c0, int64_t cend, double* __restrict__ t) {
+    const int r = threadIdx.x >> 2, cb = (threadIdx.x & 3) * 16;
+    const double* src = G + pair_row(rowidx, pr, r) * ldg + c0 + cb;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t[r * kFsLd + cb + q] = (c0 + cb + q < cend) ? src[q] : 0.0;
+}
+
+// Partial Gram matrices: Pg[(pair * S + chunk)][a][b] = sum over the chunk's
+// columns c < ncol of X[a][c] X[b][c].  Grid (S, pairs), 256 threads: wave w
+// forms rows 16w .. 16w + 15 of the 64 x 64 result.
+__global__ __launch_bounds__(kBlock) void k_fs_gram(const double* __restrict__ G, int64_t ldg, int64_t ncol,
+                                                    const int32_t* __restrict__ rowidx,
+                                                    const int2* __restrict__ pairs, int64_t chunk,
+                                                    double* __restrict__ Pg) {
+    __shared__ double t[kFsRows * kFsLd];
+    const int2 pr = pairs[blockIdx.y];
+    const int S = gridDim.x;
+    const int64_t c0 = (int64_t)blockIdx.x * chunk;
+    const int64_t c1 = c0 + chunk < ncol ? c0 + chunk : ncol;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4;
+    v4d acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t c = c0; c < c1; c += kFsRows) {
+        __syncthreads();  // the previous tile has been consumed
+        load_tile(G, ldg, rowidx, pr, c, c1, t);
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < kFsRows; kk += 4) {
+            const double a = t[(16 * w + li) * kFsLd + kk + lk];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double b = t[(16 * q + li) * kFsLd + kk + lk];
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+            }
+        }
+    }
+    double* out = Pg + ((int64_t)blockIdx.y * S + blockIdx.x) * (kFsRows * kFsRows);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(16 * w + 4 * r + lk) * kFsRows + 16 * q + li] = acc[q][r];
+}
+
+// Largest |M_ab| / (max(||x_a||, ||x_b||) F) over a != b, F = ||A||_F given as
+// inv_f = 1 / F (block-wide, every thread gets it): the component of the
+// smaller row along the larger one relative to the matrix's norm.  Below
+// c sqrt(n) eps the rows are orthogonal to the rounding level of a dense
+// SVD (backward stable: singular values to c sqrt(n) eps ||A||_F); a
+// relative cosine test cannot be met by rows near that level, which every
+// sweep renews.  M in LDS with row length kFsLd.
+__device__ double offdiag(const double* __restrict__ M, double inv_f, double* __restrict__ red) {
+    double mx = 0.0;
+    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock) {
+        const int a = e / kFsRows, b = e % kFsRows;
+        if (a == b) continue;
+        const double ma = M[a * kFsLd + a], mb = M[b * kFsLd + b];
+        const double mm = ma > mb ? ma : mb;
+        if (mm > 0.0) {
+            const double v = fabs(M[a * kFsLd + b]) / sqrt(mm) * inv_f;
+            mx = v > mx ? v : mx;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_xor(mx, o, kWave);
+        mx = y > mx ? y : mx;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < kBlock / kWave; ++i) r = red[i] > r ? red[i] : r;
+    __syncthreads();
+    return r;
+}
+
+// One workgroup per pair: M = sum of the S partial Grams; off[pair] = its
+// off-diagonal measure (offdiag); if above tol, cyclic Jacobi (round-robin
+// order, 32 disjoint rotations per step, 63 steps per sweep, rotations
+// skipped when |M_pq| <= eps/4 sqrt(M_pp M_qq); until the measure is below
+// eps or max_inner sweeps) gives M = P diag P^T, and P goes to Pout[pair]
+// with flag[pair] = 1; else flag 0.
+__global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg, int S, double tol, double inv_f,
+                                                   int max_inner, double* __restrict__ Pout,
+                                                   int32_t* __restrict__ flag, double* __restrict__ off) {
+    __shared__ double M[kFsRows * kFsLd];
+    __shared__ double P[kFsRows * kFsLd];
+    __shared__ double red[kBlock / kWave];
+    __shared__ double rc[kFsRows / 2], rs[kFsRows / 2];
+    __shared__ int rp[kFsRows / 2], rq[kFsRows / 2];
+    const int pair = blockIdx.x;
+    const double* src = Pg + (int64_t)pair * S * (kFsRows * kFsRows);
+    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock) {
+        double v = 0.0;
+        for (int s = 0; s < S; ++s) v += src[(int64_t)s * (kFsRows * kFsRows) + e];
+        const int a = e / kFsRows, b = e % kFsRows;
+        M[a * kFsLd + b] = v;
+        P[a * kFsLd + b] = a == b ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const double o0 = offdiag(M, inv_f, red);
+    if (threadIdx.x == 0) off[pair] = o0;
+    if (!(o0 > tol)) {
+        if (threadIdx.x == 0) flag[pair] = 0;
+        return;
+    }
+    const double tol_in = DBL_EPSILON;
+    for (int sweep = 0; sweep < max_inner; ++sweep) {
+        for (int step = 0; step < kFsRows - 1; ++step) {
+            if (threadIdx.x < kFsRows / 2) {
+                // round-robin: position 0 fixed, the others rotate by one per step
+                const int k = threadIdx.x;
+                const int ia = k == 0 ? 0 : 1 + (k - 1 + step) % (kFsRows - 1);
+                const int ib = 1 + (kFsRows - 2 - k + step) % (kFsRows - 1);
+                const int p = ia < ib ? ia : ib, q = ia < ib ? ib : ia;
+                const double a = M[p * kFsLd + p], d = M[q * kFsLd + q], b = M[p * kFsLd + q];
+                double c = 1.0, s = 0.0;
+                if (b != 0.0 && fabs(b) > DBL_EPSILON * 0.25 * sqrt(fabs(a * d))) {
+                    const double tau = (d - a) / (2.0 * b);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                }
+                rp[k] = p;
+                rq[k] = q;
+                rc[k] = c;
+                rs[k] = s;
+            }
+            __syncthreads();
+            // rows: M <- J^T M
+            for (int e = threadIdx.x; e < (kFsRows / 2) * kFsRows; e += kBlock) {
+                const int k = e / kFsRows, j = e % kFsRows;
+                const int p = rp[k], q = rq[k];
+                const double c = rc[k], s = rs[k];
+                const double mp = M[p * kFsLd + j], mq = M[q * kFsLd + j];
+                M[p * kFsLd + j] = c * mp - s * mq;
+                M[q * kFsLd + j] = s * mp + c * mq;
+            }
+            __syncthreads();
+            // columns: M <- M J, P <- P J
+            for (int e = threadIdx.x; e < (kFsRows / 2) * kFsRows; e += kBlock) {
+                const int k = e / kFsRows, i = e % kFsRows;
+                const int p = rp[k], q = rq[k];
+                const double c = rc[k], s = rs[k];
+                const double mp = M[i * kFsLd + p], mq = M[i * kFsLd + q];
+                M[i * kFsLd + p] = c * mp - s * mq;
+                M[i * kFsLd + q] = s * mp + c * mq;
+                const double pp = P[i * kFsLd + p], pq = P[i * kFsLd + q];
+                P[i * kFsLd + p] = c * pp - s * pq;
+                P[i * kFsLd + q] = s * pp + c * pq;
+            }
+            __syncthreads();
+        }
+        if (!(offdiag(M, inv_f, red) > tol_in)) break;
+    }
+    double* dst = Pout + (int64_t)pair * (kFsRows * kFsRows);
+    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock)
+        dst[e] = P[(e / kFsRows) * kFsLd + e % kFsRows];
+    if (threadIdx.x == 0) flag[pair] = 1;
+}
+
+// X <- P^T X on the pair's 64 rows, columns [64 bx, 64 bx + 64) of ncol (all
+// columns, the f column included).  Skipped when flag[pair] = 0.
+__global__ __launch_bounds__(kBlock) void k_fs_update(double* __restrict__ G, int64_t ldg, int64_t ncol,
+                                                      const int32_t* __restrict__ rowidx,
+                                                      const int2* __restrict__ pairs,
+                                                      const double* __restrict__ Pin,
+                                                      const int32_t* __restrict__ flag) {
+    __shared__ double Pt[kFsRows * kFsLd];
+    __shared__ double t[kFsRows * kFsLd];
+    const int pair = blockIdx.y;
+    if (flag[pair] == 0) return;  // block-uniform
+    const int2 pr = pairs[pair];
+    const int64_t c0 = (int64_t)blockIdx.x * kFsRows;
+    const double* P = Pin + (int64_t)pair * (kFsRows * kFsRows);
+    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock) Pt[(e / kFsRows) * kFsLd + e % kFsRows] = P[e];
+    load_tile(G, ldg, rowidx, pr, c0, ncol, t);
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4;
+    v4d acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    // Y[i][c] = sum_k P[k][i] X[k][c]: A[i][k] = P[k][i], B[k][c] = X[k][c]
+#pragma unroll 4
+    for (int kk = 0; kk < kFsRows; kk += 4) {
+        const double a = Pt[(kk + lk) * kFsLd + 16 * w + li];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double b = t[(kk + lk) * kFsLd + 16 * q + li];
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t col = c0 + 16 * q + li;
+        if (col >= ncol) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) G[pair_row(rowidx, pr, 16 * w + 4 * r + lk) * ldg + col] = acc[q][r];
+    }
+}
+
+// Largest entry of off[0 .. count) into *out (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_fs_maxoff(const double* __restrict__ off, int64_t count,
+                                                      double* __restrict__ out) {
+    __shared__ double red[kBlock / kWave];
+    double mx = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += kBlock) mx = off[i] > mx ? off[i] : mx;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_xor(mx, o, kWave);
+        mx = y > mx ? y : mx;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (int i = 0; i < kBlock / kWave; ++i) r = red[i] > r ? red[i] : r;
+        *out = r;
+    }
+}
+
+// sigma_i = ||row i of Q A|| (columns < n), fhat_i = G[i][n]; one workgroup per row.
+__global__ __launch_bounds__(kBlock) void k_fs_norms(const double* __restrict__ G, int64_t ldg, int64_t n,
+                                                     double* __restrict__ sig, double* __restrict__ fh) {
+    // grid: one workgroup per row (any number of rows; columns < n)
+    __shared__ double lds[kBlock / kWave];
+    const int64_t i = blockIdx.x;
+    const double* row = G + i * ldg;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += kBlock) s = fma(row[j], row[j], s);
+    s = block_sum<kBlock>(s, lds);
+    if (threadIdx.x == 0) {
+        sig[i] = sqrt(s);
+        fh[i] = row[n];
+    }
+}
+
+// Descending order: rank[i] = #{j : sig_j > sig_i or (sig_j == sig_i and j < i)};
+// sv[rank] = sig_i, fs[rank] = fh_i, order[rank] = i.
+__global__ __launch_bounds__(kBlock) void k_fs_rank(const double* __restrict__ sig, const double* __restrict__ fh,
+                                                    int64_t n, int32_t* __restrict__ rank, double* __restrict__ sv,
+                                                    double* __restrict__ fs, int32_t* __restrict__ order) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double si = sig[i];
+    int64_t rk = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        const double sj = sig[j];
+        rk += (sj > si || (sj == si && j < i)) ? 1 : 0;
+    }
+    rank[i] = (int32_t)rk;
+    sv[rk] = si;
+    fs[rk] = fh[i];
+    order[rk] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Parameter choice on the full problem (eq. (25)): sv descending (n values,
+// the r > 0 ones used), fs = U^T f in the same order, s_perp = ||f||^2 -
+// sum fs^2 (clamped at 0).  Tikhonov: GCV(lambda) on J log-spaced points on
+// [max(sigma_r, 16 eps sigma_1), sigma_1], golden-section refinement of
+// log lambda over the two cells around the grid minimum (ties to the larger
+// lambda, a minimum at an end kept with the edge flag) -- the rule of the
+// projected problem with N in the denominator.  TSVD: k minimising
+// (sum_{i>k} fs_i^2 + s_perp) / (N - k)^2 over k = 1 .. min(r, N - 1), ties to
+// the smaller k.  FIXED: lambda_fixed or k_fixed.  One workgroup.
+// ---------------------------------------------------------------------------
+
+__device__ double full_gcv(const double* __restrict__ sv, const double* __restrict__ fs, int64_t r, int64_t n,
+                           double sperp, double lam, double* __restrict__ lds) {
+    const double l2 = lam * lam;
+    double a = 0.0, t = 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += kBlock) {
+        const double s2 = sv[i] * sv[i];
+        const double den = s2 + l2;
+        const double x = l2 / den * fs[i];
+        a = fma(x, x, a);
+        t += s2 / den;
+    }
+    a = block_sum<kBlock>(a, lds);
+    t = block_sum<kBlock>(t, lds);
+    const double d = (double)n - t;
+    return (a + sperp) / (d * d);
+}
+
+__global__ __launch_bounds__(kBlock) void k_full_param(const double* __restrict__ sv, const double* __restrict__ fs,
+                                                       int64_t n, double fnorm2, int32_t method, int32_t rule,
+                                                       int32_t J, double lambda_fixed, int32_t k_fixed,
+                                                       double* __restrict__ tail, ParamOut* __restrict__ out) {
+    __shared__ double lds[kBlock / kWave];
+    __shared__ double vals[kMaxGrid];
+    __shared__ int64_t s_r;
+    if (threadIdx.x == 0) {
+        int64_t r = 0;
+        while (r < n && sv[r] > 0.0) ++r;
+        s_r = r;
+    }
+    __syncthreads();
+    const int64_t r = s_r;
+    double ssum = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) ssum = fma(fs[i], fs[i], ssum);
+    ssum = block_sum<kBlock>(ssum, lds);
+    const double sperp = fnorm2 - ssum > 0.0 ? fnorm2 - ssum : 0.0;
+    uint32_t flags = 0;
+    if (method == 0) {  // TSVD
+        int64_t k = 1;
+        double crit = 0.0;
+        const int64_t kmax = r < n - 1 ? r : n - 1;
+        if (threadIdx.x == 0) {
+            // tail[k] = sum_{i >= k} fs_i^2 over the r retained values, k = 0 .. r
+            double acc = 0.0;
+            tail[r] = 0.0;
+            for (int64_t i = r - 1; i >= 0; --i) {
+                acc = fma(fs[i], fs[i], acc);
+                tail[i] = acc;
+            }
+        }
+        __syncthreads();
+        if (rule == 2) {
+            k = k_fixed < 1 ? 1 : (k_fixed > r ? r : k_fixed);
+            const double d = (double)(n - k);
+            crit = d > 0.0 ? (tail[k] + sperp) / (d * d) : 0.0;
+        } else if (kmax >= 1) {
+            // argmin over k = 1 .. kmax, ties to the smaller k
+            double best = 0.0;
+            int64_t bk = -1;
+            for (int64_t kk = 1 + threadIdx.x; kk <= kmax; kk += kBlock) {
+                const double d = (double)(n - kk);
+                const double g = (tail[kk] + sperp) / (d * d);
+                if (bk < 0 || g < best) {
+                    best = g;
+                    bk = kk;
+                }
+            }
+            __shared__ double bv[kBlock];
+            __shared__ int64_t bi[kBlock];
+            bv[threadIdx.x] = best;
+            bi[threadIdx.x] = bk;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double b = 0.0;
+                int64_t kb = -1;
+                for (int q = 0; q < kBlock; ++q) {
+                    if (bi[q] < 0) continue;
+                    if (kb < 0 || bv[q] < b || (bv[q] == b && bi[q] < kb)) {
+                        b = bv[q];
+                        kb = bi[q];
+                    }
+                }
+                s_r = kb;
+                lds[0] = b;
+            }
+            __syncthreads();
+            k = s_r;
+            crit = lds[0];
+            if (k == 1 || k == kmax) flags |= 2u;
+        }
+        if (threadIdx.x == 0) {
+            double eta2 = 0.0;
+            for (int64_t i = 0; i < k; ++i) eta2 += (fs[i] / sv[i]) * (fs[i] / sv[i]);
+            out->lambda = 0.0;
+            out->k = (int32_t)k;
+            out->crit = crit;
+            out->flags = flags;
+            out->rho = sqrt(tail[k] + sperp);
+            out->eta = sqrt(eta2);
+        }
+        return;
+    }
+    // Tikhonov
+    double lam;
+    double crit;
+    if (rule == 2 || r == 0) {
+        lam = r == 0 ? 0.0 : lambda_fixed;
+        crit = r == 0 ? 0.0 : full_gcv(sv, fs, r, n, sperp, lam, lds);
+    } else {
+        const double s1 = sv[0];
+        double lo = sv[r - 1];
+        if (lo < 16.0 * DBL_EPSILON * s1) lo = 16.0 * DBL_EPSILON * s1;
+        if (!(lo < s1)) lo = 16.0 * DBL_EPSILON * s1;
+        const double llo = log(lo), lhi = log(s1);
+        for (int j = 0; j < J; ++j) {
+            const double lj = exp(llo + (lhi - llo) * j / (J - 1));
+            const double g = full_gcv(sv, fs, r, n, sperp, lj, lds);
+            if (threadIdx.x == 0) vals[j] = g;
+        }
+        __syncthreads();
+        int jb = 0;
+        for (int j = 1; j < J; ++j)
+            if (vals[j] <= vals[jb]) jb = j;  // ties to the larger lambda
+        lam = exp(llo + (lhi - llo) * jb / (J - 1));
+        crit = vals[jb];
+        if (jb == 0 || jb == J - 1) {
+            flags |= 2u;
+        } else {
+            // golden section on log lambda over [grid jb-1, grid jb+1]
+            double a = llo + (lhi - llo) * (jb - 1) / (J - 1), b = llo + (lhi - llo) * (jb + 1) / (J - 1);
+            const double gr = 0.5 * (sqrt(5.0) - 1.0);
+            double x1 = b - gr * (b - a), x2 = a + gr * (b - a);
+            double f1 = full_gcv(sv, fs, r, n, sperp, exp(x1), lds), f2 = full_gcv(sv, fs, r, n, sperp, exp(x2), lds);
+            for (int it = 0; it < 200 && (b - a) > 1e-10; ++it) {
+                if (f1 <= f2) {
+                    b = x2;
+                    x2 = x1;
+                    f2 = f1;
+                    x1 = b - gr * (b - a);
+                    f1 = full_gcv(sv, fs, r, n, sperp, exp(x1), lds);
+                } else {
+                    a = x1;
+                    x1 = x2;
+                    f1 = f2;
+                    x2 = a + gr * (b - a);
+                    f2 = full_gcv(sv, fs, r, n, sperp, exp(x2), lds);
+                }
+            }
+            const double xm = 0.5 * (a + b);
+            const double gm = full_gcv(sv, fs, r, n, sperp, exp(xm), lds);
+            if (gm <= crit) {
+                lam = exp(xm);
+                crit = gm;
+            }
+        }
+    }
+    // residual and solution norms at lambda
+    const double l2 = lam * lam;
+    double rho2 = 0.0, eta2 = 0.0;
+    for (int64_t i = threadIdx.x; i < r; i += kBlock) {
+        const double s2 = sv[i] * sv[i];
+        const double den = s2 + l2;
+        const double x = l2 / den * fs[i];
+        const double y = sv[i] / den * fs[i];
+        rho2 = fma(x, x, rho2);
+        eta2 = fma(y, y, eta2);
+    }
+    rho2 = block_sum<kBlock>(rho2, lds);
+    eta2 = block_sum<kBlock>(eta2, lds);
+    if (threadIdx.x == 0) {
+        out->lambda = lam;
+        out->k = 0;
+        out->crit = crit;
+        out->flags = flags;
+        out->rho = sqrt(rho2 + sperp);
+        out->eta = sqrt(eta2);
+    }
+}
+
+// The solutions.  With G = Q A (Q orthogonal), the Tikhonov solution is
+// exactly x = G^T y with (G G^T + lambda^2 I) y = Q f = f^; the TSVD solution
+// of rank k is x = G_k^T y with G_k G_k^T y = f^_k over the k rows of the
+// largest sigma.  Neither needs the rows to be orthogonal, only Q to be.
+// G G^T = diag(sigma^2) + E, E the rows' remaining off-diagonal products:
+// the convergence test bounds E_ij by tol ||A||_F max(sigma_i, sigma_j), so
+// rows with sigma near lambda keep couplings of order tol ||A||_F / lambda
+// after scaling, which the solution's large cancelling coefficients do not
+// forgive.  The system is solved by conjugate gradients preconditioned with
+// its diagonal d_i = sigma_i^2 + lambda^2 (resp. sigma_i^2 on the k rows),
+// from y = 0, until sqrt(r^T D^-1 r) <= 1e-15 of its start (the attainable
+// level) or an iteration cap.  One iteration: x = G^T q (split over row
+// chunks), w = G x + lambda^2 q, two dot products, the updates.
+
+// d_i of row i (0: row not in the solution).
+__device__ __forceinline__ double sol_diag(double sig, int32_t rank, int32_t method, double l2, int64_t k) {
+    const double s2 = sig * sig;
+    if (method == 0) return (rank < k && s2 > 0.0) ? s2 : 0.0;
+    return s2 + l2;
+}
+
+__device__ __forceinline__ double sol_l2(int32_t method, const ParamOut* po) {
+    return method == 0 ? 0.0 : po->lambda * po->lambda;
+}
+
+// y = 0, r = b (active rows), q = D^-1 r, t_i = r_i q_i.
+__global__ __launch_bounds__(kBlock) void k_fs_pcg_start(const double* __restrict__ sig,
+                                                         const double* __restrict__ fh,
+                                                         const int32_t* __restrict__ rank, int64_t n, int32_t method,
+                                                         const ParamOut* __restrict__ po, double* __restrict__ y,
+                                                         double* __restrict__ r, double* __restrict__ q,
+                                                         double* __restrict__ t) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k);
+    const double b = d > 0.0 ? fh[i] : 0.0;
+    y[i] = 0.0;
+    r[i] = b;
+    q[i] = d > 0.0 ? b / d : 0.0;
+    t[i] = d > 0.0 ? b * b / d : 0.0;
+}
+
+// part[c][j] = sum over the rows i of chunk c (rows < n) of q_i G[i][j]; grid
+// (columns / kBlock, chunks), one thread per column.
+__global__ __launch_bounds__(kBlock) void k_fs_gemvt_part(const double* __restrict__ G, int64_t ldg, int64_t n,
+                                                          int64_t rows_per_chunk, const double* __restrict__ q,
+                                                          double* __restrict__ part) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const int64_t i0 = (int64_t)blockIdx.y * rows_per_chunk;
+    const int64_t i1 = i0 + rows_per_chunk < n ? i0 + rows_per_chunk : n;
+    double s0 = 0.0, s1 = 0.0;
+    int64_t i = i0;
+    for (; i + 1 < i1; i += 2) {
+        s0 = fma(q[i], G[i * ldg + j], s0);
+        s1 = fma(q[i + 1], G[(i + 1) * ldg + j], s1);
+    }
+    if (i < i1) s0 = fma(q[i], G[i * ldg + j], s0);
+    part[(int64_t)blockIdx.y * n + j] = s0 + s1;
+}
+
+// x_j = sum_c part[c][j], chunks in order.
+__global__ __launch_bounds__(kBlock) void k_fs_colsum(const double* __restrict__ part, int chunks, int64_t n,
+                                                      double* __restrict__ x) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + j];
+    x[j] = s;
+}
+
+// w_i = G[i] . x + lambda^2 q_i on active rows (0 elsewhere), t_i = q_i w_i;
+// one workgroup per row.
+__global__ __launch_bounds__(kBlock) void k_fs_pcg_matvec(const double* __restrict__ G, int64_t ldg, int64_t n,
+                                                          const double* __restrict__ x,
+                                                          const double* __restrict__ sig,
+                                                          const int32_t* __restrict__ rank, int32_t method,
+                                                          const ParamOut* __restrict__ po,
+                                                          const double* __restrict__ q, double* __restrict__ w,
+                                                          double* __restrict__ t) {
+    __shared__ double lds[kBlock / kWave];
+    const int64_t i = blockIdx.x;
+    const double* row = G + i * ldg;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += kBlock) s = fma(row[j], x[j], s);
+    s = block_sum<kBlock>(s, lds);
+    if (threadIdx.x == 0) {
+        const double l2 = sol_l2(method, po);
+        const double d = sol_diag(sig[i], rank[i], method, l2, po->k);
+        const double wi = d > 0.0 ? s + l2 * q[i] : 0.0;
+        w[i] = wi;
+        t[i] = q[i] * wi;
+    }
+}
+
+// pc[slot] = sum_i t_i (one workgroup, fixed order).
+__global__ __launch_bounds__(kBlock) void k_fs_pcg_sum(const double* __restrict__ t, int64_t n,
+                                                       double* __restrict__ pc, int slot) {
+    __shared__ double lds[kBlock / kWave];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) s += t[i];
+    s = block_sum<kBlock>(s, lds);
+    if (threadIdx.x == 0) pc[slot] = s;
+}
+
+// a = pc[cur] / pc[0] (r^T D^-1 r over q^T B q); y += a q; r -= a w;
+// t_i = r_i^2 / d_i.
+__global__ __launch_bounds__(kBlock) void k_fs_pcg_step(const double* __restrict__ sig,
+                                                        const int32_t* __restrict__ rank, int64_t n, int32_t method,
+                                                        const ParamOut* __restrict__ po,
+                                                        const double* __restrict__ pc, int cur,
+                                                        const double* __restrict__ q, const double* __restrict__ w,
+                                                        double* __restrict__ y, double* __restrict__ r,
+                                                        double* __restrict__ t) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double qw = pc[0];
+    const double a = qw > 0.0 ? pc[cur] / qw : 0.0;
+    const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k);
+    y[i] = fma(a, q[i], y[i]);
+    const double ri = fma(-a, w[i], r[i]);
+    r[i] = ri;
+    t[i] = d > 0.0 ? ri * ri / d : 0.0;
+}
+
+// q = D^-1 r + (pc[nxt] / pc[cur]) q.
+__global__ __launch_bounds__(kBlock) void k_fs_pcg_dir(const double* __restrict__ sig,
+                                                       const int32_t* __restrict__ rank, int64_t n, int32_t method,
+                                                       const ParamOut* __restrict__ po,
+                                                       const double* __restrict__ pc, int cur, int nxt,
+                                                       const double* __restrict__ r, double* __restrict__ q) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double beta = pc[cur] > 0.0 ? pc[nxt] / pc[cur] : 0.0;
+    const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k);
+    q[i] = d > 0.0 ? fma(beta, q[i], r[i] / d) : 0.0;
+}
+
+// Norms of the returned solution: t_i = (G[i] . x - fh_i)^2 (one workgroup
+// per row; with Q orthogonal sum_i t_i = ||A x - f||^2, the padding rows
+// staying exactly zero), and w_i = x_i^2.
+__global__ __launch_bounds__(kBlock) void k_fs_resid(const double* __restrict__ G, int64_t ldg, int64_t n,
+                                                     const double* __restrict__ x, const double* __restrict__ fh,
+                                                     double* __restrict__ t, double* __restrict__ w) {
+    __shared__ double lds[kBlock / kWave];
+    const int64_t i = blockIdx.x;
+    const double* row = G + i * ldg;
+    double s = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += kBlock) s = fma(row[j], x[j], s);
+    s = block_sum<kBlock>(s, lds);
+    if (threadIdx.x == 0) {
+        const double d = s - fh[i];
+        t[i] = d * d;
+        w[i] = x[i] * x[i];
+    }
+}
+
+// po->rho = sqrt(pc[1]), po->eta = sqrt(pc[0]).
+__global__ void k_fs_set_norms(const double* __restrict__ pc, ParamOut* __restrict__ po) {
+    if (threadIdx.x == 0) {
+        po->rho = sqrt(pc[1]);
+        po->eta = sqrt(pc[0]);
+    }
+}
+
+// G[i][n] = f_i for i < n (the f column of the work matrix).
+__global__ __launch_bounds__(kBlock) void k_fs_setf(double* __restrict__ G, int64_t ldg, int64_t n,
+                                                    const double* __restrict__ f) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) G[i * ldg + n] = f != nullptr ? f[i] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+void launch_fs_setf(double* G, int64_t ldg, int64_t n, const double* f, hipStream_t s) {
+    k_fs_setf<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(G, ldg, n, f);
+}
+
+void launch_fs_gram(const double* G, int64_t ldg, int64_t ncol, const int32_t* rowidx, const int2* pairs, int npairs,
+                    int S, int64_t chunk, double* Pg, hipStream_t s) {
+    k_fs_gram<<<dim3((unsigned)S, (unsigned)npairs), kBlock, 0, s>>>(G, ldg, ncol, rowidx, pairs, chunk, Pg);
+}
+
+void launch_fs_eig(const double* Pg, int S, int npairs, double tol, double inv_f, int max_inner, double* Pout,
+                   int32_t* flag, double* off, hipStream_t s) {
+    k_fs_eig<<<(unsigned)npairs, kBlock, 0, s>>>(Pg, S, tol, inv_f, max_inner, Pout, flag, off);
+}
+
+void launch_fs_update(double* G, int64_t ldg, int64_t ncol, const int32_t* rowidx, const int2* pairs, int npairs,
+                      const double* Pin, const int32_t* flag, hipStream_t s) {
+    k_fs_update<<<dim3((unsigned)((ncol + kFsRows - 1) / kFsRows), (unsigned)npairs), kBlock, 0, s>>>(
+        G, ldg, ncol, rowidx, pairs, Pin, flag);
+}
+
+void launch_fs_maxoff(const double* off, int64_t count, double* out, hipStream_t s) {
+    k_fs_maxoff<<<1, kBlock, 0, s>>>(off, count, out);
+}
+
+void launch_fs_norms(const double* G, int64_t ldg, int64_t rows, int64_t n, double* sig, double* fh, hipStream_t s) {
+    k_fs_norms<<<(unsigned)rows, kBlock, 0, s>>>(G, ldg, n, sig, fh);
+}
+
+void launch_fs_rank(const double* sig, const double* fh, int64_t n, int32_t* rank, double* sv, double* fs,
+                    int32_t* order, hipStream_t s) {
+    k_fs_rank<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(sig, fh, n, rank, sv, fs, order);
+}
+
+void launch_full_param(const double* sv, const double* fs, int64_t n, double fnorm2, int32_t method, int32_t rule,
+                       int32_t J, double lambda_fixed, int32_t k_fixed, double* tail, ParamOut* out, hipStream_t s) {
+    k_full_param<<<1, kBlock, 0, s>>>(sv, fs, n, fnorm2, method, rule, J, lambda_fixed, k_fixed, tail, out);
+}
+
+int fs_gemvt_chunks(int64_t n) {
+    // enough workgroups to cover the chip: columns / kBlock x chunks >= 1024
+    const int64_t cols = (n + kBlock - 1) / kBlock;
+    int64_t c = (1024 + cols - 1) / cols;
+    const int64_t cmax = (n + 63) / 64;  // at least 64 rows per chunk
+    if (c > cmax) c = cmax;
+    if (c > kFsMaxChunks) c = kFsMaxChunks;
+    return (int)(c < 1 ? 1 : c);
+}
+
+void launch_fs_gemvt(const double* G, int64_t ldg, int64_t n, const double* q, double* part, double* x,
+                     hipStream_t s) {
+    const int c = fs_gemvt_chunks(n);
+    const int64_t rows = (n + c - 1) / c;
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    k_fs_gemvt_part<<<dim3(nb, (unsigned)c), kBlock, 0, s>>>(G, ldg, n, rows, q, part);
+    k_fs_colsum<<<nb, kBlock, 0, s>>>(part, c, n, x);
+}
+
+void launch_fs_pcg_start(const double* sig, const double* fh, const int32_t* rank, int64_t n, int32_t method,
+                         const ParamOut* po, double* y, double* r, double* q, double* t, double* pc, int slot,
+                         hipStream_t s) {
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    k_fs_pcg_start<<<nb, kBlock, 0, s>>>(sig, fh, rank, n, method, po, y, r, q, t);
+    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, slot);
+}
+
+void launch_fs_pcg_iter(const double* G, int64_t ldg, int64_t n, const double* sig, const int32_t* rank,
+                        int32_t method, const ParamOut* po, double* pc, int cur, int nxt, double* y, double* r,
+                        const double* q, double* w, double* t, double* part, double* x, hipStream_t s) {
+    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    launch_fs_gemvt(G, ldg, n, q, part, x, s);
+    k_fs_pcg_matvec<<<(unsigned)n, kBlock, 0, s>>>(G, ldg, n, x, sig, rank, method, po, q, w, t);
+    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, 0);
+    k_fs_pcg_step<<<nb, kBlock, 0, s>>>(sig, rank, n, method, po, pc, cur, q, w, y, r, t);
+    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, nxt);
+}
+
+void launch_fs_solution_norms(const double* G, int64_t ldg, int64_t n, const double* x, const double* fh, double* t,
+                              double* w, double* pc, ParamOut* po, hipStream_t s) {
+    k_fs_resid<<<(unsigned)n, kBlock, 0, s>>>(G, ldg, n, x, fh, t, w);
+    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, 1);
+    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(w, n, pc, 0);
+    k_fs_set_norms<<<1, 64, 0, s>>>(pc, po);
+}
+
+void launch_fs_pcg_dir(const double* sig, const int32_t* rank, int64_t n, int32_t method, const ParamOut* po,
+                       const double* pc, int cur, int nxt, const double* r, double* q, hipStream_t s) {
+    k_fs_pcg_dir<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(sig, rank, n, method, po, pc, cur, nxt, r,
+                                                                          q);
+}
+
+}  // namespace mqh

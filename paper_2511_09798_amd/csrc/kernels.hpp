@@ -14,6 +14,8 @@ constexpr int kMfmFixed = (kBlock / kWave) * kMfmFt * 16;  // fixed nodes per bl
 constexpr int kMfmChunk = kBlock;  // loop nodes staged in LDS per round (one per thread)
 constexpr int kBlkRhs = 16;        // right-hand sides of a block product (lockstep Golub-Kahan runs)
 constexpr int kMaxSlices = 64;     // largest split of a product's sum over nodes
+constexpr int kFsBlock = 32;       // rows per block of the full SVD's one-sided block Jacobi
+constexpr int kFsMaxChunks = 64;   // row chunks of the full solutions' G^T q
 
 // Learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs.
 constexpr int kMlpIn = 24;
@@ -123,5 +125,37 @@ void launch_lsqr(const double* alpha, const double* beta, int32_t l, const int32
 void launch_proj_solution(const double* sv, const double* ft, const double* V, int64_t ldv, int32_t l,
                           const int32_t* l_ptr, int32_t method, double lambda, int32_t k, const ParamOut* po,
                           double* y, int32_t l_max, hipStream_t s, int nz = 1, ProjBatch pb = ProjBatch{});
+
+// Full SVD (full_kernels.hip)
+void launch_fs_setf(double* G, int64_t ldg, int64_t n, const double* f, hipStream_t s);
+void launch_fs_gram(const double* G, int64_t ldg, int64_t ncol, const int32_t* rowidx, const int2* pairs, int npairs,
+                    int S, int64_t chunk, double* Pg, hipStream_t s);
+void launch_fs_eig(const double* Pg, int S, int npairs, double tol, double inv_f, int max_inner, double* Pout,
+                   int32_t* flag, double* off, hipStream_t s);
+void launch_fs_update(double* G, int64_t ldg, int64_t ncol, const int32_t* rowidx, const int2* pairs, int npairs,
+                      const double* Pin, const int32_t* flag, hipStream_t s);
+void launch_fs_maxoff(const double* off, int64_t count, double* out, hipStream_t s);
+void launch_fs_norms(const double* G, int64_t ldg, int64_t rows, int64_t n, double* sig, double* fh, hipStream_t s);
+void launch_fs_rank(const double* sig, const double* fh, int64_t n, int32_t* rank, double* sv, double* fs,
+                    int32_t* order, hipStream_t s);
+void launch_full_param(const double* sv, const double* fs, int64_t n, double fnorm2, int32_t method, int32_t rule,
+                       int32_t J, double lambda_fixed, int32_t k_fixed, double* tail, ParamOut* out, hipStream_t s);
+// Solutions: preconditioned conjugate gradients on (G G^T + lambda^2 I) y = f^
+// (Tikhonov) or G_k G_k^T y = f^_k (TSVD), x = G^T y.  pc holds the
+// iteration's scalars: [0] q^T B q, [2], [3] r^T D^-1 r of alternate
+// iterations.  part: fs_gemvt_chunks(n) x n doubles.
+int fs_gemvt_chunks(int64_t n);
+void launch_fs_gemvt(const double* G, int64_t ldg, int64_t n, const double* q, double* part, double* x, hipStream_t s);
+void launch_fs_pcg_start(const double* sig, const double* fh, const int32_t* rank, int64_t n, int32_t method,
+                         const ParamOut* po, double* y, double* r, double* q, double* t, double* pc, int slot,
+                         hipStream_t s);
+void launch_fs_pcg_iter(const double* G, int64_t ldg, int64_t n, const double* sig, const int32_t* rank,
+                        int32_t method, const ParamOut* po, double* pc, int cur, int nxt, double* y, double* r,
+                        const double* q, double* w, double* t, double* part, double* x, hipStream_t s);
+// ||A x - f|| = ||G x - f^|| and ||x|| of the returned solution into po->rho, po->eta.
+void launch_fs_solution_norms(const double* G, int64_t ldg, int64_t n, const double* x, const double* fh, double* t,
+                              double* w, double* pc, ParamOut* po, hipStream_t s);
+void launch_fs_pcg_dir(const double* sig, const int32_t* rank, int64_t n, int32_t method, const ParamOut* po,
+                       const double* pc, int cur, int nxt, const double* r, double* q, hipStream_t s);
 
 }  // namespace mqh

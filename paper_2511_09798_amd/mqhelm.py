@@ -24,6 +24,7 @@ MQH_ENOMEM = -2
 MQH_EDEVICE = -3
 MQH_WBREAKDOWN = 1
 MQH_WEDGE = 2
+MQH_WNOCONV = 3
 MQH_OP_STORED_FP64 = 0
 MQH_OP_MATFREE_FP64 = 1
 MQH_OP_MATFREE_FP32 = 2
@@ -42,6 +43,7 @@ MQH_INFO_BREAKDOWN = 1
 MQH_INFO_GCV_AT_EDGE = 2
 MQH_INFO_LCURVE_AT_EDGE = 4
 MQH_MAX_ELL = 1024
+MQH_FULL_MAX_N = 32768
 MQH_BLOCK_RHS = 16
 MQH_MLP_IN = 24
 MQH_MLP_WIDTH = 128
@@ -121,6 +123,9 @@ _SIGNATURES = {
     "mqh_solve_multi": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(mqh_solve_opts), _vp, _i64,
                                        ctypes.POINTER(mqh_solve_info)]),
     "mqh_solve_sweep": (ctypes.c_int, [ctypes.POINTER(mqh_sweep_item), _i32, ctypes.POINTER(mqh_solve_opts), _i32]),
+    "mqh_full_svd": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_d), _u32]),
+    "mqh_full_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(mqh_solve_opts), _vp, _vp,
+                                      ctypes.POINTER(mqh_solve_info)]),
     "mqh_eval": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _u32]),
     "mqh_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _u32]),
     "mqh_mlp_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _u32]),
@@ -483,6 +488,39 @@ def mqh_solve_sweep(problems, Fs, ell: int, workers: int = 2, coefs=None, method
     return outs
 
 
+def mqh_full_svd(h, f=None, ref=None):
+    """Full SVD of A (one-sided block Jacobi): dict(sv descending, fhat = U^T f, sweeps, off, status)."""
+    n = int(lib.mqh_problem_size(h))
+    like = f if f is not None else ref
+    sv = _empty_like_kind(like, (n,))
+    fh = _empty_like_kind(like, (n,)) if f is not None else None
+    fl = _flags(f, sv, fh)
+    sw = _i32(0)
+    off = _d(0.0)
+    st = _check(lib.mqh_full_svd(h, _ptr(f)[0], _ptr(sv)[0], _ptr(fh)[0], ctypes.byref(sw), ctypes.byref(off), fl),
+                "mqh_full_svd")
+    return dict(sv=sv, fhat=fh, sweeps=int(sw.value), off=float(off.value), status=st)
+
+
+def mqh_full_solve(h, f_int, g_bnd, method: int = MQH_METHOD_HKT, rule: int = MQH_RULE_GCV, k_trunc: int = 0,
+                   lambda_fixed: float = 0.0, n_grid: int = 200, coef=None, want_sv: bool = True) -> SolveOutput:
+    """Algorithm 3 (method MQH_METHOD_HKT: Tikhonov filter) or the full TSVD (MQH_METHOD_INE_TSVD) on the
+    full SVD of A.  SolveOutput.ell_done holds the Jacobi sweeps, t_ms[6] the last sweep's off-diagonal."""
+    n = int(lib.mqh_problem_size(h))
+    ref = f_int if f_int is not None else g_bnd
+    if coef is None:
+        coef = _empty_like_kind(ref, (n,))
+    sv = _zeros_like_kind(ref, (n,)) if want_sv else None
+    fl = _flags(f_int, g_bnd, coef, sv)
+    opts = mqh_solve_opts(ell=1, reorth=1, method=int(method), rule=int(rule), k_trunc=int(k_trunc),
+                          n_grid=int(n_grid), lambda_fixed=float(lambda_fixed), flags=fl, reserved=0, gcv_weight=1.0)
+    info = mqh_solve_info()
+    st = _check(lib.mqh_full_solve(h, _ptr(f_int)[0], _ptr(g_bnd)[0], ctypes.byref(opts), _ptr(coef)[0],
+                                   _ptr(sv)[0], ctypes.byref(info)), "mqh_full_solve")
+    return SolveOutput(coef, None, None, sv, st, info.ell_done, info.k_chosen, info.lambda_chosen, info.crit,
+                       info.resid_norm, info.sol_norm, info.flags, list(info.t_ms))
+
+
 def mqh_eval(h, coef, x_eval, u=None):
     m = int(x_eval.shape[0])
     if u is None:
@@ -626,6 +664,12 @@ class Problem:
 
     def solve_multi(self, F, ell, **kw) -> MultiSolveOutput:
         return mqh_solve_multi(self.h, F, ell, **kw)
+
+    def full_svd(self, f=None, ref=None):
+        return mqh_full_svd(self.h, f, ref)
+
+    def full_solve(self, f_int, g_bnd, **kw) -> SolveOutput:
+        return mqh_full_solve(self.h, f_int, g_bnd, **kw)
 
     def solve_learned(self, f_int, g_bnd, ell, predictor, **kw) -> LearnedOutput:
         return mqh_solve_learned(self.h, f_int, g_bnd, ell, predictor, **kw)
