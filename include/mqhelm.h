@@ -402,10 +402,13 @@ int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* 
  *
  * The SVD is one-sided block Jacobi on the rows of [A | f]: row rotations Q
  * (each sweep orders the rows by decreasing norm and pairs 32-row blocks in
- * a round-robin order; per pair the eigenvectors of the 64 x 64 Gram matrix
- * of their rows) until, in a whole sweep, every pair of rows has the
- * component of the smaller along the larger at most 16 sqrt(n) DBL_EPSILON
- * ||A||_F (backward stable: singular values to that absolute level).  Then
+ * a round-robin order; per pair the rotation of one cyclic Jacobi sweep on
+ * the 64 x 64 Gram matrix of their rows) until, in a whole sweep, every pair
+ * of rows has the component of the smaller along the larger at most
+ * 16 sqrt(n) DBL_EPSILON ||A||_F, or the largest such component stays below
+ * twice that (the rounding floor of the measure) without falling by a
+ * quarter for three sweeps (singular values to a small multiple of that
+ * absolute level).  Then
  * A = Q^T Sigma Ubar^T: sigma_i are the row norms of Q A, U^T f = Q f is the
  * rotated f column, and the solutions are combinations of the rows of Q A
  * (U and V are never formed).
@@ -413,8 +416,8 @@ int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* 
  * mqh_full_svd: sv (n, descending); fhat (n, NULL allowed) = U^T f in the
  *   same order (f NULL: fhat = 0); sweeps (host, NULL allowed) = Jacobi
  *   sweeps run; off (host, NULL allowed) = the last sweep's largest
- *   off-diagonal measure.  MQH_WNOCONV if 100 sweeps did not reach the
- *   tolerance.
+ *   off-diagonal measure.  MQH_WNOCONV if 100 sweeps did not bring it below
+ *   32 sqrt(n) DBL_EPSILON.
  * mqh_full_solve: Algorithm 3 (Tikh-Reg: opts->method = MQH_METHOD_HKT,
  *   the Tikhonov filter, eq. (17)) or the TSVD solution of eq. (14)
  *   (opts->method = MQH_METHOD_INE_TSVD, the TSVD filter on the full SVD);

@@ -8,8 +8,12 @@
 #include <math.h>
 #include <string.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -861,14 +865,29 @@ struct FullRun {
 };
 
 constexpr int kFullMaxSweeps = 100;
-constexpr int kFullMaxInner = 15;
+// One cyclic sweep of the 64 x 64 eigensolver per pair and round: rotations
+// from a pair's partly diagonalised Gram matrix still orthogonalise its rows
+// better each round, later rounds disturb an exact diagonalisation anyway,
+// and the outer sweeps barely grow (33 -> 36 at n = 5 000) while a round's
+// eigensolver time falls several-fold.
+constexpr int kFullMaxInner = 1;
+// Orthogonality levels of the Jacobi sweeps (relative to ||A||_F): the target
+// full_tol(n), and full_floor(n) = twice that.  The measure, computed from
+// FP64 Gram entries over n columns, stalls at 16 .. 20 sqrt(n) eps (measured
+// at n = 5 000 and 20 000), so the sweeps also end once it is below the floor
+// and has not fallen by a quarter in kFullStall sweeps: converged to rounding.
+inline double full_tol(int64_t n) { return 16.0 * sqrt((double)n) * DBL_EPSILON; }
+inline double full_floor(int64_t n) { return 2.0 * full_tol(n); }
+constexpr int kFullStall = 3;
+
 constexpr int kFullCgMax = 64;        // conjugate-gradient iterations of the solutions' dual system
 constexpr double kFullCgTol = 1e-15;  // stop when sqrt(r^T D^-1 r) falls below this fraction of its start
 
 // Assembles [A | f] (f already staged in r.f, or zero) and runs Jacobi
 // sweeps, each on the rows ordered by decreasing norm, until in a whole sweep
 // every pair of rows has the component of the smaller along the larger at
-// most 16 sqrt(n) DBL_EPSILON ||A||_F (or kFullMaxSweeps); then sigma, f^
+// most full_tol(n) ||A||_F, or stalls below full_floor(n) ||A||_F (or
+// kFullMaxSweeps); then sigma, f^
 // (input row order) and their descending order.
 int full_svd_run(mqh_problem* p, FullRun& r) {
     hipStream_t s = p->stream;
@@ -918,11 +937,18 @@ int full_svd_run(mqh_problem* p, FullRun& r) {
     launch_fs_setf(r.G, r.ldg, n, r.f, s);
     LAUNCHCHK("full SVD: data column");
     HIPCHK(hipEventRecord(p->ev[1], s));
-    const double tol = 16.0 * sqrt((double)n) * DBL_EPSILON;
+    const double tol = full_tol(n);
     std::vector<double> rn((size_t)r.nrow);
     std::vector<int32_t> idx((size_t)r.nrow);
     double inv_f = 0.0;
     r.sweeps = 0;
+    // MQH_TRACE_FULL=1 prints one line per sweep to stderr (diagnostics only)
+    const char* tr = getenv("MQH_TRACE_FULL");
+    const bool trace = tr != nullptr && tr[0] == '1';
+    auto t0 = std::chrono::steady_clock::now();
+    const double floor_off = full_floor(n);
+    double best = HUGE_VAL;
+    int stall = 0;
     for (int sw = 0; sw < kFullMaxSweeps; ++sw) {
         // de Rijk's ordering: rows by decreasing norm (stable), blocks of 32
         launch_fs_norms(r.G, r.ldg, r.nrow, n, r.rnorm, r.rtmp, s);
@@ -953,7 +979,25 @@ int full_svd_run(mqh_problem* p, FullRun& r) {
         HIPCHK(hipStreamSynchronize(s));
         r.sweeps = sw + 1;
         r.final_off = mo;
+        if (trace) {
+            // pairs rotated in this sweep (off above tol), and the sweep's time
+            std::vector<double> offs((size_t)r.rounds * r.npairs);
+            HIPCHK(hipMemcpy(offs.data(), r.off, offs.size() * sizeof(double), hipMemcpyDeviceToHost));
+            int64_t rot = 0;
+            for (double v : offs) rot += v > tol ? 1 : 0;
+            const auto t1 = std::chrono::steady_clock::now();
+            fprintf(stderr, "[mqh full] sweep %d off %.3e rotated %lld of %lld pairs %.1f ms\n", sw + 1, mo,
+                    (long long)rot, (long long)offs.size(),
+                    std::chrono::duration<double, std::milli>(t1 - t0).count());
+            t0 = t1;
+        }
         if (!(mo > tol)) break;
+        if (mo < 0.75 * best) {
+            best = mo;
+            stall = 0;
+        } else if (++stall >= kFullStall && !(mo > floor_off)) {
+            break;
+        }
     }
     HIPCHK(hipEventRecord(p->ev[2], s));
     launch_fs_norms(r.G, r.ldg, n, n, r.sig, r.fh, s);
@@ -1706,7 +1750,7 @@ int mqh_full_svd(mqh_problem* p, const double* f, double* sv, double* fhat, int3
     HIPCHK(hipStreamSynchronize(s));
     if (sweeps) *sweeps = r.sweeps;
     if (off) *off = r.final_off;
-    return r.final_off > 16.0 * sqrt((double)p->n) * DBL_EPSILON ? MQH_WNOCONV : MQH_OK;
+    return r.final_off > full_floor(p->n) ? MQH_WNOCONV : MQH_OK;
 }
 
 int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts, double* coef,
@@ -1759,7 +1803,7 @@ int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, con
     if (sv) HIPCHK(hipMemcpyAsync(sv, r.sv, (size_t)p->n * sizeof(double), ko, s));
     HIPCHK(hipEventRecord(p->ev[6], s));
     HIPCHK(hipStreamSynchronize(s));
-    const bool noconv = r.final_off > 16.0 * sqrt((double)p->n) * DBL_EPSILON;
+    const bool noconv = r.final_off > full_floor(p->n);
     if (info) {
         info->ell_done = r.sweeps;
         info->k_chosen = po.k;

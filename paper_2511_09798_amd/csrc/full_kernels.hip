@@ -31,6 +31,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kFsRows = 2 * kFsBlock;  // rows of a pair (64)
 constexpr int kFsLd = kFsRows + 1;     // LDS row of a 64 x 64 FP64 tile (padded)
+static_assert(kFsRows % (kBlock / kWave) == 0 && kFsRows == kWave, "tile loader: one row per wave and load");
 
 // Row of the work matrix holding row r (0..63) of pair (bi, bj): block b
 // consists of the rows rowidx[32 b .. 32 b + 31] (the sweep's order).
@@ -41,10 +42,15 @@ __device__ __forceinline__ int64_t pair_row(const int32_t* __restrict__ rowidx, 
 // Columns [c0, c0 + 64) of the pair's 64 rows into an LDS tile (zeros past cend).
 __device__ __forceinline__ void load_tile(const double* __restrict__ G, int64_t ldg, const int32_t* __restrict__ rowidx,
                                           int2 pr, int64_t c0, int64_t cend, double* __restrict__ t) {
-    const int r = threadIdx.x >> 2, cb = (threadIdx.x & 3) * 16;
-    const double* src = G + pair_row(rowidx, pr, r) * ldg + c0 + cb;
+    // a wave reads 64 consecutive doubles of one row per load (512 B, aligned
+    // when ldg and c0 are multiples of 64)
+    const int c = threadIdx.x & (kWave - 1), r0 = threadIdx.x / kWave;
+    const bool ok = c0 + c < cend;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) t[r * kFsLd + cb + q] = (c0 + cb + q < cend) ? src[q] : 0.0;
+    for (int q = 0; q < kFsRows / (kBlock / kWave); ++q) {
+        const int r = r0 + (kBlock / kWave) * q;
+        t[r * kFsLd + c] = ok ? G[pair_row(rowidx, pr, r) * ldg + c0 + c] : 0.0;
+    }
 }
 
 // Partial Gram matrices: Pg[(pair * S + chunk)][a][b] = sum over the chunk's
@@ -89,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_gram(const double* __restrict__ G
 // inv_f = 1 / F (block-wide, every thread gets it): the component of the
 // smaller row along the larger one relative to the matrix's norm.  Below
 // c sqrt(n) eps the rows are orthogonal to the rounding level of a dense
-// SVD (backward stable: singular values to c sqrt(n) eps ||A||_F); a
+// SVD (singular values to a small multiple of c sqrt(n) eps ||A||_F); a
 // relative cosine test cannot be met by rows near that level, which every
 // sweep renews.  M in LDS with row length kFsLd.
 __device__ double offdiag(const double* __restrict__ M, double inv_f, double* __restrict__ red) {
@@ -121,8 +127,8 @@ __device__ double offdiag(const double* __restrict__ M, double inv_f, double* __
 // off-diagonal measure (offdiag); if above tol, cyclic Jacobi (round-robin
 // order, 32 disjoint rotations per step, 63 steps per sweep, rotations
 // skipped when |M_pq| <= eps/4 sqrt(M_pp M_qq); until the measure is below
-// eps or max_inner sweeps) gives M = P diag P^T, and P goes to Pout[pair]
-// with flag[pair] = 1; else flag 0.
+// eps or max_inner sweeps) gives P^T M P (nearly) diagonal, and P goes to
+// Pout[pair] with flag[pair] = 1; else flag 0.
 __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg, int S, double tol, double inv_f,
                                                    int max_inner, double* __restrict__ Pout,
                                                    int32_t* __restrict__ flag, double* __restrict__ off) {
@@ -170,31 +176,34 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
                 rs[k] = s;
             }
             __syncthreads();
-            // rows: M <- J^T M
-            for (int e = threadIdx.x; e < (kFsRows / 2) * kFsRows; e += kBlock) {
-                const int k = e / kFsRows, j = e % kFsRows;
-                const int p = rp[k], q = rq[k];
-                const double c = rc[k], s = rs[k];
-                const double mp = M[p * kFsLd + j], mq = M[q * kFsLd + j];
-                M[p * kFsLd + j] = c * mp - s * mq;
-                M[q * kFsLd + j] = s * mp + c * mq;
+            // M <- J^T M J in one pass: the 32 disjoint rotations split M into
+            // 2 x 2 blocks (rows {p_a, q_a}, columns {p_b, q_b}), each updated on
+            // its own (rows first, then columns, as two separate passes would);
+            // P <- P J beside it
+            for (int e = threadIdx.x; e < (kFsRows / 2) * (kFsRows / 2); e += kBlock) {
+                const int ka = e / (kFsRows / 2), kb = e % (kFsRows / 2);
+                const int pa = rp[ka], qa = rq[ka], pb = rp[kb], qb = rq[kb];
+                const double ca = rc[ka], sa = rs[ka], cb = rc[kb], sb = rs[kb];
+                const double m00 = M[pa * kFsLd + pb], m01 = M[pa * kFsLd + qb];
+                const double m10 = M[qa * kFsLd + pb], m11 = M[qa * kFsLd + qb];
+                const double r00 = ca * m00 - sa * m10, r01 = ca * m01 - sa * m11;
+                const double r10 = sa * m00 + ca * m10, r11 = sa * m01 + ca * m11;
+                M[pa * kFsLd + pb] = cb * r00 - sb * r01;
+                M[pa * kFsLd + qb] = sb * r00 + cb * r01;
+                M[qa * kFsLd + pb] = cb * r10 - sb * r11;
+                M[qa * kFsLd + qb] = sb * r10 + cb * r11;
             }
-            __syncthreads();
-            // columns: M <- M J, P <- P J
             for (int e = threadIdx.x; e < (kFsRows / 2) * kFsRows; e += kBlock) {
                 const int k = e / kFsRows, i = e % kFsRows;
                 const int p = rp[k], q = rq[k];
                 const double c = rc[k], s = rs[k];
-                const double mp = M[i * kFsLd + p], mq = M[i * kFsLd + q];
-                M[i * kFsLd + p] = c * mp - s * mq;
-                M[i * kFsLd + q] = s * mp + c * mq;
                 const double pp = P[i * kFsLd + p], pq = P[i * kFsLd + q];
                 P[i * kFsLd + p] = c * pp - s * pq;
                 P[i * kFsLd + q] = s * pp + c * pq;
             }
             __syncthreads();
         }
-        if (!(offdiag(M, inv_f, red) > tol_in)) break;
+        if (sweep + 1 < max_inner && !(offdiag(M, inv_f, red) > tol_in)) break;
     }
     double* dst = Pout + (int64_t)pair * (kFsRows * kFsRows);
     for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock)
@@ -202,8 +211,9 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
     if (threadIdx.x == 0) flag[pair] = 1;
 }
 
-// X <- P^T X on the pair's 64 rows, columns [64 bx, 64 bx + 64) of ncol (all
-// columns, the f column included).  Skipped when flag[pair] = 0.
+// X <- P^T X on the pair's 64 rows, column tiles [kFsUpdTiles bx, kFsUpdTiles
+// (bx + 1)) of 64 columns each, of ncol (all columns, the f column included):
+// P is staged once per workgroup for its tiles.  Skipped when flag[pair] = 0.
 __global__ __launch_bounds__(kBlock) void k_fs_update(double* __restrict__ G, int64_t ldg, int64_t ncol,
                                                       const int32_t* __restrict__ rowidx,
                                                       const int2* __restrict__ pairs,
@@ -214,32 +224,42 @@ __global__ __launch_bounds__(kBlock) void k_fs_update(double* __restrict__ G, in
     const int pair = blockIdx.y;
     if (flag[pair] == 0) return;  // block-uniform
     const int2 pr = pairs[pair];
-    const int64_t c0 = (int64_t)blockIdx.x * kFsRows;
     const double* P = Pin + (int64_t)pair * (kFsRows * kFsRows);
     for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock) Pt[(e / kFsRows) * kFsLd + e % kFsRows] = P[e];
-    load_tile(G, ldg, rowidx, pr, c0, ncol, t);
-    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int li = lane & 15, lk = lane >> 4;
-    v4d acc[4];
+    // the four output rows of this lane, fixed over the tiles
+    int64_t orow[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-    // Y[i][c] = sum_k P[k][i] X[k][c]: A[i][k] = P[k][i], B[k][c] = X[k][c]
+    for (int r = 0; r < 4; ++r) orow[r] = (int64_t)pair_row(rowidx, pr, 16 * w + 4 * r + lk) * ldg;
+    const int64_t ntile = (ncol + kFsRows - 1) / kFsRows;
+    const int64_t tb = (int64_t)blockIdx.x * kFsUpdTiles;
+    const int64_t te = tb + kFsUpdTiles < ntile ? tb + kFsUpdTiles : ntile;
+    for (int64_t tile = tb; tile < te; ++tile) {
+        const int64_t c0 = tile * kFsRows;
+        __syncthreads();  // Pt staged / the previous tile's reads of t done
+        load_tile(G, ldg, rowidx, pr, c0, ncol, t);
+        __syncthreads();
+        v4d acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+        // Y[i][c] = sum_k P[k][i] X[k][c]: A[i][k] = P[k][i], B[k][c] = X[k][c]
 #pragma unroll 4
-    for (int kk = 0; kk < kFsRows; kk += 4) {
-        const double a = Pt[(kk + lk) * kFsLd + 16 * w + li];
+        for (int kk = 0; kk < kFsRows; kk += 4) {
+            const double a = Pt[(kk + lk) * kFsLd + 16 * w + li];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double b = t[(kk + lk) * kFsLd + 16 * q + li];
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+            }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const double b = t[(kk + lk) * kFsLd + 16 * q + li];
-            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+            const int64_t col = c0 + 16 * q + li;
+            if (col >= ncol) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) G[orow[r] + col] = acc[q][r];
         }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t col = c0 + 16 * q + li;
-        if (col >= ncol) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) G[pair_row(rowidx, pr, 16 * w + 4 * r + lk) * ldg + col] = acc[q][r];
     }
 }
 
@@ -680,7 +700,8 @@ void launch_fs_eig(const double* Pg, int S, int npairs, double tol, double inv_f
 
 void launch_fs_update(double* G, int64_t ldg, int64_t ncol, const int32_t* rowidx, const int2* pairs, int npairs,
                       const double* Pin, const int32_t* flag, hipStream_t s) {
-    k_fs_update<<<dim3((unsigned)((ncol + kFsRows - 1) / kFsRows), (unsigned)npairs), kBlock, 0, s>>>(
+    const int64_t ntile = (ncol + kFsRows - 1) / kFsRows;
+    k_fs_update<<<dim3((unsigned)((ntile + kFsUpdTiles - 1) / kFsUpdTiles), (unsigned)npairs), kBlock, 0, s>>>(
         G, ldg, ncol, rowidx, pairs, Pin, flag);
 }
 

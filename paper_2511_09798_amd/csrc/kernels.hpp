@@ -16,6 +16,7 @@ constexpr int kBlkRhs = 16;        // right-hand sides of a block product (locks
 constexpr int kMaxSlices = 64;     // largest split of a product's sum over nodes
 constexpr int kFsBlock = 32;       // rows per block of the full SVD's one-sided block Jacobi
 constexpr int kFsMaxChunks = 64;   // row chunks of the full solutions' G^T q
+constexpr int kFsUpdTiles = 8;     // 64-column tiles per workgroup of the full SVD's row update
 
 // Learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs.
 constexpr int kMlpIn = 24;
