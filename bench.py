@@ -347,7 +347,8 @@ def full_context(mq, torch, dev, level: int):
                              rel_l2=rel_l2(u, p.u_eval), rel_linf=rel_linf(u, p.u_eval),
                              phase_ms=dict(assembly=out.t_ms[0], jacobi=out.t_ms[1], order=out.t_ms[2],
                                            param=out.t_ms[3], solution=out.t_ms[4]),
-                             cg_iterations=int(out.t_ms[7]))
+                             cg_iterations=int(out.t_ms[7]), status=int(out.status),
+                             solution_converged=not (out.flags & mq.MQH_INFO_SOLVE_NOCONV))
             log("full", name, json.dumps(res[name]))
         pr.solve(f_int, g_bnd, p.ell)  # warmup
         torch.cuda.synchronize()

@@ -52,7 +52,8 @@ extern "C" {
 #define MQH_EDEVICE (-3)  /* a HIP runtime call or kernel launch failed */
 #define MQH_WBREAKDOWN 1  /* Golub-Kahan stopped early (ell_done < ell); outputs valid for ell_done steps */
 #define MQH_WEDGE 2       /* chosen lambda sits at an end of the search grid */
-#define MQH_WNOCONV 3     /* full SVD: the Jacobi sweeps stopped at their limit (results of the last sweep) */
+#define MQH_WNOCONV 3     /* full SVD: the Jacobi sweeps stopped at their limit (results of the last sweep),
+                             or the full solution's iteration at its cap (MQH_INFO_SOLVE_NOCONV) */
 
 /* ---- operator modes (how A enters the products) ---- */
 #define MQH_OP_STORED_FP64 0   /* A assembled once in HBM (8 N^2 bytes, row-major), FP64 products */
@@ -84,6 +85,7 @@ extern "C" {
 #define MQH_INFO_BREAKDOWN 1u
 #define MQH_INFO_GCV_AT_EDGE 2u
 #define MQH_INFO_LCURVE_AT_EDGE 4u
+#define MQH_INFO_SOLVE_NOCONV 8u  /* full solve: the conjugate gradients stopped at their cap above their tolerance */
 
 /* Largest number of Golub-Kahan steps a solve accepts (projected problem size). */
 #define MQH_MAX_ELL 1024
@@ -432,7 +434,11 @@ int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* 
  *   flags (MQH_INFO_GCV_AT_EDGE), t_ms [0] assembly, [1] Jacobi sweeps,
  *   [2] singular values and order, [3] parameter choice, [4] solution,
  *   [5] total, [6] the last sweep's largest off-diagonal measure, [7] the
- *   conjugate-gradient iterations of the solution.  The solution is
+ *   conjugate-gradient iterations of the solution (at most 64; at the cap
+ *   above the tolerance MQH_INFO_SOLVE_NOCONV is set and MQH_WNOCONV
+ *   returned: this happens when lambda lies below the accuracy of the SVD,
+ *   as GCV chooses on exact data, where the Tikhonov solution is not
+ *   determined by the data).  The solution is
  *   x = G^T y, G = Q A the rotated rows, with (G G^T + lambda^2 I) y = Q f
  *   (Tikhonov) or G_k G_k^T y = (Q f)_k on the k rows of the largest sigma
  *   (TSVD), solved by conjugate gradients preconditioned with the diagonal:

@@ -1011,7 +1011,7 @@ int full_svd_run(mqh_problem* p, FullRun& r) {
 // system by preconditioned conjugate gradients (the kernels' comment gives
 // the system); y in r.rnorm, the residual in r.rtmp, x in r.coef; then
 // po->rho = ||A x - f|| and po->eta = ||x|| of that x.
-int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters) {
+int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters, bool* converged) {
     hipStream_t s = p->stream;
     const int64_t n = p->n;
     int rc;
@@ -1028,8 +1028,10 @@ int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters) {
     HIPCHK(hipStreamSynchronize(s));
     if (!isfinite(rz0)) return fail(MQH_EDEVICE, "full problem: non-finite right-hand side of the solution");
     int it = 0;
+    *converged = true;
     if (rz0 > 0.0) {
         const double stop = kFullCgTol * kFullCgTol * rz0;
+        *converged = false;
         while (it < kFullCgMax) {
             const int cur = 2 + (it & 1), nxt = 2 + ((it + 1) & 1);
             launch_fs_pcg_iter(r.G, r.ldg, n, r.sig, r.rank, method, r.po, r.cpc, cur, nxt, y, res, r.cq, r.cw, r.ct,
@@ -1040,7 +1042,10 @@ int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters) {
             HIPCHK(hipStreamSynchronize(s));
             ++it;
             if (!isfinite(rz)) return fail(MQH_EDEVICE, "full problem: non-finite solution iterate");
-            if (!(rz > stop)) break;
+            if (!(rz > stop)) {
+                *converged = true;
+                break;
+            }
             launch_fs_pcg_dir(r.sig, r.rank, n, method, r.po, r.cpc, cur, nxt, res, r.cq, s);
         }
     }
@@ -1794,7 +1799,8 @@ int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, con
     LAUNCHCHK("full problem: parameter choice");
     HIPCHK(hipEventRecord(p->ev[4], s));
     int cg_iters = 0;
-    if ((rc = full_solution(p, r, tikh ? 1 : 0, &cg_iters))) return rc;
+    bool cg_conv = true;
+    if ((rc = full_solution(p, r, tikh ? 1 : 0, &cg_iters, &cg_conv))) return rc;
     HIPCHK(hipEventRecord(p->ev[5], s));
     ParamOut po;
     HIPCHK(hipMemcpyAsync(&po, r.po, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
@@ -1811,7 +1817,7 @@ int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, con
         info->crit = po.crit;
         info->resid_norm = po.rho;
         info->sol_norm = po.eta;
-        info->flags = po.flags;
+        info->flags = po.flags | (cg_conv ? 0u : MQH_INFO_SOLVE_NOCONV);
         float ms = 0.f;
         const int pairs[6][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {0, 6}};
         for (int q = 0; q < 6; ++q)
@@ -1819,7 +1825,7 @@ int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, con
         info->t_ms[6] = (float)r.final_off;
         info->t_ms[7] = cg_iters;
     }
-    if (noconv) return MQH_WNOCONV;
+    if (noconv || !cg_conv) return MQH_WNOCONV;
     if (po.flags & MQH_INFO_GCV_AT_EDGE) return MQH_WEDGE;
     return MQH_OK;
 }

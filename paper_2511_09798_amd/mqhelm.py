@@ -42,6 +42,7 @@ MQH_FLAG_GRAPH = 8
 MQH_INFO_BREAKDOWN = 1
 MQH_INFO_GCV_AT_EDGE = 2
 MQH_INFO_LCURVE_AT_EDGE = 4
+MQH_INFO_SOLVE_NOCONV = 8
 MQH_MAX_ELL = 1024
 MQH_FULL_MAX_N = 32768
 MQH_BLOCK_RHS = 16

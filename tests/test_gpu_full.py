@@ -148,6 +148,7 @@ def test_full_tikhonov_against_oracle(mq, orc, name, make):
     assert out.lam == pytest.approx(lam_o, rel=1e-2)
     assert du <= 1e-4
     assert dc <= _tau(A) / lam_o
+    assert not (out.flags & mq.MQH_INFO_SOLVE_NOCONV) and not (out2.flags & mq.MQH_INFO_SOLVE_NOCONV)
     # residual and solution norms of the returned coefficients (||G x - Q f|| and ||x||)
     say("resid", out2.resid_norm, "oracle", np.linalg.norm(A @ alpha_o - f), "of the GPU's coef",
         np.linalg.norm(A @ out2.coef - f))
@@ -179,6 +180,24 @@ def test_full_tsvd_against_oracle(mq, orc, name, make):
     assert out.k == k_o
     assert du <= 1e-4
     assert dc <= _tau(A) / s[k_o - 1]
+
+
+def test_full_exact_data_reports_the_solution_state(mq, orc):
+    # exact (manufactured) data: GCV may put lambda below the accuracy of any
+    # backward-stable SVD, where the dual system's iteration need not reach its
+    # tolerance; the call then says so (flag, warning status, iterations at the
+    # cap) and still returns finite coefficients
+    p = I.cube_small()
+    with _problem(mq, p) as pr:
+        say("full tikhonov exact data", p.name)
+        out = pr.full_solve(p.f_int, p.g_bnd, method=mq.MQH_METHOD_HKT)
+    say("status", out.status, "flags", out.flags, "cg iterations", out.t_ms[7], "lambda", out.lam)
+    flagged = bool(out.flags & mq.MQH_INFO_SOLVE_NOCONV)
+    if flagged:
+        assert out.t_ms[7] == 64 and out.status == mq.MQH_WNOCONV
+    if out.t_ms[7] < 64:
+        assert not flagged
+    assert np.all(np.isfinite(out.coef))
 
 
 def test_full_small_and_invalid(mq, orc):
