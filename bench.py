@@ -407,9 +407,9 @@ def main():
     ap.add_argument("--sweep-oracle", type=int, default=1, help="check the smallest sweep problem against the oracle")
     ap.add_argument("--sweep-workers", type=int, default=4, help="sweep problems run side by side")
     ap.add_argument("--sweep-fixed-shapes", type=int, default=0, help="block-product shapes from the size heuristic")
-    ap.add_argument("--full", type=int, default=0,
-                    help="full-SVD reference on the 20 000-node cube beside HKT: 1 Tikh-Reg, 2 also TSVD "
-                         "(minutes each; 0: skip)")
+    ap.add_argument("--full", type=int, default=1,
+                    help="full-SVD reference on the 20 000-node cube beside HKT: 1 Tikh-Reg (about a minute), "
+                         "2 also TSVD (0: skip)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
