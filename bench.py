@@ -76,6 +76,21 @@ def measured_traffic(kernel_key: str):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
+def measure_peaks(mq):
+    """The reference kernels of mqh_peak_probe on this GPU: HBM copy and read
+    (GB/s, bytes moved), FP32 / FP64 FMA chains and FP64 matrix-core chains
+    (TFLOP/s)."""
+    copy = mq.mqh_peak_probe(mq.MQH_PEAK_COPY, 1 << 31, reps=5)
+    read = mq.mqh_peak_probe(mq.MQH_PEAK_READ, 1 << 32, reps=5)
+    f32 = mq.mqh_peak_probe(mq.MQH_PEAK_FMA_F32, 1 << 14, reps=5)
+    f64 = mq.mqh_peak_probe(mq.MQH_PEAK_FMA_F64, 1 << 14, reps=5)
+    m64 = mq.mqh_peak_probe(mq.MQH_PEAK_MFMA_F64, 1 << 14, reps=5)
+    return dict(hbm_copy_GBs=copy / 1e9, hbm_read_GBs=read / 1e9, fp32_fma_TFLOPs=f32 / 1e12, fp64_fma_TFLOPs=f64 / 1e12,
+                fp64_mfma_TFLOPs=m64 / 1e12,
+                spec=dict(hbm_GBs=HBM_PEAK_GBS, fp32_vector_TFLOPs=157.3, fp64_vector_TFLOPs=78.6,
+                          fp64_matrix_TFLOPs=78.6))
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -439,6 +454,8 @@ def main():
         torch.cuda.synchronize()
         log("copy reference", args.copy_ref_mib, "MiB read +", args.copy_ref_mib, "MiB written")
         del src, dst
+    peaks = measure_peaks(mq)
+    log("measured peaks", json.dumps(peaks))
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
     results = {}
     for i, v in enumerate(variants):
@@ -463,9 +480,16 @@ def main():
         work = p.n_int * n * oi + p.n_bnd * n * ob  # lane-operations per product
         peak = VALU_PEAK_DUAL if mode == "matfree_fp32" else VALU_PEAK_SINGLE
         achieved = work / (dom_ms * 1e-3) / 1e12
+        # measured: FMA lane-operations per second of the probe (flop/s / 2)
+        mpeak = (peaks["fp32_fma_TFLOPs"] if mode == "matfree_fp32" else peaks["fp64_fma_TFLOPs"]) / 2.0
         roof = dict(bound="alu", achieved=achieved, peak=peak / 1e12, unit="TOP/s", frac=achieved / (peak / 1e12),
                     traffic=measured_traffic(kern), kernel=kern, kernel_ms=dom_ms,
-                    other_kernel_ms=min(k_at, k_a), ops_per_product=work)
+                    other_kernel_ms=min(k_at, k_a), ops_per_product=work,
+                    measured_peak=mpeak, frac_of_measured=achieved / mpeak,
+                    measured_peak_note=("FMA lane-operations/s of the FMA probe; achieved counts all of the formula's "
+                                        "operations, some of which run on the matrix cores, so this fraction is not "
+                                        "a VALU efficiency (issue_model_frac is)") if mode == "matfree_fp32" else
+                    "FMA lane-operations/s of the FMA probe")
         if mode == "matfree_fp32":
             quads = (p.n_int * n * QUADS_IDEAL_F32[0] + p.n_bnd * n * QUADS_IDEAL_F32[1]) / 64.0
             t_ideal = quads / (CUS * SIMDS * CLOCK / 4.0)
@@ -477,7 +501,8 @@ def main():
         achieved = 8.0 * n * n / (dom_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                     traffic=measured_traffic(kern), kernel=kern, kernel_ms=dom_ms,
-                    other_kernel_ms=min(k_at, k_a))
+                    other_kernel_ms=min(k_at, k_a), measured_peak=peaks["hbm_read_GBs"],
+                    frac_of_measured=achieved / peaks["hbm_read_GBs"])
 
     ctx = {}
     for v, r in results.items():
@@ -494,7 +519,7 @@ def main():
                 scaling="weak", vs_baseline=None, dtype="f32" if mode == "matfree_fp32" else "f64", data="synthetic",
                 config=dict(workload=p.name, n=n, n_int=p.n_int, n_bnd=p.n_bnd, kappa=p.kappa, eps=p.eps,
                             ell=p.ell, method="HKT", rule="GCV", operator=mode),
-                hkt_time_to_solution_s=head["solve_s"], roofline=roof, variants=ctx)
+                hkt_time_to_solution_s=head["solve_s"], roofline=roof, peaks_measured=peaks, variants=ctx)
     if args.learned > 0:
         from paper_2511_09798_amd import learned as L
 

@@ -159,4 +159,15 @@ void launch_fs_solution_norms(const double* G, int64_t ldg, int64_t n, const dou
 void launch_fs_pcg_dir(const double* sig, const int32_t* rank, int64_t n, int32_t method, const ParamOut* po,
                        const double* pc, int cur, int nxt, const double* r, double* q, hipStream_t s);
 
+// Measurement helpers (peak_kernels.hip): peak_blocks() workgroups of kBlock
+// threads; the copy moves count doubles (count even, x and y 16-byte aligned).
+int peak_blocks();
+void launch_peak_copy(const double* x, double* y, int64_t count, hipStream_t s);
+void launch_peak_read(const double* x, int64_t count, double* out, hipStream_t s);
+void launch_peak_fma32(float* out, int iters, hipStream_t s);
+void launch_peak_fma64(double* out, int iters, hipStream_t s);
+void launch_peak_mfma64(double* out, int iters, hipStream_t s);
+double peak_fma_ops(int iters);
+double peak_mfma_flops(int iters);
+
 }  // namespace mqh

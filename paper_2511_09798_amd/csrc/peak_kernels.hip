@@ -1,0 +1,124 @@
+// peak_kernels.hip -- measurement helpers, not part of the solver: the rates
+// the rooflines are checked against on the GPU at hand.  A device-to-device
+// copy and a read-only stream (HBM), FP32 and FP64 FMA chains as the VALU issues them in this build
+// (unpacked: every HIP source here is compiled without packed FP32), and an
+// FP64 matrix-core chain (v_mfma_f64_16x16x4f64).
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mqh {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kPeakChains = 16;  // independent FMA chains per lane
+constexpr int kPeakCopyUnroll = 4;  // independent 16-byte loads in flight per lane
+constexpr int kPeakMfma = 4;    // independent matrix-core accumulators per wave
+
+// Grid-stride copy, kPeakCopyUnroll loads issued before their stores; the
+// loads of one step are kBlock apart, so a wave reads 1 KiB runs.
+__global__ __launch_bounds__(kBlock) void k_peak_copy(const double2* __restrict__ x, double2* __restrict__ y,
+                                                      int64_t n2) {
+    const int64_t step = (int64_t)gridDim.x * kBlock * kPeakCopyUnroll;
+    int64_t i = (int64_t)blockIdx.x * kBlock * kPeakCopyUnroll + threadIdx.x;
+    for (; i + (kPeakCopyUnroll - 1) * kBlock < n2; i += step) {
+        double2 v[kPeakCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kPeakCopyUnroll; ++u) v[u] = x[i + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < kPeakCopyUnroll; ++u) y[i + u * kBlock] = v[u];
+    }
+    for (int u = 0; u < kPeakCopyUnroll; ++u)
+        if (i + u * kBlock < n2) y[i + u * kBlock] = x[i + u * kBlock];
+}
+
+// Grid-stride read of x (kPeakCopyUnroll loads in flight per lane), summed
+// per lane and stored once per thread so the loads are not dead code.
+__global__ __launch_bounds__(kBlock) void k_peak_read(const double2* __restrict__ x, int64_t n2,
+                                                      double* __restrict__ out) {
+    const int64_t step = (int64_t)gridDim.x * kBlock * kPeakCopyUnroll;
+    int64_t i = (int64_t)blockIdx.x * kBlock * kPeakCopyUnroll + threadIdx.x;
+    double s = 0.0;
+    for (; i + (kPeakCopyUnroll - 1) * kBlock < n2; i += step) {
+        double2 v[kPeakCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kPeakCopyUnroll; ++u) v[u] = x[i + u * kBlock];
+#pragma unroll
+        for (int u = 0; u < kPeakCopyUnroll; ++u) s += v[u].x + v[u].y;
+    }
+    for (int u = 0; u < kPeakCopyUnroll; ++u)
+        if (i + u * kBlock < n2) s += x[i + u * kBlock].x + x[i + u * kBlock].y;
+    out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+// kPeakChains chains v <- v a + b of iters steps each (a < 1: values stay
+// near b / (1 - a)); the sum is stored so nothing is dead code.  a and b vary
+// per lane so that they live in vector registers: gfx950 pairs two FP32
+// instructions in one issue cycle only when neither reads a scalar register.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_peak_fma(T* __restrict__ out, int iters, T a0, T b0) {
+    const T jitter = (T)1 + (T)(threadIdx.x & 7) * (T)1e-7;
+    const T a = a0 * jitter, b = b0 * jitter;
+    T v[kPeakChains];
+#pragma unroll
+    for (int k = 0; k < kPeakChains; ++k) v[k] = (T)(threadIdx.x + k) * (T)1e-3;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < kPeakChains; ++k) v[k] = fma(v[k], a, b);
+    }
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < kPeakChains; ++k) s += v[k];
+    out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+// kPeakMfma accumulators, iters matrix-core steps each.
+__global__ __launch_bounds__(kBlock) void k_peak_mfma64(double* __restrict__ out, int iters) {
+    const double a = 1e-3 * (double)(threadIdx.x & (kWave - 1)), b = 0.5;
+    v4d acc[kPeakMfma];
+#pragma unroll
+    for (int q = 0; q < kPeakMfma; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int q = 0; q < kPeakMfma; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPeakMfma; ++q) s += acc[q][0] + acc[q][1] + acc[q][2] + acc[q][3];
+    out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+}  // namespace
+
+int peak_blocks() { return 256 * 8; }  // 8 workgroups of 4 waves per CU
+
+void launch_peak_copy(const double* x, double* y, int64_t count, hipStream_t s) {
+    k_peak_copy<<<(unsigned)peak_blocks(), kBlock, 0, s>>>(reinterpret_cast<const double2*>(x),
+                                                           reinterpret_cast<double2*>(y), count / 2);
+}
+
+void launch_peak_read(const double* x, int64_t count, double* out, hipStream_t s) {
+    k_peak_read<<<(unsigned)peak_blocks(), kBlock, 0, s>>>(reinterpret_cast<const double2*>(x), count / 2, out);
+}
+
+void launch_peak_fma32(float* out, int iters, hipStream_t s) {
+    k_peak_fma<float><<<(unsigned)peak_blocks(), kBlock, 0, s>>>(out, iters, 0.999f, 1e-3f);
+}
+
+void launch_peak_fma64(double* out, int iters, hipStream_t s) {
+    k_peak_fma<double><<<(unsigned)peak_blocks(), kBlock, 0, s>>>(out, iters, 0.999, 1e-3);
+}
+
+void launch_peak_mfma64(double* out, int iters, hipStream_t s) {
+    k_peak_mfma64<<<(unsigned)peak_blocks(), kBlock, 0, s>>>(out, iters);
+}
+
+// Work per launch: FMA lane operations (fma kinds) or flops (matrix cores).
+double peak_fma_ops(int iters) { return (double)peak_blocks() * kBlock * kPeakChains * (double)iters; }
+double peak_mfma_flops(int iters) {
+    return (double)peak_blocks() * (kBlock / kWave) * kPeakMfma * (double)iters * (2.0 * 16 * 16 * 4);
+}
+
+}  // namespace mqh

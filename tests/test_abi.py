@@ -175,3 +175,17 @@ def test_network_size_matches_oracle():
     d = _header_defines()
     assert d["MQH_MLP_NPARAMS"] == M.n_params()
     assert (d["MQH_MLP_IN"], d["MQH_MLP_WIDTH"], d["MQH_MLP_OUT"]) == (M.SIZES[0], M.SIZES[1], M.SIZES[-1])
+
+
+def test_peak_probe_rejects_invalid_arguments(mq):
+    # argument checks run before any device work
+    L = mq.lib
+    r = ctypes.c_double(1.0)
+    assert L.mqh_peak_probe(7, 1024, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
+    assert L.mqh_peak_probe(mq.MQH_PEAK_READ, 8, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
+    assert r.value == 0.0
+    assert L.mqh_peak_probe(mq.MQH_PEAK_COPY, 8, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
+    assert L.mqh_peak_probe(mq.MQH_PEAK_FMA_F32, 0, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
+    assert L.mqh_peak_probe(mq.MQH_PEAK_FMA_F64, 1 << 21, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
+    assert L.mqh_peak_probe(mq.MQH_PEAK_MFMA_F64, 16, 0, ctypes.byref(r), None) == mq.MQH_EINVAL
+    assert L.mqh_peak_probe(mq.MQH_PEAK_COPY, 1024, 1, None, None) == mq.MQH_EINVAL
