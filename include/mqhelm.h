@@ -89,7 +89,8 @@ extern "C" {
 
 /* Largest number of Golub-Kahan steps a solve accepts (projected problem size). */
 #define MQH_MAX_ELL 1024
-#define MQH_FULL_MAX_N 32768 /* largest n of the full-SVD reference path (8.6 GB work matrix) */
+#define MQH_FULL_MAX_N 32768  /* largest n of the full-SVD reference path (8.6 GB work matrix) */
+#define MQH_FULL_CG_MAX 1024  /* conjugate-gradient iterations of a full solution at most */
 #define MQH_BLOCK_RHS 16 /* right-hand sides run in lockstep per group (mqh_gkb_multi, mqh_solve_multi) */
 
 /* ---- learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs ---- */
@@ -434,7 +435,7 @@ int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* 
  *   flags (MQH_INFO_GCV_AT_EDGE), t_ms [0] assembly, [1] Jacobi sweeps,
  *   [2] singular values and order, [3] parameter choice, [4] solution,
  *   [5] total, [6] the last sweep's largest off-diagonal measure, [7] the
- *   conjugate-gradient iterations of the solution (at most 64; at the cap
+ *   conjugate-gradient iterations of the solution (at most MQH_FULL_CG_MAX; at the cap
  *   above the tolerance MQH_INFO_SOLVE_NOCONV is set and MQH_WNOCONV
  *   returned: this happens when lambda lies below the accuracy of the SVD,
  *   as GCV chooses on exact data, where the Tikhonov solution is not

@@ -880,7 +880,7 @@ inline double full_tol(int64_t n) { return 16.0 * sqrt((double)n) * DBL_EPSILON;
 inline double full_floor(int64_t n) { return 2.0 * full_tol(n); }
 constexpr int kFullStall = 3;
 
-constexpr int kFullCgMax = 64;        // conjugate-gradient iterations of the solutions' dual system
+constexpr int kFullCgMax = MQH_FULL_CG_MAX;  // conjugate-gradient iterations of the solutions' dual system
 constexpr double kFullCgTol = 1e-15;  // stop when sqrt(r^T D^-1 r) falls below this fraction of its start
 
 // Assembles [A | f] (f already staged in r.f, or zero) and runs Jacobi
@@ -1027,6 +1027,8 @@ int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters, bool* 
     HIPCHK(hipMemcpyAsync(&rz0, r.cpc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (!isfinite(rz0)) return fail(MQH_EDEVICE, "full problem: non-finite right-hand side of the solution");
+    const char* tr = getenv("MQH_TRACE_FULL");
+    const bool trace = tr != nullptr && tr[0] == '1';
     int it = 0;
     *converged = true;
     if (rz0 > 0.0) {
@@ -1041,6 +1043,8 @@ int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters, bool* 
             HIPCHK(hipMemcpyAsync(&rz, r.cpc + nxt, sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             ++it;
+            if (trace && (it % 8 == 0 || it < 8))
+                fprintf(stderr, "[mqh full] cg %d sqrt(rz/rz0) %.3e\n", it, sqrt(rz / rz0));
             if (!isfinite(rz)) return fail(MQH_EDEVICE, "full problem: non-finite solution iterate");
             if (!(rz > stop)) {
                 *converged = true;

@@ -45,6 +45,7 @@ MQH_INFO_LCURVE_AT_EDGE = 4
 MQH_INFO_SOLVE_NOCONV = 8
 MQH_MAX_ELL = 1024
 MQH_FULL_MAX_N = 32768
+MQH_FULL_CG_MAX = 1024
 MQH_BLOCK_RHS = 16
 MQH_PEAK_COPY = 0
 MQH_PEAK_FMA_F32 = 1

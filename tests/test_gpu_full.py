@@ -194,8 +194,8 @@ def test_full_exact_data_reports_the_solution_state(mq, orc):
     say("status", out.status, "flags", out.flags, "cg iterations", out.t_ms[7], "lambda", out.lam)
     flagged = bool(out.flags & mq.MQH_INFO_SOLVE_NOCONV)
     if flagged:
-        assert out.t_ms[7] == 64 and out.status == mq.MQH_WNOCONV
-    if out.t_ms[7] < 64:
+        assert out.t_ms[7] == mq.MQH_FULL_CG_MAX and out.status == mq.MQH_WNOCONV
+    if out.t_ms[7] < mq.MQH_FULL_CG_MAX:
         assert not flagged
     assert np.all(np.isfinite(out.coef))
 
