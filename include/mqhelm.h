@@ -91,6 +91,7 @@ extern "C" {
 #define MQH_MAX_ELL 1024
 #define MQH_FULL_MAX_N 32768  /* largest n of the full-SVD reference path (8.6 GB work matrix) */
 #define MQH_FULL_CG_MAX 1024  /* conjugate-gradient iterations of a full solution at most */
+#define MQH_BLOCK_MAX_DIM 4096  /* (ell + 1) nrhs at most for the block Golub-Kahan calls */
 #define MQH_BLOCK_RHS 16 /* right-hand sides run in lockstep per group (mqh_gkb_multi, mqh_solve_multi) */
 
 /* ---- learned predictor network: 24 inputs, three tanh layers of width 128, 2 outputs ---- */
@@ -397,6 +398,60 @@ typedef struct {
 } mqh_sweep_item;
 
 int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* opts, int32_t workers);
+
+/*
+ * Block Golub-Kahan: nrhs <= MQH_BLOCK_RHS right-hand sides that share one
+ * Krylov space (Algorithm 1 with the n x nrhs block F in place of f; the
+ * paper has one right-hand side per problem).  The recurrence:
+ *   W_1 E_1 = F,
+ *   Z_j D_j^T = A^T W_j - Z_{j-1} E_j^T,   W_{j+1} E_{j+1} = A Z_j - W_j D_j,
+ * each right side reorthogonalised against every earlier block of its basis
+ * (classical Gram-Schmidt twice) and factored by a QR with a non-negative
+ * diagonal in R (shifted Cholesky QR applied three times, on the FP64
+ * matrix cores).  A Z_ell = W_{ell+1} C with C the lower block bidiagonal
+ * (ell + 1) nrhs x ell nrhs matrix of the D_j (lower triangular, diagonal
+ * blocks) and E_{j+1} (upper triangular, below them).  A QR whose R has a
+ * diagonal entry at most n eps times the largest diagonal entry of the D
+ * and E blocks so far (E_1 left out) is a breakdown: at a D block ell_done =
+ * j - 1 (flag 1), at an E block ell_done = j with E_{j+1} = 0 (flag 2).
+ * The products use the problem's operator (FP32-evaluated block products
+ * on the matrix cores for MQH_OP_MATFREE_FP32 and nrhs >= 2).
+ *
+ * F: n x nrhs, leading dimension ldf >= n.  Needs ell >= 1, ell nrhs <= n
+ * and (ell + 1) nrhs <= MQH_BLOCK_MAX_DIM.  Host or device pointers
+ * (MQH_FLAG_DEVICE_PTRS in flags / opts->flags); the library allocates its
+ * workspace per call.
+ *
+ * mqh_gkb_block: C ((ell + 1) nrhs x ell nrhs, row-major; blocks past
+ *   ell_done are zero), E1 (nrhs x nrhs row-major, NULL allowed), W
+ *   (n x (ell + 1) nrhs column-major, leading dimension n, NULL allowed),
+ *   Z (n x ell nrhs, NULL allowed).  Returns MQH_WBREAKDOWN after a
+ *   breakdown.
+ * mqh_solve_block: for each source k the Tikhonov solution on the shared
+ *   space, y_k = argmin ||C y - (E_1 e_k; 0)||^2 + lambda_k^2 ||y||^2 and
+ *   coef_k = Z y_k (column k of coef, leading dimension ldc >= n).
+ *   opts->method must be MQH_METHOD_HKT; opts->ell is the number of block
+ *   steps; opts->rule MQH_RULE_GCV (per source, the full-problem GCV of
+ *   eq. (25) on the (ell + 1) nrhs projected rows, s_perp = what the
+ *   retained components leave of ||E_1 e_k||^2, on the grid of
+ *   mqh_param_choice; for nrhs = 1 this is the projected GCV of eq. (30))
+ *   or MQH_RULE_FIXED (lambda_fixed for every source).  The projected
+ *   problem is solved through the full-SVD path on [C | 0] (square).  sv
+ *   (ell_done nrhs, NULL allowed): singular values of C, descending.  info:
+ *   nrhs records (NULL allowed): ell_done, lambda_chosen, crit (GCV at the
+ *   choice), resid_norm = ||A coef_k - f_k|| and sol_norm = ||coef_k|| (from
+ *   the projected problem; equal by the block relations), flags
+ *   (MQH_INFO_BREAKDOWN, MQH_INFO_GCV_AT_EDGE, MQH_INFO_SOLVE_NOCONV), t_ms
+ *   [0] upload, [1] block recurrence, [2] projected problem (SVD, choices,
+ *   solutions), [3] lift and download, [5] total, [6] Jacobi sweeps of the
+ *   projected SVD, [7] conjugate-gradient iterations of this source.
+ *   Returns MQH_WBREAKDOWN, else MQH_WNOCONV, else MQH_WEDGE (any source),
+ *   else MQH_OK.
+ */
+int mqh_gkb_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, int32_t ell, double* C, double* E1,
+                  double* W, double* Z, int32_t* ell_done, int32_t* flag, uint32_t flags);
+int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, const mqh_solve_opts* opts,
+                    double* coef, int64_t ldc, double* sv, mqh_solve_info* info);
 
 /*
  * Reference path: the full SVD of A and the classical regularised solutions

@@ -1,0 +1,225 @@
+// block_kernels.hip -- the block Golub-Kahan process for s <= 16 right-hand
+// sides that share one Krylov space (Algorithm 1 with an n x s starting
+// block) on gfx950, FP64.
+//
+// Two tall-skinny contractions carry the reorthogonalisation against a
+// shared basis of m columns (m = s j at step j) and the block QR:
+//   c = V^T P   (m x s, K = n rows)        -- k_blk_gemvt + k_blk_reduce
+//   P -= V c, or P = V c                   -- k_blk_update
+// both on the FP64 matrix cores (v_mfma_f64_16x16x4f64: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16] and receives D[4r + l/16][l%16]).  The
+// block QR is shifted Cholesky QR applied three times (the shift in the
+// first pass keeps the Cholesky factorisation defined for nearly dependent
+// columns; the two unshifted passes restore orthogonality to rounding):
+// k_blk_chol factors one 16 x 16 Gram matrix on one lane.
+
+#include <float.h>
+#include <math.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mqh {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kBt = 64;        // rows of a staged tile; basis columns per workgroup of k_blk_gemvt
+constexpr int kBtLd = kBt + 1;  // padded LDS row of the basis tile
+constexpr int kPLd = kBlkRhs + 1;
+
+// part[(chunk m + col) 16 + k] = sum over the rows i of the chunk (i < n) of
+// V[col][i] P[k][i], for col < m and all 16 k (zero for k >= s).  V: column
+// col at V + col ldv; P: column k at P + k ldp.  Grid (chunks, ceil(m / 64)),
+// chunk a multiple of 64; wave w forms columns 64 y + 16 w .. + 15.
+__global__ __launch_bounds__(kBlock) void k_blk_gemvt(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                                      int32_t m, const double* __restrict__ P, int64_t ldp,
+                                                      int32_t s, int64_t chunk, double* __restrict__ part) {
+    __shared__ double tV[kBt * kBtLd];
+    __shared__ double tP[kBt * kPLd];
+    const int64_t r0 = (int64_t)blockIdx.x * chunk;
+    const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+    const int c0 = blockIdx.y * kBt;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4;
+    const int rr = threadIdx.x & (kBt - 1), rq = threadIdx.x / kBt;  // staging: row rr, column rq + 4 q
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t rb = r0; rb < r1; rb += kBt) {
+        __syncthreads();  // the previous tile's reads are done
+        const int64_t row = rb + rr;
+        const bool rok = row < r1;
+#pragma unroll
+        for (int q = 0; q < kBt / (kBlock / kBt); ++q) {
+            const int cc = rq + (kBlock / kBt) * q;
+            const int col = c0 + cc;
+            tV[rr * kBtLd + cc] = (rok && col < m) ? V[(int64_t)col * ldv + row] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kBlkRhs / (kBlock / kBt); ++q) {
+            const int k = rq + (kBlock / kBt) * q;
+            tP[rr * kPLd + k] = (rok && k < s) ? P[(int64_t)k * ldp + row] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < kBt; kk += 4) {
+            // A[i][k'] = V[col 16 w + i][row kk + k'], B[k'][j] = P[rhs j][row kk + k']
+            const double a = tV[(kk + lk) * kBtLd + 16 * w + li];
+            const double b = tP[(kk + lk) * kPLd + li];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int col = c0 + 16 * w + 4 * r + lk;
+        if (col < m) part[((int64_t)blockIdx.x * m + col) * kBlkRhs + li] = acc[r];
+    }
+}
+
+// c[col 16 + k] = sum over chunks (in order) of part[(chunk m + col) 16 + k].
+__global__ __launch_bounds__(kBlock) void k_blk_reduce(const double* __restrict__ part, int chunks, int32_t m,
+                                                       double* __restrict__ c) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= (int64_t)m * kBlkRhs) return;
+    double v = 0.0;
+    for (int q = 0; q < chunks; ++q) v += part[(int64_t)q * m * kBlkRhs + e];
+    c[e] = v;
+}
+
+// Rows [16 (4 x + w), + 16) of the s output columns, per wave:
+//   sub = 1: P[k][i] -= sum_col V[col][i] c[col cs + k ks]
+//   sub = 0: P[k][i]  = sum_col V[col][i] c[col cs + k ks]
+// (V may be P itself for sub = 0: a wave reads all its rows before it
+// writes them, and no two waves share a row).  No barrier: waves past n
+// return at once.
+__global__ __launch_bounds__(kBlock) void k_blk_update(const double* V, int64_t ldv, int64_t n, int32_t m,
+                                                       const double* __restrict__ c, int64_t cs, int64_t ks,
+                                                       double* P, int64_t ldp, int32_t s, int32_t sub) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t row0 = ((int64_t)blockIdx.x * (kBlock / kWave) + w) * 16;
+    if (row0 >= n) return;
+    const int64_t row = row0 + li;
+    const bool rok = row < n;
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < m; kk += 4) {
+        const int col = kk + lk;
+        const bool cok = col < m;
+        // A[i][k'] = V[col kk + k'][row0 + i], B[k'][j] = c[col kk + k'][j]
+        const double a = (rok && cok) ? V[(int64_t)col * ldv + row] : 0.0;
+        const double b = (cok && li < s) ? c[(int64_t)col * cs + (int64_t)li * ks] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    if (li >= s) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t rr = row0 + 4 * r + lk;
+        if (rr < n) {
+            double* dst = P + (int64_t)li * ldp + rr;
+            *dst = sub ? *dst - acc[r] : acc[r];
+        }
+    }
+}
+
+// One pass of (shifted) Cholesky QR, on one lane: G (c layout, G[i 16 + j] =
+// P_i . P_j, i, j < s) plus, if shifted, 11 (n s + s (s + 1)) eps trace(G) on
+// the diagonal, factored as R^T R (R upper triangular); Rinv = R^{-1} in the
+// c layout of k_blk_update (Rinv[col 16 + k]); Racc <- R Racc (row-major
+// 16 x 16, the accumulated triangular factor).  status <- 1 if a pivot is
+// not positive and finite (Racc and Rinv are then left as they were).
+__global__ void k_blk_chol(const double* __restrict__ G, int32_t s, int64_t n, int32_t shifted,
+                           double* __restrict__ Rinv, double* __restrict__ Racc, int32_t* __restrict__ status) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double R[kBlkRhs][kBlkRhs];
+    double tr = 0.0;
+    for (int i = 0; i < s; ++i) tr += G[i * kBlkRhs + i];
+    const double shift = shifted ? 11.0 * ((double)n * s + (double)s * (s + 1)) * DBL_EPSILON * tr : 0.0;
+    for (int i = 0; i < kBlkRhs; ++i)
+        for (int j = 0; j < kBlkRhs; ++j) R[i][j] = 0.0;
+    for (int j = 0; j < s; ++j) {
+        double d = G[j * kBlkRhs + j] + shift;
+        for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
+        if (!(d > 0.0) || !isfinite(d)) {
+            *status = 1;
+            return;
+        }
+        const double rjj = sqrt(d);
+        R[j][j] = rjj;
+        for (int i = j + 1; i < s; ++i) {
+            double v = G[j * kBlkRhs + i];
+            for (int k = 0; k < j; ++k) v -= R[k][j] * R[k][i];
+            R[j][i] = v / rjj;
+        }
+    }
+    // inverse of the upper triangular R, column by column (back substitution)
+    double X[kBlkRhs][kBlkRhs];
+    for (int i = 0; i < kBlkRhs; ++i)
+        for (int j = 0; j < kBlkRhs; ++j) X[i][j] = 0.0;
+    for (int j = 0; j < s; ++j) {
+        for (int i = j; i >= 0; --i) {
+            double v = (i == j) ? 1.0 : 0.0;
+            for (int k = i + 1; k <= j; ++k) v -= R[i][k] * X[k][j];
+            X[i][j] = v / R[i][i];
+        }
+    }
+    for (int i = 0; i < kBlkRhs; ++i)
+        for (int j = 0; j < kBlkRhs; ++j) Rinv[i * kBlkRhs + j] = X[i][j];
+    // Racc <- R Racc (both upper triangular)
+    double T[kBlkRhs][kBlkRhs];
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) {
+            double v = 0.0;
+            for (int k = i; k <= j; ++k) v += R[i][k] * Racc[k * kBlkRhs + j];
+            T[i][j] = v;
+        }
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) Racc[i * kBlkRhs + j] = T[i][j];
+}
+
+// Racc <- identity (row-major 16 x 16), status <- 0.
+__global__ void k_blk_eye(double* __restrict__ Racc, int32_t* __restrict__ status) {
+    const int e = threadIdx.x;
+    if (e < kBlkRhs * kBlkRhs) Racc[e] = (e / kBlkRhs == e % kBlkRhs) ? 1.0 : 0.0;
+    if (e == 0) *status = 0;
+}
+
+}  // namespace
+
+int blk_chunks(int64_t n, int32_t m, int64_t* chunk) {
+    const int64_t tiles = (m + kBt - 1) / kBt;
+    int64_t want = (1024 + tiles - 1) / tiles;
+    const int64_t cmax = (n + kBt - 1) / kBt;
+    if (want > cmax) want = cmax;
+    if (want < 1) want = 1;
+    int64_t ch = (n + want - 1) / want;
+    ch = (ch + kBt - 1) / kBt * kBt;
+    *chunk = ch;
+    return (int)((n + ch - 1) / ch);
+}
+
+void launch_blk_gemvt(const double* V, int64_t ldv, int64_t n, int32_t m, const double* P, int64_t ldp, int32_t s,
+                      double* part, double* c, hipStream_t st) {
+    int64_t chunk;
+    const int chunks = blk_chunks(n, m, &chunk);
+    k_blk_gemvt<<<dim3((unsigned)chunks, (unsigned)((m + kBt - 1) / kBt)), kBlock, 0, st>>>(V, ldv, n, m, P, ldp, s,
+                                                                                           chunk, part);
+    k_blk_reduce<<<(unsigned)(((int64_t)m * kBlkRhs + kBlock - 1) / kBlock), kBlock, 0, st>>>(part, chunks, m, c);
+}
+
+void launch_blk_update(const double* V, int64_t ldv, int64_t n, int32_t m, const double* c, int64_t cs, int64_t ks,
+                       double* P, int64_t ldp, int32_t s, int32_t sub, hipStream_t st) {
+    const int64_t rows_per_block = 16 * (kBlock / kWave);
+    k_blk_update<<<(unsigned)((n + rows_per_block - 1) / rows_per_block), kBlock, 0, st>>>(V, ldv, n, m, c, cs, ks, P,
+                                                                                         ldp, s, sub);
+}
+
+void launch_blk_chol(const double* G, int32_t s, int64_t n, int32_t shifted, double* Rinv, double* Racc,
+                     int32_t* status, hipStream_t st) {
+    k_blk_chol<<<1, 64, 0, st>>>(G, s, n, shifted, Rinv, Racc, status);
+}
+
+void launch_blk_eye(double* Racc, int32_t* status, hipStream_t st) {
+    k_blk_eye<<<1, kBlkRhs * kBlkRhs, 0, st>>>(Racc, status);
+}
+
+}  // namespace mqh

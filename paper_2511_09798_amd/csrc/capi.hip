@@ -883,17 +883,13 @@ constexpr int kFullStall = 3;
 constexpr int kFullCgMax = MQH_FULL_CG_MAX;  // conjugate-gradient iterations of the solutions' dual system
 constexpr double kFullCgTol = 1e-15;  // stop when sqrt(r^T D^-1 r) falls below this fraction of its start
 
-// Assembles [A | f] (f already staged in r.f, or zero) and runs Jacobi
-// sweeps, each on the rows ordered by decreasing norm, until in a whole sweep
-// every pair of rows has the component of the smaller along the larger at
-// most full_tol(n) ||A||_F, or stalls below full_floor(n) ||A||_F (or
-// kFullMaxSweeps); then sigma, f^
-// (input row order) and their descending order.
-int full_svd_run(mqh_problem* p, FullRun& r) {
-    hipStream_t s = p->stream;
-    const int64_t n = p->n;
+// Sizes and buffers of a full SVD of an n x n matrix with nrhs data
+// columns: G = [M | F] row-major, ldg = n + nrhs rounded up to 64, rows
+// padded with zero rows to an even number of 32-row blocks; the block pairs
+// of a round-robin tournament.  G is cleared.
+int full_prepare(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
     r.n = n;
-    r.ldg = round_up(n + 1, 64);
+    r.ldg = round_up(n + nrhs, 64);
     r.nblk = (int)((n + kFsBlock - 1) / kFsBlock);
     if (r.nblk % 2) ++r.nblk;
     r.nrow = (int64_t)r.nblk * kFsBlock;
@@ -932,11 +928,17 @@ int full_svd_run(mqh_problem* p, FullRun& r) {
     }
     HIPCHK(hipMemcpyAsync(r.pairs, pr.data(), pr.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(r.G, 0, (size_t)(r.nrow * r.ldg) * sizeof(double), s));
-    launch_assemble(p->X64, n, p->n_int, r.ldg, p->ec, r.G, s);
-    LAUNCHCHK("full SVD: assembly");
-    launch_fs_setf(r.G, r.ldg, n, r.f, s);
-    LAUNCHCHK("full SVD: data column");
-    HIPCHK(hipEventRecord(p->ev[1], s));
+    HIPCHK(hipStreamSynchronize(s));  // pr is a local
+    return MQH_OK;
+}
+
+// Jacobi sweeps on the filled G (n matrix columns, nrhs data columns), each
+// on the rows ordered by decreasing norm, until in a whole sweep every pair
+// of rows has the component of the smaller along the larger at most
+// full_tol(n) ||M||_F, or stalls below full_floor(n) ||M||_F (or
+// kFullMaxSweeps); then sigma and the first data column f^ (input row
+// order) and their descending order.
+int full_sweeps(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
     const double tol = full_tol(n);
     std::vector<double> rn((size_t)r.nrow);
     std::vector<int32_t> idx((size_t)r.nrow);
@@ -956,7 +958,7 @@ int full_svd_run(mqh_problem* p, FullRun& r) {
         HIPCHK(hipMemcpyAsync(rn.data(), r.rnorm, (size_t)r.nrow * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (sw == 0) {
-            // ||A||_F (invariant under the rotations)
+            // ||M||_F (invariant under the rotations)
             double fro2 = 0.0;
             for (double v : rn) fro2 += v * v;
             if (!(fro2 > 0.0) || !isfinite(fro2)) return fail(MQH_EDEVICE, "full SVD: zero or non-finite matrix");
@@ -970,7 +972,7 @@ int full_svd_run(mqh_problem* p, FullRun& r) {
             launch_fs_gram(r.G, r.ldg, n, r.rowidx, prd, r.npairs, r.S, r.chunk, r.Pg, s);
             launch_fs_eig(r.Pg, r.S, r.npairs, tol, inv_f, kFullMaxInner, r.Pout, r.flag,
                           r.off + (int64_t)rd * r.npairs, s);
-            launch_fs_update(r.G, r.ldg, n + 1, r.rowidx, prd, r.npairs, r.Pout, r.flag, s);
+            launch_fs_update(r.G, r.ldg, n + nrhs, r.rowidx, prd, r.npairs, r.Pout, r.flag, s);
         }
         LAUNCHCHK("full SVD: Jacobi sweep");
         launch_fs_maxoff(r.off, (int64_t)r.rounds * r.npairs, r.maxoff, s);
@@ -999,29 +1001,46 @@ int full_svd_run(mqh_problem* p, FullRun& r) {
             break;
         }
     }
-    HIPCHK(hipEventRecord(p->ev[2], s));
     launch_fs_norms(r.G, r.ldg, n, n, r.sig, r.fh, s);
     launch_fs_rank(r.sig, r.fh, n, r.rank, r.sv, r.fs, r.order, s);
     LAUNCHCHK("full SVD: singular values");
+    return MQH_OK;
+}
+
+// Assembles [A | f] (f already staged in r.f, or zero) and runs the sweeps.
+int full_svd_run(mqh_problem* p, FullRun& r) {
+    hipStream_t s = p->stream;
+    const int64_t n = p->n;
+    int rc;
+    if ((rc = full_prepare(s, r, n, 1))) return rc;
+    launch_assemble(p->X64, n, p->n_int, r.ldg, p->ec, r.G, s);
+    LAUNCHCHK("full SVD: assembly");
+    launch_fs_setf(r.G, r.ldg, n, r.f, s);
+    LAUNCHCHK("full SVD: data column");
+    HIPCHK(hipEventRecord(p->ev[1], s));
+    if ((rc = full_sweeps(s, r, n, 1))) return rc;
+    HIPCHK(hipEventRecord(p->ev[2], s));
     HIPCHK(hipEventRecord(p->ev[3], s));
     return MQH_OK;
 }
 
 // The solution x = G^T y of the Tikhonov (method 1) or TSVD (method 0) dual
 // system by preconditioned conjugate gradients (the kernels' comment gives
-// the system); y in r.rnorm, the residual in r.rtmp, x in r.coef; then
-// po->rho = ||A x - f|| and po->eta = ||x|| of that x.
-int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters, bool* converged) {
-    hipStream_t s = p->stream;
-    const int64_t n = p->n;
+// the system) for the data column fh (physical row order) and the choice
+// po; rows of rank >= rcap are left out.  y in r.rnorm, the residual in
+// r.rtmp, x in r.coef; then po->rho = ||M x - f|| and po->eta = ||x||.
+int full_solution(hipStream_t s, FullRun& r, int64_t n, int32_t method, const double* fh, ParamOut* po, int64_t rcap,
+                  int* iters, bool* converged) {
     int rc;
     const int chunks = fs_gemvt_chunks(n);
-    if ((rc = dalloc(&r.cq, (size_t)n)) || (rc = dalloc(&r.cw, (size_t)n)) || (rc = dalloc(&r.ct, (size_t)n)) ||
-        (rc = dalloc(&r.cpart, (size_t)chunks * (size_t)n)) || (rc = dalloc(&r.cpc, 4)))
-        return rc;
+    if (r.cq == nullptr) {
+        if ((rc = dalloc(&r.cq, (size_t)n)) || (rc = dalloc(&r.cw, (size_t)n)) || (rc = dalloc(&r.ct, (size_t)n)) ||
+            (rc = dalloc(&r.cpart, (size_t)chunks * (size_t)n)) || (rc = dalloc(&r.cpc, 4)))
+            return rc;
+    }
     double* y = r.rnorm;
     double* res = r.rtmp;
-    launch_fs_pcg_start(r.sig, r.fh, r.rank, n, method, r.po, y, res, r.cq, r.ct, r.cpc, 2, s);
+    launch_fs_pcg_start(r.sig, fh, r.rank, n, method, rcap, po, y, res, r.cq, r.ct, r.cpc, 2, s);
     LAUNCHCHK("full problem: solution start");
     double rz0 = 0.0;
     HIPCHK(hipMemcpyAsync(&rz0, r.cpc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1036,8 +1055,8 @@ int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters, bool* 
         *converged = false;
         while (it < kFullCgMax) {
             const int cur = 2 + (it & 1), nxt = 2 + ((it + 1) & 1);
-            launch_fs_pcg_iter(r.G, r.ldg, n, r.sig, r.rank, method, r.po, r.cpc, cur, nxt, y, res, r.cq, r.cw, r.ct,
-                               r.cpart, r.coef, s);
+            launch_fs_pcg_iter(r.G, r.ldg, n, r.sig, r.rank, method, rcap, po, r.cpc, cur, nxt, y, res, r.cq, r.cw,
+                               r.ct, r.cpart, r.coef, s);
             LAUNCHCHK("full problem: solution iteration");
             double rz = 0.0;
             HIPCHK(hipMemcpyAsync(&rz, r.cpc + nxt, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1050,11 +1069,11 @@ int full_solution(mqh_problem* p, FullRun& r, int32_t method, int* iters, bool* 
                 *converged = true;
                 break;
             }
-            launch_fs_pcg_dir(r.sig, r.rank, n, method, r.po, r.cpc, cur, nxt, res, r.cq, s);
+            launch_fs_pcg_dir(r.sig, r.rank, n, method, rcap, po, r.cpc, cur, nxt, res, r.cq, s);
         }
     }
     launch_fs_gemvt(r.G, r.ldg, n, y, r.cpart, r.coef, s);
-    launch_fs_solution_norms(r.G, r.ldg, n, r.coef, r.fh, r.ct, r.cw, r.cpc, r.po, s);
+    launch_fs_solution_norms(r.G, r.ldg, n, r.coef, fh, r.ct, r.cw, r.cpc, po, s);
     LAUNCHCHK("full problem: solution");
     *iters = it;
     return MQH_OK;
@@ -1095,6 +1114,271 @@ int check_opts(const mqh_problem* p, const mqh_solve_opts* opts) {
 
 void clear_info(mqh_solve_info* info) {
     if (info) memset(info, 0, sizeof(*info));
+}
+
+// ---------------------------------------------------------------------------
+// Block Golub-Kahan for s <= 16 right-hand sides sharing one Krylov space
+// (Algorithm 1 with an n x s starting block) and the block Tikhonov
+// solutions on it.  Bases W (n x (ell + 1) s) and Z (n x ell s) are
+// column-major with leading dimension ldn, block j at column j s.
+// ---------------------------------------------------------------------------
+
+struct BlockWs {
+    double* W = nullptr;
+    double* Z = nullptr;
+    double* P = nullptr;     // ldn x 16 work block
+    double* part = nullptr;  // split-K partials of V^T P
+    double* c = nullptr;     // m x 16 coefficients
+    double* G = nullptr;     // 16 x 16 Gram matrix
+    double* Rinv = nullptr;  // 16 x 16
+    double* Racc = nullptr;  // 16 x 16 accumulated R
+    double* mat = nullptr;   // 16 x 16 shift block (c layout)
+    int32_t* status = nullptr;
+    ~BlockWs() {
+        dfree(W);
+        dfree(Z);
+        dfree(P);
+        dfree(part);
+        dfree(c);
+        dfree(G);
+        dfree(Rinv);
+        dfree(Racc);
+        dfree(mat);
+        dfree(status);
+    }
+};
+
+int block_alloc(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell) {
+    const int64_t ldn = p->ldn;
+    const int32_t mmax = (ell + 1) * s;
+    int64_t chunk;
+    int64_t most = 0;  // largest chunks x m over the m the process uses
+    for (int32_t m = s; m <= mmax; m += s) {
+        const int64_t q = (int64_t)blk_chunks(p->n, m, &chunk) * m;
+        if (q > most) most = q;
+    }
+    int rc;
+    if ((rc = dalloc(&b.W, (size_t)((int64_t)mmax * ldn))) || (rc = dalloc(&b.Z, (size_t)((int64_t)ell * s * ldn))) ||
+        (rc = dalloc(&b.P, (size_t)(kBlkRhs * ldn))) || (rc = dalloc(&b.part, (size_t)(most * kBlkRhs))) ||
+        (rc = dalloc(&b.c, (size_t)mmax * kBlkRhs)) || (rc = dalloc(&b.G, kBlkRhs * kBlkRhs)) ||
+        (rc = dalloc(&b.Rinv, kBlkRhs * kBlkRhs)) || (rc = dalloc(&b.Racc, kBlkRhs * kBlkRhs)) ||
+        (rc = dalloc(&b.mat, kBlkRhs * kBlkRhs)) || (rc = dalloc(&b.status, 1)))
+        return rc;
+    hipStream_t st = p->stream;
+    HIPCHK(hipMemsetAsync(b.W, 0, (size_t)mmax * ldn * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(b.Z, 0, (size_t)ell * s * ldn * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(b.P, 0, (size_t)kBlkRhs * ldn * sizeof(double), st));
+    return MQH_OK;
+}
+
+// Q R = X in place (X: n x s, leading dimension ldn) by shifted Cholesky QR
+// three times; R (s x s, row-major, upper triangular) to the host.  *bad is
+// set when a Cholesky factorisation fails (X numerically zero or not finite).
+int block_qr(mqh_problem* p, BlockWs& b, double* X, int32_t s, double* Rh, bool* bad) {
+    hipStream_t st = p->stream;
+    const int64_t n = p->n, ldn = p->ldn;
+    launch_blk_eye(b.Racc, b.status, st);
+    for (int pass = 0; pass < 3; ++pass) {
+        launch_blk_gemvt(X, ldn, n, s, X, ldn, s, b.part, b.G, st);
+        launch_blk_chol(b.G, s, n, pass == 0 ? 1 : 0, b.Rinv, b.Racc, b.status, st);
+        launch_blk_update(X, ldn, n, s, b.Rinv, kBlkRhs, 1, X, ldn, s, 0, st);
+    }
+    LAUNCHCHK("block QR");
+    double R[kBlkRhs * kBlkRhs];
+    int32_t status = 0;
+    HIPCHK(hipMemcpyAsync(R, b.Racc, sizeof(R), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&status, b.status, sizeof(status), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *bad = status != 0;
+    for (int i = 0; i < s; ++i)
+        for (int j = 0; j < s; ++j) Rh[i * s + j] = R[i * kBlkRhs + j];
+    return MQH_OK;
+}
+
+// X -= V M (V: n x s block of a basis, M: s x s given row-major on the host;
+// trans: use M^T).
+int block_shift(mqh_problem* p, BlockWs& b, const double* V, const double* M, int32_t s, bool trans, double* X) {
+    double c[kBlkRhs * kBlkRhs];
+    for (int i = 0; i < kBlkRhs * kBlkRhs; ++i) c[i] = 0.0;
+    for (int col = 0; col < s; ++col)
+        for (int k = 0; k < s; ++k) c[col * kBlkRhs + k] = trans ? M[k * s + col] : M[col * s + k];
+    hipStream_t st = p->stream;
+    HIPCHK(hipMemcpyAsync(b.mat, c, sizeof(c), hipMemcpyHostToDevice, st));
+    launch_blk_update(V, p->ldn, p->n, s, b.mat, kBlkRhs, 1, X, p->ldn, s, 1, st);
+    LAUNCHCHK("block shift");
+    HIPCHK(hipStreamSynchronize(st));  // c is a local
+    return MQH_OK;
+}
+
+// X -= V (V^T X) twice, V the first m columns of a basis.
+void block_cgs2(mqh_problem* p, BlockWs& b, const double* V, int32_t m, int32_t s, double* X) {
+    if (m <= 0) return;
+    hipStream_t st = p->stream;
+    for (int pass = 0; pass < 2; ++pass) {
+        launch_blk_gemvt(V, p->ldn, p->n, m, X, p->ldn, s, b.part, b.c, st);
+        launch_blk_update(V, p->ldn, p->n, m, b.c, kBlkRhs, 1, X, p->ldn, s, 1, st);
+    }
+}
+
+// The block recurrence from the block already in W's first s columns:
+// W_1 E_1 = F; Z_j D_j^T = A^T W_j - Z_{j-1} E_j^T; W_{j+1} E_{j+1} =
+// A Z_j - W_j D_j, each right side reorthogonalised against all earlier
+// blocks of its basis (CGS2) before its QR.  C (host, (ell + 1) s x ell s
+// row-major) receives D_j and E_{j+1}; E1 (s x s) the data's factor.  A QR
+// with a diagonal entry of R at most n eps times the largest diagonal entry
+// of the D and E blocks so far (E_1 left out) is a breakdown: at a D block
+// *ell_done = j - 1 (flag 1), at an E block *ell_done = j with E_{j+1} = 0
+// (flag 2).
+int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vector<double>& C, double* E1,
+                  int32_t* ell_done, int32_t* flag) {
+    hipStream_t st = p->stream;
+    const int64_t n = p->n, ldn = p->ldn;
+    const int64_t ldc = (int64_t)ell * s;
+    C.assign((size_t)((ell + 1) * s) * (size_t)ldc, 0.0);
+    bool bad = false;
+    int rc;
+    if ((rc = block_qr(p, b, b.W, s, E1, &bad))) return rc;
+    if (bad) return fail(MQH_EINVAL, "block Golub-Kahan: the right-hand sides are zero or not finite");
+    const double tau = (double)n * DBL_EPSILON;
+    double scale = 0.0;
+    std::vector<double> R((size_t)s * s), Eprev((size_t)s * s, 0.0);
+    *ell_done = ell;
+    *flag = 0;
+    auto diag_range = [&](const std::vector<double>& M, double* mn, double* mx) {
+        *mn = HUGE_VAL;
+        *mx = 0.0;
+        for (int i = 0; i < s; ++i) {
+            const double d = fabs(M[(size_t)i * s + i]);
+            *mn = d < *mn ? d : *mn;
+            *mx = d > *mx ? d : *mx;
+        }
+    };
+    for (int32_t j = 1; j <= ell; ++j) {
+        double* Wj = b.W + (int64_t)(j - 1) * s * ldn;
+        double* Zj = b.Z + (int64_t)(j - 1) * s * ldn;
+        // P = A^T W_j - Z_{j-1} E_j^T, reorthogonalised against Z_1 .. Z_{j-1}
+        if ((rc = block_product(p, s, 1, Wj, ldn, nullptr, 0, nullptr, 0, b.P, nullptr, false))) return rc;
+        if (j > 1 && (rc = block_shift(p, b, Zj - (int64_t)s * ldn, Eprev.data(), s, true, b.P))) return rc;
+        block_cgs2(p, b, b.Z, (j - 1) * s, s, b.P);
+        if ((rc = block_qr(p, b, b.P, s, R.data(), &bad))) return rc;
+        double mn, mx;
+        diag_range(R, &mn, &mx);
+        scale = mx > scale ? mx : scale;
+        if (bad || !(mn > tau * scale)) {
+            *ell_done = j - 1;
+            *flag = 1;
+            break;
+        }
+        HIPCHK(hipMemcpyAsync(Zj, b.P, (size_t)s * ldn * sizeof(double), hipMemcpyDeviceToDevice, st));
+        // D_j = R^T on the diagonal block
+        for (int i = 0; i < s; ++i)
+            for (int k = 0; k < s; ++k) C[(size_t)((j - 1) * s + i) * ldc + (size_t)(j - 1) * s + k] = R[(size_t)k * s + i];
+        std::vector<double> D((size_t)s * s);
+        for (int i = 0; i < s; ++i)
+            for (int k = 0; k < s; ++k) D[(size_t)i * s + k] = R[(size_t)k * s + i];
+        // Q = A Z_j - W_j D_j, reorthogonalised against W_1 .. W_j
+        if ((rc = block_product(p, s, 0, Zj, ldn, nullptr, 0, nullptr, 0, b.P, nullptr, false))) return rc;
+        if ((rc = block_shift(p, b, Wj, D.data(), s, false, b.P))) return rc;
+        block_cgs2(p, b, b.W, j * s, s, b.P);
+        if ((rc = block_qr(p, b, b.P, s, R.data(), &bad))) return rc;
+        diag_range(R, &mn, &mx);
+        scale = mx > scale ? mx : scale;
+        if (bad || !(mn > tau * scale)) {
+            *ell_done = j;
+            *flag = 2;
+            break;
+        }
+        HIPCHK(hipMemcpyAsync(Wj + (int64_t)s * ldn, b.P, (size_t)s * ldn * sizeof(double), hipMemcpyDeviceToDevice,
+                              st));
+        for (int i = 0; i < s; ++i)
+            for (int k = 0; k < s; ++k) C[(size_t)(j * s + i) * ldc + (size_t)(j - 1) * s + k] = R[(size_t)i * s + k];
+        Eprev = R;
+    }
+    LAUNCHCHK("block Golub-Kahan");
+    HIPCHK(hipStreamSynchronize(st));
+    return MQH_OK;
+}
+
+// Block Tikhonov on the projected problem: per source k, min ||C y - b_k||^2
+// + lambda_k^2 ||y||^2 with b_k = (E_1 e_k; 0), through the full-SVD path on
+// the square (ell + 1) s matrix [C | 0] with the s columns b_k beside it
+// (the zero columns add s zero singular values, which the rank cap ell s
+// keeps out of the choice and the solution); lambda_k by the full-problem
+// GCV on (ell + 1) s rows (rule GCV) or lambda_fixed (rule FIXED).  Y
+// (device, ell s x 16, row col = Y + 16 col) receives y_k in column k;
+// per-source records in po_h / iters / conv; sv (device, ell s, NULL
+// allowed) the singular values.
+int block_projected(mqh_problem* p, const std::vector<double>& C, const double* E1, int32_t s, int32_t ell,
+                    int32_t rule, int32_t J, double lambda_fixed, double* Y, double* sv, std::vector<ParamOut>& po_h,
+                    std::vector<int>& iters, std::vector<char>& conv, int32_t* sweeps) {
+    hipStream_t st = p->stream;
+    const int64_t m = (int64_t)(ell + 1) * s, ls = (int64_t)ell * s;
+    FullRun r;
+    int rc;
+    if ((rc = full_prepare(st, r, m, s))) return rc;
+    {
+        std::vector<double> Gh((size_t)m * (size_t)r.ldg, 0.0);
+        const int64_t ldc = ls;
+        for (int64_t i = 0; i < m; ++i) {
+            for (int64_t j = 0; j < ls; ++j) Gh[(size_t)(i * r.ldg + j)] = C[(size_t)(i * ldc + j)];
+            if (i < s)
+                for (int k = 0; k < s; ++k) Gh[(size_t)(i * r.ldg + m + k)] = E1[i * s + k];
+        }
+        HIPCHK(hipMemcpyAsync(r.G, Gh.data(), Gh.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if ((rc = full_sweeps(st, r, m, s))) return rc;
+    *sweeps = r.sweeps;
+    if (sv) HIPCHK(hipMemcpyAsync(sv, r.sv, (size_t)ls * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double* fhk = nullptr;
+    if ((rc = dalloc(&fhk, (size_t)m))) return rc;
+    struct Free {
+        double*& x;
+        ~Free() { dfree(x); }
+    } fr{fhk};
+    po_h.assign((size_t)s, ParamOut{});
+    iters.assign((size_t)s, 0);
+    conv.assign((size_t)s, 1);
+    for (int k = 0; k < s; ++k) {
+        double fn2 = 0.0;
+        for (int i = 0; i < s; ++i) fn2 += E1[i * s + k] * E1[i * s + k];
+        launch_fs_col(r.G, r.ldg, m, m + k, fhk, st);
+        launch_fs_rank(r.sig, fhk, m, r.rank, r.sv, r.fs, r.order, st);
+        launch_full_param(r.sv, r.fs, m, ls, fn2, 1, rule == MQH_RULE_FIXED ? 2 : 0, J, lambda_fixed, 0, r.tail, r.po,
+                          st);
+        LAUNCHCHK("block projected problem: parameter choice");
+        bool cv = true;
+        if ((rc = full_solution(st, r, m, 1, fhk, r.po, ls, &iters[(size_t)k], &cv))) return rc;
+        conv[(size_t)k] = cv ? 1 : 0;
+        // y_k = the first ell s entries of x, into column k of Y
+        HIPCHK(hipMemcpy2DAsync(Y + k, kBlkRhs * sizeof(double), r.coef, sizeof(double), sizeof(double), (size_t)ls,
+                                hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(&po_h[(size_t)k], r.po, sizeof(ParamOut), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return MQH_OK;
+}
+
+int check_block_args(const mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, int32_t ell) {
+    int rc;
+    if ((rc = check_problem(p))) return rc;
+    if (F == nullptr) return fail(MQH_EINVAL, "NULL right-hand sides");
+    if (nrhs < 1 || nrhs > kBlkRhs) return fail(MQH_EINVAL, "nrhs must be in [1, MQH_BLOCK_RHS]");
+    if (ldf < p->n) return fail(MQH_EINVAL, "ldf must be >= n");
+    if (ell < 1 || (int64_t)ell * nrhs > p->n || (int64_t)(ell + 1) * nrhs > MQH_BLOCK_MAX_DIM)
+        return fail(MQH_EINVAL, "need ell >= 1, ell nrhs <= n and (ell + 1) nrhs <= MQH_BLOCK_MAX_DIM");
+    return MQH_OK;
+}
+
+// F (n x nrhs, leading dimension ldf, host or device) into W's first block.
+int stage_block(mqh_problem* p, BlockWs& b, const double* F, int64_t ldf, int32_t nrhs, uint32_t flags) {
+    if (!(flags & MQH_FLAG_DEVICE_PTRS)) {
+        for (int32_t k = 0; k < nrhs; ++k)
+            if (!all_finite(F + (int64_t)k * ldf, p->n)) return fail(MQH_EINVAL, "non-finite right-hand side");
+    }
+    HIPCHK(hipMemcpy2DAsync(b.W, (size_t)p->ldn * sizeof(double), F, (size_t)ldf * sizeof(double),
+                            (size_t)p->n * sizeof(double), (size_t)nrhs, kind_in(flags), p->stream));
+    return MQH_OK;
 }
 
 }  // namespace
@@ -1798,13 +2082,13 @@ int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, con
     for (double v : fh) fn2 += v * v;
     if (!isfinite(fn2)) return fail(MQH_EINVAL, "non-finite right-hand side");
     if ((rc = full_svd_run(p, r))) return rc;
-    launch_full_param(r.sv, r.fs, p->n, fn2, tikh ? 1 : 0, opts->rule == MQH_RULE_FIXED ? 2 : 0, J,
+    launch_full_param(r.sv, r.fs, p->n, p->n, fn2, tikh ? 1 : 0, opts->rule == MQH_RULE_FIXED ? 2 : 0, J,
                       opts->lambda_fixed, opts->k_trunc, r.tail, r.po, s);
     LAUNCHCHK("full problem: parameter choice");
     HIPCHK(hipEventRecord(p->ev[4], s));
     int cg_iters = 0;
     bool cg_conv = true;
-    if ((rc = full_solution(p, r, tikh ? 1 : 0, &cg_iters, &cg_conv))) return rc;
+    if ((rc = full_solution(s, r, p->n, tikh ? 1 : 0, r.fh, r.po, p->n, &cg_iters, &cg_conv))) return rc;
     HIPCHK(hipEventRecord(p->ev[5], s));
     ParamOut po;
     HIPCHK(hipMemcpyAsync(&po, r.po, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
@@ -1831,6 +2115,149 @@ int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, con
     }
     if (noconv || !cg_conv) return MQH_WNOCONV;
     if (po.flags & MQH_INFO_GCV_AT_EDGE) return MQH_WEDGE;
+    return MQH_OK;
+}
+
+int mqh_gkb_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, int32_t ell, double* C, double* E1,
+                  double* W, double* Z, int32_t* ell_done, int32_t* flag, uint32_t flags) {
+    if (ell_done) *ell_done = 0;
+    if (flag) *flag = 0;
+    int rc;
+    if ((rc = check_block_args(p, F, ldf, nrhs, ell))) return rc;
+    if (C == nullptr) return fail(MQH_EINVAL, "NULL C");
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t st = p->stream;
+    if (p->mode == MQH_OP_MATFREE_FP32 && nrhs >= 2 && (rc = ensure_multi(p, nrhs, 1))) return rc;
+    BlockWs b;
+    if ((rc = block_alloc(p, b, nrhs, ell))) return rc;
+    if ((rc = stage_block(p, b, F, ldf, nrhs, flags))) return rc;
+    std::vector<double> Ch;
+    double E1h[kBlkRhs * kBlkRhs];
+    int32_t ld = 0, fl = 0;
+    if ((rc = run_gkb_block(p, b, nrhs, ell, Ch, E1h, &ld, &fl))) return rc;
+    const hipMemcpyKind ko = kind_out(flags);
+    const int64_t n = p->n, ldn = p->ldn;
+    HIPCHK(hipMemcpyAsync(C, Ch.data(), Ch.size() * sizeof(double),
+                          (flags & MQH_FLAG_DEVICE_PTRS) ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st));
+    if (E1)
+        HIPCHK(hipMemcpyAsync(E1, E1h, (size_t)nrhs * nrhs * sizeof(double),
+                              (flags & MQH_FLAG_DEVICE_PTRS) ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st));
+    if (W)
+        HIPCHK(hipMemcpy2DAsync(W, (size_t)n * sizeof(double), b.W, (size_t)ldn * sizeof(double), (size_t)n * sizeof(double),
+                                (size_t)(ell + 1) * nrhs, ko, st));
+    if (Z)
+        HIPCHK(hipMemcpy2DAsync(Z, (size_t)n * sizeof(double), b.Z, (size_t)ldn * sizeof(double), (size_t)n * sizeof(double),
+                                (size_t)ell * nrhs, ko, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (ell_done) *ell_done = ld;
+    if (flag) *flag = fl;
+    return fl ? MQH_WBREAKDOWN : MQH_OK;
+}
+
+int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, const mqh_solve_opts* opts,
+                    double* coef, int64_t ldc, double* sv, mqh_solve_info* info) {
+    if (info && nrhs > 0 && nrhs <= kBlkRhs)
+        for (int32_t k = 0; k < nrhs; ++k) clear_info(info + k);
+    int rc;
+    if (opts == nullptr) return fail(MQH_EINVAL, "NULL opts");
+    if ((rc = check_block_args(p, F, ldf, nrhs, opts->ell))) return rc;
+    if (coef == nullptr || ldc < p->n) return fail(MQH_EINVAL, "coef must be n x nrhs with ldc >= n");
+    if (opts->method != MQH_METHOD_HKT) return fail(MQH_EINVAL, "block solves use MQH_METHOD_HKT (the Tikhonov filter)");
+    if (opts->rule != MQH_RULE_GCV && opts->rule != MQH_RULE_FIXED)
+        return fail(MQH_EINVAL, "rule: MQH_RULE_GCV or MQH_RULE_FIXED");
+    const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
+    if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
+    if (opts->rule == MQH_RULE_FIXED && (!isfinite(opts->lambda_fixed) || opts->lambda_fixed < 0.0))
+        return fail(MQH_EINVAL, "lambda_fixed must be finite and >= 0");
+    HIPCHK(hipSetDevice(p->device));
+    hipStream_t st = p->stream;
+    const uint32_t flags = opts->flags;
+    const int64_t n = p->n, ldn = p->ldn;
+    const int32_t ell = opts->ell;
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+        return std::chrono::duration<double, std::milli>(b - a).count();
+    };
+    const auto t0 = now();
+    if (p->mode == MQH_OP_MATFREE_FP32 && nrhs >= 2 && (rc = ensure_multi(p, nrhs, 1))) return rc;
+    BlockWs b;
+    if ((rc = block_alloc(p, b, nrhs, ell))) return rc;
+    if ((rc = stage_block(p, b, F, ldf, nrhs, flags))) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    const auto t1 = now();
+    std::vector<double> Ch;
+    double E1h[kBlkRhs * kBlkRhs];
+    int32_t ld = 0, fl = 0;
+    if ((rc = run_gkb_block(p, b, nrhs, ell, Ch, E1h, &ld, &fl))) return rc;
+    const auto t2 = now();
+    if (ld == 0) {
+        // nothing to project on: zero coefficients, breakdown reported
+        HIPCHK(hipMemcpy2DAsync(coef, (size_t)ldc * sizeof(double), b.P, (size_t)ldn * sizeof(double),
+                                (size_t)n * sizeof(double), (size_t)nrhs, kind_out(flags), st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (info)
+            for (int32_t k = 0; k < nrhs; ++k) info[k].flags = MQH_INFO_BREAKDOWN;
+        return MQH_WBREAKDOWN;
+    }
+    // C of the ld steps kept: (ld + 1) s x ld s
+    const int64_t ls = (int64_t)ld * nrhs, ldfull = (int64_t)ell * nrhs;
+    std::vector<double> Ck((size_t)((ld + 1) * nrhs) * (size_t)ls);
+    for (int64_t i = 0; i < (int64_t)(ld + 1) * nrhs; ++i)
+        for (int64_t j = 0; j < ls; ++j) Ck[(size_t)(i * ls + j)] = Ch[(size_t)(i * ldfull + j)];
+    double* Y = nullptr;
+    if ((rc = dalloc(&Y, (size_t)ls * kBlkRhs))) return rc;
+    struct Free {
+        double*& x;
+        ~Free() { dfree(x); }
+    } fy{Y};
+    HIPCHK(hipMemsetAsync(Y, 0, (size_t)ls * kBlkRhs * sizeof(double), st));
+    double* svd = nullptr;
+    struct Free2 {
+        double*& x;
+        ~Free2() { dfree(x); }
+    } fs{svd};
+    if (sv && (rc = dalloc(&svd, (size_t)ls))) return rc;
+    std::vector<ParamOut> po;
+    std::vector<int> iters;
+    std::vector<char> conv;
+    int32_t sweeps = 0;
+    if ((rc = block_projected(p, Ck, E1h, nrhs, ld, opts->rule, J, opts->lambda_fixed, Y, svd, po, iters, conv,
+                              &sweeps)))
+        return rc;
+    const auto t3 = now();
+    // coefficients Z Y (in b.P, then out)
+    launch_blk_update(b.Z, ldn, n, (int32_t)ls, Y, kBlkRhs, 1, b.P, ldn, nrhs, 0, st);
+    LAUNCHCHK("block lift");
+    const hipMemcpyKind ko = kind_out(flags);
+    HIPCHK(hipMemcpy2DAsync(coef, (size_t)ldc * sizeof(double), b.P, (size_t)ldn * sizeof(double),
+                            (size_t)n * sizeof(double), (size_t)nrhs, ko, st));
+    if (sv) HIPCHK(hipMemcpyAsync(sv, svd, (size_t)ls * sizeof(double), ko, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const auto t4 = now();
+    bool edge = false, noconv = false;
+    for (int32_t k = 0; k < nrhs; ++k) {
+        edge = edge || (po[(size_t)k].flags & MQH_INFO_GCV_AT_EDGE);
+        noconv = noconv || !conv[(size_t)k];
+        if (!info) continue;
+        mqh_solve_info& I = info[k];
+        I.ell_done = ld;
+        I.k_chosen = 0;
+        I.lambda_chosen = po[(size_t)k].lambda;
+        I.crit = po[(size_t)k].crit;
+        I.resid_norm = po[(size_t)k].rho;
+        I.sol_norm = po[(size_t)k].eta;
+        I.flags = po[(size_t)k].flags | (fl ? MQH_INFO_BREAKDOWN : 0u) | (conv[(size_t)k] ? 0u : MQH_INFO_SOLVE_NOCONV);
+        I.t_ms[0] = ms(t0, t1);
+        I.t_ms[1] = ms(t1, t2);
+        I.t_ms[2] = ms(t2, t3);
+        I.t_ms[3] = ms(t3, t4);
+        I.t_ms[5] = ms(t0, t4);
+        I.t_ms[6] = sweeps;
+        I.t_ms[7] = iters[(size_t)k];
+    }
+    if (fl) return MQH_WBREAKDOWN;
+    if (noconv) return MQH_WNOCONV;
+    if (edge) return MQH_WEDGE;
     return MQH_OK;
 }
 

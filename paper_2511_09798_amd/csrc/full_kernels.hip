@@ -319,9 +319,10 @@ __global__ __launch_bounds__(kBlock) void k_fs_rank(const double* __restrict__ s
 }
 
 // ---------------------------------------------------------------------------
-// Parameter choice on the full problem (eq. (25)): sv descending (n values,
-// the r > 0 ones used), fs = U^T f in the same order, s_perp = ||f||^2 -
-// sum fs^2 (clamped at 0).  Tikhonov: GCV(lambda) on J log-spaced points on
+// Parameter choice on the full problem (eq. (25)): sv descending (n values;
+// the first r, r = the number of positive ones but at most rcap, are used),
+// fs = U^T f in the same order, s_perp = ||f||^2 - sum_{i < r} fs_i^2
+// (clamped at 0), N = n in the denominator.  Tikhonov: GCV(lambda) on J log-spaced points on
 // [max(sigma_r, 16 eps sigma_1), sigma_1], golden-section refinement of
 // log lambda over the two cells around the grid minimum (ties to the larger
 // lambda, a minimum at an end kept with the edge flag) -- the rule of the
@@ -348,21 +349,22 @@ __device__ double full_gcv(const double* __restrict__ sv, const double* __restri
 }
 
 __global__ __launch_bounds__(kBlock) void k_full_param(const double* __restrict__ sv, const double* __restrict__ fs,
-                                                       int64_t n, double fnorm2, int32_t method, int32_t rule,
-                                                       int32_t J, double lambda_fixed, int32_t k_fixed,
+                                                       int64_t n, int64_t rcap, double fnorm2, int32_t method,
+                                                       int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed,
                                                        double* __restrict__ tail, ParamOut* __restrict__ out) {
     __shared__ double lds[kBlock / kWave];
     __shared__ double vals[kMaxGrid];
     __shared__ int64_t s_r;
     if (threadIdx.x == 0) {
         int64_t r = 0;
-        while (r < n && sv[r] > 0.0) ++r;
+        while (r < n && r < rcap && sv[r] > 0.0) ++r;
         s_r = r;
     }
     __syncthreads();
     const int64_t r = s_r;
+    // s_perp: what the r retained components leave of ||f||^2
     double ssum = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) ssum = fma(fs[i], fs[i], ssum);
+    for (int64_t i = threadIdx.x; i < r; i += kBlock) ssum = fma(fs[i], fs[i], ssum);
     ssum = block_sum<kBlock>(ssum, lds);
     const double sperp = fnorm2 - ssum > 0.0 ? fnorm2 - ssum : 0.0;
     uint32_t flags = 0;
@@ -522,9 +524,12 @@ __global__ __launch_bounds__(kBlock) void k_full_param(const double* __restrict_
 // level) or an iteration cap.  One iteration: x = G^T q (split over row
 // chunks), w = G x + lambda^2 q, two dot products, the updates.
 
-// d_i of row i (0: row not in the solution).
-__device__ __forceinline__ double sol_diag(double sig, int32_t rank, int32_t method, double l2, int64_t k) {
+// d_i of row i (0: row not in the solution; rows of rank >= rcap, past the
+// retained singular values, never are).
+__device__ __forceinline__ double sol_diag(double sig, int32_t rank, int32_t method, double l2, int64_t k,
+                                           int64_t rcap) {
     const double s2 = sig * sig;
+    if (rank >= rcap) return 0.0;
     if (method == 0) return (rank < k && s2 > 0.0) ? s2 : 0.0;
     return s2 + l2;
 }
@@ -537,12 +542,13 @@ __device__ __forceinline__ double sol_l2(int32_t method, const ParamOut* po) {
 __global__ __launch_bounds__(kBlock) void k_fs_pcg_start(const double* __restrict__ sig,
                                                          const double* __restrict__ fh,
                                                          const int32_t* __restrict__ rank, int64_t n, int32_t method,
-                                                         const ParamOut* __restrict__ po, double* __restrict__ y,
+                                                         int64_t rcap, const ParamOut* __restrict__ po,
+                                                         double* __restrict__ y,
                                                          double* __restrict__ r, double* __restrict__ q,
                                                          double* __restrict__ t) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k);
+    const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k, rcap);
     const double b = d > 0.0 ? fh[i] : 0.0;
     y[i] = 0.0;
     r[i] = b;
@@ -585,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_pcg_matvec(const double* __restri
                                                           const double* __restrict__ x,
                                                           const double* __restrict__ sig,
                                                           const int32_t* __restrict__ rank, int32_t method,
-                                                          const ParamOut* __restrict__ po,
+                                                          int64_t rcap, const ParamOut* __restrict__ po,
                                                           const double* __restrict__ q, double* __restrict__ w,
                                                           double* __restrict__ t) {
     __shared__ double lds[kBlock / kWave];
@@ -596,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_pcg_matvec(const double* __restri
     s = block_sum<kBlock>(s, lds);
     if (threadIdx.x == 0) {
         const double l2 = sol_l2(method, po);
-        const double d = sol_diag(sig[i], rank[i], method, l2, po->k);
+        const double d = sol_diag(sig[i], rank[i], method, l2, po->k, rcap);
         const double wi = d > 0.0 ? s + l2 * q[i] : 0.0;
         w[i] = wi;
         t[i] = q[i] * wi;
@@ -617,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_pcg_sum(const double* __restrict_
 // t_i = r_i^2 / d_i.
 __global__ __launch_bounds__(kBlock) void k_fs_pcg_step(const double* __restrict__ sig,
                                                         const int32_t* __restrict__ rank, int64_t n, int32_t method,
-                                                        const ParamOut* __restrict__ po,
+                                                        int64_t rcap, const ParamOut* __restrict__ po,
                                                         const double* __restrict__ pc, int cur,
                                                         const double* __restrict__ q, const double* __restrict__ w,
                                                         double* __restrict__ y, double* __restrict__ r,
@@ -626,7 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_pcg_step(const double* __restrict
     if (i >= n) return;
     const double qw = pc[0];
     const double a = qw > 0.0 ? pc[cur] / qw : 0.0;
-    const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k);
+    const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k, rcap);
     y[i] = fma(a, q[i], y[i]);
     const double ri = fma(-a, w[i], r[i]);
     r[i] = ri;
@@ -636,13 +642,13 @@ __global__ __launch_bounds__(kBlock) void k_fs_pcg_step(const double* __restrict
 // q = D^-1 r + (pc[nxt] / pc[cur]) q.
 __global__ __launch_bounds__(kBlock) void k_fs_pcg_dir(const double* __restrict__ sig,
                                                        const int32_t* __restrict__ rank, int64_t n, int32_t method,
-                                                       const ParamOut* __restrict__ po,
+                                                       int64_t rcap, const ParamOut* __restrict__ po,
                                                        const double* __restrict__ pc, int cur, int nxt,
                                                        const double* __restrict__ r, double* __restrict__ q) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const double beta = pc[cur] > 0.0 ? pc[nxt] / pc[cur] : 0.0;
-    const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k);
+    const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k, rcap);
     q[i] = d > 0.0 ? fma(beta, q[i], r[i] / d) : 0.0;
 }
 
@@ -671,6 +677,13 @@ __global__ void k_fs_set_norms(const double* __restrict__ pc, ParamOut* __restri
         po->rho = sqrt(pc[1]);
         po->eta = sqrt(pc[0]);
     }
+}
+
+// out_i = G[i][col], i < rows.
+__global__ __launch_bounds__(kBlock) void k_fs_col(const double* __restrict__ G, int64_t ldg, int64_t rows,
+                                                   int64_t col, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < rows) out[i] = G[i * ldg + col];
 }
 
 // G[i][n] = f_i for i < n (the f column of the work matrix).
@@ -718,9 +731,10 @@ void launch_fs_rank(const double* sig, const double* fh, int64_t n, int32_t* ran
     k_fs_rank<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(sig, fh, n, rank, sv, fs, order);
 }
 
-void launch_full_param(const double* sv, const double* fs, int64_t n, double fnorm2, int32_t method, int32_t rule,
-                       int32_t J, double lambda_fixed, int32_t k_fixed, double* tail, ParamOut* out, hipStream_t s) {
-    k_full_param<<<1, kBlock, 0, s>>>(sv, fs, n, fnorm2, method, rule, J, lambda_fixed, k_fixed, tail, out);
+void launch_full_param(const double* sv, const double* fs, int64_t n, int64_t rcap, double fnorm2, int32_t method,
+                       int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double* tail, ParamOut* out,
+                       hipStream_t s) {
+    k_full_param<<<1, kBlock, 0, s>>>(sv, fs, n, rcap, fnorm2, method, rule, J, lambda_fixed, k_fixed, tail, out);
 }
 
 int fs_gemvt_chunks(int64_t n) {
@@ -743,21 +757,21 @@ void launch_fs_gemvt(const double* G, int64_t ldg, int64_t n, const double* q, d
 }
 
 void launch_fs_pcg_start(const double* sig, const double* fh, const int32_t* rank, int64_t n, int32_t method,
-                         const ParamOut* po, double* y, double* r, double* q, double* t, double* pc, int slot,
-                         hipStream_t s) {
+                         int64_t rcap, const ParamOut* po, double* y, double* r, double* q, double* t, double* pc,
+                         int slot, hipStream_t s) {
     const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    k_fs_pcg_start<<<nb, kBlock, 0, s>>>(sig, fh, rank, n, method, po, y, r, q, t);
+    k_fs_pcg_start<<<nb, kBlock, 0, s>>>(sig, fh, rank, n, method, rcap, po, y, r, q, t);
     k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, slot);
 }
 
 void launch_fs_pcg_iter(const double* G, int64_t ldg, int64_t n, const double* sig, const int32_t* rank,
-                        int32_t method, const ParamOut* po, double* pc, int cur, int nxt, double* y, double* r,
-                        const double* q, double* w, double* t, double* part, double* x, hipStream_t s) {
+                        int32_t method, int64_t rcap, const ParamOut* po, double* pc, int cur, int nxt, double* y,
+                        double* r, const double* q, double* w, double* t, double* part, double* x, hipStream_t s) {
     const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
     launch_fs_gemvt(G, ldg, n, q, part, x, s);
-    k_fs_pcg_matvec<<<(unsigned)n, kBlock, 0, s>>>(G, ldg, n, x, sig, rank, method, po, q, w, t);
+    k_fs_pcg_matvec<<<(unsigned)n, kBlock, 0, s>>>(G, ldg, n, x, sig, rank, method, rcap, po, q, w, t);
     k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, 0);
-    k_fs_pcg_step<<<nb, kBlock, 0, s>>>(sig, rank, n, method, po, pc, cur, q, w, y, r, t);
+    k_fs_pcg_step<<<nb, kBlock, 0, s>>>(sig, rank, n, method, rcap, po, pc, cur, q, w, y, r, t);
     k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, nxt);
 }
 
@@ -769,10 +783,15 @@ void launch_fs_solution_norms(const double* G, int64_t ldg, int64_t n, const dou
     k_fs_set_norms<<<1, 64, 0, s>>>(pc, po);
 }
 
-void launch_fs_pcg_dir(const double* sig, const int32_t* rank, int64_t n, int32_t method, const ParamOut* po,
-                       const double* pc, int cur, int nxt, const double* r, double* q, hipStream_t s) {
-    k_fs_pcg_dir<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(sig, rank, n, method, po, pc, cur, nxt, r,
-                                                                          q);
+void launch_fs_pcg_dir(const double* sig, const int32_t* rank, int64_t n, int32_t method, int64_t rcap,
+                       const ParamOut* po, const double* pc, int cur, int nxt, const double* r, double* q,
+                       hipStream_t s) {
+    k_fs_pcg_dir<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(sig, rank, n, method, rcap, po, pc, cur, nxt,
+                                                                          r, q);
+}
+
+void launch_fs_col(const double* G, int64_t ldg, int64_t rows, int64_t col, double* out, hipStream_t s) {
+    k_fs_col<<<(unsigned)((rows + kBlock - 1) / kBlock), kBlock, 0, s>>>(G, ldg, rows, col, out);
 }
 
 }  // namespace mqh

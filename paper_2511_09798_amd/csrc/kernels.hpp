@@ -139,8 +139,9 @@ void launch_fs_maxoff(const double* off, int64_t count, double* out, hipStream_t
 void launch_fs_norms(const double* G, int64_t ldg, int64_t rows, int64_t n, double* sig, double* fh, hipStream_t s);
 void launch_fs_rank(const double* sig, const double* fh, int64_t n, int32_t* rank, double* sv, double* fs,
                     int32_t* order, hipStream_t s);
-void launch_full_param(const double* sv, const double* fs, int64_t n, double fnorm2, int32_t method, int32_t rule,
-                       int32_t J, double lambda_fixed, int32_t k_fixed, double* tail, ParamOut* out, hipStream_t s);
+void launch_full_param(const double* sv, const double* fs, int64_t n, int64_t rcap, double fnorm2, int32_t method,
+                       int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double* tail, ParamOut* out,
+                       hipStream_t s);
 // Solutions: preconditioned conjugate gradients on (G G^T + lambda^2 I) y = f^
 // (Tikhonov) or G_k G_k^T y = f^_k (TSVD), x = G^T y.  pc holds the
 // iteration's scalars: [0] q^T B q, [2], [3] r^T D^-1 r of alternate
@@ -148,16 +149,32 @@ void launch_full_param(const double* sv, const double* fs, int64_t n, double fno
 int fs_gemvt_chunks(int64_t n);
 void launch_fs_gemvt(const double* G, int64_t ldg, int64_t n, const double* q, double* part, double* x, hipStream_t s);
 void launch_fs_pcg_start(const double* sig, const double* fh, const int32_t* rank, int64_t n, int32_t method,
-                         const ParamOut* po, double* y, double* r, double* q, double* t, double* pc, int slot,
-                         hipStream_t s);
+                         int64_t rcap, const ParamOut* po, double* y, double* r, double* q, double* t, double* pc,
+                         int slot, hipStream_t s);
 void launch_fs_pcg_iter(const double* G, int64_t ldg, int64_t n, const double* sig, const int32_t* rank,
-                        int32_t method, const ParamOut* po, double* pc, int cur, int nxt, double* y, double* r,
-                        const double* q, double* w, double* t, double* part, double* x, hipStream_t s);
+                        int32_t method, int64_t rcap, const ParamOut* po, double* pc, int cur, int nxt, double* y,
+                        double* r, const double* q, double* w, double* t, double* part, double* x, hipStream_t s);
 // ||A x - f|| = ||G x - f^|| and ||x|| of the returned solution into po->rho, po->eta.
 void launch_fs_solution_norms(const double* G, int64_t ldg, int64_t n, const double* x, const double* fh, double* t,
                               double* w, double* pc, ParamOut* po, hipStream_t s);
-void launch_fs_pcg_dir(const double* sig, const int32_t* rank, int64_t n, int32_t method, const ParamOut* po,
-                       const double* pc, int cur, int nxt, const double* r, double* q, hipStream_t s);
+void launch_fs_pcg_dir(const double* sig, const int32_t* rank, int64_t n, int32_t method, int64_t rcap,
+                       const ParamOut* po, const double* pc, int cur, int nxt, const double* r, double* q,
+                       hipStream_t s);
+// out_i = G[i][col] for i < rows (one data column of the work matrix)
+void launch_fs_col(const double* G, int64_t ldg, int64_t rows, int64_t col, double* out, hipStream_t s);
+
+// Block Golub-Kahan (block_kernels.hip): c = V^T P through split-K partials
+// (part: blk_chunks(n, m) x m x 16, c: m x 16, row col = c + 16 col), P -= V c
+// (sub = 1) or P = V c (sub = 0; V may be P), one pass of (shifted) Cholesky
+// QR on a 16 x 16 Gram matrix.
+int blk_chunks(int64_t n, int32_t m, int64_t* chunk);
+void launch_blk_gemvt(const double* V, int64_t ldv, int64_t n, int32_t m, const double* P, int64_t ldp, int32_t s,
+                      double* part, double* c, hipStream_t st);
+void launch_blk_update(const double* V, int64_t ldv, int64_t n, int32_t m, const double* c, int64_t cs, int64_t ks,
+                       double* P, int64_t ldp, int32_t s, int32_t sub, hipStream_t st);
+void launch_blk_chol(const double* G, int32_t s, int64_t n, int32_t shifted, double* Rinv, double* Racc,
+                     int32_t* status, hipStream_t st);
+void launch_blk_eye(double* Racc, int32_t* status, hipStream_t st);
 
 // Measurement helpers (peak_kernels.hip): peak_blocks() workgroups of kBlock
 // threads; the copy moves count doubles (count even, x and y 16-byte aligned).

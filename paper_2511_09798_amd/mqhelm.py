@@ -46,6 +46,7 @@ MQH_INFO_SOLVE_NOCONV = 8
 MQH_MAX_ELL = 1024
 MQH_FULL_MAX_N = 32768
 MQH_FULL_CG_MAX = 1024
+MQH_BLOCK_MAX_DIM = 4096
 MQH_BLOCK_RHS = 16
 MQH_PEAK_COPY = 0
 MQH_PEAK_FMA_F32 = 1
@@ -131,6 +132,10 @@ _SIGNATURES = {
                                        ctypes.POINTER(mqh_solve_info)]),
     "mqh_solve_sweep": (ctypes.c_int, [ctypes.POINTER(mqh_sweep_item), _i32, ctypes.POINTER(mqh_solve_opts), _i32]),
     "mqh_full_svd": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_d), _u32]),
+    "mqh_gkb_block": (ctypes.c_int, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_i32), _u32]),
+    "mqh_solve_block": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(mqh_solve_opts), _vp, _i64, _vp,
+                                       ctypes.POINTER(mqh_solve_info)]),
     "mqh_full_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(mqh_solve_opts), _vp, _vp,
                                       ctypes.POINTER(mqh_solve_info)]),
     "mqh_eval": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _u32]),
@@ -461,6 +466,51 @@ def mqh_solve_multi(h, F, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQ
                             np.array([list(i.t_ms) for i in infos], dtype=np.float64))
 
 
+def mqh_gkb_block(h, F, ell: int, want_bases: bool = False) -> dict:
+    """Block Golub-Kahan from the rows of F (nrhs x n, rows [f_int; g_bnd]): C ((ell + 1) nrhs x
+    ell nrhs), E1 (nrhs x nrhs), the bases W ((ell + 1) nrhs x n) and Z (ell nrhs x n) as rows if
+    want_bases, ell_done, flag, status."""
+    n = int(lib.mqh_problem_size(h))
+    s = int(F.shape[0])
+    if F.shape[1] != n:
+        raise ValueError("F must be nrhs x n")
+    C = _zeros_like_kind(F, ((ell + 1) * s, ell * s))
+    E1 = _zeros_like_kind(F, (s, s))
+    W = _zeros_like_kind(F, ((ell + 1) * s, n)) if want_bases else None
+    Z = _zeros_like_kind(F, (ell * s, n)) if want_bases else None
+    fl = _flags(F, C, E1, W, Z)
+    ld, flag = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = _check(lib.mqh_gkb_block(h, _ptr(F)[0], n, s, int(ell), _ptr(C)[0], _ptr(E1)[0], _ptr(W)[0], _ptr(Z)[0],
+                                  ctypes.byref(ld), ctypes.byref(flag), fl), "mqh_gkb_block")
+    return dict(C=C, E1=E1, W=W, Z=Z, ell_done=ld.value, flag=flag.value, status=st)
+
+
+def mqh_solve_block(h, F, ell: int, rule: int = MQH_RULE_GCV, lambda_fixed: float = 0.0, n_grid: int = 200,
+                    coef=None, want_sv: bool = False) -> MultiSolveOutput:
+    """Block HKT: every row of F (nrhs x n) solved by Tikhonov on the block Krylov space of all rows
+    (ell block steps); the returned record's sv holds the projected singular values if want_sv."""
+    n = int(lib.mqh_problem_size(h))
+    s = int(F.shape[0])
+    if F.shape[1] != n:
+        raise ValueError("F must be nrhs x n")
+    if coef is None:
+        coef = _empty_like_kind(F, (s, n))
+    sv = _zeros_like_kind(F, (ell * s,)) if want_sv else None
+    fl = _flags(F, coef, sv)
+    opts = mqh_solve_opts(ell=int(ell), reorth=1, method=MQH_METHOD_HKT, rule=int(rule), k_trunc=0,
+                          n_grid=int(n_grid), lambda_fixed=float(lambda_fixed), flags=fl, reserved=0, gcv_weight=1.0)
+    infos = (mqh_solve_info * s)()
+    st = _check(lib.mqh_solve_block(h, _ptr(F)[0], n, s, ctypes.byref(opts), _ptr(coef)[0], n, _ptr(sv)[0], infos),
+                "mqh_solve_block")
+    get = lambda f, dt: np.array([getattr(i, f) for i in infos], dtype=dt)  # noqa: E731
+    out = MultiSolveOutput(coef, st, get("ell_done", np.int32), get("k_chosen", np.int32),
+                           get("lambda_chosen", np.float64), get("crit", np.float64), get("resid_norm", np.float64),
+                           get("sol_norm", np.float64), get("flags", np.uint32),
+                           np.array([list(i.t_ms) for i in infos], dtype=np.float64))
+    out.sv = sv
+    return out
+
+
 def mqh_solve_sweep(problems, Fs, ell: int, workers: int = 2, coefs=None, method: int = MQH_METHOD_HKT,
                     rule: int = MQH_RULE_GCV, k_trunc: int = 0, lambda_fixed: float = 0.0, n_grid: int = 200,
                     reorth: int = 1, time_products: bool = False, gcv_weight: float = 1.0, graph: bool = False):
@@ -681,6 +731,12 @@ class Problem:
 
     def solve_multi(self, F, ell, **kw) -> MultiSolveOutput:
         return mqh_solve_multi(self.h, F, ell, **kw)
+
+    def gkb_block(self, F, ell, **kw):
+        return mqh_gkb_block(self.h, F, ell, **kw)
+
+    def solve_block(self, F, ell, **kw) -> MultiSolveOutput:
+        return mqh_solve_block(self.h, F, ell, **kw)
 
     def full_svd(self, f=None, ref=None):
         return mqh_full_svd(self.h, f, ref)

@@ -189,3 +189,19 @@ def test_peak_probe_rejects_invalid_arguments(mq):
     assert L.mqh_peak_probe(mq.MQH_PEAK_FMA_F64, 1 << 21, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
     assert L.mqh_peak_probe(mq.MQH_PEAK_MFMA_F64, 16, 0, ctypes.byref(r), None) == mq.MQH_EINVAL
     assert L.mqh_peak_probe(mq.MQH_PEAK_COPY, 1024, 1, None, None) == mq.MQH_EINVAL
+
+
+def test_block_entry_points_reject_invalid_arguments(mq):
+    # argument checks run before any device work
+    L = mq.lib
+    F = np.zeros((2, 8))
+    opts = mq.mqh_solve_opts(ell=2, reorth=1, method=mq.MQH_METHOD_HKT, rule=mq.MQH_RULE_GCV)
+    C = np.zeros(64)
+    ld, fl = ctypes.c_int32(5), ctypes.c_int32(5)
+    assert L.mqh_gkb_block(None, F.ctypes.data, 8, 2, 2, C.ctypes.data, None, None, None, ctypes.byref(ld),
+                           ctypes.byref(fl), 0) == mq.MQH_EINVAL
+    assert ld.value == 0 and fl.value == 0
+    assert "NULL problem" in mq.mqh_last_error()
+    assert L.mqh_solve_block(None, F.ctypes.data, 8, 2, ctypes.byref(opts), F.ctypes.data, 8, None, None) == \
+        mq.MQH_EINVAL
+    assert L.mqh_solve_block(None, F.ctypes.data, 8, 2, None, F.ctypes.data, 8, None, None) == mq.MQH_EINVAL

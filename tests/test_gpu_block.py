@@ -1,0 +1,204 @@
+"""GPU parity of the block Golub-Kahan path (mqh_gkb_block, mqh_solve_block:
+several sources sharing one Krylov space) against the block oracle
+(oracle/block.py).
+
+* The recurrence, FP64 operators: the block Krylov relations A Z = W C and
+  A^T W_l = Z_l (C_l)_{1:ls}^T with the oracle's FP64 A, orthonormal bases,
+  W_1 E_1 = F, all to 1e-12; the structure of C (triangular blocks,
+  non-negative diagonals); the singular values of C against the oracle's
+  C: the leading ten to 1e-10 relative, all to 64 (l + 1) s eps sigma_1
+  (two backward-stable recurrences; the QR differs: shifted Cholesky QR on
+  the GPU, Householder in the oracle); the first two blocks of C element
+  by element to 1e-10 of ||C|| (positive diagonals fix the signs).
+* The solve, FP64 operators: at the oracle's per-source lambda (FIXED rule)
+  u within 1e-8 and coefficients within 1e-6 relative; with GCV each
+  source's lambda within 1e-6 relative (the projected problem is small and
+  well separated: its GCV minimum moves by less under the two SVDs); one
+  source (nrhs = 1) equals the single-source HKT solve (mqh_solve) to the
+  same bars.
+* FP32-evaluated block products (nrhs >= 2 on the matrix cores): relations
+  with the oracle's A to the single FP32 product's bound scaled by ||C||
+  (1e-5), u at the oracle's lambda within 1e-3.
+* A block inside an invariant subspace breaks down after one step, as in
+  the oracle; invalid arguments are rejected.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2511_09798_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mq():
+    from paper_2511_09798_amd import mqhelm
+
+    return mqhelm
+
+
+@pytest.fixture(scope="module")
+def blk():
+    from oracle import block
+
+    return block
+
+
+@pytest.fixture(scope="module")
+def case(orc):
+    p = I.cube_scaled(333, 190, kappa=6.0, eps=2.0, ell=40)
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    F = np.stack([I.random_vector(p.n, 700 + k) for k in range(5)])  # nrhs x n
+    return p, A, F
+
+
+def _problem(mq, p, mode):
+    say("create", p.name, "n", p.n, mode)
+    return mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, mode)
+
+
+@pytest.mark.parametrize("mode", ["stored_fp64", "matfree_fp64"])
+def test_block_gkb_against_oracle(mq, blk, case, mode):
+    p, A, F = case
+    s, ell = F.shape[0], 8
+    with _problem(mq, p, mode) as pr:
+        say("block gkb", mode, "s", s, "ell", ell)
+        g = pr.gkb_block(F, ell, want_bases=True)
+    assert g["status"] == 0 and g["ell_done"] == ell
+    C, W, Z = g["C"], g["W"].T, g["Z"].T
+    nc = np.linalg.norm(C, 2)
+    assert np.linalg.norm(A @ Z - W @ C) <= 1e-12 * nc
+    assert np.linalg.norm(A.T @ W[:, : ell * s] - Z @ C[: ell * s, :].T) <= 1e-12 * nc
+    assert np.linalg.norm(W[:, :s] @ g["E1"] - F.T) <= 1e-13 * np.linalg.norm(F)
+    assert np.max(np.abs(W.T @ W - np.eye(W.shape[1]))) <= 1e-12
+    assert np.max(np.abs(Z.T @ Z - np.eye(Z.shape[1]))) <= 1e-12
+    for j in range(ell):
+        D = C[j * s:(j + 1) * s, j * s:(j + 1) * s]
+        E = C[(j + 1) * s:(j + 2) * s, j * s:(j + 1) * s]
+        assert np.all(np.triu(D, 1) == 0.0) and np.all(np.diag(D) >= 0.0)
+        assert np.all(np.tril(E, -1) == 0.0) and np.all(np.diag(E) >= 0.0)
+    o = blk.block_gkb(A, F.T, ell)
+    sg = np.linalg.svd(C, compute_uv=False)
+    so = np.linalg.svd(o.C, compute_uv=False)
+    say("sv diff", np.max(np.abs(sg - so)) / so[0], "C[:2 blocks] diff", np.max(np.abs(C[:, : 2 * s] - o.C[:, : 2 * s])) / nc)
+    assert np.max(np.abs(sg[:10] - so[:10]) / so[:10]) <= 1e-10
+    assert np.max(np.abs(sg - so)) <= 64 * (ell + 1) * s * EPS * so[0]
+    assert np.max(np.abs(C[:, : 2 * s] - o.C[:, : 2 * s])) <= 1e-10 * nc
+    assert np.max(np.abs(g["E1"] - o.E1)) <= 1e-13 * np.abs(o.E1).max()
+
+
+@pytest.fixture(scope="module")
+def blobs(case):
+    # five Gaussian-blob sources (the sweep's kind) with 1e-3 seeded noise: at 16 block steps
+    # every source's GCV minimum is interior (lambda / sigma_1 = 3e-3 .. 0.11)
+    p, A, F = case
+    cent = np.random.default_rng(5).random((5, 3))
+    Fb = np.zeros((5, p.n))
+    Fb[:, : p.n_int] = I.blob_sources(p.x_int, cent)
+    noise = np.stack([np.linalg.norm(Fb[k]) * I.random_vector(p.n, 70 + k) / np.sqrt(p.n) for k in range(5)])
+    return Fb + 1e-3 * noise
+
+
+@pytest.mark.parametrize("mode", ["stored_fp64", "matfree_fp64"])
+def test_block_solve_against_oracle(mq, orc, blk, case, blobs, mode):
+    p, A, _ = case
+    F = blobs
+    s, ell = F.shape[0], 16
+    ref = blk.block_solve(A, F.T, ell)
+    assert np.all(ref.lam < ref.sv[0])
+    fixed = blk.block_solve(A, F.T, ell, lambda_fixed=ref.lam)
+    with _problem(mq, p, mode) as pr:
+        say("block solve gcv", mode)
+        out = pr.solve_block(F, ell)
+        say("lambda", out.lam, "oracle", ref.lam, "sweeps", out.t_ms[0, 6], "cg", out.t_ms[:, 7])
+        outs = []
+        for k in range(s):
+            o = pr.solve_block(F, ell, rule=mq.MQH_RULE_FIXED, lambda_fixed=float(ref.lam[k]))
+            outs.append(o.coef[k])
+        coef = np.stack(outs)
+        u = np.stack([pr.eval(coef[k], p.x_eval) for k in range(s)])
+    assert out.status == 0 and not np.any(out.flags & mq.MQH_INFO_GCV_AT_EDGE)
+    np.testing.assert_allclose(out.lam, ref.lam, rtol=1e-6)
+    for k in range(s):
+        uo = orc.eval_u(p.nodes, p.eps, fixed.coef[:, k], p.x_eval)
+        assert np.linalg.norm(u[k] - uo) <= 1e-8 * np.linalg.norm(uo)
+        assert np.linalg.norm(coef[k] - fixed.coef[:, k]) <= 1e-6 * np.linalg.norm(fixed.coef[:, k])
+    # reported norms: ||A coef - f|| and ||coef|| of the GCV solutions
+    for k in range(s):
+        assert out.resid_norm[k] == pytest.approx(np.linalg.norm(A @ out.coef[k] - F[k]), rel=1e-8)
+        assert out.sol_norm[k] == pytest.approx(np.linalg.norm(out.coef[k]), rel=1e-8)
+
+
+def test_block_one_source_is_single_hkt(mq):
+    # the cube with an interior GCV minimum of the single-source parity tests
+    p = I.cube_scaled(400, 240, kappa=3.0, eps=0.7, ell=80)
+    f = p.rhs
+    with _problem(mq, p, "stored_fp64") as pr:
+        say("block solve, one source")
+        out = pr.solve_block(f[None, :].copy(), p.ell)
+        ref = pr.solve(p.f_int, p.g_bnd, p.ell)
+        u = pr.eval(out.coef[0], p.x_eval)
+        ur = pr.eval(ref.coef, p.x_eval)
+    assert not (ref.flags & mq.MQH_INFO_GCV_AT_EDGE)
+    say("lambda", out.lam[0], "single", ref.lam)
+    assert out.lam[0] == pytest.approx(ref.lam, rel=1e-6)
+    assert np.linalg.norm(u - ur) <= 1e-8 * np.linalg.norm(ur)
+
+
+def test_block_fp32_products(mq, orc, blk, case):
+    p, A, F = case
+    F16 = np.stack([I.random_vector(p.n, 800 + k) for k in range(16)])
+    s, ell = 16, 4
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("block gkb fp32, s", s)
+        g = pr.gkb_block(F16, ell, want_bases=True)
+        ref = blk.block_solve(A, F16.T, ell)
+        say("block solve fp32 fixed")
+        out = pr.solve_block(F16, ell, rule=mq.MQH_RULE_FIXED, lambda_fixed=float(np.median(ref.lam)))
+        u = np.stack([pr.eval(out.coef[k], p.x_eval) for k in range(s)])
+    C, W, Z = g["C"], g["W"].T, g["Z"].T
+    nc = np.linalg.norm(C, 2)
+    rel = np.linalg.norm(A @ Z - W @ C) / nc
+    say("fp32 relation", rel)
+    assert rel <= 1e-5
+    assert np.max(np.abs(Z.T @ Z - np.eye(Z.shape[1]))) <= 1e-12
+    fixed = blk.block_solve(A, F16.T, ell, lambda_fixed=float(np.median(ref.lam)))
+    for k in range(s):
+        uo = orc.eval_u(p.nodes, p.eps, fixed.coef[:, k], p.x_eval)
+        assert np.linalg.norm(u[k] - uo) <= 1e-3 * np.linalg.norm(uo)
+
+
+def test_block_breakdown_in_invariant_subspace(mq, blk, case):
+    p, A, F = case
+    U, sv, Vt = np.linalg.svd(A)
+    Fi = (U[:, :3] @ np.array([[2.0, 0.3, 0.1], [0.0, 1.0, 0.2], [0.0, 0.0, 0.5]])).T.copy()
+    with _problem(mq, p, "stored_fp64") as pr:
+        say("block gkb, invariant subspace")
+        g = pr.gkb_block(Fi, 5)
+    o = blk.block_gkb(A, Fi.T, 5)
+    assert o.flag == 2 and o.ell == 1
+    assert g["status"] == mq.MQH_WBREAKDOWN and g["flag"] == 2 and g["ell_done"] == 1
+    np.testing.assert_allclose(np.sort(np.linalg.svd(g["C"][:3, :3], compute_uv=False)), np.sort(sv[:3]), rtol=1e-10)
+
+
+def test_block_invalid_arguments(mq, case):
+    p, A, F = case
+    with _problem(mq, p, "stored_fp64") as pr:
+        with pytest.raises(mq.MQHError):
+            pr.solve_block(np.zeros((17, p.n)), 2)
+        with pytest.raises(mq.MQHError):
+            pr.solve_block(F, p.n)  # ell nrhs > n
+        opts = mq.mqh_solve_opts(ell=2, reorth=1, method=mq.MQH_METHOD_LSQR, rule=mq.MQH_RULE_GCV)
+        Fc = np.ascontiguousarray(F[:2])
+        coef = np.zeros_like(Fc)
+        assert mq.lib.mqh_solve_block(pr.h, Fc.ctypes.data, p.n, 2, opts, coef.ctypes.data, p.n, None,
+                                      None) == mq.MQH_EINVAL
