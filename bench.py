@@ -335,6 +335,68 @@ def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, 
     return res
 
 
+def block_context(mq, torch, dev, members=(0, 1), steps=(7, 25), ell_lockstep: int = 100):
+    """Block Golub-Kahan (one Krylov space for a problem's 16 sources) beside the lockstep runs (one
+    space per source, ell = 100) on the largest sweep problems: solve times, and how far the block
+    solutions' u at 1000 interior points lies from the lockstep ones; then the block solve against
+    the block oracle on the smallest sweep problem (FP32 block products and stored FP64)."""
+    import numpy as np
+
+    from oracle import block as B
+    from oracle import oracle as O
+    from paper_2511_09798_amd import inputs as I
+
+    res = dict(workload="frequency-sweep cubes, 16 Gaussian-blob sources, HKT + GCV per source, FP32-evaluated "
+                        "block products", lockstep_ell=ell_lockstep, block_steps=list(steps), problems=[])
+    xe = np.random.default_rng(3).random((1000, 3))
+    xe_t = torch.from_numpy(xe).to(dev)
+
+    def timed(fn):
+        fn()  # warm-up (shapes, workspaces)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    for k in members:
+        m = I.sweep_member(k)
+        with mq.Problem(m.x_int, m.x_bnd, m.kappa, m.eps, "matfree_fp32") as pr:
+            F = torch.from_numpy(m.F).to(dev)
+            lk, tl = timed(lambda: pr.solve_multi(F, ell_lockstep))
+            ul = torch.stack([pr.eval(lk.coef[q], xe_t) for q in range(F.shape[0])])
+            row = dict(n=int(m.F.shape[1]), kappa=m.kappa, lockstep_s=tl)
+            for lb in steps:
+                bk, tb = timed(lambda: pr.solve_block(F, lb))
+                ub = torch.stack([pr.eval(bk.coef[q], xe_t) for q in range(F.shape[0])])
+                d = ((ub - ul).norm(dim=1) / ul.norm(dim=1)).cpu().numpy()
+                row[f"block{lb}_s"] = tb
+                row[f"block{lb}_phases_ms"] = dict(recurrence=float(bk.t_ms[0][1]), projected=float(bk.t_ms[0][2]))
+                row[f"block{lb}_u_vs_lockstep_median"] = float(np.median(d))
+                row[f"block{lb}_resid_over_lockstep_median"] = float(np.median(bk.resid_norm / lk.resid_norm))
+        res["problems"].append(row)
+        log("block", json.dumps(row))
+    k = int(np.argmin(I.sweep_sizes()))
+    m = I.sweep_member(k)
+    X = np.vstack([m.x_int, m.x_bnd])
+    A = O.assemble(X, m.x_int.shape[0], m.kappa, m.eps)
+    lb = steps[-1]
+    r = B.block_solve(A, m.F.T, lb)
+    chk = dict(problem=k, n=int(X.shape[0]), block_steps=lb)
+    for mode in ("matfree_fp32", "stored_fp64"):
+        with mq.Problem(m.x_int, m.x_bnd, m.kappa, m.eps, mode) as pr:
+            b = pr.solve_block(m.F, lb)
+            errs = []
+            for q in range(m.F.shape[0]):
+                u = pr.eval(b.coef[q], xe)
+                uo = O.eval_u(X, m.eps, r.coef[:, q], xe)
+                errs.append(float(np.linalg.norm(u - uo) / np.linalg.norm(uo)))
+        chk[mode] = dict(max_rel_l2_vs_oracle=max(errs), lambda_max_rel=float(np.max(np.abs(b.lam / r.lam - 1.0))))
+    res["oracle_check"] = chk
+    log("block oracle check", json.dumps(chk))
+    return res
+
+
 def full_context(mq, torch, dev, level: int):
     """Classical Tikhonov with GCV on the full SVD (Algorithm 3) on the 20 000-node cube, stored FP64 A,
     against HKT (ell = 200, GCV) on the same problem: time to solution and error against the manufactured u."""
@@ -422,6 +484,8 @@ def main():
     ap.add_argument("--sweep-oracle", type=int, default=1, help="check the smallest sweep problem against the oracle")
     ap.add_argument("--sweep-workers", type=int, default=4, help="sweep problems run side by side")
     ap.add_argument("--sweep-fixed-shapes", type=int, default=0, help="block-product shapes from the size heuristic")
+    ap.add_argument("--block", type=int, default=1,
+                    help="block Golub-Kahan beside the lockstep runs on the largest sweep problems (0: skip)")
     ap.add_argument("--full", type=int, default=1,
                     help="full-SVD reference on the 20 000-node cube beside HKT: 1 Tikh-Reg (about a minute), "
                          "2 also TSVD (0: skip)")
@@ -530,6 +594,8 @@ def main():
     if args.sweep > 0:
         line["sweep"] = sweep_context(mq, torch, dev, args.sweep, args.sweep_compare, bool(args.sweep_oracle),
                                       args.sweep_workers, bool(args.sweep_fixed_shapes))
+    if args.block > 0:
+        line["block_gkb"] = block_context(mq, torch, dev)
     if args.full > 0:
         line["full_svd_reference"] = full_context(mq, torch, dev, args.full)
     if args.cpu_rows > 0:

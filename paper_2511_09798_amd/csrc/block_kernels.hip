@@ -11,7 +11,7 @@
 // block QR is shifted Cholesky QR applied three times (the shift in the
 // first pass keeps the Cholesky factorisation defined for nearly dependent
 // columns; the two unshifted passes restore orthogonality to rounding):
-// k_blk_chol factors one 16 x 16 Gram matrix on one lane.
+// k_blk_chol factors one 16 x 16 Gram matrix on one workgroup.
 
 #include <float.h>
 #include <math.h>
@@ -76,14 +76,19 @@ __global__ __launch_bounds__(kBlock) void k_blk_gemvt(const double* __restrict__
     }
 }
 
-// c[col 16 + k] = sum over chunks (in order) of part[(chunk m + col) 16 + k].
+// c[col 16 + k] = sum over chunks of part[(chunk m + col) 16 + k]: one wave
+// per entry, lane l summing chunks l, l + 64, ... in order, then a fixed
+// shuffle tree (deterministic).
 __global__ __launch_bounds__(kBlock) void k_blk_reduce(const double* __restrict__ part, int chunks, int32_t m,
                                                        double* __restrict__ c) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= (int64_t)m * kBlkRhs) return;
+    const int64_t e = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (e >= (int64_t)m * kBlkRhs) return;  // wave-uniform
+    const int lane = threadIdx.x & (kWave - 1);
     double v = 0.0;
-    for (int q = 0; q < chunks; ++q) v += part[(int64_t)q * m * kBlkRhs + e];
-    c[e] = v;
+    for (int q = lane; q < chunks; q += kWave) v += part[(int64_t)q * m * kBlkRhs + e];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if (lane == 0) c[e] = v;
 }
 
 // Rows [16 (4 x + w), + 16) of the s output columns, per wave:
@@ -121,59 +126,66 @@ __global__ __launch_bounds__(kBlock) void k_blk_update(const double* V, int64_t 
     }
 }
 
-// One pass of (shifted) Cholesky QR, on one lane: G (c layout, G[i 16 + j] =
-// P_i . P_j, i, j < s) plus, if shifted, 11 (n s + s (s + 1)) eps trace(G) on
-// the diagonal, factored as R^T R (R upper triangular); Rinv = R^{-1} in the
-// c layout of k_blk_update (Rinv[col 16 + k]); Racc <- R Racc (row-major
-// 16 x 16, the accumulated triangular factor).  status <- 1 if a pivot is
-// not positive and finite (Racc and Rinv are then left as they were).
-__global__ void k_blk_chol(const double* __restrict__ G, int32_t s, int64_t n, int32_t shifted,
-                           double* __restrict__ Rinv, double* __restrict__ Racc, int32_t* __restrict__ status) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double R[kBlkRhs][kBlkRhs];
-    double tr = 0.0;
-    for (int i = 0; i < s; ++i) tr += G[i * kBlkRhs + i];
+// One pass of (shifted) Cholesky QR on one workgroup of 256 threads, thread
+// (i, j) = (t / 16, t % 16) owning entry (i, j) of the 16 x 16 tiles in LDS:
+// G (c layout, G[i 16 + j] = P_i . P_j, i, j < s) plus, if shifted,
+// 11 (n s + s (s + 1)) eps trace(G) on the diagonal is factored as R^T R
+// (R upper triangular, right-looking: per column a pivot, a row of R, a
+// rank-one update of the trailing block); Rinv = R^{-1} (back substitution,
+// column j by thread j) in the c layout of k_blk_update (Rinv[col 16 + k]);
+// Racc <- R Racc (row-major 16 x 16, the accumulated triangular factor).
+// status <- 1 if a pivot is not positive and finite (Racc and Rinv are then
+// left as they were).
+__global__ __launch_bounds__(kBlock) void k_blk_chol(const double* __restrict__ G, int32_t s, int64_t n,
+                                                     int32_t shifted, double* __restrict__ Rinv,
+                                                     double* __restrict__ Racc, int32_t* __restrict__ status) {
+    __shared__ double M[kBlkRhs][kBlkRhs];  // the trailing matrix, then R
+    __shared__ double X[kBlkRhs][kBlkRhs];  // R^{-1}
+    __shared__ double red[kBlock / kWave];
+    __shared__ int bad;
+    const int i = threadIdx.x / kBlkRhs, j = threadIdx.x % kBlkRhs;
+    const bool in = i < s && j < s;
+    const double g = in ? G[i * kBlkRhs + j] : 0.0;
+    double tr = (in && i == j) ? g : 0.0;
+    tr = block_sum<kBlock>(tr, red);
     const double shift = shifted ? 11.0 * ((double)n * s + (double)s * (s + 1)) * DBL_EPSILON * tr : 0.0;
-    for (int i = 0; i < kBlkRhs; ++i)
-        for (int j = 0; j < kBlkRhs; ++j) R[i][j] = 0.0;
-    for (int j = 0; j < s; ++j) {
-        double d = G[j * kBlkRhs + j] + shift;
-        for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
-        if (!(d > 0.0) || !isfinite(d)) {
-            *status = 1;
-            return;
+    M[i][j] = in ? g + (i == j ? shift : 0.0) : 0.0;
+    X[i][j] = 0.0;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int c = 0; c < s; ++c) {
+        if (threadIdx.x == 0) {
+            const double d = M[c][c];
+            if (!(d > 0.0) || !isfinite(d)) bad = 1;
+            M[c][c] = (d > 0.0 && isfinite(d)) ? sqrt(d) : 1.0;
         }
-        const double rjj = sqrt(d);
-        R[j][j] = rjj;
-        for (int i = j + 1; i < s; ++i) {
-            double v = G[j * kBlkRhs + i];
-            for (int k = 0; k < j; ++k) v -= R[k][j] * R[k][i];
-            R[j][i] = v / rjj;
+        __syncthreads();
+        if (i == c && j > c && j < s) M[c][j] /= M[c][c];  // row c of R
+        __syncthreads();
+        if (i > c && j >= i && j < s) M[i][j] -= M[c][i] * M[c][j];  // trailing upper triangle
+        __syncthreads();
+    }
+    if (bad) {
+        if (threadIdx.x == 0) *status = 1;
+        return;
+    }
+    // R = upper triangle of M; R^{-1} column by column (thread j < s)
+    if (threadIdx.x < s) {
+        const int cj = threadIdx.x;
+        for (int r = cj; r >= 0; --r) {
+            double v = (r == cj) ? 1.0 : 0.0;
+            for (int k = r + 1; k <= cj; ++k) v -= M[r][k] * X[k][cj];
+            X[r][cj] = v / M[r][r];
         }
     }
-    // inverse of the upper triangular R, column by column (back substitution)
-    double X[kBlkRhs][kBlkRhs];
-    for (int i = 0; i < kBlkRhs; ++i)
-        for (int j = 0; j < kBlkRhs; ++j) X[i][j] = 0.0;
-    for (int j = 0; j < s; ++j) {
-        for (int i = j; i >= 0; --i) {
-            double v = (i == j) ? 1.0 : 0.0;
-            for (int k = i + 1; k <= j; ++k) v -= R[i][k] * X[k][j];
-            X[i][j] = v / R[i][i];
-        }
-    }
-    for (int i = 0; i < kBlkRhs; ++i)
-        for (int j = 0; j < kBlkRhs; ++j) Rinv[i * kBlkRhs + j] = X[i][j];
-    // Racc <- R Racc (both upper triangular)
-    double T[kBlkRhs][kBlkRhs];
-    for (int i = 0; i < s; ++i)
-        for (int j = 0; j < s; ++j) {
-            double v = 0.0;
-            for (int k = i; k <= j; ++k) v += R[i][k] * Racc[k * kBlkRhs + j];
-            T[i][j] = v;
-        }
-    for (int i = 0; i < s; ++i)
-        for (int j = 0; j < s; ++j) Racc[i * kBlkRhs + j] = T[i][j];
+    __syncthreads();
+    Rinv[i * kBlkRhs + j] = X[i][j];
+    // Racc <- R Racc (upper triangular), entry (i, j) by thread (i, j)
+    double v = 0.0;
+    if (in && j >= i)
+        for (int k = i; k <= j; ++k) v += M[i][k] * Racc[k * kBlkRhs + j];
+    __syncthreads();  // every thread has read Racc
+    if (in) Racc[i * kBlkRhs + j] = j >= i ? v : 0.0;
 }
 
 // Racc <- identity (row-major 16 x 16), status <- 0.
@@ -203,7 +215,8 @@ void launch_blk_gemvt(const double* V, int64_t ldv, int64_t n, int32_t m, const 
     const int chunks = blk_chunks(n, m, &chunk);
     k_blk_gemvt<<<dim3((unsigned)chunks, (unsigned)((m + kBt - 1) / kBt)), kBlock, 0, st>>>(V, ldv, n, m, P, ldp, s,
                                                                                            chunk, part);
-    k_blk_reduce<<<(unsigned)(((int64_t)m * kBlkRhs + kBlock - 1) / kBlock), kBlock, 0, st>>>(part, chunks, m, c);
+    const int64_t waves = (int64_t)m * kBlkRhs, per = kBlock / kWave;
+    k_blk_reduce<<<(unsigned)((waves + per - 1) / per), kBlock, 0, st>>>(part, chunks, m, c);
 }
 
 void launch_blk_update(const double* V, int64_t ldv, int64_t n, int32_t m, const double* c, int64_t cs, int64_t ks,
@@ -215,7 +228,7 @@ void launch_blk_update(const double* V, int64_t ldv, int64_t n, int32_t m, const
 
 void launch_blk_chol(const double* G, int32_t s, int64_t n, int32_t shifted, double* Rinv, double* Racc,
                      int32_t* status, hipStream_t st) {
-    k_blk_chol<<<1, 64, 0, st>>>(G, s, n, shifted, Rinv, Racc, status);
+    k_blk_chol<<<1, kBlock, 0, st>>>(G, s, n, shifted, Rinv, Racc, status);
 }
 
 void launch_blk_eye(double* Racc, int32_t* status, hipStream_t st) {

@@ -1132,8 +1132,9 @@ struct BlockWs {
     double* G = nullptr;     // 16 x 16 Gram matrix
     double* Rinv = nullptr;  // 16 x 16
     double* Racc = nullptr;  // 16 x 16 accumulated R
-    double* mat = nullptr;   // 16 x 16 shift block (c layout)
+    double* mat = nullptr;   // two 16 x 16 shift blocks (c layout)
     int32_t* status = nullptr;
+    std::vector<double> host = std::vector<double>(2 * kBlkRhs * kBlkRhs);  // their host copies
     ~BlockWs() {
         dfree(W);
         dfree(Z);
@@ -1162,7 +1163,7 @@ int block_alloc(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell) {
         (rc = dalloc(&b.P, (size_t)(kBlkRhs * ldn))) || (rc = dalloc(&b.part, (size_t)(most * kBlkRhs))) ||
         (rc = dalloc(&b.c, (size_t)mmax * kBlkRhs)) || (rc = dalloc(&b.G, kBlkRhs * kBlkRhs)) ||
         (rc = dalloc(&b.Rinv, kBlkRhs * kBlkRhs)) || (rc = dalloc(&b.Racc, kBlkRhs * kBlkRhs)) ||
-        (rc = dalloc(&b.mat, kBlkRhs * kBlkRhs)) || (rc = dalloc(&b.status, 1)))
+        (rc = dalloc(&b.mat, 2 * kBlkRhs * kBlkRhs)) || (rc = dalloc(&b.status, 1)))
         return rc;
     hipStream_t st = p->stream;
     HIPCHK(hipMemsetAsync(b.W, 0, (size_t)mmax * ldn * sizeof(double), st));
@@ -1196,17 +1197,20 @@ int block_qr(mqh_problem* p, BlockWs& b, double* X, int32_t s, double* Rh, bool*
 }
 
 // X -= V M (V: n x s block of a basis, M: s x s given row-major on the host;
-// trans: use M^T).
-int block_shift(mqh_problem* p, BlockWs& b, const double* V, const double* M, int32_t s, bool trans, double* X) {
-    double c[kBlkRhs * kBlkRhs];
+// trans: use M^T).  The coefficients go through host slot `slot` of b.host
+// (kept until the process's next synchronisation, which every block step
+// has after its QR) and device slot `slot` of b.mat.
+int block_shift(mqh_problem* p, BlockWs& b, const double* V, const double* M, int32_t s, bool trans, double* X,
+                int slot) {
+    double* c = b.host.data() + slot * kBlkRhs * kBlkRhs;
     for (int i = 0; i < kBlkRhs * kBlkRhs; ++i) c[i] = 0.0;
     for (int col = 0; col < s; ++col)
         for (int k = 0; k < s; ++k) c[col * kBlkRhs + k] = trans ? M[k * s + col] : M[col * s + k];
     hipStream_t st = p->stream;
-    HIPCHK(hipMemcpyAsync(b.mat, c, sizeof(c), hipMemcpyHostToDevice, st));
-    launch_blk_update(V, p->ldn, p->n, s, b.mat, kBlkRhs, 1, X, p->ldn, s, 1, st);
+    double* dm = b.mat + slot * kBlkRhs * kBlkRhs;
+    HIPCHK(hipMemcpyAsync(dm, c, kBlkRhs * kBlkRhs * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_blk_update(V, p->ldn, p->n, s, dm, kBlkRhs, 1, X, p->ldn, s, 1, st);
     LAUNCHCHK("block shift");
-    HIPCHK(hipStreamSynchronize(st));  // c is a local
     return MQH_OK;
 }
 
@@ -1258,7 +1262,7 @@ int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vecto
         double* Zj = b.Z + (int64_t)(j - 1) * s * ldn;
         // P = A^T W_j - Z_{j-1} E_j^T, reorthogonalised against Z_1 .. Z_{j-1}
         if ((rc = block_product(p, s, 1, Wj, ldn, nullptr, 0, nullptr, 0, b.P, nullptr, false))) return rc;
-        if (j > 1 && (rc = block_shift(p, b, Zj - (int64_t)s * ldn, Eprev.data(), s, true, b.P))) return rc;
+        if (j > 1 && (rc = block_shift(p, b, Zj - (int64_t)s * ldn, Eprev.data(), s, true, b.P, 0))) return rc;
         block_cgs2(p, b, b.Z, (j - 1) * s, s, b.P);
         if ((rc = block_qr(p, b, b.P, s, R.data(), &bad))) return rc;
         double mn, mx;
@@ -1278,7 +1282,7 @@ int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vecto
             for (int k = 0; k < s; ++k) D[(size_t)i * s + k] = R[(size_t)k * s + i];
         // Q = A Z_j - W_j D_j, reorthogonalised against W_1 .. W_j
         if ((rc = block_product(p, s, 0, Zj, ldn, nullptr, 0, nullptr, 0, b.P, nullptr, false))) return rc;
-        if ((rc = block_shift(p, b, Wj, D.data(), s, false, b.P))) return rc;
+        if ((rc = block_shift(p, b, Wj, D.data(), s, false, b.P, 1))) return rc;
         block_cgs2(p, b, b.W, j * s, s, b.P);
         if ((rc = block_qr(p, b, b.P, s, R.data(), &bad))) return rc;
         diag_range(R, &mn, &mx);
