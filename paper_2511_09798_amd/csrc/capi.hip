@@ -833,6 +833,8 @@ struct FullRun {
     double* ct = nullptr;
     double* cpart = nullptr;
     double* cpc = nullptr;
+    int32_t* pair_ok = nullptr;    // per schedule slot: round at which the pair was last found orthogonal, or -1
+    int32_t* blk_stamp = nullptr;  // per block: round of its last rotation, or -1
     int sweeps = 0;
     double final_off = 0.0;
     ~FullRun() {
@@ -844,6 +846,8 @@ struct FullRun {
         dfree(ct);
         dfree(cpart);
         dfree(cpc);
+        dfree(pair_ok);
+        dfree(blk_stamp);
         dfree(G);
         dfree(pairs);
         dfree(Pg);
@@ -879,6 +883,9 @@ constexpr int kFullMaxInner = 1;
 inline double full_tol(int64_t n) { return 16.0 * sqrt((double)n) * DBL_EPSILON; }
 inline double full_floor(int64_t n) { return 2.0 * full_tol(n); }
 constexpr int kFullStall = 3;
+// Fraction of rotated pairs below which a sweep keeps the row order of the
+// one before (de Rijk's ordering matters while many pairs rotate).
+constexpr double kFullFreeze = 0.05;
 
 constexpr int kFullCgMax = MQH_FULL_CG_MAX;  // conjugate-gradient iterations of the solutions' dual system
 constexpr double kFullCgTol = 1e-15;  // stop when sqrt(r^T D^-1 r) falls below this fraction of its start
@@ -907,7 +914,8 @@ int full_prepare(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
     if ((rc = dalloc(&r.G, (size_t)(r.nrow * r.ldg))) || (rc = dalloc(&r.pairs, (size_t)r.rounds * r.npairs)) ||
         (rc = dalloc(&r.Pg, (size_t)r.npairs * r.S * 4096)) || (rc = dalloc(&r.Pout, (size_t)r.npairs * 4096)) ||
         (rc = dalloc(&r.flag, (size_t)r.npairs)) || (rc = dalloc(&r.off, (size_t)r.rounds * r.npairs)) ||
-        (rc = dalloc(&r.maxoff, 1)) || (rc = dalloc(&r.sig, (size_t)n)) || (rc = dalloc(&r.fh, (size_t)n)) ||
+        (rc = dalloc(&r.maxoff, 2)) || (rc = dalloc(&r.sig, (size_t)n)) || (rc = dalloc(&r.fh, (size_t)n)) ||
+        (rc = dalloc(&r.pair_ok, (size_t)r.rounds * r.npairs)) || (rc = dalloc(&r.blk_stamp, (size_t)r.nblk)) ||
         (rc = dalloc(&r.rank, (size_t)n)) || (rc = dalloc(&r.sv, (size_t)n)) || (rc = dalloc(&r.fs, (size_t)n)) ||
         (rc = dalloc(&r.order, (size_t)n)) || (rc = dalloc(&r.tail, (size_t)n + 1)) || (rc = dalloc(&r.po, 1)) ||
         (rc = dalloc(&r.coef, (size_t)n)) || (rc = dalloc(&r.rowidx, (size_t)r.nrow)) ||
@@ -928,20 +936,25 @@ int full_prepare(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
     }
     HIPCHK(hipMemcpyAsync(r.pairs, pr.data(), pr.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(r.G, 0, (size_t)(r.nrow * r.ldg) * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(r.pair_ok, 0xff, (size_t)r.rounds * r.npairs * sizeof(int32_t), s));  // -1
+    HIPCHK(hipMemsetAsync(r.blk_stamp, 0xff, (size_t)r.nblk * sizeof(int32_t), s));
     HIPCHK(hipStreamSynchronize(s));  // pr is a local
     return MQH_OK;
 }
 
 // Jacobi sweeps on the filled G (n matrix columns, nrhs data columns), each
-// on the rows ordered by decreasing norm, until in a whole sweep every pair
-// of rows has the component of the smaller along the larger at most
-// full_tol(n) ||M||_F, or stalls below full_floor(n) ||M||_F (or
-// kFullMaxSweeps); then sigma and the first data column f^ (input row
-// order) and their descending order.
+// on the rows ordered by decreasing norm (kept from the sweep before once
+// fewer than kFullFreeze of the pairs rotate; a pair whose rows have not
+// changed since it was last found orthogonal is then left out), until in a
+// whole sweep every pair of rows has the component of the smaller along
+// the larger at most full_tol(n) ||M||_F, or stalls below full_floor(n)
+// ||M||_F (or kFullMaxSweeps); then sigma and the first data column f^
+// (input row order) and their descending order.
 int full_sweeps(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
     const double tol = full_tol(n);
+    const int64_t slots = (int64_t)r.rounds * r.npairs;
     std::vector<double> rn((size_t)r.nrow);
-    std::vector<int32_t> idx((size_t)r.nrow);
+    std::vector<int32_t> idx((size_t)r.nrow), prev;
     double inv_f = 0.0;
     r.sweeps = 0;
     // MQH_TRACE_FULL=1 prints one line per sweep to stderr (diagnostics only)
@@ -951,53 +964,64 @@ int full_sweeps(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
     const double floor_off = full_floor(n);
     double best = HUGE_VAL;
     int stall = 0;
+    bool frozen = false;  // row order fixed (few pairs still rotate)
     for (int sw = 0; sw < kFullMaxSweeps; ++sw) {
-        // de Rijk's ordering: rows by decreasing norm (stable), blocks of 32
-        launch_fs_norms(r.G, r.ldg, r.nrow, n, r.rnorm, r.rtmp, s);
-        LAUNCHCHK("full SVD: row norms");
-        HIPCHK(hipMemcpyAsync(rn.data(), r.rnorm, (size_t)r.nrow * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (sw == 0) {
-            // ||M||_F (invariant under the rotations)
-            double fro2 = 0.0;
-            for (double v : rn) fro2 += v * v;
-            if (!(fro2 > 0.0) || !isfinite(fro2)) return fail(MQH_EDEVICE, "full SVD: zero or non-finite matrix");
-            inv_f = 1.0 / sqrt(fro2);
+        int same = 1;
+        if (!frozen) {
+            // de Rijk's ordering: rows by decreasing norm (stable), blocks of 32
+            launch_fs_norms(r.G, r.ldg, r.nrow, n, r.rnorm, r.rtmp, s);
+            LAUNCHCHK("full SVD: row norms");
+            HIPCHK(hipMemcpyAsync(rn.data(), r.rnorm, (size_t)r.nrow * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (sw == 0) {
+                // ||M||_F (invariant under the rotations)
+                double fro2 = 0.0;
+                for (double v : rn) fro2 += v * v;
+                if (!(fro2 > 0.0) || !isfinite(fro2)) return fail(MQH_EDEVICE, "full SVD: zero or non-finite matrix");
+                inv_f = 1.0 / sqrt(fro2);
+            }
+            for (int64_t i = 0; i < r.nrow; ++i) idx[(size_t)i] = (int32_t)i;
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int32_t a, int32_t b) { return rn[(size_t)a] > rn[(size_t)b]; });
+            same = idx == prev ? 1 : 0;
+            if (!same) {
+                prev = idx;
+                HIPCHK(hipMemcpyAsync(r.rowidx, prev.data(), prev.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                      s));
+            }
         }
-        for (int64_t i = 0; i < r.nrow; ++i) idx[(size_t)i] = (int32_t)i;
-        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return rn[(size_t)a] > rn[(size_t)b]; });
-        HIPCHK(hipMemcpyAsync(r.rowidx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         for (int rd = 0; rd < r.rounds; ++rd) {
             const int2* prd = r.pairs + (int64_t)rd * r.npairs;
-            launch_fs_gram(r.G, r.ldg, n, r.rowidx, prd, r.npairs, r.S, r.chunk, r.Pg, s);
-            launch_fs_eig(r.Pg, r.S, r.npairs, tol, inv_f, kFullMaxInner, r.Pout, r.flag,
-                          r.off + (int64_t)rd * r.npairs, s);
+            const int64_t slot0 = (int64_t)rd * r.npairs;
+            const int32_t g = sw * r.rounds + rd;
+            launch_fs_gram(r.G, r.ldg, n, r.rowidx, prd, r.npairs, r.S, r.chunk, r.Pg, r.pair_ok, r.blk_stamp, slot0,
+                           same, s);
+            launch_fs_eig(r.Pg, r.S, r.npairs, tol, inv_f, kFullMaxInner, r.Pout, r.flag, r.off + slot0, prd,
+                          r.pair_ok, r.blk_stamp, slot0, g, same, s);
             launch_fs_update(r.G, r.ldg, n + nrhs, r.rowidx, prd, r.npairs, r.Pout, r.flag, s);
         }
         LAUNCHCHK("full SVD: Jacobi sweep");
-        launch_fs_maxoff(r.off, (int64_t)r.rounds * r.npairs, r.maxoff, s);
-        double mo = 0.0;
-        HIPCHK(hipMemcpyAsync(&mo, r.maxoff, sizeof(double), hipMemcpyDeviceToHost, s));
+        launch_fs_maxoff(r.off, slots, tol, r.maxoff, s);
+        double mo[2] = {0.0, 0.0};
+        HIPCHK(hipMemcpyAsync(mo, r.maxoff, sizeof(mo), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         r.sweeps = sw + 1;
-        r.final_off = mo;
+        r.final_off = mo[0];
         if (trace) {
-            // pairs rotated in this sweep (off above tol), and the sweep's time
-            std::vector<double> offs((size_t)r.rounds * r.npairs);
-            HIPCHK(hipMemcpy(offs.data(), r.off, offs.size() * sizeof(double), hipMemcpyDeviceToHost));
-            int64_t rot = 0;
-            for (double v : offs) rot += v > tol ? 1 : 0;
             const auto t1 = std::chrono::steady_clock::now();
-            fprintf(stderr, "[mqh full] sweep %d off %.3e rotated %lld of %lld pairs %.1f ms\n", sw + 1, mo,
-                    (long long)rot, (long long)offs.size(),
+            fprintf(stderr, "[mqh full] sweep %d off %.3e rotated %.0f of %lld pairs%s %.1f ms\n", sw + 1, mo[0], mo[1],
+                    (long long)slots, same ? " (order kept)" : "",
                     std::chrono::duration<double, std::milli>(t1 - t0).count());
             t0 = t1;
         }
-        if (!(mo > tol)) break;
-        if (mo < 0.75 * best) {
-            best = mo;
+        if (!(mo[0] > tol)) break;
+        // once fewer than 5% of the pairs still rotate, keep the row order: blocks stay the same,
+        // and pairs whose rows have not changed are left out
+        if (mo[1] < kFullFreeze * (double)slots) frozen = true;
+        if (mo[0] < 0.75 * best) {
+            best = mo[0];
             stall = 0;
-        } else if (++stall >= kFullStall && !(mo > floor_off)) {
+        } else if (++stall >= kFullStall && !(mo[0] > floor_off)) {
             break;
         }
     }

@@ -53,15 +53,32 @@ __device__ __forceinline__ void load_tile(const double* __restrict__ G, int64_t 
     }
 }
 
+// Whether the pair in schedule slot `slot` (blocks pr.x, pr.y) can be left
+// out this round: with the row order unchanged (same != 0), its blocks were
+// both last rotated before the round at which this pair was last found
+// orthogonal (pair_ok[slot] >= 0), so its rows, and its Gram matrix, are
+// exactly as they were then.  blk_stamp: per block the global round of its
+// last rotation (-1: none).
+__device__ __forceinline__ bool pair_unchanged(const int32_t* __restrict__ pair_ok,
+                                               const int32_t* __restrict__ blk_stamp, int2 pr, int64_t slot,
+                                               int same) {
+    if (!same) return false;
+    const int32_t g0 = pair_ok[slot];
+    return g0 >= 0 && blk_stamp[pr.x] < g0 && blk_stamp[pr.y] < g0;
+}
+
 // Partial Gram matrices: Pg[(pair * S + chunk)][a][b] = sum over the chunk's
 // columns c < ncol of X[a][c] X[b][c].  Grid (S, pairs), 256 threads: wave w
-// forms rows 16w .. 16w + 15 of the 64 x 64 result.
+// forms rows 16w .. 16w + 15 of the 64 x 64 result.  Pairs left out this
+// round (pair_unchanged) write nothing.
 __global__ __launch_bounds__(kBlock) void k_fs_gram(const double* __restrict__ G, int64_t ldg, int64_t ncol,
                                                     const int32_t* __restrict__ rowidx,
                                                     const int2* __restrict__ pairs, int64_t chunk,
-                                                    double* __restrict__ Pg) {
+                                                    double* __restrict__ Pg, const int32_t* __restrict__ pair_ok,
+                                                    const int32_t* __restrict__ blk_stamp, int64_t slot0, int same) {
     __shared__ double t[kFsRows * kFsLd];
     const int2 pr = pairs[blockIdx.y];
+    if (pair_unchanged(pair_ok, blk_stamp, pr, slot0 + blockIdx.y, same)) return;  // block-uniform
     const int S = gridDim.x;
     const int64_t c0 = (int64_t)blockIdx.x * chunk;
     const int64_t c1 = c0 + chunk < ncol ? c0 + chunk : ncol;
@@ -123,21 +140,34 @@ __device__ double offdiag(const double* __restrict__ M, double inv_f, double* __
     return r;
 }
 
-// One workgroup per pair: M = sum of the S partial Grams; off[pair] = its
-// off-diagonal measure (offdiag); if above tol, cyclic Jacobi (round-robin
+// One workgroup per pair (schedule slot slot0 + pair, global round g): pairs
+// left out (pair_unchanged) only clear their flag; otherwise M = sum of the
+// S partial Grams, off[pair] = its off-diagonal measure (offdiag), and at or
+// below tol the slot is marked orthogonal at round g (pair_ok), while above
+// tol both blocks are stamped with g and a cyclic Jacobi (round-robin
 // order, 32 disjoint rotations per step, 63 steps per sweep, rotations
 // skipped when |M_pq| <= eps/4 sqrt(M_pp M_qq); until the measure is below
 // eps or max_inner sweeps) gives P^T M P (nearly) diagonal, and P goes to
 // Pout[pair] with flag[pair] = 1; else flag 0.
 __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg, int S, double tol, double inv_f,
                                                    int max_inner, double* __restrict__ Pout,
-                                                   int32_t* __restrict__ flag, double* __restrict__ off) {
+                                                   int32_t* __restrict__ flag, double* __restrict__ off,
+                                                   const int2* __restrict__ pairs, int32_t* __restrict__ pair_ok,
+                                                   int32_t* __restrict__ blk_stamp, int64_t slot0, int32_t g,
+                                                   int same) {
     __shared__ double M[kFsRows * kFsLd];
     __shared__ double P[kFsRows * kFsLd];
     __shared__ double red[kBlock / kWave];
     __shared__ double rc[kFsRows / 2], rs[kFsRows / 2];
     __shared__ int rp[kFsRows / 2], rq[kFsRows / 2];
     const int pair = blockIdx.x;
+    const int2 pr = pairs[pair];
+    const int64_t slot = slot0 + pair;
+    if (pair_unchanged(pair_ok, blk_stamp, pr, slot, same)) {
+        // left out: off[pair] keeps the value this slot had when it was found orthogonal
+        if (threadIdx.x == 0) flag[pair] = 0;
+        return;
+    }
     const double* src = Pg + (int64_t)pair * S * (kFsRows * kFsRows);
     for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock) {
         double v = 0.0;
@@ -150,8 +180,16 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
     const double o0 = offdiag(M, inv_f, red);
     if (threadIdx.x == 0) off[pair] = o0;
     if (!(o0 > tol)) {
-        if (threadIdx.x == 0) flag[pair] = 0;
+        if (threadIdx.x == 0) {
+            flag[pair] = 0;
+            pair_ok[slot] = g;
+        }
         return;
+    }
+    if (threadIdx.x == 0) {
+        pair_ok[slot] = -1;
+        blk_stamp[pr.x] = g;
+        blk_stamp[pr.y] = g;
     }
     const double tol_in = DBL_EPSILON;
     for (int sweep = 0; sweep < max_inner; ++sweep) {
@@ -263,12 +301,18 @@ __global__ __launch_bounds__(kBlock) void k_fs_update(double* __restrict__ G, in
     }
 }
 
-// Largest entry of off[0 .. count) into *out (one workgroup).
-__global__ __launch_bounds__(kBlock) void k_fs_maxoff(const double* __restrict__ off, int64_t count,
+// Largest entry of off[0 .. count) into out[0] and the number of entries
+// above tol into out[1] (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_fs_maxoff(const double* __restrict__ off, int64_t count, double tol,
                                                       double* __restrict__ out) {
     __shared__ double red[kBlock / kWave];
-    double mx = 0.0;
-    for (int64_t i = threadIdx.x; i < count; i += kBlock) mx = off[i] > mx ? off[i] : mx;
+    __shared__ double cnt[kBlock / kWave];
+    double mx = 0.0, c = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += kBlock) {
+        mx = off[i] > mx ? off[i] : mx;
+        c += off[i] > tol ? 1.0 : 0.0;
+    }
+    c = block_sum<kBlock>(c, cnt);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const double y = __shfl_xor(mx, o, kWave);
@@ -279,7 +323,8 @@ __global__ __launch_bounds__(kBlock) void k_fs_maxoff(const double* __restrict__
     if (threadIdx.x == 0) {
         double r = 0.0;
         for (int i = 0; i < kBlock / kWave; ++i) r = red[i] > r ? red[i] : r;
-        *out = r;
+        out[0] = r;
+        out[1] = c;
     }
 }
 
@@ -702,13 +747,17 @@ void launch_fs_setf(double* G, int64_t ldg, int64_t n, const double* f, hipStrea
 }
 
 void launch_fs_gram(const double* G, int64_t ldg, int64_t ncol, const int32_t* rowidx, const int2* pairs, int npairs,
-                    int S, int64_t chunk, double* Pg, hipStream_t s) {
-    k_fs_gram<<<dim3((unsigned)S, (unsigned)npairs), kBlock, 0, s>>>(G, ldg, ncol, rowidx, pairs, chunk, Pg);
+                    int S, int64_t chunk, double* Pg, const int32_t* pair_ok, const int32_t* blk_stamp, int64_t slot0,
+                    int same, hipStream_t s) {
+    k_fs_gram<<<dim3((unsigned)S, (unsigned)npairs), kBlock, 0, s>>>(G, ldg, ncol, rowidx, pairs, chunk, Pg, pair_ok,
+                                                                     blk_stamp, slot0, same);
 }
 
 void launch_fs_eig(const double* Pg, int S, int npairs, double tol, double inv_f, int max_inner, double* Pout,
-                   int32_t* flag, double* off, hipStream_t s) {
-    k_fs_eig<<<(unsigned)npairs, kBlock, 0, s>>>(Pg, S, tol, inv_f, max_inner, Pout, flag, off);
+                   int32_t* flag, double* off, const int2* pairs, int32_t* pair_ok, int32_t* blk_stamp, int64_t slot0,
+                   int32_t g, int same, hipStream_t s) {
+    k_fs_eig<<<(unsigned)npairs, kBlock, 0, s>>>(Pg, S, tol, inv_f, max_inner, Pout, flag, off, pairs, pair_ok,
+                                                 blk_stamp, slot0, g, same);
 }
 
 void launch_fs_update(double* G, int64_t ldg, int64_t ncol, const int32_t* rowidx, const int2* pairs, int npairs,
@@ -718,8 +767,8 @@ void launch_fs_update(double* G, int64_t ldg, int64_t ncol, const int32_t* rowid
         G, ldg, ncol, rowidx, pairs, Pin, flag);
 }
 
-void launch_fs_maxoff(const double* off, int64_t count, double* out, hipStream_t s) {
-    k_fs_maxoff<<<1, kBlock, 0, s>>>(off, count, out);
+void launch_fs_maxoff(const double* off, int64_t count, double tol, double* out, hipStream_t s) {
+    k_fs_maxoff<<<1, kBlock, 0, s>>>(off, count, tol, out);
 }
 
 void launch_fs_norms(const double* G, int64_t ldg, int64_t rows, int64_t n, double* sig, double* fh, hipStream_t s) {

@@ -129,13 +129,20 @@ void launch_proj_solution(const double* sv, const double* ft, const double* V, i
 
 // Full SVD (full_kernels.hip)
 void launch_fs_setf(double* G, int64_t ldg, int64_t n, const double* f, hipStream_t s);
+// pair_ok (per schedule slot) and blk_stamp (per block): the bookkeeping that
+// lets a round leave out pairs whose rows have not changed since they were
+// last found orthogonal (same != 0: the row order is that of the previous
+// sweep); slot0 = round x pairs, g = the global round.
 void launch_fs_gram(const double* G, int64_t ldg, int64_t ncol, const int32_t* rowidx, const int2* pairs, int npairs,
-                    int S, int64_t chunk, double* Pg, hipStream_t s);
+                    int S, int64_t chunk, double* Pg, const int32_t* pair_ok, const int32_t* blk_stamp, int64_t slot0,
+                    int same, hipStream_t s);
 void launch_fs_eig(const double* Pg, int S, int npairs, double tol, double inv_f, int max_inner, double* Pout,
-                   int32_t* flag, double* off, hipStream_t s);
+                   int32_t* flag, double* off, const int2* pairs, int32_t* pair_ok, int32_t* blk_stamp, int64_t slot0,
+                   int32_t g, int same, hipStream_t s);
 void launch_fs_update(double* G, int64_t ldg, int64_t ncol, const int32_t* rowidx, const int2* pairs, int npairs,
                       const double* Pin, const int32_t* flag, hipStream_t s);
-void launch_fs_maxoff(const double* off, int64_t count, double* out, hipStream_t s);
+// out[0] = max off, out[1] = number of entries above tol
+void launch_fs_maxoff(const double* off, int64_t count, double tol, double* out, hipStream_t s);
 void launch_fs_norms(const double* G, int64_t ldg, int64_t rows, int64_t n, double* sig, double* fh, hipStream_t s);
 void launch_fs_rank(const double* sig, const double* fh, int64_t n, int32_t* rank, double* sv, double* fs,
                     int32_t* order, hipStream_t s);
