@@ -823,16 +823,21 @@ struct FullRun {
     int32_t* order = nullptr;
     double* tail = nullptr;
     ParamOut* po = nullptr;
-    double* coef = nullptr;
     double* f = nullptr;
     int32_t* rowidx = nullptr;  // the sweep's row order (blocks = runs of 32)
     double* rnorm = nullptr;    // row norms of all nrow rows
     double* rtmp = nullptr;
-    double* cq = nullptr;       // conjugate-gradient direction, B q, dot-product terms, G^T q partials, scalars
+    // conjugate-gradient iterates y, residuals, directions, B q, dot-product terms, x = G^T y (nz data
+    // columns each), G^T q partials, scalars, ||f||^2 per data column
+    double* cy = nullptr;
+    double* cr = nullptr;
+    double* cq = nullptr;
     double* cw = nullptr;
     double* ct = nullptr;
+    double* cx = nullptr;
     double* cpart = nullptr;
     double* cpc = nullptr;
+    double* fn2 = nullptr;
     int32_t* pair_ok = nullptr;    // per schedule slot: round at which the pair was last found orthogonal, or -1
     int32_t* blk_stamp = nullptr;  // per block: round of its last rotation, or -1
     int sweeps = 0;
@@ -841,11 +846,15 @@ struct FullRun {
         dfree(rowidx);
         dfree(rnorm);
         dfree(rtmp);
+        dfree(cy);
+        dfree(cr);
         dfree(cq);
         dfree(cw);
         dfree(ct);
+        dfree(cx);
         dfree(cpart);
         dfree(cpc);
+        dfree(fn2);
         dfree(pair_ok);
         dfree(blk_stamp);
         dfree(G);
@@ -863,7 +872,6 @@ struct FullRun {
         dfree(order);
         dfree(tail);
         dfree(po);
-        dfree(coef);
         dfree(f);
     }
 };
@@ -918,7 +926,7 @@ int full_prepare(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
         (rc = dalloc(&r.pair_ok, (size_t)r.rounds * r.npairs)) || (rc = dalloc(&r.blk_stamp, (size_t)r.nblk)) ||
         (rc = dalloc(&r.rank, (size_t)n)) || (rc = dalloc(&r.sv, (size_t)n)) || (rc = dalloc(&r.fs, (size_t)n)) ||
         (rc = dalloc(&r.order, (size_t)n)) || (rc = dalloc(&r.tail, (size_t)n + 1)) || (rc = dalloc(&r.po, 1)) ||
-        (rc = dalloc(&r.coef, (size_t)n)) || (rc = dalloc(&r.rowidx, (size_t)r.nrow)) ||
+        (rc = dalloc(&r.rowidx, (size_t)r.nrow)) ||
         (rc = dalloc(&r.rnorm, (size_t)r.nrow)) || (rc = dalloc(&r.rtmp, (size_t)r.nrow)))
         return rc;
     // round-robin tournament of the blocks: block 0 stays, the others rotate
@@ -1048,58 +1056,70 @@ int full_svd_run(mqh_problem* p, FullRun& r) {
     return MQH_OK;
 }
 
-// The solution x = G^T y of the Tikhonov (method 1) or TSVD (method 0) dual
-// system by preconditioned conjugate gradients (the kernels' comment gives
-// the system) for the data column fh (physical row order) and the choice
-// po; rows of rank >= rcap are left out.  y in r.rnorm, the residual in
-// r.rtmp, x in r.coef; then po->rho = ||M x - f|| and po->eta = ||x||.
-int full_solution(hipStream_t s, FullRun& r, int64_t n, int32_t method, const double* fh, ParamOut* po, int64_t rcap,
-                  int* iters, bool* converged) {
+// The solutions x = G^T y of the Tikhonov (method 1) or TSVD (method 0) dual
+// systems by preconditioned conjugate gradients (the kernels' comment gives
+// the system) for nz data columns at once: column z's data fh + z vs
+// (physical row order) and choice po + z; rows of rank >= rcap are left
+// out.  Every column runs until all have reached the tolerance (or the
+// cap); a column past its own tolerance keeps taking steps whose size has
+// fallen with its residual.  x_z in r.cx + z vs; then po[z].rho =
+// ||M x_z - f_z|| and po[z].eta = ||x_z||.  iters[z]: the iteration at which
+// column z reached its tolerance (or the cap, converged[z] false).
+int full_solution(hipStream_t s, FullRun& r, int64_t n, int32_t method, const double* fh, int64_t vs, ParamOut* po,
+                  int64_t rcap, int nz, int* iters, bool* converged) {
     int rc;
     const int chunks = fs_gemvt_chunks(n);
     if (r.cq == nullptr) {
-        if ((rc = dalloc(&r.cq, (size_t)n)) || (rc = dalloc(&r.cw, (size_t)n)) || (rc = dalloc(&r.ct, (size_t)n)) ||
-            (rc = dalloc(&r.cpart, (size_t)chunks * (size_t)n)) || (rc = dalloc(&r.cpc, 4)))
+        const size_t v = (size_t)vs * (size_t)nz;
+        if ((rc = dalloc(&r.cy, v)) || (rc = dalloc(&r.cr, v)) || (rc = dalloc(&r.cq, v)) || (rc = dalloc(&r.cw, v)) ||
+            (rc = dalloc(&r.ct, v)) || (rc = dalloc(&r.cx, v)) ||
+            (rc = dalloc(&r.cpart, (size_t)nz * (size_t)chunks * (size_t)n)) || (rc = dalloc(&r.cpc, 4 * (size_t)nz)))
             return rc;
     }
-    double* y = r.rnorm;
-    double* res = r.rtmp;
-    launch_fs_pcg_start(r.sig, fh, r.rank, n, method, rcap, po, y, res, r.cq, r.ct, r.cpc, 2, s);
+    launch_fs_pcg_start(r.sig, fh, r.rank, n, method, rcap, po, vs, r.cy, r.cr, r.cq, r.ct, r.cpc, 2, nz, s);
     LAUNCHCHK("full problem: solution start");
-    double rz0 = 0.0;
-    HIPCHK(hipMemcpyAsync(&rz0, r.cpc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> pc((size_t)4 * nz), stop((size_t)nz);
+    HIPCHK(hipMemcpyAsync(pc.data(), r.cpc, pc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (!isfinite(rz0)) return fail(MQH_EDEVICE, "full problem: non-finite right-hand side of the solution");
+    int open = 0;
+    for (int z = 0; z < nz; ++z) {
+        const double rz0 = pc[(size_t)4 * z + 2];
+        if (!isfinite(rz0)) return fail(MQH_EDEVICE, "full problem: non-finite right-hand side of the solution");
+        stop[(size_t)z] = kFullCgTol * kFullCgTol * rz0;
+        iters[z] = 0;
+        converged[z] = !(rz0 > 0.0);
+        open += converged[z] ? 0 : 1;
+    }
     const char* tr = getenv("MQH_TRACE_FULL");
     const bool trace = tr != nullptr && tr[0] == '1';
     int it = 0;
-    *converged = true;
-    if (rz0 > 0.0) {
-        const double stop = kFullCgTol * kFullCgTol * rz0;
-        *converged = false;
-        while (it < kFullCgMax) {
-            const int cur = 2 + (it & 1), nxt = 2 + ((it + 1) & 1);
-            launch_fs_pcg_iter(r.G, r.ldg, n, r.sig, r.rank, method, rcap, po, r.cpc, cur, nxt, y, res, r.cq, r.cw,
-                               r.ct, r.cpart, r.coef, s);
-            LAUNCHCHK("full problem: solution iteration");
-            double rz = 0.0;
-            HIPCHK(hipMemcpyAsync(&rz, r.cpc + nxt, sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            ++it;
-            if (trace && (it % 8 == 0 || it < 8))
-                fprintf(stderr, "[mqh full] cg %d sqrt(rz/rz0) %.3e\n", it, sqrt(rz / rz0));
+    while (open > 0 && it < kFullCgMax) {
+        const int cur = 2 + (it & 1), nxt = 2 + ((it + 1) & 1);
+        launch_fs_pcg_iter(r.G, r.ldg, n, r.sig, r.rank, method, rcap, po, vs, r.cpc, cur, nxt, r.cy, r.cr, r.cq,
+                           r.cw, r.ct, r.cpart, r.cx, nz, s);
+        LAUNCHCHK("full problem: solution iteration");
+        HIPCHK(hipMemcpyAsync(pc.data(), r.cpc, pc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ++it;
+        for (int z = 0; z < nz; ++z) {
+            const double rz = pc[(size_t)4 * z + nxt];
             if (!isfinite(rz)) return fail(MQH_EDEVICE, "full problem: non-finite solution iterate");
-            if (!(rz > stop)) {
-                *converged = true;
-                break;
+            if (!converged[z] && !(rz > stop[(size_t)z])) {
+                converged[z] = true;
+                iters[z] = it;
+                --open;
             }
-            launch_fs_pcg_dir(r.sig, r.rank, n, method, rcap, po, r.cpc, cur, nxt, res, r.cq, s);
         }
+        if (trace && (it % 8 == 0 || it < 8))
+            fprintf(stderr, "[mqh full] cg %d: %d of %d columns still open\n", it, open, nz);
+        if (open == 0) break;
+        launch_fs_pcg_dir(r.sig, r.rank, n, method, rcap, po, vs, r.cpc, cur, nxt, r.cr, r.cq, nz, s);
     }
-    launch_fs_gemvt(r.G, r.ldg, n, y, r.cpart, r.coef, s);
-    launch_fs_solution_norms(r.G, r.ldg, n, r.coef, fh, r.ct, r.cw, r.cpc, po, s);
+    for (int z = 0; z < nz; ++z)
+        if (!converged[z]) iters[z] = it;
+    launch_fs_gemvt(r.G, r.ldg, n, r.cy, vs, r.cpart, r.cx, nz, s);
+    launch_fs_solution_norms(r.G, r.ldg, n, r.cx, fh, vs, r.ct, r.cw, r.cpc, po, nz, s);
     LAUNCHCHK("full problem: solution");
-    *iters = it;
     return MQH_OK;
 }
 
@@ -1358,32 +1378,55 @@ int block_projected(mqh_problem* p, const std::vector<double>& C, const double* 
     if ((rc = full_sweeps(st, r, m, s))) return rc;
     *sweeps = r.sweeps;
     if (sv) HIPCHK(hipMemcpyAsync(sv, r.sv, (size_t)ls * sizeof(double), hipMemcpyDeviceToDevice, st));
-    double* fhk = nullptr;
-    if ((rc = dalloc(&fhk, (size_t)m))) return rc;
+    // the sources' data columns, their sorted order, the choices and the solutions, all at once
+    double* fh_all = nullptr;
+    double* fs_all = nullptr;
+    double* tail_all = nullptr;
+    double* fn2 = nullptr;
+    ParamOut* po_all = nullptr;
     struct Free {
-        double*& x;
-        ~Free() { dfree(x); }
-    } fr{fhk};
-    po_h.assign((size_t)s, ParamOut{});
+        double*& a;
+        double*& b;
+        double*& c;
+        double*& d;
+        ParamOut*& e;
+        ~Free() {
+            dfree(a);
+            dfree(b);
+            dfree(c);
+            dfree(d);
+            dfree(e);
+        }
+    } fr{fh_all, fs_all, tail_all, fn2, po_all};
+    if ((rc = dalloc(&fh_all, (size_t)(m * s))) || (rc = dalloc(&fs_all, (size_t)(m * s))) ||
+        (rc = dalloc(&tail_all, (size_t)((m + 1) * s))) || (rc = dalloc(&fn2, (size_t)s)) ||
+        (rc = dalloc(&po_all, (size_t)s)))
+        return rc;
+    std::vector<double> fn2h((size_t)s, 0.0);
+    for (int k = 0; k < s; ++k)
+        for (int i = 0; i < s; ++i) fn2h[(size_t)k] += E1[i * s + k] * E1[i * s + k];
+    HIPCHK(hipMemcpyAsync(fn2, fn2h.data(), (size_t)s * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_fs_col(r.G, r.ldg, m, m, m, fh_all, s, st);
+    launch_fs_rank(r.sig, fh_all, m, r.rank, r.sv, r.fs, r.order, st);
+    launch_fs_gather(r.rank, fh_all, m, m, fs_all, s, st);
+    launch_full_param(r.sv, fs_all, m, ls, fn2, m, 1, rule == MQH_RULE_FIXED ? 2 : 0, J, lambda_fixed, 0, tail_all,
+                      po_all, s, st);
+    LAUNCHCHK("block projected problem: parameter choice");
     iters.assign((size_t)s, 0);
+    std::vector<int> it((size_t)s, 0);
+    bool cv[kBlkRhs];
+    if ((rc = full_solution(st, r, m, 1, fh_all, m, po_all, ls, s, it.data(), cv))) return rc;
     conv.assign((size_t)s, 1);
     for (int k = 0; k < s; ++k) {
-        double fn2 = 0.0;
-        for (int i = 0; i < s; ++i) fn2 += E1[i * s + k] * E1[i * s + k];
-        launch_fs_col(r.G, r.ldg, m, m + k, fhk, st);
-        launch_fs_rank(r.sig, fhk, m, r.rank, r.sv, r.fs, r.order, st);
-        launch_full_param(r.sv, r.fs, m, ls, fn2, 1, rule == MQH_RULE_FIXED ? 2 : 0, J, lambda_fixed, 0, r.tail, r.po,
-                          st);
-        LAUNCHCHK("block projected problem: parameter choice");
-        bool cv = true;
-        if ((rc = full_solution(st, r, m, 1, fhk, r.po, ls, &iters[(size_t)k], &cv))) return rc;
-        conv[(size_t)k] = cv ? 1 : 0;
-        // y_k = the first ell s entries of x, into column k of Y
-        HIPCHK(hipMemcpy2DAsync(Y + k, kBlkRhs * sizeof(double), r.coef, sizeof(double), sizeof(double), (size_t)ls,
-                                hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(&po_h[(size_t)k], r.po, sizeof(ParamOut), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        iters[(size_t)k] = it[(size_t)k];
+        conv[(size_t)k] = cv[k] ? 1 : 0;
+        // y_k = the first ell s entries of x_k, into column k of Y
+        HIPCHK(hipMemcpy2DAsync(Y + k, kBlkRhs * sizeof(double), r.cx + (int64_t)k * m, sizeof(double), sizeof(double),
+                                (size_t)ls, hipMemcpyDeviceToDevice, st));
     }
+    po_h.assign((size_t)s, ParamOut{});
+    HIPCHK(hipMemcpyAsync(po_h.data(), po_all, (size_t)s * sizeof(ParamOut), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     return MQH_OK;
 }
 
@@ -2110,18 +2153,20 @@ int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, con
     for (double v : fh) fn2 += v * v;
     if (!isfinite(fn2)) return fail(MQH_EINVAL, "non-finite right-hand side");
     if ((rc = full_svd_run(p, r))) return rc;
-    launch_full_param(r.sv, r.fs, p->n, p->n, fn2, tikh ? 1 : 0, opts->rule == MQH_RULE_FIXED ? 2 : 0, J,
-                      opts->lambda_fixed, opts->k_trunc, r.tail, r.po, s);
+    if ((rc = dalloc(&r.fn2, 1))) return rc;
+    HIPCHK(hipMemcpyAsync(r.fn2, &fn2, sizeof(double), hipMemcpyHostToDevice, s));
+    launch_full_param(r.sv, r.fs, p->n, p->n, r.fn2, p->n, tikh ? 1 : 0, opts->rule == MQH_RULE_FIXED ? 2 : 0, J,
+                      opts->lambda_fixed, opts->k_trunc, r.tail, r.po, 1, s);
     LAUNCHCHK("full problem: parameter choice");
     HIPCHK(hipEventRecord(p->ev[4], s));
     int cg_iters = 0;
     bool cg_conv = true;
-    if ((rc = full_solution(s, r, p->n, tikh ? 1 : 0, r.fh, r.po, p->n, &cg_iters, &cg_conv))) return rc;
+    if ((rc = full_solution(s, r, p->n, tikh ? 1 : 0, r.fh, p->n, r.po, p->n, 1, &cg_iters, &cg_conv))) return rc;
     HIPCHK(hipEventRecord(p->ev[5], s));
     ParamOut po;
     HIPCHK(hipMemcpyAsync(&po, r.po, sizeof(ParamOut), hipMemcpyDeviceToHost, s));
     const hipMemcpyKind ko = kind_out(flags);
-    HIPCHK(hipMemcpyAsync(coef, r.coef, (size_t)p->n * sizeof(double), ko, s));
+    HIPCHK(hipMemcpyAsync(coef, r.cx, (size_t)p->n * sizeof(double), ko, s));
     if (sv) HIPCHK(hipMemcpyAsync(sv, r.sv, (size_t)p->n * sizeof(double), ko, s));
     HIPCHK(hipEventRecord(p->ev[6], s));
     HIPCHK(hipStreamSynchronize(s));

@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_rank(const double* __restrict__ s
 // Parameter choice on the full problem (eq. (25)): sv descending (n values;
 // the first r, r = the number of positive ones but at most rcap, are used),
 // fs = U^T f in the same order, s_perp = ||f||^2 - sum_{i < r} fs_i^2
-// (clamped at 0), N = n in the denominator.  Tikhonov: GCV(lambda) on J log-spaced points on
+// (clamped at 0), N = n in the denominator.  One workgroup per source.  Tikhonov: GCV(lambda) on J log-spaced points on
 // [max(sigma_r, 16 eps sigma_1), sigma_1], golden-section refinement of
 // log lambda over the two cells around the grid minimum (ties to the larger
 // lambda, a minimum at an end kept with the edge flag) -- the rule of the
@@ -394,10 +394,17 @@ __device__ double full_gcv(const double* __restrict__ sv, const double* __restri
 }
 
 __global__ __launch_bounds__(kBlock) void k_full_param(const double* __restrict__ sv, const double* __restrict__ fs,
-                                                       int64_t n, int64_t rcap, double fnorm2, int32_t method,
-                                                       int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed,
+                                                       int64_t n, int64_t rcap, const double* __restrict__ fnorm2v,
+                                                       int64_t vs, int32_t method, int32_t rule, int32_t J,
+                                                       double lambda_fixed, int32_t k_fixed,
                                                        double* __restrict__ tail, ParamOut* __restrict__ out) {
     __shared__ double lds[kBlock / kWave];
+    // source z = blockIdx.x: its data at fs + z vs, its tail at + z (n + 1), its choice at out + z
+    const int64_t z = blockIdx.x;
+    fs += z * vs;
+    tail += z * (n + 1);
+    out += z;
+    const double fnorm2 = fnorm2v[z];
     __shared__ double vals[kMaxGrid];
     __shared__ int64_t s_r;
     if (threadIdx.x == 0) {
@@ -583,31 +590,37 @@ __device__ __forceinline__ double sol_l2(int32_t method, const ParamOut* po) {
     return method == 0 ? 0.0 : po->lambda * po->lambda;
 }
 
-// y = 0, r = b (active rows), q = D^-1 r, t_i = r_i q_i.
+// Every solution kernel serves nz data columns at once (source z from the
+// grid, see each kernel): its vectors for source z start at + z vs, its
+// scalars pc at + 4 z, its choice at po + z.
+
+// y = 0, r = b (active rows), q = D^-1 r, t_i = r_i q_i.  Grid (rows, nz).
 __global__ __launch_bounds__(kBlock) void k_fs_pcg_start(const double* __restrict__ sig,
                                                          const double* __restrict__ fh,
                                                          const int32_t* __restrict__ rank, int64_t n, int32_t method,
-                                                         int64_t rcap, const ParamOut* __restrict__ po,
-                                                         double* __restrict__ y,
-                                                         double* __restrict__ r, double* __restrict__ q,
-                                                         double* __restrict__ t) {
+                                                         int64_t rcap, const ParamOut* __restrict__ po, int64_t vs,
+                                                         double* __restrict__ y, double* __restrict__ r,
+                                                         double* __restrict__ q, double* __restrict__ t) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
+    const int64_t z = blockIdx.y, o = z * vs + i;
+    po += z;
     const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k, rcap);
-    const double b = d > 0.0 ? fh[i] : 0.0;
-    y[i] = 0.0;
-    r[i] = b;
-    q[i] = d > 0.0 ? b / d : 0.0;
-    t[i] = d > 0.0 ? b * b / d : 0.0;
+    const double b = d > 0.0 ? fh[o] : 0.0;
+    y[o] = 0.0;
+    r[o] = b;
+    q[o] = d > 0.0 ? b / d : 0.0;
+    t[o] = d > 0.0 ? b * b / d : 0.0;
 }
 
-// part[c][j] = sum over the rows i of chunk c (rows < n) of q_i G[i][j]; grid
-// (columns / kBlock, chunks), one thread per column.
+// part[z][c][j] = sum over the rows i of chunk c (rows < n) of q_z[i] G[i][j];
+// grid (columns / kBlock, chunks, nz), one thread per column.
 __global__ __launch_bounds__(kBlock) void k_fs_gemvt_part(const double* __restrict__ G, int64_t ldg, int64_t n,
                                                           int64_t rows_per_chunk, const double* __restrict__ q,
-                                                          double* __restrict__ part) {
+                                                          int64_t vs, double* __restrict__ part) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
+    q += (int64_t)blockIdx.z * vs;
     const int64_t i0 = (int64_t)blockIdx.y * rows_per_chunk;
     const int64_t i1 = i0 + rows_per_chunk < n ? i0 + rows_per_chunk : n;
     double s0 = 0.0, s1 = 0.0;
@@ -617,118 +630,144 @@ __global__ __launch_bounds__(kBlock) void k_fs_gemvt_part(const double* __restri
         s1 = fma(q[i + 1], G[(i + 1) * ldg + j], s1);
     }
     if (i < i1) s0 = fma(q[i], G[i * ldg + j], s0);
-    part[(int64_t)blockIdx.y * n + j] = s0 + s1;
+    part[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * n + j] = s0 + s1;
 }
 
-// x_j = sum_c part[c][j], chunks in order.
+// x_z[j] = sum_c part[z][c][j], chunks in order; grid (columns / kBlock, nz).
 __global__ __launch_bounds__(kBlock) void k_fs_colsum(const double* __restrict__ part, int chunks, int64_t n,
-                                                      double* __restrict__ x) {
+                                                      int64_t vs, double* __restrict__ x) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
+    const int64_t z = blockIdx.y;
+    part += z * chunks * n;
     double s = 0.0;
     for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + j];
-    x[j] = s;
+    x[z * vs + j] = s;
 }
 
 // w_i = G[i] . x + lambda^2 q_i on active rows (0 elsewhere), t_i = q_i w_i;
-// one workgroup per row.
+// grid (rows, nz), one workgroup per row.
 __global__ __launch_bounds__(kBlock) void k_fs_pcg_matvec(const double* __restrict__ G, int64_t ldg, int64_t n,
                                                           const double* __restrict__ x,
                                                           const double* __restrict__ sig,
                                                           const int32_t* __restrict__ rank, int32_t method,
-                                                          int64_t rcap, const ParamOut* __restrict__ po,
+                                                          int64_t rcap, const ParamOut* __restrict__ po, int64_t vs,
                                                           const double* __restrict__ q, double* __restrict__ w,
                                                           double* __restrict__ t) {
     __shared__ double lds[kBlock / kWave];
-    const int64_t i = blockIdx.x;
+    const int64_t i = blockIdx.x, z = blockIdx.y;
+    x += z * vs;
     const double* row = G + i * ldg;
     double s = 0.0;
     for (int64_t j = threadIdx.x; j < n; j += kBlock) s = fma(row[j], x[j], s);
     s = block_sum<kBlock>(s, lds);
     if (threadIdx.x == 0) {
+        po += z;
+        const int64_t o = z * vs + i;
         const double l2 = sol_l2(method, po);
         const double d = sol_diag(sig[i], rank[i], method, l2, po->k, rcap);
-        const double wi = d > 0.0 ? s + l2 * q[i] : 0.0;
-        w[i] = wi;
-        t[i] = q[i] * wi;
+        const double wi = d > 0.0 ? s + l2 * q[o] : 0.0;
+        w[o] = wi;
+        t[o] = q[o] * wi;
     }
 }
 
-// pc[slot] = sum_i t_i (one workgroup, fixed order).
-__global__ __launch_bounds__(kBlock) void k_fs_pcg_sum(const double* __restrict__ t, int64_t n,
+// pc[4 z + slot] = sum_i t_z[i] (one workgroup per source, fixed order).
+__global__ __launch_bounds__(kBlock) void k_fs_pcg_sum(const double* __restrict__ t, int64_t n, int64_t vs,
                                                        double* __restrict__ pc, int slot) {
     __shared__ double lds[kBlock / kWave];
+    const int64_t z = blockIdx.x;
+    t += z * vs;
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += kBlock) s += t[i];
     s = block_sum<kBlock>(s, lds);
-    if (threadIdx.x == 0) pc[slot] = s;
+    if (threadIdx.x == 0) pc[4 * z + slot] = s;
 }
 
 // a = pc[cur] / pc[0] (r^T D^-1 r over q^T B q); y += a q; r -= a w;
-// t_i = r_i^2 / d_i.
+// t_i = r_i^2 / d_i.  Grid (rows, nz).
 __global__ __launch_bounds__(kBlock) void k_fs_pcg_step(const double* __restrict__ sig,
                                                         const int32_t* __restrict__ rank, int64_t n, int32_t method,
-                                                        int64_t rcap, const ParamOut* __restrict__ po,
+                                                        int64_t rcap, const ParamOut* __restrict__ po, int64_t vs,
                                                         const double* __restrict__ pc, int cur,
                                                         const double* __restrict__ q, const double* __restrict__ w,
                                                         double* __restrict__ y, double* __restrict__ r,
                                                         double* __restrict__ t) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
+    const int64_t z = blockIdx.y, o = z * vs + i;
+    po += z;
+    pc += 4 * z;
     const double qw = pc[0];
     const double a = qw > 0.0 ? pc[cur] / qw : 0.0;
     const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k, rcap);
-    y[i] = fma(a, q[i], y[i]);
-    const double ri = fma(-a, w[i], r[i]);
-    r[i] = ri;
-    t[i] = d > 0.0 ? ri * ri / d : 0.0;
+    y[o] = fma(a, q[o], y[o]);
+    const double ri = fma(-a, w[o], r[o]);
+    r[o] = ri;
+    t[o] = d > 0.0 ? ri * ri / d : 0.0;
 }
 
-// q = D^-1 r + (pc[nxt] / pc[cur]) q.
+// q = D^-1 r + (pc[nxt] / pc[cur]) q.  Grid (rows, nz).
 __global__ __launch_bounds__(kBlock) void k_fs_pcg_dir(const double* __restrict__ sig,
                                                        const int32_t* __restrict__ rank, int64_t n, int32_t method,
-                                                       int64_t rcap, const ParamOut* __restrict__ po,
+                                                       int64_t rcap, const ParamOut* __restrict__ po, int64_t vs,
                                                        const double* __restrict__ pc, int cur, int nxt,
                                                        const double* __restrict__ r, double* __restrict__ q) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
+    const int64_t z = blockIdx.y, o = z * vs + i;
+    po += z;
+    pc += 4 * z;
     const double beta = pc[cur] > 0.0 ? pc[nxt] / pc[cur] : 0.0;
     const double d = sol_diag(sig[i], rank[i], method, sol_l2(method, po), po->k, rcap);
-    q[i] = d > 0.0 ? fma(beta, q[i], r[i] / d) : 0.0;
+    q[o] = d > 0.0 ? fma(beta, q[o], r[o] / d) : 0.0;
 }
 
 // Norms of the returned solution: t_i = (G[i] . x - fh_i)^2 (one workgroup
 // per row; with Q orthogonal sum_i t_i = ||A x - f||^2, the padding rows
-// staying exactly zero), and w_i = x_i^2.
+// staying exactly zero), and w_i = x_i^2.  Grid (rows, nz).
 __global__ __launch_bounds__(kBlock) void k_fs_resid(const double* __restrict__ G, int64_t ldg, int64_t n,
                                                      const double* __restrict__ x, const double* __restrict__ fh,
-                                                     double* __restrict__ t, double* __restrict__ w) {
+                                                     int64_t vs, double* __restrict__ t, double* __restrict__ w) {
     __shared__ double lds[kBlock / kWave];
-    const int64_t i = blockIdx.x;
+    const int64_t i = blockIdx.x, z = blockIdx.y;
+    x += z * vs;
     const double* row = G + i * ldg;
     double s = 0.0;
     for (int64_t j = threadIdx.x; j < n; j += kBlock) s = fma(row[j], x[j], s);
     s = block_sum<kBlock>(s, lds);
     if (threadIdx.x == 0) {
-        const double d = s - fh[i];
-        t[i] = d * d;
-        w[i] = x[i] * x[i];
+        const double d = s - fh[z * vs + i];
+        t[z * vs + i] = d * d;
+        w[z * vs + i] = x[i] * x[i];
     }
 }
 
-// po->rho = sqrt(pc[1]), po->eta = sqrt(pc[0]).
-__global__ void k_fs_set_norms(const double* __restrict__ pc, ParamOut* __restrict__ po) {
-    if (threadIdx.x == 0) {
-        po->rho = sqrt(pc[1]);
-        po->eta = sqrt(pc[0]);
+// po[z].rho = sqrt(pc[4 z + 1]), po[z].eta = sqrt(pc[4 z]), z < nz.
+__global__ void k_fs_set_norms(const double* __restrict__ pc, ParamOut* __restrict__ po, int nz) {
+    const int z = threadIdx.x;
+    if (z < nz) {
+        po[z].rho = sqrt(pc[4 * z + 1]);
+        po[z].eta = sqrt(pc[4 * z]);
     }
 }
 
-// out_i = G[i][col], i < rows.
-__global__ __launch_bounds__(kBlock) void k_fs_col(const double* __restrict__ G, int64_t ldg, int64_t rows,
-                                                   int64_t col, double* __restrict__ out) {
+// fs_z[rank[i]] = fh_z[i] (the data columns in descending singular-value
+// order); grid (rows, nz).
+__global__ __launch_bounds__(kBlock) void k_fs_gather(const int32_t* __restrict__ rank, const double* __restrict__ fh,
+                                                      int64_t n, int64_t vs, double* __restrict__ fs) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < rows) out[i] = G[i * ldg + col];
+    if (i >= n) return;
+    const int64_t z = blockIdx.y;
+    fs[z * vs + rank[i]] = fh[z * vs + i];
+}
+
+// out[z vs + i] = G[i][col0 + z], i < rows; grid (rows, nz).
+__global__ __launch_bounds__(kBlock) void k_fs_col(const double* __restrict__ G, int64_t ldg, int64_t rows,
+                                                   int64_t col0, int64_t vs, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t z = blockIdx.y;
+    if (i < rows) out[z * vs + i] = G[i * ldg + col0 + z];
 }
 
 // G[i][n] = f_i for i < n (the f column of the work matrix).
@@ -780,10 +819,11 @@ void launch_fs_rank(const double* sig, const double* fh, int64_t n, int32_t* ran
     k_fs_rank<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(sig, fh, n, rank, sv, fs, order);
 }
 
-void launch_full_param(const double* sv, const double* fs, int64_t n, int64_t rcap, double fnorm2, int32_t method,
-                       int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double* tail, ParamOut* out,
-                       hipStream_t s) {
-    k_full_param<<<1, kBlock, 0, s>>>(sv, fs, n, rcap, fnorm2, method, rule, J, lambda_fixed, k_fixed, tail, out);
+void launch_full_param(const double* sv, const double* fs, int64_t n, int64_t rcap, const double* fnorm2v,
+                       int64_t vs, int32_t method, int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed,
+                       double* tail, ParamOut* out, int nz, hipStream_t s) {
+    k_full_param<<<(unsigned)nz, kBlock, 0, s>>>(sv, fs, n, rcap, fnorm2v, vs, method, rule, J, lambda_fixed, k_fixed,
+                                                 tail, out);
 }
 
 int fs_gemvt_chunks(int64_t n) {
@@ -796,51 +836,61 @@ int fs_gemvt_chunks(int64_t n) {
     return (int)(c < 1 ? 1 : c);
 }
 
-void launch_fs_gemvt(const double* G, int64_t ldg, int64_t n, const double* q, double* part, double* x,
-                     hipStream_t s) {
+void launch_fs_gemvt(const double* G, int64_t ldg, int64_t n, const double* q, int64_t vs, double* part, double* x,
+                     int nz, hipStream_t s) {
     const int c = fs_gemvt_chunks(n);
     const int64_t rows = (n + c - 1) / c;
     const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    k_fs_gemvt_part<<<dim3(nb, (unsigned)c), kBlock, 0, s>>>(G, ldg, n, rows, q, part);
-    k_fs_colsum<<<nb, kBlock, 0, s>>>(part, c, n, x);
+    k_fs_gemvt_part<<<dim3(nb, (unsigned)c, (unsigned)nz), kBlock, 0, s>>>(G, ldg, n, rows, q, vs, part);
+    k_fs_colsum<<<dim3(nb, (unsigned)nz), kBlock, 0, s>>>(part, c, n, vs, x);
 }
 
 void launch_fs_pcg_start(const double* sig, const double* fh, const int32_t* rank, int64_t n, int32_t method,
-                         int64_t rcap, const ParamOut* po, double* y, double* r, double* q, double* t, double* pc,
-                         int slot, hipStream_t s) {
+                         int64_t rcap, const ParamOut* po, int64_t vs, double* y, double* r, double* q, double* t,
+                         double* pc, int slot, int nz, hipStream_t s) {
     const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    k_fs_pcg_start<<<nb, kBlock, 0, s>>>(sig, fh, rank, n, method, rcap, po, y, r, q, t);
-    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, slot);
+    k_fs_pcg_start<<<dim3(nb, (unsigned)nz), kBlock, 0, s>>>(sig, fh, rank, n, method, rcap, po, vs, y, r, q, t);
+    k_fs_pcg_sum<<<(unsigned)nz, kBlock, 0, s>>>(t, n, vs, pc, slot);
 }
 
 void launch_fs_pcg_iter(const double* G, int64_t ldg, int64_t n, const double* sig, const int32_t* rank,
-                        int32_t method, int64_t rcap, const ParamOut* po, double* pc, int cur, int nxt, double* y,
-                        double* r, const double* q, double* w, double* t, double* part, double* x, hipStream_t s) {
+                        int32_t method, int64_t rcap, const ParamOut* po, int64_t vs, double* pc, int cur, int nxt,
+                        double* y, double* r, const double* q, double* w, double* t, double* part, double* x, int nz,
+                        hipStream_t s) {
     const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
-    launch_fs_gemvt(G, ldg, n, q, part, x, s);
-    k_fs_pcg_matvec<<<(unsigned)n, kBlock, 0, s>>>(G, ldg, n, x, sig, rank, method, rcap, po, q, w, t);
-    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, 0);
-    k_fs_pcg_step<<<nb, kBlock, 0, s>>>(sig, rank, n, method, rcap, po, pc, cur, q, w, y, r, t);
-    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, nxt);
+    launch_fs_gemvt(G, ldg, n, q, vs, part, x, nz, s);
+    k_fs_pcg_matvec<<<dim3((unsigned)n, (unsigned)nz), kBlock, 0, s>>>(G, ldg, n, x, sig, rank, method, rcap, po, vs,
+                                                                       q, w, t);
+    k_fs_pcg_sum<<<(unsigned)nz, kBlock, 0, s>>>(t, n, vs, pc, 0);
+    k_fs_pcg_step<<<dim3(nb, (unsigned)nz), kBlock, 0, s>>>(sig, rank, n, method, rcap, po, vs, pc, cur, q, w, y, r,
+                                                           t);
+    k_fs_pcg_sum<<<(unsigned)nz, kBlock, 0, s>>>(t, n, vs, pc, nxt);
 }
 
-void launch_fs_solution_norms(const double* G, int64_t ldg, int64_t n, const double* x, const double* fh, double* t,
-                              double* w, double* pc, ParamOut* po, hipStream_t s) {
-    k_fs_resid<<<(unsigned)n, kBlock, 0, s>>>(G, ldg, n, x, fh, t, w);
-    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(t, n, pc, 1);
-    k_fs_pcg_sum<<<1, kBlock, 0, s>>>(w, n, pc, 0);
-    k_fs_set_norms<<<1, 64, 0, s>>>(pc, po);
+void launch_fs_solution_norms(const double* G, int64_t ldg, int64_t n, const double* x, const double* fh, int64_t vs,
+                              double* t, double* w, double* pc, ParamOut* po, int nz, hipStream_t s) {
+    k_fs_resid<<<dim3((unsigned)n, (unsigned)nz), kBlock, 0, s>>>(G, ldg, n, x, fh, vs, t, w);
+    k_fs_pcg_sum<<<(unsigned)nz, kBlock, 0, s>>>(t, n, vs, pc, 1);
+    k_fs_pcg_sum<<<(unsigned)nz, kBlock, 0, s>>>(w, n, vs, pc, 0);
+    k_fs_set_norms<<<1, 64, 0, s>>>(pc, po, nz);
 }
 
 void launch_fs_pcg_dir(const double* sig, const int32_t* rank, int64_t n, int32_t method, int64_t rcap,
-                       const ParamOut* po, const double* pc, int cur, int nxt, const double* r, double* q,
-                       hipStream_t s) {
-    k_fs_pcg_dir<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(sig, rank, n, method, rcap, po, pc, cur, nxt,
-                                                                          r, q);
+                       const ParamOut* po, int64_t vs, const double* pc, int cur, int nxt, const double* r, double* q,
+                       int nz, hipStream_t s) {
+    k_fs_pcg_dir<<<dim3((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nz), kBlock, 0, s>>>(
+        sig, rank, n, method, rcap, po, vs, pc, cur, nxt, r, q);
 }
 
-void launch_fs_col(const double* G, int64_t ldg, int64_t rows, int64_t col, double* out, hipStream_t s) {
-    k_fs_col<<<(unsigned)((rows + kBlock - 1) / kBlock), kBlock, 0, s>>>(G, ldg, rows, col, out);
+void launch_fs_col(const double* G, int64_t ldg, int64_t rows, int64_t col0, int64_t vs, double* out, int nz,
+                   hipStream_t s) {
+    k_fs_col<<<dim3((unsigned)((rows + kBlock - 1) / kBlock), (unsigned)nz), kBlock, 0, s>>>(G, ldg, rows, col0, vs,
+                                                                                            out);
+}
+
+void launch_fs_gather(const int32_t* rank, const double* fh, int64_t n, int64_t vs, double* fs, int nz,
+                      hipStream_t s) {
+    k_fs_gather<<<dim3((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nz), kBlock, 0, s>>>(rank, fh, n, vs, fs);
 }
 
 }  // namespace mqh

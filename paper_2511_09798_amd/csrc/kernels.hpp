@@ -146,29 +146,38 @@ void launch_fs_maxoff(const double* off, int64_t count, double tol, double* out,
 void launch_fs_norms(const double* G, int64_t ldg, int64_t rows, int64_t n, double* sig, double* fh, hipStream_t s);
 void launch_fs_rank(const double* sig, const double* fh, int64_t n, int32_t* rank, double* sv, double* fs,
                     int32_t* order, hipStream_t s);
-void launch_full_param(const double* sv, const double* fs, int64_t n, int64_t rcap, double fnorm2, int32_t method,
-                       int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double* tail, ParamOut* out,
-                       hipStream_t s);
+// Parameter choice for nz data columns at once (one workgroup each): column
+// z's sorted data at fs + z vs, ||f_z||^2 at fnorm2v[z] (device), its tail
+// buffer at tail + z (n + 1), its choice at out + z.
+void launch_full_param(const double* sv, const double* fs, int64_t n, int64_t rcap, const double* fnorm2v,
+                       int64_t vs, int32_t method, int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed,
+                       double* tail, ParamOut* out, int nz, hipStream_t s);
 // Solutions: preconditioned conjugate gradients on (G G^T + lambda^2 I) y = f^
-// (Tikhonov) or G_k G_k^T y = f^_k (TSVD), x = G^T y.  pc holds the
-// iteration's scalars: [0] q^T B q, [2], [3] r^T D^-1 r of alternate
-// iterations.  part: fs_gemvt_chunks(n) x n doubles.
+// (Tikhonov) or G_k G_k^T y = f^_k (TSVD), x = G^T y, for nz data columns at
+// once: vectors of column z at + z vs, its scalars at pc + 4 z ([0] q^T B q,
+// [2], [3] r^T D^-1 r of alternate iterations), its choice at po + z.  part:
+// nz x fs_gemvt_chunks(n) x n doubles.
 int fs_gemvt_chunks(int64_t n);
-void launch_fs_gemvt(const double* G, int64_t ldg, int64_t n, const double* q, double* part, double* x, hipStream_t s);
+void launch_fs_gemvt(const double* G, int64_t ldg, int64_t n, const double* q, int64_t vs, double* part, double* x,
+                     int nz, hipStream_t s);
 void launch_fs_pcg_start(const double* sig, const double* fh, const int32_t* rank, int64_t n, int32_t method,
-                         int64_t rcap, const ParamOut* po, double* y, double* r, double* q, double* t, double* pc,
-                         int slot, hipStream_t s);
+                         int64_t rcap, const ParamOut* po, int64_t vs, double* y, double* r, double* q, double* t,
+                         double* pc, int slot, int nz, hipStream_t s);
 void launch_fs_pcg_iter(const double* G, int64_t ldg, int64_t n, const double* sig, const int32_t* rank,
-                        int32_t method, int64_t rcap, const ParamOut* po, double* pc, int cur, int nxt, double* y,
-                        double* r, const double* q, double* w, double* t, double* part, double* x, hipStream_t s);
-// ||A x - f|| = ||G x - f^|| and ||x|| of the returned solution into po->rho, po->eta.
-void launch_fs_solution_norms(const double* G, int64_t ldg, int64_t n, const double* x, const double* fh, double* t,
-                              double* w, double* pc, ParamOut* po, hipStream_t s);
+                        int32_t method, int64_t rcap, const ParamOut* po, int64_t vs, double* pc, int cur, int nxt,
+                        double* y, double* r, const double* q, double* w, double* t, double* part, double* x, int nz,
+                        hipStream_t s);
+// ||A x - f|| = ||G x - f^|| and ||x|| of the returned solutions into po[z].rho, po[z].eta.
+void launch_fs_solution_norms(const double* G, int64_t ldg, int64_t n, const double* x, const double* fh, int64_t vs,
+                              double* t, double* w, double* pc, ParamOut* po, int nz, hipStream_t s);
 void launch_fs_pcg_dir(const double* sig, const int32_t* rank, int64_t n, int32_t method, int64_t rcap,
-                       const ParamOut* po, const double* pc, int cur, int nxt, const double* r, double* q,
-                       hipStream_t s);
-// out_i = G[i][col] for i < rows (one data column of the work matrix)
-void launch_fs_col(const double* G, int64_t ldg, int64_t rows, int64_t col, double* out, hipStream_t s);
+                       const ParamOut* po, int64_t vs, const double* pc, int cur, int nxt, const double* r, double* q,
+                       int nz, hipStream_t s);
+// out[z vs + i] = G[i][col0 + z] for i < rows, z < nz (data columns of the work matrix)
+void launch_fs_col(const double* G, int64_t ldg, int64_t rows, int64_t col0, int64_t vs, double* out, int nz,
+                   hipStream_t s);
+// fs[z vs + rank[i]] = fh[z vs + i]: data columns in descending singular-value order
+void launch_fs_gather(const int32_t* rank, const double* fh, int64_t n, int64_t vs, double* fs, int nz, hipStream_t s);
 
 // Block Golub-Kahan (block_kernels.hip): c = V^T P through split-K partials
 // (part: blk_chunks(n, m) x m x 16, c: m x 16, row col = c + 16 col), P -= V c
