@@ -418,7 +418,11 @@ int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* 
  * on the matrix cores for MQH_OP_MATFREE_FP32 and nrhs >= 2).
  *
  * F: n x nrhs, leading dimension ldf >= n.  Needs ell >= 1, ell nrhs <= n
- * and (ell + 1) nrhs <= MQH_BLOCK_MAX_DIM.  Host or device pointers
+ * and (ell + 1) nrhs <= MQH_BLOCK_MAX_DIM.  The sources must be linearly
+ * independent to working precision: zero or repeated sources (a pivot of
+ * the QR of F that is not positive, or a diagonal entry of E_1 at most
+ * n DBL_EPSILON times its largest) are MQH_EINVAL, since W_1 would carry a
+ * direction of rounding noise.  Host or device pointers
  * (MQH_FLAG_DEVICE_PTRS in flags / opts->flags); the library allocates its
  * workspace per call.
  *

@@ -23,6 +23,9 @@ block form concrete:
   largest diagonal entry of the D and E blocks so far (E_1, the data's
   scale, left out) ends the process: at a D_j, l = j - 1 steps are kept; at
   an E_{j+1}, l = j steps with E_{j+1} = 0 (as reading 7 for one source);
+* the sources must be linearly independent to working precision: E_1 with a
+  diagonal entry at most n eps_mach times its largest (a zero or repeated
+  source) is rejected, since W_1 would carry a direction of rounding noise;
 * projected problem of source k: min ||C_l y - b_k||^2 + lambda^2 ||y||^2
   with b_k = (E_1 e_k; 0), solved through the SVD C_l = U S V^T:
   f~ = U^T b_k, y = V diag(s / (s^2 + lambda^2)) f~, coefficients Z_l y;
@@ -72,6 +75,9 @@ def block_gkb(A: np.ndarray, F: np.ndarray, ell: int) -> BlockGKB:
     """The block recurrence of the module docstring, with full reorthogonalisation."""
     n, s = F.shape
     W1, E1 = qr_pos(F)
+    d = np.abs(np.diag(E1))
+    if not float(d.min()) > n * EPS_MACH * float(d.max()):
+        raise ValueError("the sources are zero or linearly dependent")
     Ws, Zs, Ds, Es = [W1], [], [], []
     scale = 0.0
     tau = n * EPS_MACH

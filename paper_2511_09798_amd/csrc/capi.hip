@@ -1285,14 +1285,8 @@ int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vecto
     C.assign((size_t)((ell + 1) * s) * (size_t)ldc, 0.0);
     bool bad = false;
     int rc;
-    if ((rc = block_qr(p, b, b.W, s, E1, &bad))) return rc;
-    if (bad) return fail(MQH_EINVAL, "block Golub-Kahan: the right-hand sides are zero or not finite");
     const double tau = (double)n * DBL_EPSILON;
-    double scale = 0.0;
-    std::vector<double> R((size_t)s * s), Eprev((size_t)s * s, 0.0);
-    *ell_done = ell;
-    *flag = 0;
-    auto diag_range = [&](const std::vector<double>& M, double* mn, double* mx) {
+    auto diag_range = [&](const double* M, double* mn, double* mx) {
         *mn = HUGE_VAL;
         *mx = 0.0;
         for (int i = 0; i < s; ++i) {
@@ -1301,6 +1295,18 @@ int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vecto
             *mx = d > *mx ? d : *mx;
         }
     };
+    if ((rc = block_qr(p, b, b.W, s, E1, &bad))) return rc;
+    double mn, mx;
+    diag_range(E1, &mn, &mx);
+    // a zero source fails the Cholesky step; sources dependent to working precision leave E_1 a
+    // diagonal entry at the rounding level (or, by rounding, fail it too): either way W_1 would
+    // carry a direction of rounding noise, so both are rejected
+    if (bad || !(mn > tau * mx))
+        return fail(MQH_EINVAL, "block Golub-Kahan: the right-hand sides are zero or linearly dependent");
+    double scale = 0.0;
+    std::vector<double> R((size_t)s * s), Eprev((size_t)s * s, 0.0);
+    *ell_done = ell;
+    *flag = 0;
     for (int32_t j = 1; j <= ell; ++j) {
         double* Wj = b.W + (int64_t)(j - 1) * s * ldn;
         double* Zj = b.Z + (int64_t)(j - 1) * s * ldn;
@@ -1309,8 +1315,7 @@ int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vecto
         if (j > 1 && (rc = block_shift(p, b, Zj - (int64_t)s * ldn, Eprev.data(), s, true, b.P, 0))) return rc;
         block_cgs2(p, b, b.Z, (j - 1) * s, s, b.P);
         if ((rc = block_qr(p, b, b.P, s, R.data(), &bad))) return rc;
-        double mn, mx;
-        diag_range(R, &mn, &mx);
+        diag_range(R.data(), &mn, &mx);
         scale = mx > scale ? mx : scale;
         if (bad || !(mn > tau * scale)) {
             *ell_done = j - 1;
@@ -1329,7 +1334,7 @@ int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vecto
         if ((rc = block_shift(p, b, Wj, D.data(), s, false, b.P, 1))) return rc;
         block_cgs2(p, b, b.W, j * s, s, b.P);
         if ((rc = block_qr(p, b, b.P, s, R.data(), &bad))) return rc;
-        diag_range(R, &mn, &mx);
+        diag_range(R.data(), &mn, &mx);
         scale = mx > scale ? mx : scale;
         if (bad || !(mn > tau * scale)) {
             *ell_done = j;

@@ -21,6 +21,8 @@ several sources sharing one Krylov space) against the block oracle
   (1e-5), u at the oracle's lambda within 1e-3.
 * A block inside an invariant subspace breaks down after one step, as in
   the oracle; invalid arguments are rejected.
+* Permuting the sources permutes the choices and the solutions; zero and
+  linearly dependent sources are rejected, nearly dependent ones are not.
 """
 import sys
 
@@ -188,6 +190,42 @@ def test_block_breakdown_in_invariant_subspace(mq, blk, case):
     assert o.flag == 2 and o.ell == 1
     assert g["status"] == mq.MQH_WBREAKDOWN and g["flag"] == 2 and g["ell_done"] == 1
     np.testing.assert_allclose(np.sort(np.linalg.svd(g["C"][:3, :3], compute_uv=False)), np.sort(sv[:3]), rtol=1e-10)
+
+
+def test_block_source_order(mq, case, blobs):
+    # the block Krylov space depends on the span of F only: permuting the sources permutes the
+    # GCV choices and the solutions (the oracle's pin of the same property); on the GPU the
+    # Cholesky QR of the permuted block rounds differently, so to the bars of the oracle parity
+    p, A, _ = case
+    F = blobs
+    perm = np.array([3, 0, 4, 2, 1])
+    with _problem(mq, p, "stored_fp64") as pr:
+        say("block solve, sources in two orders")
+        a = pr.solve_block(F, 16)
+        b = pr.solve_block(np.ascontiguousarray(F[perm]), 16)
+    assert a.status == 0 and b.status == 0
+    np.testing.assert_allclose(b.lam, a.lam[perm], rtol=1e-6)
+    for k in range(F.shape[0]):
+        ref = a.coef[perm[k]]
+        assert np.linalg.norm(b.coef[k] - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_block_dependent_or_zero_sources_are_rejected(mq, case, blobs):
+    # as the oracle: the sources must be linearly independent to working precision
+    p, A, _ = case
+    F = blobs
+    bad = [np.stack([F[0], F[1], F[0]]), np.stack([F[0], np.zeros(p.n), F[2]]),
+           np.stack([F[0], F[1], 2.0 * F[0] - 3.0 * F[1]])]
+    with _problem(mq, p, "stored_fp64") as pr:
+        for k, G in enumerate(bad):
+            say("block, dependent or zero sources, case", k)
+            with pytest.raises(mq.MQHError):
+                pr.solve_block(np.ascontiguousarray(G), 4)
+            with pytest.raises(mq.MQHError):
+                pr.gkb_block(np.ascontiguousarray(G), 4)
+        say("block, nearly dependent sources")
+        g = pr.gkb_block(np.ascontiguousarray(np.stack([F[0], F[0] + 1e-6 * F[1]])), 4)
+    assert g["status"] == 0 and g["ell_done"] == 4
 
 
 def test_block_invalid_arguments(mq, case):

@@ -14,7 +14,7 @@ Tikhonov for several right-hand sides sharing one Krylov space).
 * the sources' order does not matter: permuting the columns of F permutes
   the solutions at fixed lambda (the block Krylov space is the same);
 * breakdown: a block F inside an invariant subspace of A A^T stops the
-  process after one step;
+  process after one step; zero or linearly dependent sources are rejected;
 * the block GCV: equal to the GCV formed from the projected influence matrix
   by dense solves (no SVD), and, for one source with a short run (large
   f~_{l+1}), to the projected HKT choice of eq. (30).
@@ -125,6 +125,17 @@ def test_breakdown_in_an_invariant_subspace(blk, small):
     assert g.flag == 2 and g.ell == 1
     assert np.all(g.C[s:, :] == 0.0)
     np.testing.assert_allclose(np.sort(np.linalg.svd(g.C[:s, :], compute_uv=False)), np.sort(sv[:s]), rtol=1e-12)
+
+
+def test_dependent_or_zero_sources_are_rejected(blk, small):
+    p, A, F = small
+    for G in (F[:, [0, 1, 0]], np.column_stack([F[:, 0], np.zeros(p.n), F[:, 2]]),
+              np.column_stack([F[:, 0], F[:, 1], 2.0 * F[:, 0] - 3.0 * F[:, 1]])):
+        with pytest.raises(ValueError):
+            blk.block_gkb(A, G, 3)
+    # nearly dependent but distinct sources are valid
+    G = np.column_stack([F[:, 0], F[:, 0] + 1e-6 * F[:, 1]])
+    assert blk.block_gkb(A, G, 3).ell == 3
 
 
 def test_block_gcv_equals_explicit_influence_matrix(orc, blk, small):
