@@ -67,11 +67,24 @@ __device__ __forceinline__ bool pair_unchanged(const int32_t* __restrict__ pair_
     return g0 >= 0 && blk_stamp[pr.x] < g0 && blk_stamp[pr.y] < g0;
 }
 
+// The 16 x 16 tiles (tr, tc), tr <= tc, of a 64 x 64 Gram matrix's upper
+// triangle: tile u = 0..9 is (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2)
+// (2,3) (3,3).
+__device__ __forceinline__ int gram_tr(int u) { return u < 4 ? 0 : u < 7 ? 1 : u < 9 ? 2 : 3; }
+__device__ __forceinline__ int gram_tc(int u) { return u < 4 ? u : u < 7 ? u - 3 : u < 9 ? u - 5 : 3; }
+constexpr int kGramTiles = 10;
+
 // Partial Gram matrices: Pg[(pair * S + chunk)][a][b] = sum over the chunk's
-// columns c < ncol of X[a][c] X[b][c].  Grid (S, pairs), 256 threads: wave w
-// forms rows 16w .. 16w + 15 of the 64 x 64 result.  Pairs left out this
-// round (pair_unchanged) write nothing.
-__global__ __launch_bounds__(kBlock) void k_fs_gram(const double* __restrict__ G, int64_t ldg, int64_t ncol,
+// columns c < ncol of X[a][c] X[b][c], for the entries of the upper-triangle
+// tiles (a / 16 <= b / 16) only: the lower tiles are left unwritten (the
+// reader takes M[a][b] = M[b][a] there).  Grid (S, pairs), 256 threads.
+// Per staged 64-column tile, wave w takes columns 16 w .. 16 w + 15 and
+// forms all 10 tiles over them: its four operand loads per 4 columns feed
+// 10 independent matrix-core chains (the operands of A and B are the same
+// rows, lane l supplying X[16 t + l % 16][k + l / 16] for tile row or
+// column t).  At the end the four waves' sums are added in LDS in wave
+// order.  Pairs left out this round (pair_unchanged) write nothing.
+__global__ __launch_bounds__(kBlock, 3) void k_fs_gram(const double* __restrict__ G, int64_t ldg, int64_t ncol,
                                                     const int32_t* __restrict__ rowidx,
                                                     const int2* __restrict__ pairs, int64_t chunk,
                                                     double* __restrict__ Pg, const int32_t* __restrict__ pair_ok,
@@ -84,28 +97,41 @@ __global__ __launch_bounds__(kBlock) void k_fs_gram(const double* __restrict__ G
     const int64_t c1 = c0 + chunk < ncol ? c0 + chunk : ncol;
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int li = lane & 15, lk = lane >> 4;
-    v4d acc[4];
+    v4d acc[kGramTiles];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < kGramTiles; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
     for (int64_t c = c0; c < c1; c += kFsRows) {
         __syncthreads();  // the previous tile has been consumed
         load_tile(G, ldg, rowidx, pr, c, c1, t);
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < kFsRows; kk += 4) {
-            const double a = t[(16 * w + li) * kFsLd + kk + lk];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double b = t[(16 * q + li) * kFsLd + kk + lk];
-                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
-            }
+        for (int kk = 16 * w; kk < 16 * w + 16; kk += 4) {
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = t[(16 * q + li) * kFsLd + kk + lk];
+#pragma unroll
+            for (int u = 0; u < kGramTiles; ++u)
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[gram_tr(u)], v[gram_tc(u)], acc[u], 0, 0, 0);
         }
     }
+    // sum over the waves in LDS (wave order), then the partial Gram's upper tiles to Pg
     double* out = Pg + ((int64_t)blockIdx.y * S + blockIdx.x) * (kFsRows * kFsRows);
+    for (int src = 0; src < kBlock / kWave; ++src) {
+        __syncthreads();  // t free (the last tile consumed) / the previous wave's sums stored
+        if (w == src) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+            for (int u = 0; u < kGramTiles; ++u)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) out[(16 * w + 4 * r + lk) * kFsRows + 16 * q + li] = acc[q][r];
+                for (int r = 0; r < 4; ++r) {
+                    const int e = (16 * gram_tr(u) + 4 * r + lk) * kFsLd + 16 * gram_tc(u) + li;
+                    const double s = src == 0 ? acc[u][r] : t[e] + acc[u][r];
+                    if (src + 1 < kBlock / kWave)
+                        t[e] = s;
+                    else
+                        out[(16 * gram_tr(u) + 4 * r + lk) * kFsRows + 16 * gram_tc(u) + li] = s;
+                }
+        }
+    }
 }
 
 // Largest |M_ab| / (max(||x_a||, ||x_b||) F) over a != b, F = ||A||_F given as
@@ -170,9 +196,10 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
     }
     const double* src = Pg + (int64_t)pair * S * (kFsRows * kFsRows);
     for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock) {
-        double v = 0.0;
-        for (int s = 0; s < S; ++s) v += src[(int64_t)s * (kFsRows * kFsRows) + e];
         const int a = e / kFsRows, b = e % kFsRows;
+        const int es = a / 16 > b / 16 ? b * kFsRows + a : e;  // k_fs_gram writes the upper tiles only
+        double v = 0.0;
+        for (int s = 0; s < S; ++s) v += src[(int64_t)s * (kFsRows * kFsRows) + es];
         M[a * kFsLd + b] = v;
         P[a * kFsLd + b] = a == b ? 1.0 : 0.0;
     }
