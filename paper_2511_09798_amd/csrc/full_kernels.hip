@@ -277,22 +277,26 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
 }
 
 // X <- P^T X on the pair's 64 rows, column tiles [kFsUpdTiles bx, kFsUpdTiles
-// (bx + 1)) of 64 columns each, of ncol (all columns, the f column included):
-// P is staged once per workgroup for its tiles.  Skipped when flag[pair] = 0.
-__global__ __launch_bounds__(kBlock) void k_fs_update(double* __restrict__ G, int64_t ldg, int64_t ncol,
+// (bx + 1)) of 64 columns each, of ncol (all columns, the f column included).
+// Each lane holds the 16 entries of P it supplies as the A operand in
+// registers for all the workgroup's tiles, so LDS holds only the staged
+// tile (four workgroups per CU).  Skipped when flag[pair] = 0.
+__global__ __launch_bounds__(kBlock, 4) void k_fs_update(double* __restrict__ G, int64_t ldg, int64_t ncol,
                                                       const int32_t* __restrict__ rowidx,
                                                       const int2* __restrict__ pairs,
                                                       const double* __restrict__ Pin,
                                                       const int32_t* __restrict__ flag) {
-    __shared__ double Pt[kFsRows * kFsLd];
     __shared__ double t[kFsRows * kFsLd];
     const int pair = blockIdx.y;
     if (flag[pair] == 0) return;  // block-uniform
     const int2 pr = pairs[pair];
     const double* P = Pin + (int64_t)pair * (kFsRows * kFsRows);
-    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock) Pt[(e / kFsRows) * kFsLd + e % kFsRows] = P[e];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int li = lane & 15, lk = lane >> 4;
+    // Y[i][c] = sum_k P[k][i] X[k][c]: A[i][k] = P[k][i] (lane: k = kk + lk, i = 16 w + li)
+    double pa[kFsRows / 4];
+#pragma unroll
+    for (int s = 0; s < kFsRows / 4; ++s) pa[s] = P[(4 * s + lk) * kFsRows + 16 * w + li];
     // the four output rows of this lane, fixed over the tiles
     int64_t orow[4];
 #pragma unroll
@@ -302,20 +306,18 @@ __global__ __launch_bounds__(kBlock) void k_fs_update(double* __restrict__ G, in
     const int64_t te = tb + kFsUpdTiles < ntile ? tb + kFsUpdTiles : ntile;
     for (int64_t tile = tb; tile < te; ++tile) {
         const int64_t c0 = tile * kFsRows;
-        __syncthreads();  // Pt staged / the previous tile's reads of t done
+        __syncthreads();  // the previous tile's reads of t done
         load_tile(G, ldg, rowidx, pr, c0, ncol, t);
         __syncthreads();
         v4d acc[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-        // Y[i][c] = sum_k P[k][i] X[k][c]: A[i][k] = P[k][i], B[k][c] = X[k][c]
-#pragma unroll 4
-        for (int kk = 0; kk < kFsRows; kk += 4) {
-            const double a = Pt[(kk + lk) * kFsLd + 16 * w + li];
+#pragma unroll
+        for (int s = 0; s < kFsRows / 4; ++s) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double b = t[(kk + lk) * kFsLd + 16 * q + li];
-                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+                const double bv = t[(4 * s + lk) * kFsLd + 16 * q + li];
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[s], bv, acc[q], 0, 0, 0);
             }
         }
 #pragma unroll
