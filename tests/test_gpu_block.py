@@ -228,6 +228,20 @@ def test_block_dependent_or_zero_sources_are_rejected(mq, case, blobs):
     assert g["status"] == 0 and g["ell_done"] == 4
 
 
+def test_block_size_limits(mq):
+    # (ell + 1) nrhs at the limit MQH_BLOCK_MAX_DIM passes the argument check, one more step does not;
+    # n = 8 200 nodes so that ell nrhs <= n holds on both sides (matrix-free: nothing of size n^2)
+    X = I.random_nodes_cube(8200, 31)
+    f = np.stack([I.random_vector(8200, 40 + k) for k in range(2)])
+    with mq.Problem(X[:7000], X[7000:], 2.0, 1.5, "matfree_fp32") as pr:
+        ell_max = mq.MQH_BLOCK_MAX_DIM // 2 - 1
+        say("block size limit: ell", ell_max + 1, "nrhs 2 rejected")
+        with pytest.raises(mq.MQHError):
+            pr.gkb_block(f, ell_max + 1)
+        with pytest.raises(mq.MQHError):
+            pr.solve_block(f, ell_max + 1)
+
+
 def test_block_invalid_arguments(mq, case):
     p, A, F = case
     with _problem(mq, p, "stored_fp64") as pr:

@@ -20,11 +20,14 @@ of a small multiple of that level (measured: 2.7x at 523 nodes, 6.8x at
   is ~0.1, so rounding at 1e-13 fixes the argmin to ~1e-6) and exactly;
 * the choices and solutions end to end against the oracle's LAPACK SVD, on
   data with seeded noise of 1e-2 relative, with bars from the oracle's own
-  sensitivity to a backward error of size tau (the oracle on A + E, E random
-  with ||E|| = tau, at 1 800 nodes: GCV at its lambda within 5e-7 of the
-  minimum, lambda within 2e-3, the rank unchanged, u within 1.3e-5, the
-  residual norm within 1.3e-4): GCV within 1e-6 of the minimum, lambda to
-  1e-2, the TSVD rank exactly (the runner-up's GCV lies 3e-3 above the
+  sensitivity to a backward error (the oracle on A + E, E random, at 1 800
+  nodes, where tau = 5 500 eps sigma_1; 8 draws per size): ||E|| = 3 000
+  eps sigma_1 moves lambda by up to 3.4e-3 and GCV at it by up to 1.1e-6,
+  ||E|| = 10 000 eps sigma_1 by up to 1.7e-2 and 2.8e-5; the rank stays, u
+  moves by about 1e-5 and the residual norm by 1e-4.  Bars: GCV within 1e-6
+  of the minimum and lambda to 1e-2 (the sensitivity at about tau / 2, so
+  tighter than the singular-value bar alone implies; measured 3.7e-7 and
+  1.9e-3), the TSVD rank exactly (the runner-up's GCV lies 3e-3 above the
   minimum), u at the oracle's lambda or rank to 1e-4, coefficients to
   tau / lambda (Tikhonov) or tau / sigma_k (TSVD), the first-order
   amplification of a backward error, and ||A x - f|| to 1e-3.
@@ -33,7 +36,8 @@ of a small multiple of that level (measured: 2.7x at 523 nodes, 6.8x at
   property of the problem; at 1e-2 noise it is.
 At the full 20 000-node cube (in the launch configuration of the benchmark)
 the Tikhonov solution is checked against the normal equations
-(A^T A + lambda^2 I) x = A^T f with the oracle's own FP64 products.
+(A^T A + lambda^2 I) x = A^T f with the oracle's own FP64 products.  n above
+MQH_FULL_MAX_N is rejected.
 """
 import sys
 
@@ -216,6 +220,19 @@ def test_full_small_and_invalid(mq, orc):
             pr.full_solve(f[:14], f[14:], rule=mq.MQH_RULE_LCURVE)
         with pytest.raises(mq.MQHError):
             pr.full_solve(f[:14], f[14:], method=mq.MQH_METHOD_INE_TSVD, rule=mq.MQH_RULE_FIXED, k_trunc=0)
+
+
+def test_full_size_limit(mq):
+    # n = MQH_FULL_MAX_N + 1 is rejected before anything of size n^2 is allocated
+    n = mq.MQH_FULL_MAX_N + 1
+    X = I.random_nodes_cube(n, 32)
+    f = I.random_vector(n, 33)
+    with mq.Problem(X[:n - 4000], X[n - 4000:], 2.0, 1.5, "matfree_fp32") as pr:
+        say("full svd n", n, "rejected")
+        with pytest.raises(mq.MQHError):
+            pr.full_svd(f)
+        with pytest.raises(mq.MQHError):
+            pr.full_solve(f[:n - 4000], f[n - 4000:])
 
 
 def test_full_size_cube_normal_equations(mq, orc):
