@@ -838,6 +838,8 @@ struct FullRun {
     double* cpart = nullptr;
     double* cpc = nullptr;
     double* fn2 = nullptr;
+    int cz = 0;     // data columns the solution buffers were allocated for
+    size_t cv = 0;  // and their length in doubles (columns times spacing)
     int32_t* pair_ok = nullptr;    // per schedule slot: round at which the pair was last found orthogonal, or -1
     int32_t* blk_stamp = nullptr;  // per block: round of its last rotation, or -1
     int sweeps = 0;
@@ -1069,12 +1071,17 @@ int full_solution(hipStream_t s, FullRun& r, int64_t n, int32_t method, const do
                   int64_t rcap, int nz, int* iters, bool* converged) {
     int rc;
     const int chunks = fs_gemvt_chunks(n);
+    if (vs < n) return fail(MQH_EINVAL, "full problem: solution columns closer than n apart");
+    const size_t v = (size_t)vs * (size_t)nz;
+    if (r.cq != nullptr && (r.cz < nz || r.cv < v))
+        return fail(MQH_EINVAL, "full problem: more solution columns than allocated");
     if (r.cq == nullptr) {
-        const size_t v = (size_t)vs * (size_t)nz;
         if ((rc = dalloc(&r.cy, v)) || (rc = dalloc(&r.cr, v)) || (rc = dalloc(&r.cq, v)) || (rc = dalloc(&r.cw, v)) ||
             (rc = dalloc(&r.ct, v)) || (rc = dalloc(&r.cx, v)) ||
             (rc = dalloc(&r.cpart, (size_t)nz * (size_t)chunks * (size_t)n)) || (rc = dalloc(&r.cpc, 4 * (size_t)nz)))
             return rc;
+        r.cz = nz;
+        r.cv = v;
     }
     launch_fs_pcg_start(r.sig, fh, r.rank, n, method, rcap, po, vs, r.cy, r.cr, r.cq, r.ct, r.cpc, 2, nz, s);
     LAUNCHCHK("full problem: solution start");
