@@ -84,7 +84,7 @@ constexpr int kGramTiles = 10;
 // rows, lane l supplying X[16 t + l % 16][k + l / 16] for tile row or
 // column t).  At the end the four waves' sums are added in LDS in wave
 // order.  Pairs left out this round (pair_unchanged) write nothing.
-__global__ __launch_bounds__(kBlock, 3) void k_fs_gram(const double* __restrict__ G, int64_t ldg, int64_t ncol,
+__global__ __launch_bounds__(kBlock, 2) void k_fs_gram(const double* __restrict__ G, int64_t ldg, int64_t ncol,
                                                     const int32_t* __restrict__ rowidx,
                                                     const int2* __restrict__ pairs, int64_t chunk,
                                                     double* __restrict__ Pg, const int32_t* __restrict__ pair_ok,
@@ -100,10 +100,26 @@ __global__ __launch_bounds__(kBlock, 3) void k_fs_gram(const double* __restrict_
     v4d acc[kGramTiles];
 #pragma unroll
     for (int u = 0; u < kGramTiles; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    // software pipeline: the next tile's loads are in flight (registers) while
+    // this tile's products run from LDS
+    constexpr int kQ = kFsRows / (kBlock / kWave);  // rows loaded per lane
+    const int lc = threadIdx.x & (kWave - 1), lr = threadIdx.x / kWave;
+    int64_t rowoff[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) rowoff[q] = pair_row(rowidx, pr, lr + (kBlock / kWave) * q) * ldg;
+    double nxt[kQ];
+    auto fetch = [&](int64_t cc) {
+        const bool ok = cc < c1 && cc + lc < c1;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) nxt[q] = ok ? G[rowoff[q] + cc + lc] : 0.0;
+    };
+    fetch(c0);
     for (int64_t c = c0; c < c1; c += kFsRows) {
         __syncthreads();  // the previous tile has been consumed
-        load_tile(G, ldg, rowidx, pr, c, c1, t);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) t[(lr + (kBlock / kWave) * q) * kFsLd + lc] = nxt[q];
         __syncthreads();
+        fetch(c + kFsRows);
 #pragma unroll
         for (int kk = 16 * w; kk < 16 * w + 16; kk += 4) {
             double v[4];
@@ -281,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
 // Each lane holds the 16 entries of P it supplies as the A operand in
 // registers for all the workgroup's tiles, so LDS holds only the staged
 // tile (four workgroups per CU).  Skipped when flag[pair] = 0.
-__global__ __launch_bounds__(kBlock, 4) void k_fs_update(double* __restrict__ G, int64_t ldg, int64_t ncol,
+__global__ __launch_bounds__(kBlock, 3) void k_fs_update(double* __restrict__ G, int64_t ldg, int64_t ncol,
                                                       const int32_t* __restrict__ rowidx,
                                                       const int2* __restrict__ pairs,
                                                       const double* __restrict__ Pin,
@@ -304,11 +320,29 @@ __global__ __launch_bounds__(kBlock, 4) void k_fs_update(double* __restrict__ G,
     const int64_t ntile = (ncol + kFsRows - 1) / kFsRows;
     const int64_t tb = (int64_t)blockIdx.x * kFsUpdTiles;
     const int64_t te = tb + kFsUpdTiles < ntile ? tb + kFsUpdTiles : ntile;
+    // software pipeline: the next tile's loads are in flight (registers) while
+    // this tile's products run from LDS (the tiles' columns are disjoint, so
+    // the in-place stores never meet a pending load)
+    constexpr int kQ = kFsRows / (kBlock / kWave);  // rows loaded per lane
+    const int lc = threadIdx.x & (kWave - 1), lr = threadIdx.x / kWave;
+    int64_t rowoff[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) rowoff[q] = pair_row(rowidx, pr, lr + (kBlock / kWave) * q) * ldg;
+    double nxt[kQ];
+    auto fetch = [&](int64_t tl) {
+        const int64_t cc = tl * kFsRows;
+        const bool ok = tl < te && cc + lc < ncol;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) nxt[q] = ok ? G[rowoff[q] + cc + lc] : 0.0;
+    };
+    fetch(tb);
     for (int64_t tile = tb; tile < te; ++tile) {
         const int64_t c0 = tile * kFsRows;
         __syncthreads();  // the previous tile's reads of t done
-        load_tile(G, ldg, rowidx, pr, c0, ncol, t);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) t[(lr + (kBlock / kWave) * q) * kFsLd + lc] = nxt[q];
         __syncthreads();
+        fetch(tile + 1);
         v4d acc[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
