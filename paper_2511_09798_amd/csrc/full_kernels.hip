@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
 // (bx + 1)) of 64 columns each, of ncol (all columns, the f column included).
 // Each lane holds the 16 entries of P it supplies as the A operand in
 // registers for all the workgroup's tiles, so LDS holds only the staged
-// tile (four workgroups per CU).  Skipped when flag[pair] = 0.
+// tile.  Skipped when flag[pair] = 0.
 __global__ __launch_bounds__(kBlock, 3) void k_fs_update(double* __restrict__ G, int64_t ldg, int64_t ncol,
                                                       const int32_t* __restrict__ rowidx,
                                                       const int2* __restrict__ pairs,
