@@ -228,6 +228,16 @@ def test_block_dependent_or_zero_sources_are_rejected(mq, case, blobs):
     assert g["status"] == 0 and g["ell_done"] == 4
 
 
+def test_block_deterministic(mq, case, blobs):
+    # fixed-order reductions throughout: a repeated call returns the same bits
+    p, A, _ = case
+    with _problem(mq, p, "matfree_fp32") as pr:
+        say("block determinism")
+        a = pr.solve_block(blobs, 16)
+        b = pr.solve_block(blobs, 16)
+    assert np.array_equal(a.coef, b.coef) and np.array_equal(a.lam, b.lam)
+
+
 def test_block_size_limits(mq):
     # (ell + 1) nrhs at the limit MQH_BLOCK_MAX_DIM passes the argument check, one more step does not;
     # n = 8 200 nodes so that ell nrhs <= n holds on both sides (matrix-free: nothing of size n^2)

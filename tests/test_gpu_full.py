@@ -222,6 +222,17 @@ def test_full_small_and_invalid(mq, orc):
             pr.full_solve(f[:14], f[14:], method=mq.MQH_METHOD_INE_TSVD, rule=mq.MQH_RULE_FIXED, k_trunc=0)
 
 
+def test_full_deterministic(mq):
+    # fixed-order reductions and a fixed schedule: a repeated call returns the same bits
+    p = I.cube_scaled(333, 190, kappa=6.0, eps=2.0, ell=40)
+    f, fi, gb = _noisy(p)
+    with _problem(mq, p) as pr:
+        say("full determinism")
+        a = pr.full_solve(fi, gb)
+        b = pr.full_solve(fi, gb)
+    assert np.array_equal(a.coef, b.coef) and a.lam == b.lam and np.array_equal(a.sv, b.sv)
+
+
 def test_full_size_limit(mq):
     # n = MQH_FULL_MAX_N + 1 is rejected before anything of size n^2 is allocated
     n = mq.MQH_FULL_MAX_N + 1
