@@ -838,6 +838,7 @@ struct FullRun {
     double* cpart = nullptr;
     double* cpc = nullptr;
     double* fn2 = nullptr;
+    int inner = 1;  // cyclic Jacobi sweeps per pair and round (at most): kFullMaxInner, or 2 when small
     int cz = 0;     // data columns the solution buffers were allocated for
     size_t cv = 0;  // and their length in doubles (columns times spacing)
     int32_t* pair_ok = nullptr;    // per schedule slot: round at which the pair was last found orthogonal, or -1
@@ -885,6 +886,13 @@ constexpr int kFullMaxSweeps = 100;
 // and the outer sweeps barely grow (33 -> 36 at n = 5 000) while a round's
 // eigensolver time falls several-fold.
 constexpr int kFullMaxInner = 1;
+// Small matrices (at most kFullSmallBlocks blocks of 32 rows, as the
+// projected problems of the block Golub-Kahan path) take two: there the
+// eigensolver is the whole cost of a round, and two sweeps per pair halve the
+// outer sweeps (measured on 16-source projected problems: 4 blocks 17 -> 7
+// sweeps, 9.7 -> 6.1 ms; 10 blocks 19 -> 11, 28.9 -> 27.9 ms; 14 blocks
+// 18 -> 13 but 40 -> 48 ms).
+constexpr int kFullSmallBlocks = 10;
 // Orthogonality levels of the Jacobi sweeps (relative to ||A||_F): the target
 // full_tol(n), and full_floor(n) = twice that.  The measure, computed from
 // FP64 Gram entries over n columns, stalls at 16 .. 20 sqrt(n) eps (measured
@@ -912,6 +920,7 @@ int full_prepare(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
     r.nrow = (int64_t)r.nblk * kFsBlock;
     r.npairs = r.nblk / 2;
     r.rounds = r.nblk - 1;
+    r.inner = r.nblk <= kFullSmallBlocks ? 2 : kFullMaxInner;
     {
         int64_t S = (2048 + r.npairs - 1) / r.npairs;
         const int64_t smax = (n + 63) / 64;
@@ -1006,7 +1015,7 @@ int full_sweeps(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
             const int32_t g = sw * r.rounds + rd;
             launch_fs_gram(r.G, r.ldg, n, r.rowidx, prd, r.npairs, r.S, r.chunk, r.Pg, r.pair_ok, r.blk_stamp, slot0,
                            same, s);
-            launch_fs_eig(r.Pg, r.S, r.npairs, tol, inv_f, kFullMaxInner, r.Pout, r.flag, r.off + slot0, prd,
+            launch_fs_eig(r.Pg, r.S, r.npairs, tol, inv_f, r.inner, r.Pout, r.flag, r.off + slot0, prd,
                           r.pair_ok, r.blk_stamp, slot0, g, same, s);
             launch_fs_update(r.G, r.ldg, n + nrhs, r.rowidx, prd, r.npairs, r.Pout, r.flag, s);
         }
