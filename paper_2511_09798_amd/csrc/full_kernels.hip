@@ -150,6 +150,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_fs_gram(const double* __restrict_
     }
 }
 
+// Threads of the pair eigensolver: the rotation steps are chains of LDS
+// accesses, so more threads per pair shorten each step (one 2 x 2 block of M
+// and two column pairs of P per thread).
+constexpr int kEigThreads = 1024;
+
 // Largest |M_ab| / (max(||x_a||, ||x_b||) F) over a != b, F = ||A||_F given as
 // inv_f = 1 / F (block-wide, every thread gets it): the component of the
 // smaller row along the larger one relative to the matrix's norm.  Below
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_fs_gram(const double* __restrict_
 // sweep renews.  M in LDS with row length kFsLd.
 __device__ double offdiag(const double* __restrict__ M, double inv_f, double* __restrict__ red) {
     double mx = 0.0;
-    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock) {
+    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kEigThreads) {
         const int a = e / kFsRows, b = e % kFsRows;
         if (a == b) continue;
         const double ma = M[a * kFsLd + a], mb = M[b * kFsLd + b];
@@ -177,7 +182,7 @@ __device__ double offdiag(const double* __restrict__ M, double inv_f, double* __
     if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = mx;
     __syncthreads();
     double r = 0.0;
-    for (int i = 0; i < kBlock / kWave; ++i) r = red[i] > r ? red[i] : r;
+    for (int i = 0; i < kEigThreads / kWave; ++i) r = red[i] > r ? red[i] : r;
     __syncthreads();
     return r;
 }
@@ -191,7 +196,7 @@ __device__ double offdiag(const double* __restrict__ M, double inv_f, double* __
 // skipped when |M_pq| <= eps/4 sqrt(M_pp M_qq); until the measure is below
 // eps or max_inner sweeps) gives P^T M P (nearly) diagonal, and P goes to
 // Pout[pair] with flag[pair] = 1; else flag 0.
-__global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg, int S, double tol, double inv_f,
+__global__ __launch_bounds__(kEigThreads) void k_fs_eig(const double* __restrict__ Pg, int S, double tol, double inv_f,
                                                    int max_inner, double* __restrict__ Pout,
                                                    int32_t* __restrict__ flag, double* __restrict__ off,
                                                    const int2* __restrict__ pairs, int32_t* __restrict__ pair_ok,
@@ -199,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
                                                    int same) {
     __shared__ double M[kFsRows * kFsLd];
     __shared__ double P[kFsRows * kFsLd];
-    __shared__ double red[kBlock / kWave];
+    __shared__ double red[kEigThreads / kWave];
     __shared__ double rc[kFsRows / 2], rs[kFsRows / 2];
     __shared__ int rp[kFsRows / 2], rq[kFsRows / 2];
     const int pair = blockIdx.x;
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
         return;
     }
     const double* src = Pg + (int64_t)pair * S * (kFsRows * kFsRows);
-    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock) {
+    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kEigThreads) {
         const int a = e / kFsRows, b = e % kFsRows;
         const int es = a / 16 > b / 16 ? b * kFsRows + a : e;  // k_fs_gram writes the upper tiles only
         double v = 0.0;
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
             // 2 x 2 blocks (rows {p_a, q_a}, columns {p_b, q_b}), each updated on
             // its own (rows first, then columns, as two separate passes would);
             // P <- P J beside it
-            for (int e = threadIdx.x; e < (kFsRows / 2) * (kFsRows / 2); e += kBlock) {
+            for (int e = threadIdx.x; e < (kFsRows / 2) * (kFsRows / 2); e += kEigThreads) {
                 const int ka = e / (kFsRows / 2), kb = e % (kFsRows / 2);
                 const int pa = rp[ka], qa = rq[ka], pb = rp[kb], qb = rq[kb];
                 const double ca = rc[ka], sa = rs[ka], cb = rc[kb], sb = rs[kb];
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
                 M[qa * kFsLd + pb] = cb * r10 - sb * r11;
                 M[qa * kFsLd + qb] = sb * r10 + cb * r11;
             }
-            for (int e = threadIdx.x; e < (kFsRows / 2) * kFsRows; e += kBlock) {
+            for (int e = threadIdx.x; e < (kFsRows / 2) * kFsRows; e += kEigThreads) {
                 const int k = e / kFsRows, i = e % kFsRows;
                 const int p = rp[k], q = rq[k];
                 const double c = rc[k], s = rs[k];
@@ -287,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void k_fs_eig(const double* __restrict__ Pg
         if (sweep + 1 < max_inner && !(offdiag(M, inv_f, red) > tol_in)) break;
     }
     double* dst = Pout + (int64_t)pair * (kFsRows * kFsRows);
-    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kBlock)
+    for (int e = threadIdx.x; e < kFsRows * kFsRows; e += kEigThreads)
         dst[e] = P[(e / kFsRows) * kFsLd + e % kFsRows];
     if (threadIdx.x == 0) flag[pair] = 1;
 }
@@ -858,7 +863,7 @@ void launch_fs_gram(const double* G, int64_t ldg, int64_t ncol, const int32_t* r
 void launch_fs_eig(const double* Pg, int S, int npairs, double tol, double inv_f, int max_inner, double* Pout,
                    int32_t* flag, double* off, const int2* pairs, int32_t* pair_ok, int32_t* blk_stamp, int64_t slot0,
                    int32_t g, int same, hipStream_t s) {
-    k_fs_eig<<<(unsigned)npairs, kBlock, 0, s>>>(Pg, S, tol, inv_f, max_inner, Pout, flag, off, pairs, pair_ok,
+    k_fs_eig<<<(unsigned)npairs, kEigThreads, 0, s>>>(Pg, S, tol, inv_f, max_inner, Pout, flag, off, pairs, pair_ok,
                                                  blk_stamp, slot0, g, same);
 }
 
