@@ -82,6 +82,22 @@ bool all_finite(const double* x, int64_t n) {
 hipMemcpyKind kind_in(uint32_t flags) { return (flags & MQH_FLAG_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
 hipMemcpyKind kind_out(uint32_t flags) { return (flags & MQH_FLAG_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
 
+// height columns of width bytes, dpitch / spitch bytes apart.  Copies that
+// touch host memory go column by column: 2D copies between pageable host
+// memory and the device returned wrong data under a kernel tracer on this
+// runtime (the first one right, later ones zeros or stale values), while
+// plain copies did not.  Device-to-device copies stay 2D.
+hipError_t copy_strided(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t height,
+                     hipMemcpyKind kind, hipStream_t s) {
+    if (kind == hipMemcpyDeviceToDevice) return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, height, kind, s);
+    for (size_t c = 0; c < height; ++c) {
+        const hipError_t e = hipMemcpyAsync(static_cast<char*>(dst) + c * dpitch,
+                                            static_cast<const char*>(src) + c * spitch, width, kind, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Small device-to-host results of a solve, in pinned memory.
 struct HostResults {
     GkbState st;
@@ -792,7 +808,7 @@ int stage_multi(mqh_problem* p, const double* F, int64_t ldf, int k0, int nz, ui
     if (!(flags & MQH_FLAG_DEVICE_PTRS))
         for (int k = 0; k < nz; ++k)
             if (!all_finite(F + (int64_t)(k0 + k) * ldf, n)) return fail(MQH_EINVAL, "non-finite right-hand side");
-    HIPCHK(hipMemcpy2DAsync(w.X, (size_t)p->ldn * sizeof(double), F + (int64_t)k0 * ldf, (size_t)ldf * sizeof(double),
+    HIPCHK(copy_strided(w.X, (size_t)p->ldn * sizeof(double), F + (int64_t)k0 * ldf, (size_t)ldf * sizeof(double),
                             (size_t)n * sizeof(double), (size_t)nz, kind_in(flags), p->stream));
     return MQH_OK;
 }
@@ -1442,7 +1458,7 @@ int block_projected(mqh_problem* p, const std::vector<double>& C, const double* 
         iters[(size_t)k] = it[(size_t)k];
         conv[(size_t)k] = cv[k] ? 1 : 0;
         // y_k = the first ell s entries of x_k, into column k of Y
-        HIPCHK(hipMemcpy2DAsync(Y + k, kBlkRhs * sizeof(double), r.cx + (int64_t)k * m, sizeof(double), sizeof(double),
+        HIPCHK(copy_strided(Y + k, kBlkRhs * sizeof(double), r.cx + (int64_t)k * m, sizeof(double), sizeof(double),
                                 (size_t)ls, hipMemcpyDeviceToDevice, st));
     }
     po_h.assign((size_t)s, ParamOut{});
@@ -1468,7 +1484,7 @@ int stage_block(mqh_problem* p, BlockWs& b, const double* F, int64_t ldf, int32_
         for (int32_t k = 0; k < nrhs; ++k)
             if (!all_finite(F + (int64_t)k * ldf, p->n)) return fail(MQH_EINVAL, "non-finite right-hand side");
     }
-    HIPCHK(hipMemcpy2DAsync(b.W, (size_t)p->ldn * sizeof(double), F, (size_t)ldf * sizeof(double),
+    HIPCHK(copy_strided(b.W, (size_t)p->ldn * sizeof(double), F, (size_t)ldf * sizeof(double),
                             (size_t)p->n * sizeof(double), (size_t)nrhs, kind_in(flags), p->stream));
     return MQH_OK;
 }
@@ -1690,7 +1706,7 @@ int mqh_matrix_rows(mqh_problem* p, int64_t row0, int64_t count, double* out, ui
         double* dst = dev ? out + (r - row0) * p->n : tmp;
         hipError_t e;
         if (p->mode == MQH_OP_STORED_FP64) {
-            e = hipMemcpy2DAsync(dst, (size_t)p->n * sizeof(double), p->A + r * p->lda, (size_t)p->lda * sizeof(double),
+            e = copy_strided(dst, (size_t)p->n * sizeof(double), p->A + r * p->lda, (size_t)p->lda * sizeof(double),
                                  (size_t)p->n * sizeof(double), (size_t)c, hipMemcpyDeviceToDevice, p->stream);
         } else {
             launch_gen_rows(p->mode == MQH_OP_MATFREE_FP64 ? 64 : 32,
@@ -1734,7 +1750,7 @@ int mqh_gkb(mqh_problem* p, const double* f, int32_t ell, int32_t reorth, double
     auto copy_cols = [&](double* dst, const double* src, int32_t total, int32_t valid) -> int {
         if (dst == nullptr) return MQH_OK;
         if (valid > 0)
-            HIPCHK(hipMemcpy2DAsync(dst, (size_t)n * sizeof(double), src, (size_t)p->ldn * sizeof(double),
+            HIPCHK(copy_strided(dst, (size_t)n * sizeof(double), src, (size_t)p->ldn * sizeof(double),
                                     (size_t)n * sizeof(double), (size_t)valid, ko, p->stream));
         if (total > valid) {
             if (flags & MQH_FLAG_DEVICE_PTRS) {
@@ -1873,7 +1889,7 @@ int mqh_apply_multi(mqh_problem* p, int32_t trans, const double* X, int64_t ldx,
             if (!(flags & MQH_FLAG_DEVICE_PTRS))
                 for (int k = 0; k < nz; ++k)
                     if (!all_finite(Zs + (int64_t)(k0 + k) * ldz, p->n)) return fail(MQH_EINVAL, "non-finite z");
-            HIPCHK(hipMemcpy2DAsync(w.Z, (size_t)w.bstr * sizeof(double), Zs + (int64_t)k0 * ldz,
+            HIPCHK(copy_strided(w.Z, (size_t)w.bstr * sizeof(double), Zs + (int64_t)k0 * ldz,
                                     (size_t)ldz * sizeof(double), (size_t)p->n * sizeof(double), (size_t)nz,
                                     kind_in(flags), s));
             zs = w.Z;
@@ -1885,7 +1901,7 @@ int mqh_apply_multi(mqh_problem* p, int32_t trans, const double* X, int64_t ldx,
         HIPCHK(hipMemcpyAsync(w.alpha, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
         if ((rc = block_product(p, nz, trans, w.X, p->ldn, w.alpha, w.vstr, zs, w.bstr, w.Y, nullptr, false)))
             return rc;
-        HIPCHK(hipMemcpy2DAsync(Y + (int64_t)k0 * ldy, (size_t)ldy * sizeof(double), w.Y,
+        HIPCHK(copy_strided(Y + (int64_t)k0 * ldy, (size_t)ldy * sizeof(double), w.Y,
                                 (size_t)p->ldn * sizeof(double), (size_t)p->n * sizeof(double), (size_t)nz,
                                 kind_out(flags), s));
         HIPCHK(hipStreamSynchronize(s));  // sh lives until the copy has run
@@ -1917,7 +1933,7 @@ int mqh_gkb_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, in
         std::vector<GkbState> st((size_t)nz);
         std::vector<double> b1((size_t)nz);
         HIPCHK(hipMemcpyAsync(st.data(), w.st, (size_t)nz * sizeof(GkbState), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpy2DAsync(b1.data(), sizeof(double), w.beta, (size_t)w.vstr * sizeof(double), sizeof(double),
+        HIPCHK(copy_strided(b1.data(), sizeof(double), w.beta, (size_t)w.vstr * sizeof(double), sizeof(double),
                                 (size_t)nz, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int k = 0; k < nz; ++k)
@@ -1929,7 +1945,7 @@ int mqh_gkb_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, in
             auto copy_cols = [&](double* dst, const double* src, int32_t total, int32_t valid) -> int {
                 if (dst == nullptr) return MQH_OK;
                 if (valid > 0)
-                    HIPCHK(hipMemcpy2DAsync(dst, (size_t)n * sizeof(double), src, (size_t)p->ldn * sizeof(double),
+                    HIPCHK(copy_strided(dst, (size_t)n * sizeof(double), src, (size_t)p->ldn * sizeof(double),
                                             (size_t)n * sizeof(double), (size_t)valid, ko, s));
                 if (total > valid) {
                     if (dev) {
@@ -2021,14 +2037,14 @@ int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
         HIPCHK(hipMemcpyAsync(st.data(), w.st, (size_t)nz * sizeof(GkbState), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(po.data(), w.pout, (size_t)nz * sizeof(ParamOut), hipMemcpyDeviceToHost, s));
         if (!lsqr) HIPCHK(hipMemcpyAsync(svs.data(), w.status, (size_t)nz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpy2DAsync(b1.data(), sizeof(double), w.beta, (size_t)w.vstr * sizeof(double), sizeof(double),
+        HIPCHK(copy_strided(b1.data(), sizeof(double), w.beta, (size_t)w.vstr * sizeof(double), sizeof(double),
                                 (size_t)nz, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int k = 0; k < nz; ++k) {
             if (!isfinite(b1[(size_t)k])) return fail(MQH_EINVAL, "non-finite right-hand side");
             if (svs[(size_t)k] != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
         }
-        HIPCHK(hipMemcpy2DAsync(coef + (int64_t)k0 * ldc, (size_t)ldc * sizeof(double), w.coef,
+        HIPCHK(copy_strided(coef + (int64_t)k0 * ldc, (size_t)ldc * sizeof(double), w.coef,
                                 (size_t)p->ldn * sizeof(double), (size_t)p->n * sizeof(double), (size_t)nz, ko, s));
         HIPCHK(hipEventRecord(p->ev[6], s));
         HIPCHK(hipStreamSynchronize(s));
@@ -2237,10 +2253,10 @@ int mqh_gkb_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, in
         HIPCHK(hipMemcpyAsync(E1, E1h, (size_t)nrhs * nrhs * sizeof(double),
                               (flags & MQH_FLAG_DEVICE_PTRS) ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st));
     if (W)
-        HIPCHK(hipMemcpy2DAsync(W, (size_t)n * sizeof(double), b.W, (size_t)ldn * sizeof(double), (size_t)n * sizeof(double),
+        HIPCHK(copy_strided(W, (size_t)n * sizeof(double), b.W, (size_t)ldn * sizeof(double), (size_t)n * sizeof(double),
                                 (size_t)(ell + 1) * nrhs, ko, st));
     if (Z)
-        HIPCHK(hipMemcpy2DAsync(Z, (size_t)n * sizeof(double), b.Z, (size_t)ldn * sizeof(double), (size_t)n * sizeof(double),
+        HIPCHK(copy_strided(Z, (size_t)n * sizeof(double), b.Z, (size_t)ldn * sizeof(double), (size_t)n * sizeof(double),
                                 (size_t)ell * nrhs, ko, st));
     HIPCHK(hipStreamSynchronize(st));
     if (ell_done) *ell_done = ld;
@@ -2286,7 +2302,7 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     const auto t2 = now();
     if (ld == 0) {
         // nothing to project on: zero coefficients, breakdown reported
-        HIPCHK(hipMemcpy2DAsync(coef, (size_t)ldc * sizeof(double), b.P, (size_t)ldn * sizeof(double),
+        HIPCHK(copy_strided(coef, (size_t)ldc * sizeof(double), b.P, (size_t)ldn * sizeof(double),
                                 (size_t)n * sizeof(double), (size_t)nrhs, kind_out(flags), st));
         HIPCHK(hipStreamSynchronize(st));
         if (info)
@@ -2323,7 +2339,7 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     launch_blk_update(b.Z, ldn, n, (int32_t)ls, Y, kBlkRhs, 1, b.P, ldn, nrhs, 0, st);
     LAUNCHCHK("block lift");
     const hipMemcpyKind ko = kind_out(flags);
-    HIPCHK(hipMemcpy2DAsync(coef, (size_t)ldc * sizeof(double), b.P, (size_t)ldn * sizeof(double),
+    HIPCHK(copy_strided(coef, (size_t)ldc * sizeof(double), b.P, (size_t)ldn * sizeof(double),
                             (size_t)n * sizeof(double), (size_t)nrhs, ko, st));
     if (sv) HIPCHK(hipMemcpyAsync(sv, svd, (size_t)ls * sizeof(double), ko, st));
     HIPCHK(hipStreamSynchronize(st));
