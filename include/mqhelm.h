@@ -464,8 +464,9 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
  *
  * The SVD is one-sided block Jacobi on the rows of [A | f]: row rotations Q
  * (each sweep orders the rows by decreasing norm and pairs 32-row blocks in
- * a round-robin order; per pair the rotation of one cyclic Jacobi sweep on
- * the 64 x 64 Gram matrix of their rows) until, in a whole sweep, every pair
+ * a round-robin order; per pair the rotation of one cyclic Jacobi sweep,
+ * two on matrices of at most 10 blocks, on the 64 x 64 Gram matrix of their
+ * rows) until, in a whole sweep, every pair
  * of rows has the component of the smaller along the larger at most
  * 16 sqrt(n) DBL_EPSILON ||A||_F, or the largest such component stays below
  * twice that (the rounding floor of the measure) without falling by a
