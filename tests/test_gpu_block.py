@@ -23,6 +23,9 @@ several sources sharing one Krylov space) against the block oracle
   the oracle; invalid arguments are rejected.
 * Permuting the sources permutes the choices and the solutions; zero and
   linearly dependent sources are rejected, nearly dependent ones are not.
+* At the benchmark's size (the 20 596-node sweep cube, 16 sources, 7 block
+  steps, FP32 block products): A Z = W C on sampled rows with the oracle's
+  FP64 entries (measured 1e-9 of ||C||), orthonormal bases, W_1 E_1 = F.
 """
 import sys
 
@@ -226,6 +229,32 @@ def test_block_dependent_or_zero_sources_are_rejected(mq, case, blobs):
         say("block, nearly dependent sources")
         g = pr.gkb_block(np.ascontiguousarray(np.stack([F[0], F[0] + 1e-6 * F[1]])), 4)
     assert g["status"] == 0 and g["ell_done"] == 4
+
+
+def test_block_relations_full_size_sampled(mq, orc):
+    # the benchmark's launch configuration: the 20 596-node sweep cube, its 16 sources, 7 block
+    # steps on the FP32-evaluated block products.  The relation A Z = W C on 3 columns of Z at
+    # 64 sampled rows, with the oracle's FP64 entries one by one, to the FP32 products' bar of the
+    # small-case test (1e-5 of ||C||); the bases orthonormal (FP64 reorthogonalisation) and
+    # W_1 E_1 = F on the same rows.
+    m = I.sweep_member(0)
+    X = np.vstack([m.x_int, m.x_bnd])
+    n_int = m.x_int.shape[0]
+    with mq.Problem(m.x_int, m.x_bnd, m.kappa, m.eps, "matfree_fp32") as pr:
+        say("block gkb full size n", X.shape[0], "s 16 ell 7")
+        g = pr.gkb_block(m.F, 7, want_bases=True)
+    assert g["status"] == 0 and g["ell_done"] == 7
+    C, W, Z = g["C"], g["W"].T, g["Z"].T
+    nc = np.linalg.norm(C, 2)
+    rows = np.random.default_rng(11).choice(X.shape[0], 64, replace=False)
+    for j in (0, 57, 111):
+        az = orc.apply_sampled(X, n_int, m.kappa, m.eps, Z[:, j], rows)
+        err = np.max(np.abs(az - W[rows] @ C[:, j]))
+        say("column", j, "max |A z - W c| / ||C||", err / nc)
+        assert err <= 1e-5 * nc
+    assert np.max(np.abs(Z.T @ Z - np.eye(Z.shape[1]))) <= 1e-12
+    assert np.max(np.abs(W.T @ W - np.eye(W.shape[1]))) <= 1e-12
+    assert np.max(np.abs(W[rows, :16] @ g["E1"] - m.F[:, rows].T)) <= 1e-13 * np.abs(m.F).max() * 16
 
 
 def test_block_deterministic(mq, case, blobs):
