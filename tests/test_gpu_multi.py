@@ -89,6 +89,28 @@ def test_apply_multi_against_oracle(mq, orc, name, make, nrhs, mode):
             assert np.all(err2 <= tol), float(err2.max())
 
 
+def test_apply_multi_full_size_sampled(mq, orc):
+    # the sweep's largest shapes in the benchmark's mode: the 20 596-node and 29 619-node members,
+    # 16 vectors, FP32-evaluated block products; 64 sampled outputs of A X and A^T X per vector
+    # against the oracle's FP64 entries one by one, to the bar of the small cases relative to
+    # |A| |x| (every entry of A is positive, so |A| |x| = A |x|, computed the same way)
+    for k in (0, int(np.argmax(I.sweep_sizes()))):
+        m = I.sweep_member(k)
+        X = np.vstack([m.x_int, m.x_bnd])
+        n, n_int = X.shape[0], m.x_int.shape[0]
+        V = np.random.default_rng(20 + k).standard_normal((16, n))
+        rows = np.random.default_rng(30 + k).choice(n, 64, replace=False)
+        with mq.Problem(m.x_int, m.x_bnd, m.kappa, m.eps, "matfree_fp32") as pr:
+            for trans in (False, True):
+                say("apply_multi full size n", n, "trans", trans)
+                Y = pr.apply_multi(V, trans=trans)
+                for q in range(16):
+                    ref = orc.apply_sampled(X, n_int, m.kappa, m.eps, V[q], rows, trans=trans)
+                    scale = orc.apply_sampled(X, n_int, m.kappa, m.eps, np.abs(V[q]), rows, trans=trans)
+                    err = np.abs(Y[q][rows] - ref) / scale
+                    assert np.all(err <= 4e-6), (k, trans, q, float(err.max()))
+
+
 def test_apply_multi_columns_independent(mq):
     # a column's block product does not depend on the other columns of its group
     p = I.multi_cube(700, 300, 4.0, 1.5, 16, 10, seed=3)
