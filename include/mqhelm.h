@@ -423,8 +423,10 @@ int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* 
  * the QR of F that is not positive, or a diagonal entry of E_1 at most
  * n DBL_EPSILON times its largest) are MQH_EINVAL, since W_1 would carry a
  * direction of rounding noise.  Host or device pointers
- * (MQH_FLAG_DEVICE_PTRS in flags / opts->flags); the library allocates its
- * workspace per call.
+ * (MQH_FLAG_DEVICE_PTRS in flags / opts->flags).  The workspace (the bases,
+ * (2 ell + 1) nrhs n doubles, and the projected problem's) stays on the
+ * problem between calls and is reused by calls of the same nrhs and ell;
+ * mqh_problem_destroy frees it.
  *
  * mqh_gkb_block: C ((ell + 1) nrhs x ell nrhs, row-major; blocks past
  *   ell_done are zero), E1 (nrhs x nrhs row-major, NULL allowed), W

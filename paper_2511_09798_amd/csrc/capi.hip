@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -146,6 +147,11 @@ struct MultiWs {
     int32_t g_ell = 0, g_reorth = -1;
 };
 
+namespace {
+struct BlockCache;  // workspaces of the block calls, kept between calls (defined below)
+void block_cache_free(BlockCache* c);
+}  // namespace
+
 struct mqh_problem {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -214,6 +220,7 @@ struct mqh_problem {
     ParamOut* pout2 = nullptr;
     // multi-right-hand-side runs
     MultiWs mw;
+    BlockCache* bc = nullptr;
     // timing
     hipEvent_t ev[8] = {};
     std::vector<hipEvent_t> pev;
@@ -928,6 +935,18 @@ constexpr double kFullCgTol = 1e-15;  // stop when sqrt(r^T D^-1 r) falls below 
 // columns: G = [M | F] row-major, ldg = n + nrhs rounded up to 64, rows
 // padded with zero rows to an even number of 32-row blocks; the block pairs
 // of a round-robin tournament.  G is cleared.
+// The per-call state of a prepared run: a zero work matrix, no slot found
+// orthogonal, no block rotated (so a run can be reused for another matrix of
+// the same size).
+int full_reset(hipStream_t s, FullRun& r) {
+    HIPCHK(hipMemsetAsync(r.G, 0, (size_t)(r.nrow * r.ldg) * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(r.pair_ok, 0xff, (size_t)r.rounds * r.npairs * sizeof(int32_t), s));  // -1
+    HIPCHK(hipMemsetAsync(r.blk_stamp, 0xff, (size_t)r.nblk * sizeof(int32_t), s));
+    r.sweeps = 0;
+    r.final_off = 0.0;
+    return MQH_OK;
+}
+
 int full_prepare(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
     r.n = n;
     r.ldg = round_up(n + nrhs, 64);
@@ -970,9 +989,8 @@ int full_prepare(hipStream_t s, FullRun& r, int64_t n, int nrhs) {
         pos[1] = last;
     }
     HIPCHK(hipMemcpyAsync(r.pairs, pr.data(), pr.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(r.G, 0, (size_t)(r.nrow * r.ldg) * sizeof(double), s));
-    HIPCHK(hipMemsetAsync(r.pair_ok, 0xff, (size_t)r.rounds * r.npairs * sizeof(int32_t), s));  // -1
-    HIPCHK(hipMemsetAsync(r.blk_stamp, 0xff, (size_t)r.nblk * sizeof(int32_t), s));
+    int rc2;
+    if ((rc2 = full_reset(s, r))) return rc2;
     HIPCHK(hipStreamSynchronize(s));  // pr is a local
     return MQH_OK;
 }
@@ -1248,6 +1266,77 @@ int block_alloc(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell) {
     return MQH_OK;
 }
 
+// Workspaces of the block calls, kept on the problem between calls: at the
+// sizes of the block solves the allocations and frees of a call (about 50,
+// each free waiting for the device) cost more than a tenth of the call.  The
+// block bases for (s, ell) with the projected solutions Y (ell s x 16) and
+// singular values, and the projected problem's run for its size (m, s) with
+// its per-source buffers.
+struct BlockCache {
+    std::unique_ptr<BlockWs> ws;
+    int32_t s = 0, ell = 0;
+    double* Y = nullptr;
+    double* sv = nullptr;
+    std::unique_ptr<FullRun> fr;
+    int64_t m = 0;
+    int32_t fs = 0;
+    double* fh = nullptr;    // data columns, m x s
+    double* fsrt = nullptr;  // the same in descending singular-value order
+    double* tail = nullptr;  // (m + 1) x s
+    double* fn2 = nullptr;   // ||f_k||^2
+    ParamOut* po = nullptr;
+    void drop_ws() {
+        ws.reset();
+        dfree(Y);
+        dfree(sv);
+        Y = sv = nullptr;
+    }
+    void drop_run() {
+        fr.reset();
+        dfree(fh);
+        dfree(fsrt);
+        dfree(tail);
+        dfree(fn2);
+        dfree(po);
+        fh = fsrt = tail = fn2 = nullptr;
+        po = nullptr;
+    }
+    ~BlockCache() {
+        drop_run();
+        drop_ws();
+    }
+};
+
+void block_cache_free(BlockCache* c) { delete c; }
+
+// The block workspace for s sources and ell steps, from the cache or newly
+// allocated; bases cleared either way.
+int block_ws(mqh_problem* p, int32_t s, int32_t ell, BlockWs** out) {
+    if (p->bc == nullptr) p->bc = new BlockCache;
+    BlockCache& c = *p->bc;
+    int rc;
+    if (c.ws && c.s == s && c.ell == ell) {
+        const int64_t ldn = p->ldn;
+        hipStream_t st = p->stream;
+        HIPCHK(hipMemsetAsync(c.ws->W, 0, (size_t)(ell + 1) * s * ldn * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(c.ws->Z, 0, (size_t)ell * s * ldn * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(c.ws->P, 0, (size_t)kBlkRhs * ldn * sizeof(double), st));
+    } else {
+        c.drop_ws();
+        c.ws.reset(new BlockWs);
+        c.s = s;
+        c.ell = ell;
+        if ((rc = block_alloc(p, *c.ws, s, ell)) || (rc = dalloc(&c.Y, (size_t)ell * s * kBlkRhs)) ||
+            (rc = dalloc(&c.sv, (size_t)ell * s))) {
+            c.drop_ws();
+            c.s = c.ell = 0;
+            return rc;
+        }
+    }
+    *out = c.ws.get();
+    return MQH_OK;
+}
+
 // Q R = X in place (X: n x s, leading dimension ldn) by shifted Cholesky QR
 // three times; R (s x s, row-major, upper triangular) to the host.  *bad is
 // set when a Cholesky factorisation fails (X numerically zero or not finite).
@@ -1398,9 +1487,24 @@ int block_projected(mqh_problem* p, const std::vector<double>& C, const double* 
                     std::vector<int>& iters, std::vector<char>& conv, int32_t* sweeps) {
     hipStream_t st = p->stream;
     const int64_t m = (int64_t)(ell + 1) * s, ls = (int64_t)ell * s;
-    FullRun r;
+    BlockCache& bc = *p->bc;  // made by block_ws
     int rc;
-    if ((rc = full_prepare(st, r, m, s))) return rc;
+    if (bc.fr && bc.m == m && bc.fs == s) {
+        if ((rc = full_reset(st, *bc.fr))) return rc;
+    } else {
+        bc.drop_run();
+        bc.fr.reset(new FullRun);
+        bc.m = m;
+        bc.fs = s;
+        if ((rc = full_prepare(st, *bc.fr, m, s)) || (rc = dalloc(&bc.fh, (size_t)(m * s))) ||
+            (rc = dalloc(&bc.fsrt, (size_t)(m * s))) || (rc = dalloc(&bc.tail, (size_t)((m + 1) * s))) ||
+            (rc = dalloc(&bc.fn2, (size_t)s)) || (rc = dalloc(&bc.po, (size_t)s))) {
+            bc.drop_run();
+            bc.m = 0;
+            return rc;
+        }
+    }
+    FullRun& r = *bc.fr;
     {
         std::vector<double> Gh((size_t)m * (size_t)r.ldg, 0.0);
         const int64_t ldc = ls;
@@ -1416,29 +1520,11 @@ int block_projected(mqh_problem* p, const std::vector<double>& C, const double* 
     *sweeps = r.sweeps;
     if (sv) HIPCHK(hipMemcpyAsync(sv, r.sv, (size_t)ls * sizeof(double), hipMemcpyDeviceToDevice, st));
     // the sources' data columns, their sorted order, the choices and the solutions, all at once
-    double* fh_all = nullptr;
-    double* fs_all = nullptr;
-    double* tail_all = nullptr;
-    double* fn2 = nullptr;
-    ParamOut* po_all = nullptr;
-    struct Free {
-        double*& a;
-        double*& b;
-        double*& c;
-        double*& d;
-        ParamOut*& e;
-        ~Free() {
-            dfree(a);
-            dfree(b);
-            dfree(c);
-            dfree(d);
-            dfree(e);
-        }
-    } fr{fh_all, fs_all, tail_all, fn2, po_all};
-    if ((rc = dalloc(&fh_all, (size_t)(m * s))) || (rc = dalloc(&fs_all, (size_t)(m * s))) ||
-        (rc = dalloc(&tail_all, (size_t)((m + 1) * s))) || (rc = dalloc(&fn2, (size_t)s)) ||
-        (rc = dalloc(&po_all, (size_t)s)))
-        return rc;
+    double* fh_all = bc.fh;
+    double* fs_all = bc.fsrt;
+    double* tail_all = bc.tail;
+    double* fn2 = bc.fn2;
+    ParamOut* po_all = bc.po;
     std::vector<double> fn2h((size_t)s, 0.0);
     for (int k = 0; k < s; ++k)
         for (int i = 0; i < s; ++i) fn2h[(size_t)k] += E1[i * s + k] * E1[i * s + k];
@@ -1550,6 +1636,7 @@ int mqh_problem_destroy(mqh_problem* p) {
     dfree(p->EP);
     dfree(p->u);
     multi_free(p->mw);
+    block_cache_free(p->bc);
     if (p->hres) (void)hipHostFree(p->hres);
     for (auto& e : p->ev)
         if (e) (void)hipEventDestroy(e);
@@ -2238,8 +2325,9 @@ int mqh_gkb_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, in
     HIPCHK(hipSetDevice(p->device));
     hipStream_t st = p->stream;
     if (p->mode == MQH_OP_MATFREE_FP32 && nrhs >= 2 && (rc = ensure_multi(p, nrhs, 1))) return rc;
-    BlockWs b;
-    if ((rc = block_alloc(p, b, nrhs, ell))) return rc;
+    BlockWs* bw = nullptr;
+    if ((rc = block_ws(p, nrhs, ell, &bw))) return rc;
+    BlockWs& b = *bw;
     if ((rc = stage_block(p, b, F, ldf, nrhs, flags))) return rc;
     std::vector<double> Ch;
     double E1h[kBlkRhs * kBlkRhs];
@@ -2290,8 +2378,9 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     };
     const auto t0 = now();
     if (p->mode == MQH_OP_MATFREE_FP32 && nrhs >= 2 && (rc = ensure_multi(p, nrhs, 1))) return rc;
-    BlockWs b;
-    if ((rc = block_alloc(p, b, nrhs, ell))) return rc;
+    BlockWs* bw = nullptr;
+    if ((rc = block_ws(p, nrhs, ell, &bw))) return rc;
+    BlockWs& b = *bw;
     if ((rc = stage_block(p, b, F, ldf, nrhs, flags))) return rc;
     HIPCHK(hipStreamSynchronize(st));
     const auto t1 = now();
@@ -2314,19 +2403,9 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     std::vector<double> Ck((size_t)((ld + 1) * nrhs) * (size_t)ls);
     for (int64_t i = 0; i < (int64_t)(ld + 1) * nrhs; ++i)
         for (int64_t j = 0; j < ls; ++j) Ck[(size_t)(i * ls + j)] = Ch[(size_t)(i * ldfull + j)];
-    double* Y = nullptr;
-    if ((rc = dalloc(&Y, (size_t)ls * kBlkRhs))) return rc;
-    struct Free {
-        double*& x;
-        ~Free() { dfree(x); }
-    } fy{Y};
+    double* Y = p->bc->Y;  // ell nrhs x 16, cached with the block workspace
     HIPCHK(hipMemsetAsync(Y, 0, (size_t)ls * kBlkRhs * sizeof(double), st));
-    double* svd = nullptr;
-    struct Free2 {
-        double*& x;
-        ~Free2() { dfree(x); }
-    } fs{svd};
-    if (sv && (rc = dalloc(&svd, (size_t)ls))) return rc;
+    double* svd = sv ? p->bc->sv : nullptr;
     std::vector<ParamOut> po;
     std::vector<int> iters;
     std::vector<char> conv;
