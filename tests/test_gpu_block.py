@@ -23,6 +23,8 @@ several sources sharing one Krylov space) against the block oracle
   the oracle; invalid arguments are rejected.
 * Permuting the sources permutes the choices and the solutions; zero and
   linearly dependent sources are rejected, nearly dependent ones are not.
+* The workspace kept on the problem: a call after calls of other sizes
+  returns the bits of a fresh problem's call.
 * At the benchmark's size (the 20 596-node sweep cube, 16 sources, 7 block
   steps, FP32 block products): A Z = W C on sampled rows with the oracle's
   FP64 entries (measured 1e-9 of ||C||), orthonormal bases, W_1 E_1 = F.
@@ -265,6 +267,25 @@ def test_block_deterministic(mq, case, blobs):
         a = pr.solve_block(blobs, 16)
         b = pr.solve_block(blobs, 16)
     assert np.array_equal(a.coef, b.coef) and np.array_equal(a.lam, b.lam)
+
+
+def test_block_workspace_reuse(mq, case, blobs):
+    # the block calls keep their workspace on the problem: calls of other sizes in between (another
+    # step count, another source count, a bare recurrence) must not change a later call's bits
+    p, A, _ = case
+    F = np.ascontiguousarray(blobs)
+    with _problem(mq, p, "stored_fp64") as fresh:
+        say("block workspace: fresh problem")
+        ref = fresh.solve_block(F, 8)
+    with _problem(mq, p, "stored_fp64") as pr:
+        say("block workspace: calls of other sizes in between")
+        pr.solve_block(F, 16)
+        pr.solve_block(np.ascontiguousarray(F[:3]), 8)
+        pr.gkb_block(F, 5)
+        a = pr.solve_block(F, 8)
+        b = pr.solve_block(F, 8)
+    assert np.array_equal(a.coef, ref.coef) and np.array_equal(b.coef, ref.coef)
+    assert np.array_equal(a.lam, ref.lam)
 
 
 def test_block_size_limits(mq):
