@@ -13,7 +13,8 @@
  *       L phi = Lap(phi) + kappa^2 phi                               (eqs. (7), (8))
  *   - the Kansa matrix A = [H; R]: interior rows L phi, Dirichlet
  *     boundary rows phi, centres = nodes                              (eqs. (10), (11))
- *   - products A v and A^T u, stored or entry-by-entry
+ *   - products A v and A^T u, stored or entry-by-entry, optionally with the
+ *     rows scaled by D = diag(A)^{-1} (an opt-in equilibration, not in the paper)
  *   - Golub-Kahan bidiagonalisation with full reorthogonalisation     (Algorithm 1)
  *   - one-sided Jacobi SVD of a small dense matrix (projected SVD)    (Algorithm 2 step 2, Algorithm 4 step 2)
  *   - the lift alpha = Z y and evaluation u(X) = sum_j alpha_j phi   (Algorithm 2 step 5, eq. (18))
@@ -99,7 +100,14 @@ typedef struct {
     const double* X; /* nodes n x 3 */
     int64_t n, n_int;
     double kappa, eps;
+    const double* d; /* row scale of the entry-by-entry operator (NULL: none); see orc_row_scale */
 } orc_op;
+
+/* Entry of the operator: A_ij, or d_i A_ij under row scaling. */
+static double op_entry(const orc_op* op, int64_t i, int64_t j) {
+    double a = orc_entry(op->X, op->n_int, i, j, op->kappa, op->eps);
+    return op->d ? op->d[i] * a : a;
+}
 
 static void op_apply(const orc_op* op, int trans, const double* x, double* y) {
     const int64_t n = op->n;
@@ -113,20 +121,21 @@ static void op_apply(const orc_op* op, int trans, const double* x, double* y) {
                 for (int64_t j = 0; j < n; ++j) s += row[j] * x[j];
             } else {
                 for (int64_t j = 0; j < n; ++j)
-                    s += orc_entry(op->X, op->n_int, i, j, op->kappa, op->eps) * x[j];
+                    s += op_entry(op, i, j) * x[j];
             }
             y[i] = s;
         }
     } else {
         /* y_j = sum_i A_ij x_i, i ascending.  Columns are processed in
-         * blocks of 64 so that a stored row segment is read contiguously;
-         * every y_j is still one sum in ascending i. */
-        const int64_t BS = 64;
+         * blocks of 512 so that a stored row segment (4 KB) is read
+         * contiguously; every y_j is still one sum in ascending i, so the
+         * block width changes no result. */
+        enum { BS = 512 };
         const int64_t nb = (n + BS - 1) / BS;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(dynamic, 1)
         for (int64_t b = 0; b < nb; ++b) {
             int64_t j0 = b * BS, j1 = j0 + BS < n ? j0 + BS : n;
-            double acc[64];
+            double acc[BS];
             for (int64_t j = j0; j < j1; ++j) acc[j - j0] = 0.0;
             for (int64_t i = 0; i < n; ++i) {
                 double xi = x[i];
@@ -135,7 +144,7 @@ static void op_apply(const orc_op* op, int trans, const double* x, double* y) {
                     for (int64_t j = j0; j < j1; ++j) acc[j - j0] += row[j] * xi;
                 } else {
                     for (int64_t j = j0; j < j1; ++j)
-                        acc[j - j0] += orc_entry(op->X, op->n_int, i, j, op->kappa, op->eps) * xi;
+                        acc[j - j0] += op_entry(op, i, j) * xi;
                 }
             }
             for (int64_t j = j0; j < j1; ++j) y[j] = acc[j - j0];
@@ -143,28 +152,52 @@ static void op_apply(const orc_op* op, int trans, const double* x, double* y) {
     }
 }
 
-/* Public product: A == NULL selects entry-by-entry evaluation. */
+/*
+ * Row scaling of the stacked system A c = f (eq. (11)) by D = diag(A)^{-1}:
+ * d_i = 1 / A_ii.  Not in the paper: an opt-in equilibration of the two row
+ * classes (interior rows carry L phi, of size about 3 eps^2 + kappa^2 at
+ * r = 0, boundary rows phi, of size 1 there).  The scaled problem is
+ * (D A) c = D f, with the same solution c when A is nonsingular.
+ */
+void orc_row_scale(const double* X, int64_t n, int64_t n_int, double kappa, double eps, double* d) {
+    for (int64_t i = 0; i < n; ++i) d[i] = 1.0 / orc_entry(X, n_int, i, i, kappa, eps);
+}
+
+/* Public product: A == NULL selects entry-by-entry evaluation; d (NULL
+ * allowed) scales the rows of the entry-by-entry operator (a stored A is
+ * passed already scaled). */
+void orc_apply_rs(const double* A, const double* X, int64_t n, int64_t n_int, double kappa, double eps,
+                  const double* d, int trans, const double* x, double* y) {
+    orc_op op = {A, X, n, n_int, kappa, eps, A ? NULL : d};
+    op_apply(&op, trans, x, y);
+}
+
 void orc_apply(const double* A, const double* X, int64_t n, int64_t n_int, double kappa, double eps,
                int trans, const double* x, double* y) {
-    orc_op op = {A, X, n, n_int, kappa, eps};
-    op_apply(&op, trans, x, y);
+    orc_apply_rs(A, X, n, n_int, kappa, eps, NULL, trans, x, y);
 }
 
 /* Sampled rows (trans = 0) or columns (trans = 1) of the product, entry by
  * entry: out[k] = (A x)_{idx[k]} or (A^T x)_{idx[k]}.  Used to check single
  * outputs at sizes where a full product is too slow on the CPU. */
-void orc_apply_sampled(const double* X, int64_t n, int64_t n_int, double kappa, double eps, int trans,
-                       const double* x, const int64_t* idx, int64_t cnt, double* out) {
+void orc_apply_sampled_rs(const double* X, int64_t n, int64_t n_int, double kappa, double eps, const double* d,
+                          int trans, const double* x, const int64_t* idx, int64_t cnt, double* out) {
+    orc_op op = {NULL, X, n, n_int, kappa, eps, d};
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < cnt; ++k) {
         int64_t o = idx[k];
         double s = 0.0;
         for (int64_t l = 0; l < n; ++l) {
-            double a = trans ? orc_entry(X, n_int, l, o, kappa, eps) : orc_entry(X, n_int, o, l, kappa, eps);
+            double a = trans ? op_entry(&op, l, o) : op_entry(&op, o, l);
             s += a * x[l];
         }
         out[k] = s;
     }
+}
+
+void orc_apply_sampled(const double* X, int64_t n, int64_t n_int, double kappa, double eps, int trans,
+                       const double* x, const int64_t* idx, int64_t cnt, double* out) {
+    orc_apply_sampled_rs(X, n, n_int, kappa, eps, NULL, trans, x, idx, cnt, out);
 }
 
 /* ------------------------------------------------------------------ */
@@ -222,11 +255,14 @@ static double norm2(const double* v, int64_t n) { return sqrt(dot(v, v, n)); }
  * beta[ell+1] (beta[0] = beta_1 = ||f||).  Returns ell_eff; *flag is set to
  * 1 on an alpha breakdown and 2 on a beta breakdown, else 0.
  * If reorth == 0 no reorthogonalisation is done (plain Algorithm 1).
+ * d (NULL allowed): the run is on the row-scaled operator D A of an
+ * entry-by-entry A (a stored A is passed already scaled); f is passed
+ * scaled by the caller.
  */
-int64_t orc_gkb(const double* A, const double* X, int64_t n, int64_t n_int, double kappa, double eps,
-                const double* f, int64_t ell, int reorth, double* W, double* Z, double* alpha, double* beta,
-                int* flag) {
-    orc_op op = {A, X, n, n_int, kappa, eps};
+int64_t orc_gkb_rs(const double* A, const double* X, int64_t n, int64_t n_int, double kappa, double eps,
+                   const double* d, const double* f, int64_t ell, int reorth, double* W, double* Z, double* alpha,
+                   double* beta, int* flag) {
+    orc_op op = {A, X, n, n_int, kappa, eps, A ? NULL : d};
     double* r = (double*)malloc(sizeof(double) * n);
     double* c = (double*)malloc(sizeof(double) * (ell + 2));
     *flag = 0;
@@ -269,6 +305,13 @@ int64_t orc_gkb(const double* A, const double* X, int64_t n, int64_t n_int, doub
     free(r);
     free(c);
     return ell_eff;
+}
+
+/* Algorithm 1 on the unscaled operator (d = NULL). */
+int64_t orc_gkb(const double* A, const double* X, int64_t n, int64_t n_int, double kappa, double eps,
+                const double* f, int64_t ell, int reorth, double* W, double* Z, double* alpha, double* beta,
+                int* flag) {
+    return orc_gkb_rs(A, X, n, n_int, kappa, eps, NULL, f, ell, reorth, W, Z, alpha, beta, flag);
 }
 
 /* ------------------------------------------------------------------ */

@@ -110,6 +110,15 @@ def lib():
         L.orc_apply_sampled.argtypes = [_pd, _i64, _i64, _d, _d, ctypes.c_int, _pd, _pi64, _i64, _pd]
         L.orc_gkb.restype = _i64
         L.orc_gkb.argtypes = [_pd, _pd, _i64, _i64, _d, _d, _pd, _i64, ctypes.c_int, _pd, _pd, _pd, _pd, _pint]
+        L.orc_row_scale.restype = None
+        L.orc_row_scale.argtypes = [_pd, _i64, _i64, _d, _d, _pd]
+        L.orc_apply_rs.restype = None
+        L.orc_apply_rs.argtypes = [_pd, _pd, _i64, _i64, _d, _d, _pd, ctypes.c_int, _pd, _pd]
+        L.orc_apply_sampled_rs.restype = None
+        L.orc_apply_sampled_rs.argtypes = [_pd, _i64, _i64, _d, _d, _pd, ctypes.c_int, _pd, _pi64, _i64, _pd]
+        L.orc_gkb_rs.restype = _i64
+        L.orc_gkb_rs.argtypes = [_pd, _pd, _i64, _i64, _d, _d, _pd, _pd, _i64, ctypes.c_int, _pd, _pd, _pd, _pd,
+                                 _pint]
         L.orc_jacobi_svd.restype = ctypes.c_int
         L.orc_jacobi_svd.argtypes = [_pd, _i64, _i64, _pd, _pd, _pd]
         L.orc_proj_svd.restype = ctypes.c_int
@@ -176,25 +185,44 @@ def interp_matrix(P: np.ndarray, X: np.ndarray, eps: float) -> np.ndarray:
     return B
 
 
+def row_scale(X: np.ndarray, n_int: int, kappa: float, eps: float) -> np.ndarray:
+    """d_i = 1 / A_ii: the row scaling D = diag(A)^{-1} of the stacked system A c = f (eq. (11)).
+
+    Not in the paper (an opt-in equilibration of the interior and boundary
+    rows); the scaled problem is (D A) c = D f."""
+    X = _c(X)
+    d = np.empty(X.shape[0])
+    lib().orc_row_scale(_p(X), X.shape[0], int(n_int), float(kappa), float(eps), _p(d))
+    return d
+
+
+_row_scale_vector = row_scale
+
+
 def apply(A: Optional[np.ndarray], X: np.ndarray, n_int: int, kappa: float, eps: float,
-          x: np.ndarray, trans: bool = False) -> np.ndarray:
-    """y = A x (trans False) or A^T x (trans True); A None evaluates entries on the fly."""
+          x: np.ndarray, trans: bool = False, d: Optional[np.ndarray] = None) -> np.ndarray:
+    """y = A x (trans False) or A^T x (trans True); A None evaluates entries on the fly.
+
+    d: row scale of the entry-by-entry operator (y = D A x, A^T D x); a stored A
+    is passed already scaled."""
     X, x = _c(X), _c(x)
     n = X.shape[0]
     y = np.empty(n)
     Ap = None if A is None else _p(_c(A))
-    lib().orc_apply(Ap, _p(X), n, int(n_int), float(kappa), float(eps), int(bool(trans)), _p(x), _p(y))
+    lib().orc_apply_rs(Ap, _p(X), n, int(n_int), float(kappa), float(eps), _p(None if d is None else _c(d)),
+                       int(bool(trans)), _p(x), _p(y))
     return y
 
 
 def apply_sampled(X: np.ndarray, n_int: int, kappa: float, eps: float, x: np.ndarray,
-                  idx: np.ndarray, trans: bool = False) -> np.ndarray:
-    """Selected outputs (A x)_idx or (A^T x)_idx, entry by entry."""
+                  idx: np.ndarray, trans: bool = False, d: Optional[np.ndarray] = None) -> np.ndarray:
+    """Selected outputs (A x)_idx or (A^T x)_idx, entry by entry (of D A when d is given)."""
     X, x = _c(X), _c(x)
     idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
     out = np.empty(idx.shape[0])
-    lib().orc_apply_sampled(_p(X), X.shape[0], int(n_int), float(kappa), float(eps), int(bool(trans)), _p(x),
-                            idx.ctypes.data_as(_pi64), idx.shape[0], _p(out))
+    lib().orc_apply_sampled_rs(_p(X), X.shape[0], int(n_int), float(kappa), float(eps),
+                               _p(None if d is None else _c(d)), int(bool(trans)), _p(x),
+                               idx.ctypes.data_as(_pi64), idx.shape[0], _p(out))
     return out
 
 
@@ -209,8 +237,11 @@ class GKBResult:
 
 
 def gkb(A: Optional[np.ndarray], X: np.ndarray, n_int: int, kappa: float, eps: float, f: np.ndarray,
-        ell: int, reorth: bool = True) -> GKBResult:
-    """Algorithm 1 (Golub-Kahan bidiagonalisation) with full CGS2 reorthogonalisation."""
+        ell: int, reorth: bool = True, d: Optional[np.ndarray] = None) -> GKBResult:
+    """Algorithm 1 (Golub-Kahan bidiagonalisation) with full CGS2 reorthogonalisation.
+
+    d: row scale of the entry-by-entry operator (the run is on D A; a stored
+    A and f are passed already scaled)."""
     X, f = _c(X), _c(f)
     n = X.shape[0]
     W = np.zeros((ell + 1, n))  # row k is column w_{k+1} (column-major storage)
@@ -219,8 +250,8 @@ def gkb(A: Optional[np.ndarray], X: np.ndarray, n_int: int, kappa: float, eps: f
     be = np.zeros(ell + 1)
     flag = ctypes.c_int(0)
     Ap = None if A is None else _p(_c(A))
-    le = lib().orc_gkb(Ap, _p(X), n, int(n_int), float(kappa), float(eps), _p(f), int(ell), int(bool(reorth)),
-                       _p(W), _p(Z), _p(al), _p(be), ctypes.byref(flag))
+    le = lib().orc_gkb_rs(Ap, _p(X), n, int(n_int), float(kappa), float(eps), _p(None if d is None else _c(d)),
+                          _p(f), int(ell), int(bool(reorth)), _p(W), _p(Z), _p(al), _p(be), ctypes.byref(flag))
     le = int(le)
     return GKBResult(W[: le + 1].T.copy(), Z[:le].T.copy(), al[:le].copy(), be[: le + 1].copy(), le,
                      int(flag.value))
@@ -556,12 +587,22 @@ class SolveResult:
 
 def solve(X: np.ndarray, n_int: int, kappa: float, eps: float, f: np.ndarray, ell: int,
           method: int = METHOD_HKT, rule: int = RULE_GCV, k_trunc: int = 0, lambda_fixed: float = 0.0,
-          n_grid: int = 200, stored: bool = True, reorth: bool = True, gcv_weight: float = 1.0) -> SolveResult:
+          n_grid: int = 200, stored: bool = True, reorth: bool = True, gcv_weight: float = 1.0,
+          row_scale: int = 0) -> SolveResult:
     """Ine-TSVD (Algorithm 2), HKT (Algorithm 4) or LSQR with early stopping (Section 3.4) from
-    nodes and data to RBF coefficients."""
+    nodes and data to RBF coefficients.
+
+    row_scale = 1 runs the method on the row-scaled system (D A) c = D f,
+    D = diag(A)^{-1} (see row_scale()); every projected quantity then refers
+    to that system, and the coefficients are its regularised solution."""
     X = _c(X)
+    d = _row_scale_vector(X, n_int, kappa, eps) if row_scale else None
     A = assemble(X, n_int, kappa, eps) if stored else None
-    g = gkb(A, X, n_int, kappa, eps, f, ell, reorth)
+    if d is not None:
+        f = d * _c(f)
+        if A is not None:
+            A *= d[:, None]
+    g = gkb(A, X, n_int, kappa, eps, f, ell, reorth, d=None if A is not None else d)
     del A
     flags = FLAG_BREAKDOWN if g.flag else 0
     le = g.ell
