@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MQH_VERSION 10300 /* 1.3.0 */
+#define MQH_VERSION 10400 /* 1.4.0 */
 
 /* ---- status codes ---- */
 #define MQH_OK 0
@@ -78,8 +78,11 @@ extern "C" {
                                        do not depend on timing noise; see mqh_gkb_multi) */
 #define MQH_FLAG_GRAPH 8u           /* mqh_solve_multi / mqh_solve_sweep: run each group's Golub-Kahan loop
                                        as a captured HIP graph, kept with the problem and replayed while
-                                       the group size, ell and reorth stay the same (ignored with
-                                       MQH_FLAG_TIME_PRODUCTS) */
+                                       the group size, ell, reorth and row scaling stay the same (ignored
+                                       with MQH_FLAG_TIME_PRODUCTS) */
+#define MQH_FLAG_ROW_SCALE 16u      /* mqh_apply, mqh_apply_multi, mqh_matrix_rows, mqh_gkb, mqh_gkb_multi:
+                                       the operator is D A with D = diag(A)^-1 (see mqh_solve_opts.row_scale);
+                                       mqh_gkb / mqh_gkb_multi also scale f to D f */
 
 /* ---- info flags ---- */
 #define MQH_INFO_BREAKDOWN 1u
@@ -113,7 +116,16 @@ typedef struct {
     int32_t n_grid;       /* lambda grid size J (>= 3; 0 -> 200) */
     double lambda_fixed;  /* HKT with MQH_RULE_FIXED: lambda >= 0 */
     uint32_t flags;       /* MQH_FLAG_* for this call */
-    int32_t reserved;
+    int32_t row_scale;    /* 0: the paper's system A c = f (eq. (11)).  1: the rows scaled by
+                             D = diag(A)^-1 (interior rows divided by 3 eps^2 + kappa^2, the value
+                             of L phi at r = 0; boundary rows by 1), i.e. the method runs on
+                             (D A) c = D f (not in the paper: an opt-in equilibration of the two
+                             row classes).  Every Golub-Kahan scalar, Ritz value, residual norm
+                             and GCV value then refers to the scaled system; the coefficients are
+                             its regularised solution.  mqh_solve, mqh_solve_multi and
+                             mqh_solve_sweep; the block, full-SVD and learned solves take 0 only.
+                             A stored matrix is kept assembled for the scaling of the last call
+                             that used it: a call with the other scaling assembles it again. */
     double gcv_weight;    /* MQH_RULE_WGCV: weight omega in (0, 1] of the trace term (1 -> plain GCV) */
 } mqh_solve_opts;
 

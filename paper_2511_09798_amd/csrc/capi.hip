@@ -144,7 +144,7 @@ struct MultiWs {
     // the Golub-Kahan loop of one group as a captured graph, and its key
     hipGraphExec_t graph = nullptr;
     int g_nz = 0;
-    int32_t g_ell = 0, g_reorth = -1;
+    int32_t g_ell = 0, g_reorth = -1, g_rs = -1;
 };
 
 namespace {
@@ -162,6 +162,13 @@ struct mqh_problem {
     bool fixed_shapes = false;
     double center[3] = {0.0, 0.0, 0.0};
     EntryConst ec{};
+    // row scaling D = diag(A)^-1 (opt-in): the interior rows' factor, the
+    // entry constants of D A, the scaling of the current call's products and
+    // the one the stored matrix was assembled with
+    double d_int = 1.0;
+    EntryConst ec_rs{};
+    int32_t rs = 0;
+    int32_t A_rs = 0;
     double4* X64 = nullptr;
     float4* X32 = nullptr;
     // FP32-evaluated products: nodes in Morton order within each class (FP32
@@ -353,6 +360,34 @@ void choose_shapes(mqh_problem* p) {
     p->P_rows = rows;
 }
 
+// Entry constants of the operator the current call runs on: A, or D A with
+// D = diag(A)^-1.  The scaling only changes the interior rows' constants
+// (kappa^2, eps^2, 2 eps^2 times 1 / (3 eps^2 + kappa^2)): boundary rows have
+// A_ii = phi(0) = 1.
+const EntryConst& op_ec(const mqh_problem* p) { return p->rs ? p->ec_rs : p->ec; }
+
+// Select the row scaling of the call's products (0: A, 1: D A); a stored
+// matrix assembled for the other scaling is assembled again.
+int set_row_scale(mqh_problem* p, int32_t rs) {
+    if (rs != 0 && rs != 1) return fail(MQH_EINVAL, "row_scale must be 0 or 1");
+    p->rs = rs;
+    if (p->mode == MQH_OP_STORED_FP64 && p->A_rs != rs) {
+        launch_assemble(p->X64, p->n, p->n_int, p->lda, op_ec(p), p->A, p->stream);
+        LAUNCHCHK("assembly");
+        p->A_rs = rs;
+    }
+    return MQH_OK;
+}
+
+// Right-hand sides to D f: the interior entries of nz staged vectors
+// (stride apart) times 1 / (3 eps^2 + kappa^2), when the call scales rows.
+int scale_rhs(mqh_problem* p, double* x, int nz, int64_t stride) {
+    if (p->rs == 0) return MQH_OK;
+    launch_scale(x, p->n_int, p->d_int, nz, stride, p->stream);
+    LAUNCHCHK("row scaling of the data");
+    return MQH_OK;
+}
+
 // One product y = op(A) x - shift z on device vectors (x, z of length ldn,
 // zero-padded).  shift from *shift_ptr when non-null.
 int op_product(mqh_problem* p, int trans, const double* x, const double* shift_ptr, double shift_val, const double* z,
@@ -361,7 +396,7 @@ int op_product(mqh_problem* p, int trans, const double* x, const double* shift_p
     if (p->mode == MQH_OP_MATFREE_FP32) {
         // x into the sorted node order, folded into the entry coefficients
         // (outside the timed span)
-        launch_gather_coef(x, p->perm, p->n, p->ec, p->cf, st, s);
+        launch_gather_coef(x, p->perm, p->n, op_ec(p), p->cf, st, s);
         LAUNCHCHK("gather");
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -399,10 +434,10 @@ int op_product(mqh_problem* p, int trans, const double* x, const double* shift_p
         perm = p->perm;
     } else if (!trans) {
         S = p->S_rows;
-        launch_mf_rows(p->X64, x, p->n, p->n_int, S, p->slice_rows, p->ec, p->P, p->ldn, st, s);
+        launch_mf_rows(p->X64, x, p->n, p->n_int, S, p->slice_rows, op_ec(p), p->P, p->ldn, st, s);
     } else {
         S = p->S_cols;
-        launch_mf_cols(p->X64, x, p->n, p->n_int, S, p->slice_cols, p->ec, p->P, p->ldn, st, s);
+        launch_mf_cols(p->X64, x, p->n, p->n_int, S, p->slice_cols, op_ec(p), p->P, p->ldn, st, s);
     }
     LAUNCHCHK("matrix-free product");
     if (timed) HIPCHK(hipEventRecord(e1, s));
@@ -575,7 +610,8 @@ int tune_block_shapes(mqh_problem* p, MultiWs& w, int nz) {
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     int rc = MQH_OK;
     auto product = [&](int trans, const std::pair<int, int64_t>& c) {
-        launch_mfm_block(trans, p->XS, p->frames, w.Vg, p->n, p->n_int, c.first, c.second, p->ec, w.PB, p->ldn, s);
+        launch_mfm_block(trans, p->XS, p->frames, w.Vg, p->n, p->n_int, c.first, c.second, op_ec(p), w.PB, p->ldn,
+                         s);
         launch_reduce_block(w.PB, p->ldn, c.first, p->n, nz, p->perm, nullptr, 0, nullptr, 0, w.Y, p->ldn, nullptr,
                             s);
     };
@@ -709,8 +745,8 @@ int block_product(mqh_problem* p, int nz, int trans, const double* X, int64_t xs
         HIPCHK(hipEventRecord(e0, s));
     }
     const int S = trans ? w.S_cols : w.S_rows;
-    launch_mfm_block(trans, p->XS, p->frames, w.Vg, p->n, p->n_int, S, trans ? w.slice_cols : w.slice_rows, p->ec,
-                     w.PB, p->ldn, s);
+    launch_mfm_block(trans, p->XS, p->frames, w.Vg, p->n, p->n_int, S, trans ? w.slice_cols : w.slice_rows,
+                     op_ec(p), w.PB, p->ldn, s);
     LAUNCHCHK("block product");
     if (timed) HIPCHK(hipEventRecord(e1, s));
     launch_reduce_block(w.PB, p->ldn, S, p->n, nz, p->perm, shift, sstr, Zs, zstr, Y, p->ldn, st, s);
@@ -773,13 +809,14 @@ int run_gkb_multi(mqh_problem* p, int nz, int32_t ell, int32_t reorth, bool time
 }
 
 // The Golub-Kahan loop of a group (run_gkb_multi) as a graph: captured on
-// the problem's stream at the first call with this group size, ell and
-// reorth, replayed after that.  The captured launches hold workspace
+// the problem's stream at the first call with this group size, ell, reorth
+// and row scaling (the captured launches hold the entry constants), replayed
+// after that.  The captured launches hold workspace
 // addresses, so a workspace reallocation drops the graph (multi_free).
 int run_gkb_multi_graph(mqh_problem* p, int nz, int32_t ell, int32_t reorth) {
     MultiWs& w = p->mw;
     hipStream_t s = p->stream;
-    if (w.graph != nullptr && (w.g_nz != nz || w.g_ell != ell || w.g_reorth != reorth)) {
+    if (w.graph != nullptr && (w.g_nz != nz || w.g_ell != ell || w.g_reorth != reorth || w.g_rs != p->rs)) {
         HIPCHK(hipGraphExecDestroy(w.graph));
         w.graph = nullptr;
     }
@@ -802,6 +839,7 @@ int run_gkb_multi_graph(mqh_problem* p, int nz, int32_t ell, int32_t reorth) {
         w.g_nz = nz;
         w.g_ell = ell;
         w.g_reorth = reorth;
+        w.g_rs = p->rs;
     }
     HIPCHK(hipGraphLaunch(w.graph, s));
     return MQH_OK;
@@ -1192,6 +1230,7 @@ int check_opts(const mqh_problem* p, const mqh_solve_opts* opts) {
     if (opts->method != MQH_METHOD_INE_TSVD && opts->method != MQH_METHOD_HKT && opts->method != MQH_METHOD_LSQR)
         return fail(MQH_EINVAL, "method");
     if (opts->rule < MQH_RULE_GCV || opts->rule > MQH_RULE_WGCV) return fail(MQH_EINVAL, "rule");
+    if (opts->row_scale != 0 && opts->row_scale != 1) return fail(MQH_EINVAL, "row_scale must be 0 or 1");
     if (opts->method == MQH_METHOD_LSQR && opts->rule == MQH_RULE_WGCV)
         return fail(MQH_EINVAL, "the weighted GCV rule applies to HKT and Ine-TSVD");
     if (opts->rule == MQH_RULE_WGCV && !(opts->gcv_weight > 0.0 && opts->gcv_weight <= 1.0))
@@ -1688,6 +1727,14 @@ int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, 
     p->ec.k2f = (float)p->ec.k2;
     p->ec.e2f = (float)p->ec.e2;
     p->ec.e2x2f = (float)p->ec.e2x2;
+    p->d_int = 1.0 / (p->ec.k2 + 3.0 * p->ec.e2);
+    p->ec_rs = p->ec;
+    p->ec_rs.k2 = p->d_int * p->ec.k2;
+    p->ec_rs.e2 = p->d_int * p->ec.e2;
+    p->ec_rs.e2x2 = p->d_int * p->ec.e2x2;
+    p->ec_rs.k2f = (float)p->ec_rs.k2;
+    p->ec_rs.e2f = (float)p->ec_rs.e2;
+    p->ec_rs.e2x2f = (float)p->ec_rs.e2x2;
     for (int a = 0; a < 3; ++a) {
         double lo = xyz[a], hi = xyz[a];
         for (int64_t i = 1; i < n; ++i) {
@@ -1771,6 +1818,7 @@ int mqh_apply(mqh_problem* p, int32_t trans, const double* x, double shift, cons
     if (trans != 0 && trans != 1) return fail(MQH_EINVAL, "trans must be 0 or 1");
     if (!isfinite(shift)) return fail(MQH_EINVAL, "non-finite shift");
     HIPCHK(hipSetDevice(p->device));
+    if ((rc = set_row_scale(p, (flags & MQH_FLAG_ROW_SCALE) ? 1 : 0))) return rc;
     if ((rc = stage_in(p->vx, x, p->n, flags, p->stream))) return rc;
     if (z && (rc = stage_in(p->vz, z, p->n, flags, p->stream))) return rc;
     if ((rc = op_product(p, trans, p->vx, nullptr, shift, z ? p->vz : nullptr, p->vy, nullptr, false))) return rc;
@@ -1784,6 +1832,7 @@ int mqh_matrix_rows(mqh_problem* p, int64_t row0, int64_t count, double* out, ui
     if ((rc = check_problem(p))) return rc;
     if (out == nullptr || row0 < 0 || count < 1 || row0 + count > p->n) return fail(MQH_EINVAL, "bad row range");
     HIPCHK(hipSetDevice(p->device));
+    if ((rc = set_row_scale(p, (flags & MQH_FLAG_ROW_SCALE) ? 1 : 0))) return rc;
     const bool dev = (flags & MQH_FLAG_DEVICE_PTRS) != 0;
     const int64_t chunk = 1024;
     double* tmp = nullptr;
@@ -1798,7 +1847,7 @@ int mqh_matrix_rows(mqh_problem* p, int64_t row0, int64_t count, double* out, ui
         } else {
             launch_gen_rows(p->mode == MQH_OP_MATFREE_FP64 ? 64 : 32,
                             p->mode == MQH_OP_MATFREE_FP64 ? (const void*)p->X64 : (const void*)p->X32, p->n, p->n_int,
-                            r, c, p->ec, dst, p->stream);
+                            r, c, op_ec(p), dst, p->stream);
             e = hipGetLastError();
         }
         if (e == hipSuccess && !dev)
@@ -1822,8 +1871,10 @@ int mqh_gkb(mqh_problem* p, const double* f, int32_t ell, int32_t reorth, double
     if (ell < 1 || ell > p->n || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= min(n, MQH_MAX_ELL)");
     if (reorth != 0 && reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
     HIPCHK(hipSetDevice(p->device));
+    if ((rc = set_row_scale(p, (flags & MQH_FLAG_ROW_SCALE) ? 1 : 0))) return rc;
     if ((rc = ensure_gkb(p, ell))) return rc;
     if ((rc = stage_in(p->vx, f, p->n, flags, p->stream))) return rc;
+    if ((rc = scale_rhs(p, p->vx, 1, 0))) return rc;
     if ((rc = run_gkb(p, ell, reorth, false))) return rc;
     HIPCHK(hipMemcpyAsync(&p->hres->st, p->st, sizeof(GkbState), hipMemcpyDeviceToHost, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
@@ -1875,12 +1926,14 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
     HIPCHK(hipSetDevice(p->device));
     hipStream_t s = p->stream;
     if ((rc = ensure_gkb(p, ell))) return rc;
+    if ((rc = set_row_scale(p, opts->row_scale))) return rc;
     for (auto& e : p->pev) (void)hipEventDestroy(e);
     p->pev.clear();
     if (timed) p->pev.reserve((size_t)ell * 4);
     HIPCHK(hipEventRecord(p->ev[0], s));
     if ((rc = stage_in(p->vx, f_int, p->n_int, flags, s))) return rc;
     if ((rc = stage_in(p->vx + p->n_int, g_bnd, p->n_bnd, flags, s))) return rc;
+    if ((rc = scale_rhs(p, p->vx, 1, 0))) return rc;
     HIPCHK(hipEventRecord(p->ev[1], s));
     if ((rc = run_gkb(p, ell, opts->reorth, timed))) return rc;
     HIPCHK(hipEventRecord(p->ev[2], s));
@@ -1965,6 +2018,7 @@ int mqh_apply_multi(mqh_problem* p, int32_t trans, const double* X, int64_t ldx,
         for (int32_t k = 0; k < nrhs; ++k)
             if (!isfinite(shifts[k])) return fail(MQH_EINVAL, "non-finite shift");
     HIPCHK(hipSetDevice(p->device));
+    if ((rc = set_row_scale(p, (flags & MQH_FLAG_ROW_SCALE) ? 1 : 0))) return rc;
     hipStream_t s = p->stream;
     for (int k0 = 0; k0 < nrhs; k0 += kBlkRhs) {
         const int nz = nrhs - k0 < kBlkRhs ? nrhs - k0 : kBlkRhs;
@@ -2006,6 +2060,7 @@ int mqh_gkb_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, in
     if (ell < 1 || ell > p->n || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= min(n, MQH_MAX_ELL)");
     if (reorth != 0 && reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
     HIPCHK(hipSetDevice(p->device));
+    if ((rc = set_row_scale(p, (flags & MQH_FLAG_ROW_SCALE) ? 1 : 0))) return rc;
     hipStream_t s = p->stream;
     const int64_t n = p->n;
     const hipMemcpyKind ko = kind_out(flags);
@@ -2016,6 +2071,7 @@ int mqh_gkb_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, in
         if ((rc = ensure_multi(p, nz, ell))) return rc;
         MultiWs& w = p->mw;
         if ((rc = stage_multi(p, F, ldf, k0, nz, flags))) return rc;
+        if ((rc = scale_rhs(p, w.X, nz, p->ldn))) return rc;
         if ((rc = run_gkb_multi(p, nz, ell, reorth, false))) return rc;
         std::vector<GkbState> st((size_t)nz);
         std::vector<double> b1((size_t)nz);
@@ -2076,6 +2132,7 @@ int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     const bool timed = (flags & MQH_FLAG_TIME_PRODUCTS) != 0;
     const bool lsqr = opts->method == MQH_METHOD_LSQR;
     HIPCHK(hipSetDevice(p->device));
+    if ((rc = set_row_scale(p, opts->row_scale))) return rc;
     hipStream_t s = p->stream;
     const hipMemcpyKind ko = kind_out(flags);
     bool broke = false, edge = false;
@@ -2088,6 +2145,7 @@ int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
         if (timed) p->pev.reserve((size_t)ell * 4 * (size_t)nz);
         HIPCHK(hipEventRecord(p->ev[0], s));
         if ((rc = stage_multi(p, F, ldf, k0, nz, flags))) return rc;
+        if ((rc = scale_rhs(p, w.X, nz, p->ldn))) return rc;
         HIPCHK(hipEventRecord(p->ev[1], s));
         if ((flags & MQH_FLAG_GRAPH) && !timed) {
             if ((rc = run_gkb_multi_graph(p, nz, ell, opts->reorth))) return rc;
@@ -2250,6 +2308,7 @@ int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, con
     if (coef == nullptr) return fail(MQH_EINVAL, "NULL coef");
     if ((p->n_int > 0 && f_int == nullptr) || (p->n_bnd > 0 && g_bnd == nullptr)) return fail(MQH_EINVAL, "NULL data");
     if (p->n > MQH_FULL_MAX_N) return fail(MQH_EINVAL, "the full SVD takes n <= MQH_FULL_MAX_N");
+    if (opts->row_scale != 0) return fail(MQH_EINVAL, "the full-SVD solve takes row_scale = 0");
     if (opts->method != MQH_METHOD_HKT && opts->method != MQH_METHOD_INE_TSVD)
         return fail(MQH_EINVAL, "method: MQH_METHOD_HKT (Tikhonov filter) or MQH_METHOD_INE_TSVD (TSVD filter)");
     if (opts->rule != MQH_RULE_GCV && opts->rule != MQH_RULE_FIXED)
@@ -2322,7 +2381,9 @@ int mqh_gkb_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, in
     int rc;
     if ((rc = check_block_args(p, F, ldf, nrhs, ell))) return rc;
     if (C == nullptr) return fail(MQH_EINVAL, "NULL C");
+    if (flags & MQH_FLAG_ROW_SCALE) return fail(MQH_EINVAL, "the block Golub-Kahan calls run on A (no row scaling)");
     HIPCHK(hipSetDevice(p->device));
+    if ((rc = set_row_scale(p, 0))) return rc;
     hipStream_t st = p->stream;
     if (p->mode == MQH_OP_MATFREE_FP32 && nrhs >= 2 && (rc = ensure_multi(p, nrhs, 1))) return rc;
     BlockWs* bw = nullptr;
@@ -2367,7 +2428,9 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
     if (opts->rule == MQH_RULE_FIXED && (!isfinite(opts->lambda_fixed) || opts->lambda_fixed < 0.0))
         return fail(MQH_EINVAL, "lambda_fixed must be finite and >= 0");
+    if (opts->row_scale != 0) return fail(MQH_EINVAL, "the block solve takes row_scale = 0");
     HIPCHK(hipSetDevice(p->device));
+    if ((rc = set_row_scale(p, 0))) return rc;
     hipStream_t st = p->stream;
     const uint32_t flags = opts->flags;
     const int64_t n = p->n, ldn = p->ldn;
@@ -2838,6 +2901,7 @@ int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, 
     if (opts->reorth != 0 && opts->reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
     if (opts->method != MQH_METHOD_HKT || opts->rule != MQH_RULE_GCV)
         return fail(MQH_EINVAL, "the learned solve is HKT with GCV as judge and fallback");
+    if (opts->row_scale != 0) return fail(MQH_EINVAL, "the learned solve takes row_scale = 0");
     const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
     if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
     if (!(pred->h > 0.0) || !isfinite(pred->h) || pred->ell_step < 1 ||
@@ -2850,6 +2914,7 @@ int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, 
         if (!(pred->out_std[i] > 0.0f) || !isfinite(pred->out_mean[i])) return fail(MQH_EINVAL, "bad standardisation");
     const uint32_t flags = opts->flags;
     HIPCHK(hipSetDevice(p->device));
+    if ((rc = set_row_scale(p, 0))) return rc;
     hipStream_t s = p->stream;
     if ((rc = ensure_gkb(p, ell))) return rc;
     const size_t mlp_floats = kMlpIn + kMlpOut + 3 * kMlpWidth + 2 * kMlpIn;

@@ -42,6 +42,13 @@ __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
     if (i < n) x[i] = v;
 }
 
+// x[z stride + i] *= a for i < n, z < gridDim.y (the interior entries of
+// right-hand sides under the row scaling D = diag(A)^-1).
+__global__ void k_scale(double* __restrict__ x, int64_t n, double a, int64_t stride) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[(int64_t)blockIdx.y * stride + i] *= a;
+}
+
 // ---------------------------------------------------------------------------
 // Norms
 // ---------------------------------------------------------------------------
@@ -307,6 +314,11 @@ __global__ void k_fill_f32(float* __restrict__ x, int64_t n, float v) {
 void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s) {
     if (n <= 0) return;
     k_fill_f32<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, n, v);
+}
+
+void launch_scale(double* x, int64_t n, double a, int nz, int64_t stride, hipStream_t s) {
+    if (n <= 0 || nz <= 0) return;
+    k_scale<<<dim3((unsigned)((n + kBlock - 1) / kBlock), (unsigned)nz), kBlock, 0, s>>>(x, n, a, stride);
 }
 
 void launch_fill(double* x, int64_t n, double v, hipStream_t s) {

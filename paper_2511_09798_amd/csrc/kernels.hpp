@@ -85,6 +85,8 @@ void launch_mlp_features(const double* alpha, const double* beta, double kappa, 
 void launch_cap_ell(GkbState* st, int32_t ell, hipStream_t s);
 void launch_init_state(GkbState* st, int32_t ell, double* alpha, double* beta, hipStream_t s);
 void launch_fill(double* x, int64_t n, double v, hipStream_t s);
+// x[z stride + i] *= a for i < n, z < nz
+void launch_scale(double* x, int64_t n, double a, int nz, int64_t stride, hipStream_t s);
 int sumsq_blocks(int64_t n);
 void launch_sumsq_partial(const double* x, int64_t n, double* partial, int nb, const GkbState* st, hipStream_t s);
 // norm of x from partial sums of squares, breakdown test, dst = x / norm

@@ -39,6 +39,7 @@ MQH_FLAG_DEVICE_PTRS = 1
 MQH_FLAG_TIME_PRODUCTS = 2
 MQH_FLAG_FIXED_SHAPES = 4
 MQH_FLAG_GRAPH = 8
+MQH_FLAG_ROW_SCALE = 16
 MQH_INFO_BREAKDOWN = 1
 MQH_INFO_GCV_AT_EDGE = 2
 MQH_INFO_LCURVE_AT_EDGE = 4
@@ -72,7 +73,7 @@ class MQHError(RuntimeError):
 class mqh_solve_opts(ctypes.Structure):
     _fields_ = [("ell", ctypes.c_int32), ("reorth", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("rule", ctypes.c_int32), ("k_trunc", ctypes.c_int32), ("n_grid", ctypes.c_int32),
-                ("lambda_fixed", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("lambda_fixed", ctypes.c_double), ("flags", ctypes.c_uint32), ("row_scale", ctypes.c_int32),
                 ("gcv_weight", ctypes.c_double)]
 
 
@@ -266,29 +267,29 @@ def mqh_problem_destroy(h) -> None:
     lib.mqh_problem_destroy(h)
 
 
-def mqh_apply(h, trans: int, x, shift: float = 0.0, z=None, y=None):
-    fl = _flags(x, z, y)
+def mqh_apply(h, trans: int, x, shift: float = 0.0, z=None, y=None, row_scale: int = 0):
+    fl = _flags(x, z, y) | (MQH_FLAG_ROW_SCALE if row_scale else 0)
     if y is None:
         y = _empty_like_kind(x, (x.shape[0],))
     _check(lib.mqh_apply(h, int(trans), _ptr(x)[0], float(shift), _ptr(z)[0], _ptr(y)[0], fl), "mqh_apply")
     return y
 
 
-def mqh_matrix_rows(h, row0: int, count: int, out=None, n: Optional[int] = None):
+def mqh_matrix_rows(h, row0: int, count: int, out=None, n: Optional[int] = None, row_scale: int = 0):
     if out is None:
         out = np.empty((count, int(lib.mqh_problem_size(h))), dtype=np.float64)
-    fl = _flags(out)
+    fl = _flags(out) | (MQH_FLAG_ROW_SCALE if row_scale else 0)
     _check(lib.mqh_matrix_rows(h, int(row0), int(count), _ptr(out)[0], fl), "mqh_matrix_rows")
     return out
 
 
-def mqh_gkb(h, f, ell: int, reorth: int = 1, want_bases: bool = True):
+def mqh_gkb(h, f, ell: int, reorth: int = 1, want_bases: bool = True, row_scale: int = 0):
     n = int(lib.mqh_problem_size(h))
     W = _empty_like_kind(f, (ell + 1, n)) if want_bases else None  # row k = column k of the n x (ell+1) basis
     Z = _empty_like_kind(f, (ell, n)) if want_bases else None
     al = _empty_like_kind(f, (ell,))
     be = _empty_like_kind(f, (ell + 1,))
-    fl = _flags(f, W, Z, al, be)
+    fl = _flags(f, W, Z, al, be) | (MQH_FLAG_ROW_SCALE if row_scale else 0)
     done = _i32(0)
     st = _check(lib.mqh_gkb(h, _ptr(f)[0], int(ell), int(reorth), _ptr(W)[0], _ptr(Z)[0], _ptr(al)[0], _ptr(be)[0],
                             ctypes.byref(done), fl), "mqh_gkb")
@@ -372,7 +373,8 @@ class SolveOutput:
 
 def mqh_solve(h, f_int, g_bnd, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQH_RULE_GCV,
               k_trunc: int = 0, lambda_fixed: float = 0.0, n_grid: int = 200, reorth: int = 1,
-              time_products: bool = False, coef=None, gcv_weight: float = 1.0, want_sv: bool = True) -> SolveOutput:
+              time_products: bool = False, coef=None, gcv_weight: float = 1.0, want_sv: bool = True,
+              row_scale: int = 0) -> SolveOutput:
     n = int(lib.mqh_problem_size(h))
     ref = f_int if f_int is not None else g_bnd
     if coef is None:
@@ -383,7 +385,7 @@ def mqh_solve(h, f_int, g_bnd, ell: int, method: int = MQH_METHOD_HKT, rule: int
     fl = _flags(f_int, g_bnd, coef, al, be, sv)
     opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=int(method), rule=int(rule),
                           k_trunc=int(k_trunc), n_grid=int(n_grid), lambda_fixed=float(lambda_fixed),
-                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), reserved=0,
+                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), row_scale=int(row_scale),
                           gcv_weight=float(gcv_weight))
     info = mqh_solve_info()
     st = _check(lib.mqh_solve(h, _ptr(f_int)[0], _ptr(g_bnd)[0], ctypes.byref(opts), _ptr(coef)[0], _ptr(al)[0],
@@ -392,7 +394,7 @@ def mqh_solve(h, f_int, g_bnd, ell: int, method: int = MQH_METHOD_HKT, rule: int
                        info.resid_norm, info.sol_norm, info.flags, list(info.t_ms))
 
 
-def mqh_apply_multi(h, trans: int, X, shifts=None, Z=None, Y=None):
+def mqh_apply_multi(h, trans: int, X, shifts=None, Z=None, Y=None, row_scale: int = 0):
     """Rows of Y (nrhs x n): Y[k] = op(A) X[k] - shifts[k] Z[k]."""
     n = int(lib.mqh_problem_size(h))
     nrhs = int(X.shape[0])
@@ -400,7 +402,7 @@ def mqh_apply_multi(h, trans: int, X, shifts=None, Z=None, Y=None):
         raise ValueError("X and Z must be nrhs x n")
     if Y is None:
         Y = _empty_like_kind(X, (nrhs, n))
-    fl = _flags(X, Z, Y)
+    fl = _flags(X, Z, Y) | (MQH_FLAG_ROW_SCALE if row_scale else 0)
     sh = None
     if shifts is not None:
         sh = np.ascontiguousarray(np.asarray(shifts, dtype=np.float64).reshape(nrhs))
@@ -409,7 +411,7 @@ def mqh_apply_multi(h, trans: int, X, shifts=None, Z=None, Y=None):
     return Y
 
 
-def mqh_gkb_multi(h, F, ell: int, reorth: int = 1, want_bases: bool = True):
+def mqh_gkb_multi(h, F, ell: int, reorth: int = 1, want_bases: bool = True, row_scale: int = 0):
     """Lockstep runs of Algorithm 1 for the rows of F (nrhs x n): per run k,
     W[k] (ell+1 x n, row j = w_{j+1}), Z[k], alpha[k], beta[k], ell_done[k]."""
     n = int(lib.mqh_problem_size(h))
@@ -420,7 +422,7 @@ def mqh_gkb_multi(h, F, ell: int, reorth: int = 1, want_bases: bool = True):
     Z = _empty_like_kind(F, (nrhs, ell, n)) if want_bases else None
     al = _empty_like_kind(F, (nrhs, ell))
     be = _empty_like_kind(F, (nrhs, ell + 1))
-    fl = _flags(F, W, Z, al, be)
+    fl = _flags(F, W, Z, al, be) | (MQH_FLAG_ROW_SCALE if row_scale else 0)
     done = np.zeros(nrhs, dtype=np.int32)
     st = _check(lib.mqh_gkb_multi(h, _ptr(F)[0], n, nrhs, int(ell), int(reorth), _ptr(W)[0], _ptr(Z)[0], _ptr(al)[0],
                                   _ptr(be)[0], ctypes.c_void_p(done.ctypes.data), fl), "mqh_gkb_multi")
@@ -443,7 +445,7 @@ class MultiSolveOutput:
 
 def mqh_solve_multi(h, F, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQH_RULE_GCV, k_trunc: int = 0,
                     lambda_fixed: float = 0.0, n_grid: int = 200, reorth: int = 1, time_products: bool = False,
-                    coef=None, gcv_weight: float = 1.0, graph: bool = False) -> MultiSolveOutput:
+                    coef=None, gcv_weight: float = 1.0, graph: bool = False, row_scale: int = 0) -> MultiSolveOutput:
     """Algorithm 4 for every row of F (nrhs x n, rows [f_int; g_bnd])."""
     n = int(lib.mqh_problem_size(h))
     nrhs = int(F.shape[0])
@@ -454,7 +456,7 @@ def mqh_solve_multi(h, F, ell: int, method: int = MQH_METHOD_HKT, rule: int = MQ
     fl = _flags(F, coef) | (MQH_FLAG_GRAPH if graph else 0)
     opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=int(method), rule=int(rule),
                           k_trunc=int(k_trunc), n_grid=int(n_grid), lambda_fixed=float(lambda_fixed),
-                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), reserved=0,
+                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), row_scale=int(row_scale),
                           gcv_weight=float(gcv_weight))
     infos = (mqh_solve_info * nrhs)()
     st = _check(lib.mqh_solve_multi(h, _ptr(F)[0], n, nrhs, ctypes.byref(opts), _ptr(coef)[0], n, infos),
@@ -498,7 +500,7 @@ def mqh_solve_block(h, F, ell: int, rule: int = MQH_RULE_GCV, lambda_fixed: floa
     sv = _zeros_like_kind(F, (ell * s,)) if want_sv else None
     fl = _flags(F, coef, sv)
     opts = mqh_solve_opts(ell=int(ell), reorth=1, method=MQH_METHOD_HKT, rule=int(rule), k_trunc=0,
-                          n_grid=int(n_grid), lambda_fixed=float(lambda_fixed), flags=fl, reserved=0, gcv_weight=1.0)
+                          n_grid=int(n_grid), lambda_fixed=float(lambda_fixed), flags=fl, row_scale=0, gcv_weight=1.0)
     infos = (mqh_solve_info * s)()
     st = _check(lib.mqh_solve_block(h, _ptr(F)[0], n, s, ctypes.byref(opts), _ptr(coef)[0], n, _ptr(sv)[0], infos),
                 "mqh_solve_block")
@@ -513,7 +515,8 @@ def mqh_solve_block(h, F, ell: int, rule: int = MQH_RULE_GCV, lambda_fixed: floa
 
 def mqh_solve_sweep(problems, Fs, ell: int, workers: int = 2, coefs=None, method: int = MQH_METHOD_HKT,
                     rule: int = MQH_RULE_GCV, k_trunc: int = 0, lambda_fixed: float = 0.0, n_grid: int = 200,
-                    reorth: int = 1, time_products: bool = False, gcv_weight: float = 1.0, graph: bool = False):
+                    reorth: int = 1, time_products: bool = False, gcv_weight: float = 1.0, graph: bool = False,
+                    row_scale: int = 0):
     """Solve every problem of a sweep (Problem objects, each with its own right-hand sides Fs[i],
     nrhs_i x n_i) side by side on `workers` host threads; returns a list of MultiSolveOutput."""
     if len(problems) != len(Fs) or not problems:
@@ -531,7 +534,7 @@ def mqh_solve_sweep(problems, Fs, ell: int, workers: int = 2, coefs=None, method
                                   coef=_ptr(C)[0].value, ldc=pr.n, info=ctypes.cast(infos[i], ctypes.c_void_p).value)
     opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=int(method), rule=int(rule),
                           k_trunc=int(k_trunc), n_grid=int(n_grid), lambda_fixed=float(lambda_fixed),
-                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), reserved=0,
+                          flags=fl | (MQH_FLAG_TIME_PRODUCTS if time_products else 0), row_scale=int(row_scale),
                           gcv_weight=float(gcv_weight))
     _check(lib.mqh_solve_sweep(items, count, ctypes.byref(opts), int(workers)), "mqh_solve_sweep")
     outs = []
@@ -571,7 +574,7 @@ def mqh_full_solve(h, f_int, g_bnd, method: int = MQH_METHOD_HKT, rule: int = MQ
     sv = _zeros_like_kind(ref, (n,)) if want_sv else None
     fl = _flags(f_int, g_bnd, coef, sv)
     opts = mqh_solve_opts(ell=1, reorth=1, method=int(method), rule=int(rule), k_trunc=int(k_trunc),
-                          n_grid=int(n_grid), lambda_fixed=float(lambda_fixed), flags=fl, reserved=0, gcv_weight=1.0)
+                          n_grid=int(n_grid), lambda_fixed=float(lambda_fixed), flags=fl, row_scale=0, gcv_weight=1.0)
     info = mqh_solve_info()
     st = _check(lib.mqh_full_solve(h, _ptr(f_int)[0], _ptr(g_bnd)[0], ctypes.byref(opts), _ptr(coef)[0],
                                    _ptr(sv)[0], ctypes.byref(info)), "mqh_full_solve")
@@ -672,7 +675,7 @@ def mqh_solve_learned(h, f_int, g_bnd, ell: int, predictor: mqh_predictor, coef=
         coef = _empty_like_kind(ref, (n,))
     fl = _flags(f_int, g_bnd, coef)
     opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=MQH_METHOD_HKT, rule=MQH_RULE_GCV, k_trunc=0,
-                          n_grid=int(n_grid), lambda_fixed=0.0, flags=fl, reserved=0, gcv_weight=1.0)
+                          n_grid=int(n_grid), lambda_fixed=0.0, flags=fl, row_scale=0, gcv_weight=1.0)
     info, li = mqh_solve_info(), mqh_learned_info()
     st = _check(lib.mqh_solve_learned(h, _ptr(f_int)[0], _ptr(g_bnd)[0], ctypes.byref(opts), ctypes.byref(predictor),
                                       _ptr(coef)[0], ctypes.byref(info), ctypes.byref(li)), "mqh_solve_learned")
@@ -714,20 +717,20 @@ class Problem:
     def __exit__(self, *exc):
         self.close()
 
-    def apply(self, x, trans=False, shift=0.0, z=None, y=None):
-        return mqh_apply(self.h, int(bool(trans)), x, shift, z, y)
+    def apply(self, x, trans=False, shift=0.0, z=None, y=None, row_scale=0):
+        return mqh_apply(self.h, int(bool(trans)), x, shift, z, y, row_scale)
 
-    def matrix_rows(self, row0, count, out=None):
-        return mqh_matrix_rows(self.h, row0, count, out)
+    def matrix_rows(self, row0, count, out=None, row_scale=0):
+        return mqh_matrix_rows(self.h, row0, count, out, row_scale=row_scale)
 
-    def gkb(self, f, ell, reorth=True, want_bases=True):
-        return mqh_gkb(self.h, f, ell, int(bool(reorth)), want_bases)
+    def gkb(self, f, ell, reorth=True, want_bases=True, row_scale=0):
+        return mqh_gkb(self.h, f, ell, int(bool(reorth)), want_bases, row_scale)
 
-    def apply_multi(self, X, trans=False, shifts=None, Z=None, Y=None):
-        return mqh_apply_multi(self.h, int(bool(trans)), X, shifts, Z, Y)
+    def apply_multi(self, X, trans=False, shifts=None, Z=None, Y=None, row_scale=0):
+        return mqh_apply_multi(self.h, int(bool(trans)), X, shifts, Z, Y, row_scale)
 
-    def gkb_multi(self, F, ell, reorth=True, want_bases=True):
-        return mqh_gkb_multi(self.h, F, ell, int(bool(reorth)), want_bases)
+    def gkb_multi(self, F, ell, reorth=True, want_bases=True, row_scale=0):
+        return mqh_gkb_multi(self.h, F, ell, int(bool(reorth)), want_bases, row_scale)
 
     def solve_multi(self, F, ell, **kw) -> MultiSolveOutput:
         return mqh_solve_multi(self.h, F, ell, **kw)

@@ -60,8 +60,9 @@ def test_struct_layouts(mq, tmp_path):
     src.write_text(
         '#include <stddef.h>\n#include <stdio.h>\n#include "mqhelm.h"\n'
         'int main(void) {\n'
-        '  printf("%zu %zu %zu %zu %zu\\n", sizeof(mqh_solve_opts), offsetof(mqh_solve_opts, lambda_fixed),\n'
-        '         offsetof(mqh_solve_opts, flags), offsetof(mqh_solve_opts, gcv_weight), sizeof(mqh_solve_info));\n'
+        '  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(mqh_solve_opts), offsetof(mqh_solve_opts, lambda_fixed),\n'
+        '         offsetof(mqh_solve_opts, flags), offsetof(mqh_solve_opts, row_scale),\n'
+        '         offsetof(mqh_solve_opts, gcv_weight), sizeof(mqh_solve_info));\n'
         '  printf("%zu %zu\\n", offsetof(mqh_solve_info, flags), offsetof(mqh_solve_info, t_ms));\n'
         '  printf("%zu %zu %zu %zu\\n", sizeof(mqh_predictor), offsetof(mqh_predictor, h),\n'
         '         offsetof(mqh_predictor, ell_step), offsetof(mqh_predictor, judge_ratio));\n'
@@ -75,7 +76,8 @@ def test_struct_layouts(mq, tmp_path):
     vals = [int(v) for v in out]
     O, F, P, L = mq.mqh_solve_opts, mq.mqh_solve_info, mq.mqh_predictor, mq.mqh_learned_info
     S = mq.mqh_sweep_item
-    assert vals == [ctypes.sizeof(O), O.lambda_fixed.offset, O.flags.offset, O.gcv_weight.offset, ctypes.sizeof(F),
+    assert vals == [ctypes.sizeof(O), O.lambda_fixed.offset, O.flags.offset, O.row_scale.offset, O.gcv_weight.offset,
+                    ctypes.sizeof(F),
                     F.flags.offset, F.t_ms.offset, ctypes.sizeof(P), P.h.offset, P.ell_step.offset,
                     P.judge_ratio.offset, ctypes.sizeof(L), L.out.offset, ctypes.sizeof(S), S.status.offset,
                     S.coef.offset, S.info.offset]

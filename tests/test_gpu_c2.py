@@ -131,3 +131,30 @@ def test_c2_hkt_gcv_end_to_end(mq, orc, c2, mode):
     e_gpu, e_ref = orc.rel_l2(u_gcv, p.u_eval), orc.rel_l2(u_ref, p.u_eval)
     say("c2 rel-L2 gpu", e_gpu, "oracle", e_ref)
     assert abs(e_gpu - e_ref) <= 1e-4 * e_ref
+
+
+@pytest.fixture(scope="module")
+def c2_rs(orc, c2):
+    p = c2[0]
+    say("oracle solve, row scale", p.name)
+    ref = orc.solve(p.nodes, p.n_int, p.kappa, p.eps, p.rhs, p.ell, stored=True, row_scale=1)
+    u_ref = orc.eval_u(p.nodes, p.eps, ref.coef, p.x_eval)
+    say("oracle done, row scale: lambda", ref.lam, "rel-L2", orc.rel_l2(u_ref, p.u_eval))
+    return ref, u_ref
+
+
+def test_c2_hkt_row_scaled(mq, orc, c2, c2_rs):
+    # the same workload on (D A) c = D f, D = diag(A)^-1 (opt-in row scaling)
+    p = c2[0]
+    ref, u_ref = c2_rs
+    say("create", p.name, "stored_fp64")
+    with mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, "stored_fp64") as pr:
+        say("c2 solve gcv, row scale")
+        out = pr.solve(p.f_int, p.g_bnd, p.ell, row_scale=1)
+        fix = pr.solve(p.f_int, p.g_bnd, p.ell, rule=mq.MQH_RULE_FIXED, lambda_fixed=ref.lam, row_scale=1)
+        u = pr.eval(fix.coef, p.x_eval)
+    assert out.ell_done == ref.ell
+    assert np.max(np.abs(out.sv[:10] - ref.s[:10]) / ref.s[:10]) < 1e-12
+    assert bool(out.flags & mq.MQH_INFO_GCV_AT_EDGE) == bool(ref.flags & orc.FLAG_GCV_AT_EDGE)
+    assert out.lam == pytest.approx(ref.lam, rel=1e-6)
+    assert np.linalg.norm(u - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
