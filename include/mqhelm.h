@@ -258,6 +258,27 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
                  void* stream, uint32_t flags);
 
 /*
+ * mqh_proj_svd without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same computation and outputs as mqh_proj_svd
+ * (bit for bit); every array is a device pointer on the current device and
+ * stream runs on that device (NULL: the default stream).  V may be NULL.
+ * The workspace (the ell x ell rotation matrix, V when V is NULL, a status
+ * word) is a fixed array of MQH_NOALLOC_SCRATCH_BYTES in the library's
+ * device memory, one per GPU, held until the process ends; hence
+ * 1 <= ell <= MQH_NOALLOC_MAX_ELL (MQH_EINVAL beyond).  All calls on one GPU
+ * share that array: calls that overlap in time on one GPU (other streams or
+ * host threads) race and must be serialised by the caller.  The call
+ * synchronises the stream to read the status word (MQH_EDEVICE if the QR
+ * iteration did not converge).  No hipMalloc, hipFree or allocating library
+ * routine is called.
+ */
+#define MQH_NOALLOC_MAX_ELL 512
+#define MQH_NOALLOC_SCRATCH_BYTES 4194560 /* 8 (2 * 512 * 512 + 32): 4 MiB + 256 B */
+int mqh_proj_svd_noalloc(const double* alpha, const double* beta, int32_t ell, double* sv, double* ftil, double* V,
+                         void* stream);
+
+/*
  * Parameter choice on the projected problem (Section 3.2-3.3), on the device.
  *   method HKT:      rule GCV    -> lambda* = argmin GCV_l (eq. (30)) on a
  *                                   log grid of n_grid points over

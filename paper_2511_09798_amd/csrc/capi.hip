@@ -2679,6 +2679,72 @@ int dev_out(Tmp& t, T* dst, size_t count, uint32_t flags, T** out) {
 
 extern "C" {
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free projected SVD: the workspace of k_bidiag_svd (the rotation
+// matrix Vw, the status word, and V when the caller does not want it) lives
+// in one file-scope device array.  Host code never passes the array's name
+// to a kernel or a copy: its device address is looked up once per device
+// (hipGetSymbolAddress) and kept in g_scratch_addr.
+// ---------------------------------------------------------------------------
+
+constexpr int kNoAllocMaxEll = MQH_NOALLOC_MAX_ELL;
+constexpr size_t kScratchMat = (size_t)kNoAllocMaxEll * kNoAllocMaxEll;  // doubles per ell x ell matrix
+constexpr size_t kScratchDoubles = 2 * kScratchMat + 32;                  // Vw, V, status (+ padding)
+static_assert(MQH_NOALLOC_SCRATCH_BYTES == kScratchDoubles * sizeof(double), "scratch size in the header");
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (looked up on
+// the first call on that device).
+int scratch_addr(double** out) {
+    *out = nullptr;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MQH_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[dev] == nullptr) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (p == nullptr) return fail(MQH_EDEVICE, "scratch array has no device address");
+        g_scratch_addr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return MQH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mqh_proj_svd_noalloc(const double* alpha, const double* beta, int32_t ell, double* sv, double* ftil, double* V,
+                         void* stream) {
+    if (alpha == nullptr || beta == nullptr || sv == nullptr || ftil == nullptr) return fail(MQH_EINVAL, "NULL array");
+    if (ell < 1 || ell > kNoAllocMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= MQH_NOALLOC_MAX_ELL");
+    hipStream_t s = (hipStream_t)stream;
+    double* base = nullptr;
+    int rc;
+    if ((rc = scratch_addr(&base))) return rc;
+    double* dVw = base;
+    double* dV = V != nullptr ? V : base + kScratchMat;
+    int32_t* dst = reinterpret_cast<int32_t*>(base + 2 * kScratchMat);
+    // k_bidiag_svd initialises Vw and writes the status word itself; nothing
+    // in the scratch array has to start at zero
+    launch_bidiag_svd(alpha, beta, ell, nullptr, dVw, ell, sv, ftil, dV, ell, dst, s);
+    LAUNCHCHK("projected SVD");
+    int32_t status = 0;
+    HIPCHK(hipMemcpyAsync(&status, dst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    return MQH_OK;
+}
+
 int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* sv, double* ftil, double* V,
                  void* stream, uint32_t flags) {
     if (alpha == nullptr || beta == nullptr || sv == nullptr || ftil == nullptr) return fail(MQH_EINVAL, "NULL array");

@@ -45,6 +45,8 @@ MQH_INFO_GCV_AT_EDGE = 2
 MQH_INFO_LCURVE_AT_EDGE = 4
 MQH_INFO_SOLVE_NOCONV = 8
 MQH_MAX_ELL = 1024
+MQH_NOALLOC_MAX_ELL = 512
+MQH_NOALLOC_SCRATCH_BYTES = 4194560
 MQH_FULL_MAX_N = 32768
 MQH_FULL_CG_MAX = 1024
 MQH_BLOCK_MAX_DIM = 4096
@@ -118,6 +120,7 @@ _SIGNATURES = {
     "mqh_matrix_rows": (ctypes.c_int, [_vp, _i64, _i64, _vp, _u32]),
     "mqh_gkb": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), _u32]),
     "mqh_proj_svd": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _u32]),
+    "mqh_proj_svd_noalloc": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "mqh_param_choice": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _d, _i32, _d, ctypes.POINTER(_d),
                                         ctypes.POINTER(_i32), ctypes.POINTER(_d), ctypes.POINTER(_u32), _vp, _vp,
                                         _u32]),
@@ -305,6 +308,18 @@ def mqh_proj_svd(alpha, beta, want_v: bool = True, stream=None):
     _check(lib.mqh_proj_svd(_ptr(alpha)[0], _ptr(beta)[0], ell, _ptr(sv)[0], _ptr(ft)[0], _ptr(V)[0],
                             _stream_of(stream), fl), "mqh_proj_svd")
     return sv, ft, V
+
+
+def mqh_proj_svd_noalloc(alpha, beta, sv, ftil, V=None, stream=None):
+    """mqh_proj_svd into caller-provided device arrays with no device allocation (all torch CUDA tensors):
+    sv (ell), ftil (ell + 1), V (ell x ell, row i = v~_i) or None."""
+    ell = int(alpha.shape[0])
+    arrays = [a for a in (alpha, beta, sv, ftil, V) if a is not None]
+    if _flags(*arrays) != MQH_FLAG_DEVICE_PTRS:
+        raise TypeError("mqh_proj_svd_noalloc takes device (torch CUDA) arrays only")
+    _check(lib.mqh_proj_svd_noalloc(_ptr(alpha)[0], _ptr(beta)[0], ell, _ptr(sv)[0], _ptr(ftil)[0], _ptr(V)[0],
+                                    _stream_of(stream)), "mqh_proj_svd_noalloc")
+    return sv, ftil, V
 
 
 def mqh_param_choice(sv, ftil, method: int, rule: int, n_grid: int = 200, lambda_fixed: float = 0.0,

@@ -160,6 +160,16 @@ def test_invalid_projected_arguments(mq):
                       0) == mq.MQH_EINVAL  # NULL y
     assert L.mqh_proj_solution(a.ctypes.data, b.ctypes.data, a.ctypes.data, 4, 1, -1.0, 0, out.ctypes.data, None,
                                0) == mq.MQH_EINVAL  # negative lambda
+    # the allocation-free projected SVD checks its arguments before any device work
+    assert L.mqh_proj_svd_noalloc(None, b.ctypes.data, 4, out.ctypes.data, out.ctypes.data, None, None) == \
+        mq.MQH_EINVAL
+    assert L.mqh_proj_svd_noalloc(a.ctypes.data, b.ctypes.data, 0, out.ctypes.data, out.ctypes.data, None, None) == \
+        mq.MQH_EINVAL
+    assert L.mqh_proj_svd_noalloc(a.ctypes.data, b.ctypes.data, mq.MQH_NOALLOC_MAX_ELL + 1, out.ctypes.data,
+                                  out.ctypes.data, None, None) == mq.MQH_EINVAL
+    assert "MQH_NOALLOC_MAX_ELL" in mq.mqh_last_error()
+    with pytest.raises(TypeError):
+        mq.mqh_proj_svd_noalloc(a, b, np.empty(4), np.empty(5))  # host arrays are refused by the binding
     assert L.mqh_problem_destroy(None) == mq.MQH_OK
     assert L.mqh_problem_size(None) == -1
 
