@@ -56,7 +56,11 @@ extern "C" {
                              or the full solution's iteration at its cap (MQH_INFO_SOLVE_NOCONV) */
 
 /* ---- operator modes (how A enters the products) ---- */
-#define MQH_OP_STORED_FP64 0   /* A assembled once in HBM (8 N^2 bytes, row-major), FP64 products */
+#define MQH_OP_STORED_FP64 0   /* A assembled once in HBM, FP64 products.  Stored in 128 x 128 tiles;
+                                  the interior-interior and boundary-boundary blocks of A are symmetric
+                                  (their entries depend on |X_i - X_j| only) and are stored once, so A
+                                  takes about 8 (N^2 - (N_I^2 + N_B^2) / 2) bytes (53 GB instead of 80 GB
+                                  at N = 100 000, N_I = 80 000) */
 #define MQH_OP_MATFREE_FP64 1  /* entries regenerated inside every product, FP64 throughout */
 #define MQH_OP_MATFREE_FP32 2  /* entries evaluated in FP32 (the squared distances on the matrix
                                   cores, FP32-accurate), accumulated in FP64 */

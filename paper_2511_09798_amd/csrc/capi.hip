@@ -180,8 +180,18 @@ struct mqh_problem {
     int32_t* iperm = nullptr;  // iperm[perm[q]] = q
     float4* frames = nullptr;
     float4* cf = nullptr;
+    // stored matrix: kTile x kTile tiles with the symmetric blocks stored once
+    // (layout at the stored operator in op_kernels.hip), its tables, and the
+    // product partials (PR per work item, PC per stored tile)
     double* A = nullptr;
-    int64_t lda = 0;
+    PackedLayout pk{};
+    int32_t pk_max_row = 0;
+    int64_t pk_tiles = 0;
+    int64_t* pk_tile_base = nullptr;
+    int4* pk_items = nullptr;
+    int32_t* pk_item_first = nullptr;
+    double* PR = nullptr;
+    double* PC = nullptr;
     // length-ldn vectors (zero past n)
     double* vx = nullptr;
     double* vy = nullptr;
@@ -192,9 +202,6 @@ struct mqh_problem {
     // launch shapes
     int S_rows = 1, S_cols = 1;
     int64_t slice_rows = 0, slice_cols = 0;
-    int stored_rw = 4;
-    int64_t stored_tile_rows = 0;
-    int stored_tiles = 1;
     // Golub-Kahan workspace
     int32_t ell_cap = 0;
     double* W = nullptr;
@@ -323,6 +330,34 @@ void sorted_layout(const std::vector<double4>& r, int64_t n, int64_t n_int, std:
     }
 }
 
+// Tables of the tiled stored matrix: tile rows (interior tiles first), the
+// first stored tile of each, and the work items of a product (at most
+// kTileChunk consecutive tiles of one tile row).
+struct PackedTables {
+    int32_t nti = 0, nt = 0, max_row = 0;
+    std::vector<int64_t> tile_base;
+    std::vector<int4> items;
+    std::vector<int32_t> item_first;
+};
+
+void packed_tables(int64_t n, int64_t n_int, PackedTables& t) {
+    t.nti = (int32_t)((n_int + kTile - 1) / kTile);
+    t.nt = t.nti + (int32_t)((n - n_int + kTile - 1) / kTile);
+    t.tile_base.assign((size_t)t.nt + 1, 0);
+    t.item_first.assign((size_t)t.nt + 1, 0);
+    t.items.clear();
+    t.max_row = 0;
+    for (int32_t R = 0; R < t.nt; ++R) {
+        const int32_t ntr = R < t.nti ? t.nt - R : t.nti + (t.nt - R);
+        t.max_row = ntr > t.max_row ? ntr : t.max_row;
+        t.tile_base[(size_t)R + 1] = t.tile_base[(size_t)R] + ntr;
+        t.item_first[(size_t)R] = (int32_t)t.items.size();
+        for (int32_t p0 = 0; p0 < ntr; p0 += kTileChunk)
+            t.items.push_back(make_int4(R, p0, ntr - p0 < kTileChunk ? ntr - p0 : kTileChunk, 0));
+    }
+    t.item_first[(size_t)t.nt] = (int32_t)t.items.size();
+}
+
 void choose_shapes(mqh_problem* p) {
     const int64_t n = p->n;
     // Enough blocks for many rounds of resident waves over 256 CUs.
@@ -346,18 +381,7 @@ void choose_shapes(mqh_problem* p) {
     };
     pick(nb_rows, p->S_rows, p->slice_rows);
     pick(nb_cols, p->S_cols, p->slice_cols);
-    p->stored_rw = n >= 50000 ? 8 : (n >= 5000 ? 4 : 2);
-    const int64_t col_tiles = (p->ldn + 2 * kBlock - 1) / (2 * kBlock);
-    int64_t tiles = (target_blocks + col_tiles - 1) / col_tiles;
-    if (tiles > 128) tiles = 128;
-    if (tiles > n) tiles = n;
-    if (tiles < 1) tiles = 1;
-    p->stored_tile_rows = (n + tiles - 1) / tiles;
-    p->stored_tiles = (int)((n + p->stored_tile_rows - 1) / p->stored_tile_rows);
-    int64_t rows = p->S_rows;
-    if (p->S_cols > rows) rows = p->S_cols;
-    if (p->stored_tiles > rows) rows = p->stored_tiles;
-    p->P_rows = rows;
+    p->P_rows = p->S_rows > p->S_cols ? p->S_rows : p->S_cols;
 }
 
 // Entry constants of the operator the current call runs on: A, or D A with
@@ -372,7 +396,7 @@ int set_row_scale(mqh_problem* p, int32_t rs) {
     if (rs != 0 && rs != 1) return fail(MQH_EINVAL, "row_scale must be 0 or 1");
     p->rs = rs;
     if (p->mode == MQH_OP_STORED_FP64 && p->A_rs != rs) {
-        launch_assemble(p->X64, p->n, p->n_int, p->lda, op_ec(p), p->A, p->stream);
+        launch_assemble_packed(p->X64, p->pk, p->pk_max_row, op_ec(p), p->A, p->stream);
         LAUNCHCHK("assembly");
         p->A_rs = rs;
     }
@@ -412,17 +436,11 @@ int op_product(mqh_problem* p, int trans, const double* x, const double* shift_p
         HIPCHK(hipEventRecord(e0, s));
     }
     if (p->mode == MQH_OP_STORED_FP64) {
-        if (!trans) {
-            launch_stored_rows(p->stored_rw, p->A, p->lda, p->n, x, shift_ptr, shift_val, z, y, st, s);
-            LAUNCHCHK("stored rows product");
-            if (timed) HIPCHK(hipEventRecord(e1, s));
-        } else {
-            launch_stored_cols(p->A, p->lda, p->n, x, p->stored_tile_rows, p->stored_tiles, p->P, p->ldn, st, s);
-            LAUNCHCHK("stored columns product");
-            if (timed) HIPCHK(hipEventRecord(e1, s));
-            launch_reduce_slices(p->P, p->ldn, p->stored_tiles, p->n, nullptr, shift_ptr, shift_val, z, y, st, s);
-            LAUNCHCHK("slice reduction");
-        }
+        launch_packed_product(trans, p->A, p->pk, x, p->PR, p->PC, st, s);
+        LAUNCHCHK("stored product");
+        if (timed) HIPCHK(hipEventRecord(e1, s));
+        launch_packed_reduce(trans, p->pk, p->PR, p->PC, shift_ptr, shift_val, z, y, st, s);
+        LAUNCHCHK("stored product reduction");
         return MQH_OK;
     }
     int S;
@@ -1651,6 +1669,11 @@ int mqh_problem_destroy(mqh_problem* p) {
     dfree(p->frames);
     dfree(p->cf);
     dfree(p->A);
+    dfree(p->pk_tile_base);
+    dfree(p->pk_items);
+    dfree(p->pk_item_first);
+    dfree(p->PR);
+    dfree(p->PC);
     dfree(p->vx);
     dfree(p->vy);
     dfree(p->vz);
@@ -1801,10 +1824,36 @@ int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, 
             return bail(hip_fail(e, "upload of the sorted layout"));
     }
     if (op_mode == MQH_OP_STORED_FP64) {
-        p->lda = p->ldn;
-        if ((rc = dalloc(&p->A, (size_t)(n * p->lda)))) return bail(rc);
-        launch_assemble(p->X64, n, n_int, p->lda, p->ec, p->A, p->stream);
+        PackedTables t;
+        packed_tables(n, n_int, t);
+        p->pk_max_row = t.max_row;
+        p->pk_tiles = t.tile_base[(size_t)t.nt];
+        if ((rc = dalloc(&p->pk_tile_base, t.tile_base.size())) || (rc = dalloc(&p->pk_items, t.items.size())) ||
+            (rc = dalloc(&p->pk_item_first, t.item_first.size())) ||
+            (rc = dalloc(&p->PR, t.items.size() * (size_t)kTile)) ||
+            (rc = dalloc(&p->PC, (size_t)p->pk_tiles * (size_t)kTile)) ||
+            (rc = dalloc(&p->A, (size_t)p->pk_tiles * (size_t)kTileElems)))
+            return bail(rc);
+        p->pk.n = n;
+        p->pk.n_int = n_int;
+        p->pk.nti = t.nti;
+        p->pk.nt = t.nt;
+        p->pk.nitems = (int32_t)t.items.size();
+        p->pk.pad = 0;
+        p->pk.tile_base = p->pk_tile_base;
+        p->pk.items = p->pk_items;
+        p->pk.item_first = p->pk_item_first;
+        if ((e = hipMemcpyAsync(p->pk_tile_base, t.tile_base.data(), t.tile_base.size() * sizeof(int64_t),
+                                hipMemcpyHostToDevice, p->stream)) ||
+            (e = hipMemcpyAsync(p->pk_items, t.items.data(), t.items.size() * sizeof(int4), hipMemcpyHostToDevice,
+                                p->stream)) ||
+            (e = hipMemcpyAsync(p->pk_item_first, t.item_first.data(), t.item_first.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, p->stream)))
+            return bail(hip_fail(e, "upload of the tile tables"));
+        launch_assemble_packed(p->X64, p->pk, p->pk_max_row, p->ec, p->A, p->stream);
         if ((e = hipGetLastError())) return bail(hip_fail(e, "assembly launch"));
+        // the tables must stay alive until the copies have run
+        if ((e = hipStreamSynchronize(p->stream))) return bail(hip_fail(e, "assembly"));
     }
     if ((e = hipStreamSynchronize(p->stream))) return bail(hip_fail(e, "create"));
     *out = p;
@@ -1842,8 +1891,8 @@ int mqh_matrix_rows(mqh_problem* p, int64_t row0, int64_t count, double* out, ui
         double* dst = dev ? out + (r - row0) * p->n : tmp;
         hipError_t e;
         if (p->mode == MQH_OP_STORED_FP64) {
-            e = copy_strided(dst, (size_t)p->n * sizeof(double), p->A + r * p->lda, (size_t)p->lda * sizeof(double),
-                                 (size_t)p->n * sizeof(double), (size_t)c, hipMemcpyDeviceToDevice, p->stream);
+            launch_packed_rows(p->A, p->pk, r, c, dst, p->stream);
+            e = hipGetLastError();
         } else {
             launch_gen_rows(p->mode == MQH_OP_MATFREE_FP64 ? 64 : 32,
                             p->mode == MQH_OP_MATFREE_FP64 ? (const void*)p->X64 : (const void*)p->X32, p->n, p->n_int,

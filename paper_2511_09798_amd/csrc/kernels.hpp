@@ -27,6 +27,22 @@ constexpr int kMlpProbe = 10;  // Golub-Kahan steps read by the features (alpha_
 constexpr int64_t kMlpParams = (int64_t)kMlpIn * kMlpWidth + kMlpWidth + 2 * ((int64_t)kMlpWidth * kMlpWidth + kMlpWidth) +
                                (int64_t)kMlpWidth * kMlpOut + kMlpOut;
 
+// Stored matrix in kTile x kTile tiles, the symmetric interior-interior and
+// boundary-boundary blocks stored once (upper tiles); layout at the stored
+// operator in op_kernels.hip.  Work items of a product: (R, first position,
+// tile count, 0), at most kTileChunk tiles of one tile row each, rows in order.
+constexpr int kTile = 128;
+constexpr int64_t kTileElems = (int64_t)kTile * kTile;
+constexpr int kTileChunk = 16;
+struct PackedLayout {
+    int64_t n, n_int;
+    int32_t nti, nt;            // interior tile rows, all tile rows
+    int32_t nitems, pad;        // work items of a product
+    const int64_t* tile_base;   // nt + 1 entries: first stored tile of each tile row
+    const int4* items;          // nitems work items
+    const int32_t* item_first;  // nt + 1 entries: first item of each tile row
+};
+
 // Result of the parameter choice, device-resident.
 struct ParamOut {
     double lambda;
@@ -59,12 +75,21 @@ void launch_reduce_block(const double* P, int64_t ldp, int S, int64_t n, int nrh
 void launch_reduce_slices(const double* P, int64_t ldp, int S, int64_t n, const int32_t* perm,
                           const double* shift_ptr, double shift_val, const double* z, double* y,
                           const GkbState* st, hipStream_t s);
+// dense row-major A (lda >= n, zero columns past n): the full SVD's work matrix
 void launch_assemble(const double4* X, int64_t n, int64_t n_int, int64_t lda, const EntryConst& c, double* A,
                      hipStream_t s);
-void launch_stored_rows(int rw, const double* A, int64_t lda, int64_t n, const double* x, const double* shift_ptr,
-                        double shift_val, const double* z, double* y, const GkbState* st, hipStream_t s);
-void launch_stored_cols(const double* A, int64_t lda, int64_t n, const double* x, int64_t rows_per_tile, int tiles,
-                        double* P, int64_t ldp, const GkbState* st, hipStream_t s);
+// stored tiled matrix: assembly (grid max_row_tiles x nt), product partials
+// (PR: nitems x kTile, PC: stored tiles x kTile) and their reduction into
+// y = op(A) x - shift z, rows of A
+void launch_assemble_packed(const double4* X, const PackedLayout& L, int32_t max_row_tiles, const EntryConst& c,
+                            double* A, hipStream_t s);
+void launch_packed_product(int trans, const double* A, const PackedLayout& L, const double* x, double* PR, double* PC,
+                           const GkbState* st, hipStream_t s);
+void launch_packed_reduce(int trans, const PackedLayout& L, const double* PR, const double* PC,
+                          const double* shift_ptr, double shift_val, const double* z, double* y, const GkbState* st,
+                          hipStream_t s);
+void launch_packed_rows(const double* A, const PackedLayout& L, int64_t row0, int64_t count, double* out,
+                        hipStream_t s);
 void launch_gen_rows(int prec, const void* X, int64_t n, int64_t n_int, int64_t row0, int64_t count,
                      const EntryConst& c, double* out, hipStream_t s);
 void launch_eval_partial(const double4* X, const double* coef, int64_t n, const double4* E, int64_t m, int S,

@@ -3,8 +3,9 @@
 Workload: unit cube, 16 000 Halton interior nodes and 4 000 uniform face
 nodes, kappa = 20, eps = 4, u = sin 3x sin 2y sin(sqrt(12) z), 200 Golub-Kahan
 steps with full reorthogonalisation, HKT with the projected GCV of eq. (30)
-(Algorithm 4).  At this size the stored products run the four-rows-per-lane
-form of the row product, which the smaller parity cases do not reach.
+(Algorithm 4).  At this size the stored matrix spans 125 interior and 32
+boundary tile rows (several work items per tile row and many column-use
+partials per output tile), which the smaller parity cases do not reach.
 
 Checks against the FP64 oracle (which stores A on the host and runs
 Algorithm 1 with classical Gram-Schmidt twice):
