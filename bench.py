@@ -7,17 +7,22 @@ manufactured u = sin(kappa (x+y+z)/sqrt(3)) (so f = 0 inside, g = u on the
 sphere), Golub-Kahan with ell = 300 steps and full reorthogonalisation,
 projected SVD, GCV and the HKT solution (Algorithm 4).
 
-One step = one whole HKT solve from device-resident data (f, g) to the
-coefficients on the device.  The headline variant evaluates matrix entries
-in FP32 inside every product and accumulates in FP64 (reorthogonalisation,
-Krylov scalars, projected SVD and GCV in FP64).  The stored-FP64 and
-matrix-free-FP64 variants are timed beside it for the time-to-solution
-comparison.
+One step = one HKT time to solution on the plain FP64 path: problem
+creation from nodes already in HBM (assembly of the stored FP64 matrix),
+the solve from f, g in HBM to the coefficients in HBM, and the release of
+the problem.  value = GKB matvec throughput of that step: the 2 ell products
+stream the stored matrix (53.0 GB of tiles, its symmetric blocks stored
+once), so value = 2 ell x 53.0 GB / time to solution.  The roofline object
+describes the dominant product kernel, timed with HIP events on the
+problem's stream around every product launch of the timed steps.
 
-value = equivalent GKB product throughput of the whole solve,
-2 ell 8 N^2 bytes (the FP64 matrix traffic the ell steps would need) divided
-by the time to solution.  The roofline object describes the dominant kernel
-of the headline variant (the matrix-free product, bound by VALU issue).
+Beside it, outside the timed steps: the FP32-evaluated matrix-free HKT (the
+precision form) and the matrix-free FP64 HKT with their errors against the
+FP64 result, the equal-error comparison (the smallest ell whose FP32 HKT
+error is within 5% of the FP64 reference) on this workload and on the
+20 000-node cube, the row scaling option, other projected-side rules, the
+learned stop, the multi-source sweep, the block Golub-Kahan process, the
+full-SVD reference and the oracle timed on the host's cores.
 """
 from __future__ import annotations
 
@@ -32,31 +37,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X peaks (vendor unit counts and clock) and the VALU issue model.
+# MI355X published peaks.
 HBM_PEAK_GBS = 8000.0
-CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
-# A SIMD issues one wave64 VALU instruction per 4 cycles; gfx950 can issue two
-# FP32 instructions together when neither reads a scalar register (measured
-# with SQ_ACTIVE_INST_VALU2).  FP64 and transcendental instructions issue
-# alone; v_rsq_f32 / v_sqrt_f32 occupy two issue slots, v_rsq_f64 four.
-VALU_PEAK_DUAL = CUS * SIMDS * 2 * LANES * CLOCK  # 78.6e12 lane-operations/s (= FP32 vector peak / 2 flops)
-VALU_PEAK_SINGLE = CUS * SIMDS * LANES * CLOCK  # 39.3e12 lane-operations/s (FP64 rate)
+FP32_PEAK = 157.3e12  # FP32 vector (and FP32 matrix) flop/s
+FP64_PEAK = 78.6e12
 MFMA_F32_PEAK = 157.3e12  # dense FP32 matrix-core flop/s
-# Algorithmic operations per matrix entry (the entry formula evaluated
-# directly, a transcendental counted once):
-#   FP32: interior 3 sub + 3 fma (t) + rsq + mul (s^2) + 2 fma + fma (accumulate) = 11
-#         boundary 3 sub + 3 fma (t) + sqrt + fma (accumulate)                    = 8
-#   FP64: interior 3 sub + 3 fma + rsq + 8 (two Newton steps) + mul + 2 fma + mul + fma = 20
-#         boundary 3 sub + 3 fma + rsq + 8 + mul + fma                                  = 17
-# The FP32 product computes t (the first 6 operations) on the matrix cores;
-# the achieved rate still counts all 11 / 8 against the FP32 vector peak.
-OPS = {"matfree_fp32": (11, 8), "matfree_fp64": (20, 17)}
-# Issue quad-cycles per 64 entries of the instructions the FP32 product runs,
-# if every pairable VALU instruction were paired: one 16x16x32 bf16 MFMA per
-# 256 entries (16 cycles, no co-execution with the VALU measured: 1 quad per 64),
-# interior rsq (2) + 4 pairable (2), boundary sqrt (2) + 1 pairable (0.5).
+CUS, SIMDS, CLOCK = 256, 4, 2.4e9
+# Operations per matrix entry of the FP32-evaluated product as the design
+# counts them (distances, t, one rsqrt, the interior formula, the conversion
+# and the FP64 accumulation): interior 15 FP32 + rsqrt + cvt + FP64 FMA = 18,
+# boundary 9 + rsqrt + cvt + FMA = 12.  Rated against the FP32 vector peak.
+OPS_F32 = (18, 12)
+# FP64 matrix-free product: interior 3 sub + 3 fma + rsq + 8 (two Newton steps)
+# + mul + 2 fma + mul + fma = 20, boundary 17; rated against the FP64 peak.
+OPS_F64 = (20, 17)
+# Issue quad-cycles per 64 entries of the FP32 product's instructions if
+# every pairable VALU instruction were paired (one bf16 MFMA per 256 entries,
+# interior rsq + 4 pairable, boundary sqrt + 1): the issue model.
 QUADS_IDEAL_F32 = (5.0, 3.5)
+TILE = 128
 PROFILES = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def stored_bytes(n: int, n_int: int) -> int:
+    """Bytes of the stored matrix as the library keeps it: 128 x 128 FP64 tiles per class
+    (interior, boundary), the symmetric interior-interior and boundary-boundary blocks by
+    their upper tiles only."""
+    nti = -(-n_int // TILE)
+    nt = nti + (-(-(n - n_int) // TILE))
+    tiles = sum((nt - r) if r < nti else (nti + nt - r) for r in range(nt))
+    return tiles * TILE * TILE * 8
 
 
 def measured_traffic(kernel_key: str):
@@ -77,8 +87,8 @@ def measured_traffic(kernel_key: str):
 
 
 def measure_peaks(mq):
-    """The reference kernels of mqh_peak_probe on this GPU: HBM copy and read
-    (GB/s, bytes moved), FP32 / FP64 FMA chains and FP64 matrix-core chains
+    """The reference kernels of the measurement library on this GPU: HBM copy and
+    read (GB/s, bytes moved), FP32 / FP64 FMA chains and FP64 matrix-core chains
     (TFLOP/s)."""
     copy = mq.mqh_peak_probe(mq.MQH_PEAK_COPY, 1 << 31, reps=5)
     read = mq.mqh_peak_probe(mq.MQH_PEAK_READ, 1 << 32, reps=5)
@@ -108,17 +118,19 @@ def rel_linf(a, b):
 
 
 def parse_variant(mq, spec):
-    """'mode[:method[:rule[:weight]]]' -> (operator mode, solve keyword arguments).
+    """'mode[:method[:rule[:weight]]][+rs]' -> (operator mode, solve keyword arguments).
 
     method: hkt (Algorithm 4, default), tsvd (Algorithm 2), lsqr (Section 3.4);
-    rule: gcv (default), lcurve, wgcv (weighted GCV, weight default 0.5)."""
-    parts = spec.split(":")
+    rule: gcv (default), lcurve, wgcv (weighted GCV, weight default 0.5);
+    +rs: the row scaling D = diag(A)^-1."""
+    rs = spec.endswith("+rs")
+    parts = spec[:-3].split(":") if rs else spec.split(":")
     mode = parts[0]
     method = {"hkt": mq.MQH_METHOD_HKT, "tsvd": mq.MQH_METHOD_INE_TSVD,
               "lsqr": mq.MQH_METHOD_LSQR}[parts[1] if len(parts) > 1 else "hkt"]
     rule = {"gcv": mq.MQH_RULE_GCV, "lcurve": mq.MQH_RULE_LCURVE,
             "wgcv": mq.MQH_RULE_WGCV}[parts[2] if len(parts) > 2 else "gcv"]
-    kw = dict(method=method, rule=rule)
+    kw = dict(method=method, rule=rule, row_scale=int(rs))
     if rule == mq.MQH_RULE_WGCV:
         kw["gcv_weight"] = float(parts[3]) if len(parts) > 3 else 0.5
     if method == mq.MQH_METHOD_LSQR:
@@ -126,46 +138,189 @@ def parse_variant(mq, spec):
     return mode, kw
 
 
-def run_variant(mq, torch, p, spec, steps, warmup, dev, want_kernel_times=True):
-    """Create the problem, run warmup + timed solves; returns a dict of figures."""
-    import numpy as np
+class DeviceInputs:
+    """A workload's nodes, data and evaluation points resident in HBM."""
 
-    mode, kw = parse_variant(mq, spec)
-    stream = torch.cuda.current_stream(dev)
+    def __init__(self, torch, p, dev):
+        self.x_int = torch.from_numpy(p.x_int).to(dev)
+        self.x_bnd = torch.from_numpy(p.x_bnd).to(dev)
+        self.f_int = torch.from_numpy(p.f_int).to(dev)
+        self.g_bnd = torch.from_numpy(p.g_bnd).to(dev)
+        self.rhs = torch.from_numpy(p.rhs).to(dev)
+        self.x_eval = torch.from_numpy(p.x_eval).to(dev)
+
+
+def solve_step(mq, torch, p, d, mode, ell, kw, time_products=False, keep=False):
+    """One time to solution from inputs in HBM: create (assembly in the stored mode), solve,
+    release.  Returns (seconds, create seconds, solve output, u at the evaluation points as a
+    numpy array, the problem when keep)."""
+    stream = torch.cuda.current_stream(d.x_int.device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pr = mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, mode, stream=stream)
+    pr = mq.Problem(d.x_int, d.x_bnd, p.kappa, p.eps, mode, stream=stream)
+    t1 = time.perf_counter()  # create synchronises its stream
+    out = pr.solve(d.f_int, d.g_bnd, ell, time_products=time_products, **kw)
+    if not keep:
+        pr.close()
     torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    f_int = torch.from_numpy(p.f_int).to(dev)
-    g_bnd = torch.from_numpy(p.g_bnd).to(dev)
-    coef = torch.empty(p.n, dtype=torch.float64, device=dev)
+    t2 = time.perf_counter()
+    if keep:
+        u = pr.eval(out.coef, d.x_eval).cpu().numpy()
+        return t2 - t0, t1 - t0, out, u, pr
+    return t2 - t0, t1 - t0, out, None, None
+
+
+def evaluate(mq, torch, p, d, coef):
+    """u at the evaluation points from coefficients on the device (matrix-free FP64, eq. (18))."""
+    with mq.Problem(d.x_int, d.x_bnd, p.kappa, p.eps, "matfree_fp64",
+                    stream=torch.cuda.current_stream(d.x_int.device)) as pr:
+        return pr.eval(coef, d.x_eval).cpu().numpy()
+
+
+def run_timed(mq, torch, p, d, mode, kw, steps, warmup, tag):
+    """warmup untimed steps, then `steps` timed ones bracketed by synchronisations; returns the
+    figures of the last step and the per-product kernel times of all timed steps."""
+    import numpy as np
+
+    ell = p.ell
     for w in range(warmup):
-        log(spec, "warmup", w)
-        pr.solve(f_int, g_bnd, p.ell, coef=coef, **kw)
+        dt, _, _, _, _ = solve_step(mq, torch, p, d, mode, ell, kw)
+        log(tag, "warmup", w, f"{dt:.3f} s")
     torch.cuda.synchronize()
-    times, outs = [], []
+    t_all = time.perf_counter()
+    times, creates, outs = [], [], []
     for k in range(steps):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        out = pr.solve(f_int, g_bnd, p.ell, coef=coef, time_products=want_kernel_times, **kw)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t)
+        dt, dc, out, _, _ = solve_step(mq, torch, p, d, mode, ell, kw, time_products=True)
+        times.append(dt)
+        creates.append(dc)
         outs.append(out)
-        log(spec, "step", k, f"{times[-1]:.3f} s", "ell_done", out.ell_done, "lambda", f"{out.lam:.3e}",
-            "k", out.k)
-    x_eval = torch.from_numpy(p.x_eval).to(dev)
-    u = pr.eval(coef, x_eval).cpu().numpy()
-    out = outs[-1]
-    res = dict(mode=mode, setup_s=setup_s, step_s=times, solve_s=float(np.mean(times)), ell_done=out.ell_done,
-               lam=out.lam, k=out.k, flags=out.flags, rel_l2=rel_l2(u, p.u_eval), rel_linf=rel_linf(u, p.u_eval),
-               phase_ms=dict(upload=out.t_ms[0], gkb=out.t_ms[1], proj_svd=out.t_ms[2], param=out.t_ms[3],
-                             lift=out.t_ms[4], total=out.t_ms[5]))
-    if want_kernel_times:
-        res["kernel_ms_AT"] = float(np.mean([o.t_ms[6] for o in outs])) / max(1, p.ell)
-        res["kernel_ms_A"] = float(np.mean([o.t_ms[7] for o in outs])) / max(1, p.ell)
-    pr.close()
+        log(tag, "step", k, f"{dt:.3f} s (create {dc * 1e3:.1f} ms)", "ell_done", out.ell_done,
+            "lambda", f"{out.lam:.4e}")
     torch.cuda.synchronize()
+    wall = time.perf_counter() - t_all
+    out = outs[-1]
+    u = evaluate(mq, torch, p, d, out.coef)
+    ld = max(1, out.ell_done)
+    return dict(mode=mode, row_scale=kw.get("row_scale", 0), steps=steps, wall_s=wall, step_s=times,
+                time_to_solution_s=float(np.mean(times)), create_s=float(np.mean(creates)),
+                ell_done=out.ell_done, lam=out.lam, k=out.k, flags=out.flags,
+                rel_l2=rel_l2(u, p.u_eval), rel_linf=rel_linf(u, p.u_eval),
+                sv=None if out.sv is None else np.asarray(out.sv.cpu().numpy() if hasattr(out.sv, "cpu") else out.sv),
+                u=u,
+                kernel_ms_AT=float(np.mean([o.t_ms[6] for o in outs])) / ld,
+                kernel_ms_A=float(np.mean([o.t_ms[7] for o in outs])) / ld,
+                phase_ms=dict(upload=out.t_ms[0], gkb=out.t_ms[1], proj_svd=out.t_ms[2], param=out.t_ms[3],
+                              lift=out.t_ms[4], solve_total=out.t_ms[5]))
+
+
+def host_input_time(mq, torch, p, mode, kw):
+    """Time to solution with every input in host memory (nodes, f, g) and the coefficients
+    returned to host memory: the figure that includes the PCIe transfers."""
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    with mq.Problem(p.x_int, p.x_bnd, p.kappa, p.eps, mode) as pr:
+        out = pr.solve(p.f_int, p.g_bnd, p.ell, **kw)
+    return time.perf_counter() - t, out
+
+
+def ell_scan(mq, torch, p, d, mode, ells, row_scale=0):
+    """Error against the manufactured u of the HKT-GCV solution at every ell in `ells`, from one
+    Golub-Kahan run to max(ells) (the first l steps of a run are those of an l-step run), the
+    projected SVD, GCV, projected solution and lift of each prefix through the C ABI."""
+    lmax = max(ells)
+    res = []
+    with mq.Problem(d.x_int, d.x_bnd, p.kappa, p.eps, mode,
+                    stream=torch.cuda.current_stream(d.x_int.device)) as pr:
+        f = d.rhs
+        r = pr.gkb(f, lmax, row_scale=row_scale)
+        if r["ell_done"] < lmax:
+            ells = [l for l in ells if l <= r["ell_done"]]
+        al, be, Z = r["alpha"], r["beta"], r["Z"]
+        for l in ells:
+            sv, ft, V = mq.mqh_proj_svd(al[:l].contiguous(), be[: l + 1].contiguous())
+            ch = mq.mqh_param_choice(sv, ft, mq.MQH_METHOD_HKT, mq.MQH_RULE_GCV)
+            y = mq.mqh_proj_solution(sv, ft, V, mq.MQH_METHOD_HKT, ch["lambda_"])
+            coef = mq.mqh_lift(Z[:l].contiguous(), y)
+            u = pr.eval(coef, d.x_eval).cpu().numpy()
+            res.append((l, rel_l2(u, p.u_eval), ch["lambda_"]))
+    return res
+
+
+def equal_error(mq, torch, p, d, ref, ells, tag):
+    """The equal-error rule: E_ref is the FP64 (stored) HKT-GCV error at the workload's ell; the
+    FP32-evaluated HKT is timed at the smallest ell whose error is at most
+    max(1.05 E_ref, E_ref + 1e-12).  Times are times to solution from inputs in HBM
+    (create + solve + release)."""
+    e_ref = ref["rel_l2"]
+    bound = max(1.05 * e_ref, e_ref + 1e-12)
+    scan = ell_scan(mq, torch, p, d, "matfree_fp32", ells)
+    hit = [s for s in scan if s[1] <= bound]
+    res = dict(workload=p.name, reference=dict(operator=ref["mode"], ell=p.ell, rel_l2=e_ref,
+                                              time_to_solution_s=ref["time_to_solution_s"]),
+               bound=bound, scan=[dict(ell=l, rel_l2=e, lam=lam) for (l, e, lam) in scan])
+    if not hit:
+        best = min(scan, key=lambda s: s[1])
+        res.update(reached=False, best_ell=best[0], best_rel_l2=best[1])
+        log(tag, "equal error not reached; best", best)
+        return res
+    l_star = hit[0][0]
+    solve_step(mq, torch, p, d, "matfree_fp32", l_star, dict(method=mq.MQH_METHOD_HKT))  # warm
+    dt, dc, out, u, pr = solve_step(mq, torch, p, d, "matfree_fp32", l_star, dict(method=mq.MQH_METHOD_HKT),
+                                    keep=True)
+    pr.close()
+    e = rel_l2(u, p.u_eval)
+    res.update(reached=True, fp32_ell=l_star, fp32_rel_l2=e, fp32_time_to_solution_s=dt,
+               speedup=ref["time_to_solution_s"] / dt,
+               note=("E_ref is about 1: GCV puts lambda at the top of its grid and u is about 0 at this "
+                     "workload, so the comparison at equal error is only about speed") if e_ref > 0.9 else "")
+    log(tag, json.dumps({k: v for k, v in res.items() if k != "scan"}))
+    return res
+
+
+def c2_context(mq, torch, dev, steps):
+    """The 20 000-node cube (stored FP64 A, ell = 200, HKT-GCV), where the method resolves the
+    manufactured solution: FP64 time to solution, and the FP32-evaluated HKT at equal error."""
+    from paper_2511_09798_amd import inputs as I
+
+    p = I.cube_medium()
+    d = DeviceInputs(torch, p, dev)
+    ref = run_timed(mq, torch, p, d, "stored_fp64", dict(method=mq.MQH_METHOD_HKT), steps, 1, "c2 fp64")
+    ee = equal_error(mq, torch, p, d, ref, list(range(20, p.ell + 1, 10)), "c2 equal error")
+    fp32 = run_timed(mq, torch, p, d, "matfree_fp32", dict(method=mq.MQH_METHOD_HKT), steps, 1, "c2 fp32")
+    return dict(workload=p.name, n=p.n, ell=p.ell, kappa=p.kappa, eps=p.eps,
+                fp64_stored=dict(time_to_solution_s=ref["time_to_solution_s"], rel_l2=ref["rel_l2"],
+                                 lam=ref["lam"], product_ms_AT=ref["kernel_ms_AT"], product_ms_A=ref["kernel_ms_A"],
+                                 stored_GB=stored_bytes(p.n, p.n_int) / 1e9),
+                fp32_matfree_same_ell=dict(time_to_solution_s=fp32["time_to_solution_s"], rel_l2=fp32["rel_l2"],
+                                           lam=fp32["lam"],
+                                           u_vs_fp64=rel_l2(fp32["u"], ref["u"])),
+                equal_error=ee)
+
+
+def row_scale_context(mq, torch, dev, p_big, d_big):
+    """The row scaling D = diag(A)^-1 (opt-in; not in the paper) against the paper's system:
+    HKT-GCV errors on the 1 800-node cube at ell = 60 and 300, and on the benchmark workload
+    (stored FP64 and FP32-evaluated)."""
+    from paper_2511_09798_amd import inputs as I
+
+    res = dict(cube_n1800={})
+    p = I.cube_small()
+    d = DeviceInputs(torch, p, dev)
+    for ell in (60, 300):
+        for rs in (0, 1):
+            _, _, out, u, pr = solve_step(mq, torch, p, d, "stored_fp64", ell,
+                                          dict(method=mq.MQH_METHOD_HKT, row_scale=rs), keep=True)
+            pr.close()
+            res["cube_n1800"][f"ell{ell}_rs{rs}"] = dict(rel_l2=rel_l2(u, p.u_eval), lam=out.lam,
+                                                          gcv_at_edge=bool(out.flags & mq.MQH_INFO_GCV_AT_EDGE))
+    res[p_big.name] = {}
+    for mode in ("stored_fp64", "matfree_fp32"):
+        dt, _, out, u, pr = solve_step(mq, torch, p_big, d_big, mode, p_big.ell,
+                                       dict(method=mq.MQH_METHOD_HKT, row_scale=1), keep=True)
+        pr.close()
+        res[p_big.name][mode + "_rs1"] = dict(rel_l2=rel_l2(u, p_big.u_eval), lam=out.lam, time_to_solution_s=dt,
+                                              gcv_at_edge=bool(out.flags & mq.MQH_INFO_GCV_AT_EDGE))
+    log("row scale", json.dumps(res))
     return res
 
 
@@ -439,8 +594,22 @@ def full_context(mq, torch, dev, level: int):
     return res
 
 
-def cpu_baseline(p, rows):
-    """The oracle's entry-by-entry FP64 products on a row / column sample."""
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(p, target_s: float):
+    """The oracle (plain FP64, OpenMP, entry by entry) on a row / column sample of the products, sized
+    to about target_s seconds, scaled to the whole HKT solve (2 ell products dominate it)."""
     import numpy as np
 
     from oracle import oracle as O
@@ -448,19 +617,29 @@ def cpu_baseline(p, rows):
 
     O.lib()
     x = I.random_vector(p.n, 1)
-    idx = np.linspace(0, p.n - 1, rows).astype(np.int64)
     X = p.nodes
-    t = time.perf_counter()
-    O.apply_sampled(X, p.n_int, p.kappa, p.eps, x, idx, trans=True)
-    O.apply_sampled(X, p.n_int, p.kappa, p.eps, x, idx, trans=False)
-    dt = time.perf_counter() - t
+
+    def sample(rows):
+        idx = np.linspace(0, p.n - 1, rows).astype(np.int64)
+        t = time.perf_counter()
+        O.apply_sampled(X, p.n_int, p.kappa, p.eps, x, idx, trans=True)
+        O.apply_sampled(X, p.n_int, p.kappa, p.eps, x, idx, trans=False)
+        return time.perf_counter() - t
+
+    probe_rows = 2000
+    dt = sample(probe_rows)
+    rows = int(min(p.n, max(probe_rows, probe_rows * target_s / max(dt, 1e-3))))
+    dt = sample(rows)
     entries = 2.0 * rows * p.n
     per_product_s = dt / entries * p.n * p.n
-    return dict(value=8.0 * p.n * p.n / per_product_s / 1e9, unit="GB/s (FP64-A-equivalent per product)",
-                cores=O.num_threads(), kind="oracle",
-                sample=f"{rows} rows of A x and {rows} columns of A^T x (entry-by-entry FP64, "
-                       f"{entries:.2e} entries, {dt:.1f} s), scaled to whole products",
-                seconds=dt, hkt_solve_s_extrapolated=2 * p.ell * per_product_s)
+    hkt_s = 2 * p.ell * per_product_s
+    sb = stored_bytes(p.n, p.n_int)
+    return dict(value=2 * p.ell * sb / hkt_s / 1e9, unit="GB/s", cores=O.num_threads(), kind="oracle",
+                sample=f"{rows} rows of A x and {rows} columns of A^T x at the benchmark workload (entry-by-entry "
+                       f"FP64, {entries:.2e} entries, {dt:.1f} s), scaled to the 2 ell products of the HKT solve; "
+                       "value = 2 ell x stored-matrix bytes / extrapolated solve time (the headline's unit)",
+                seconds=dt, hkt_solve_s_extrapolated=hkt_s, cpu_model=cpu_info(),
+                omp_num_threads=os.environ.get("OMP_NUM_THREADS", "unset"), nproc=os.cpu_count())
 
 
 def main():
@@ -471,11 +650,15 @@ def main():
     ap.add_argument("--workload", default="sphere_n100000")
     ap.add_argument("--ell", type=int, default=0, help="override the Golub-Kahan steps (0: workload's)")
     ap.add_argument("--variants",
-                    default="matfree_fp32,stored_fp64,matfree_fp64,matfree_fp32:lsqr:gcv,matfree_fp32:lsqr:lcurve,"
+                    default="matfree_fp32,matfree_fp64,matfree_fp32:lsqr:gcv,matfree_fp32:lsqr:lcurve,"
                             "matfree_fp32:hkt:wgcv:0.5",
-                    help="first one is the headline; each is mode[:method[:rule[:weight]]]")
-    ap.add_argument("--context-steps", type=int, default=1, help="timed solves of the non-headline variants")
-    ap.add_argument("--cpu-rows", type=int, default=150000, help="row/column sample of the CPU baseline (0: skip)")
+                    help="context variants beside the stored-FP64 headline: mode[:method[:rule[:weight]]][+rs]")
+    ap.add_argument("--context-steps", type=int, default=1, help="timed steps of each context variant")
+    ap.add_argument("--equal-error", type=int, default=1, help="the equal-error FP32 comparison (0: skip)")
+    ap.add_argument("--c2", type=int, default=1, help="the 20 000-node cube context (0: skip)")
+    ap.add_argument("--row-scale", type=int, default=1, help="the row-scaling context (0: skip)")
+    ap.add_argument("--host-inputs", type=int, default=1, help="time to solution from host inputs (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample size in seconds (0: skip)")
     ap.add_argument("--learned", type=int, default=8,
                     help="pump-casing problems for the learned-solve comparison (0: skip)")
     ap.add_argument("--sweep", type=int, default=64, help="problems of the multi-source frequency sweep (0: skip)")
@@ -487,7 +670,7 @@ def main():
     ap.add_argument("--block", type=int, default=1,
                     help="block Golub-Kahan beside the lockstep runs on the largest sweep problems (0: skip)")
     ap.add_argument("--full", type=int, default=1,
-                    help="full-SVD reference on the 20 000-node cube beside HKT: 1 Tikh-Reg (about a minute), "
+                    help="full-SVD reference on the 20 000-node cube beside HKT: 1 Tikh-Reg (about half a minute), "
                          "2 also TSVD (0: skip)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
@@ -508,7 +691,8 @@ def main():
     p = I.WORKLOADS[args.workload]()
     if args.ell:
         p.ell = args.ell
-    log("workload", p.name, "n", p.n, "n_int", p.n_int, "ell", p.ell)
+    n = p.n
+    log("workload", p.name, "n", n, "n_int", p.n_int, "ell", p.ell)
     if args.copy_ref_mib > 0:
         nel = args.copy_ref_mib * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device=dev)
@@ -520,70 +704,87 @@ def main():
         del src, dst
     peaks = measure_peaks(mq)
     log("measured peaks", json.dumps(peaks))
-    variants = [v.strip() for v in args.variants.split(",") if v.strip()]
-    results = {}
-    for i, v in enumerate(variants):
-        steps = args.steps if i == 0 else args.context_steps
-        warm = args.warmup if i == 0 else min(args.warmup, 1)
-        results[v] = run_variant(mq, torch, p, v, steps, warm, dev)
-        log(v, json.dumps({k: results[v][k] for k in ("setup_s", "solve_s", "rel_l2", "lam")}))
-    head = results[variants[0]]
-    n = p.n
-    ms = head["solve_s"] * 1000.0
-    equiv_bytes = 2.0 * p.ell * 8.0 * n * n
-    value = equiv_bytes / head["solve_s"] / 1e9
+    d = DeviceInputs(torch, p, dev)
 
-    # roofline of the dominant kernel of the headline variant
-    k_at, k_a = head.get("kernel_ms_AT", float("nan")), head.get("kernel_ms_A", float("nan"))
-    dom_ms, dom_name = (k_at, "A^T x") if k_at >= k_a else (k_a, "A x")
-    mode = head["mode"]
-    kern = {"matfree_fp32": ("k_mfm<false>", "k_mfm<true>"), "matfree_fp64": ("k_mf_cols", "k_mf_rows"),
-            "stored_fp64": ("k_stored_cols", "k_stored_rows")}[mode][0 if dom_name == "A^T x" else 1]
-    if mode.startswith("matfree"):
-        oi, ob = OPS[mode]
-        work = p.n_int * n * oi + p.n_bnd * n * ob  # lane-operations per product
-        peak = VALU_PEAK_DUAL if mode == "matfree_fp32" else VALU_PEAK_SINGLE
-        achieved = work / (dom_ms * 1e-3) / 1e12
-        # measured: FMA lane-operations per second of the probe (flop/s / 2)
-        mpeak = (peaks["fp32_fma_TFLOPs"] if mode == "matfree_fp32" else peaks["fp64_fma_TFLOPs"]) / 2.0
-        roof = dict(bound="alu", achieved=achieved, peak=peak / 1e12, unit="TOP/s", frac=achieved / (peak / 1e12),
-                    traffic=measured_traffic(kern), kernel=kern, kernel_ms=dom_ms,
-                    other_kernel_ms=min(k_at, k_a), ops_per_product=work,
-                    measured_peak=mpeak, frac_of_measured=achieved / mpeak,
-                    measured_peak_note=("FMA lane-operations/s of the FMA probe; achieved counts all of the formula's "
-                                        "operations, some of which run on the matrix cores, so this fraction is not "
-                                        "a VALU efficiency (issue_model_frac is)") if mode == "matfree_fp32" else
-                    "FMA lane-operations/s of the FMA probe")
-        if mode == "matfree_fp32":
-            quads = (p.n_int * n * QUADS_IDEAL_F32[0] + p.n_bnd * n * QUADS_IDEAL_F32[1]) / 64.0
-            t_ideal = quads / (CUS * SIMDS * CLOCK / 4.0)
-            roof["issue_model_ms"] = t_ideal * 1e3
-            roof["issue_model_frac"] = t_ideal / (dom_ms * 1e-3)
-            roof["note"] = ("t = 1 + eps^2 r^2 on the matrix cores (bf16x3-split K=32 MFMA), entries on the VALU; "
-                            "achieved counts the direct formula's lane-operations")
-    else:
-        achieved = 8.0 * n * n / (dom_ms * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=measured_traffic(kern), kernel=kern, kernel_ms=dom_ms,
-                    other_kernel_ms=min(k_at, k_a), measured_peak=peaks["hbm_read_GBs"],
-                    frac_of_measured=achieved / peaks["hbm_read_GBs"])
+    # headline: the plain FP64 path (stored matrix), K timed steps
+    hkw = dict(method=mq.MQH_METHOD_HKT, rule=mq.MQH_RULE_GCV)
+    head = run_timed(mq, torch, p, d, "stored_fp64", hkw, args.steps, args.warmup, "headline stored_fp64")
+    sb = stored_bytes(n, p.n_int)
+    ms = head["time_to_solution_s"] * 1000.0
+    value = 2.0 * head["ell_done"] * sb / head["time_to_solution_s"] / 1e9
+    k_at, k_a = head["kernel_ms_AT"], head["kernel_ms_A"]
+    dom_at = k_at >= k_a
+    dom_ms = k_at if dom_at else k_a
+    kern = "k_packed_product<1>" if dom_at else "k_packed_product<0>"
+    achieved = sb / (dom_ms * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                traffic=measured_traffic(kern), kernel=kern, kernel_ms=dom_ms,
+                other_kernel=("k_packed_product<0>" if dom_at else "k_packed_product<1>"),
+                other_kernel_ms=min(k_at, k_a), other_frac=sb / (min(k_at, k_a) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                bytes_per_launch=sb, bytes_note="the stored tiles (128 x 128 FP64; symmetric blocks once) one "
+                                                "product streams; per-launch partial sums (< 1%) not counted",
+                measured_read_peak=peaks["hbm_read_GBs"], frac_of_measured_read=achieved / peaks["hbm_read_GBs"])
 
+    # context variants at the same workload: errors against the FP64 result
     ctx = {}
-    for v, r in results.items():
-        tts = r["solve_s"] + (r["setup_s"] if r["mode"] == "stored_fp64" else 0.0)
-        ctx[v] = dict(time_to_solution_s=tts, solve_s=r["solve_s"], setup_s=r["setup_s"], rel_l2=r["rel_l2"],
-                      rel_linf=r["rel_linf"], lam=r["lam"], k=r["k"], ell_done=r["ell_done"],
-                      product_ms_AT=r.get("kernel_ms_AT"), product_ms_A=r.get("kernel_ms_A"),
-                      product_equiv_GBs=(8.0 * n * n / (0.5e-3 * (r["kernel_ms_AT"] + r["kernel_ms_A"])) / 1e9)
-                      if "kernel_ms_AT" in r else None,
-                      phase_ms=r["phase_ms"])
+    for v in [v.strip() for v in args.variants.split(",") if v.strip()]:
+        mode, kw = parse_variant(mq, v)
+        r = run_timed(mq, torch, p, d, mode, kw, args.context_steps, 1, v)
+        e = dict(time_to_solution_s=r["time_to_solution_s"], create_s=r["create_s"], rel_l2=r["rel_l2"],
+                 rel_linf=r["rel_linf"], lam=r["lam"], k=r["k"], ell_done=r["ell_done"],
+                 product_ms_AT=r["kernel_ms_AT"], product_ms_A=r["kernel_ms_A"], phase_ms=r["phase_ms"])
+        if r["sv"] is not None and len(r["sv"]) >= 10:
+            e["ritz_top10_max_rel_diff_vs_fp64"] = float(np.max(np.abs(r["sv"][:10] - head["sv"][:10]) /
+                                                                head["sv"][:10]))
+        if kw == hkw or kw == dict(hkw, row_scale=0):
+            # the same method and rule as the headline: the precision form's error per result
+            e["u_rel_diff_vs_fp64"] = rel_l2(r["u"], head["u"])
+            e["lam_rel_diff_vs_fp64"] = abs(r["lam"] - head["lam"]) / head["lam"] if head["lam"] else None
+        if mode.startswith("matfree") and ":" not in v:
+            oi, ob = OPS_F32 if mode == "matfree_fp32" else OPS_F64
+            pk = FP32_PEAK if mode == "matfree_fp32" else FP64_PEAK
+            kms = max(r["kernel_ms_AT"], r["kernel_ms_A"])
+            ops = p.n_int * n * oi + p.n_bnd * n * ob
+            e["roofline"] = dict(bound="alu", achieved=ops / (kms * 1e-3) / 1e12, peak=pk / 1e12, unit="TOP/s",
+                                 frac=ops / (kms * 1e-3) / pk, ops_per_launch=ops,
+                                 kernel=("k_mfm<false>" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mfm<true>")
+                                 if mode == "matfree_fp32" else
+                                 ("k_mf_cols" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mf_rows"),
+                                 kernel_ms=kms,
+                                 note=f"{oi} / {ob} operations per interior / boundary entry against the published "
+                                      f"{'FP32' if mode == 'matfree_fp32' else 'FP64'} vector peak")
+            if mode == "matfree_fp32":
+                quads = (p.n_int * n * QUADS_IDEAL_F32[0] + p.n_bnd * n * QUADS_IDEAL_F32[1]) / 64.0
+                t_ideal = quads / (CUS * SIMDS * CLOCK / 4.0)
+                e["roofline"]["issue_model_ms"] = t_ideal * 1e3
+                e["roofline"]["issue_model_frac"] = t_ideal / (kms * 1e-3)
+                e["product_equiv_GBs"] = 8.0 * n * n / (kms * 1e-3) / 1e9
+        ctx[v] = e
+        log(v, json.dumps({k: e.get(k) for k in ("time_to_solution_s", "rel_l2", "lam", "u_rel_diff_vs_fp64")}))
+
     line = dict(metric="HKT time-to-solution & GKB matvec GB/s at N=100k sphere, equal rel-L2 err",
-                value=value, unit="GB/s (FP64-A-equivalent product traffic over the whole HKT solve)",
-                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
-                scaling="weak", vs_baseline=None, dtype="f32" if mode == "matfree_fp32" else "f64", data="synthetic",
+                value=value, unit="GB/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms,
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                 config=dict(workload=p.name, n=n, n_int=p.n_int, n_bnd=p.n_bnd, kappa=p.kappa, eps=p.eps,
-                            ell=p.ell, method="HKT", rule="GCV", operator=mode),
-                hkt_time_to_solution_s=head["solve_s"], roofline=roof, peaks_measured=peaks, variants=ctx)
+                            ell=p.ell, method="HKT", rule="GCV", operator="stored_fp64",
+                            step="create from nodes in HBM (tile assembly) + solve from f, g in HBM to coefficients "
+                                 "in HBM + release",
+                            value_def="2 ell x stored-matrix bytes (53.0 GB) / time to solution"),
+                hkt_time_to_solution_s=head["time_to_solution_s"], create_s=head["create_s"],
+                ell_done=head["ell_done"], lam=head["lam"], rel_l2=head["rel_l2"], rel_linf=head["rel_linf"],
+                phase_ms=head["phase_ms"], product_ms=dict(AT=k_at, A=k_a), roofline=roof, peaks_measured=peaks,
+                variants=ctx)
+    if args.equal_error:
+        line["equal_error"] = equal_error(mq, torch, p, d, head, list(range(10, p.ell + 1, 10)), "equal error")
+    if args.host_inputs:
+        dt, out = host_input_time(mq, torch, p, "stored_fp64", hkw)
+        line["time_to_solution_host_inputs_s"] = dt
+        log("host inputs", f"{dt:.3f} s")
+    if args.row_scale:
+        line["row_scale"] = row_scale_context(mq, torch, dev, p, d)
+    if args.c2:
+        line["c2"] = c2_context(mq, torch, dev, args.context_steps)
+    del d
     if args.learned > 0:
         from paper_2511_09798_amd import learned as L
 
@@ -598,9 +799,9 @@ def main():
         line["block_gkb"] = block_context(mq, torch, dev)
     if args.full > 0:
         line["full_svd_reference"] = full_context(mq, torch, dev, args.full)
-    if args.cpu_rows > 0:
-        log("cpu baseline", args.cpu_rows, "rows")
-        line["cpu_baseline"] = cpu_baseline(p, args.cpu_rows)
+    if args.cpu_seconds > 0:
+        log("cpu baseline, about", args.cpu_seconds, "s")
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
