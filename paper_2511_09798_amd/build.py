@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmqhelm.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["op_kernels.hip", "gkb_kernels.hip", "proj_kernels.hip", "mlp_kernels.hip", "full_kernels.hip",
+SOURCES = ["op_kernels.hip", "stored_kernels.hip", "gkb_kernels.hip", "proj_kernels.hip", "mlp_kernels.hip", "full_kernels.hip",
            "peak_kernels.hip", "block_kernels.hip", "capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
