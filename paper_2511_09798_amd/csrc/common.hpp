@@ -20,6 +20,12 @@ struct GkbState {
     int32_t flag;      // 0, 1 = alpha breakdown, 2 = beta breakdown
     int32_t pad;
     double scale;      // running max of alpha_j, beta_{j+1}: the operator scale
+    // copies of stopped and scale taken by the kernel that produces a norm's
+    // partial sums; the normalisation kernel decides from these while its
+    // block 0 updates stopped and scale
+    int32_t snap_stopped;
+    int32_t pad2;
+    double snap_scale;
 };
 
 // Per-batch-slice strides of a kernel's pointer arguments (in elements):

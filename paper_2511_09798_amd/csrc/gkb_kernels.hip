@@ -27,6 +27,9 @@ __global__ void k_init_state(GkbState* st, int32_t ell, double* alpha, double* b
         st->flag = 0;
         st->pad = 0;
         st->scale = 0.0;
+        st->snap_stopped = 0;
+        st->pad2 = 0;
+        st->snap_scale = 0.0;
     }
     if (alpha != nullptr && i < ell) alpha[i] = 0.0;
     if (beta != nullptr && i <= ell) beta[i] = 0.0;
@@ -55,13 +58,18 @@ __global__ void k_scale(double* __restrict__ x, int64_t n, double a, int64_t str
 
 // partial[b] = sum of x_i^2 over the grid-stride share of block b.
 __global__ __launch_bounds__(kBlock) void k_sumsq_partial(const double* __restrict__ x, int64_t n,
-                                                          double* __restrict__ partial,
-                                                          const GkbState* __restrict__ st, Bz bz) {
+                                                          double* __restrict__ partial, GkbState* __restrict__ st,
+                                                          Bz bz) {
     __shared__ double lds[kBlock / kWave];
     const int64_t z = blockIdx.z;  // batch: x + z bz.a, partial + z bz.b, state z
     x += z * bz.a;
     partial += z * bz.b;
     if (st != nullptr) st += z;
+    if (st != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+        // the state the normalisation that consumes these partials decides from
+        st->snap_stopped = st->stopped;
+        st->snap_scale = st->scale;
+    }
     if (st != nullptr && st->stopped) return;  // uniform over the grid
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
@@ -75,11 +83,10 @@ __global__ __launch_bounds__(kBlock) void k_sumsq_partial(const double* __restri
 // alpha_{j+1}; kind 2: beta_{j+2}, 0-based j).  The threshold is
 // n * DBL_EPSILON * (running max of alpha, beta_{>=2}).  Every block sums the
 // partials in the same order (thread t takes t, t + 256, ..., then the block
-// reduction), so all blocks hold the same norm and take the same decision;
-// block 0 records it.  Block 0 may raise the running scale to this norm while
-// other blocks read it, but a norm above the old threshold is also above the
-// raised one (n DBL_EPSILON < 1), and after a breakdown the scale is left as
-// it was, so the decision does not depend on that order.  With Vg, the
+// reduction), so all blocks hold the same norm and take the same decision
+// from the same state: the snapshot (snap_stopped, snap_scale) that the
+// kernel producing the partials wrote, which no block of this launch writes;
+// block 0 records the decision in stopped, scale and the scalars.  With Vg, the
 // normalised vector also goes, in FP32, to column z of the sorted
 // block-product operand, Vg[iperm[i]][z] (zeros for a stopped run).
 __global__ __launch_bounds__(kBlock) void k_finalize_scale(const double* __restrict__ partial, int nparts, int kind,
@@ -98,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_scale(const double* __restr
     dst += z * bz.d;
     st += z;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (threadIdx.x == 0) s_stopped = st->stopped;
+    if (threadIdx.x == 0) s_stopped = st->snap_stopped;
     __syncthreads();
     if (s_stopped) {  // block-uniform
         if (Vg != nullptr && i < n) Vg[(int64_t)iperm[i] * kBlkRhs + z] = 0.f;
@@ -112,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_scale(const double* __restr
     if (kind == 0) {
         ok = nrm > 0.0;
     } else {
-        const double tau = (double)n * DBL_EPSILON * st->scale;
+        const double tau = (double)n * DBL_EPSILON * st->snap_scale;
         ok = nrm > tau;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -141,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_scale(const double* __restr
                 beta[j + 1] = nrm;
             }
         }
-        if (ok && kind != 0 && nrm > st->scale) st->scale = nrm;
+        if (ok && kind != 0 && nrm > st->snap_scale) st->scale = nrm;
     }
     if (i >= n) return;
     if (!ok) {
@@ -233,8 +240,8 @@ __global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restric
 // x_i -= sum_k V[k][i] c_k; optionally partial[b] = sum over the block of the updated x_i^2.
 __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V, int64_t ldn, int64_t n, int32_t m,
                                                    const double* __restrict__ c, double* __restrict__ x,
-                                                   double* __restrict__ sumsq_partial,
-                                                   const GkbState* __restrict__ st, Bz bz) {
+                                                   double* __restrict__ sumsq_partial, GkbState* __restrict__ st,
+                                                   Bz bz) {
     __shared__ double lds[kBlock / kWave];
     const int64_t z = blockIdx.z;  // batch: V + z bz.a, c + z bz.b, x + z bz.c, sumsq + z bz.d, state z
     V += z * bz.a;
@@ -242,6 +249,11 @@ __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V,
     x += z * bz.c;
     if (sumsq_partial != nullptr) sumsq_partial += z * bz.d;
     if (st != nullptr) st += z;
+    if (st != nullptr && sumsq_partial != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+        // the state the normalisation that consumes these partials decides from
+        st->snap_stopped = st->stopped;
+        st->snap_scale = st->scale;
+    }
     if (st != nullptr && st->stopped) return;  // uniform over the grid
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double xi = 0.0;
@@ -331,11 +343,11 @@ int sumsq_blocks(int64_t n) {
     return (int)(nb < 1024 ? nb : 1024);
 }
 
-void launch_sumsq_partial(const double* x, int64_t n, double* partial, int nb, const GkbState* st, hipStream_t s) {
+void launch_sumsq_partial(const double* x, int64_t n, double* partial, int nb, GkbState* st, hipStream_t s) {
     launch_sumsq_partial_b(x, n, partial, nb, st, 1, Bz{}, s);
 }
 
-void launch_sumsq_partial_b(const double* x, int64_t n, double* partial, int nb, const GkbState* st, int nz, Bz bz,
+void launch_sumsq_partial_b(const double* x, int64_t n, double* partial, int nb, GkbState* st, int nz, Bz bz,
                             hipStream_t s) {
     k_sumsq_partial<<<dim3(nb, 1, nz), kBlock, 0, s>>>(x, n, partial, st, bz);
 }
@@ -369,12 +381,12 @@ void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const do
 }
 
 void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
-                   double* sumsq_partial, const GkbState* st, hipStream_t s) {
+                   double* sumsq_partial, GkbState* st, hipStream_t s) {
     launch_update_b(V, ldn, n, m, c, x, sumsq_partial, st, 1, Bz{}, s);
 }
 
 void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
-                     double* sumsq_partial, const GkbState* st, int nz, Bz bz, hipStream_t s) {
+                     double* sumsq_partial, GkbState* st, int nz, Bz bz, hipStream_t s) {
     k_update<<<dim3((unsigned)((n + kBlock - 1) / kBlock), 1, nz), kBlock, 0, s>>>(V, ldn, n, m, c, x, sumsq_partial,
                                                                                  st, bz);
 }

@@ -113,7 +113,7 @@ void launch_fill(double* x, int64_t n, double v, hipStream_t s);
 // x[z stride + i] *= a for i < n, z < nz
 void launch_scale(double* x, int64_t n, double a, int nz, int64_t stride, hipStream_t s);
 int sumsq_blocks(int64_t n);
-void launch_sumsq_partial(const double* x, int64_t n, double* partial, int nb, const GkbState* st, hipStream_t s);
+void launch_sumsq_partial(const double* x, int64_t n, double* partial, int nb, GkbState* st, hipStream_t s);
 // norm of x from partial sums of squares, breakdown test, dst = x / norm
 void launch_finalize_scale(const double* partial, int nparts, int kind, int32_t j, int64_t n, double* alpha,
                            double* beta, GkbState* st, const double* x, double* dst, hipStream_t s);
@@ -123,12 +123,12 @@ void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const doub
                   const GkbState* st, hipStream_t s);
 int update_blocks(int64_t n);
 void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
-                   double* sumsq_partial, const GkbState* st, hipStream_t s);
+                   double* sumsq_partial, GkbState* st, hipStream_t s);
 void launch_lift(const double* Z, int64_t ldz, int64_t n, int32_t ell, const int32_t* ell_ptr, const double* y,
                  double* coef, hipStream_t s, int nz = 1, Bz bz = Bz{});
 // batched forms: nz slices, strides per slice as stated at the kernels
 void launch_init_state_b(GkbState* st, int32_t ell, double* alpha, double* beta, int nz, Bz bz, hipStream_t s);
-void launch_sumsq_partial_b(const double* x, int64_t n, double* partial, int nb, const GkbState* st, int nz, Bz bz,
+void launch_sumsq_partial_b(const double* x, int64_t n, double* partial, int nb, GkbState* st, int nz, Bz bz,
                             hipStream_t s);
 // iperm / Vg: also write the normalised vectors into the sorted FP32
 // block-product operand (both NULL: not)
@@ -138,7 +138,7 @@ void launch_finalize_scale_b(const double* partial, int nparts, int kind, int32_
 void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* x, double* partial, double* c,
                     const GkbState* st, int nz, int64_t sV, int64_t sx, int64_t sp, int64_t sc, hipStream_t s);
 void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
-                     double* sumsq_partial, const GkbState* st, int nz, Bz bz, hipStream_t s);
+                     double* sumsq_partial, GkbState* st, int nz, Bz bz, hipStream_t s);
 void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
 
 // projected problem (proj_kernels.hip)
