@@ -48,7 +48,9 @@ extern "C" {
 /* ---- status codes ---- */
 #define MQH_OK 0
 #define MQH_EINVAL (-1)   /* bad argument: NaN/Inf input, n <= 0, eps <= 0, ell < 1, ell > n or > MQH_MAX_ELL, ... */
-#define MQH_ENOMEM (-2)   /* device allocation failed (e.g. the stored matrix does not fit) */
+#define MQH_ENOMEM (-2)   /* device allocation failed (e.g. the stored matrix does not fit), or it would take
+                             the library past the cap set by the environment variable MQH_DEVICE_MEM_CAP
+                             (bytes; read at every allocation; unset or empty: no cap) */
 #define MQH_EDEVICE (-3)  /* a HIP runtime call or kernel launch failed */
 #define MQH_WBREAKDOWN 1  /* Golub-Kahan stopped early (ell_done < ell); outputs valid for ell_done steps */
 #define MQH_WEDGE 2       /* chosen lambda sits at an end of the search grid */
@@ -207,6 +209,10 @@ int mqh_problem_destroy(mqh_problem* p);
 
 /* Problem size n = n_int + n_bnd, or -1 for NULL. */
 int64_t mqh_problem_size(const mqh_problem* p);
+
+/* Bytes of device memory the library holds at this moment, over all problems
+ * and devices (what MQH_DEVICE_MEM_CAP is compared with). */
+int64_t mqh_device_bytes(void);
 
 /*
  * One product of the Golub-Kahan recurrence (Algorithm 1, steps 3 and 5):

@@ -18,6 +18,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -55,22 +56,64 @@ int hip_fail(hipError_t e, const char* what) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Device memory the library holds (every allocation goes through dalloc),
+// and an optional cap from the environment variable MQH_DEVICE_MEM_CAP
+// (bytes): an allocation that would take the library past the cap fails with
+// MQH_ENOMEM before hipMalloc is called.
+std::mutex g_mem_mu;
+std::unordered_map<void*, size_t> g_mem_sizes;
+size_t g_mem_bytes = 0;
+
+int64_t mem_cap() {
+    const char* v = getenv("MQH_DEVICE_MEM_CAP");
+    if (v == nullptr || *v == '\0') return -1;
+    char* end = nullptr;
+    const long long c = strtoll(v, &end, 10);
+    return (end != v && *end == '\0' && c >= 0) ? (int64_t)c : -1;
+}
+
 template <typename T>
 int dalloc(T** p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    const size_t bytes = count * sizeof(T);
+    const int64_t cap = mem_cap();
+    {
+        std::lock_guard<std::mutex> lock(g_mem_mu);
+        if (cap >= 0 && g_mem_bytes + bytes > (size_t)cap)
+            return fail(MQH_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes would take the library "
+                                    "past MQH_DEVICE_MEM_CAP = " + std::to_string(cap) + " bytes (" +
+                                    std::to_string(g_mem_bytes) + " held)");
+        g_mem_bytes += bytes;  // reserved; released below if hipMalloc fails
+    }
+    hipError_t e = hipMalloc((void**)p, bytes);
+    std::lock_guard<std::mutex> lock(g_mem_mu);
     if (e != hipSuccess) {
         *p = nullptr;
+        g_mem_bytes -= bytes;
         (void)hipGetLastError();
         return hip_fail(e, "hipMalloc");
     }
+    g_mem_sizes[(void*)*p] = bytes;
     return MQH_OK;
+}
+
+void dfree_raw(void* p) {
+    if (p == nullptr) return;
+    {
+        std::lock_guard<std::mutex> lock(g_mem_mu);
+        auto it = g_mem_sizes.find(p);
+        if (it != g_mem_sizes.end()) {
+            g_mem_bytes -= it->second;
+            g_mem_sizes.erase(it);
+        }
+    }
+    (void)hipFree(p);
 }
 
 template <typename T>
 void dfree(T*& p) {
-    if (p != nullptr) (void)hipFree((void*)p);
+    dfree_raw((void*)p);
     p = nullptr;
 }
 
@@ -1655,6 +1698,11 @@ const char* mqh_last_error(void) { return g_last_error.c_str(); }
 
 int64_t mqh_problem_size(const mqh_problem* p) { return p ? p->n : -1; }
 
+int64_t mqh_device_bytes(void) {
+    std::lock_guard<std::mutex> lock(g_mem_mu);
+    return (int64_t)g_mem_bytes;
+}
+
 int mqh_problem_destroy(mqh_problem* p) {
     if (p == nullptr) return MQH_OK;
     (void)hipSetDevice(p->device);
@@ -2691,7 +2739,7 @@ namespace {
 struct Tmp {
     std::vector<void*> bufs;
     ~Tmp() {
-        for (void* b : bufs) (void)hipFree(b);
+        for (void* b : bufs) dfree_raw(b);
     }
     template <typename T>
     int get(T** p, size_t count) {

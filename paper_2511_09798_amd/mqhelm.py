@@ -116,6 +116,7 @@ _SIGNATURES = {
     "mqh_problem_create": (ctypes.c_int, [_vp, _i64, _vp, _i64, _d, _d, _i32, _vp, _u32, ctypes.POINTER(_vp)]),
     "mqh_problem_destroy": (ctypes.c_int, [_vp]),
     "mqh_problem_size": (_i64, [_vp]),
+    "mqh_device_bytes": (_i64, []),
     "mqh_apply": (ctypes.c_int, [_vp, _i32, _vp, _d, _vp, _vp, _u32]),
     "mqh_matrix_rows": (ctypes.c_int, [_vp, _i64, _i64, _vp, _u32]),
     "mqh_gkb": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp, ctypes.POINTER(_i32), _u32]),
@@ -264,6 +265,11 @@ def mqh_problem_create(x_int, x_bnd, kappa: float, eps: float, op_mode: int, str
     _check(lib.mqh_problem_create(pi, n_int, pb, n_bnd, float(kappa), float(eps), int(op_mode), _stream_of(stream),
                                   fl, ctypes.byref(h)), "mqh_problem_create")
     return h
+
+
+def mqh_device_bytes() -> int:
+    """Bytes of device memory the library holds (compared with MQH_DEVICE_MEM_CAP)."""
+    return int(lib.mqh_device_bytes())
 
 
 def mqh_problem_destroy(h) -> None:
