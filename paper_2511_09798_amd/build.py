@@ -61,6 +61,41 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+             "-fno-omit-frame-pointer"]
+SAN_DRIVER = os.path.join(ROOT, "tests", "host", "capi_san_main.cpp")
+SAN_EXE = os.path.join(ROOT, "tests", "host", "capi_san")
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """A test executable that drives the C ABI (tests/host/capi_san_main.cpp) through the
+    library's sources with AddressSanitizer and UndefinedBehaviorSanitizer on the host code
+    (device code is built as usual); returns its path."""
+    objdir = os.path.join(OBJDIR, "san")
+    os.makedirs(objdir, exist_ok=True)
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"] + SAN_FLAGS
+
+    def comp(src):
+        obj = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + ".o")
+        res = subprocess.run([HIPCC, *flags, "-c", src, "-o", obj], capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"sanitized build failed for {src}:\n{res.stderr}")
+        return obj
+
+    srcs = [os.path.join(CSRC, s) for s in SOURCES] + [SAN_DRIVER]
+    with cf.ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+        objs = list(ex.map(comp, srcs))
+    tmp = SAN_EXE + ".tmp"
+    res = subprocess.run([HIPCC, "--offload-arch=gfx950", *SAN_FLAGS, *objs, "-o", tmp], capture_output=True,
+                         text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"sanitized link failed:\n{res.stderr}")
+    os.replace(tmp, SAN_EXE)
+    if verbose:
+        print(f"built {SAN_EXE}")
+    return SAN_EXE
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
