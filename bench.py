@@ -86,15 +86,17 @@ def measured_traffic(kernel_key: str):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
-def measure_peaks(mq):
-    """The reference kernels of the measurement library on this GPU: HBM copy and
-    read (GB/s, bytes moved), FP32 / FP64 FMA chains and FP64 matrix-core chains
+def measure_peaks():
+    """The reference kernels of the measurement library (libmqhpeak) on this GPU: HBM copy
+    and read (GB/s, bytes moved), FP32 / FP64 FMA chains and FP64 matrix-core chains
     (TFLOP/s)."""
-    copy = mq.mqh_peak_probe(mq.MQH_PEAK_COPY, 1 << 31, reps=5)
-    read = mq.mqh_peak_probe(mq.MQH_PEAK_READ, 1 << 32, reps=5)
-    f32 = mq.mqh_peak_probe(mq.MQH_PEAK_FMA_F32, 1 << 14, reps=5)
-    f64 = mq.mqh_peak_probe(mq.MQH_PEAK_FMA_F64, 1 << 14, reps=5)
-    m64 = mq.mqh_peak_probe(mq.MQH_PEAK_MFMA_F64, 1 << 14, reps=5)
+    from paper_2511_09798_amd import peak as pk
+
+    copy = pk.mqh_peak_probe(pk.MQH_PEAK_COPY, 1 << 31, reps=5)
+    read = pk.mqh_peak_probe(pk.MQH_PEAK_READ, 1 << 32, reps=5)
+    f32 = pk.mqh_peak_probe(pk.MQH_PEAK_FMA_F32, 1 << 14, reps=5)
+    f64 = pk.mqh_peak_probe(pk.MQH_PEAK_FMA_F64, 1 << 14, reps=5)
+    m64 = pk.mqh_peak_probe(pk.MQH_PEAK_MFMA_F64, 1 << 14, reps=5)
     return dict(hbm_copy_GBs=copy / 1e9, hbm_read_GBs=read / 1e9, fp32_fma_TFLOPs=f32 / 1e12, fp64_fma_TFLOPs=f64 / 1e12,
                 fp64_mfma_TFLOPs=m64 / 1e12,
                 spec=dict(hbm_GBs=HBM_PEAK_GBS, fp32_vector_TFLOPs=157.3, fp64_vector_TFLOPs=78.6,
@@ -702,7 +704,7 @@ def main():
         torch.cuda.synchronize()
         log("copy reference", args.copy_ref_mib, "MiB read +", args.copy_ref_mib, "MiB written")
         del src, dst
-    peaks = measure_peaks(mq)
+    peaks = measure_peaks()
     log("measured peaks", json.dumps(peaks))
     d = DeviceInputs(torch, p, dev)
 

@@ -556,35 +556,6 @@ int mqh_full_solve(mqh_problem* p, const double* f_int, const double* g_bnd, con
                    double* sv, mqh_solve_info* info);
 
 /*
- * Measurement helper, not part of the method: the rate of a reference
- * kernel on the current device, against which the rooflines' spec peaks can
- * be checked (MI355X spec: HBM 8 TB/s, FP32 and FP64 vector 157.3 and
- * 78.6 TFLOP/s, FP64 matrix 78.6 TFLOP/s).
- *   MQH_PEAK_COPY:     device-to-device copy of size bytes (rounded down to
- *                      16 B); rate = bytes read + written per second.
- *   MQH_PEAK_FMA_F32:  chains of FP32 FMA (unpacked, as every kernel of this
- *                      library is built; operands in vector registers, so
- *                      the SIMD may issue two at once), size iterations;
- *                      rate = flop/s (2 per FMA).
- *   MQH_PEAK_FMA_F64:  the same in FP64.
- *   MQH_PEAK_MFMA_F64: chains of v_mfma_f64_16x16x4f64, size iterations;
- *                      rate = flop/s.
- *   MQH_PEAK_READ:     read-only stream of size bytes (summed per thread);
- *                      rate = bytes read per second.
- * One warm-up launch, then reps timed launches (HIP events) on stream (NULL:
- * a stream of its own).  The library allocates and frees the buffers
- * (2 x size bytes for the copy).  MQH_EINVAL for an unknown kind, reps
- * outside [1, 1000], a copy or read outside [16 B, 64 GiB] or iterations
- * outside [1, 2^20].
- */
-#define MQH_PEAK_COPY 0
-#define MQH_PEAK_FMA_F32 1
-#define MQH_PEAK_FMA_F64 2
-#define MQH_PEAK_MFMA_F64 3
-#define MQH_PEAK_READ 4
-int mqh_peak_probe(int32_t kind, int64_t size, int32_t reps, double* rate, void* stream);
-
-/*
  * The predictor network's kernels (FP32; every array is a device pointer and
  * flags must contain MQH_FLAG_DEVICE_PTRS).  Batches are row-major.
  *   mqh_mlp_forward:  y (batch x 2) from x (batch x 24); hidden receives the

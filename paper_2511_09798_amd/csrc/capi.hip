@@ -2610,79 +2610,6 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     return MQH_OK;
 }
 
-int mqh_peak_probe(int32_t kind, int64_t size, int32_t reps, double* rate, void* stream) {
-    if (rate == nullptr) return fail(MQH_EINVAL, "NULL rate");
-    *rate = 0.0;
-    if (kind < MQH_PEAK_COPY || kind > MQH_PEAK_READ) return fail(MQH_EINVAL, "unknown probe kind");
-    if (reps < 1 || reps > 1000) return fail(MQH_EINVAL, "reps must be in [1, 1000]");
-    const bool stream_kind = kind == MQH_PEAK_COPY || kind == MQH_PEAK_READ;
-    if (stream_kind && (size < 16 || size > ((int64_t)64 << 30)))
-        return fail(MQH_EINVAL, "copy / read size must be in [16 B, 64 GiB]");
-    if (!stream_kind && (size < 1 || size > (1 << 20))) return fail(MQH_EINVAL, "iterations must be in [1, 2^20]");
-    hipStream_t s = (hipStream_t)stream;
-    hipStream_t own = nullptr;
-    if (s == nullptr) {
-        HIPCHK(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
-        s = own;
-    }
-    struct Cleanup {
-        hipStream_t own = nullptr;
-        double* a = nullptr;
-        double* b = nullptr;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        ~Cleanup() {
-            dfree(a);
-            dfree(b);
-            if (e0) (void)hipEventDestroy(e0);
-            if (e1) (void)hipEventDestroy(e1);
-            if (own) (void)hipStreamDestroy(own);
-        }
-    } c;
-    c.own = own;
-    int rc;
-    const int64_t count = stream_kind ? (size / 16) * 2 : (int64_t)peak_blocks() * kBlock;
-    if ((rc = dalloc(&c.a, (size_t)count))) return rc;
-    if (stream_kind) {
-        // b: the copy's destination, or the read's per-thread sums
-        const int64_t nb = kind == MQH_PEAK_COPY ? count : (int64_t)peak_blocks() * kBlock;
-        if ((rc = dalloc(&c.b, (size_t)nb))) return rc;
-        HIPCHK(hipMemsetAsync(c.a, 0, (size_t)count * sizeof(double), s));
-    }
-    HIPCHK(hipEventCreate(&c.e0));
-    HIPCHK(hipEventCreate(&c.e1));
-    const int iters = (int)size;
-    auto launch = [&]() {
-        switch (kind) {
-            case MQH_PEAK_COPY: launch_peak_copy(c.a, c.b, count, s); break;
-            case MQH_PEAK_READ: launch_peak_read(c.a, count, c.b, s); break;
-            case MQH_PEAK_FMA_F32: launch_peak_fma32(reinterpret_cast<float*>(c.a), iters, s); break;
-            case MQH_PEAK_FMA_F64: launch_peak_fma64(c.a, iters, s); break;
-            default: launch_peak_mfma64(c.a, iters, s); break;
-        }
-    };
-    launch();  // warm-up
-    LAUNCHCHK("peak probe");
-    HIPCHK(hipEventRecord(c.e0, s));
-    for (int r = 0; r < reps; ++r) launch();
-    LAUNCHCHK("peak probe");
-    HIPCHK(hipEventRecord(c.e1, s));
-    HIPCHK(hipEventSynchronize(c.e1));
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, c.e0, c.e1));
-    if (!(ms > 0.f)) return fail(MQH_EDEVICE, "peak probe: no elapsed time");
-    const double sec = (double)ms * 1e-3 / reps;
-    double work = 0.0;
-    switch (kind) {
-        case MQH_PEAK_COPY: work = 2.0 * (double)count * sizeof(double); break;
-        case MQH_PEAK_READ: work = (double)count * sizeof(double); break;
-        case MQH_PEAK_FMA_F32:
-        case MQH_PEAK_FMA_F64: work = 2.0 * peak_fma_ops(iters); break;
-        default: work = peak_mfma_flops(iters); break;
-    }
-    *rate = work / sec;
-    return MQH_OK;
-}
-
 int mqh_eval(mqh_problem* p, const double* coef, const double* x_eval, int64_t m, double* u, uint32_t flags) {
     int rc;
     if ((rc = check_problem(p))) return rc;

@@ -1,4 +1,4 @@
-// peak_kernels.hip -- measurement helpers, not part of the solver: the rates
+// peak_kernels.hip -- measurement helpers (libmqhpeak), not part of the solver: the rates
 // the rooflines are checked against on the GPU at hand.  A device-to-device
 // copy and a read-only stream (HBM), FP32 and FP64 FMA chains as the VALU issues them in this build
 // (unpacked: every HIP source here is compiled without packed FP32), and an
@@ -14,7 +14,8 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kPeakChains = 16;  // independent FMA chains per lane
-constexpr int kPeakCopyUnroll = 4;  // independent 16-byte loads in flight per lane
+constexpr int kPeakCopyUnroll = 4;  // independent 16-byte loads in flight per lane (copy)
+constexpr int kPeakReadUnroll = 8;  // the same for the read-only stream
 constexpr int kPeakMfma = 4;    // independent matrix-core accumulators per wave
 
 // Grid-stride copy, kPeakCopyUnroll loads issued before their stores; the
@@ -34,21 +35,21 @@ __global__ __launch_bounds__(kBlock) void k_peak_copy(const double2* __restrict_
         if (i + u * kBlock < n2) y[i + u * kBlock] = x[i + u * kBlock];
 }
 
-// Grid-stride read of x (kPeakCopyUnroll loads in flight per lane), summed
+// Grid-stride read of x (kPeakReadUnroll loads in flight per lane), summed
 // per lane and stored once per thread so the loads are not dead code.
 __global__ __launch_bounds__(kBlock) void k_peak_read(const double2* __restrict__ x, int64_t n2,
                                                       double* __restrict__ out) {
-    const int64_t step = (int64_t)gridDim.x * kBlock * kPeakCopyUnroll;
-    int64_t i = (int64_t)blockIdx.x * kBlock * kPeakCopyUnroll + threadIdx.x;
+    const int64_t step = (int64_t)gridDim.x * kBlock * kPeakReadUnroll;
+    int64_t i = (int64_t)blockIdx.x * kBlock * kPeakReadUnroll + threadIdx.x;
     double s = 0.0;
-    for (; i + (kPeakCopyUnroll - 1) * kBlock < n2; i += step) {
-        double2 v[kPeakCopyUnroll];
+    for (; i + (kPeakReadUnroll - 1) * kBlock < n2; i += step) {
+        double2 v[kPeakReadUnroll];
 #pragma unroll
-        for (int u = 0; u < kPeakCopyUnroll; ++u) v[u] = x[i + u * kBlock];
+        for (int u = 0; u < kPeakReadUnroll; ++u) v[u] = x[i + u * kBlock];
 #pragma unroll
-        for (int u = 0; u < kPeakCopyUnroll; ++u) s += v[u].x + v[u].y;
+        for (int u = 0; u < kPeakReadUnroll; ++u) s += v[u].x + v[u].y;
     }
-    for (int u = 0; u < kPeakCopyUnroll; ++u)
+    for (int u = 0; u < kPeakReadUnroll; ++u)
         if (i + u * kBlock < n2) s += x[i + u * kBlock].x + x[i + u * kBlock].y;
     out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
 }

@@ -51,11 +51,6 @@ MQH_FULL_MAX_N = 32768
 MQH_FULL_CG_MAX = 1024
 MQH_BLOCK_MAX_DIM = 4096
 MQH_BLOCK_RHS = 16
-MQH_PEAK_COPY = 0
-MQH_PEAK_FMA_F32 = 1
-MQH_PEAK_FMA_F64 = 2
-MQH_PEAK_MFMA_F64 = 3
-MQH_PEAK_READ = 4
 MQH_MLP_IN = 24
 MQH_MLP_WIDTH = 128
 MQH_MLP_OUT = 2
@@ -144,7 +139,6 @@ _SIGNATURES = {
     "mqh_full_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.POINTER(mqh_solve_opts), _vp, _vp,
                                       ctypes.POINTER(mqh_solve_info)]),
     "mqh_eval": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _u32]),
-    "mqh_peak_probe": (ctypes.c_int, [_i32, _i64, _i32, ctypes.POINTER(_d), _vp]),
     "mqh_mlp_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _u32]),
     "mqh_mlp_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _u32]),
     "mqh_mlp_loss": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _u32]),
@@ -601,15 +595,6 @@ def mqh_full_solve(h, f_int, g_bnd, method: int = MQH_METHOD_HKT, rule: int = MQ
                                    _ptr(sv)[0], ctypes.byref(info)), "mqh_full_solve")
     return SolveOutput(coef, None, None, sv, st, info.ell_done, info.k_chosen, info.lambda_chosen, info.crit,
                        info.resid_norm, info.sol_norm, info.flags, list(info.t_ms))
-
-
-def mqh_peak_probe(kind: int, size: int, reps: int = 5, stream=None) -> float:
-    """Rate of a reference kernel (bytes/s for MQH_PEAK_COPY and MQH_PEAK_READ, flop/s otherwise); see
-    include/mqhelm.h."""
-    rate = ctypes.c_double(0.0)
-    _check(lib.mqh_peak_probe(int(kind), int(size), int(reps), ctypes.byref(rate), _stream_of(stream)),
-           "mqh_peak_probe")
-    return rate.value
 
 
 def mqh_eval(h, coef, x_eval, u=None):

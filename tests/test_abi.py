@@ -189,18 +189,26 @@ def test_network_size_matches_oracle():
     assert (d["MQH_MLP_IN"], d["MQH_MLP_WIDTH"], d["MQH_MLP_OUT"]) == (M.SIZES[0], M.SIZES[1], M.SIZES[-1])
 
 
-def test_peak_probe_rejects_invalid_arguments(mq):
-    # argument checks run before any device work
-    L = mq.lib
+def test_peak_library_separate_and_checks_arguments():
+    # the measurement helper lives in its own library (include/mqh_peak.h), not in the solver's ABI
+    from paper_2511_09798_amd import mqhelm
+    from paper_2511_09798_amd import peak
+
+    with open(os.path.join(INCLUDE, "mqh_peak.h")) as fh:
+        txt = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+    assert sorted(set(re.findall(r"\b(mqh_[a-z_]+)\s*\(", txt))) == ["mqh_peak_last_error", "mqh_peak_probe"]
+    assert not hasattr(mqhelm.lib, "mqh_peak_probe") or "mqh_peak_probe" not in mqhelm._SIGNATURES
+    L = peak.lib
     r = ctypes.c_double(1.0)
-    assert L.mqh_peak_probe(7, 1024, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
-    assert L.mqh_peak_probe(mq.MQH_PEAK_READ, 8, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
+    assert L.mqh_peak_probe(7, 1024, 1, ctypes.byref(r), None) == -1
+    assert L.mqh_peak_probe(peak.MQH_PEAK_READ, 8, 1, ctypes.byref(r), None) == -1
     assert r.value == 0.0
-    assert L.mqh_peak_probe(mq.MQH_PEAK_COPY, 8, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
-    assert L.mqh_peak_probe(mq.MQH_PEAK_FMA_F32, 0, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
-    assert L.mqh_peak_probe(mq.MQH_PEAK_FMA_F64, 1 << 21, 1, ctypes.byref(r), None) == mq.MQH_EINVAL
-    assert L.mqh_peak_probe(mq.MQH_PEAK_MFMA_F64, 16, 0, ctypes.byref(r), None) == mq.MQH_EINVAL
-    assert L.mqh_peak_probe(mq.MQH_PEAK_COPY, 1024, 1, None, None) == mq.MQH_EINVAL
+    assert L.mqh_peak_probe(peak.MQH_PEAK_COPY, 8, 1, ctypes.byref(r), None) == -1
+    assert L.mqh_peak_probe(peak.MQH_PEAK_FMA_F32, 0, 1, ctypes.byref(r), None) == -1
+    assert L.mqh_peak_probe(peak.MQH_PEAK_FMA_F64, 1 << 21, 1, ctypes.byref(r), None) == -1
+    assert L.mqh_peak_probe(peak.MQH_PEAK_MFMA_F64, 16, 0, ctypes.byref(r), None) == -1
+    assert L.mqh_peak_probe(peak.MQH_PEAK_COPY, 1024, 1, None, None) == -1
+    assert b"reps" in L.mqh_peak_last_error() or b"NULL" in L.mqh_peak_last_error()
 
 
 def test_block_entry_points_reject_invalid_arguments(mq):

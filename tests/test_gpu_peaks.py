@@ -1,4 +1,4 @@
-"""The measurement helper mqh_peak_probe on the GPU: each reference kernel
+"""The measurement library's mqh_peak_probe (include/mqh_peak.h) on the GPU: each reference kernel
 reports a positive rate within a plausible band of the MI355X spec peak it
 measures (a copy or a read of 1-2 GiB, beyond the 256 MB last-level cache,
 reaches at most the 8 TB/s HBM figure; FP32 FMA at most
@@ -19,9 +19,9 @@ def say(*a):
 
 @pytest.fixture(scope="module")
 def mq():
-    from paper_2511_09798_amd import mqhelm
+    from paper_2511_09798_amd import peak
 
-    return mqhelm
+    return peak
 
 
 @pytest.mark.parametrize("kind,size,lo,hi", [
