@@ -165,11 +165,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize_scale(const double* __restr
 // ---------------------------------------------------------------------------
 
 // partial[b * m + k] = sum over the kGtRows rows of block row b of V[k][i] x_i.
-// A block owns kGtRows rows (kGtRows/256 per lane, x held in registers)
-// and kGtCols consecutive columns (blockIdx.y): every lane issues
-// kGtCols * kGtRows/256 independent loads, then each column is reduced
-// over the block in a fixed order.
-constexpr int kGtRows = 1024;
+// A block owns kGtRows rows and kGtCols consecutive columns (blockIdx.y).
+// Rows in kGtQ passes of 512: in pass q wave w takes rows 512 q + 128 w ..
+// + 127 of the block, lane l the pair 2l, 2l + 1 (one 16-byte load per
+// column, 1 KB per wave load), so every lane has kGtQ * kGtCols loads in
+// flight; then each column is reduced over the block in a fixed order.  V is
+// zero past n up to ldn (a multiple of 64), so the pair i, i + 1 with i < n
+// even stays inside the padded column.
+constexpr int kGtQ = 2;
+constexpr int kGtRows = kGtQ * 4 * 2 * 64;  // 1024
 constexpr int kGtCols = 8;
 
 __global__ __launch_bounds__(kBlock) void k_gemvt_partial(const double* __restrict__ V, int64_t ldn, int64_t n,
@@ -183,33 +187,36 @@ __global__ __launch_bounds__(kBlock) void k_gemvt_partial(const double* __restri
     partial += z * bz.c;
     if (st != nullptr) st += z;
     if (st != nullptr && st->stopped) return;
-    constexpr int Q = kGtRows / kBlock;
-    const int64_t r0 = (int64_t)blockIdx.x * kGtRows + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t ib = (int64_t)blockIdx.x * kGtRows + w * (2 * kWave) + 2 * lane;
     const int k0 = blockIdx.y * kGtCols;
-    double xv[Q];
-    bool in[Q];
+    double x0[kGtQ], x1[kGtQ];
+    bool in[kGtQ];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int64_t i = r0 + q * kBlock;
-        in[q] = i < ldn;  // V is zero-padded up to ldn
-        xv[q] = i < n ? x[i] : 0.0;
+    for (int q = 0; q < kGtQ; ++q) {
+        const int64_t i = ib + q * (kBlock * 2);
+        in[q] = i < n;
+        x0[q] = in[q] ? x[i] : 0.0;
+        x1[q] = in[q] && i + 1 < n ? x[i + 1] : 0.0;
     }
     double acc[kGtCols];
 #pragma unroll
     for (int c = 0; c < kGtCols; ++c) {
         acc[c] = 0.0;
         if (k0 + c < m) {
-            const double* v = V + (int64_t)(k0 + c) * ldn;
+            const double* v = V + (int64_t)(k0 + c) * ldn + ib;
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (in[q]) acc[c] = fma(v[r0 + q * kBlock], xv[q], acc[c]);
+            for (int q = 0; q < kGtQ; ++q)
+                if (in[q]) {
+                    const v2d a = load2(v + q * (kBlock * 2));
+                    acc[c] = fma(a.y, x1[q], fma(a.x, x0[q], acc[c]));
+                }
         }
     }
-    const int w = threadIdx.x / kWave;
 #pragma unroll
     for (int c = 0; c < kGtCols; ++c) {
         const double sc = wave_sum(acc[c]);
-        if ((threadIdx.x & (kWave - 1)) == 0) lds[w][c] = sc;
+        if (lane == 0) lds[w][c] = sc;
     }
     __syncthreads();
     if (threadIdx.x < kGtCols && k0 + (int)threadIdx.x < m) {
@@ -237,12 +244,20 @@ __global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restric
     if (lane == 0) c[k] = s;
 }
 
-// x_i -= sum_k V[k][i] c_k; optionally partial[b] = sum over the block of the updated x_i^2.
+// x_i -= sum_k V[k][i] c_k for the kUpdRows rows of block b; optionally
+// partial[b] = sum over the block of the updated x_i^2.  Lane l of every wave
+// owns the block's rows 2l, 2l + 1 (16-byte loads, 1 KB per wave load); wave
+// w sums the columns k = w, w + 4, ... with eight loads in flight, and the
+// four waves' sums are added in wave order through LDS.
+constexpr int kUpdRows = 2 * kWave;
+
 __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V, int64_t ldn, int64_t n, int32_t m,
                                                    const double* __restrict__ c, double* __restrict__ x,
                                                    double* __restrict__ sumsq_partial, GkbState* __restrict__ st,
                                                    Bz bz) {
-    __shared__ double lds[kBlock / kWave];
+    constexpr int kW = kBlock / kWave;
+    __shared__ double part[kW][kUpdRows];
+    __shared__ double lds[kW];
     const int64_t z = blockIdx.z;  // batch: V + z bz.a, c + z bz.b, x + z bz.c, sumsq + z bz.d, state z
     V += z * bz.a;
     c += z * bz.b;
@@ -255,19 +270,36 @@ __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V,
         st->snap_scale = st->scale;
     }
     if (st != nullptr && st->stopped) return;  // uniform over the grid
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    double xi = 0.0;
-    if (i < n) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int k = 0;
-        for (; k + 3 < m; k += 4) {
-            s0 = fma(V[(int64_t)k * ldn + i], c[k], s0);
-            s1 = fma(V[(int64_t)(k + 1) * ldn + i], c[k + 1], s1);
-            s2 = fma(V[(int64_t)(k + 2) * ldn + i], c[k + 2], s2);
-            s3 = fma(V[(int64_t)(k + 3) * ldn + i], c[k + 3], s3);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t i0 = (int64_t)blockIdx.x * kUpdRows + 2 * lane;  // i0 even, so i0 + 1 < ldn when i0 < n
+    double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
+    if (i0 < n) {
+        const double* v = V + i0;
+        int k = w;
+#pragma unroll 4
+        for (; k + kW < m; k += 2 * kW) {
+            const v2d a = load2(v + (int64_t)k * ldn);
+            const v2d b = load2(v + (int64_t)(k + kW) * ldn);
+            const double ca = c[k], cb = c[k + kW];
+            s0 = fma(a.x, ca, s0);
+            s1 = fma(a.y, ca, s1);
+            t0 = fma(b.x, cb, t0);
+            t1 = fma(b.y, cb, t1);
         }
-        for (; k < m; ++k) s0 = fma(V[(int64_t)k * ldn + i], c[k], s0);
-        xi = x[i] - ((s0 + s1) + (s2 + s3));
+        if (k < m) {
+            const v2d a = load2(v + (int64_t)k * ldn);
+            s0 = fma(a.x, c[k], s0);
+            s1 = fma(a.y, c[k], s1);
+        }
+    }
+    part[w][2 * lane] = s0 + t0;
+    part[w][2 * lane + 1] = s1 + t1;
+    __syncthreads();
+    double xi = 0.0;
+    const int64_t i = (int64_t)blockIdx.x * kUpdRows + threadIdx.x;
+    if (threadIdx.x < kUpdRows && i < n) {
+        const int t = threadIdx.x;
+        xi = x[i] - (((part[0][t] + part[1][t]) + part[2][t]) + part[3][t]);
         x[i] = xi;
     }
     if (sumsq_partial != nullptr) {
@@ -387,11 +419,10 @@ void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const dou
 
 void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
                      double* sumsq_partial, GkbState* st, int nz, Bz bz, hipStream_t s) {
-    k_update<<<dim3((unsigned)((n + kBlock - 1) / kBlock), 1, nz), kBlock, 0, s>>>(V, ldn, n, m, c, x, sumsq_partial,
-                                                                                 st, bz);
+    k_update<<<dim3((unsigned)update_blocks(n), 1, nz), kBlock, 0, s>>>(V, ldn, n, m, c, x, sumsq_partial, st, bz);
 }
 
-int update_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+int update_blocks(int64_t n) { return (int)((n + kUpdRows - 1) / kUpdRows); }
 
 void launch_lift(const double* Z, int64_t ldz, int64_t n, int32_t ell, const int32_t* ell_ptr, const double* y,
                  double* coef, hipStream_t s, int nz, Bz bz) {
