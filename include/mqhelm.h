@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MQH_VERSION 10400 /* 1.4.0 */
+#define MQH_VERSION 10500 /* 1.5.0 */
 
 /* ---- status codes ---- */
 #define MQH_OK 0
@@ -91,10 +91,15 @@ extern "C" {
                                        mqh_gkb / mqh_gkb_multi also scale f to D f */
 
 /* ---- info flags ---- */
+#define MQH_FLAG_PROJ_QR 32u         /* mqh_proj_svd: the implicit QR iteration only (the fast path's fallback) */
+#define MQH_FLAG_PROJ_NO_FALLBACK 64u /* mqh_proj_svd: the fast path only; MQH_EDEVICE if it fails its acceptance
+                                        test (for tests of the fast path) */
 #define MQH_INFO_BREAKDOWN 1u
 #define MQH_INFO_GCV_AT_EDGE 2u
 #define MQH_INFO_LCURVE_AT_EDGE 4u
 #define MQH_INFO_SOLVE_NOCONV 8u  /* full solve: the conjugate gradients stopped at their cap above their tolerance */
+#define MQH_INFO_SVD_QR 16u       /* the projected SVD failed the fast path's acceptance test and was computed by
+                                     the implicit QR iteration (same outputs to rounding, about 100 times slower) */
 
 /* Largest number of Golub-Kahan steps a solve accepts (projected problem size). */
 #define MQH_MAX_ELL 1024
@@ -262,7 +267,19 @@ int mqh_gkb(mqh_problem* p, const double* f, int32_t ell, int32_t reorth, double
  *         may be NULL
  * alpha (ell) and beta (ell+1, beta[0] = beta_1) are inputs.  Signs of
  * singular vectors are arbitrary (f~_i and v~_i flip together).
+ * Method: Givens rotations take C_ell to an upper bidiagonal B; each
+ * singular value by multisection on the inertia of B^T B - x I (differential
+ * qd form, high relative accuracy), each pair of vectors by twisted
+ * factorisations of B^T B - s^2 I and B B^T - s^2 I, then a symmetric
+ * orthogonalisation.  An acceptance test (Gram matrices within 1e-9 of I,
+ * residuals ||B v - s u||, ||B^T u - s v|| within 1e-9 s) guards the result;
+ * a problem that fails it (tight clusters, exactly singular B) is computed
+ * again by the implicit QR iteration with the zero-shift sweeps of Demmel and
+ * Kahan.  flags: MQH_FLAG_DEVICE_PTRS, MQH_FLAG_PROJ_QR, MQH_FLAG_PROJ_NO_FALLBACK.
  * stream: hipStream_t or NULL (default stream).  1 <= ell <= MQH_MAX_ELL.
+ * Errors: MQH_EINVAL (arguments, non-finite host input, both PROJ flags),
+ * MQH_EDEVICE (QR iteration at its limit; fast path rejected under
+ * MQH_FLAG_PROJ_NO_FALLBACK).
  */
 int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* sv, double* ftil, double* V,
                  void* stream, uint32_t flags);
@@ -273,7 +290,8 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
  * that forbid hipMalloc).  Same computation and outputs as mqh_proj_svd
  * (bit for bit); every array is a device pointer on the current device and
  * stream runs on that device (NULL: the default stream).  V may be NULL.
- * The workspace (the ell x ell rotation matrix, V when V is NULL, a status
+ * The workspace (the left vectors, a Gram matrix and the bidiagonal's
+ * bookkeeping for ell = MQH_NOALLOC_MAX_ELL, V when V is NULL, a status
  * word) is a fixed array of MQH_NOALLOC_SCRATCH_BYTES in the library's
  * device memory, one per GPU, held until the process ends; hence
  * 1 <= ell <= MQH_NOALLOC_MAX_ELL (MQH_EINVAL beyond).  All calls on one GPU
@@ -284,7 +302,7 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
  * routine is called.
  */
 #define MQH_NOALLOC_MAX_ELL 512
-#define MQH_NOALLOC_SCRATCH_BYTES 4194560 /* 8 (2 * 512 * 512 + 32): 4 MiB + 256 B */
+#define MQH_NOALLOC_SCRATCH_BYTES 6332800 /* 8 (3 * 512 * 512 + 6 * 512 + 2 * 1024 + 48): about 6 MiB */
 int mqh_proj_svd_noalloc(const double* alpha, const double* beta, int32_t ell, double* sv, double* ftil, double* V,
                          void* stream);
 

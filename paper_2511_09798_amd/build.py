@@ -17,8 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmqhelm.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["op_kernels.hip", "stored_kernels.hip", "gkb_kernels.hip", "proj_kernels.hip", "mlp_kernels.hip",
-           "full_kernels.hip", "block_kernels.hip", "capi.hip"]
+SOURCES = ["op_kernels.hip", "stored_kernels.hip", "gkb_kernels.hip", "proj_kernels.hip", "svd_kernels.hip",
+           "mlp_kernels.hip", "full_kernels.hip", "block_kernels.hip", "capi.hip"]
 # the measurement library beside it (reference kernels for the rooflines; not part of the method)
 PEAK_SOURCES = ["peak_kernels.hip", "peak_capi.hip"]
 PEAK_LIB = os.path.join(HERE, "libmqhpeak.so")

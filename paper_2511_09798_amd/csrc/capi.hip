@@ -533,7 +533,7 @@ int ensure_gkb(mqh_problem* p, int32_t ell) {
     if ((rc = dalloc(&p->cvec, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->sv, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->ftil, (size_t)cols + 1))) return rc;
-    if ((rc = dalloc(&p->Vw, (size_t)ell * (size_t)ell))) return rc;
+    if ((rc = dalloc(&p->Vw, svd_ws_doubles(ell)))) return rc;
     if ((rc = dalloc(&p->V, (size_t)ell * (size_t)ell))) return rc;
     if ((rc = dalloc(&p->y, (size_t)cols))) return rc;
     p->ell_cap = ell;
@@ -726,7 +726,7 @@ int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
         (rc = dalloc(&w.sv, Z * (size_t)w.vstr)) || (rc = dalloc(&w.ftil, Z * (size_t)w.vstr)) ||
         (rc = dalloc(&w.y, Z * (size_t)w.vstr)) || (rc = dalloc(&w.cvec, Z * (size_t)w.vstr)) ||
         (rc = dalloc(&w.gpart, Z * (size_t)w.gstr)) || (rc = dalloc(&w.npart, Z * (size_t)w.nstr)) ||
-        (rc = dalloc(&w.Vw, Z * (size_t)lc * (size_t)lc)) || (rc = dalloc(&w.V, Z * (size_t)lc * (size_t)lc)) ||
+        (rc = dalloc(&w.Vw, Z * svd_ws_doubles(lc))) || (rc = dalloc(&w.V, Z * (size_t)lc * (size_t)lc)) ||
         (rc = dalloc(&w.st, Z)) || (rc = dalloc(&w.pout, Z)) || (rc = dalloc(&w.status, Z)) ||
         (rc = dalloc(&w.X, Z * (size_t)ldn)) || (rc = dalloc(&w.Y, Z * (size_t)ldn)) ||
         (rc = dalloc(&w.coef, Z * (size_t)ldn))) {
@@ -2039,7 +2039,7 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
     const bool svd_runs = !lsqr || ritz_sv != nullptr;
     launch_fill(p->sv, ell, 0.0, s);
     if (svd_runs) {
-        launch_bidiag_svd(p->alpha, p->beta, ell, lp, p->Vw, ell, p->sv, p->ftil, p->V, ell, p->svd_status, s);
+        launch_bidiag_svd(p->alpha, p->beta, ell, lp, p->Vw, p->sv, p->ftil, p->V, ell, p->svd_status, 0, s);
         LAUNCHCHK("projected SVD");
     }
     HIPCHK(hipEventRecord(p->ev[3], s));
@@ -2063,7 +2063,7 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
     double b1 = 0.0;
     HIPCHK(hipMemcpy(&b1, p->beta, sizeof(double), hipMemcpyDeviceToHost));
     if (!isfinite(b1)) return fail(MQH_EINVAL, "non-finite right-hand side");
-    if (svd_runs && p->hres->svd_status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    if (svd_runs && p->hres->svd_status < 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
     const hipMemcpyKind ko = kind_out(flags);
     HIPCHK(hipMemcpyAsync(coef, p->coef, (size_t)p->n * sizeof(double), ko, s));
     if (gkb_alpha) HIPCHK(hipMemcpyAsync(gkb_alpha, p->alpha, (size_t)ell * sizeof(double), ko, s));
@@ -2075,6 +2075,7 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
     const ParamOut& po = p->hres->po;
     uint32_t iflags = po.flags;
     if (st.flag != 0) iflags |= MQH_INFO_BREAKDOWN;
+    if (svd_runs && p->hres->svd_status == 1) iflags |= MQH_INFO_SVD_QR;
     if (info) {
         info->ell_done = st.ell_done;
         info->k_chosen = po.k;
@@ -2251,10 +2252,11 @@ int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
         }
         HIPCHK(hipEventRecord(p->ev[2], s));
         const int32_t* lp = &w.st->ell_done;
-        const ProjBatch pb{w.vstr, (int64_t)w.ell_cap * w.ell_cap, (int64_t)(sizeof(GkbState) / sizeof(int32_t)), 0};
+        const ProjBatch pb{w.vstr, (int64_t)w.ell_cap * w.ell_cap, (int64_t)(sizeof(GkbState) / sizeof(int32_t)), 0,
+                           (int64_t)svd_ws_doubles(w.ell_cap)};
         launch_fill(w.sv, (int64_t)nz * w.vstr, 0.0, s);
         if (!lsqr) {
-            launch_bidiag_svd(w.alpha, w.beta, ell, lp, w.Vw, ell, w.sv, w.ftil, w.V, ell, w.status, s, nz, pb);
+            launch_bidiag_svd(w.alpha, w.beta, ell, lp, w.Vw, w.sv, w.ftil, w.V, ell, w.status, 0, s, nz, pb);
             LAUNCHCHK("projected SVD");
         }
         HIPCHK(hipEventRecord(p->ev[3], s));
@@ -2284,7 +2286,7 @@ int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
         HIPCHK(hipStreamSynchronize(s));
         for (int k = 0; k < nz; ++k) {
             if (!isfinite(b1[(size_t)k])) return fail(MQH_EINVAL, "non-finite right-hand side");
-            if (svs[(size_t)k] != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+            if (svs[(size_t)k] < 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
         }
         HIPCHK(copy_strided(coef + (int64_t)k0 * ldc, (size_t)ldc * sizeof(double), w.coef,
                                 (size_t)p->ldn * sizeof(double), (size_t)p->n * sizeof(double), (size_t)nz, ko, s));
@@ -2310,6 +2312,7 @@ int mqh_solve_multi(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
             const ParamOut& o = po[(size_t)k];
             uint32_t iflags = o.flags;
             if (g.flag != 0) iflags |= MQH_INFO_BREAKDOWN;
+            if (!lsqr && svs[(size_t)k] == 1) iflags |= MQH_INFO_SVD_QR;
             broke = broke || g.flag != 0;
             edge = edge || (iflags & (MQH_INFO_GCV_AT_EDGE | MQH_INFO_LCURVE_AT_EDGE)) != 0;
             if (info) {
@@ -2706,16 +2709,18 @@ extern "C" {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Allocation-free projected SVD: the workspace of k_bidiag_svd (the rotation
-// matrix Vw, the status word, and V when the caller does not want it) lives
+// Allocation-free projected SVD: the workspace of the projected SVD (left
+// vectors, Gram matrix, bidiagonal and bookkeeping; the QR fallback's
+// rotation matrix), the status word, and V when the caller does not want it, lives
 // in one file-scope device array.  Host code never passes the array's name
 // to a kernel or a copy: its device address is looked up once per device
 // (hipGetSymbolAddress) and kept in g_scratch_addr.
 // ---------------------------------------------------------------------------
 
 constexpr int kNoAllocMaxEll = MQH_NOALLOC_MAX_ELL;
-constexpr size_t kScratchMat = (size_t)kNoAllocMaxEll * kNoAllocMaxEll;  // doubles per ell x ell matrix
-constexpr size_t kScratchDoubles = 2 * kScratchMat + 32;                  // Vw, V, status (+ padding)
+constexpr size_t kScratchWs = svd_ws_doubles(kNoAllocMaxEll);             // the projected SVD's workspace
+constexpr size_t kScratchMat = (size_t)kNoAllocMaxEll * kNoAllocMaxEll;  // V when the caller passes none
+constexpr size_t kScratchDoubles = kScratchWs + kScratchMat + 32;         // + status (and padding)
 static_assert(MQH_NOALLOC_SCRATCH_BYTES == kScratchDoubles * sizeof(double), "scratch size in the header");
 
 static __device__ __align__(256) double scratch[kScratchDoubles];
@@ -2755,17 +2760,17 @@ int mqh_proj_svd_noalloc(const double* alpha, const double* beta, int32_t ell, d
     double* base = nullptr;
     int rc;
     if ((rc = scratch_addr(&base))) return rc;
-    double* dVw = base;
-    double* dV = V != nullptr ? V : base + kScratchMat;
-    int32_t* dst = reinterpret_cast<int32_t*>(base + 2 * kScratchMat);
-    // k_bidiag_svd initialises Vw and writes the status word itself; nothing
-    // in the scratch array has to start at zero
-    launch_bidiag_svd(alpha, beta, ell, nullptr, dVw, ell, sv, ftil, dV, ell, dst, s);
+    double* dws = base;
+    double* dV = V != nullptr ? V : base + kScratchWs;
+    int32_t* dst = reinterpret_cast<int32_t*>(base + kScratchWs + kScratchMat);
+    // the kernels write every workspace entry and the status word before
+    // reading them; nothing in the scratch array has to start at zero
+    launch_bidiag_svd(alpha, beta, ell, nullptr, dws, sv, ftil, dV, ell, dst, 0, s);
     LAUNCHCHK("projected SVD");
     int32_t status = 0;
     HIPCHK(hipMemcpyAsync(&status, dst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    if (status < 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
     return MQH_OK;
 }
 
@@ -2773,13 +2778,16 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
                  void* stream, uint32_t flags) {
     if (alpha == nullptr || beta == nullptr || sv == nullptr || ftil == nullptr) return fail(MQH_EINVAL, "NULL array");
     if (ell < 1 || ell > kMaxEll) return fail(MQH_EINVAL, "need 1 <= ell <= MQH_MAX_ELL");
+    if ((flags & MQH_FLAG_PROJ_QR) && (flags & MQH_FLAG_PROJ_NO_FALLBACK))
+        return fail(MQH_EINVAL, "MQH_FLAG_PROJ_QR and MQH_FLAG_PROJ_NO_FALLBACK exclude each other");
     if (!(flags & MQH_FLAG_DEVICE_PTRS) && (!all_finite(alpha, ell) || !all_finite(beta, ell + 1)))
         return fail(MQH_EINVAL, "non-finite input");
+    const int mode = (flags & MQH_FLAG_PROJ_QR) ? 1 : (flags & MQH_FLAG_PROJ_NO_FALLBACK) ? 2 : 0;
     hipStream_t s = (hipStream_t)stream;
     Tmp t;
     int rc;
     const double *da, *db;
-    double *dsv, *dft, *dV, *dVw;
+    double *dsv, *dft, *dV, *dws;
     int32_t* dst;
     if ((rc = dev_in(t, alpha, (size_t)ell, flags, s, &da))) return rc;
     if ((rc = dev_in(t, beta, (size_t)ell + 1, flags, s, &db))) return rc;
@@ -2790,9 +2798,9 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
     } else if ((rc = t.get(&dV, (size_t)ell * ell))) {
         return rc;
     }
-    if ((rc = t.get(&dVw, (size_t)ell * ell))) return rc;
+    if ((rc = t.get(&dws, svd_ws_doubles(ell)))) return rc;
     if ((rc = t.get(&dst, 1))) return rc;
-    launch_bidiag_svd(da, db, ell, nullptr, dVw, ell, dsv, dft, dV, ell, dst, s);
+    launch_bidiag_svd(da, db, ell, nullptr, dws, dsv, dft, dV, ell, dst, mode, s);
     LAUNCHCHK("projected SVD");
     int32_t status = 0;
     HIPCHK(hipMemcpyAsync(&status, dst, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -2802,7 +2810,8 @@ int mqh_proj_svd(const double* alpha, const double* beta, int32_t ell, double* s
         if (V) HIPCHK(hipMemcpyAsync(V, dV, (size_t)ell * ell * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
-    if (status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    if (status < 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    if (status == 2) return fail(MQH_EDEVICE, "projected SVD: the fast path failed its acceptance test");
     return MQH_OK;
 }
 
@@ -3050,7 +3059,7 @@ int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, 
     HIPCHK(hipEventRecord(p->ev[2], s));
     const int32_t* lp = &p->st->ell_done;
     launch_fill(p->sv, ell, 0.0, s);
-    launch_bidiag_svd(p->alpha, p->beta, ell, lp, p->Vw, ell, p->sv, p->ftil, p->V, ell, p->svd_status, s);
+    launch_bidiag_svd(p->alpha, p->beta, ell, lp, p->Vw, p->sv, p->ftil, p->V, ell, p->svd_status, 0, s);
     LAUNCHCHK("projected SVD");
     HIPCHK(hipEventRecord(p->ev[3], s));
     launch_param_choice(p->sv, p->ftil, ell, lp, MQH_METHOD_HKT, MQH_RULE_GCV, J, 0.0, 0, 1.0, nullptr, p->pout, s);
@@ -3065,7 +3074,7 @@ int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, 
     HIPCHK(hipMemcpyAsync(&p->hres->st, p->st, sizeof(GkbState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(svh.data(), p->sv, (size_t)ell * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (p->hres->svd_status != 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
+    if (p->hres->svd_status < 0) return fail(MQH_EDEVICE, "projected SVD did not converge");
     // GCV's search range at ell_pred: a network lambda more than 10x outside it is an extrapolation
     const int32_t le = p->hres->st.ell_done;
     bool use_net = lam_net > 0.0 && isfinite(lam_net) && le >= 1;
@@ -3088,6 +3097,7 @@ int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, 
     const GkbState& st = p->hres->st;
     uint32_t iflags = use_net ? 0u : po_gcv.flags;
     if (st.flag != 0) iflags |= MQH_INFO_BREAKDOWN;
+    if (p->hres->svd_status == 1) iflags |= MQH_INFO_SVD_QR;
     if (info) {
         info->ell_done = st.ell_done;
         info->k_chosen = 0;

@@ -40,9 +40,10 @@ struct Bz {
 // problem kernels, one workgroup (row of workgroups) per problem z:
 // vec for alpha, beta, sv, ftil, y, rho, eta; mat for Vw and V; lstr for
 // the step-count pointer (int32 elements); curve for the criterion curve;
-// ParamOut and the status word advance by one per problem.
+// ParamOut and the status word advance by one per problem; ws for the
+// projected SVD's workspace (svd_ws_doubles of the allocation's l).
 struct ProjBatch {
-    int64_t vec = 0, mat = 0, lstr = 0, curve = 0;
+    int64_t vec = 0, mat = 0, lstr = 0, curve = 0, ws = 0;
 };
 
 // Native 2 x FP64 vector for 16-byte (non-temporal) loads and stores.

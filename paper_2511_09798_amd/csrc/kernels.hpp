@@ -141,10 +141,58 @@ void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const d
                      double* sumsq_partial, GkbState* st, int nz, Bz bz, hipStream_t s);
 void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
 
+// projected SVD (svd_kernels.hip; the QR iteration in proj_kernels.hip).
+// The workspace of a problem holds svd_ws_doubles(l) doubles (l = the
+// allocation's step count, also V's ld); problem z of a batch uses
+// ws + z * pb.ws.  mode 0: multisection and twisted factorisations, the QR
+// iteration for problems that fail the acceptance test; 1: the QR iteration
+// only; 2: the fast path only.  status per problem: 0 fast path, 1 QR
+// iteration converged, -1 QR iteration at its limit, 2 fast path rejected
+// (mode 2 only).
+constexpr int kSvdTiles = 1024;  // 32 x 32 tiles of 32: l up to kMaxEll
+static_assert(kMaxEll <= 32 * 32, "Gram tile maxima sized for l <= 1024");
+// Workspace of one problem (svd_ws_doubles(L) doubles; L = the allocation's l):
+struct SvdWs {
+    double* U;      // L x L, column j = u_j, ld L (the fallback's rotation matrix)
+    double* E;      // L x L, V^T V - I, ld L
+    double* d;      // L: diagonal of B
+    double* e;      // L: superdiagonal of B (L - 1 used)
+    double* g;      // L: beta_1 e_1 after the left rotations
+    double* lam;    // L: s_j^2
+    double* h;      // L: u_j^T g
+    double* res;    // L: residual of triple j over its bound
+    double* tmax;   // 2 * kSvdTiles: tile maxima of |V^T V - I| and |U^T U - I|
+    double* misc;   // [0] eigenvalue bound, [1] pivot floor
+    int32_t* flag;  // [0] setup or values unresolved, [1] fallback needed
+};
+
+__device__ __forceinline__ SvdWs svd_ws(double* base, int32_t L) {
+    const int64_t LL = (int64_t)L * L;
+    SvdWs w;
+    w.U = base;
+    w.E = base + LL;
+    w.d = base + 2 * LL;
+    w.e = w.d + L;
+    w.g = w.e + L;
+    w.lam = w.g + L;
+    w.h = w.lam + L;
+    w.res = w.h + L;
+    w.tmax = w.res + L;
+    w.misc = w.tmax + 2 * kSvdTiles;
+    w.flag = reinterpret_cast<int32_t*>(w.misc + 8);
+    return w;
+}
+constexpr size_t svd_ws_doubles(int32_t l) {
+    return 2 * (size_t)l * (size_t)l + 6 * (size_t)l + 2 * (size_t)kSvdTiles + 16;
+}
+void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* ws,
+                       double* sv, double* ftil, double* V, int64_t ldv, int32_t* status, int mode, hipStream_t s,
+                       int nz = 1, ProjBatch pb = ProjBatch{});
+void launch_bidiag_qr(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* ws,
+                      double* sv, double* ftil, double* V, int64_t ldv, int32_t* status, bool flagged_only,
+                      hipStream_t s, int nz, ProjBatch pb);
+
 // projected problem (proj_kernels.hip)
-void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* Vw,
-                       int64_t ldw, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
-                       hipStream_t s, int nz = 1, ProjBatch pb = ProjBatch{});
 void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,
                          int32_t rule, int32_t J, double lambda_fixed, int32_t k_fixed, double omega, double* curve,
                          ParamOut* out, hipStream_t s, int nz = 1, ProjBatch pb = ProjBatch{});

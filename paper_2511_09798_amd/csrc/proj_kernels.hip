@@ -14,42 +14,46 @@ namespace mqh {
 constexpr int kProjThreads = 256;
 
 // ---------------------------------------------------------------------------
-// SVD of C_l.  Lane 0 of wave 0 runs the scalar bulge chase; the other four
-// waves apply the right rotations of the previous sweep to their rows of the
-// work matrix Vw (column-major, ld = ldw) at the same time, through two
-// rotation buffers.  Outputs: sv (descending), ftil (l+1), V (ld = ldv).
-// l is taken from *l_ptr when given (steps kept by the Golub-Kahan run).
-// status[0] = 0 on success, -1 if the iteration limit was hit.
+// SVD of C_l by the implicit QR iteration (the fallback of the fast path in
+// svd_kernels.hip).  Lane 0 of wave 0 runs the scalar bulge chase; the other
+// four waves apply the right rotations of the previous sweep to their rows
+// of the work matrix Vw (the workspace's U, column-major, ld = L) at the same
+// time, through two rotation buffers.  Outputs: sv (descending), ftil (l+1),
+// V (ld = ldv).  l is taken from *l_ptr when given (steps kept by the
+// Golub-Kahan run).  With flagged_only the kernel returns at once unless the
+// fast path flagged the problem.  status[0] = 1 on convergence, -1 if the
+// iteration limit was hit.
 // ---------------------------------------------------------------------------
 constexpr int kSvdThreads = kProjThreads + kWave;  // one chain wave + four applier waves
 
 __global__ __launch_bounds__(kSvdThreads) void k_bidiag_svd(const double* __restrict__ alpha,
-                                                            const double* __restrict__ beta, int32_t l_arg,
+                                                            const double* __restrict__ beta, int32_t L,
                                                             const int32_t* __restrict__ l_ptr,
-                                                            double* __restrict__ Vw, int64_t ldw,
-                                                            double* __restrict__ sv, double* __restrict__ ftil,
-                                                            double* __restrict__ V, int64_t ldv,
-                                                            int32_t* __restrict__ status, ProjBatch pb) {
-    {
-        const int64_t z = blockIdx.x;  // batch: problem z
-        alpha += z * pb.vec;
-        beta += z * pb.vec;
-        if (l_ptr != nullptr) l_ptr += z * pb.lstr;
-        Vw += z * pb.mat;
-        sv += z * pb.vec;
-        ftil += z * pb.vec;
-        V += z * pb.mat;
-        if (status != nullptr) status += z;
-    }
+                                                            double* __restrict__ ws, double* __restrict__ sv,
+                                                            double* __restrict__ ftil, double* __restrict__ V,
+                                                            int64_t ldv, int32_t* __restrict__ status,
+                                                            int32_t flagged_only, ProjBatch pb) {
+    const int64_t z = blockIdx.x;  // batch: problem z
+    const SvdWs wsz = svd_ws(ws + z * pb.ws, L);
+    if (flagged_only && wsz.flag[1] == 0) return;
+    double* __restrict__ Vw = wsz.U;
+    const int64_t ldw = L;
+    alpha += z * pb.vec;
+    beta += z * pb.vec;
+    if (l_ptr != nullptr) l_ptr += z * pb.lstr;
+    sv += z * pb.vec;
+    ftil += z * pb.vec;
+    V += z * pb.mat;
+    if (status != nullptr) status += z;
     __shared__ double d[kMaxEll], e[kMaxEll], g[kMaxEll];
     __shared__ double rc[2][kMaxEll], rs[2][kMaxEll];
     __shared__ int rank[kMaxEll];
     __shared__ int s_ll[2], s_m[2], s_res[2];
     const int tid = threadIdx.x;
-    const int l = l_ptr != nullptr ? *l_ptr : l_arg;
+    const int l = l_ptr != nullptr ? *l_ptr : L;
     if (l <= 0) {
         if (tid == 0) {
-            if (status) status[0] = 0;
+            if (status) status[0] = 1;
             ftil[0] = beta[0];
         }
         return;
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(kSvdThreads) void k_bidiag_svd(const double* __rest
         __syncthreads();
         b = 1 - b;
     }
-    if (tid == 0 && status != nullptr) status[0] = s_res[b] == 0 ? 0 : -1;
+    if (tid == 0 && status != nullptr) status[0] = s_res[b] == 0 ? 1 : -1;
     // order descending: rank of |d_i| among all (ties by index), one i per thread
     for (int i = tid; i < l; i += kSvdThreads) {
         const double si = fabs(d[i]);
@@ -562,10 +566,11 @@ __global__ __launch_bounds__(kProjThreads) void k_lsqr(const double* __restrict_
 // Host launchers
 // ---------------------------------------------------------------------------
 
-void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* Vw,
-                       int64_t ldw, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
-                       hipStream_t s, int nz, ProjBatch pb) {
-    k_bidiag_svd<<<nz, kSvdThreads, 0, s>>>(alpha, beta, l, l_ptr, Vw, ldw, sv, ftil, V, ldv, status, pb);
+void launch_bidiag_qr(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* ws,
+                      double* sv, double* ftil, double* V, int64_t ldv, int32_t* status, bool flagged_only,
+                      hipStream_t s, int nz, ProjBatch pb) {
+    k_bidiag_svd<<<nz, kSvdThreads, 0, s>>>(alpha, beta, l, l_ptr, ws, sv, ftil, V, ldv, status,
+                                            flagged_only ? 1 : 0, pb);
 }
 
 void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,

@@ -40,13 +40,16 @@ MQH_FLAG_TIME_PRODUCTS = 2
 MQH_FLAG_FIXED_SHAPES = 4
 MQH_FLAG_GRAPH = 8
 MQH_FLAG_ROW_SCALE = 16
+MQH_FLAG_PROJ_QR = 32
+MQH_FLAG_PROJ_NO_FALLBACK = 64
 MQH_INFO_BREAKDOWN = 1
 MQH_INFO_GCV_AT_EDGE = 2
 MQH_INFO_LCURVE_AT_EDGE = 4
 MQH_INFO_SOLVE_NOCONV = 8
+MQH_INFO_SVD_QR = 16
 MQH_MAX_ELL = 1024
 MQH_NOALLOC_MAX_ELL = 512
-MQH_NOALLOC_SCRATCH_BYTES = 4194560
+MQH_NOALLOC_SCRATCH_BYTES = 6332800
 MQH_FULL_MAX_N = 32768
 MQH_FULL_CG_MAX = 1024
 MQH_BLOCK_MAX_DIM = 4096
@@ -299,12 +302,14 @@ def mqh_gkb(h, f, ell: int, reorth: int = 1, want_bases: bool = True, row_scale:
     return dict(W=W, Z=Z, alpha=al, beta=be, ell_done=int(done.value), status=st)
 
 
-def mqh_proj_svd(alpha, beta, want_v: bool = True, stream=None):
+def mqh_proj_svd(alpha, beta, want_v: bool = True, stream=None, path: str = "auto"):
+    """path: "auto" (fast path, QR iteration for rejected problems), "qr" (QR iteration only) or
+    "fast" (fast path only; MQHError if it rejects the problem)."""
     ell = int(alpha.shape[0])
     sv = _empty_like_kind(alpha, (ell,))
     ft = _empty_like_kind(alpha, (ell + 1,))
     V = _empty_like_kind(alpha, (ell, ell)) if want_v else None  # row i = v~_i
-    fl = _flags(alpha, beta, sv, ft, V)
+    fl = _flags(alpha, beta, sv, ft, V) | {"auto": 0, "qr": MQH_FLAG_PROJ_QR, "fast": MQH_FLAG_PROJ_NO_FALLBACK}[path]
     _check(lib.mqh_proj_svd(_ptr(alpha)[0], _ptr(beta)[0], ell, _ptr(sv)[0], _ptr(ft)[0], _ptr(V)[0],
                             _stream_of(stream), fl), "mqh_proj_svd")
     return sv, ft, V

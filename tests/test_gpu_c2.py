@@ -123,6 +123,7 @@ def test_c2_hkt_gcv_end_to_end(mq, orc, c2, mode):
     # the workload has an interior GCV minimum (the design notes list its value)
     assert not (ref.flags & orc.FLAG_GCV_AT_EDGE)
     assert not (out.flags & mq.MQH_INFO_GCV_AT_EDGE)
+    assert not (out.flags & mq.MQH_INFO_SVD_QR)  # the projected SVD took the fast path
     assert out.lam == pytest.approx(ref.lam, rel=1e-6)
     assert np.linalg.norm(u - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
     assert np.linalg.norm(fix.coef - ref.coef) <= 1e-6 * np.linalg.norm(ref.coef)

@@ -220,6 +220,64 @@ def test_proj_svd_small(mq, orc, ell):
     assert np.max(np.abs(np.abs(ftg) - np.abs(ft))) < 1e-13
 
 
+def _decaying(l, seed):
+    # a spectrum like that of a Golub-Kahan run on an ill-posed operator
+    rng = np.random.default_rng(seed)
+    a = np.logspace(0, -7, l) * (1.0 + 0.3 * rng.random(l))
+    b = np.concatenate([[1.0], np.logspace(-0.3, -7.3, l) * (1.0 + 0.3 * rng.random(l))])
+    return a, b
+
+
+@pytest.mark.parametrize("source", ["gkb", "decaying300", "decaying1024"])
+def test_proj_svd_fast_path_and_qr(mq, orc, proj_case, source):
+    # the fast path alone (multisection + twisted factorisations) and the QR
+    # iteration alone, each against the oracle's one-sided Jacobi SVD (values,
+    # |f~|) and against each other (projected Tikhonov solutions)
+    if source == "gkb":
+        g = proj_case[1]
+        a, b = g.alpha, g.beta
+    else:
+        a, b = _decaying(int(source[8:]), 5)
+    l = len(a)
+    say("proj_svd paths", source, "l =", l)
+    sf, ff, Vf = mq.mqh_proj_svd(a, b, path="fast")
+    sq, fq, Vq = mq.mqh_proj_svd(a, b, path="qr")
+    sd, fd, Vd = mq.mqh_proj_svd(a, b)
+    assert np.array_equal(sd, sf) and np.array_equal(fd, ff) and np.array_equal(Vd, Vf)  # no fallback needed
+    s, ft, V = orc.proj_svd(a, b)
+    for sv, ftg, Vg in ((sf, ff, Vf), (sq, fq, Vq)):
+        assert np.max(np.abs(sv[:10] - s[:10]) / s[:10]) < 1e-12
+        assert np.max(np.abs(sv - s)) < 64 * l * EPS * s[0]
+        assert abs(abs(ftg[-1]) - abs(ft[-1])) < 1e-12 * b[0]
+        assert np.sum(ftg ** 2) == pytest.approx(b[0] ** 2, rel=1e-13)
+        assert np.max(np.abs(Vg @ Vg.T - np.eye(l))) < 1e-12
+    assert np.max(np.abs(sf - sq) / sq) < 256 * EPS
+    assert np.max(np.abs(np.abs(ff) - np.abs(fq))) < 1e-12 * b[0]
+    for lam in (sq[0] * 1e-2, sq[l // 3], sq[-1] * 10):
+        yf = Vf.T @ (sf / (sf ** 2 + lam ** 2) * ff[:-1])
+        yq = Vq.T @ (sq / (sq ** 2 + lam ** 2) * fq[:-1])
+        assert np.linalg.norm(yf - yq) <= 1e-9 * np.linalg.norm(yq)
+
+
+def test_proj_svd_exact_cluster_falls_back(mq, orc):
+    # two identical decoupled blocks: double singular values, rejected by the
+    # fast path's acceptance test and computed by the QR iteration
+    blk_a = np.array([1.0, 0.7, 0.4])
+    blk_b = np.array([0.6, 0.3, 0.0])
+    a = np.concatenate([blk_a, blk_a])
+    b = np.concatenate([[1.0], blk_b, blk_b])
+    say("proj_svd exact cluster")
+    with pytest.raises(mq.MQHError) as ex:
+        mq.mqh_proj_svd(a, b, path="fast")
+    assert "acceptance test" in str(ex.value)
+    sd, fd, Vd = mq.mqh_proj_svd(a, b)
+    sq, fq, Vq = mq.mqh_proj_svd(a, b, path="qr")
+    assert np.array_equal(sd, sq) and np.array_equal(fd, fq) and np.array_equal(Vd, Vq)
+    s = np.linalg.svd(orc.bidiag_matrix(a, b), compute_uv=False)
+    assert np.max(np.abs(sd - s) / s) < 1e-13
+    assert np.max(np.abs(Vd @ Vd.T - np.eye(6))) < 1e-13
+
+
 def test_param_choice(mq, orc, proj_case):
     p, g, s, ft, V = proj_case
     say("param_choice gcv")
