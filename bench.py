@@ -89,7 +89,8 @@ def measured_traffic(kernel_key: str):
 def measure_peaks():
     """The reference kernels of the measurement library (libmqhpeak) on this GPU: HBM copy
     and read (GB/s, bytes moved), FP32 / FP64 FMA chains and FP64 matrix-core chains
-    (TFLOP/s)."""
+    (TFLOP/s), v_rsq_f32 alone and followed by four FMAs (lane operations or groups per
+    second, in units of 1e12) and the bf16 matrix-core instruction of the FP32 product (TFLOP/s)."""
     from paper_2511_09798_amd import peak as pk
 
     copy = pk.mqh_peak_probe(pk.MQH_PEAK_COPY, 1 << 31, reps=5)
@@ -97,8 +98,12 @@ def measure_peaks():
     f32 = pk.mqh_peak_probe(pk.MQH_PEAK_FMA_F32, 1 << 14, reps=5)
     f64 = pk.mqh_peak_probe(pk.MQH_PEAK_FMA_F64, 1 << 14, reps=5)
     m64 = pk.mqh_peak_probe(pk.MQH_PEAK_MFMA_F64, 1 << 14, reps=5)
+    rsq = pk.mqh_peak_probe(pk.MQH_PEAK_RSQ_F32, 1 << 12, reps=5)
+    mix = pk.mqh_peak_probe(pk.MQH_PEAK_RSQ_FMA_F32, 1 << 12, reps=5)
+    mbf = pk.mqh_peak_probe(pk.MQH_PEAK_MFMA_BF16, 1 << 13, reps=5)
     return dict(hbm_copy_GBs=copy / 1e9, hbm_read_GBs=read / 1e9, fp32_fma_TFLOPs=f32 / 1e12, fp64_fma_TFLOPs=f64 / 1e12,
-                fp64_mfma_TFLOPs=m64 / 1e12,
+                fp64_mfma_TFLOPs=m64 / 1e12, fp32_rsq_Tps=rsq / 1e12, fp32_rsq_plus_4fma_Tps=mix / 1e12,
+                bf16_mfma_TFLOPs=mbf / 1e12,
                 spec=dict(hbm_GBs=HBM_PEAK_GBS, fp32_vector_TFLOPs=157.3, fp64_vector_TFLOPs=78.6,
                           fp64_matrix_TFLOPs=78.6))
 
@@ -756,10 +761,26 @@ def main():
                                  note=f"{oi} / {ob} operations per interior / boundary entry against the published "
                                       f"{'FP32' if mode == 'matfree_fp32' else 'FP64'} vector peak")
             if mode == "matfree_fp32":
+                e["arithmetic"] = ("entries in FP32 from FP32 node coordinates; the Krylov vector entering each "
+                                   "product rounded to FP32 (folded into the entry coefficients); entry x weight "
+                                   "products summed in FP32 over chunks of 256 loop nodes, chunks and slices "
+                                   "accumulated in FP64; reorthogonalisation, alpha/beta, the projected SVD and "
+                                   "GCV in FP64")
                 quads = (p.n_int * n * QUADS_IDEAL_F32[0] + p.n_bnd * n * QUADS_IDEAL_F32[1]) / 64.0
                 t_ideal = quads / (CUS * SIMDS * CLOCK / 4.0)
                 e["roofline"]["issue_model_ms"] = t_ideal * 1e3
                 e["roofline"]["issue_model_frac"] = t_ideal / (kms * 1e-3)
+                if peaks and peaks.get("fp32_rsq_plus_4fma_Tps"):
+                    # the same instruction mix at the rates the probes measure on this GPU (the
+                    # transcendental unit's work does not overlap the FMAs, nor the matrix cores the
+                    # VALU of the same wave): interior entry = one rsq + 4 FMA group, boundary entry =
+                    # one sqrt (rsq rate) + one FMA, every entry 64 bf16 matrix-core flops
+                    t_mix = (p.n_int * n / (peaks["fp32_rsq_plus_4fma_Tps"] * 1e12)
+                             + p.n_bnd * n * (1.0 / (peaks["fp32_rsq_Tps"] * 1e12)
+                                              + 2.0 / (peaks["fp32_fma_TFLOPs"] * 1e12))
+                             + n * n * 64.0 / (peaks["bf16_mfma_TFLOPs"] * 1e12))
+                    e["roofline"]["measured_mix_model_ms"] = t_mix * 1e3
+                    e["roofline"]["measured_mix_model_frac"] = t_mix / (kms * 1e-3)
                 e["product_equiv_GBs"] = 8.0 * n * n / (kms * 1e-3) / 1e9
         ctx[v] = e
         log(v, json.dumps({k: e.get(k) for k in ("time_to_solution_s", "rel_l2", "lam", "u_rel_diff_vs_fp64")}))

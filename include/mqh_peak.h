@@ -17,6 +17,13 @@
  *   MQH_PEAK_READ:     read-only stream of size bytes (eight 16-byte loads
  *                      in flight per lane, summed per thread); rate = bytes
  *                      read per second.
+ *   MQH_PEAK_RSQ_F32:  chains of v_rsq_f32 (each followed by one add), size
+ *                      iterations; rate = rsq lane operations per second.
+ *   MQH_PEAK_RSQ_FMA_F32: the same with four independent FP32 FMAs after
+ *                      each rsq (the FP32 product's interior instruction
+ *                      mix); rate = groups (rsq + add + 4 FMA) per second.
+ *   MQH_PEAK_MFMA_BF16: chains of v_mfma_f32_16x16x32_bf16, size
+ *                      iterations; rate = flop/s.
  * One warm-up launch, then reps timed launches (HIP events) on stream (NULL:
  * a stream of its own).  The call allocates and frees its buffers (2 x size
  * bytes for the copy).  Returns 0, or -1 (invalid argument: an unknown kind,
@@ -38,6 +45,9 @@ extern "C" {
 #define MQH_PEAK_FMA_F64 2
 #define MQH_PEAK_MFMA_F64 3
 #define MQH_PEAK_READ 4
+#define MQH_PEAK_RSQ_F32 5
+#define MQH_PEAK_RSQ_FMA_F32 6
+#define MQH_PEAK_MFMA_BF16 7
 
 int mqh_peak_probe(int32_t kind, int64_t size, int32_t reps, double* rate, void* stream);
 const char* mqh_peak_last_error(void);

@@ -275,7 +275,10 @@ void launch_peak_read(const double* x, int64_t count, double* out, hipStream_t s
 void launch_peak_fma32(float* out, int iters, hipStream_t s);
 void launch_peak_fma64(double* out, int iters, hipStream_t s);
 void launch_peak_mfma64(double* out, int iters, hipStream_t s);
+void launch_peak_rsq(float* out, int iters, int mix, hipStream_t s);
+void launch_peak_mfma_bf16(float* out, int iters, hipStream_t s);
 double peak_fma_ops(int iters);
 double peak_mfma_flops(int iters);
+double peak_mfma_bf16_flops(int iters);
 
 }  // namespace mqh

@@ -35,7 +35,7 @@ const char* mqh_peak_last_error(void) { return g_peak_error.c_str(); }
 int mqh_peak_probe(int32_t kind, int64_t size, int32_t reps, double* rate, void* stream) {
     if (rate == nullptr) return peak_fail(-1, "NULL rate");
     *rate = 0.0;
-    if (kind < MQH_PEAK_COPY || kind > MQH_PEAK_READ) return peak_fail(-1, "unknown probe kind");
+    if (kind < MQH_PEAK_COPY || kind > MQH_PEAK_MFMA_BF16) return peak_fail(-1, "unknown probe kind");
     if (reps < 1 || reps > 1000) return peak_fail(-1, "reps must be in [1, 1000]");
     const bool stream_kind = kind == MQH_PEAK_COPY || kind == MQH_PEAK_READ;
     if (stream_kind && (size < 16 || size > ((int64_t)64 << 30)))
@@ -76,6 +76,9 @@ int mqh_peak_probe(int32_t kind, int64_t size, int32_t reps, double* rate, void*
             case MQH_PEAK_READ: launch_peak_read(c.a, count, c.b, s); break;
             case MQH_PEAK_FMA_F32: launch_peak_fma32(reinterpret_cast<float*>(c.a), iters, s); break;
             case MQH_PEAK_FMA_F64: launch_peak_fma64(c.a, iters, s); break;
+            case MQH_PEAK_RSQ_F32: launch_peak_rsq(reinterpret_cast<float*>(c.a), iters, 0, s); break;
+            case MQH_PEAK_RSQ_FMA_F32: launch_peak_rsq(reinterpret_cast<float*>(c.a), iters, 1, s); break;
+            case MQH_PEAK_MFMA_BF16: launch_peak_mfma_bf16(reinterpret_cast<float*>(c.a), iters, s); break;
             default: launch_peak_mfma64(c.a, iters, s); break;
         }
     };
@@ -96,6 +99,9 @@ int mqh_peak_probe(int32_t kind, int64_t size, int32_t reps, double* rate, void*
         case MQH_PEAK_READ: work = (double)count * sizeof(double); break;
         case MQH_PEAK_FMA_F32:
         case MQH_PEAK_FMA_F64: work = 2.0 * peak_fma_ops(iters); break;
+        case MQH_PEAK_RSQ_F32:
+        case MQH_PEAK_RSQ_FMA_F32: work = peak_fma_ops(iters); break;
+        case MQH_PEAK_MFMA_BF16: work = peak_mfma_bf16_flops(iters); break;
         default: work = peak_mfma_flops(iters); break;
     }
     *rate = work / sec;

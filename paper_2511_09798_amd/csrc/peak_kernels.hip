@@ -1,8 +1,10 @@
 // peak_kernels.hip -- measurement helpers (libmqhpeak), not part of the solver: the rates
 // the rooflines are checked against on the GPU at hand.  A device-to-device
 // copy and a read-only stream (HBM), FP32 and FP64 FMA chains as the VALU issues them in this build
-// (unpacked: every HIP source here is compiled without packed FP32), and an
-// FP64 matrix-core chain (v_mfma_f64_16x16x4f64).
+// (unpacked: every HIP source here is compiled without packed FP32), an
+// FP64 matrix-core chain (v_mfma_f64_16x16x4f64), and the issue rates of the
+// FP32 product's instructions (v_rsq_f32 alone and mixed with FMAs, the bf16
+// matrix-core instruction).
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -12,6 +14,8 @@ namespace mqh {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kPeakChains = 16;  // independent FMA chains per lane
 constexpr int kPeakCopyUnroll = 4;  // independent 16-byte loads in flight per lane (copy)
@@ -75,6 +79,62 @@ __global__ __launch_bounds__(kBlock) void k_peak_fma(T* __restrict__ out, int it
     out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
 }
 
+// kPeakChains chains v <- rsq(v) + b (one v_rsq_f32 and one add per step;
+// b > 1 keeps v in [b, b + 1]).  With mix, four independent FMAs on other
+// chains follow each rsq: the instruction mix of the FP32 product's
+// interior entry, which shows whether the transcendental unit's work
+// overlaps ordinary VALU instructions.
+__global__ __launch_bounds__(kBlock) void k_peak_rsq(float* __restrict__ out, int iters, float b0, int mix) {
+    const float b = b0 * (1.f + (float)(threadIdx.x & 7) * 1e-7f);
+    const float a = 0.999f * (1.f + (float)(threadIdx.x & 3) * 1e-7f);
+    float v[kPeakChains], w[kPeakChains];
+#pragma unroll
+    for (int k = 0; k < kPeakChains; ++k) {
+        v[k] = b + (float)k * 1e-3f;
+        w[k] = (float)(threadIdx.x + k) * 1e-3f;
+    }
+    if (mix) {
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int k = 0; k < kPeakChains; ++k) {
+                v[k] = __builtin_amdgcn_rsqf(v[k]) + b;
+                w[k] = fmaf(fmaf(fmaf(fmaf(w[k], a, b), a, b), a, b), a, b);
+            }
+        }
+    } else {
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int k = 0; k < kPeakChains; ++k) v[k] = __builtin_amdgcn_rsqf(v[k]) + b;
+        }
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < kPeakChains; ++k) s += v[k] + w[k];
+    out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+// kPeakMfma accumulators, iters steps of v_mfma_f32_16x16x32_bf16 each (the
+// instruction that forms t in the FP32 product).
+__global__ __launch_bounds__(kBlock) void k_peak_mfma_bf16(float* __restrict__ out, int iters) {
+    v8bf a, bb;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        a[i] = (__bf16)(1e-3f * (float)((threadIdx.x + i) & 63));
+        bb[i] = (__bf16)(0.5f - 1e-3f * (float)i);
+    }
+    v4f acc[kPeakMfma];
+#pragma unroll
+    for (int q = 0; q < kPeakMfma; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int q = 0; q < kPeakMfma; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[q], 0, 0, 0);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < kPeakMfma; ++q) s += acc[q][0] + acc[q][1] + acc[q][2] + acc[q][3];
+    out[(int64_t)blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
 // kPeakMfma accumulators, iters matrix-core steps each.
 __global__ __launch_bounds__(kBlock) void k_peak_mfma64(double* __restrict__ out, int iters) {
     const double a = 1e-3 * (double)(threadIdx.x & (kWave - 1)), b = 0.5;
@@ -116,10 +176,21 @@ void launch_peak_mfma64(double* out, int iters, hipStream_t s) {
     k_peak_mfma64<<<(unsigned)peak_blocks(), kBlock, 0, s>>>(out, iters);
 }
 
+void launch_peak_rsq(float* out, int iters, int mix, hipStream_t s) {
+    k_peak_rsq<<<(unsigned)peak_blocks(), kBlock, 0, s>>>(out, iters, 1.5f, mix);
+}
+
+void launch_peak_mfma_bf16(float* out, int iters, hipStream_t s) {
+    k_peak_mfma_bf16<<<(unsigned)peak_blocks(), kBlock, 0, s>>>(out, iters);
+}
+
 // Work per launch: FMA lane operations (fma kinds) or flops (matrix cores).
 double peak_fma_ops(int iters) { return (double)peak_blocks() * kBlock * kPeakChains * (double)iters; }
 double peak_mfma_flops(int iters) {
     return (double)peak_blocks() * (kBlock / kWave) * kPeakMfma * (double)iters * (2.0 * 16 * 16 * 4);
+}
+double peak_mfma_bf16_flops(int iters) {
+    return (double)peak_blocks() * (kBlock / kWave) * kPeakMfma * (double)iters * (2.0 * 16 * 16 * 32);
 }
 
 }  // namespace mqh

@@ -13,6 +13,9 @@ MQH_PEAK_FMA_F32 = 1
 MQH_PEAK_FMA_F64 = 2
 MQH_PEAK_MFMA_F64 = 3
 MQH_PEAK_READ = 4
+MQH_PEAK_RSQ_F32 = 5
+MQH_PEAK_RSQ_FMA_F32 = 6
+MQH_PEAK_MFMA_BF16 = 7
 
 
 def _load():
@@ -35,7 +38,8 @@ lib = _load()
 
 
 def mqh_peak_probe(kind: int, size: int, reps: int = 5, stream=None) -> float:
-    """Rate of a reference kernel: bytes/s for MQH_PEAK_COPY and MQH_PEAK_READ, flop/s otherwise."""
+    """Rate of a reference kernel: bytes/s for MQH_PEAK_COPY and MQH_PEAK_READ, rsq (or rsq + 4 FMA
+    groups) per second for MQH_PEAK_RSQ_F32 (MQH_PEAK_RSQ_FMA_F32), flop/s otherwise."""
     rate = ctypes.c_double(0.0)
     st = lib.mqh_peak_probe(int(kind), int(size), int(reps), ctypes.byref(rate),
                             None if stream is None else int(getattr(stream, "cuda_stream", stream)))

@@ -200,7 +200,7 @@ def test_peak_library_separate_and_checks_arguments():
     assert not hasattr(mqhelm.lib, "mqh_peak_probe") or "mqh_peak_probe" not in mqhelm._SIGNATURES
     L = peak.lib
     r = ctypes.c_double(1.0)
-    assert L.mqh_peak_probe(7, 1024, 1, ctypes.byref(r), None) == -1
+    assert L.mqh_peak_probe(8, 1024, 1, ctypes.byref(r), None) == -1
     assert L.mqh_peak_probe(peak.MQH_PEAK_READ, 8, 1, ctypes.byref(r), None) == -1
     assert r.value == 0.0
     assert L.mqh_peak_probe(peak.MQH_PEAK_COPY, 8, 1, ctypes.byref(r), None) == -1
