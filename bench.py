@@ -51,10 +51,13 @@ OPS_F32 = (18, 12)
 # FP64 matrix-free product: interior 3 sub + 3 fma + rsq + 8 (two Newton steps)
 # + mul + 2 fma + mul + fma = 20, boundary 17; rated against the FP64 peak.
 OPS_F64 = (20, 17)
-# Issue quad-cycles per 64 entries of the FP32 product's instructions if
-# every pairable VALU instruction were paired (one bf16 MFMA per 256 entries,
-# interior rsq + 4 pairable, boundary sqrt + 1): the issue model.
-QUADS_IDEAL_F32 = (5.0, 3.5)
+# The FP32-evaluated product evaluates every unordered pair of nodes once
+# (t, the rsqrt and the formula serve A_ij and A_ji).  Issue quad-cycles per
+# 64 pairs if every pairable VALU instruction were paired: one bf16 MFMA per
+# 256 pairs (1), rsq or sqrt (2), and half the pairable FP32 instructions:
+# interior-interior 6 (s^2, 2 for the formula, the product by s, the row and
+# the column sums), interior-boundary 7 (also t s), boundary-boundary 2.
+QUADS_IDEAL_PAIR = dict(ii=1.0 + 2.0 + 3.0, ib=1.0 + 2.0 + 3.5, bb=1.0 + 2.0 + 1.0)
 TILE = 128
 PROFILES = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
@@ -754,31 +757,39 @@ def main():
             ops = p.n_int * n * oi + p.n_bnd * n * ob
             e["roofline"] = dict(bound="alu", achieved=ops / (kms * 1e-3) / 1e12, peak=pk / 1e12, unit="TOP/s",
                                  frac=ops / (kms * 1e-3) / pk, ops_per_launch=ops,
-                                 kernel=("k_mfm<false>" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mfm<true>")
+                                 kernel=("k_mfs<true>" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mfs<false>")
                                  if mode == "matfree_fp32" else
                                  ("k_mf_cols" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mf_rows"),
                                  kernel_ms=kms,
                                  note=f"{oi} / {ob} operations per interior / boundary entry against the published "
                                       f"{'FP32' if mode == 'matfree_fp32' else 'FP64'} vector peak")
             if mode == "matfree_fp32":
-                e["arithmetic"] = ("entries in FP32 from FP32 node coordinates; the Krylov vector entering each "
-                                   "product rounded to FP32 (folded into the entry coefficients); entry x weight "
-                                   "products summed in FP32 over chunks of 256 loop nodes, chunks and slices "
-                                   "accumulated in FP64; reorthogonalisation, alpha/beta, the projected SVD and "
-                                   "GCV in FP64")
-                quads = (p.n_int * n * QUADS_IDEAL_F32[0] + p.n_bnd * n * QUADS_IDEAL_F32[1]) / 64.0
+                e["arithmetic"] = ("entries in FP32 from FP32 node coordinates, each unordered pair of nodes "
+                                   "evaluated once for A_ij and A_ji; the Krylov vector entering each product "
+                                   "rounded to FP32; row sums in FP32 over chunks of 256 loop nodes and column "
+                                   "sums in FP32 over 32 fixed nodes, both accumulated in FP64; "
+                                   "reorthogonalisation, alpha/beta, the projected SVD and GCV in FP64")
+                e["roofline"]["note"] += ("; the kernel evaluates each unordered pair of nodes once, about half "
+                                          "of these operations")
+                pii = p.n_int * p.n_int / 2.0
+                pib = float(p.n_int) * p.n_bnd
+                pbb = p.n_bnd * p.n_bnd / 2.0
+                quads = (pii * QUADS_IDEAL_PAIR["ii"] + pib * QUADS_IDEAL_PAIR["ib"] + pbb * QUADS_IDEAL_PAIR["bb"]) / 64.0
                 t_ideal = quads / (CUS * SIMDS * CLOCK / 4.0)
                 e["roofline"]["issue_model_ms"] = t_ideal * 1e3
                 e["roofline"]["issue_model_frac"] = t_ideal / (kms * 1e-3)
                 if peaks and peaks.get("fp32_rsq_plus_4fma_Tps"):
-                    # the same instruction mix at the rates the probes measure on this GPU (the
+                    # the pairs' instruction mix at the rates the probes measure on this GPU (the
                     # transcendental unit's work does not overlap the FMAs, nor the matrix cores the
-                    # VALU of the same wave): interior entry = one rsq + 4 FMA group, boundary entry =
-                    # one sqrt (rsq rate) + one FMA, every entry 64 bf16 matrix-core flops
-                    t_mix = (p.n_int * n / (peaks["fp32_rsq_plus_4fma_Tps"] * 1e12)
-                             + p.n_bnd * n * (1.0 / (peaks["fp32_rsq_Tps"] * 1e12)
-                                              + 2.0 / (peaks["fp32_fma_TFLOPs"] * 1e12))
-                             + n * n * 64.0 / (peaks["bf16_mfma_TFLOPs"] * 1e12))
+                    # VALU of the same wave): an interior-interior pair = one rsq + 4 FMA group and 2
+                    # FMAs more, interior-boundary 3 more, boundary-boundary one sqrt and 2 FMAs; every
+                    # pair 64 bf16 matrix-core flops
+                    grp = peaks["fp32_rsq_plus_4fma_Tps"] * 1e12
+                    fma = peaks["fp32_fma_TFLOPs"] * 1e12 / 2.0
+                    rsq = peaks["fp32_rsq_Tps"] * 1e12
+                    t_mix = (pii * (1.0 / grp + 2.0 / fma) + pib * (1.0 / grp + 3.0 / fma)
+                             + pbb * (1.0 / rsq + 2.0 / fma)
+                             + (pii + pib + pbb) * 64.0 / (peaks["bf16_mfma_TFLOPs"] * 1e12))
                     e["roofline"]["measured_mix_model_ms"] = t_mix * 1e3
                     e["roofline"]["measured_mix_model_frac"] = t_mix / (kms * 1e-3)
                 e["product_equiv_GBs"] = 8.0 * n * n / (kms * 1e-3) / 1e9

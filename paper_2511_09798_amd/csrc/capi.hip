@@ -223,6 +223,13 @@ struct mqh_problem {
     int32_t* iperm = nullptr;  // iperm[perm[q]] = q
     float4* frames = nullptr;
     float4* cf = nullptr;
+    // the single-vector FP32 products over unordered node pairs: work items,
+    // their tables, and the row / column partials of a product
+    SymLayout sym{};
+    int2* sym_items = nullptr;
+    int32_t* sym_first = nullptr;
+    double* sym_row = nullptr;
+    double* sym_col = nullptr;
     // stored matrix: kTile x kTile tiles with the symmetric blocks stored once
     // (layout at the stored operator in op_kernels.hip), its tables, and the
     // product partials (PR per work item, PC per stored tile)
@@ -402,22 +409,25 @@ void packed_tables(int64_t n, int64_t n_int, PackedTables& t) {
 }
 
 void choose_shapes(mqh_problem* p) {
+    // the split of the FP64 matrix-free products (the FP32-evaluated ones run
+    // over work items of node pairs, the stored ones over tiles): slices of
+    // even length, enough blocks for many rounds of resident waves over 256 CUs
     const int64_t n = p->n;
-    // Enough blocks for many rounds of resident waves over 256 CUs.
-    const bool f32 = p->mode == MQH_OP_MATFREE_FP32;
-    const int64_t target_blocks = f32 ? 24576 : 4096;
-    // FP32-evaluated products: blocks of kMfmFixed sorted nodes and slices of
-    // whole LDS chunks; FP64 ones: one output per lane, slices of even length.
-    const int64_t quantum = f32 ? kBlock : 2;
-    const int64_t nb_rows = f32 ? mfm_blocks(n, p->n_int)
-                                : (p->n_int + kBlock - 1) / kBlock + (p->n_bnd + kBlock - 1) / kBlock;
-    const int64_t nb_cols = f32 ? mfm_blocks(n, p->n_int) : (n + kBlock - 1) / kBlock;
+    if (p->mode != MQH_OP_MATFREE_FP64) {
+        p->S_rows = p->S_cols = 1;
+        p->slice_rows = p->slice_cols = n;
+        p->P_rows = 1;
+        return;
+    }
+    const int64_t target_blocks = 4096;
+    const int64_t nb_rows = (p->n_int + kBlock - 1) / kBlock + (p->n_bnd + kBlock - 1) / kBlock;
+    const int64_t nb_cols = (n + kBlock - 1) / kBlock;
     auto pick = [&](int64_t nb, int& S, int64_t& len) {
         int64_t s = (target_blocks + nb - 1) / nb;
         if (s < 1) s = 1;
         if (s > 64) s = 64;
         int64_t l = (n + s - 1) / s;
-        l = round_up(l < 64 ? 64 : l, quantum);
+        l = round_up(l < 64 ? 64 : l, 2);
         s = (n + l - 1) / l;
         S = (int)(s < 1 ? 1 : s);
         len = l;
@@ -457,6 +467,47 @@ int scale_rhs(mqh_problem* p, double* x, int nz, int64_t stride) {
 
 // One product y = op(A) x - shift z on device vectors (x, z of length ldn,
 // zero-padded).  shift from *shift_ptr when non-null.
+// Work items of the pair products (SymLayout): blocks of kMfmFixed sorted
+// nodes per class; super-rows of F fixed blocks and segments of Lb loop
+// blocks, the largest (F, Lb) that still gives enough items to fill the GPU;
+// first[k] indexes the items in (super-row, segment) order, the list itself
+// is in launch order.
+void sym_tables(int64_t n, int64_t n_int, SymLayout& L, std::vector<int2>& items, std::vector<int32_t>& first) {
+    L = SymLayout{};
+    L.n = n;
+    L.n_int = n_int;
+    L.nb_int = (int32_t)((n_int + kMfmFixed - 1) / kMfmFixed);
+    L.nb = L.nb_int + (int32_t)((n - n_int + kMfmFixed - 1) / kMfmFixed);
+    static const int shapes[][2] = {{8, 14}, {4, 8}, {2, 4}, {1, 2}};
+    for (const auto& sh : shapes) {
+        items.clear();
+        first.clear();
+        const int F = sh[0], Lb = sh[1];
+        const int nsr = (L.nb + F - 1) / F;
+        for (int k = 0; k < nsr; ++k) {
+            first.push_back((int32_t)items.size());
+            const int nseg = (L.nb - k * F + Lb - 1) / Lb;
+            for (int sg = 0; sg < nseg; ++sg) items.push_back(make_int2(k, sg));
+        }
+        first.push_back((int32_t)items.size());
+        L.F = F;
+        L.Lb = Lb;
+        L.nsr = nsr;
+        L.nitems = (int32_t)items.size();
+        if (L.nitems >= 1200) break;
+    }
+    // launch order: items by their number of block pairs, largest first
+    // (stable), so the last workgroups to start are the short ones
+    auto pairs = [&](const int2& it) {
+        const int b0 = it.x * L.F, b1 = std::min(b0 + L.F, L.nb);
+        const int c0 = b0 + it.y * L.Lb, c1 = std::min(c0 + L.Lb, L.nb);
+        int64_t cnt = 0;
+        for (int b = b0; b < b1; ++b) cnt += std::max(0, c1 - std::max(c0, b));
+        return cnt;
+    };
+    std::stable_sort(items.begin(), items.end(), [&](const int2& a, const int2& b) { return pairs(a) > pairs(b); });
+}
+
 int op_product(mqh_problem* p, int trans, const double* x, const double* shift_ptr, double shift_val, const double* z,
                double* y, const GkbState* st, bool timed) {
     hipStream_t s = p->stream;
@@ -486,14 +537,17 @@ int op_product(mqh_problem* p, int trans, const double* x, const double* shift_p
         LAUNCHCHK("stored product reduction");
         return MQH_OK;
     }
+    if (p->mode == MQH_OP_MATFREE_FP32) {
+        launch_mfs_product(trans, p->XS, p->frames, p->cf, p->sym, op_ec(p), p->sym_row, p->sym_col, st, s);
+        LAUNCHCHK("pair product");
+        if (timed) HIPCHK(hipEventRecord(e1, s));
+        launch_mfs_reduce(p->sym, p->sym_row, p->sym_col, p->perm, shift_ptr, shift_val, z, y, st, s);
+        LAUNCHCHK("pair product reduction");
+        return MQH_OK;
+    }
     int S;
     const int32_t* perm = nullptr;
-    if (p->mode == MQH_OP_MATFREE_FP32) {
-        S = trans ? p->S_cols : p->S_rows;
-        launch_mfm_product(trans, p->XS, p->frames, p->cf, p->n, p->n_int, S, trans ? p->slice_cols : p->slice_rows,
-                           p->P, p->ldn, st, s);
-        perm = p->perm;
-    } else if (!trans) {
+    if (!trans) {
         S = p->S_rows;
         launch_mf_rows(p->X64, x, p->n, p->n_int, S, p->slice_rows, op_ec(p), p->P, p->ldn, st, s);
     } else {
@@ -1716,6 +1770,10 @@ int mqh_problem_destroy(mqh_problem* p) {
     dfree(p->iperm);
     dfree(p->frames);
     dfree(p->cf);
+    dfree(p->sym_items);
+    dfree(p->sym_first);
+    dfree(p->sym_row);
+    dfree(p->sym_col);
     dfree(p->A);
     dfree(p->pk_tile_base);
     dfree(p->pk_items);
@@ -1870,6 +1928,21 @@ int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, 
                                 p->stream)) ||
             (e = hipStreamSynchronize(p->stream)))
             return bail(hip_fail(e, "upload of the sorted layout"));
+        std::vector<int2> items;
+        std::vector<int32_t> first;
+        sym_tables(n, n_int, p->sym, items, first);
+        if ((rc = dalloc(&p->sym_items, items.size())) || (rc = dalloc(&p->sym_first, first.size())) ||
+            (rc = dalloc(&p->sym_row, items.size() * (size_t)p->sym.F * kMfmFixed)) ||
+            (rc = dalloc(&p->sym_col, items.size() * (size_t)p->sym.Lb * kMfmFixed)))
+            return bail(rc);
+        if ((e = hipMemcpyAsync(p->sym_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                p->stream)) ||
+            (e = hipMemcpyAsync(p->sym_first, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                p->stream)) ||
+            (e = hipStreamSynchronize(p->stream)))
+            return bail(hip_fail(e, "upload of the pair-product tables"));
+        p->sym.items = p->sym_items;
+        p->sym.item_first = p->sym_first;
     }
     if (op_mode == MQH_OP_STORED_FP64) {
         PackedTables t;

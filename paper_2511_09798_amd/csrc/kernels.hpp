@@ -43,6 +43,26 @@ struct PackedLayout {
     const int32_t* item_first;  // nt + 1 entries: first item of each tile row
 };
 
+// FP32-evaluated products over unordered node pairs (each pair's t and
+// rsqrt once, feeding y_i and y_j): nodes in the sorted order cut into
+// blocks of kMfmFixed per class (interior blocks 0 .. nb_int-1, boundary
+// blocks nb_int .. nb-1).  Work item (k, s): fixed blocks [kF, kF + F) (a
+// super-row) against loop blocks [kF + s Lb, kF + (s+1) Lb) (a segment),
+// only pairs of blocks b <= c (b == c: the block's own square, row sums
+// only).  Each item writes F x kMfmFixed row partials and Lb x kMfmFixed
+// column partials; a node's output adds the row partials of its super-row's
+// items and the column partials of the items whose segment holds it.
+constexpr int kSymMaxF = 8;    // fixed blocks per super-row (at most)
+constexpr int kSymMaxLb = 14;  // loop blocks per segment (at most; the LDS of four workgroups per CU)
+struct SymLayout {
+    int64_t n, n_int;
+    int32_t nb_int, nb;         // blocks of kMfmFixed nodes per class, all blocks
+    int32_t F, Lb;              // fixed blocks per super-row, loop blocks per segment
+    int32_t nsr, nitems;        // super-rows, work items
+    const int2* items;          // (super-row, segment) of every item, in launch order (largest first)
+    const int32_t* item_first;  // nsr + 1 entries: first item of each super-row
+};
+
 // Result of the parameter choice, device-resident.
 struct ParamOut {
     double lambda;
@@ -61,9 +81,11 @@ void launch_mf_cols(const double4* X, const double* x, int64_t n, int64_t n_int,
 int64_t mfm_blocks(int64_t n, int64_t n_int);
 void launch_gather_coef(const double* x, const int32_t* perm, int64_t n, const EntryConst& c, float4* CF,
                         const GkbState* st, hipStream_t s);
-void launch_mfm_product(int trans, const float4* XS, const float4* frames, const float4* CF, int64_t n,
-                        int64_t n_int, int S, int64_t slice_len, double* P, int64_t ldp, const GkbState* st,
-                        hipStream_t s);
+void launch_mfs_product(int trans, const float4* XS, const float4* frames, const float4* CF, const SymLayout& L,
+                        const EntryConst& c, double* RowP, double* ColP, const GkbState* st, hipStream_t s);
+void launch_mfs_reduce(const SymLayout& L, const double* RowP, const double* ColP, const int32_t* perm,
+                       const double* shift_ptr, double shift_val, const double* z, double* y, const GkbState* st,
+                       hipStream_t s);
 void launch_mfm_block(int trans, const float4* XS, const float4* frames, const float* Vg, int64_t n, int64_t n_int,
                       int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp, hipStream_t s);
 void launch_fill_hash(float* Vg, int64_t count, hipStream_t s);

@@ -119,12 +119,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce_slices(const double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// FP32-evaluated matrix-free products on the matrix cores.
+// FP32-evaluated matrix-free products: the squared distances on the matrix
+// cores.
 //
 // Nodes are visited in a spatially sorted order (Morton order within each
-// class, interior first) and cut into blocks of kMfmFixed "fixed" nodes (the
-// outputs: rows for A x, columns for A^T x), each with a frame centre c among
-// its nodes.  With d = P - c (P the eps-scaled node, in FP32),
+// class, interior first) and cut into blocks of kMfmFixed "fixed" nodes, each
+// with a frame centre c among its nodes.  With d = P - c (P the eps-scaled
+// node, in FP32),
 //     t_ij = 1 + |d_i - d_j|^2 = |d_i|^2 + sum_k a_ik b_kj,
 //     a_i = (-2 d_i, 1),  b_j = (d_j, 1 + |d_j|^2),
 // a K = 4 contraction per 16 x 16 tile of entries.  Each FP32 factor is split
@@ -134,10 +135,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_slices(const double* __restri
 // one v_mfma_f32_16x16x32_bf16: t comes out with FP32 accuracy at half the
 // matrix-core time of the FP32 MFMA.  Close pairs have small |d_i|, |d_j|
 // (the frame sits among the fixed nodes), so t keeps its relative accuracy
-// where 1 + eps^2 r^2 is near 1.  The entry is evaluated on the VALU from t
-// (interior: (w kappa^2 t + 2 w eps^2 + w eps^2 s^2) s with s = t^(-1/2);
-// boundary: w sqrt(t)), summed in FP32 over the 16 loop nodes a lane sees per
-// chunk, then in FP64.
+// where 1 + eps^2 r^2 is near 1.  The entries are evaluated on the VALU from
+// t: by the pair products (one vector) and the block products (16 vectors)
+// below.
 //
 // Lane layout of v_mfma_f32_16x16x32_bf16 (wave64): lane l holds A[l%16][k]
 // and B[k][l%16] for k = 8(l/16) .. 8(l/16)+7, and D[4(l/16)+r][l%16],
@@ -189,181 +189,337 @@ __device__ __forceinline__ v4u loop_terms(float b) {
     return r;
 }
 
-// Accumulates, for the 4 * kMfmFt fixed nodes of this lane, the sum over loop
-// nodes j in [j0, j1) (a lane sees the loop nodes j = l mod 16) of
-// w_j * entry, the entry kind INTERIOR.  CF holds the weight-folded
-// coefficients (w kappa^2, 2 w eps^2, w eps^2, w) of every sorted node.
-// j0, j1 are block-uniform (contains barriers).
-template <bool INTERIOR>
-__device__ __forceinline__ void mfm_span(const float4* __restrict__ XS, const float4* __restrict__ CF, int64_t j0,
-                                         int64_t j1, const float4& fr, const v4u (&a)[kMfmFt],
-                                         const v4f (&C)[kMfmFt], double (&acc)[kMfmFt][4],
-                                         v4u* __restrict__ lds_b, float4* __restrict__ lds_c) {
+// ---------------------------------------------------------------------------
+// FP32-evaluated products over unordered pairs of nodes.
+//
+// The entry of A depends on t_ij = 1 + eps^2 r_ij^2 and on the kind of its
+// row only, so A_ij and A_ji share t and s = t^(-1/2): for an interior row
+// the entry is (kappa^2 t + 2 eps^2 + eps^2 s^2) s, for a boundary row
+// t s = sqrt(t).  A product y = A x (or A^T x) therefore needs each
+// unordered pair {i, j} once: y_i += A_ij x_j and y_j += A_ji x_i (A^T: the
+// two entries swap).  On this GPU the rsqrt of an entry costs as much as all
+// its other VALU work together and overlaps none of it, so halving the
+// pairs halves the dominant cost.
+//
+// Work item (k, s) of the SymLayout: fixed blocks fb of super-row k one
+// after another; for each, the loop blocks c >= fb of segment s in chunks
+// of at most two blocks of one class (the block's own square fb == fb on its
+// own, row sums only).  Per 16 x 16 tile the MFMA above gives t (frame of
+// the fixed block); a lane holds 4 fixed rows x 1 loop column per tile and
+// kMfmFt tiles.  Row sums stay per lane in FP32 over a chunk, then FP64;
+// a tile's column sums (a lane's 8 rows in FP32) are added over pairs of
+// lane groups by a swizzle and stored to LDS, and after the chunk the 8
+// partials of each loop node are added in FP64 and collected in LDS over the
+// item's fixed blocks.  Weights come
+// from CF[q].w (w = x[perm[q]] in FP32).  Work items are launched largest
+// first and write their partials at their place in (super-row, segment) order.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t sym_blk_start(int b, const SymLayout& L) {
+    return b < L.nb_int ? (int64_t)b * kMfmFixed : L.n_int + (int64_t)(b - L.nb_int) * kMfmFixed;
+}
+__device__ __forceinline__ int64_t sym_blk_end(int b, const SymLayout& L) {
+    const int64_t e = sym_blk_start(b, L) + kMfmFixed;
+    const int64_t lim = b < L.nb_int ? L.n_int : L.n;
+    return e < lim ? e : lim;
+}
+
+// NT staged tiles of 16 loop nodes against the lane's fixed rows.  RI / CI:
+// the row sums / column sums take the interior formula (else the boundary
+// one); SYM: column sums wanted (off the block's own square).
+template <bool RI, bool CI, bool SYM, int NT>
+__device__ __forceinline__ void mfs_tiles(const v4u* __restrict__ lds_b, const float* __restrict__ lds_w,
+                                          const v4u (&a)[kMfmFt], const v4f (&C)[kMfmFt],
+                                          const float (&xi)[kMfmFt][4], float k2, float e2x2, float e2,
+                                          double (&acc)[kMfmFt][4], float* __restrict__ colw) {
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15;
-    for (int64_t t0 = j0; t0 < j1; t0 += kMfmChunk) {
-        // stage one loop node per thread: B operand (4 lane groups x 8 bf16)
-        // and its coefficients; nodes past j1 get d = 0, w = 0
-        const int64_t j = t0 + threadIdx.x;
-        float dx = 0.f, dy = 0.f, dz = 0.f;
-        float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (j < j1) {
-            const float4 q = XS[j];
-            cf = CF[j];
-            dx = q.x - fr.x;
-            dy = q.y - fr.y;
-            dz = q.z - fr.z;
-        }
-        const v4u b0 = loop_terms(dx), b1 = loop_terms(dy), b2 = loop_terms(dz);
-        unsigned h, m, l;
-        split_bf16x3(fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 1.0f))), h, m, l);
-        v4u b3;
-        b3[0] = pack_bf16(h, m);
-        b3[1] = l >> 16;
-        b3[2] = 0u;
-        b3[3] = 0u;
-        __syncthreads();  // the previous chunk has been consumed
-        lds_b[threadIdx.x * 4 + 0] = b0;
-        lds_b[threadIdx.x * 4 + 1] = b1;
-        lds_b[threadIdx.x * 4 + 2] = b2;
-        lds_b[threadIdx.x * 4 + 3] = b3;
-        lds_c[threadIdx.x] = cf;
-        __syncthreads();
-        // 16 tiles of 16 loop nodes; the next tile's products are issued
-        // before this tile's entries are evaluated
-        float s32[kMfmFt][4];
+    float s32[kMfmFt][4];
+#pragma unroll
+    for (int f = 0; f < kMfmFt; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s32[f][r] = 0.f;
+    v4f t[kMfmFt];
+    float wl = lds_w[jj];
+    {
+        const v8bf bk = __builtin_bit_cast(v8bf, lds_b[jj * 4 + g]);
 #pragma unroll
         for (int f = 0; f < kMfmFt; ++f)
+            t[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[f]), bk, C[f], 0, 0, 0);
+    }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) s32[f][r] = 0.f;
-        float4 q = lds_c[jj];
-        v4f t[kMfmFt];
-        {
-            const v8bf bk = __builtin_bit_cast(v8bf, lds_b[jj * 4 + g]);
-#pragma unroll
-            for (int f = 0; f < kMfmFt; ++f)
-                t[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[f]), bk, C[f], 0, 0, 0);
-        }
-#pragma unroll
-        for (int u = 0; u < kMfmChunk / 16; ++u) {
+    for (int u = 0; u < 16; ++u) {
+        if (u < NT) {
             v4f tn[kMfmFt];
-            float4 qn = q;
-            if (u + 1 < kMfmChunk / 16) {
+            float wn = wl;
+            if (u + 1 < NT) {
                 const v8bf bn = __builtin_bit_cast(v8bf, lds_b[((u + 1) * 16 + jj) * 4 + g]);
-                qn = lds_c[(u + 1) * 16 + jj];
+                wn = lds_w[(u + 1) * 16 + jj];
 #pragma unroll
                 for (int f = 0; f < kMfmFt; ++f)
                     tn[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a[f]), bn, C[f], 0, 0, 0);
             }
+            float cp = 0.f;
 #pragma unroll
             for (int f = 0; f < kMfmFt; ++f) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    if (INTERIOR) {
-                        const float s = __builtin_amdgcn_rsqf(t[f][r]);
-                        const float inner = fmaf(q.z, s * s, fmaf(q.x, t[f][r], q.y));
-                        s32[f][r] = fmaf(inner, s, s32[f][r]);
+                    const float tt = t[f][r];
+                    if (RI && CI) {
+                        const float sv = __builtin_amdgcn_rsqf(tt);
+                        const float e = fmaf(e2, sv * sv, fmaf(k2, tt, e2x2)) * sv;
+                        s32[f][r] = fmaf(e, wl, s32[f][r]);
+                        if (SYM) cp = fmaf(e, xi[f][r], cp);
+                    } else if (!RI && !CI) {
+                        const float e = __builtin_amdgcn_sqrtf(tt);
+                        s32[f][r] = fmaf(e, wl, s32[f][r]);
+                        if (SYM) cp = fmaf(e, xi[f][r], cp);
                     } else {
-                        s32[f][r] = fmaf(__builtin_amdgcn_sqrtf(t[f][r]), q.w, s32[f][r]);
+                        const float sv = __builtin_amdgcn_rsqf(tt);
+                        const float ei = fmaf(e2, sv * sv, fmaf(k2, tt, e2x2)) * sv;
+                        const float eb = tt * sv;
+                        s32[f][r] = fmaf(RI ? ei : eb, wl, s32[f][r]);
+                        cp = fmaf(CI ? ei : eb, xi[f][r], cp);
                     }
                 }
             }
-            if (u + 1 < kMfmChunk / 16) {
+            // keep the row and column sums at their tile: left to itself the
+            // compiler sinks them to their uses after the loop and holds every
+            // tile's entries live until then
+#pragma unroll
+            for (int f = 0; f < kMfmFt; ++f)
+                asm volatile("" : "+v"(s32[f][0]), "+v"(s32[f][1]), "+v"(s32[f][2]), "+v"(s32[f][3]));
+            if (SYM) {
+                // lanes l and l ^ 16 hold the same loop node: add them (ds_swizzle,
+                // xor 16 within each half-wave) and let the lower lane store
+                const float o = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(cp), 0x401F));
+                cp += o;
+                if ((lane & 16) == 0) colw[u * 16] = cp;
+            }
+            if (u + 1 < NT) {
 #pragma unroll
                 for (int f = 0; f < kMfmFt; ++f) t[f] = tn[f];
-                q = qn;
+                wl = wn;
             }
         }
-#pragma unroll
-        for (int f = 0; f < kMfmFt; ++f)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[f][r] += (double)s32[f][r];
     }
+#pragma unroll
+    for (int f = 0; f < kMfmFt; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[f][r] += (double)s32[f][r];
 }
 
-// Partial products in sorted order: P[slice][q] for fixed node q of block
-// blockIdx.x (blocks [0, nb_int) hold interior nodes, the rest boundary
-// ones).  ROWS: y = A x (entry kind from the fixed row); otherwise
-// y = A^T x (entry kind from the loop row; the loop range is split at n_int).
-template <bool ROWS>
-__global__ __launch_bounds__(kBlock) void k_mfm(const float4* __restrict__ XS, const float4* __restrict__ CF,
-                                                int64_t n, int64_t n_int, int64_t nb_int, int64_t slice_len,
-                                                const float4* __restrict__ frames, double* __restrict__ P,
-                                                int64_t ldp, const GkbState* __restrict__ st) {
+template <int NT>
+__device__ __forceinline__ void mfs_dispatch(bool ri, bool ci, const v4u* lds_b, const float* lds_w,
+                                             const v4u (&a)[kMfmFt], const v4f (&C)[kMfmFt],
+                                             const float (&xi)[kMfmFt][4], float k2, float e2x2, float e2,
+                                             double (&acc)[kMfmFt][4], float* colw) {
+    if (ri && ci)
+        mfs_tiles<true, true, true, NT>(lds_b, lds_w, a, C, xi, k2, e2x2, e2, acc, colw);
+    else if (!ri && !ci)
+        mfs_tiles<false, false, true, NT>(lds_b, lds_w, a, C, xi, k2, e2x2, e2, acc, colw);
+    else if (ri)
+        mfs_tiles<true, false, true, NT>(lds_b, lds_w, a, C, xi, k2, e2x2, e2, acc, colw);
+    else
+        mfs_tiles<false, true, true, NT>(lds_b, lds_w, a, C, xi, k2, e2x2, e2, acc, colw);
+}
+
+// One work item (blockIdx.x) of the SymLayout.  TRANS: y = A^T x.
+// RowP[item][(fb - kF) kMfmFixed + row], ColP[item][(c - c0) kMfmFixed + node].
+template <bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_mfs(const float4* __restrict__ XS, const float4* __restrict__ CF,
+                                                SymLayout L, const float4* __restrict__ frames, EntryConst c,
+                                                double* __restrict__ RowP, double* __restrict__ ColP,
+                                                const GkbState* __restrict__ st) {
     __shared__ v4u lds_b[4 * kMfmChunk];
-    __shared__ float4 lds_c[kMfmChunk];
+    __shared__ float lds_w[kMfmChunk];
+    __shared__ float lds_col[2 * (kBlock / kWave)][kMfmChunk];  // per (wave, lane-group pair)
+    __shared__ double colacc[kSymMaxLb * kMfmFixed];
     if (st != nullptr && st->stopped) return;
-    const int64_t b = blockIdx.x;
-    const bool fint = b < nb_int;
-    const int64_t fb0 = fint ? b * kMfmFixed : n_int + (b - nb_int) * kMfmFixed;
-    const int64_t fend = fint ? n_int : n;
-    const int64_t fb1 = fb0 + kMfmFixed < fend ? fb0 + kMfmFixed : fend;
-    const float4 fr = frames[b];
-    const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15, wv = threadIdx.x / kWave;
-    v4u a[kMfmFt];
-    v4f C[kMfmFt];
-    double acc[kMfmFt][4];
+    const int2 item = L.items[blockIdx.x];  // launch order: the largest items first
+    const int64_t slot = (int64_t)L.item_first[item.x] + item.y;  // the item's place in the partials
+    const int b0 = item.x * L.F;
+    const int b1 = b0 + L.F < L.nb ? b0 + L.F : L.nb;
+    const int c0 = b0 + item.y * L.Lb;
+    const int c1 = c0 + L.Lb < L.nb ? c0 + L.Lb : L.nb;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), g = lane >> 4, jj = lane & 15, wv = tid / kWave;
+    for (int i = tid; i < kSymMaxLb * kMfmFixed; i += kBlock) colacc[i] = 0.0;
+    // the entry constants in vector registers: an FP32 instruction with a
+    // scalar operand does not pair with another in one issue cycle
+    float k2 = c.k2f, e2x2 = c.e2x2f, e2 = c.e2f;
+    asm volatile("" : "+v"(k2), "+v"(e2x2), "+v"(e2));
+    double* red = reinterpret_cast<double*>(lds_b);  // 64 rows x 17 (padded) doubles, between chunks
+    for (int fb = b0; fb < b1; ++fb) {
+        const int64_t fs = sym_blk_start(fb, L), fe = sym_blk_end(fb, L);
+        const bool fint = fb < L.nb_int;
+        const float4 fr = frames[fb];
+        v4u a[kMfmFt];
+        v4f C[kMfmFt];
+        float xi[kMfmFt][4];
+        double acc[kMfmFt][4];
 #pragma unroll
-    for (int f = 0; f < kMfmFt; ++f) {
-        const int64_t base = fb0 + (int64_t)(wv * kMfmFt + f) * 16;
-        const int64_t i = base + jj;
-        float d[3] = {0.f, 0.f, 0.f};
-        if (i < fb1) {
-            const float4 q = XS[i];
-            d[0] = q.x - fr.x;
-            d[1] = q.y - fr.y;
-            d[2] = q.z - fr.z;
-        }
-        if (g < 3) {
-            a[f] = fixed_terms(-2.0f * d[g]);
-        } else {
-            const unsigned one = 0x3F80u;  // bf16 1.0
-            a[f][0] = one | (one << 16);
-            a[f][1] = one;
-            a[f][2] = 0u;
-            a[f][3] = 0u;
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t i2 = base + 4 * g + r;
-            float d2 = 0.f;
-            if (i2 < fb1) {
-                const float4 q = XS[i2];
-                const float ex = q.x - fr.x, ey = q.y - fr.y, ez = q.z - fr.z;
-                d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+        for (int f = 0; f < kMfmFt; ++f) {
+            const int64_t base = fs + (int64_t)(wv * kMfmFt + f) * 16;
+            const int64_t i = base + jj;
+            float d[3] = {0.f, 0.f, 0.f};
+            if (i < fe) {
+                const float4 q = XS[i];
+                d[0] = q.x - fr.x;
+                d[1] = q.y - fr.y;
+                d[2] = q.z - fr.z;
             }
-            C[f][r] = d2;
-            acc[f][r] = 0.0;
+            if (g < 3) {
+                a[f] = fixed_terms(-2.0f * d[g]);
+            } else {
+                const unsigned one = 0x3F80u;  // bf16 1.0
+                a[f][0] = one | (one << 16);
+                a[f][1] = one;
+                a[f][2] = 0u;
+                a[f][3] = 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i2 = base + 4 * g + r;
+                float d2 = 0.f, w = 0.f;
+                if (i2 < fe) {
+                    const float4 q = XS[i2];
+                    const float ex = q.x - fr.x, ey = q.y - fr.y, ez = q.z - fr.z;
+                    d2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+                    w = CF[i2].w;
+                }
+                C[f][r] = d2;
+                xi[f][r] = w;
+                acc[f][r] = 0.0;
+            }
+        }
+        for (int cb = c0 > fb ? c0 : fb; cb < c1;) {
+            const bool diag = cb == fb;
+            const bool cint = cb < L.nb_int;
+            int ce = cb + 1;
+            if (!diag && ce < c1 && (ce < L.nb_int) == cint && sym_blk_end(cb, L) - sym_blk_start(cb, L) == kMfmFixed)
+                ce = cb + 2;
+            const int64_t j0 = sym_blk_start(cb, L), j1 = sym_blk_end(ce - 1, L);
+            // stage the chunk's loop nodes in the fixed block's frame: B
+            // operand (4 lane groups x 8 bf16) and weight; past j1: d = 0, w = 0
+            const int64_t j = j0 + tid;
+            float dx = 0.f, dy = 0.f, dz = 0.f, w = 0.f;
+            if (j < j1) {
+                const float4 q = XS[j];
+                w = CF[j].w;
+                dx = q.x - fr.x;
+                dy = q.y - fr.y;
+                dz = q.z - fr.z;
+            }
+            const v4u bb0 = loop_terms(dx), bb1 = loop_terms(dy), bb2 = loop_terms(dz);
+            unsigned h, m, l;
+            split_bf16x3(fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, 1.0f))), h, m, l);
+            v4u bb3;
+            bb3[0] = pack_bf16(h, m);
+            bb3[1] = l >> 16;
+            bb3[2] = 0u;
+            bb3[3] = 0u;
+            __syncthreads();  // the previous chunk (or the row reduction) is done with LDS
+            lds_b[tid * 4 + 0] = bb0;
+            lds_b[tid * 4 + 1] = bb1;
+            lds_b[tid * 4 + 2] = bb2;
+            lds_b[tid * 4 + 3] = bb3;
+            lds_w[tid] = w;
+            __syncthreads();
+            // row sums: formula of the rows of A the fixed nodes stand for
+            // (A x: the fixed rows; A^T x: the loop rows); column sums: the other
+            const bool ri = TRANS ? cint : fint, ci = TRANS ? fint : cint;
+            float* colw = &lds_col[2 * wv + (g >> 1)][jj];
+            if (diag) {
+                if (fint)
+                    mfs_tiles<true, true, false, 8>(lds_b, lds_w, a, C, xi, k2, e2x2, e2, acc, colw);
+                else
+                    mfs_tiles<false, false, false, 8>(lds_b, lds_w, a, C, xi, k2, e2x2, e2, acc, colw);
+            } else if (ce == cb + 2) {
+                mfs_dispatch<16>(ri, ci, lds_b, lds_w, a, C, xi, k2, e2x2, e2, acc, colw);
+            } else {
+                mfs_dispatch<8>(ri, ci, lds_b, lds_w, a, C, xi, k2, e2x2, e2, acc, colw);
+            }
+            if (!diag) {
+                // the chunk's column sums: the 8 (wave, lane-group pair) partials of each loop node
+                __syncthreads();
+                if (tid < (int)(j1 - j0)) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 2 * (kBlock / kWave); ++q) v += (double)lds_col[q][tid];
+                    colacc[(cb - c0) * kMfmFixed + tid] += v;
+                }
+            }
+            cb = ce;
+        }
+        // the fixed block's row sums: each row's 16 lane partials in a fixed order
+        double* rp = RowP + slot * L.F * kMfmFixed + (int64_t)(fb - b0) * kMfmFixed;
+#pragma unroll
+        for (int f = 0; f < kMfmFt; ++f) {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[(wv * 16 + 4 * g + r) * 17 + jj] = acc[f][r];
+            __syncthreads();
+            if (tid < 64) {
+                const int node = tid;
+                double sum = 0.0;
+                for (int q = 0; q < 16; ++q) sum += red[node * 17 + q];
+                const int row = ((node >> 4) * kMfmFt + f) * 16 + (node & 15);
+                rp[row] = fs + row < fe ? sum : 0.0;
+            }
         }
     }
-    const int64_t j0 = (int64_t)blockIdx.y * slice_len;
-    const int64_t j1 = j0 + slice_len < n ? j0 + slice_len : n;
-    if (ROWS) {
-        if (fint)
-            mfm_span<true>(XS, CF, j0, j1, fr, a, C, acc, lds_b, lds_c);
-        else
-            mfm_span<false>(XS, CF, j0, j1, fr, a, C, acc, lds_b, lds_c);
-    } else {
-        const int64_t m1 = j1 < n_int ? j1 : n_int;
-        if (j0 < m1) mfm_span<true>(XS, CF, j0, m1, fr, a, C, acc, lds_b, lds_c);
-        const int64_t m0 = j0 > n_int ? j0 : n_int;
-        if (m0 < j1) mfm_span<false>(XS, CF, m0, j1, fr, a, C, acc, lds_b, lds_c);
+    __syncthreads();
+    double* cpo = ColP + slot * L.Lb * kMfmFixed;
+    for (int i = tid; i < L.Lb * kMfmFixed; i += kBlock) cpo[i] = colacc[i];
+}
+
+// y_o = (row partials of the items of q's super-row + column partials of
+// the items whose segment holds q's block) - shift z_o, o = perm[q]; the
+// partials are added in item order, four running sums combined at the end.
+__global__ __launch_bounds__(kBlock) void k_mfs_reduce(SymLayout L, const double* __restrict__ RowP,
+                                                       const double* __restrict__ ColP,
+                                                       const int32_t* __restrict__ perm,
+                                                       const double* __restrict__ shift_ptr, double shift_val,
+                                                       const double* __restrict__ z, double* __restrict__ y,
+                                                       const GkbState* __restrict__ st) {
+    if (st != nullptr && st->stopped) return;
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= L.n) return;
+    const int beta = q < L.n_int ? (int)(q / kMfmFixed) : L.nb_int + (int)((q - L.n_int) / kMfmFixed);
+    const int64_t off = q - sym_blk_start(beta, L);
+    const int k = beta / L.F;
+    const int64_t rs = (int64_t)L.F * kMfmFixed, cs = (int64_t)L.Lb * kMfmFixed;
+    const int64_t roff = (int64_t)(beta - k * L.F) * kMfmFixed + off;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int i0 = L.item_first[k], i1 = L.item_first[k + 1];
+    int it = i0;
+    for (; it + 3 < i1; it += 4) {
+        a0 += RowP[(int64_t)it * rs + roff];
+        a1 += RowP[(int64_t)(it + 1) * rs + roff];
+        a2 += RowP[(int64_t)(it + 2) * rs + roff];
+        a3 += RowP[(int64_t)(it + 3) * rs + roff];
     }
-    // sum each fixed node's 16 lane partials (fixed order) through LDS
-    double* red = reinterpret_cast<double*>(lds_b);  // 64 nodes x 17 (padded) doubles
-#pragma unroll
-    for (int f = 0; f < kMfmFt; ++f) {
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) red[(wv * 16 + 4 * g + r) * 17 + jj] = acc[f][r];
-        __syncthreads();
-        if (threadIdx.x < 64) {
-            const int node = threadIdx.x;
-            double s = 0.0;
-            for (int q = 0; q < 16; ++q) s += red[node * 17 + q];
-            const int64_t i = fb0 + (int64_t)((node >> 4) * kMfmFt + f) * 16 + (node & 15);
-            if (i < fb1) P[(int64_t)blockIdx.y * ldp + i] = s;
-        }
+    for (; it < i1; ++it) a0 += RowP[(int64_t)it * rs + roff];
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    auto col = [&](int kk) {
+        const int sg = (beta - kk * L.F) / L.Lb;
+        const int cst = kk * L.F + sg * L.Lb;
+        return ColP[(int64_t)(L.item_first[kk] + sg) * cs + (int64_t)(beta - cst) * kMfmFixed + off];
+    };
+    int kk = 0;
+    for (; kk + 3 <= k; kk += 4) {
+        b0 += col(kk);
+        b1 += col(kk + 1);
+        b2 += col(kk + 2);
+        b3 += col(kk + 3);
     }
+    for (; kk <= k; ++kk) b0 += col(kk);
+    double s = ((a0 + a1) + (a2 + a3)) + ((b0 + b1) + (b2 + b3));
+    const int64_t o = perm[q];
+    if (z != nullptr) {
+        const double sh = shift_ptr != nullptr ? *shift_ptr : shift_val;
+        s -= sh * z[o];
+    }
+    y[o] = s;
 }
 
 // CF[q] = (w kappa^2, 2 w eps^2, w eps^2, w) with w = x[perm[q]]: the
@@ -385,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_coef(const double* __restrict
 // kBlkRhs vectors in FP32, sorted node order.
 //
 // Per 16 x 16 tile the squared distances come from the same bf16x3 MFMA as
-// in k_mfm with the operands swapped (A = loop nodes, B = fixed nodes), so a
+// in the pair products with the operands swapped (A = loop nodes, B = fixed nodes), so a
 // lane holds t for 4 loop nodes j = 4g + r and one fixed node; the lane
 // evaluates the (unweighted) entries and they enter, as they are, the A
 // operand of four v_mfma_f32_16x16x4_f32 against the staged right-hand sides
@@ -688,15 +844,21 @@ void launch_gather_coef(const double* x, const int32_t* perm, int64_t n, const E
     k_gather_coef<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, perm, n, c, CF, st);
 }
 
-void launch_mfm_product(int trans, const float4* XS, const float4* frames, const float4* CF, int64_t n,
-                        int64_t n_int, int S, int64_t slice_len, double* P, int64_t ldp, const GkbState* st,
-                        hipStream_t s) {
-    const int64_t nb_int = (n_int + kMfmFixed - 1) / kMfmFixed;
-    dim3 grid((unsigned)mfm_blocks(n, n_int), (unsigned)S);
+void launch_mfs_product(int trans, const float4* XS, const float4* frames, const float4* CF, const SymLayout& L,
+                        const EntryConst& c, double* RowP, double* ColP, const GkbState* st, hipStream_t s) {
+    if (L.nitems <= 0) return;
     if (trans)
-        k_mfm<false><<<grid, kBlock, 0, s>>>(XS, CF, n, n_int, nb_int, slice_len, frames, P, ldp, st);
+        k_mfs<true><<<(unsigned)L.nitems, kBlock, 0, s>>>(XS, CF, L, frames, c, RowP, ColP, st);
     else
-        k_mfm<true><<<grid, kBlock, 0, s>>>(XS, CF, n, n_int, nb_int, slice_len, frames, P, ldp, st);
+        k_mfs<false><<<(unsigned)L.nitems, kBlock, 0, s>>>(XS, CF, L, frames, c, RowP, ColP, st);
+}
+
+void launch_mfs_reduce(const SymLayout& L, const double* RowP, const double* ColP, const int32_t* perm,
+                       const double* shift_ptr, double shift_val, const double* z, double* y, const GkbState* st,
+                       hipStream_t s) {
+    if (L.n <= 0) return;
+    k_mfs_reduce<<<(unsigned)((L.n + kBlock - 1) / kBlock), kBlock, 0, s>>>(L, RowP, ColP, perm, shift_ptr, shift_val,
+                                                                          z, y, st);
 }
 
 void launch_mfm_block(int trans, const float4* XS, const float4* frames, const float* Vg, int64_t n, int64_t n_int,
