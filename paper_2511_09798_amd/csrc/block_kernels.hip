@@ -195,6 +195,69 @@ __global__ void k_blk_eye(double* __restrict__ Racc, int32_t* __restrict__ statu
     if (e == 0) *status = 0;
 }
 
+// The breakdown test of a block QR on the device (no host round trip per
+// step).  kind 0: E_1 (the data's factor, kept in E1; a diagonal entry at
+// most tau times its largest, or a failed factorisation, marks the sources
+// invalid); kind 1: D_j = R^T of step j; kind 2: E_{j+1} = R.  For kinds 1
+// and 2 the running scale is the largest diagonal entry of the D and E blocks
+// so far; a failed factorisation or a diagonal entry at most tau times the
+// scale stops the run (ell_done = j - 1 at a D block, j at an E block, flag =
+// kind).  Otherwise the block goes into C (row-major, ld ldc) and its
+// transpose (16 x 16, the update kernel's coefficient layout) into mat, the
+// coefficients of the next shift.  Once stopped, nothing is written.
+__global__ __launch_bounds__(kBlkRhs * kBlkRhs) void k_blk_check(const double* __restrict__ Racc,
+                                                                 const int32_t* __restrict__ status, int32_t s,
+                                                                 int32_t kind, int32_t j, double tau,
+                                                                 BlkState* __restrict__ bs, double* __restrict__ C,
+                                                                 int64_t ldc, double* __restrict__ E1,
+                                                                 double* __restrict__ mat) {
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        int ok = bs->stopped ? 0 : 1;
+        if (ok) {
+            double mn = HUGE_VAL, mx = 0.0;
+            for (int i = 0; i < s; ++i) {
+                const double d = fabs(Racc[i * kBlkRhs + i]);
+                mn = d < mn ? d : mn;
+                mx = d > mx ? d : mx;
+            }
+            const bool bad = *status != 0;
+            if (kind == 0) {
+                if (bad || !(mn > tau * mx)) {
+                    bs->invalid = 1;
+                    bs->stopped = 1;
+                    bs->ell_done = 0;
+                    ok = 0;
+                }
+            } else {
+                const double sc = mx > bs->scale ? mx : bs->scale;
+                if (bad || !(mn > tau * sc)) {
+                    bs->stopped = 1;
+                    bs->ell_done = kind == 1 ? j - 1 : j;
+                    bs->flag = kind;
+                    ok = 0;
+                } else {
+                    bs->scale = sc;
+                }
+            }
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const int r = threadIdx.x / kBlkRhs, c = threadIdx.x % kBlkRhs;
+    const double v = Racc[r * kBlkRhs + c];
+    const bool in = r < s && c < s;
+    mat[c * kBlkRhs + r] = in ? v : 0.0;
+    if (!in) return;
+    if (kind == 0)
+        E1[r * s + c] = v;
+    else if (kind == 1)
+        C[(int64_t)((j - 1) * s + c) * ldc + (j - 1) * s + r] = v;  // D_j = R^T
+    else
+        C[(int64_t)(j * s + r) * ldc + (j - 1) * s + c] = v;  // E_{j+1} = R
+}
+
 }  // namespace
 
 int blk_chunks(int64_t n, int32_t m, int64_t* chunk) {
@@ -229,6 +292,11 @@ void launch_blk_update(const double* V, int64_t ldv, int64_t n, int32_t m, const
 void launch_blk_chol(const double* G, int32_t s, int64_t n, int32_t shifted, double* Rinv, double* Racc,
                      int32_t* status, hipStream_t st) {
     k_blk_chol<<<1, kBlock, 0, st>>>(G, s, n, shifted, Rinv, Racc, status);
+}
+
+void launch_blk_check(const double* Racc, const int32_t* status, int32_t s, int32_t kind, int32_t j, double tau,
+                      BlkState* bs, double* C, int64_t ldc, double* E1, double* mat, hipStream_t st) {
+    k_blk_check<<<1, kBlkRhs * kBlkRhs, 0, st>>>(Racc, status, s, kind, j, tau, bs, C, ldc, E1, mat);
 }
 
 void launch_blk_eye(double* Racc, int32_t* status, hipStream_t st) {

@@ -184,6 +184,7 @@ struct MultiWs {
     double* PB = nullptr;
     int S_rows = 1, S_cols = 1;
     int64_t slice_rows = 0, slice_cols = 0;
+    int ft_rows = 2, ft_cols = 2;  // fixed tiles of 16 nodes per wave (blocks of 64 ft fixed nodes)
     // the Golub-Kahan loop of one group as a captured graph, and its key
     hipGraphExec_t graph = nullptr;
     int g_nz = 0;
@@ -682,8 +683,8 @@ void multi_free(MultiWs& w) {
 
 // Slice count S and length (whole LDS chunks) of a block product aiming at
 // target_blocks workgroups.
-void block_slices(const mqh_problem* p, int64_t target_blocks, int& S, int64_t& len) {
-    const int64_t n = p->n, nb = mfm_blocks(n, p->n_int);
+void block_slices(const mqh_problem* p, int ft, int64_t target_blocks, int& S, int64_t& len) {
+    const int64_t n = p->n, nb = mfm_block_blocks(n, p->n_int, ft);
     int64_t s = (target_blocks + nb - 1) / nb;
     if (s < 1) s = 1;
     if (s > kMaxSlices) s = kMaxSlices;
@@ -696,39 +697,45 @@ void block_slices(const mqh_problem* p, int64_t target_blocks, int& S, int64_t& 
 
 // Heuristic shapes: a few rounds of resident workgroups over the chip.
 void block_shapes(mqh_problem* p, MultiWs& w) {
-    block_slices(p, 4096, w.S_rows, w.slice_rows);
+    w.ft_rows = w.ft_cols = 2;
+    block_slices(p, 2, 4096, w.S_rows, w.slice_rows);
     w.S_cols = w.S_rows;
     w.slice_cols = w.slice_rows;
 }
 
-// Autotuner of the block products: the candidates aim at 1024 .. 16384
-// workgroups (about one to sixteen rounds of resident workgroups).  Each is
-// timed as the whole product (the slice kernel and the reduction of its
-// nz-column partials) on a pseudo-random operand, once untimed and then five
-// times between event pairs on the problem's stream; the best of the five
+// Autotuner of the block products: the tile shape (64 or 128 fixed nodes
+// per workgroup, one or two 16-node tiles per wave) and the split of the
+// loop range (candidates aiming at 1024 .. 16384 workgroups, about one to
+// sixteen rounds of resident workgroups).  Each candidate is timed as the
+// whole product (the slice kernel and the reduction of its nz-column
+// partials) on a pseudo-random operand, once untimed and then five times
+// between event pairs on the problem's stream; the best of the five
 // decides, per direction.  w.PB must hold kMaxSlices slices.
 int tune_block_shapes(mqh_problem* p, MultiWs& w, int nz) {
     hipStream_t s = p->stream;
     launch_fill_hash(w.Vg, p->n * kBlkRhs, s);
     LAUNCHCHK("tuning operand");
-    std::vector<std::pair<int, int64_t>> cand;
-    for (int64_t target = 1024; target <= 16384; target *= 2) {
-        int S;
+    struct Cand {
+        int ft, S;
         int64_t len;
-        block_slices(p, target, S, len);
-        bool seen = false;
-        for (auto& c : cand) seen = seen || c.first == S;
-        if (!seen) cand.emplace_back(S, len);
-    }
+    };
+    std::vector<Cand> cand;
+    for (int ft = 1; ft <= 2; ++ft)
+        for (int64_t target = 1024; target <= 16384; target *= 2) {
+            int S;
+            int64_t len;
+            block_slices(p, ft, target, S, len);
+            bool seen = false;
+            for (auto& c : cand) seen = seen || (c.ft == ft && c.S == S);
+            if (!seen) cand.push_back(Cand{ft, S, len});
+        }
     constexpr int kReps = 5;
     hipEvent_t ev[kReps + 1] = {};
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     int rc = MQH_OK;
-    auto product = [&](int trans, const std::pair<int, int64_t>& c) {
-        launch_mfm_block(trans, p->XS, p->frames, w.Vg, p->n, p->n_int, c.first, c.second, op_ec(p), w.PB, p->ldn,
-                         s);
-        launch_reduce_block(w.PB, p->ldn, c.first, p->n, nz, p->perm, nullptr, 0, nullptr, 0, w.Y, p->ldn, nullptr,
-                            s);
+    auto product = [&](int trans, const Cand& c) {
+        launch_mfm_block(trans, c.ft, p->XS, p->frames, w.Vg, p->n, p->n_int, c.S, c.len, op_ec(p), w.PB, p->ldn, s);
+        launch_reduce_block(w.PB, p->ldn, c.S, p->n, nz, p->perm, nullptr, 0, nullptr, 0, w.Y, p->ldn, nullptr, s);
     };
     for (int trans = 0; trans < 2 && rc == MQH_OK; ++trans) {
         float best = 0.f;
@@ -753,8 +760,9 @@ int tune_block_shapes(mqh_problem* p, MultiWs& w, int nz) {
             }
             if (best == 0.f || t < best) {
                 best = t;
-                (trans ? w.S_cols : w.S_rows) = c.first;
-                (trans ? w.slice_cols : w.slice_rows) = c.second;
+                (trans ? w.ft_cols : w.ft_rows) = c.ft;
+                (trans ? w.S_cols : w.S_rows) = c.S;
+                (trans ? w.slice_cols : w.slice_rows) = c.len;
             }
         }
     }
@@ -860,7 +868,8 @@ int block_product(mqh_problem* p, int nz, int trans, const double* X, int64_t xs
         HIPCHK(hipEventRecord(e0, s));
     }
     const int S = trans ? w.S_cols : w.S_rows;
-    launch_mfm_block(trans, p->XS, p->frames, w.Vg, p->n, p->n_int, S, trans ? w.slice_cols : w.slice_rows,
+    launch_mfm_block(trans, trans ? w.ft_cols : w.ft_rows, p->XS, p->frames, w.Vg, p->n, p->n_int, S,
+                     trans ? w.slice_cols : w.slice_rows,
                      op_ec(p), w.PB, p->ldn, s);
     LAUNCHCHK("block product");
     if (timed) HIPCHK(hipEventRecord(e1, s));
@@ -1380,10 +1389,15 @@ struct BlockWs {
     double* G = nullptr;     // 16 x 16 Gram matrix
     double* Rinv = nullptr;  // 16 x 16
     double* Racc = nullptr;  // 16 x 16 accumulated R
-    double* mat = nullptr;   // two 16 x 16 shift blocks (c layout)
+    double* mat = nullptr;   // two 16 x 16 shift blocks (c layout), written by the QR checks
     int32_t* status = nullptr;
-    std::vector<double> host = std::vector<double>(2 * kBlkRhs * kBlkRhs);  // their host copies
+    double* Cd = nullptr;    // C ((ell + 1) s x ell s, row-major) on the device
+    double* E1d = nullptr;   // E_1 (s x s)
+    BlkState* bs = nullptr;  // breakdown state of the run
     ~BlockWs() {
+        dfree(Cd);
+        dfree(E1d);
+        dfree(bs);
         dfree(W);
         dfree(Z);
         dfree(P);
@@ -1411,7 +1425,9 @@ int block_alloc(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell) {
         (rc = dalloc(&b.P, (size_t)(kBlkRhs * ldn))) || (rc = dalloc(&b.part, (size_t)(most * kBlkRhs))) ||
         (rc = dalloc(&b.c, (size_t)mmax * kBlkRhs)) || (rc = dalloc(&b.G, kBlkRhs * kBlkRhs)) ||
         (rc = dalloc(&b.Rinv, kBlkRhs * kBlkRhs)) || (rc = dalloc(&b.Racc, kBlkRhs * kBlkRhs)) ||
-        (rc = dalloc(&b.mat, 2 * kBlkRhs * kBlkRhs)) || (rc = dalloc(&b.status, 1)))
+        (rc = dalloc(&b.mat, 2 * kBlkRhs * kBlkRhs)) || (rc = dalloc(&b.status, 1)) ||
+        (rc = dalloc(&b.Cd, (size_t)mmax * (size_t)ell * s)) || (rc = dalloc(&b.E1d, kBlkRhs * kBlkRhs)) ||
+        (rc = dalloc(&b.bs, 1)))
         return rc;
     hipStream_t st = p->stream;
     HIPCHK(hipMemsetAsync(b.W, 0, (size_t)mmax * ldn * sizeof(double), st));
@@ -1494,7 +1510,11 @@ int block_ws(mqh_problem* p, int32_t s, int32_t ell, BlockWs** out) {
 // Q R = X in place (X: n x s, leading dimension ldn) by shifted Cholesky QR
 // three times; R (s x s, row-major, upper triangular) to the host.  *bad is
 // set when a Cholesky factorisation fails (X numerically zero or not finite).
-int block_qr(mqh_problem* p, BlockWs& b, double* X, int32_t s, double* Rh, bool* bad) {
+// Cholesky QR of the s columns of X in place (three passes, the first
+// shifted), then the breakdown test and the bookkeeping of the factor on
+// the device (k_blk_check: kind 0 for E_1, 1 for D_j, 2 for E_{j+1}); the
+// factor's transpose goes to shift slot `slot` of b.mat.
+void block_qr(mqh_problem* p, BlockWs& b, double* X, int32_t s, int32_t kind, int32_t j, int32_t ell, int slot) {
     hipStream_t st = p->stream;
     const int64_t n = p->n, ldn = p->ldn;
     launch_blk_eye(b.Racc, b.status, st);
@@ -1503,34 +1523,14 @@ int block_qr(mqh_problem* p, BlockWs& b, double* X, int32_t s, double* Rh, bool*
         launch_blk_chol(b.G, s, n, pass == 0 ? 1 : 0, b.Rinv, b.Racc, b.status, st);
         launch_blk_update(X, ldn, n, s, b.Rinv, kBlkRhs, 1, X, ldn, s, 0, st);
     }
-    LAUNCHCHK("block QR");
-    double R[kBlkRhs * kBlkRhs];
-    int32_t status = 0;
-    HIPCHK(hipMemcpyAsync(R, b.Racc, sizeof(R), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&status, b.status, sizeof(status), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    *bad = status != 0;
-    for (int i = 0; i < s; ++i)
-        for (int j = 0; j < s; ++j) Rh[i * s + j] = R[i * kBlkRhs + j];
-    return MQH_OK;
+    launch_blk_check(b.Racc, b.status, s, kind, j, (double)n * DBL_EPSILON, b.bs, b.Cd, (int64_t)ell * s, b.E1d,
+                     b.mat + slot * kBlkRhs * kBlkRhs, st);
 }
 
-// X -= V M (V: n x s block of a basis, M: s x s given row-major on the host;
-// trans: use M^T).  The coefficients go through host slot `slot` of b.host
-// (kept until the process's next synchronisation, which every block step
-// has after its QR) and device slot `slot` of b.mat.
-int block_shift(mqh_problem* p, BlockWs& b, const double* V, const double* M, int32_t s, bool trans, double* X,
-                int slot) {
-    double* c = b.host.data() + slot * kBlkRhs * kBlkRhs;
-    for (int i = 0; i < kBlkRhs * kBlkRhs; ++i) c[i] = 0.0;
-    for (int col = 0; col < s; ++col)
-        for (int k = 0; k < s; ++k) c[col * kBlkRhs + k] = trans ? M[k * s + col] : M[col * s + k];
-    hipStream_t st = p->stream;
-    double* dm = b.mat + slot * kBlkRhs * kBlkRhs;
-    HIPCHK(hipMemcpyAsync(dm, c, kBlkRhs * kBlkRhs * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_blk_update(V, p->ldn, p->n, s, dm, kBlkRhs, 1, X, p->ldn, s, 1, st);
-    LAUNCHCHK("block shift");
-    return MQH_OK;
+// X -= V M with M the device coefficients in shift slot `slot` of b.mat (the
+// transpose of the QR factor k_blk_check left there).
+void block_shift_dev(mqh_problem* p, BlockWs& b, const double* V, int32_t s, double* X, int slot) {
+    launch_blk_update(V, p->ldn, p->n, s, b.mat + slot * kBlkRhs * kBlkRhs, kBlkRhs, 1, X, p->ldn, s, 1, p->stream);
 }
 
 // X -= V (V^T X) twice, V the first m columns of a basis.
@@ -1551,79 +1551,61 @@ void block_cgs2(mqh_problem* p, BlockWs& b, const double* V, int32_t m, int32_t 
 // with a diagonal entry of R at most n eps times the largest diagonal entry
 // of the D and E blocks so far (E_1 left out) is a breakdown: at a D block
 // *ell_done = j - 1 (flag 1), at an E block *ell_done = j with E_{j+1} = 0
-// (flag 2).
+// (flag 2).  The tests run on the device and the whole run is enqueued
+// without a synchronisation; steps after a breakdown still run but write
+// nothing into C, and the basis columns past the kept steps are cleared at
+// the end.
 int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vector<double>& C, double* E1,
                   int32_t* ell_done, int32_t* flag) {
     hipStream_t st = p->stream;
-    const int64_t n = p->n, ldn = p->ldn;
+    const int64_t ldn = p->ldn;
     const int64_t ldc = (int64_t)ell * s;
-    C.assign((size_t)((ell + 1) * s) * (size_t)ldc, 0.0);
-    bool bad = false;
-    int rc;
-    const double tau = (double)n * DBL_EPSILON;
-    auto diag_range = [&](const double* M, double* mn, double* mx) {
-        *mn = HUGE_VAL;
-        *mx = 0.0;
-        for (int i = 0; i < s; ++i) {
-            const double d = fabs(M[(size_t)i * s + i]);
-            *mn = d < *mn ? d : *mn;
-            *mx = d > *mx ? d : *mx;
-        }
-    };
-    if ((rc = block_qr(p, b, b.W, s, E1, &bad))) return rc;
-    double mn, mx;
-    diag_range(E1, &mn, &mx);
-    // a zero source fails the Cholesky step; sources dependent to working precision leave E_1 a
-    // diagonal entry at the rounding level (or, by rounding, fail it too): either way W_1 would
-    // carry a direction of rounding noise, so both are rejected
-    if (bad || !(mn > tau * mx))
-        return fail(MQH_EINVAL, "block Golub-Kahan: the right-hand sides are zero or linearly dependent");
-    double scale = 0.0;
-    std::vector<double> R((size_t)s * s), Eprev((size_t)s * s, 0.0);
-    *ell_done = ell;
-    *flag = 0;
+    const size_t csize = (size_t)((ell + 1) * s) * (size_t)ldc;
+    C.assign(csize, 0.0);
+    HIPCHK(hipMemsetAsync(b.Cd, 0, csize * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(b.bs, 0, sizeof(BlkState), st));
+    block_qr(p, b, b.W, s, 0, 0, ell, 0);
     for (int32_t j = 1; j <= ell; ++j) {
         double* Wj = b.W + (int64_t)(j - 1) * s * ldn;
         double* Zj = b.Z + (int64_t)(j - 1) * s * ldn;
         // P = A^T W_j - Z_{j-1} E_j^T, reorthogonalised against Z_1 .. Z_{j-1}
+        int rc;
         if ((rc = block_product(p, s, 1, Wj, ldn, nullptr, 0, nullptr, 0, b.P, nullptr, false))) return rc;
-        if (j > 1 && (rc = block_shift(p, b, Zj - (int64_t)s * ldn, Eprev.data(), s, true, b.P, 0))) return rc;
+        if (j > 1) block_shift_dev(p, b, Zj - (int64_t)s * ldn, s, b.P, 0);
         block_cgs2(p, b, b.Z, (j - 1) * s, s, b.P);
-        if ((rc = block_qr(p, b, b.P, s, R.data(), &bad))) return rc;
-        diag_range(R.data(), &mn, &mx);
-        scale = mx > scale ? mx : scale;
-        if (bad || !(mn > tau * scale)) {
-            *ell_done = j - 1;
-            *flag = 1;
-            break;
-        }
+        block_qr(p, b, b.P, s, 1, j, ell, 1);  // D_j = R^T into C; the shift below reads slot 1
         HIPCHK(hipMemcpyAsync(Zj, b.P, (size_t)s * ldn * sizeof(double), hipMemcpyDeviceToDevice, st));
-        // D_j = R^T on the diagonal block
-        for (int i = 0; i < s; ++i)
-            for (int k = 0; k < s; ++k) C[(size_t)((j - 1) * s + i) * ldc + (size_t)(j - 1) * s + k] = R[(size_t)k * s + i];
-        std::vector<double> D((size_t)s * s);
-        for (int i = 0; i < s; ++i)
-            for (int k = 0; k < s; ++k) D[(size_t)i * s + k] = R[(size_t)k * s + i];
         // Q = A Z_j - W_j D_j, reorthogonalised against W_1 .. W_j
         if ((rc = block_product(p, s, 0, Zj, ldn, nullptr, 0, nullptr, 0, b.P, nullptr, false))) return rc;
-        if ((rc = block_shift(p, b, Wj, D.data(), s, false, b.P, 1))) return rc;
+        block_shift_dev(p, b, Wj, s, b.P, 1);
         block_cgs2(p, b, b.W, j * s, s, b.P);
-        if ((rc = block_qr(p, b, b.P, s, R.data(), &bad))) return rc;
-        diag_range(R.data(), &mn, &mx);
-        scale = mx > scale ? mx : scale;
-        if (bad || !(mn > tau * scale)) {
-            *ell_done = j;
-            *flag = 2;
-            break;
-        }
+        block_qr(p, b, b.P, s, 2, j, ell, 0);  // E_{j+1} = R, the next step's shift
         HIPCHK(hipMemcpyAsync(Wj + (int64_t)s * ldn, b.P, (size_t)s * ldn * sizeof(double), hipMemcpyDeviceToDevice,
                               st));
-        for (int i = 0; i < s; ++i)
-            for (int k = 0; k < s; ++k) C[(size_t)(j * s + i) * ldc + (size_t)(j - 1) * s + k] = R[(size_t)i * s + k];
-        Eprev = R;
     }
     LAUNCHCHK("block Golub-Kahan");
+    BlkState h{};
+    HIPCHK(hipMemcpyAsync(&h, b.bs, sizeof(BlkState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(C.data(), b.Cd, csize * sizeof(double), hipMemcpyDeviceToHost, st));
+    double E1h[kBlkRhs * kBlkRhs];
+    HIPCHK(hipMemcpyAsync(E1h, b.E1d, (size_t)s * s * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    // a zero source fails the Cholesky step; sources dependent to working precision leave E_1 a
+    // diagonal entry at the rounding level (or, by rounding, fail it too): either way W_1 would
+    // carry a direction of rounding noise, so both are rejected
+    if (h.invalid)
+        return fail(MQH_EINVAL, "block Golub-Kahan: the right-hand sides are zero or linearly dependent");
+    for (int i = 0; i < s * s; ++i) E1[i] = E1h[i];
+    *ell_done = h.stopped ? h.ell_done : ell;
+    *flag = h.stopped ? h.flag : 0;
+    if (h.stopped) {
+        // the kept basis: W_1 .. W_{ell_done + 1} after a D breakdown, W_1 .. W_{ell_done} after an E
+        // breakdown (E_{ell_done + 1} = 0), Z_1 .. Z_{ell_done}; the rest is cleared
+        const int64_t wk = (int64_t)(*ell_done + (*flag == 1 ? 1 : 0)) * s;
+        const int64_t zk = (int64_t)(*ell_done) * s;
+        HIPCHK(hipMemsetAsync(b.W + wk * ldn, 0, (size_t)(((int64_t)(ell + 1) * s - wk) * ldn) * sizeof(double), st));
+        HIPCHK(hipMemsetAsync(b.Z + zk * ldn, 0, (size_t)(((int64_t)ell * s - zk) * ldn) * sizeof(double), st));
+    }
     return MQH_OK;
 }
 

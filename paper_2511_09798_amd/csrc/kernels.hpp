@@ -86,8 +86,12 @@ void launch_mfs_product(int trans, const float4* XS, const float4* frames, const
 void launch_mfs_reduce(const SymLayout& L, const double* RowP, const double* ColP, const int32_t* perm,
                        const double* shift_ptr, double shift_val, const double* z, double* y, const GkbState* st,
                        hipStream_t s);
-void launch_mfm_block(int trans, const float4* XS, const float4* frames, const float* Vg, int64_t n, int64_t n_int,
-                      int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp, hipStream_t s);
+// Block products over blocks of 64 ft fixed nodes (ft = 1 or 2: fixed tiles of
+// 16 per wave); mfm_block_blocks gives the grid's block count.
+int64_t mfm_block_blocks(int64_t n, int64_t n_int, int ft);
+void launch_mfm_block(int trans, int ft, const float4* XS, const float4* frames, const float* Vg, int64_t n,
+                      int64_t n_int, int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp,
+                      hipStream_t s);
 void launch_fill_hash(float* Vg, int64_t count, hipStream_t s);
 void launch_gather_block(const double* X, int64_t ldx, int nrhs, const int32_t* perm, int64_t n,
                          const GkbState* st, float* Vg, hipStream_t s);
@@ -288,6 +292,14 @@ void launch_blk_update(const double* V, int64_t ldv, int64_t n, int32_t m, const
 void launch_blk_chol(const double* G, int32_t s, int64_t n, int32_t shifted, double* Rinv, double* Racc,
                      int32_t* status, hipStream_t st);
 void launch_blk_eye(double* Racc, int32_t* status, hipStream_t st);
+// Device state of a block Golub-Kahan run: the breakdown test of every QR
+// without a host round trip.
+struct BlkState {
+    int32_t stopped, ell_done, flag, invalid;
+    double scale;
+};
+void launch_blk_check(const double* Racc, const int32_t* status, int32_t s, int32_t kind, int32_t j, double tau,
+                      BlkState* bs, double* C, int64_t ldc, double* E1, double* mat, hipStream_t st);
 
 // Measurement helpers (peak_kernels.hip): peak_blocks() workgroups of kBlock
 // threads; the copy moves count doubles (count even, x and y 16-byte aligned).

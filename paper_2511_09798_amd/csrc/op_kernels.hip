@@ -555,10 +555,10 @@ constexpr int kBlkVs = kBlkRhs + 4;  // LDS row of the staged right-hand sides (
 
 // Entries of the lane's 4 loop nodes x kMfmFt fixed nodes from their
 // squared distances t (unweighted; INTERIOR selects the formula).
-template <bool INTERIOR>
-__device__ __forceinline__ void block_entries(const v4f (&t)[kMfmFt], const EntryConst& c, float (&e)[kMfmFt][4]) {
+template <bool INTERIOR, int FT>
+__device__ __forceinline__ void block_entries(const v4f (&t)[FT], const EntryConst& c, float (&e)[FT][4]) {
 #pragma unroll
-    for (int f = 0; f < kMfmFt; ++f)
+    for (int f = 0; f < FT; ++f)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             if (INTERIOR) {
@@ -571,11 +571,12 @@ __device__ __forceinline__ void block_entries(const v4f (&t)[kMfmFt], const Entr
 }
 
 // Squared distances of tile u (16 staged loop nodes) to the lane's fixed nodes.
-__device__ __forceinline__ void block_tdist(const v4u* __restrict__ lds_a, int u, int jj, int g,
-                                            const v4u (&bf)[kMfmFt], const v4f (&Cf)[kMfmFt], v4f (&t)[kMfmFt]) {
+template <int FT>
+__device__ __forceinline__ void block_tdist(const v4u* __restrict__ lds_a, int u, int jj, int g, const v4u (&bf)[FT],
+                                            const v4f (&Cf)[FT], v4f (&t)[FT]) {
     const v8bf ak = __builtin_bit_cast(v8bf, lds_a[(u * 16 + jj) * 4 + g]);
 #pragma unroll
-    for (int f = 0; f < kMfmFt; ++f)
+    for (int f = 0; f < FT; ++f)
         t[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ak, __builtin_bit_cast(v8bf, bf[f]), Cf[f], 0, 0, 0);
 }
 
@@ -584,11 +585,10 @@ __device__ __forceinline__ void block_tdist(const v4u* __restrict__ lds_a, int u
 // squared distances of tile u + 2, the entries of tile u + 1 and the
 // contraction of tile u are in flight together, so no stage waits on the
 // one before it.
-template <bool INTERIOR>
+template <bool INTERIOR, int FT>
 __device__ __forceinline__ void mfb_span(const float4* __restrict__ XS, const float* __restrict__ Vg, int64_t j0,
-                                         int64_t j1, const float4& fr, const EntryConst& c,
-                                         const v4u (&bf)[kMfmFt], const v4f (&Cf)[kMfmFt],
-                                         double (&acc)[kMfmFt][4], v4u* __restrict__ lds_a,
+                                         int64_t j1, const float4& fr, const EntryConst& c, const v4u (&bf)[FT],
+                                         const v4f (&Cf)[FT], double (&acc)[FT][4], v4u* __restrict__ lds_a,
                                          float* __restrict__ lds_v) {
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15;
     constexpr int kTiles = kMfmChunk / 16;
@@ -626,32 +626,32 @@ __device__ __forceinline__ void mfb_span(const float4* __restrict__ XS, const fl
         vrow[2] = v2;
         vrow[3] = v3;
         __syncthreads();
-        v4f d2[kMfmFt];
+        v4f d2[FT];
 #pragma unroll
-        for (int f = 0; f < kMfmFt; ++f) d2[f] = v4f{0.f, 0.f, 0.f, 0.f};
-        v4f tc[kMfmFt], tn[kMfmFt];
-        float ec[kMfmFt][4];
-        block_tdist(lds_a, 0, jj, g, bf, Cf, tc);
-        block_tdist(lds_a, 1, jj, g, bf, Cf, tn);
-        block_entries<INTERIOR>(tc, c, ec);
+        for (int f = 0; f < FT; ++f) d2[f] = v4f{0.f, 0.f, 0.f, 0.f};
+        v4f tc[FT], tn[FT];
+        float ec[FT][4];
+        block_tdist<FT>(lds_a, 0, jj, g, bf, Cf, tc);
+        block_tdist<FT>(lds_a, 1, jj, g, bf, Cf, tn);
+        block_entries<INTERIOR, FT>(tc, c, ec);
 #pragma unroll
         for (int u = 0; u < kTiles; ++u) {
             float vb[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) vb[r] = lds_v[(u * 16 + 4 * g + r) * kBlkVs + jj];
-            v4f tnn[kMfmFt];
-            if (u + 2 < kTiles) block_tdist(lds_a, u + 2, jj, g, bf, Cf, tnn);
-            float en[kMfmFt][4];
-            if (u + 1 < kTiles) block_entries<INTERIOR>(tn, c, en);
+            v4f tnn[FT];
+            if (u + 2 < kTiles) block_tdist<FT>(lds_a, u + 2, jj, g, bf, Cf, tnn);
+            float en[FT][4];
+            if (u + 1 < kTiles) block_entries<INTERIOR, FT>(tn, c, en);
             // the entries enter the A operand as they are: K = loop nodes r, 4 + r, 8 + r, 12 + r
 #pragma unroll
-            for (int f = 0; f < kMfmFt; ++f)
+            for (int f = 0; f < FT; ++f)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     d2[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(ec[f][r], vb[r], d2[f], 0, 0, 0);
             if (u + 1 < kTiles) {
 #pragma unroll
-                for (int f = 0; f < kMfmFt; ++f) {
+                for (int f = 0; f < FT; ++f) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) ec[f][r] = en[f][r];
                     tn[f] = tnn[f];
@@ -659,32 +659,36 @@ __device__ __forceinline__ void mfb_span(const float4* __restrict__ XS, const fl
             }
         }
 #pragma unroll
-        for (int f = 0; f < kMfmFt; ++f)
+        for (int f = 0; f < FT; ++f)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[f][r] += (double)d2[f][r];
     }
 }
 
-template <bool ROWS>
+template <bool ROWS, int FT>
 __global__ __launch_bounds__(kBlock) void k_mfm_block(const float4* __restrict__ XS, const float* __restrict__ Vg,
                                                       int64_t n, int64_t n_int, int64_t nb_int, int64_t slice_len,
                                                       const float4* __restrict__ frames, EntryConst c,
                                                       double* __restrict__ P, int64_t ldp) {
     __shared__ v4u lds_a[4 * kMfmChunk];
     __shared__ float lds_v[kMfmChunk * kBlkVs];
+    // blocks of kFix = 64 FT fixed nodes per class; the frame is that of the
+    // kMfmFixed-node block holding the first of them
+    constexpr int kFix = (kBlock / kWave) * FT * 16;
     const int64_t b = blockIdx.x;
     const bool fint = b < nb_int;
-    const int64_t fb0 = fint ? b * kMfmFixed : n_int + (b - nb_int) * kMfmFixed;
+    const int64_t fb0 = fint ? b * kFix : n_int + (b - nb_int) * kFix;
     const int64_t fend = fint ? n_int : n;
-    const int64_t fb1 = fb0 + kMfmFixed < fend ? fb0 + kMfmFixed : fend;
-    const float4 fr = frames[b];
+    const int64_t fb1 = fb0 + kFix < fend ? fb0 + kFix : fend;
+    const int64_t nbf_int = (n_int + kMfmFixed - 1) / kMfmFixed;
+    const float4 fr = frames[fint ? (b * kFix) / kMfmFixed : nbf_int + ((b - nb_int) * kFix) / kMfmFixed];
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15, wv = threadIdx.x / kWave;
-    v4u bf[kMfmFt];
-    v4f Cf[kMfmFt];
-    double acc[kMfmFt][4];
+    v4u bf[FT];
+    v4f Cf[FT];
+    double acc[FT][4];
 #pragma unroll
-    for (int f = 0; f < kMfmFt; ++f) {
-        const int64_t i = fb0 + (int64_t)(wv * kMfmFt + f) * 16 + jj;
+    for (int f = 0; f < FT; ++f) {
+        const int64_t i = fb0 + (int64_t)(wv * FT + f) * 16 + jj;
         float d[3] = {0.f, 0.f, 0.f};
         if (i < fb1) {
             const float4 q = XS[i];
@@ -710,20 +714,20 @@ __global__ __launch_bounds__(kBlock) void k_mfm_block(const float4* __restrict__
     const int64_t j1 = j0 + slice_len < n ? j0 + slice_len : n;
     if (ROWS) {
         if (fint)
-            mfb_span<true>(XS, Vg, j0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
+            mfb_span<true, FT>(XS, Vg, j0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
         else
-            mfb_span<false>(XS, Vg, j0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
+            mfb_span<false, FT>(XS, Vg, j0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
     } else {
         const int64_t m1 = j1 < n_int ? j1 : n_int;
-        if (j0 < m1) mfb_span<true>(XS, Vg, j0, m1, fr, c, bf, Cf, acc, lds_a, lds_v);
+        if (j0 < m1) mfb_span<true, FT>(XS, Vg, j0, m1, fr, c, bf, Cf, acc, lds_a, lds_v);
         const int64_t m0 = j0 > n_int ? j0 : n_int;
-        if (m0 < j1) mfb_span<false>(XS, Vg, m0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
+        if (m0 < j1) mfb_span<false, FT>(XS, Vg, m0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
     }
 #pragma unroll
-    for (int f = 0; f < kMfmFt; ++f) {
+    for (int f = 0; f < FT; ++f) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int64_t i = fb0 + (int64_t)(wv * kMfmFt + f) * 16 + 4 * g + r;
+            const int64_t i = fb0 + (int64_t)(wv * FT + f) * 16 + 4 * g + r;
             if (i < fb1) P[((int64_t)blockIdx.y * kBlkRhs + jj) * ldp + i] = acc[f][r];
         }
     }
@@ -861,14 +865,28 @@ void launch_mfs_reduce(const SymLayout& L, const double* RowP, const double* Col
                                                                           z, y, st);
 }
 
-void launch_mfm_block(int trans, const float4* XS, const float4* frames, const float* Vg, int64_t n, int64_t n_int,
-                      int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp, hipStream_t s) {
-    const int64_t nb_int = (n_int + kMfmFixed - 1) / kMfmFixed;
-    dim3 grid((unsigned)mfm_blocks(n, n_int), (unsigned)S);
-    if (trans)
-        k_mfm_block<false><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
-    else
-        k_mfm_block<true><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+int64_t mfm_block_blocks(int64_t n, int64_t n_int, int ft) {
+    const int64_t fix = (kBlock / kWave) * ft * 16;
+    return (n_int + fix - 1) / fix + (n - n_int + fix - 1) / fix;
+}
+
+void launch_mfm_block(int trans, int ft, const float4* XS, const float4* frames, const float* Vg, int64_t n,
+                      int64_t n_int, int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp,
+                      hipStream_t s) {
+    const int64_t fix = (kBlock / kWave) * ft * 16;
+    const int64_t nb_int = (n_int + fix - 1) / fix;
+    dim3 grid((unsigned)mfm_block_blocks(n, n_int, ft), (unsigned)S);
+    if (ft == 1) {
+        if (trans)
+            k_mfm_block<false, 1><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+        else
+            k_mfm_block<true, 1><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+    } else {
+        if (trans)
+            k_mfm_block<false, 2><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+        else
+            k_mfm_block<true, 2><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+    }
 }
 
 void launch_fill_hash(float* Vg, int64_t count, hipStream_t s) {
