@@ -539,6 +539,13 @@ def block_context(mq, torch, dev, members=(0, 1), steps=(7, 25), ell_lockstep: i
                 row[f"block{lb}_phases_ms"] = dict(recurrence=float(bk.t_ms[0][1]), projected=float(bk.t_ms[0][2]))
                 row[f"block{lb}_u_vs_lockstep_median"] = float(np.median(d))
                 row[f"block{lb}_resid_over_lockstep_median"] = float(np.median(bk.resid_norm / lk.resid_norm))
+                row[f"block{lb}_projected_path"] = ("jacobi" if np.any(bk.flags & mq.MQH_INFO_BLOCK_JACOBI)
+                                                    else "band")
+                # the same solve with the projected problem on the Jacobi full SVD, for comparison
+                bj, tj = timed(lambda: pr.solve_block(F, lb, jacobi=True))
+                row[f"block{lb}_jacobi_s"] = tj
+                row[f"block{lb}_jacobi_projected_ms"] = float(bj.t_ms[0][2])
+                row[f"block{lb}_lambda_max_rel_vs_jacobi"] = float(np.max(np.abs(bk.lam / bj.lam - 1.0)))
         res["problems"].append(row)
         log("block", json.dumps(row))
     k = int(np.argmin(I.sweep_sizes()))

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MQH_VERSION 10500 /* 1.5.0 */
+#define MQH_VERSION 10600 /* 1.6.0 */
 
 /* ---- status codes ---- */
 #define MQH_OK 0
@@ -90,16 +90,22 @@ extern "C" {
                                        the operator is D A with D = diag(A)^-1 (see mqh_solve_opts.row_scale);
                                        mqh_gkb / mqh_gkb_multi also scale f to D f */
 
-/* ---- info flags ---- */
 #define MQH_FLAG_PROJ_QR 32u         /* mqh_proj_svd: the implicit QR iteration only (the fast path's fallback) */
 #define MQH_FLAG_PROJ_NO_FALLBACK 64u /* mqh_proj_svd: the fast path only; MQH_EDEVICE if it fails its acceptance
                                         test (for tests of the fast path) */
+#define MQH_FLAG_BLOCK_JACOBI 128u    /* mqh_solve_block: the projected problem through the one-sided Jacobi full
+                                        SVD only (the band path's fallback) */
+
+/* ---- info flags ---- */
 #define MQH_INFO_BREAKDOWN 1u
 #define MQH_INFO_GCV_AT_EDGE 2u
 #define MQH_INFO_LCURVE_AT_EDGE 4u
 #define MQH_INFO_SOLVE_NOCONV 8u  /* full solve: the conjugate gradients stopped at their cap above their tolerance */
 #define MQH_INFO_SVD_QR 16u       /* the projected SVD failed the fast path's acceptance test and was computed by
                                      the implicit QR iteration (same outputs to rounding, about 100 times slower) */
+#define MQH_INFO_BLOCK_JACOBI 32u /* mqh_solve_block: the projected problem went through the Jacobi full SVD
+                                     (too large for the band reduction, its SVD failed the acceptance test, or
+                                     MQH_FLAG_BLOCK_JACOBI) */
 
 /* Largest number of Golub-Kahan steps a solve accepts (projected problem size). */
 #define MQH_MAX_ELL 1024
@@ -503,7 +509,14 @@ int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* 
  *   retained components leave of ||E_1 e_k||^2, on the grid of
  *   mqh_param_choice; for nrhs = 1 this is the projected GCV of eq. (30))
  *   or MQH_RULE_FIXED (lambda_fixed for every source).  The projected
- *   problem is solved through the full-SVD path on [C | 0] (square).  sv
+ *   problem is solved through the SVD of C: C^T (upper banded, bandwidth
+ *   nrhs) is reduced to a bidiagonal by Householder bulge chasing in one
+ *   workgroup's LDS (ell_done nrhs (3 nrhs + 1) <= 19 600 and ell_done nrhs
+ *   <= 1024: for 16 sources up to 25 block steps), whose SVD the
+ *   multisection path of mqh_proj_svd computes, the data and solutions
+ *   going through the reflectors.  Larger problems, a failed acceptance
+ *   test of that SVD, or MQH_FLAG_BLOCK_JACOBI in opts->flags take the
+ *   full-SVD path on [C | 0] (square) instead (MQH_INFO_BLOCK_JACOBI).  sv
  *   (ell_done nrhs, NULL allowed): singular values of C, descending.  info:
  *   nrhs records (NULL allowed): ell_done, lambda_chosen, crit (GCV at the
  *   choice), resid_norm = ||A coef_k - f_k|| and sol_norm = ||coef_k|| (from
@@ -511,7 +524,8 @@ int mqh_solve_sweep(mqh_sweep_item* items, int32_t count, const mqh_solve_opts* 
  *   (MQH_INFO_BREAKDOWN, MQH_INFO_GCV_AT_EDGE, MQH_INFO_SOLVE_NOCONV), t_ms
  *   [0] upload, [1] block recurrence, [2] projected problem (SVD, choices,
  *   solutions), [3] lift and download, [5] total, [6] Jacobi sweeps of the
- *   projected SVD, [7] conjugate-gradient iterations of this source.
+ *   projected SVD, [7] conjugate-gradient iterations of this source (both 0
+ *   on the band path).
  *   Returns MQH_WBREAKDOWN, else MQH_WNOCONV, else MQH_WEDGE (any source),
  *   else MQH_OK.
  */

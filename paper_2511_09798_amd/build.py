@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmqhelm.so")
 OBJDIR = os.path.join(ROOT, "_build")
 SOURCES = ["op_kernels.hip", "stored_kernels.hip", "gkb_kernels.hip", "proj_kernels.hip", "svd_kernels.hip",
-           "mlp_kernels.hip", "full_kernels.hip", "block_kernels.hip", "capi.hip"]
+           "mlp_kernels.hip", "full_kernels.hip", "block_kernels.hip", "band_kernels.hip", "capi.hip"]
 # the measurement library beside it (reference kernels for the rooflines; not part of the method)
 PEAK_SOURCES = ["peak_kernels.hip", "peak_capi.hip"]
 PEAK_LIB = os.path.join(HERE, "libmqhpeak.so")

@@ -1442,8 +1442,43 @@ int block_alloc(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell) {
 // block bases for (s, ell) with the projected solutions Y (ell s x 16) and
 // singular values, and the projected problem's run for its size (m, s) with
 // its per-source buffers.
+// Buffers of the band path of a projected problem of N = ell s columns and s
+// sources (band_kernels.hip): the chase's reflectors and step offsets, the
+// bidiagonal, the SVD workspace, values and vectors, the data G, H = U g,
+// U^T H, F~ (column-major per source), yhat, ||b_k||^2, the parameter
+// choices and the acceptance status.
+struct BandRun {
+    int N = 0, s = 0, T = 0, ntask = 0;
+    double *RR = nullptr, *LL = nullptr, *d = nullptr, *e = nullptr, *ws = nullptr, *sv = nullptr, *V = nullptr,
+           *ftil = nullptr, *G = nullptr, *H = nullptr, *Wt = nullptr, *F = nullptr, *Yh = nullptr, *fn2 = nullptr,
+           *tail = nullptr;
+    int32_t *toff = nullptr, *status = nullptr;
+    ParamOut* po = nullptr;
+    ~BandRun() {
+        dfree(RR);
+        dfree(LL);
+        dfree(d);
+        dfree(e);
+        dfree(ws);
+        dfree(sv);
+        dfree(V);
+        dfree(ftil);
+        dfree(G);
+        dfree(H);
+        dfree(Wt);
+        dfree(F);
+        dfree(Yh);
+        dfree(fn2);
+        dfree(tail);
+        dfree(toff);
+        dfree(status);
+        dfree(po);
+    }
+};
+
 struct BlockCache {
     std::unique_ptr<BlockWs> ws;
+    std::unique_ptr<BandRun> br;  // the band path's buffers for its (N, s)
     int32_t s = 0, ell = 0;
     double* Y = nullptr;
     double* sv = nullptr;
@@ -1547,7 +1582,8 @@ void block_cgs2(mqh_problem* p, BlockWs& b, const double* V, int32_t m, int32_t 
 // W_1 E_1 = F; Z_j D_j^T = A^T W_j - Z_{j-1} E_j^T; W_{j+1} E_{j+1} =
 // A Z_j - W_j D_j, each right side reorthogonalised against all earlier
 // blocks of its basis (CGS2) before its QR.  C (host, (ell + 1) s x ell s
-// row-major) receives D_j and E_{j+1}; E1 (s x s) the data's factor.  A QR
+// row-major; left empty when host_c is false, the device copy b.Cd holds it
+// either way) receives D_j and E_{j+1}; E1 (s x s) the data's factor.  A QR
 // with a diagonal entry of R at most n eps times the largest diagonal entry
 // of the D and E blocks so far (E_1 left out) is a breakdown: at a D block
 // *ell_done = j - 1 (flag 1), at an E block *ell_done = j with E_{j+1} = 0
@@ -1556,12 +1592,12 @@ void block_cgs2(mqh_problem* p, BlockWs& b, const double* V, int32_t m, int32_t 
 // nothing into C, and the basis columns past the kept steps are cleared at
 // the end.
 int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vector<double>& C, double* E1,
-                  int32_t* ell_done, int32_t* flag) {
+                  int32_t* ell_done, int32_t* flag, bool host_c = true) {
     hipStream_t st = p->stream;
     const int64_t ldn = p->ldn;
     const int64_t ldc = (int64_t)ell * s;
     const size_t csize = (size_t)((ell + 1) * s) * (size_t)ldc;
-    C.assign(csize, 0.0);
+    C.assign(host_c ? csize : 0, 0.0);
     HIPCHK(hipMemsetAsync(b.Cd, 0, csize * sizeof(double), st));
     HIPCHK(hipMemsetAsync(b.bs, 0, sizeof(BlkState), st));
     block_qr(p, b, b.W, s, 0, 0, ell, 0);
@@ -1586,7 +1622,7 @@ int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vecto
     LAUNCHCHK("block Golub-Kahan");
     BlkState h{};
     HIPCHK(hipMemcpyAsync(&h, b.bs, sizeof(BlkState), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(C.data(), b.Cd, csize * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (host_c) HIPCHK(hipMemcpyAsync(C.data(), b.Cd, csize * sizeof(double), hipMemcpyDeviceToHost, st));
     double E1h[kBlkRhs * kBlkRhs];
     HIPCHK(hipMemcpyAsync(E1h, b.E1d, (size_t)s * s * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1606,6 +1642,64 @@ int run_gkb_block(mqh_problem* p, BlockWs& b, int32_t s, int32_t ell, std::vecto
         HIPCHK(hipMemsetAsync(b.W + wk * ldn, 0, (size_t)(((int64_t)(ell + 1) * s - wk) * ldn) * sizeof(double), st));
         HIPCHK(hipMemsetAsync(b.Z + zk * ldn, 0, (size_t)(((int64_t)ell * s - zk) * ldn) * sizeof(double), st));
     }
+    return MQH_OK;
+}
+
+// The projected problem by the band path: the chase of C^T (C on the
+// device, (ell + 1) s x ell s at leading dimension ldc; E1 on the device,
+// s x s row-major), the multisection SVD of the bidiagonal, F~ for the s
+// sources, the parameter choices (as block_projected) and the solutions into
+// Y.  *ok = false when the SVD failed its acceptance test (Y, sv untouched
+// in meaning; the caller takes the Jacobi path).
+int band_projected(mqh_problem* p, const double* Cd, int64_t ldc, const double* E1d, int32_t s, int32_t ell,
+                   int32_t rule, int32_t J, double lambda_fixed, double* Y, double* sv_out,
+                   std::vector<ParamOut>& po_h, bool* ok) {
+    hipStream_t st = p->stream;
+    const int N = ell * s, Mc = N + s;
+    BlockCache& bc = *p->bc;
+    int rc;
+    if (!bc.br || bc.br->N != N || bc.br->s != s) {
+        bc.br.reset(new BandRun);
+        BandRun& r = *bc.br;
+        r.N = N;
+        r.s = s;
+        r.ntask = band_ntasks(N, s, &r.T);
+        const size_t nt = (size_t)(r.ntask > 0 ? r.ntask : 1) * (size_t)(s + 1);
+        if ((rc = dalloc(&r.RR, nt)) || (rc = dalloc(&r.LL, nt)) || (rc = dalloc(&r.d, (size_t)N)) ||
+            (rc = dalloc(&r.e, (size_t)N)) || (rc = dalloc(&r.ws, svd_ws_doubles(N))) ||
+            (rc = dalloc(&r.sv, (size_t)N)) || (rc = dalloc(&r.V, (size_t)N * N)) ||
+            (rc = dalloc(&r.ftil, (size_t)N + 1)) || (rc = dalloc(&r.G, (size_t)N * kBlkRhs)) ||
+            (rc = dalloc(&r.H, (size_t)N * kBlkRhs)) || (rc = dalloc(&r.Wt, (size_t)N * kBlkRhs)) ||
+            (rc = dalloc(&r.F, (size_t)N * kBlkRhs)) || (rc = dalloc(&r.Yh, (size_t)N * kBlkRhs)) ||
+            (rc = dalloc(&r.fn2, (size_t)kBlkRhs)) || (rc = dalloc(&r.tail, (size_t)(Mc + 1) * kBlkRhs)) ||
+            (rc = dalloc(&r.toff, (size_t)r.T + 1)) || (rc = dalloc(&r.status, 1)) ||
+            (rc = dalloc(&r.po, (size_t)kBlkRhs))) {
+            bc.br.reset();
+            return rc;
+        }
+    }
+    BandRun& r = *bc.br;
+    launch_band_chase(Cd, ldc, N, s, r.T, r.RR, r.LL, r.toff, r.d, r.e, st);
+    launch_band_data(E1d, N, s, r.RR, r.toff, r.T, r.d, r.e, r.ws, r.G, r.fn2, st);
+    LAUNCHCHK("block projected problem: band reduction");
+    launch_msvd_core(N, r.ws, r.sv, r.ftil, r.V, N, r.status, st);
+    LAUNCHCHK("block projected problem: SVD");
+    const double* U = r.ws;  // the SVD workspace starts with U (rows u_j, ld N)
+    launch_band_mm(0, U, N, N, s, r.G, nullptr, nullptr, nullptr, r.H, st);
+    launch_band_mm(1, U, N, N, s, r.H, nullptr, nullptr, nullptr, r.Wt, st);
+    launch_band_mm(2, U, N, N, s, r.Wt, r.H, nullptr, nullptr, r.F, st);
+    launch_full_param(r.sv, r.F, Mc, N, r.fn2, N, 1, rule == MQH_RULE_FIXED ? 2 : 0, J, lambda_fixed, 0, r.tail, r.po,
+                      s, st);
+    launch_band_mm(3, r.V, N, N, s, r.F, nullptr, r.sv, r.po, r.Yh, st);
+    launch_band_solve(r.Yh, N, s, r.LL, r.toff, r.T, Y, st);
+    LAUNCHCHK("block projected problem: choices and solutions");
+    if (sv_out) HIPCHK(hipMemcpyAsync(sv_out, r.sv, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    int32_t status = -1;
+    po_h.assign((size_t)s, ParamOut{});
+    HIPCHK(hipMemcpyAsync(&status, r.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(po_h.data(), r.po, (size_t)s * sizeof(ParamOut), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *ok = status == 0;
     return MQH_OK;
 }
 
@@ -2605,7 +2699,7 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     std::vector<double> Ch;
     double E1h[kBlkRhs * kBlkRhs];
     int32_t ld = 0, fl = 0;
-    if ((rc = run_gkb_block(p, b, nrhs, ell, Ch, E1h, &ld, &fl))) return rc;
+    if ((rc = run_gkb_block(p, b, nrhs, ell, Ch, E1h, &ld, &fl, false))) return rc;
     const auto t2 = now();
     if (ld == 0) {
         // nothing to project on: zero coefficients, breakdown reported
@@ -2616,11 +2710,7 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
             for (int32_t k = 0; k < nrhs; ++k) info[k].flags = MQH_INFO_BREAKDOWN;
         return MQH_WBREAKDOWN;
     }
-    // C of the ld steps kept: (ld + 1) s x ld s
     const int64_t ls = (int64_t)ld * nrhs, ldfull = (int64_t)ell * nrhs;
-    std::vector<double> Ck((size_t)((ld + 1) * nrhs) * (size_t)ls);
-    for (int64_t i = 0; i < (int64_t)(ld + 1) * nrhs; ++i)
-        for (int64_t j = 0; j < ls; ++j) Ck[(size_t)(i * ls + j)] = Ch[(size_t)(i * ldfull + j)];
     double* Y = p->bc->Y;  // ell nrhs x 16, cached with the block workspace
     HIPCHK(hipMemsetAsync(Y, 0, (size_t)ls * kBlkRhs * sizeof(double), st));
     double* svd = sv ? p->bc->sv : nullptr;
@@ -2628,9 +2718,27 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
     std::vector<int> iters;
     std::vector<char> conv;
     int32_t sweeps = 0;
-    if ((rc = block_projected(p, Ck, E1h, nrhs, ld, opts->rule, J, opts->lambda_fixed, Y, svd, po, iters, conv,
-                              &sweeps)))
-        return rc;
+    bool banded = false;
+    if (!(flags & MQH_FLAG_BLOCK_JACOBI) && band_fits((int)ls, nrhs)) {
+        if ((rc = band_projected(p, b.Cd, ldfull, b.E1d, nrhs, ld, opts->rule, J, opts->lambda_fixed, Y, svd, po,
+                                 &banded)))
+            return rc;
+        if (banded) {
+            iters.assign((size_t)nrhs, 0);
+            conv.assign((size_t)nrhs, 1);
+        }
+    }
+    if (!banded) {
+        // the Jacobi path takes C of the ld steps kept, (ld + 1) s x ld s, from the host
+        const size_t rows = (size_t)((ld + 1) * nrhs);
+        std::vector<double> Ck(rows * (size_t)ls);
+        HIPCHK(hipMemcpy2DAsync(Ck.data(), (size_t)ls * sizeof(double), b.Cd, (size_t)ldfull * sizeof(double),
+                                (size_t)ls * sizeof(double), rows, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if ((rc = block_projected(p, Ck, E1h, nrhs, ld, opts->rule, J, opts->lambda_fixed, Y, svd, po, iters, conv,
+                                  &sweeps)))
+            return rc;
+    }
     const auto t3 = now();
     // coefficients Z Y (in b.P, then out)
     launch_blk_update(b.Z, ldn, n, (int32_t)ls, Y, kBlkRhs, 1, b.P, ldn, nrhs, 0, st);
@@ -2653,7 +2761,8 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
         I.crit = po[(size_t)k].crit;
         I.resid_norm = po[(size_t)k].rho;
         I.sol_norm = po[(size_t)k].eta;
-        I.flags = po[(size_t)k].flags | (fl ? MQH_INFO_BREAKDOWN : 0u) | (conv[(size_t)k] ? 0u : MQH_INFO_SOLVE_NOCONV);
+        I.flags = po[(size_t)k].flags | (fl ? MQH_INFO_BREAKDOWN : 0u) | (conv[(size_t)k] ? 0u : MQH_INFO_SOLVE_NOCONV) |
+                  (banded ? 0u : MQH_INFO_BLOCK_JACOBI);
         I.t_ms[0] = ms(t0, t1);
         I.t_ms[1] = ms(t1, t2);
         I.t_ms[2] = ms(t2, t3);

@@ -217,6 +217,29 @@ void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const
 void launch_bidiag_qr(const double* alpha, const double* beta, int32_t l, const int32_t* l_ptr, double* ws,
                       double* sv, double* ftil, double* V, int64_t ldv, int32_t* status, bool flagged_only,
                       hipStream_t s, int nz, ProjBatch pb);
+// The multisection path without its setup, for one problem whose workspace
+// already holds B (d, e), g, the bounds and the flags: values, vectors, Gram
+// matrices, acceptance test (status 0 or 2) and the correction of V.
+void launch_msvd_core(int32_t l, double* ws, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
+                      hipStream_t s);
+
+// Projected problem of the block Golub-Kahan path by a band reduction of C^T
+// (band_kernels.hip, band.hpp).  Sizes: N = ell s columns of C, Mc = N + s
+// rows; the chase holds C^T in LDS (band_fits), T = steps of its schedule.
+constexpr int kBandLdsDoubles = 20160;  // N band::width(s) at most: 157.5 KiB of LDS
+constexpr int kBandDataDoubles = 7200;  // (N + s)(s + 1) at most
+constexpr int kBandMaxN = kMaxEll;
+constexpr int kBandMaxSteps = 4096;
+bool band_fits(int N, int s);
+int band_ntasks(int N, int s, int* nsteps);  // reflectors per side; *nsteps = T
+void launch_band_chase(const double* C, int64_t ldc, int N, int s, int T, double* RR, double* LL, int32_t* toff,
+                       double* d, double* e, hipStream_t st);
+void launch_band_data(const double* E1, int N, int s, const double* RR, const int32_t* toff, int T, const double* d,
+                      const double* e, double* ws, double* G, double* fn2, hipStream_t st);
+void launch_band_mm(int mode, const double* A, int64_t lda, int N, int s, const double* X, const double* X2,
+                    const double* sv, const ParamOut* po, double* out, hipStream_t st);
+void launch_band_solve(const double* Yh, int N, int s, const double* LL, const int32_t* toff, int T, double* Y,
+                       hipStream_t st);
 
 // projected problem (proj_kernels.hip)
 void launch_param_choice(const double* sv, const double* ft, int32_t l, const int32_t* l_ptr, int32_t method,

@@ -431,4 +431,14 @@ void launch_bidiag_svd(const double* alpha, const double* beta, int32_t l, const
     if (mode != 2) launch_bidiag_qr(alpha, beta, l, l_ptr, ws, sv, ftil, V, ldv, status, mode == 0, s, nz, pb);
 }
 
+void launch_msvd_core(int32_t l, double* ws, double* sv, double* ftil, double* V, int64_t ldv, int32_t* status,
+                      hipStream_t s) {
+    const ProjBatch pb{};
+    k_msvd_values<<<dim3(l, 1), kBlock, 0, s>>>(l, nullptr, ws, sv, pb);
+    k_msvd_vectors<<<dim3(l, 1), kWave, 6 * (size_t)l * sizeof(double), s>>>(l, nullptr, ws, sv, V, ldv, pb);
+    const int nt = (l + kGramTile - 1) / kGramTile;
+    k_msvd_gram<<<dim3(nt, nt, 2), kBlock, 0, s>>>(l, nullptr, ws, V, ldv, pb);
+    k_msvd_finish<<<dim3((l + kFinRows - 1) / kFinRows, 1), kBlock, 0, s>>>(l, nullptr, ws, V, ldv, ftil, status, pb);
+}
+
 }  // namespace mqh

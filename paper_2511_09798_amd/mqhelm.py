@@ -42,11 +42,13 @@ MQH_FLAG_GRAPH = 8
 MQH_FLAG_ROW_SCALE = 16
 MQH_FLAG_PROJ_QR = 32
 MQH_FLAG_PROJ_NO_FALLBACK = 64
+MQH_FLAG_BLOCK_JACOBI = 128
 MQH_INFO_BREAKDOWN = 1
 MQH_INFO_GCV_AT_EDGE = 2
 MQH_INFO_LCURVE_AT_EDGE = 4
 MQH_INFO_SOLVE_NOCONV = 8
 MQH_INFO_SVD_QR = 16
+MQH_INFO_BLOCK_JACOBI = 32
 MQH_MAX_ELL = 1024
 MQH_NOALLOC_MAX_ELL = 512
 MQH_NOALLOC_SCRATCH_BYTES = 6332800
@@ -508,9 +510,10 @@ def mqh_gkb_block(h, F, ell: int, want_bases: bool = False) -> dict:
 
 
 def mqh_solve_block(h, F, ell: int, rule: int = MQH_RULE_GCV, lambda_fixed: float = 0.0, n_grid: int = 200,
-                    coef=None, want_sv: bool = False) -> MultiSolveOutput:
+                    coef=None, want_sv: bool = False, jacobi: bool = False) -> MultiSolveOutput:
     """Block HKT: every row of F (nrhs x n) solved by Tikhonov on the block Krylov space of all rows
-    (ell block steps); the returned record's sv holds the projected singular values if want_sv."""
+    (ell block steps); the returned record's sv holds the projected singular values if want_sv.
+    jacobi: the projected problem through the Jacobi full SVD only (MQH_FLAG_BLOCK_JACOBI)."""
     n = int(lib.mqh_problem_size(h))
     s = int(F.shape[0])
     if F.shape[1] != n:
@@ -518,7 +521,7 @@ def mqh_solve_block(h, F, ell: int, rule: int = MQH_RULE_GCV, lambda_fixed: floa
     if coef is None:
         coef = _empty_like_kind(F, (s, n))
     sv = _zeros_like_kind(F, (ell * s,)) if want_sv else None
-    fl = _flags(F, coef, sv)
+    fl = _flags(F, coef, sv) | (MQH_FLAG_BLOCK_JACOBI if jacobi else 0)
     opts = mqh_solve_opts(ell=int(ell), reorth=1, method=MQH_METHOD_HKT, rule=int(rule), k_trunc=0,
                           n_grid=int(n_grid), lambda_fixed=float(lambda_fixed), flags=fl, row_scale=0, gcv_weight=1.0)
     infos = (mqh_solve_info * s)()

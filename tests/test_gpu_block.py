@@ -145,6 +145,52 @@ def test_block_solve_against_oracle(mq, orc, blk, case, blobs, mode):
         assert out.sol_norm[k] == pytest.approx(np.linalg.norm(out.coef[k]), rel=1e-8)
 
 
+@pytest.mark.parametrize("nsrc,ell", [(5, 16), (2, 60), (16, 7)])
+def test_block_band_path_matches_jacobi(mq, case, blobs, nsrc, ell):
+    # the projected problem by the band reduction of C^T (the default) and by the Jacobi full SVD
+    # (MQH_FLAG_BLOCK_JACOBI): the same singular values, GCV choices and fixed-lambda solutions to
+    # rounding; the info flags say which path ran
+    p, A, _ = case
+    F = blobs if nsrc == 5 else np.stack([I.random_vector(p.n, 900 + k) for k in range(nsrc)])
+    with _problem(mq, p, "stored_fp64") as pr:
+        say("block solve, band and Jacobi paths, s", nsrc, "ell", ell)
+        a = pr.solve_block(F, ell, want_sv=True)
+        b = pr.solve_block(F, ell, want_sv=True, jacobi=True)
+        lam = float(np.median(b.lam))
+        af = pr.solve_block(F, ell, rule=mq.MQH_RULE_FIXED, lambda_fixed=lam)
+        bf = pr.solve_block(F, ell, rule=mq.MQH_RULE_FIXED, lambda_fixed=lam, jacobi=True)
+    assert not np.any(a.flags & mq.MQH_INFO_BLOCK_JACOBI) and np.all(b.flags & mq.MQH_INFO_BLOCK_JACOBI)
+    assert np.all(a.ell_done == b.ell_done)
+    n_sv = int(a.ell_done[0]) * nsrc
+    dsv = np.max(np.abs(a.sv[:n_sv] - b.sv[:n_sv])) / b.sv[0]
+    say("sv diff", dsv, "lambda", a.lam, b.lam)
+    assert dsv <= 64 * n_sv * EPS
+    np.testing.assert_allclose(a.lam, b.lam, rtol=1e-6)
+    for k in range(nsrc):
+        assert np.linalg.norm(af.coef[k] - bf.coef[k]) <= 1e-9 * np.linalg.norm(bf.coef[k])
+        assert np.linalg.norm(a.coef[k] - b.coef[k]) <= 1e-5 * np.linalg.norm(b.coef[k])
+
+
+def test_block_band_path_size_limit(mq):
+    # 16 sources: 25 block steps (N = 400 columns of C) are the most the band chase holds in LDS;
+    # 26 take the Jacobi path.  At 25 the two paths agree as above.
+    p = I.cube_scaled(2400, 600, kappa=4.0, eps=1.5, ell=25)
+    F = np.stack([I.random_vector(p.n, 950 + k) for k in range(16)])
+    with _problem(mq, p, "stored_fp64") as pr:
+        say("block solve at the band path's size limit")
+        a = pr.solve_block(F, 25, want_sv=True)
+        lam = float(np.median(a.lam))
+        af = pr.solve_block(F, 25, rule=mq.MQH_RULE_FIXED, lambda_fixed=lam)
+        bf = pr.solve_block(F, 25, rule=mq.MQH_RULE_FIXED, lambda_fixed=lam, jacobi=True)
+        say("one step more")
+        c = pr.solve_block(F, 26)
+    say("ell_done", a.ell_done[0], c.ell_done[0], "flags", a.flags[0], c.flags[0])
+    assert a.ell_done[0] == 25 and c.ell_done[0] == 26
+    assert not np.any(a.flags & mq.MQH_INFO_BLOCK_JACOBI) and np.all(c.flags & mq.MQH_INFO_BLOCK_JACOBI)
+    for k in range(16):
+        assert np.linalg.norm(af.coef[k] - bf.coef[k]) <= 1e-9 * np.linalg.norm(bf.coef[k])
+
+
 def test_block_one_source_is_single_hkt(mq):
     # the cube with an interior GCV minimum of the single-source parity tests
     p = I.cube_scaled(400, 240, kappa=3.0, eps=0.7, ell=80)
