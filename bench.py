@@ -766,10 +766,13 @@ def main():
                                  frac=ops / (kms * 1e-3) / pk, ops_per_launch=ops,
                                  kernel=("k_mfs<true>" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mfs<false>")
                                  if mode == "matfree_fp32" else
-                                 ("k_mf_cols" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mf_rows"),
+                                 ("k_mfs64<true>" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mfs64<false>"),
                                  kernel_ms=kms,
                                  note=f"{oi} / {ob} operations per interior / boundary entry against the published "
                                       f"{'FP32' if mode == 'matfree_fp32' else 'FP64'} vector peak")
+            if mode == "matfree_fp64":
+                e["roofline"]["note"] += ("; the kernel evaluates each unordered pair of nodes once (one t and "
+                                          "one rsqrt for A_ij and A_ji), about half of these operations")
             if mode == "matfree_fp32":
                 e["arithmetic"] = ("entries in FP32 from FP32 node coordinates, each unordered pair of nodes "
                                    "evaluated once for A_ij and A_ji; the Krylov vector entering each product "

@@ -220,6 +220,7 @@ struct mqh_problem {
     // per block of kMfmFixed sorted nodes, and the weight-folded coefficients
     // of the current product in the sorted order
     float4* XS = nullptr;
+    double4* XS64 = nullptr;  // FP64 pair products: sorted coordinates, the product's weights in .w
     int32_t* perm = nullptr;
     int32_t* iperm = nullptr;  // iperm[perm[q]] = q
     float4* frames = nullptr;
@@ -247,12 +248,6 @@ struct mqh_problem {
     double* vx = nullptr;
     double* vy = nullptr;
     double* vz = nullptr;
-    // split-K partials, P_rows x ldn
-    double* P = nullptr;
-    int64_t P_rows = 0;
-    // launch shapes
-    int S_rows = 1, S_cols = 1;
-    int64_t slice_rows = 0, slice_cols = 0;
     // Golub-Kahan workspace
     int32_t ell_cap = 0;
     double* W = nullptr;
@@ -349,7 +344,7 @@ void morton_order(const std::vector<double4>& r, int64_t a, int64_t b, std::vect
 // Sorted records and one frame centre (bounding-box midpoint) per block of
 // kMfmFixed sorted nodes, interior blocks first.
 void sorted_layout(const std::vector<double4>& r, int64_t n, int64_t n_int, std::vector<int32_t>& perm,
-                   std::vector<float4>& rs32, std::vector<float4>& frames) {
+                   std::vector<float4>& rs32, std::vector<float4>& frames, std::vector<double4>* rs64 = nullptr) {
     perm.clear();
     perm.reserve((size_t)n);
     morton_order(r, 0, n_int, perm);
@@ -379,6 +374,7 @@ void sorted_layout(const std::vector<double4>& r, int64_t n, int64_t n_int, std:
         frames[(size_t)b] = make_float4((float)(0.5 * (lo[0] + hi[0])), (float)(0.5 * (lo[1] + hi[1])),
                                         (float)(0.5 * (lo[2] + hi[2])), 0.0f);
     }
+    if (rs64 != nullptr) rs64->swap(rs);
 }
 
 // Tables of the tiled stored matrix: tile rows (interior tiles first), the
@@ -407,35 +403,6 @@ void packed_tables(int64_t n, int64_t n_int, PackedTables& t) {
             t.items.push_back(make_int4(R, p0, ntr - p0 < kTileChunk ? ntr - p0 : kTileChunk, 0));
     }
     t.item_first[(size_t)t.nt] = (int32_t)t.items.size();
-}
-
-void choose_shapes(mqh_problem* p) {
-    // the split of the FP64 matrix-free products (the FP32-evaluated ones run
-    // over work items of node pairs, the stored ones over tiles): slices of
-    // even length, enough blocks for many rounds of resident waves over 256 CUs
-    const int64_t n = p->n;
-    if (p->mode != MQH_OP_MATFREE_FP64) {
-        p->S_rows = p->S_cols = 1;
-        p->slice_rows = p->slice_cols = n;
-        p->P_rows = 1;
-        return;
-    }
-    const int64_t target_blocks = 4096;
-    const int64_t nb_rows = (p->n_int + kBlock - 1) / kBlock + (p->n_bnd + kBlock - 1) / kBlock;
-    const int64_t nb_cols = (n + kBlock - 1) / kBlock;
-    auto pick = [&](int64_t nb, int& S, int64_t& len) {
-        int64_t s = (target_blocks + nb - 1) / nb;
-        if (s < 1) s = 1;
-        if (s > 64) s = 64;
-        int64_t l = (n + s - 1) / s;
-        l = round_up(l < 64 ? 64 : l, 2);
-        s = (n + l - 1) / l;
-        S = (int)(s < 1 ? 1 : s);
-        len = l;
-    };
-    pick(nb_rows, p->S_rows, p->slice_rows);
-    pick(nb_cols, p->S_cols, p->slice_cols);
-    p->P_rows = p->S_rows > p->S_cols ? p->S_rows : p->S_cols;
 }
 
 // Entry constants of the operator the current call runs on: A, or D A with
@@ -517,6 +484,9 @@ int op_product(mqh_problem* p, int trans, const double* x, const double* shift_p
         // (outside the timed span)
         launch_gather_coef(x, p->perm, p->n, op_ec(p), p->cf, st, s);
         LAUNCHCHK("gather");
+    } else if (p->mode == MQH_OP_MATFREE_FP64) {
+        launch_gather_w64(x, p->perm, p->n, p->XS64, st, s);
+        LAUNCHCHK("gather");
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -546,19 +516,12 @@ int op_product(mqh_problem* p, int trans, const double* x, const double* shift_p
         LAUNCHCHK("pair product reduction");
         return MQH_OK;
     }
-    int S;
-    const int32_t* perm = nullptr;
-    if (!trans) {
-        S = p->S_rows;
-        launch_mf_rows(p->X64, x, p->n, p->n_int, S, p->slice_rows, op_ec(p), p->P, p->ldn, st, s);
-    } else {
-        S = p->S_cols;
-        launch_mf_cols(p->X64, x, p->n, p->n_int, S, p->slice_cols, op_ec(p), p->P, p->ldn, st, s);
-    }
-    LAUNCHCHK("matrix-free product");
+    // FP64 matrix-free: the same pair structure with FP64 entries
+    launch_mfs64_product(trans, p->XS64, p->sym, op_ec(p), p->sym_row, p->sym_col, st, s);
+    LAUNCHCHK("FP64 pair product");
     if (timed) HIPCHK(hipEventRecord(e1, s));
-    launch_reduce_slices(p->P, p->ldn, S, p->n, perm, shift_ptr, shift_val, z, y, st, s);
-    LAUNCHCHK("slice reduction");
+    launch_mfs_reduce(p->sym, p->sym_row, p->sym_col, p->perm, shift_ptr, shift_val, z, y, st, s);
+    LAUNCHCHK("pair product reduction");
     return MQH_OK;
 }
 
@@ -1842,6 +1805,7 @@ int mqh_problem_destroy(mqh_problem* p) {
     dfree(p->mlp);
     dfree(p->pout2);
     dfree(p->XS);
+    dfree(p->XS64);
     dfree(p->perm);
     dfree(p->iperm);
     dfree(p->frames);
@@ -1859,7 +1823,6 @@ int mqh_problem_destroy(mqh_problem* p) {
     dfree(p->vx);
     dfree(p->vy);
     dfree(p->vz);
-    dfree(p->P);
     dfree(p->W);
     dfree(p->Z);
     dfree(p->alpha);
@@ -1960,13 +1923,11 @@ int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, 
     std::vector<double4> r64((size_t)n);
     std::vector<float4> r32((size_t)n);
     to_records(p, xyz.data(), n, r64.data(), r32.data());
-    choose_shapes(p);
     if ((rc = dalloc(&p->X64, (size_t)n))) return bail(rc);
     if ((rc = dalloc(&p->X32, (size_t)n))) return bail(rc);
     if ((rc = dalloc(&p->vx, (size_t)p->ldn))) return bail(rc);
     if ((rc = dalloc(&p->vy, (size_t)p->ldn))) return bail(rc);
     if ((rc = dalloc(&p->vz, (size_t)p->ldn))) return bail(rc);
-    if ((rc = dalloc(&p->P, (size_t)(p->P_rows * p->ldn)))) return bail(rc);
     if ((rc = dalloc(&p->st, 1))) return bail(rc);
     if ((rc = dalloc(&p->npart, (size_t)(update_blocks(n) > 1024 ? update_blocks(n) : 1024)))) return bail(rc);
     if ((rc = dalloc(&p->pout, 1))) return bail(rc);
@@ -1984,26 +1945,37 @@ int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, 
         (e = hipMemsetAsync(p->vz, 0, (size_t)p->ldn * sizeof(double), p->stream)) ||
         (e = hipMemsetAsync(p->coef, 0, (size_t)p->ldn * sizeof(double), p->stream)))
         return bail(hip_fail(e, "upload"));
-    if (op_mode == MQH_OP_MATFREE_FP32) {
+    if (op_mode == MQH_OP_MATFREE_FP32 || op_mode == MQH_OP_MATFREE_FP64) {
+        // both matrix-free modes run over unordered node pairs in the sorted order
         std::vector<int32_t> perm;
         std::vector<float4> rs, frames;
-        sorted_layout(r64, n, n_int, perm, rs, frames);
-        if ((rc = dalloc(&p->XS, (size_t)n))) return bail(rc);
+        std::vector<double4> rs64;
+        sorted_layout(r64, n, n_int, perm, rs, frames, &rs64);
         if ((rc = dalloc(&p->perm, (size_t)n))) return bail(rc);
         if ((rc = dalloc(&p->iperm, (size_t)n))) return bail(rc);
         std::vector<int32_t> iperm((size_t)n);
         for (int64_t q = 0; q < n; ++q) iperm[(size_t)perm[(size_t)q]] = (int32_t)q;
-        if ((rc = dalloc(&p->frames, frames.size()))) return bail(rc);
-        if ((rc = dalloc(&p->cf, (size_t)n))) return bail(rc);
-        if ((e = hipMemcpyAsync(p->XS, rs.data(), (size_t)n * sizeof(float4), hipMemcpyHostToDevice, p->stream)) ||
-            (e = hipMemcpyAsync(p->perm, perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice,
+        if ((e = hipMemcpyAsync(p->perm, perm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice,
                                 p->stream)) ||
             (e = hipMemcpyAsync(p->iperm, iperm.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice,
-                                p->stream)) ||
-            (e = hipMemcpyAsync(p->frames, frames.data(), frames.size() * sizeof(float4), hipMemcpyHostToDevice,
-                                p->stream)) ||
-            (e = hipStreamSynchronize(p->stream)))
+                                p->stream)))
             return bail(hip_fail(e, "upload of the sorted layout"));
+        if (op_mode == MQH_OP_MATFREE_FP32) {
+            if ((rc = dalloc(&p->XS, (size_t)n)) || (rc = dalloc(&p->frames, frames.size())) ||
+                (rc = dalloc(&p->cf, (size_t)n)))
+                return bail(rc);
+            if ((e = hipMemcpyAsync(p->XS, rs.data(), (size_t)n * sizeof(float4), hipMemcpyHostToDevice,
+                                    p->stream)) ||
+                (e = hipMemcpyAsync(p->frames, frames.data(), frames.size() * sizeof(float4), hipMemcpyHostToDevice,
+                                    p->stream)))
+                return bail(hip_fail(e, "upload of the sorted layout"));
+        } else {
+            if ((rc = dalloc(&p->XS64, (size_t)n))) return bail(rc);
+            if ((e = hipMemcpyAsync(p->XS64, rs64.data(), (size_t)n * sizeof(double4), hipMemcpyHostToDevice,
+                                    p->stream)))
+                return bail(hip_fail(e, "upload of the sorted layout"));
+        }
+        if ((e = hipStreamSynchronize(p->stream))) return bail(hip_fail(e, "upload of the sorted layout"));
         std::vector<int2> items;
         std::vector<int32_t> first;
         sym_tables(n, n_int, p->sym, items, first);

@@ -74,15 +74,17 @@ struct ParamOut {
 };
 
 // operator (op_kernels.hip)
-void launch_mf_rows(const double4* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
-                    const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s);
-void launch_mf_cols(const double4* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
-                    const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s);
 int64_t mfm_blocks(int64_t n, int64_t n_int);
 void launch_gather_coef(const double* x, const int32_t* perm, int64_t n, const EntryConst& c, float4* CF,
                         const GkbState* st, hipStream_t s);
 void launch_mfs_product(int trans, const float4* XS, const float4* frames, const float4* CF, const SymLayout& L,
                         const EntryConst& c, double* RowP, double* ColP, const GkbState* st, hipStream_t s);
+// FP64 products over unordered node pairs (same work items and partials as
+// the FP32 form; XS64 sorted coordinates, weights written into .w by the gather)
+void launch_gather_w64(const double* x, const int32_t* perm, int64_t n, double4* XS64, const GkbState* st,
+                       hipStream_t s);
+void launch_mfs64_product(int trans, const double4* XS64, const SymLayout& L, const EntryConst& c, double* RowP,
+                          double* ColP, const GkbState* st, hipStream_t s);
 void launch_mfs_reduce(const SymLayout& L, const double* RowP, const double* ColP, const int32_t* perm,
                        const double* shift_ptr, double shift_val, const double* z, double* y, const GkbState* st,
                        hipStream_t s);

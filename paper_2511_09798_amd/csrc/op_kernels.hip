@@ -12,11 +12,11 @@
 namespace mqh {
 
 // ---------------------------------------------------------------------------
-// Matrix-free products.  One lane per output element; the loop index is
-// wave-uniform, so the loop node's record and weight are scalar loads and
-// each entry costs only VALU work (entry + one FP64 FMA).  The loop range is
-// cut into S slices (split-K, blockIdx.y) whose partial sums go to
-// P[slice * ldp + out]; k_reduce_slices adds them in slice order.
+// A span of loop nodes against one output position (the evaluation of the
+// RBF expansion): the loop index is wave-uniform, so the loop node's record
+// and weight are scalar loads and each term costs only VALU work.  Split
+// over the loop range, the partial sums go to P[slice * ldp + out] and
+// k_reduce_slices adds them in slice order.
 // ---------------------------------------------------------------------------
 
 template <typename R, int KIND>
@@ -41,52 +41,6 @@ __device__ __forceinline__ void mf_span(const typename NodeOf<R>::type* __restri
         const R e0 = KIND == 0 ? entry_interior(t0, c) : entry_boundary(t0, c);
         acc0 = fma((double)e0, w[j], acc0);
     }
-}
-
-// y = A x partials.  Blocks [0, nb_int) cover interior rows, the rest the
-// boundary rows, so the row kind is uniform per block.
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_mf_rows(const typename NodeOf<R>::type* __restrict__ X,
-                                                    const double* __restrict__ x, int64_t n, int64_t n_int,
-                                                    int64_t nb_int, int64_t slice_len, EntryConst c,
-                                                    double* __restrict__ P, int64_t ldp,
-                                                    const GkbState* __restrict__ st) {
-    if (st != nullptr && st->stopped) return;
-    const int64_t b = blockIdx.x;
-    const bool interior = b < nb_int;
-    const int64_t row = interior ? b * kBlock + threadIdx.x : n_int + (b - nb_int) * kBlock + threadIdx.x;
-    const int64_t row_end = interior ? n_int : n;
-    const bool valid = row < row_end;
-    const auto p = X[valid ? row : 0];
-    const int64_t j0 = (int64_t)blockIdx.y * slice_len;
-    const int64_t j1 = j0 + slice_len < n ? j0 + slice_len : n;
-    double a0 = 0.0, a1 = 0.0;
-    if (interior)
-        mf_span<R, 0>(X, x, j0, j1, p.x, p.y, p.z, c, a0, a1);
-    else
-        mf_span<R, 1>(X, x, j0, j1, p.x, p.y, p.z, c, a0, a1);
-    if (valid) P[(int64_t)blockIdx.y * ldp + row] = a0 + a1;
-}
-
-// y = A^T x partials: one lane per column; the loop runs over rows, first
-// the interior ones (L phi), then the boundary ones (phi).
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_mf_cols(const typename NodeOf<R>::type* __restrict__ X,
-                                                    const double* __restrict__ x, int64_t n, int64_t n_int,
-                                                    int64_t slice_len, EntryConst c, double* __restrict__ P,
-                                                    int64_t ldp, const GkbState* __restrict__ st) {
-    if (st != nullptr && st->stopped) return;
-    const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = col < n;
-    const auto p = X[valid ? col : 0];
-    const int64_t i0 = (int64_t)blockIdx.y * slice_len;
-    const int64_t i1 = i0 + slice_len < n ? i0 + slice_len : n;
-    double a0 = 0.0, a1 = 0.0;
-    const int64_t m1 = i1 < n_int ? i1 : n_int;
-    if (i0 < m1) mf_span<R, 0>(X, x, i0, m1, p.x, p.y, p.z, c, a0, a1);
-    const int64_t m0 = i0 > n_int ? i0 : n_int;
-    if (m0 < i1) mf_span<R, 1>(X, x, m0, i1, p.x, p.y, p.z, c, a0, a1);
-    if (valid) P[(int64_t)blockIdx.y * ldp + col] = a0 + a1;
 }
 
 // y_o = sum_s P[s][i] - shift * z_o with o = perm[i] (o = i when perm is
@@ -472,6 +426,195 @@ __global__ __launch_bounds__(kBlock) void k_mfs(const float4* __restrict__ XS, c
     for (int i = tid; i < L.Lb * kMfmFixed; i += kBlock) cpo[i] = colacc[i];
 }
 
+// ---------------------------------------------------------------------------
+// FP64 products over unordered pairs of nodes: the work items, lane layout
+// and partials of k_mfs with every quantity in FP64.  A lane holds the
+// coordinates and weights of 4 fixed rows (4g + r) of each of its kMfmFt
+// tiles and takes loop node jj of each staged tile of 16; t = 1 + |P_i -
+// P_j|^2 comes from the coordinate differences (FP64 VALU; the matrix cores
+// at FP64 would save little and leave t exposed to the rank-4 form's
+// cancellation), s = t^(-1/2) from the FP64 estimate and two Newton steps,
+// the entry as in the single-entry FP64 products.  Row sums stay per lane in
+// FP64 and are reduced over the 16 lanes of a row at the end of the fixed
+// block; column sums are added over the lane's 8 rows, over lane groups g by
+// a swizzle and LDS, and collected per item as in k_mfs.  XS64: sorted
+// coordinates, the weight x[perm[q]] in .w (written by k_gather_w64).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double swizzle_xor16(double v) {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+    return __hiloint2double(hi, lo);
+}
+
+template <bool RI, bool CI, bool SYM, int NT>
+__device__ __forceinline__ void mfs64_tiles(const double4* __restrict__ lds_p, const double (&px)[kMfmFt][4],
+                                            const double (&py)[kMfmFt][4], const double (&pz)[kMfmFt][4],
+                                            const double (&xi)[kMfmFt][4], double k2, double e2x2, double e2,
+                                            double (&acc)[kMfmFt][4], double* __restrict__ colw) {
+    const int lane = threadIdx.x & (kWave - 1), jj = lane & 15;
+    for (int u = 0; u < NT; ++u) {
+        const double4 q = lds_p[u * 16 + jj];
+        double cp = 0.0;
+#pragma unroll
+        for (int f = 0; f < kMfmFt; ++f) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double dx = px[f][r] - q.x, dy = py[f][r] - q.y, dz = pz[f][r] - q.z;
+                const double t = fma(dz, dz, fma(dy, dy, fma(dx, dx, 1.0)));
+                const double sv = rsqrt_f64(t);
+                if (RI && CI) {
+                    const double e = fma(e2, sv * sv, fma(k2, t, e2x2)) * sv;
+                    acc[f][r] = fma(e, q.w, acc[f][r]);
+                    if (SYM) cp = fma(e, xi[f][r], cp);
+                } else if (!RI && !CI) {
+                    const double e = t * sv;
+                    acc[f][r] = fma(e, q.w, acc[f][r]);
+                    if (SYM) cp = fma(e, xi[f][r], cp);
+                } else {
+                    const double ei = fma(e2, sv * sv, fma(k2, t, e2x2)) * sv;
+                    const double eb = t * sv;
+                    acc[f][r] = fma(RI ? ei : eb, q.w, acc[f][r]);
+                    cp = fma(CI ? ei : eb, xi[f][r], cp);
+                }
+            }
+        }
+        // keep the row sums at their tile (left to itself the compiler sinks
+        // them past the loop and holds every tile's entries live)
+#pragma unroll
+        for (int f = 0; f < kMfmFt; ++f)
+            asm volatile("" : "+v"(acc[f][0]), "+v"(acc[f][1]), "+v"(acc[f][2]), "+v"(acc[f][3]));
+        if (SYM) {
+            // lanes l and l ^ 16 hold the same loop node: add them and let the lower lane store
+            cp += swizzle_xor16(cp);
+            if ((lane & 16) == 0) colw[u * 16] = cp;
+        }
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void mfs64_dispatch(bool ri, bool ci, const double4* lds_p, const double (&px)[kMfmFt][4],
+                                               const double (&py)[kMfmFt][4], const double (&pz)[kMfmFt][4],
+                                               const double (&xi)[kMfmFt][4], double k2, double e2x2, double e2,
+                                               double (&acc)[kMfmFt][4], double* colw) {
+    if (ri && ci)
+        mfs64_tiles<true, true, true, NT>(lds_p, px, py, pz, xi, k2, e2x2, e2, acc, colw);
+    else if (!ri && !ci)
+        mfs64_tiles<false, false, true, NT>(lds_p, px, py, pz, xi, k2, e2x2, e2, acc, colw);
+    else if (ri)
+        mfs64_tiles<true, false, true, NT>(lds_p, px, py, pz, xi, k2, e2x2, e2, acc, colw);
+    else
+        mfs64_tiles<false, true, true, NT>(lds_p, px, py, pz, xi, k2, e2x2, e2, acc, colw);
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(kBlock) void k_mfs64(const double4* __restrict__ XS64, SymLayout L, EntryConst c,
+                                                  double* __restrict__ RowP, double* __restrict__ ColP,
+                                                  const GkbState* __restrict__ st) {
+    __shared__ double4 lds_p[kMfmChunk];
+    __shared__ double lds_col[2 * (kBlock / kWave)][kMfmChunk];  // per (wave, lane-group pair)
+    __shared__ double colacc[kSymMaxLb * kMfmFixed];
+    __shared__ double red[64 * 17];
+    if (st != nullptr && st->stopped) return;
+    const int2 item = L.items[blockIdx.x];
+    const int64_t slot = (int64_t)L.item_first[item.x] + item.y;
+    const int b0 = item.x * L.F;
+    const int b1 = b0 + L.F < L.nb ? b0 + L.F : L.nb;
+    const int c0 = b0 + item.y * L.Lb;
+    const int c1 = c0 + L.Lb < L.nb ? c0 + L.Lb : L.nb;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), g = lane >> 4, jj = lane & 15, wv = tid / kWave;
+    for (int i = tid; i < kSymMaxLb * kMfmFixed; i += kBlock) colacc[i] = 0.0;
+    const double k2 = c.k2, e2x2 = c.e2x2, e2 = c.e2;
+    for (int fb = b0; fb < b1; ++fb) {
+        const int64_t fs = sym_blk_start(fb, L), fe = sym_blk_end(fb, L);
+        const bool fint = fb < L.nb_int;
+        double px[kMfmFt][4], py[kMfmFt][4], pz[kMfmFt][4], xi[kMfmFt][4], acc[kMfmFt][4];
+#pragma unroll
+        for (int f = 0; f < kMfmFt; ++f) {
+            const int64_t base = fs + (int64_t)(wv * kMfmFt + f) * 16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i2 = base + 4 * g + r;
+                const double4 q = XS64[i2 < fe ? i2 : fs];
+                const bool in = i2 < fe;
+                px[f][r] = q.x;
+                py[f][r] = q.y;
+                pz[f][r] = q.z;
+                xi[f][r] = in ? q.w : 0.0;
+                acc[f][r] = 0.0;
+            }
+        }
+        for (int cb = c0 > fb ? c0 : fb; cb < c1;) {
+            const bool diag = cb == fb;
+            const bool cint = cb < L.nb_int;
+            int ce = cb + 1;
+            if (!diag && ce < c1 && (ce < L.nb_int) == cint && sym_blk_end(cb, L) - sym_blk_start(cb, L) == kMfmFixed)
+                ce = cb + 2;
+            const int64_t j0 = sym_blk_start(cb, L), j1 = sym_blk_end(ce - 1, L);
+            // stage the chunk's loop nodes (coordinates and weight); past j1 the
+            // first node with weight 0 (its column sums are not collected)
+            const int64_t j = j0 + tid;
+            double4 q = XS64[j < j1 ? j : j0];
+            if (!(j < j1)) q.w = 0.0;
+            __syncthreads();  // the previous chunk (or the row reduction) is done with LDS
+            lds_p[tid] = q;
+            __syncthreads();
+            const bool ri = TRANS ? cint : fint, ci = TRANS ? fint : cint;
+            double* colw = &lds_col[2 * wv + (g >> 1)][jj];
+            if (diag) {
+                if (fint)
+                    mfs64_tiles<true, true, false, 8>(lds_p, px, py, pz, xi, k2, e2x2, e2, acc, colw);
+                else
+                    mfs64_tiles<false, false, false, 8>(lds_p, px, py, pz, xi, k2, e2x2, e2, acc, colw);
+            } else if (ce == cb + 2) {
+                mfs64_dispatch<16>(ri, ci, lds_p, px, py, pz, xi, k2, e2x2, e2, acc, colw);
+            } else {
+                mfs64_dispatch<8>(ri, ci, lds_p, px, py, pz, xi, k2, e2x2, e2, acc, colw);
+            }
+            if (!diag) {
+                // the chunk's column sums: the 8 (wave, lane-group pair) partials of each loop node
+                __syncthreads();
+                if (tid < (int)(j1 - j0)) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int qq = 0; qq < 2 * (kBlock / kWave); ++qq) v += lds_col[qq][tid];
+                    colacc[(cb - c0) * kMfmFixed + tid] += v;
+                }
+            }
+            cb = ce;
+        }
+        // the fixed block's row sums: each row's 16 lane partials in a fixed order
+        double* rp = RowP + slot * L.F * kMfmFixed + (int64_t)(fb - b0) * kMfmFixed;
+#pragma unroll
+        for (int f = 0; f < kMfmFt; ++f) {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[(wv * 16 + 4 * g + r) * 17 + jj] = acc[f][r];
+            __syncthreads();
+            if (tid < 64) {
+                const int node = tid;
+                double sum = 0.0;
+                for (int qq = 0; qq < 16; ++qq) sum += red[node * 17 + qq];
+                const int row = ((node >> 4) * kMfmFt + f) * 16 + (node & 15);
+                rp[row] = fs + row < fe ? sum : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    double* cpo = ColP + slot * L.Lb * kMfmFixed;
+    for (int i = tid; i < L.Lb * kMfmFixed; i += kBlock) cpo[i] = colacc[i];
+}
+
+// XS64[q].w = x[perm[q]]: the weights of a FP64 pair product in the sorted order.
+__global__ __launch_bounds__(kBlock) void k_gather_w64(const double* __restrict__ x, const int32_t* __restrict__ perm,
+                                                       int64_t n, double4* __restrict__ XS64,
+                                                       const GkbState* __restrict__ st) {
+    if (st != nullptr && st->stopped) return;
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    XS64[q].w = x[perm[q]];
+}
+
 // y_o = (row partials of the items of q's super-row + column partials of
 // the items whose segment holds q's block) - shift z_o, o = perm[q]; the
 // partials are added in item order, four running sums combined at the end.
@@ -825,20 +968,6 @@ __global__ __launch_bounds__(kBlock) void k_eval_partial(const double4* __restri
 // Host launchers
 // ---------------------------------------------------------------------------
 
-void launch_mf_rows(const double4* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
-                    const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s) {
-    const int64_t nb_int = (n_int + kBlock - 1) / kBlock;
-    const int64_t nb_bnd = (n - n_int + kBlock - 1) / kBlock;
-    dim3 grid((unsigned)(nb_int + nb_bnd), (unsigned)S);
-    k_mf_rows<double><<<grid, kBlock, 0, s>>>(X, x, n, n_int, nb_int, slice_len, c, P, ldp, st);
-}
-
-void launch_mf_cols(const double4* X, const double* x, int64_t n, int64_t n_int, int S, int64_t slice_len,
-                    const EntryConst& c, double* P, int64_t ldp, const GkbState* st, hipStream_t s) {
-    dim3 grid((unsigned)((n + kBlock - 1) / kBlock), (unsigned)S);
-    k_mf_cols<double><<<grid, kBlock, 0, s>>>(X, x, n, n_int, slice_len, c, P, ldp, st);
-}
-
 int64_t mfm_blocks(int64_t n, int64_t n_int) {
     return (n_int + kMfmFixed - 1) / kMfmFixed + (n - n_int + kMfmFixed - 1) / kMfmFixed;
 }
@@ -855,6 +984,20 @@ void launch_mfs_product(int trans, const float4* XS, const float4* frames, const
         k_mfs<true><<<(unsigned)L.nitems, kBlock, 0, s>>>(XS, CF, L, frames, c, RowP, ColP, st);
     else
         k_mfs<false><<<(unsigned)L.nitems, kBlock, 0, s>>>(XS, CF, L, frames, c, RowP, ColP, st);
+}
+
+void launch_gather_w64(const double* x, const int32_t* perm, int64_t n, double4* XS64, const GkbState* st,
+                       hipStream_t s) {
+    k_gather_w64<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(x, perm, n, XS64, st);
+}
+
+void launch_mfs64_product(int trans, const double4* XS64, const SymLayout& L, const EntryConst& c, double* RowP,
+                          double* ColP, const GkbState* st, hipStream_t s) {
+    if (L.nitems <= 0) return;
+    if (trans)
+        k_mfs64<true><<<(unsigned)L.nitems, kBlock, 0, s>>>(XS64, L, c, RowP, ColP, st);
+    else
+        k_mfs64<false><<<(unsigned)L.nitems, kBlock, 0, s>>>(XS64, L, c, RowP, ColP, st);
 }
 
 void launch_mfs_reduce(const SymLayout& L, const double* RowP, const double* ColP, const int32_t* perm,
