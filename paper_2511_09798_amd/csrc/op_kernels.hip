@@ -514,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_mfs64(const double4* __restrict__ XS
     __shared__ double4 lds_p[kMfmChunk];
     __shared__ double lds_col[2 * (kBlock / kWave)][kMfmChunk];  // per (wave, lane-group pair)
     __shared__ double colacc[kSymMaxLb * kMfmFixed];
-    __shared__ double red[64 * 17];
+    double* red = &lds_col[0][0];  // 64 rows x 17 (padded), between chunks (four workgroups fit a CU's LDS)
     if (st != nullptr && st->stopped) return;
     const int2 item = L.items[blockIdx.x];
     const int64_t slot = (int64_t)L.item_first[item.x] + item.y;
