@@ -299,6 +299,26 @@ void launch_blk_check(const double* Racc, const int32_t* status, int32_t s, int3
     k_blk_check<<<1, kBlkRhs * kBlkRhs, 0, st>>>(Racc, status, s, kind, j, tau, bs, C, ldc, E1, mat);
 }
 
+// The Jacobi route's work matrix of the projected problem from the device
+// copies: G[i][j] = C[i][j] (m x ls, leading dimension ldc) and the data
+// columns G[i][m + k] = E1[i][k] for i < s (rows i >= s stay zero).  G is
+// zero on entry (full_reset).
+__global__ __launch_bounds__(kBlock) void k_blk_fill_g(const double* __restrict__ C, int64_t ldc, int64_t m,
+                                                       int64_t ls, const double* __restrict__ E1, int32_t s,
+                                                       double* __restrict__ G, int64_t ldg) {
+    const int64_t i = blockIdx.y;
+    const double* ci = C + i * ldc;
+    double* gi = G + i * ldg;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < ls; j += (int64_t)gridDim.x * kBlock) gi[j] = ci[j];
+    if (blockIdx.x == 0 && i < s && (int)threadIdx.x < s) gi[m + threadIdx.x] = E1[i * s + threadIdx.x];
+}
+
+void launch_blk_fill_g(const double* C, int64_t ldc, int64_t m, int64_t ls, const double* E1, int32_t s, double* G,
+                       int64_t ldg, hipStream_t st) {
+    const unsigned gx = (unsigned)((ls + kBlock - 1) / kBlock);
+    k_blk_fill_g<<<dim3(gx, (unsigned)m), kBlock, 0, st>>>(C, ldc, m, ls, E1, s, G, ldg);
+}
+
 void launch_blk_eye(double* Racc, int32_t* status, hipStream_t st) {
     k_blk_eye<<<1, kBlkRhs * kBlkRhs, 0, st>>>(Racc, status);
 }

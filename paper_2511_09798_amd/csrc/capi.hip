@@ -1675,9 +1675,9 @@ int band_projected(mqh_problem* p, const double* Cd, int64_t ldc, const double* 
 // (device, ell s x 16, row col = Y + 16 col) receives y_k in column k;
 // per-source records in po_h / iters / conv; sv (device, ell s, NULL
 // allowed) the singular values.
-int block_projected(mqh_problem* p, const std::vector<double>& C, const double* E1, int32_t s, int32_t ell,
-                    int32_t rule, int32_t J, double lambda_fixed, double* Y, double* sv, std::vector<ParamOut>& po_h,
-                    std::vector<int>& iters, std::vector<char>& conv, int32_t* sweeps) {
+int block_projected(mqh_problem* p, const double* Cd, int64_t ldcd, const double* E1d, const double* E1, int32_t s,
+                    int32_t ell, int32_t rule, int32_t J, double lambda_fixed, double* Y, double* sv,
+                    std::vector<ParamOut>& po_h, std::vector<int>& iters, std::vector<char>& conv, int32_t* sweeps) {
     hipStream_t st = p->stream;
     const int64_t m = (int64_t)(ell + 1) * s, ls = (int64_t)ell * s;
     BlockCache& bc = *p->bc;  // made by block_ws
@@ -1698,17 +1698,8 @@ int block_projected(mqh_problem* p, const std::vector<double>& C, const double* 
         }
     }
     FullRun& r = *bc.fr;
-    {
-        std::vector<double> Gh((size_t)m * (size_t)r.ldg, 0.0);
-        const int64_t ldc = ls;
-        for (int64_t i = 0; i < m; ++i) {
-            for (int64_t j = 0; j < ls; ++j) Gh[(size_t)(i * r.ldg + j)] = C[(size_t)(i * ldc + j)];
-            if (i < s)
-                for (int k = 0; k < s; ++k) Gh[(size_t)(i * r.ldg + m + k)] = E1[i * s + k];
-        }
-        HIPCHK(hipMemcpyAsync(r.G, Gh.data(), Gh.size() * sizeof(double), hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
-    }
+    launch_blk_fill_g(Cd, ldcd, m, ls, E1d, s, r.G, r.ldg, st);
+    LAUNCHCHK("block projected problem: work matrix");
     if ((rc = full_sweeps(st, r, m, s))) return rc;
     *sweeps = r.sweeps;
     if (sv) HIPCHK(hipMemcpyAsync(sv, r.sv, (size_t)ls * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -2700,17 +2691,9 @@ int mqh_solve_block(mqh_problem* p, const double* F, int64_t ldf, int32_t nrhs, 
             conv.assign((size_t)nrhs, 1);
         }
     }
-    if (!banded) {
-        // the Jacobi path takes C of the ld steps kept, (ld + 1) s x ld s, from the host
-        const size_t rows = (size_t)((ld + 1) * nrhs);
-        std::vector<double> Ck(rows * (size_t)ls);
-        HIPCHK(hipMemcpy2DAsync(Ck.data(), (size_t)ls * sizeof(double), b.Cd, (size_t)ldfull * sizeof(double),
-                                (size_t)ls * sizeof(double), rows, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if ((rc = block_projected(p, Ck, E1h, nrhs, ld, opts->rule, J, opts->lambda_fixed, Y, svd, po, iters, conv,
-                                  &sweeps)))
-            return rc;
-    }
+    if (!banded && (rc = block_projected(p, b.Cd, ldfull, b.E1d, E1h, nrhs, ld, opts->rule, J, opts->lambda_fixed, Y,
+                                         svd, po, iters, conv, &sweeps)))
+        return rc;
     const auto t3 = now();
     // coefficients Z Y (in b.P, then out)
     launch_blk_update(b.Z, ldn, n, (int32_t)ls, Y, kBlkRhs, 1, b.P, ldn, nrhs, 0, st);

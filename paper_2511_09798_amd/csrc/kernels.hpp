@@ -325,6 +325,9 @@ struct BlkState {
 };
 void launch_blk_check(const double* Racc, const int32_t* status, int32_t s, int32_t kind, int32_t j, double tau,
                       BlkState* bs, double* C, int64_t ldc, double* E1, double* mat, hipStream_t st);
+// G (zero) <- [C | (E1; 0)]: the Jacobi route's work matrix from the device copies of C and E1
+void launch_blk_fill_g(const double* C, int64_t ldc, int64_t m, int64_t ls, const double* E1, int32_t s, double* G,
+                       int64_t ldg, hipStream_t st);
 
 // Measurement helpers (peak_kernels.hip): peak_blocks() workgroups of kBlock
 // threads; the copy moves count doubles (count even, x and y 16-byte aligned).

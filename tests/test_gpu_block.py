@@ -171,6 +171,27 @@ def test_block_band_path_matches_jacobi(mq, case, blobs, nsrc, ell):
         assert np.linalg.norm(a.coef[k] - b.coef[k]) <= 1e-5 * np.linalg.norm(b.coef[k])
 
 
+@pytest.mark.parametrize("mode", ["matfree_fp32", "stored_fp64"])
+def test_block_jacobi_path_twice_in_a_row(mq, case, mode):
+    # two Jacobi-route solves of the same sizes back to back (the second reuses the cached run),
+    # device pointers as the benchmark passes them: the same bits both times
+    import torch
+
+    p, A, _ = case
+    F = torch.from_numpy(np.stack([I.random_vector(p.n, 990 + k) for k in range(16)])).to("cuda:0")
+    with _problem(mq, p, mode) as pr:
+        say("block solve, Jacobi route twice,", mode)
+        a = pr.solve_block(F, 4, jacobi=True)
+        b = pr.solve_block(F, 4, jacobi=True)
+        c = pr.solve_block(F, 4)
+    assert a.status in (0, mq.MQH_WEDGE) and b.status == a.status
+    assert np.all(a.flags & mq.MQH_INFO_BLOCK_JACOBI) and not np.any(c.flags & mq.MQH_INFO_BLOCK_JACOBI)
+    ac, bc, cc = a.coef.cpu().numpy(), b.coef.cpu().numpy(), c.coef.cpu().numpy()
+    assert np.array_equal(ac, bc)
+    for k in range(16):
+        assert np.linalg.norm(cc[k] - ac[k]) <= 1e-5 * np.linalg.norm(ac[k])
+
+
 def test_block_band_path_size_limit(mq):
     # 16 sources: 25 block steps (N = 400 columns of C) are the most the band chase holds in LDS;
     # 26 take the Jacobi path.  At 25 the two paths agree as above.
