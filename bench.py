@@ -453,9 +453,10 @@ def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, 
                block_product_ms=kern_ms,
                roofline=dict(bound="mfma", achieved=flops / (kern_ms * 1e-3) / 1e12, peak=MFMA_F32_PEAK / 1e12,
                              unit="TFLOP/s", frac=flops / (kern_ms * 1e-3) / MFMA_F32_PEAK,
-                             kernel="k_mfm_block", flops=flops,
-                             note="2 n^2 s flops per block product (the dense n x n by n x s contraction); "
-                                  "entries and squared distances are extra issue on the same SIMDs"))
+                             kernel="k_mfh_block", flops=flops,
+                             note="2 n^2 s flops per block product (the dense n x n by n x s contraction), priced against the "
+                                  "FP32 peak; it runs as FP16 split products on the matrix cores, entries and squared "
+                                  "distances are extra issue on the same SIMDs"))
     seq = []
     for k in range(min(compare, count)):
         p, h, F = probs[k], handles[k], Fs[k]

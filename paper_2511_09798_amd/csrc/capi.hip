@@ -179,8 +179,14 @@ struct MultiWs {
     double* Y = nullptr;     // product outputs, ldn each
     double* coef = nullptr;  // coefficients, ldn each
     // block products (FP32-evaluated entries): right-hand sides in the sorted
-    // node order, n x kBlkRhs FP32, and split-K partials S x kBlkRhs x ldn
+    // node order, n x kBlkRhs FP32, their split for the FP16 matrix cores
+    // (ceil(n / 4) x kBlkRhs quads), the column scales (2^14 for columns of
+    // at most unit size; per call for the products of arbitrary vectors),
+    // and split-K partials S x kBlkRhs x ldn
     float* Vg = nullptr;
+    uint4* Vh = nullptr;
+    float* vsc_unit = nullptr;
+    float* vsc_data = nullptr;
     double* PB = nullptr;
     int S_rows = 1, S_cols = 1;
     int64_t slice_rows = 0, slice_cols = 0;
@@ -225,6 +231,7 @@ struct mqh_problem {
     int32_t* iperm = nullptr;  // iperm[perm[q]] = q
     float4* frames = nullptr;
     float4* cf = nullptr;
+    double blk_tmax = 1.0;  // bound on t = 1 + |P - Q|^2 over node pairs (the block products' entry scale)
     // the single-vector FP32 products over unordered node pairs: work items,
     // their tables, and the row / column partials of a product
     SymLayout sym{};
@@ -639,6 +646,9 @@ void multi_free(MultiWs& w) {
     dfree(w.Y);
     dfree(w.coef);
     dfree(w.Vg);
+    dfree(w.Vh);
+    dfree(w.vsc_unit);
+    dfree(w.vsc_data);
     dfree(w.PB);
     w.nz_cap = 0;
     w.ell_cap = 0;
@@ -647,7 +657,7 @@ void multi_free(MultiWs& w) {
 // Slice count S and length (whole LDS chunks) of a block product aiming at
 // target_blocks workgroups.
 void block_slices(const mqh_problem* p, int ft, int64_t target_blocks, int& S, int64_t& len) {
-    const int64_t n = p->n, nb = mfm_block_blocks(n, p->n_int, ft);
+    const int64_t n = p->n, nb = mfh_block_blocks(n, p->n_int, ft);
     int64_t s = (target_blocks + nb - 1) / nb;
     if (s < 1) s = 1;
     if (s > kMaxSlices) s = kMaxSlices;
@@ -677,7 +687,9 @@ void block_shapes(mqh_problem* p, MultiWs& w) {
 int tune_block_shapes(mqh_problem* p, MultiWs& w, int nz) {
     hipStream_t s = p->stream;
     launch_fill_hash(w.Vg, p->n * kBlkRhs, s);
+    launch_split_block(w.Vg, p->n, w.vsc_unit, w.Vh, s);
     LAUNCHCHK("tuning operand");
+    const BlockEntry be = block_entry(op_ec(p), p->blk_tmax);
     struct Cand {
         int ft, S;
         int64_t len;
@@ -697,7 +709,8 @@ int tune_block_shapes(mqh_problem* p, MultiWs& w, int nz) {
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     int rc = MQH_OK;
     auto product = [&](int trans, const Cand& c) {
-        launch_mfm_block(trans, c.ft, p->XS, p->frames, w.Vg, p->n, p->n_int, c.S, c.len, op_ec(p), w.PB, p->ldn, s);
+        launch_mfh_block(trans, c.ft, p->XS, p->frames, w.Vh, w.vsc_unit, p->n, p->n_int, c.S, c.len, be, w.PB,
+                         p->ldn, s);
         launch_reduce_block(w.PB, p->ldn, c.S, p->n, nz, p->perm, nullptr, 0, nullptr, 0, w.Y, p->ldn, nullptr, s);
     };
     for (int trans = 0; trans < 2 && rc == MQH_OK; ++trans) {
@@ -771,11 +784,15 @@ int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
     if (p->mode == MQH_OP_MATFREE_FP32) {
         block_shapes(p, w);
         const int S = p->fixed_shapes ? (w.S_rows > w.S_cols ? w.S_rows : w.S_cols) : kMaxSlices;
-        if ((rc = dalloc(&w.Vg, (size_t)n * kBlkRhs)) ||
+        if ((rc = dalloc(&w.Vg, (size_t)n * kBlkRhs)) || (rc = dalloc(&w.Vh, (size_t)((n + 3) / 4) * kBlkRhs)) ||
+            (rc = dalloc(&w.vsc_unit, (size_t)kBlkRhs)) || (rc = dalloc(&w.vsc_data, (size_t)kBlkRhs)) ||
             (rc = dalloc(&w.PB, (size_t)S * kBlkRhs * (size_t)ldn))) {
             multi_free(w);
             return rc;
         }
+        launch_fill_f32(w.vsc_unit, kBlkRhs, 16384.0f, s);
+        launch_fill_f32(w.vsc_data, kBlkRhs, 1.0f, s);
+        LAUNCHCHK("block-product scales");
         if (!p->fixed_shapes) {
             if ((rc = tune_block_shapes(p, w, zc))) {
                 multi_free(w);
@@ -804,7 +821,7 @@ int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
 // sorted FP32 layout (written by the normalisation that produced X).
 int block_product(mqh_problem* p, int nz, int trans, const double* X, int64_t xstr, const double* shift,
                   int64_t sstr, const double* Zs, int64_t zstr, double* Y, const GkbState* st, bool timed,
-                  bool staged = false) {
+                  bool staged = false, bool unit = true) {
     MultiWs& w = p->mw;
     hipStream_t s = p->stream;
     if (p->mode != MQH_OP_MATFREE_FP32 || nz < 2) {
@@ -831,9 +848,14 @@ int block_product(mqh_problem* p, int nz, int trans, const double* X, int64_t xs
         HIPCHK(hipEventRecord(e0, s));
     }
     const int S = trans ? w.S_cols : w.S_rows;
-    launch_mfm_block(trans, trans ? w.ft_cols : w.ft_rows, p->XS, p->frames, w.Vg, p->n, p->n_int, S,
-                     trans ? w.slice_cols : w.slice_rows,
-                     op_ec(p), w.PB, p->ldn, s);
+    const float* vsc = w.vsc_unit;
+    if (!unit) {
+        launch_block_vscale(w.Vg, p->n, w.vsc_data, s);
+        vsc = w.vsc_data;
+    }
+    launch_split_block(w.Vg, p->n, vsc, w.Vh, s);
+    launch_mfh_block(trans, trans ? w.ft_cols : w.ft_rows, p->XS, p->frames, w.Vh, vsc, p->n, p->n_int, S,
+                     trans ? w.slice_cols : w.slice_rows, block_entry(op_ec(p), p->blk_tmax), w.PB, p->ldn, s);
     LAUNCHCHK("block product");
     if (timed) HIPCHK(hipEventRecord(e1, s));
     launch_reduce_block(w.PB, p->ldn, S, p->n, nz, p->perm, shift, sstr, Zs, zstr, Y, p->ldn, st, s);
@@ -1952,6 +1974,13 @@ int mqh_problem_create(const double* x_int, int64_t n_int, const double* x_bnd, 
                                 p->stream)))
             return bail(hip_fail(e, "upload of the sorted layout"));
         if (op_mode == MQH_OP_MATFREE_FP32) {
+            // nodes are centred, so |P - Q| <= 2 max |P|
+            double m2 = 0.0;
+            for (const auto& q : rs) {
+                const double r2 = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z;
+                m2 = r2 > m2 ? r2 : m2;
+            }
+            p->blk_tmax = (1.0 + 4.0 * m2) * (1.0 + 1e-3);
             if ((rc = dalloc(&p->XS, (size_t)n)) || (rc = dalloc(&p->frames, frames.size())) ||
                 (rc = dalloc(&p->cf, (size_t)n)))
                 return bail(rc);
@@ -2250,7 +2279,8 @@ int mqh_apply_multi(mqh_problem* p, int32_t trans, const double* X, int64_t ldx,
         if (shifts != nullptr)
             for (int k = 0; k < nz; ++k) sh[(size_t)k * (size_t)w.vstr] = shifts[k0 + k];
         HIPCHK(hipMemcpyAsync(w.alpha, sh.data(), sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        if ((rc = block_product(p, nz, trans, w.X, p->ldn, w.alpha, w.vstr, zs, w.bstr, w.Y, nullptr, false)))
+        if ((rc = block_product(p, nz, trans, w.X, p->ldn, w.alpha, w.vstr, zs, w.bstr, w.Y, nullptr, false, false,
+                                false)))
             return rc;
         HIPCHK(copy_strided(Y + (int64_t)k0 * ldy, (size_t)ldy * sizeof(double), w.Y,
                                 (size_t)p->ldn * sizeof(double), (size_t)p->n * sizeof(double), (size_t)nz,

@@ -89,11 +89,23 @@ void launch_mfs_reduce(const SymLayout& L, const double* RowP, const double* Col
                        const double* shift_ptr, double shift_val, const double* z, double* y, const GkbState* st,
                        hipStream_t s);
 // Block products over blocks of 64 ft fixed nodes (ft = 1 or 2: fixed tiles of
-// 16 per wave); mfm_block_blocks gives the grid's block count.
-int64_t mfm_block_blocks(int64_t n, int64_t n_int, int ft);
-void launch_mfm_block(int trans, int ft, const float4* XS, const float4* frames, const float* Vg, int64_t n,
-                      int64_t n_int, int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp,
-                      hipStream_t s);
+// 16 per wave); mfh_block_blocks gives the grid's block count.  Vh: the
+// right-hand sides split for the FP16 matrix cores by launch_split_block
+// (vsc: the power-of-two scale of each column, launch_block_vscale or 2^14
+// for columns of at most unit size); block_entry: the entry constants scaled
+// by 2^se so that no entry of a problem whose squared distances stay below
+// tmax exceeds 2^14, and 2^-se.
+struct BlockEntry {
+    float k2, e2x2, e2, bsc;  // interior constants times 2^se, 2^se for the boundary entries
+    double unscale;           // 2^-se
+};
+BlockEntry block_entry(const EntryConst& c, double tmax);
+int64_t mfh_block_blocks(int64_t n, int64_t n_int, int ft);
+void launch_mfh_block(int trans, int ft, const float4* XS, const float4* frames, const uint4* Vh, const float* vsc,
+                      int64_t n, int64_t n_int, int S, int64_t slice_len, const BlockEntry& c, double* P,
+                      int64_t ldp, hipStream_t s);
+void launch_split_block(const float* Vg, int64_t n, const float* vsc, uint4* Vh, hipStream_t s);
+void launch_block_vscale(const float* Vg, int64_t n, float* vsc, hipStream_t s);
 void launch_fill_hash(float* Vg, int64_t count, hipStream_t s);
 void launch_gather_block(const double* X, int64_t ldx, int nrhs, const int32_t* perm, int64_t n,
                          const GkbState* st, float* Vg, hipStream_t s);

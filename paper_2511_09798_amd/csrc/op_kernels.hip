@@ -680,37 +680,76 @@ __global__ __launch_bounds__(kBlock) void k_gather_coef(const double* __restrict
 // ---------------------------------------------------------------------------
 // Block products for kBlkRhs right-hand sides at once (lockstep Golub-Kahan
 // runs sharing each pass over A): P[slice][k][q] = sum over the slice's loop
-// nodes j of A(q, j) V[j][k] (rows) or A(j, q) V[j][k] (columns), V the
-// kBlkRhs vectors in FP32, sorted node order.
+// nodes j of A(q, j) v_k[j] (rows) or A(j, q) v_k[j] (columns), in sorted
+// node order.
 //
 // Per 16 x 16 tile the squared distances come from the same bf16x3 MFMA as
-// in the pair products with the operands swapped (A = loop nodes, B = fixed nodes), so a
-// lane holds t for 4 loop nodes j = 4g + r and one fixed node; the lane
-// evaluates the (unweighted) entries and they enter, as they are, the A
-// operand of four v_mfma_f32_16x16x4_f32 against the staged right-hand sides
-// (K = the 4 loop nodes {r, 4 + r, 8 + r, 12 + r}): the contraction
-// E (16 fixed x 16 loop) V (16 loop x 16 rhs) on the matrix cores, FP32,
-// summed over the 256 loop nodes of a chunk, then added in FP64.  Each lane
-// ends with its own outputs (4 fixed nodes x 1 right-hand side).
+// in the pair products with the operands swapped (A = loop nodes, B = fixed
+// nodes), so a lane holds t for 4 loop nodes j = 4g + r and one fixed node.
+// The contraction E (16 fixed x 16 loop) V (16 loop x 16 rhs) runs on the
+// matrix cores in FP16 with both operands split in two: the entries, scaled
+// by 2^se, as e = e_h + e_l (e_h = fp16(e) to nearest, e_l = fp16(e - e_h)),
+// the right-hand sides, each column scaled by its own power of two, as v =
+// v_h + v_l alike, and E V ~ E_h V_h + E_h V_l + E_l V_h: one
+// v_mfma_f32_16x16x32_f16 for the first two (a lane group's 8 K slots: its
+// 4 loop nodes against v_h, then against v_l) and one
+// v_mfma_f32_16x16x16_f16 for the third.  e_h + e_l keeps e to 2^-22
+// relative (the FP32 entries carry an error of that order from their rsqrt
+// already), and the dropped E_l V_l is below 2^-22 |e v|.  Products of two
+// fp16 values are exact in FP32; sums are FP32 over one 256-node chunk,
+// FP64 across chunks and slices, and the scales are taken out exactly in
+// FP64.  On this GPU the FP32 matrix instructions do not overlap VALU work
+// while the FP16 ones largely do: four v_mfma_f32_16x16x4_f32 per tile
+// (128 cycles, exposed) become two FP16 ones (24 cycles, mostly hidden)
+// and 12 VALU instructions for the split of 4 entries.
 // ---------------------------------------------------------------------------
 
-constexpr int kBlkVs = kBlkRhs + 4;  // LDS row of the staged right-hand sides (padded against bank conflicts)
+typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
-// Entries of the lane's 4 loop nodes x kMfmFt fixed nodes from their
-// squared distances t (unweighted; INTERIOR selects the formula).
-template <bool INTERIOR, int FT>
-__device__ __forceinline__ void block_entries(const v4f (&t)[FT], const EntryConst& c, float (&e)[FT][4]) {
+constexpr float kBlkRange = 16384.0f;  // scaled entries and right-hand sides stay below this (fp16 max 65504)
+
+// Two FP32 values as fp16 pairs: H = (fp16(a), fp16(b)) rounded to nearest,
+// L = the same of the remainders a - H.lo, b - H.hi (exact in FP32).
+__device__ __forceinline__ void split_f16x2(float a, float b, unsigned& H, unsigned& L) {
+    const v2h h = __builtin_convertvector((v2f){a, b}, v2h);
+    const v2h l = __builtin_convertvector((v2f){a - (float)h[0], b - (float)h[1]}, v2h);
+    H = __builtin_bit_cast(unsigned, h);
+    L = __builtin_bit_cast(unsigned, l);
+}
+
+// Entries of the lane's 4 loop nodes x FT fixed nodes from their squared
+// distances, scaled by 2^se, split into (H01, H23, L01, L23).  MIX = 1: the
+// interior formula, 0: the boundary one, 2: by the loop node's class
+// (node jb + r interior when below n_int; the chunk of a column product that
+// straddles the classes).
+template <int MIX, int FT>
+__device__ __forceinline__ void block_split(const v4f (&t)[FT], const BlockEntry& c, int64_t jb, int64_t n_int,
+                                            unsigned (&h)[FT][4]) {
 #pragma unroll
-    for (int f = 0; f < FT; ++f)
+    for (int f = 0; f < FT; ++f) {
+        float e[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            if (INTERIOR) {
-                const float sv = __builtin_amdgcn_rsqf(t[f][r]);
-                e[f][r] = fmaf(c.e2f, sv * sv, fmaf(c.k2f, t[f][r], c.e2x2f)) * sv;
+            const float tt = t[f][r];
+            if (MIX == 1) {
+                const float sv = __builtin_amdgcn_rsqf(tt);
+                e[r] = fmaf(c.e2, sv * sv, fmaf(c.k2, tt, c.e2x2)) * sv;
+            } else if (MIX == 0) {
+                e[r] = __builtin_amdgcn_sqrtf(tt) * c.bsc;
             } else {
-                e[f][r] = __builtin_amdgcn_sqrtf(t[f][r]);
+                const float sv = __builtin_amdgcn_rsqf(tt);
+                const float ei = fmaf(c.e2, sv * sv, fmaf(c.k2, tt, c.e2x2)) * sv;
+                const float eb = tt * sv * c.bsc;
+                e[r] = jb + r < n_int ? ei : eb;
             }
         }
+        split_f16x2(e[0], e[1], h[f][0], h[f][2]);
+        split_f16x2(e[2], e[3], h[f][1], h[f][3]);
+    }
 }
 
 // Squared distances of tile u (16 staged loop nodes) to the lane's fixed nodes.
@@ -723,32 +762,80 @@ __device__ __forceinline__ void block_tdist(const v4u* __restrict__ lds_a, int u
         t[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ak, __builtin_bit_cast(v8bf, bf[f]), Cf[f], 0, 0, 0);
 }
 
-// One slice [j0, j1) of loop nodes (block-uniform; contains barriers).  The
-// chunk's 16 tiles run as a three-stage pipeline, fully unrolled: the
-// squared distances of tile u + 2, the entries of tile u + 1 and the
-// contraction of tile u are in flight together, so no stage waits on the
-// one before it.
-template <bool INTERIOR, int FT>
-__device__ __forceinline__ void mfb_span(const float4* __restrict__ XS, const float* __restrict__ Vg, int64_t j0,
-                                         int64_t j1, const float4& fr, const EntryConst& c, const v4u (&bf)[FT],
-                                         const v4f (&Cf)[FT], double (&acc)[FT][4], v4u* __restrict__ lds_a,
-                                         float* __restrict__ lds_v) {
+// The 16 staged tiles of one chunk (first loop node t0) against the lane's
+// fixed tiles, as a three-stage pipeline, fully unrolled: the squared
+// distances of tile u + 2, the entries and their split of tile u + 1 and
+// the contraction of tile u are in flight together.
+template <int MIX, int FT>
+__device__ __forceinline__ void mfh_chunk(const v4u* __restrict__ lds_a, const uint4* __restrict__ lds_v, int64_t t0,
+                                          int64_t n_int, const BlockEntry& c, const v4u (&bf)[FT],
+                                          const v4f (&Cf)[FT], double (&acc)[FT][4]) {
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15;
     constexpr int kTiles = kMfmChunk / 16;
+    // one accumulator per instruction shape: each chain feeds its own result
+    // back as C, the case the matrix cores forward without waiting; a
+    // 16x16x16 reading the fresh result of a 16x16x32 as C is not
+    v4f dh[FT], dl[FT];
+#pragma unroll
+    for (int f = 0; f < FT; ++f) {
+        dh[f] = v4f{0.f, 0.f, 0.f, 0.f};
+        dl[f] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    v4f tc[FT], tn[FT];
+    unsigned hc[FT][4];
+    block_tdist<FT>(lds_a, 0, jj, g, bf, Cf, tc);
+    block_tdist<FT>(lds_a, 1, jj, g, bf, Cf, tn);
+    block_split<MIX, FT>(tc, c, t0 + 4 * g, n_int, hc);
+#pragma unroll
+    for (int u = 0; u < kTiles; ++u) {
+        // the lane group's 4 loop nodes, split, for right-hand side jj
+        const uint4 bv = lds_v[(u * 4 + g) * kBlkRhs + jj];
+        v4f tnn[FT];
+        if (u + 2 < kTiles) block_tdist<FT>(lds_a, u + 2, jj, g, bf, Cf, tnn);
+        unsigned hn[FT][4];
+        if (u + 1 < kTiles) block_split<MIX, FT>(tn, c, t0 + (u + 1) * 16 + 4 * g, n_int, hn);
+        const v4u b32 = {bv.x, bv.y, bv.z, bv.w};
+        const v2u b16 = {bv.x, bv.y};
+#pragma unroll
+        for (int f = 0; f < FT; ++f) {
+            const v4u a32 = {hc[f][0], hc[f][1], hc[f][0], hc[f][1]};
+            const v2u a16 = {hc[f][2], hc[f][3]};
+            dh[f] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a32), __builtin_bit_cast(v8h, b32),
+                                                           dh[f], 0, 0, 0);
+            dl[f] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, a16), __builtin_bit_cast(v4h, b16),
+                                                          dl[f], 0, 0, 0);
+        }
+        if (u + 1 < kTiles) {
+#pragma unroll
+            for (int f = 0; f < FT; ++f) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) hc[f][q] = hn[f][q];
+                tn[f] = tnn[f];
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < FT; ++f)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[f][r] += (double)dh[f][r] + (double)dl[f][r];
+}
+
+// One slice [j0, j1) of loop nodes (block-uniform; contains barriers; j0 a
+// multiple of kMfmChunk).  ROWS: the fixed nodes' class (fint) picks the
+// formula; columns: each chunk's loop nodes do.
+template <bool ROWS, int FT>
+__device__ __forceinline__ void mfh_span(const float4* __restrict__ XS, const uint4* __restrict__ Vh, int64_t j0,
+                                         int64_t j1, int64_t n_int, bool fint, const float4& fr, const BlockEntry& c,
+                                         const v4u (&bf)[FT], const v4f (&Cf)[FT], double (&acc)[FT][4],
+                                         v4u* __restrict__ lds_a, uint4* __restrict__ lds_v) {
     for (int64_t t0 = j0; t0 < j1; t0 += kMfmChunk) {
         const int64_t j = t0 + threadIdx.x;
         float dx = 0.f, dy = 0.f, dz = 0.f;
-        float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0, v2 = v0, v3 = v0;
         if (j < j1) {
             const float4 q = XS[j];
             dx = q.x - fr.x;
             dy = q.y - fr.y;
             dz = q.z - fr.z;
-            const float4* vr = reinterpret_cast<const float4*>(Vg + j * kBlkRhs);
-            v0 = vr[0];
-            v1 = vr[1];
-            v2 = vr[2];
-            v3 = vr[3];
         }
         const v4u a0 = loop_terms(dx), a1 = loop_terms(dy), a2 = loop_terms(dz);
         unsigned h, m, l;
@@ -758,63 +845,42 @@ __device__ __forceinline__ void mfb_span(const float4* __restrict__ XS, const fl
         a3[1] = l >> 16;
         a3[2] = 0u;
         a3[3] = 0u;
+        // the chunk's split right-hand sides: kMfmChunk / 4 quads x kBlkRhs
+        // (a quad past j1 lies past n, where Vh holds zeros, or in the next
+        // slice, which starts at a multiple of kMfmChunk: none is read)
+        uint4 vq[4];
+#pragma unroll
+        for (int m4 = 0; m4 < 4; ++m4) {
+            const int i = threadIdx.x + m4 * kBlock;
+            const int64_t node = t0 + 4 * (i / kBlkRhs);
+            vq[m4] = node < j1 ? Vh[((t0 >> 2) + i / kBlkRhs) * kBlkRhs + (i % kBlkRhs)] : make_uint4(0u, 0u, 0u, 0u);
+        }
         __syncthreads();  // the previous chunk has been consumed
         lds_a[threadIdx.x * 4 + 0] = a0;
         lds_a[threadIdx.x * 4 + 1] = a1;
         lds_a[threadIdx.x * 4 + 2] = a2;
         lds_a[threadIdx.x * 4 + 3] = a3;
-        float4* vrow = reinterpret_cast<float4*>(lds_v + threadIdx.x * kBlkVs);
-        vrow[0] = v0;
-        vrow[1] = v1;
-        vrow[2] = v2;
-        vrow[3] = v3;
+#pragma unroll
+        for (int m4 = 0; m4 < 4; ++m4) lds_v[threadIdx.x + m4 * kBlock] = vq[m4];
         __syncthreads();
-        v4f d2[FT];
-#pragma unroll
-        for (int f = 0; f < FT; ++f) d2[f] = v4f{0.f, 0.f, 0.f, 0.f};
-        v4f tc[FT], tn[FT];
-        float ec[FT][4];
-        block_tdist<FT>(lds_a, 0, jj, g, bf, Cf, tc);
-        block_tdist<FT>(lds_a, 1, jj, g, bf, Cf, tn);
-        block_entries<INTERIOR, FT>(tc, c, ec);
-#pragma unroll
-        for (int u = 0; u < kTiles; ++u) {
-            float vb[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) vb[r] = lds_v[(u * 16 + 4 * g + r) * kBlkVs + jj];
-            v4f tnn[FT];
-            if (u + 2 < kTiles) block_tdist<FT>(lds_a, u + 2, jj, g, bf, Cf, tnn);
-            float en[FT][4];
-            if (u + 1 < kTiles) block_entries<INTERIOR, FT>(tn, c, en);
-            // the entries enter the A operand as they are: K = loop nodes r, 4 + r, 8 + r, 12 + r
-#pragma unroll
-            for (int f = 0; f < FT; ++f)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    d2[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(ec[f][r], vb[r], d2[f], 0, 0, 0);
-            if (u + 1 < kTiles) {
-#pragma unroll
-                for (int f = 0; f < FT; ++f) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) ec[f][r] = en[f][r];
-                    tn[f] = tnn[f];
-                }
-            }
-        }
-#pragma unroll
-        for (int f = 0; f < FT; ++f)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[f][r] += (double)d2[f][r];
+        const int64_t cend = t0 + kMfmChunk < j1 ? t0 + kMfmChunk : j1;
+        if (ROWS ? fint : cend <= n_int)
+            mfh_chunk<1, FT>(lds_a, lds_v, t0, n_int, c, bf, Cf, acc);
+        else if (ROWS || t0 >= n_int)
+            mfh_chunk<0, FT>(lds_a, lds_v, t0, n_int, c, bf, Cf, acc);
+        else
+            mfh_chunk<2, FT>(lds_a, lds_v, t0, n_int, c, bf, Cf, acc);
     }
 }
 
 template <bool ROWS, int FT>
-__global__ __launch_bounds__(kBlock) void k_mfm_block(const float4* __restrict__ XS, const float* __restrict__ Vg,
-                                                      int64_t n, int64_t n_int, int64_t nb_int, int64_t slice_len,
-                                                      const float4* __restrict__ frames, EntryConst c,
+__global__ __launch_bounds__(kBlock) void k_mfh_block(const float4* __restrict__ XS, const uint4* __restrict__ Vh,
+                                                      const float* __restrict__ vsc, int64_t n, int64_t n_int,
+                                                      int64_t nb_int, int64_t slice_len,
+                                                      const float4* __restrict__ frames, BlockEntry c,
                                                       double* __restrict__ P, int64_t ldp) {
     __shared__ v4u lds_a[4 * kMfmChunk];
-    __shared__ float lds_v[kMfmChunk * kBlkVs];
+    __shared__ uint4 lds_v[(kMfmChunk / 4) * kBlkRhs];
     // blocks of kFix = 64 FT fixed nodes per class; the frame is that of the
     // kMfmFixed-node block holding the first of them
     constexpr int kFix = (kBlock / kWave) * FT * 16;
@@ -855,24 +921,71 @@ __global__ __launch_bounds__(kBlock) void k_mfm_block(const float4* __restrict__
     }
     const int64_t j0 = (int64_t)blockIdx.y * slice_len;
     const int64_t j1 = j0 + slice_len < n ? j0 + slice_len : n;
-    if (ROWS) {
-        if (fint)
-            mfb_span<true, FT>(XS, Vg, j0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
-        else
-            mfb_span<false, FT>(XS, Vg, j0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
-    } else {
-        const int64_t m1 = j1 < n_int ? j1 : n_int;
-        if (j0 < m1) mfb_span<true, FT>(XS, Vg, j0, m1, fr, c, bf, Cf, acc, lds_a, lds_v);
-        const int64_t m0 = j0 > n_int ? j0 : n_int;
-        if (m0 < j1) mfb_span<false, FT>(XS, Vg, m0, j1, fr, c, bf, Cf, acc, lds_a, lds_v);
-    }
+    mfh_span<ROWS, FT>(XS, Vh, j0, j1, n_int, fint, fr, c, bf, Cf, acc, lds_a, lds_v);
+    // the scales out: 2^-se of the entries and the column's own
+    const double un = c.unscale / (double)vsc[jj];
 #pragma unroll
     for (int f = 0; f < FT; ++f) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t i = fb0 + (int64_t)(wv * FT + f) * 16 + 4 * g + r;
-            if (i < fb1) P[((int64_t)blockIdx.y * kBlkRhs + jj) * ldp + i] = acc[f][r];
+            if (i < fb1) P[((int64_t)blockIdx.y * kBlkRhs + jj) * ldp + i] = acc[f][r] * un;
         }
+    }
+}
+
+// Vh[q][k] = the split of the scaled values vsc[k] Vg[4q + r][k], r = 0..3
+// (zeros past n): (H01, H23, L01, L23), fp16 pairs as in split_f16x2.
+// Values beyond the scaled range are clamped to it (NaN stays NaN); the
+// block products only receive such values from steps whose results are
+// discarded (after a breakdown), the unit-norm operands of the Golub-Kahan
+// runs stay within it by construction.
+__global__ __launch_bounds__(kBlock) void k_split_block(const float* __restrict__ Vg, int64_t n,
+                                                        const float* __restrict__ vsc, uint4* __restrict__ Vh) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t nq = (n + 3) / 4;
+    if (e >= nq * kBlkRhs) return;
+    const int64_t q = e / kBlkRhs;
+    const int k = (int)(e % kBlkRhs);
+    const float sc = vsc[k];
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int64_t j = 4 * q + r;
+        float x = j < n ? Vg[j * kBlkRhs + k] * sc : 0.f;
+        if (__builtin_isfinite(x) && fabsf(x) > kBlkRange) x = copysignf(kBlkRange, x);
+        v[r] = x;
+    }
+    uint4 o;
+    split_f16x2(v[0], v[1], o.x, o.z);
+    split_f16x2(v[2], v[3], o.y, o.w);
+    Vh[e] = o;
+}
+
+// vsc[k] = 2^(14 - e_k) with max_j |Vg[j][k]| < 2^e_k (1 for a zero column):
+// column k scaled below kBlkRange.  One workgroup per column.
+__global__ __launch_bounds__(kBlock) void k_block_vscale(const float* __restrict__ Vg, int64_t n,
+                                                         float* __restrict__ vsc) {
+    __shared__ float red[kBlock / kWave];
+    const int k = blockIdx.x;
+    float m = 0.f;
+    for (int64_t j = threadIdx.x; j < n; j += kBlock) m = fmaxf(m, fabsf(Vg[j * kBlkRhs + k]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float mm = 0.f;
+        for (int w = 0; w < kBlock / kWave; ++w) mm = fmaxf(mm, red[w]);
+        float s = 1.f;
+        if (mm > 0.f) {
+            int ex;
+            (void)frexpf(mm, &ex);
+            int p = 14 - ex;
+            p = p > 126 ? 126 : (p < -126 ? -126 : p);
+            s = ldexpf(1.f, p);
+        }
+        vsc[k] = s;
     }
 }
 
@@ -1008,28 +1121,58 @@ void launch_mfs_reduce(const SymLayout& L, const double* RowP, const double* Col
                                                                           z, y, st);
 }
 
-int64_t mfm_block_blocks(int64_t n, int64_t n_int, int ft) {
+int64_t mfh_block_blocks(int64_t n, int64_t n_int, int ft) {
     const int64_t fix = (kBlock / kWave) * ft * 16;
     return (n_int + fix - 1) / fix + (n - n_int + fix - 1) / fix;
 }
 
-void launch_mfm_block(int trans, int ft, const float4* XS, const float4* frames, const float* Vg, int64_t n,
-                      int64_t n_int, int S, int64_t slice_len, const EntryConst& c, double* P, int64_t ldp,
-                      hipStream_t s) {
+BlockEntry block_entry(const EntryConst& c, double tmax) {
+    // every term of the interior entry (kappa^2 t + 2 eps^2 + eps^2 s^2) s is
+    // positive and at most kappa^2 sqrt(tmax), 2 eps^2, eps^2 (s <= 1); the
+    // boundary entry sqrt(t) is at most sqrt(tmax)
+    const double st = sqrt(tmax > 1.0 ? tmax : 1.0);
+    double bound = fabs((double)c.k2f) * st + fabs((double)c.e2x2f) + fabs((double)c.e2f);
+    if (st > bound) bound = st;
+    int ex = 0;
+    (void)frexp(bound, &ex);  // bound < 2^ex
+    int se = 14 - ex;
+    se = se > 60 ? 60 : (se < -60 ? -60 : se);
+    BlockEntry b{};
+    b.k2 = ldexpf(c.k2f, se);
+    b.e2x2 = ldexpf(c.e2x2f, se);
+    b.e2 = ldexpf(c.e2f, se);
+    b.bsc = ldexpf(1.0f, se);
+    b.unscale = ldexp(1.0, -se);
+    return b;
+}
+
+void launch_mfh_block(int trans, int ft, const float4* XS, const float4* frames, const uint4* Vh, const float* vsc,
+                      int64_t n, int64_t n_int, int S, int64_t slice_len, const BlockEntry& c, double* P,
+                      int64_t ldp, hipStream_t s) {
     const int64_t fix = (kBlock / kWave) * ft * 16;
     const int64_t nb_int = (n_int + fix - 1) / fix;
-    dim3 grid((unsigned)mfm_block_blocks(n, n_int, ft), (unsigned)S);
+    dim3 grid((unsigned)mfh_block_blocks(n, n_int, ft), (unsigned)S);
     if (ft == 1) {
         if (trans)
-            k_mfm_block<false, 1><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+            k_mfh_block<false, 1><<<grid, kBlock, 0, s>>>(XS, Vh, vsc, n, n_int, nb_int, slice_len, frames, c, P, ldp);
         else
-            k_mfm_block<true, 1><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+            k_mfh_block<true, 1><<<grid, kBlock, 0, s>>>(XS, Vh, vsc, n, n_int, nb_int, slice_len, frames, c, P, ldp);
     } else {
         if (trans)
-            k_mfm_block<false, 2><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+            k_mfh_block<false, 2><<<grid, kBlock, 0, s>>>(XS, Vh, vsc, n, n_int, nb_int, slice_len, frames, c, P, ldp);
         else
-            k_mfm_block<true, 2><<<grid, kBlock, 0, s>>>(XS, Vg, n, n_int, nb_int, slice_len, frames, c, P, ldp);
+            k_mfh_block<true, 2><<<grid, kBlock, 0, s>>>(XS, Vh, vsc, n, n_int, nb_int, slice_len, frames, c, P, ldp);
     }
+}
+
+void launch_split_block(const float* Vg, int64_t n, const float* vsc, uint4* Vh, hipStream_t s) {
+    const int64_t cnt = (n + 3) / 4 * kBlkRhs;
+    if (cnt <= 0) return;
+    k_split_block<<<(unsigned)((cnt + kBlock - 1) / kBlock), kBlock, 0, s>>>(Vg, n, vsc, Vh);
+}
+
+void launch_block_vscale(const float* Vg, int64_t n, float* vsc, hipStream_t s) {
+    k_block_vscale<<<kBlkRhs, kBlock, 0, s>>>(Vg, n, vsc);
 }
 
 void launch_fill_hash(float* Vg, int64_t count, hipStream_t s) {

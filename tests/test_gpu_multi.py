@@ -9,11 +9,13 @@ Tolerances:
 * FP64 forms and groups of one: the multi path performs, per run, exactly
   the operations of the single-run path (same kernels, same reduction
   orders), so its outputs are compared bit for bit with mqh_gkb / mqh_solve.
-* Block products (FP32-evaluated entries, FP32 matrix-core products, FP32
-  sums over one 256-node chunk, FP64 across chunks and slices):
-  |dy_i| <= 4e-6 (|A||x|)_i against the oracle, the bar of the single FP32
-  product (entries to ~1e-6 relative; a 256-term FP32 sum adds at most
-  ~256 u32 / 2 of its absolute sum in the worst case, ~1e-6 typically).
+* Block products (FP32-evaluated entries; the contraction on the matrix
+  cores with entries and vectors each split into two fp16 parts, 2^-22
+  relative, products exact in FP32; FP32 sums over one 256-node chunk,
+  FP64 across chunks and slices): |dy_i| <= 4e-6 (|A||x|)_i against the
+  oracle, the bar of the single FP32 product (entries to ~1e-6 relative; a
+  256-term FP32 sum adds at most ~256 u32 / 2 of its absolute sum in the
+  worst case, ~1e-6 typically).
 * Golub-Kahan scalars with FP32 entries: leading Ritz values to 1e-5
   relative, bases orthonormal to 1e-12 (reorthogonalisation stays FP64).
 * Runs in a group do not interact: a run's outputs are bit-identical
