@@ -690,18 +690,16 @@ __global__ __launch_bounds__(kBlock) void k_gather_coef(const double* __restrict
 // matrix cores in FP16 with both operands split in two: the entries, scaled
 // by 2^se, as e = e_h + e_l (e_h = fp16(e) to nearest, e_l = fp16(e - e_h)),
 // the right-hand sides, each column scaled by its own power of two, as v =
-// v_h + v_l alike, and E V ~ E_h V_h + E_h V_l + E_l V_h: one
-// v_mfma_f32_16x16x32_f16 for the first two (a lane group's 8 K slots: its
-// 4 loop nodes against v_h, then against v_l) and one
-// v_mfma_f32_16x16x16_f16 for the third.  e_h + e_l keeps e to 2^-22
+// v_h + v_l alike, and E V ~ E_h V_h + E_l V_h + E_h V_l: three
+// v_mfma_f32_16x16x16_f16 (a lane group's 4 K slots are its 4 loop nodes).  e_h + e_l keeps e to 2^-22
 // relative (the FP32 entries carry an error of that order from their rsqrt
 // already), and the dropped E_l V_l is below 2^-22 |e v|.  Products of two
 // fp16 values are exact in FP32; sums are FP32 over one 256-node chunk,
 // FP64 across chunks and slices, and the scales are taken out exactly in
 // FP64.  On this GPU the FP32 matrix instructions do not overlap VALU work
 // while the FP16 ones largely do: four v_mfma_f32_16x16x4_f32 per tile
-// (128 cycles, exposed) become two FP16 ones (24 cycles, mostly hidden)
-// and 12 VALU instructions for the split of 4 entries.
+// (128 cycles, exposed) become three FP16 ones (24 cycles, mostly hidden)
+// and 8 VALU instructions for the split of 4 entries.
 // ---------------------------------------------------------------------------
 
 typedef _Float16 v2h __attribute__((ext_vector_type(2)));
@@ -772,15 +770,12 @@ __device__ __forceinline__ void mfh_chunk(const v4u* __restrict__ lds_a, const u
                                           const v4f (&Cf)[FT], double (&acc)[FT][4]) {
     const int lane = threadIdx.x & (kWave - 1), g = lane >> 4, jj = lane & 15;
     constexpr int kTiles = kMfmChunk / 16;
-    // one accumulator per instruction shape: each chain feeds its own result
-    // back as C, the case the matrix cores forward without waiting; a
-    // 16x16x16 reading the fresh result of a 16x16x32 as C is not
-    v4f dh[FT], dl[FT];
+    // one instruction shape on each accumulator: a chain feeding its own
+    // result back as C is the case the matrix cores forward without waiting
+    // (a 16x16x16 reading the fresh result of a 16x16x32 as C is not)
+    v4f d2[FT];
 #pragma unroll
-    for (int f = 0; f < FT; ++f) {
-        dh[f] = v4f{0.f, 0.f, 0.f, 0.f};
-        dl[f] = v4f{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int f = 0; f < FT; ++f) d2[f] = v4f{0.f, 0.f, 0.f, 0.f};
     v4f tc[FT], tn[FT];
     unsigned hc[FT][4];
     block_tdist<FT>(lds_a, 0, jj, g, bf, Cf, tc);
@@ -794,16 +789,17 @@ __device__ __forceinline__ void mfh_chunk(const v4u* __restrict__ lds_a, const u
         if (u + 2 < kTiles) block_tdist<FT>(lds_a, u + 2, jj, g, bf, Cf, tnn);
         unsigned hn[FT][4];
         if (u + 1 < kTiles) block_split<MIX, FT>(tn, c, t0 + (u + 1) * 16 + 4 * g, n_int, hn);
-        const v4u b32 = {bv.x, bv.y, bv.z, bv.w};
-        const v2u b16 = {bv.x, bv.y};
+        // the lane group's 4 loop nodes in the K slots: e_h v_h, e_l v_h, e_h v_l
+        const v2u vhi = {bv.x, bv.y}, vlo = {bv.z, bv.w};
 #pragma unroll
         for (int f = 0; f < FT; ++f) {
-            const v4u a32 = {hc[f][0], hc[f][1], hc[f][0], hc[f][1]};
-            const v2u a16 = {hc[f][2], hc[f][3]};
-            dh[f] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a32), __builtin_bit_cast(v8h, b32),
-                                                           dh[f], 0, 0, 0);
-            dl[f] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, a16), __builtin_bit_cast(v4h, b16),
-                                                          dl[f], 0, 0, 0);
+            const v2u ehi = {hc[f][0], hc[f][1]}, elo = {hc[f][2], hc[f][3]};
+            d2[f] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, ehi), __builtin_bit_cast(v4h, vhi),
+                                                          d2[f], 0, 0, 0);
+            d2[f] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, elo), __builtin_bit_cast(v4h, vhi),
+                                                          d2[f], 0, 0, 0);
+            d2[f] = __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, ehi), __builtin_bit_cast(v4h, vlo),
+                                                          d2[f], 0, 0, 0);
         }
         if (u + 1 < kTiles) {
 #pragma unroll
@@ -817,7 +813,7 @@ __device__ __forceinline__ void mfh_chunk(const v4u* __restrict__ lds_a, const u
 #pragma unroll
     for (int f = 0; f < FT; ++f)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[f][r] += (double)dh[f][r] + (double)dl[f][r];
+        for (int r = 0; r < 4; ++r) acc[f][r] += (double)d2[f][r];
 }
 
 // One slice [j0, j1) of loop nodes (block-uniform; contains barriers; j0 a
@@ -921,7 +917,11 @@ __global__ __launch_bounds__(kBlock) void k_mfh_block(const float4* __restrict__
     }
     const int64_t j0 = (int64_t)blockIdx.y * slice_len;
     const int64_t j1 = j0 + slice_len < n ? j0 + slice_len : n;
-    mfh_span<ROWS, FT>(XS, Vh, j0, j1, n_int, fint, fr, c, bf, Cf, acc, lds_a, lds_v);
+    // the entry constants in vector registers: an FP32 instruction with a
+    // scalar operand does not pair with another in one issue cycle
+    BlockEntry cv = c;
+    asm volatile("" : "+v"(cv.k2), "+v"(cv.e2x2), "+v"(cv.e2), "+v"(cv.bsc));
+    mfh_span<ROWS, FT>(XS, Vh, j0, j1, n_int, fint, fr, cv, bf, Cf, acc, lds_a, lds_v);
     // the scales out: 2^-se of the entries and the column's own
     const double un = c.unscale / (double)vsc[jj];
 #pragma unroll
