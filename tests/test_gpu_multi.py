@@ -345,3 +345,55 @@ def test_fixed_shapes_against_oracle(mq, orc):
             Aop = A.T if trans else A
             err = np.abs(Y.T - Aop @ X.T) / (np.abs(Aop) @ np.abs(X.T))
             assert np.all(err <= 4e-6), float(err.max())
+
+
+# the block products' FP16 split: each column carries its own power-of-two scale, the entries one
+# per problem (from a bound on the largest entry), so the bar holds whatever the columns' sizes and
+# wherever the class boundary and the end of the node range fall within the 4-node quads
+@pytest.mark.parametrize("n_int,n_bnd", [(5, 3), (13, 10), (61, 66), (258, 131)])
+def test_apply_multi_tiny_and_unaligned(mq, orc, n_int, n_bnd):
+    p = I.multi_cube(n_int, n_bnd, 9.0, 3.0, 3, 5, seed=n_int)
+    rng = np.random.default_rng(n_bnd)
+    X = rng.standard_normal((3, p.n))
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        for trans in (False, True):
+            say("tiny / unaligned", n_int, n_bnd, "trans", trans)
+            Y = pr.apply_multi(X, trans=trans)
+            Aop = A.T if trans else A
+            err = np.abs(Y.T - Aop @ X.T) / (np.abs(Aop) @ np.abs(X.T))
+            assert np.all(err <= 4e-6), float(err.max())
+
+
+def test_apply_multi_column_scales(mq, orc):
+    # columns from 1e-30 to 1e30 in one call, one of them zero, another with a single nonzero entry
+    p = I.multi_cube(700, 300, 12.0, 4.0, 6, 10, seed=4)
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((6, p.n)) * np.array([1e-30, 1e-8, 1.0, 1e12, 1e30, 0.0])[:, None]
+    X[5, 17] = 3.0
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        for trans in (False, True):
+            say("column scales, trans", trans)
+            Y = pr.apply_multi(X, trans=trans)
+            Aop = A.T if trans else A
+            err = np.abs(Y.T - Aop @ X.T) / (np.abs(Aop) @ np.abs(X.T))
+            assert np.all(err <= 4e-6), float(err.max())
+
+
+def test_apply_multi_row_scaled_against_oracle(mq, orc):
+    # D A (D = diag(A)^-1) through the block products: the interior constants shrink, the entry
+    # scale follows them
+    p = I.multi_cube(333, 190, 20.0, 5.0, 4, 10, seed=8)
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((4, p.n))
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    d = orc.row_scale(p.nodes, p.n_int, p.kappa, p.eps)
+    DA = d[:, None] * A
+    with _problem(mq, p, "matfree_fp32") as pr:
+        for trans in (False, True):
+            say("row scaled block product, trans", trans)
+            Y = pr.apply_multi(X, trans=trans, row_scale=1)
+            Aop = DA.T if trans else DA
+            err = np.abs(Y.T - Aop @ X.T) / (np.abs(Aop) @ np.abs(X.T))
+            assert np.all(err <= 4e-6), float(err.max())
