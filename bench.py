@@ -451,12 +451,13 @@ def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, 
                same_choices_graph=bool(graph_same),
                phase_ms_one_at_a_time=dict(gkb=gkb_ms, proj_svd=svd_ms, param=par_ms, lift=lift_ms),
                block_product_ms=kern_ms,
-               roofline=dict(bound="mfma", achieved=flops / (kern_ms * 1e-3) / 1e12, peak=MFMA_F32_PEAK / 1e12,
+               roofline=dict(bound="alu", achieved=flops / (kern_ms * 1e-3) / 1e12, peak=MFMA_F32_PEAK / 1e12,
                              unit="TFLOP/s", frac=flops / (kern_ms * 1e-3) / MFMA_F32_PEAK,
                              kernel="k_mfh_block", flops=flops,
-                             note="2 n^2 s flops per block product (the dense n x n by n x s contraction), priced against the "
-                                  "FP32 peak; it runs as FP16 split products on the matrix cores, entries and squared "
-                                  "distances are extra issue on the same SIMDs"))
+                             note="2 n^2 s flops per block product (the dense n x n by n x s contraction) priced "
+                                  "against the FP32 peak (vector and matrix alike); the kernel is VALU-issue bound "
+                                  "(the FP32 entries: one rsq and about six FP32 instructions each), the contraction "
+                                  "runs as FP16 products of split operands on the matrix cores beside it"))
     seq = []
     for k in range(min(compare, count)):
         p, h, F = probs[k], handles[k], Fs[k]
