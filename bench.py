@@ -765,12 +765,12 @@ def main():
             pk = FP32_PEAK if mode == "matfree_fp32" else FP64_PEAK
             kms = max(r["kernel_ms_AT"], r["kernel_ms_A"])
             ops = p.n_int * n * oi + p.n_bnd * n * ob
+            kname = (("k_mfs<true>" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mfs<false>")
+                     if mode == "matfree_fp32" else
+                     ("k_mfs64<true>" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mfs64<false>"))
             e["roofline"] = dict(bound="alu", achieved=ops / (kms * 1e-3) / 1e12, peak=pk / 1e12, unit="TOP/s",
-                                 frac=ops / (kms * 1e-3) / pk, ops_per_launch=ops,
-                                 kernel=("k_mfs<true>" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mfs<false>")
-                                 if mode == "matfree_fp32" else
-                                 ("k_mfs64<true>" if r["kernel_ms_AT"] >= r["kernel_ms_A"] else "k_mfs64<false>"),
-                                 kernel_ms=kms,
+                                 frac=ops / (kms * 1e-3) / pk, ops_per_launch=ops, kernel=kname,
+                                 traffic=measured_traffic(kname), kernel_ms=kms,
                                  note=f"{oi} / {ob} operations per interior / boundary entry against the published "
                                       f"{'FP32' if mode == 'matfree_fp32' else 'FP64'} vector peak")
             if mode == "matfree_fp64":
