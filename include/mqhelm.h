@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MQH_VERSION 10600 /* 1.6.0 */
+#define MQH_VERSION 10700 /* 1.7.0 */
 
 /* ---- status codes ---- */
 #define MQH_OK 0
@@ -402,12 +402,15 @@ int mqh_solve(mqh_problem* p, const double* f_int, const double* g_bnd, const mq
  * together, so one pass over A serves the whole group.  In
  * MQH_OP_MATFREE_FP32 a group of two or more shares a block product: the
  * FP32-evaluated entries of a tile multiply all the group's vectors on the
- * matrix cores (FP32 products, FP32 sums over 256 nodes, FP64 across
- * chunks and slices); a group of one, and the FP64 forms, run one product
- * per run, bit-identical to mqh_gkb / mqh_solve.  The slice count of the
- * block products (the split of the sum over nodes, so the order of the FP64
- * additions) is picked on the first block product of a problem by timing a
- * few candidates, unless the problem was created with MQH_FLAG_FIXED_SHAPES;
+ * matrix cores as FP16 products of operands split in two parts each (the
+ * entries scaled by a power of two per problem, each vector by its own;
+ * 2^-22 relative per part, products exact in FP32, FP32 sums over 256
+ * nodes, FP64 across chunks and slices); a group of one, and the FP64
+ * forms, run one product per run, bit-identical to mqh_gkb / mqh_solve.
+ * The tile shape and slice count of the block products (the split of the
+ * sum over nodes, so the order of the FP64 additions) are picked on the
+ * first block product of a problem by timing a few candidates, unless the
+ * problem was created with MQH_FLAG_FIXED_SHAPES;
  * results are bit-reproducible for a given problem handle either way.  Everything else (norms,
  * reorthogonalisation, scalars, breakdown tests, projected SVD, parameter
  * choice, lift) is per run in FP64 as in the single-run calls.
