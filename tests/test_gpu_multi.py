@@ -397,3 +397,20 @@ def test_apply_multi_row_scaled_against_oracle(mq, orc):
             Aop = DA.T if trans else DA
             err = np.abs(Y.T - Aop @ X.T) / (np.abs(Aop) @ np.abs(X.T))
             assert np.all(err <= 4e-6), float(err.max())
+
+
+@pytest.mark.parametrize("kappa,eps", [(80.0, 25.0), (0.5, 0.1)])
+def test_apply_multi_entry_scale_extremes(mq, orc, kappa, eps):
+    # entries far above the FP16 range before their power-of-two scale (kappa^2 sqrt(t) ~ 3e5)
+    # and far below it (2 eps^2 + eps^2 ~ 0.03): the bar holds at both ends
+    p = I.multi_cube(400, 200, kappa, eps, 4, 10, seed=12)
+    rng = np.random.default_rng(13)
+    X = rng.standard_normal((4, p.n))
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    with _problem(mq, p, "matfree_fp32") as pr:
+        for trans in (False, True):
+            say("entry scale extremes", kappa, eps, "trans", trans)
+            Y = pr.apply_multi(X, trans=trans)
+            Aop = A.T if trans else A
+            err = np.abs(Y.T - Aop @ X.T) / (np.abs(Aop) @ np.abs(X.T))
+            assert np.all(err <= 4e-6), float(err.max())
