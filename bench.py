@@ -337,45 +337,71 @@ def row_scale_context(mq, torch, dev, p_big, d_big):
 
 def learned_context(mq, torch, dev, count: int, n: int = 60000, ell: int = 60, seed: int = 5):
     """Pump-casing-like solid, n nodes (80% interior), kappa in [5, 35], eps in [2, 8]: the plain
-    method (ell steps, GCV) against the learned solve (predicted steps and lambda, GCV as judge)."""
+    method (ell steps, GCV) against the learned solve (predicted steps and lambda, GCV as judge),
+    on A and, with the predictor trained on row-scaled runs, on the row-scaled problem (D A, D f);
+    beside each, the smallest error over a 13-point lambda grid at ell (what any choice of lambda
+    on that Krylov space reaches)."""
+    import os
+
     import numpy as np
 
     from paper_2511_09798_amd import learned as L
 
-    model = L.load_predictor()
+    models = {0: L.load_predictor()}
+    if os.path.exists(L.MODEL_PATH_RS):
+        models[1] = L.load_predictor(L.MODEL_PATH_RS)
     rng = np.random.default_rng(seed)
     rows = []
     for k in range(count):
         prob = L.sample_problem(rng, kind="casing", n=n, kappa=float(rng.uniform(5, 35)),
                                 eps=float(rng.uniform(2, 8)), n_eval=2000)
-        pred, keep = L.make_device_predictor(mq, torch, model, prob["h"], dev)
+        row = dict(kappa=prob["kappa"], eps=prob["eps"])
         with mq.Problem(prob["x_int"], prob["x_bnd"], prob["kappa"], prob["eps"], "matfree_fp32") as pr:
             fi = torch.from_numpy(prob["f_int"]).to(dev)
             gb = torch.from_numpy(prob["g_bnd"]).to(dev)
             xe = torch.from_numpy(prob["x_eval"]).to(dev)
-            pr.solve(fi, gb, ell)  # warm
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            base = pr.solve(fi, gb, ell)
-            torch.cuda.synchronize()
-            t_base = time.perf_counter() - t
-            t = time.perf_counter()
-            out = pr.solve_learned(fi, gb, ell, pred)
-            torch.cuda.synchronize()
-            t_net = time.perf_counter() - t
-            ub = pr.eval(base.coef, xe).cpu().numpy()
-            un = pr.eval(out.coef, xe).cpu().numpy()
-        rows.append(dict(kappa=prob["kappa"], eps=prob["eps"], steps=out.ell_pred, used_net=out.used_net_lambda,
-                         t_gcv=t_base, t_learned=t_net, err_gcv=rel_l2(ub, prob["u_eval"]),
-                         err_learned=rel_l2(un, prob["u_eval"]), lam_gcv=base.lam, lam_learned=out.lam))
+            for rs, model in models.items():
+                sfx = "" if rs == 0 else "_rs"
+                pred, keep = L.make_device_predictor(mq, torch, model, prob["h"], dev)
+                pr.solve(fi, gb, ell, row_scale=rs)  # warm
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                base = pr.solve(fi, gb, ell, row_scale=rs)
+                torch.cuda.synchronize()
+                t_base = time.perf_counter() - t
+                t = time.perf_counter()
+                out = pr.solve_learned(fi, gb, ell, pred, row_scale=rs)
+                torch.cuda.synchronize()
+                t_net = time.perf_counter() - t
+                ub = pr.eval(base.coef, xe).cpu().numpy()
+                un = pr.eval(out.coef, xe).cpu().numpy()
+                sv0 = float(base.sv[0])
+                best = min(rel_l2(pr.eval(pr.solve(fi, gb, ell, rule=mq.MQH_RULE_FIXED, lambda_fixed=float(lam),
+                                                   row_scale=rs).coef, xe).cpu().numpy(), prob["u_eval"])
+                           for lam in np.geomspace(sv0 * 1e-12, sv0, 13))
+                row.update({"steps" + sfx: out.ell_pred, "used_net" + sfx: out.used_net_lambda,
+                            "t_gcv" + sfx: t_base, "t_learned" + sfx: t_net,
+                            "err_gcv" + sfx: rel_l2(ub, prob["u_eval"]), "err_learned" + sfx: rel_l2(un, prob["u_eval"]),
+                            "err_best_grid" + sfx: best, "lam_gcv" + sfx: base.lam, "lam_learned" + sfx: out.lam})
+        rows.append(row)
         log("learned casing", k, json.dumps(rows[-1]))
-    eg = np.array([r["err_gcv"] for r in rows])
-    en = np.array([r["err_learned"] for r in rows])
-    return dict(workload=f"casing_n{n}", problems=count, ell=ell, mean_steps_learned=float(np.mean([r["steps"] for r in rows])),
-                steps_gcv=ell, mean_time_gcv_s=float(np.mean([r["t_gcv"] for r in rows])),
-                mean_time_learned_s=float(np.mean([r["t_learned"] for r in rows])),
-                median_rel_l2_gcv=float(np.median(eg)), median_rel_l2_learned=float(np.median(en)),
-                net_lambda_used=int(sum(r["used_net"] for r in rows)), cases=rows)
+    res = dict(workload=f"casing_n{n}", problems=count, ell=ell, steps_gcv=ell)
+    for rs in models:
+        sfx = "" if rs == 0 else "_rs"
+        eg = np.array([r["err_gcv" + sfx] for r in rows])
+        en = np.array([r["err_learned" + sfx] for r in rows])
+        eb = np.array([r["err_best_grid" + sfx] for r in rows])
+        res.update({"mean_steps_learned" + sfx: float(np.mean([r["steps" + sfx] for r in rows])),
+                    "mean_time_gcv_s" + sfx: float(np.mean([r["t_gcv" + sfx] for r in rows])),
+                    "mean_time_learned_s" + sfx: float(np.mean([r["t_learned" + sfx] for r in rows])),
+                    "median_rel_l2_gcv" + sfx: float(np.median(eg)), "median_rel_l2_learned" + sfx: float(np.median(en)),
+                    "median_rel_l2_best_grid" + sfx: float(np.median(eb)),
+                    "learned_better" + sfx: int(np.sum(en < eg)),
+                    "net_lambda_used" + sfx: int(sum(r["used_net" + sfx] for r in rows))})
+    res["row_scaled"] = ("the same problems with the row scaling D = diag(A)^-1 and the predictor trained on "
+                         "row-scaled runs (fields ending _rs)") if 1 in models else "no row-scaled predictor"
+    res["cases"] = rows
+    return res
 
 
 def sweep_context(mq, torch, dev, count: int, compare: int, oracle_check: bool, workers: int,

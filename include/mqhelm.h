@@ -623,7 +623,9 @@ int mqh_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t n
  * lambda_net not finite or positive, more than a factor 10 outside GCV's
  * search range [max(s_l, 16 eps_mach s_1), s_1], or (judge_ratio >= 1)
  * GCV(lambda_net) > judge_ratio * GCV(lambda_gcv).
- * opts: method HKT, rule GCV, ell >= MQH_MLP_PROBE; kappa > 0.
+ * opts: method HKT, rule GCV, ell >= MQH_MLP_PROBE; kappa > 0; row_scale 0
+ * or 1 (1: the whole run on D A and D f as in mqh_solve, so the features come
+ * from the scaled process: use a predictor trained on such runs).
  * coef (n) out; info and linfo may be NULL.
  */
 int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, const mqh_solve_opts* opts,

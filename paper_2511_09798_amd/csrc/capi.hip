@@ -3149,7 +3149,7 @@ int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, 
     if (opts->reorth != 0 && opts->reorth != 1) return fail(MQH_EINVAL, "reorth must be 0 or 1");
     if (opts->method != MQH_METHOD_HKT || opts->rule != MQH_RULE_GCV)
         return fail(MQH_EINVAL, "the learned solve is HKT with GCV as judge and fallback");
-    if (opts->row_scale != 0) return fail(MQH_EINVAL, "the learned solve takes row_scale = 0");
+    if (opts->row_scale != 0 && opts->row_scale != 1) return fail(MQH_EINVAL, "row_scale must be 0 or 1");
     const int32_t J = opts->n_grid == 0 ? 200 : opts->n_grid;
     if (J < 3 || J > kMaxGrid) return fail(MQH_EINVAL, "n_grid must be 0 or in [3, 4096]");
     if (!(pred->h > 0.0) || !isfinite(pred->h) || pred->ell_step < 1 ||
@@ -3162,7 +3162,9 @@ int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, 
         if (!(pred->out_std[i] > 0.0f) || !isfinite(pred->out_mean[i])) return fail(MQH_EINVAL, "bad standardisation");
     const uint32_t flags = opts->flags;
     HIPCHK(hipSetDevice(p->device));
-    if ((rc = set_row_scale(p, 0))) return rc;
+    // with the row scaling the whole run is on D A and D f: the features come
+    // from its scalars, so the predictor must have been trained on such runs
+    if ((rc = set_row_scale(p, opts->row_scale))) return rc;
     hipStream_t s = p->stream;
     if ((rc = ensure_gkb(p, ell))) return rc;
     const size_t mlp_floats = kMlpIn + kMlpOut + 3 * kMlpWidth + 2 * kMlpIn;
@@ -3180,6 +3182,7 @@ int mqh_solve_learned(mqh_problem* p, const double* f_int, const double* g_bnd, 
     HIPCHK(hipMemcpyAsync(dstd, pred->in_std, kMlpIn * sizeof(float), hipMemcpyHostToDevice, s));
     if ((rc = stage_in(p->vx, f_int, p->n_int, flags, s))) return rc;
     if ((rc = stage_in(p->vx + p->n_int, g_bnd, p->n_bnd, flags, s))) return rc;
+    if ((rc = scale_rhs(p, p->vx, 1, 0))) return rc;
     HIPCHK(hipEventRecord(p->ev[1], s));
     // probe: the first kMlpProbe steps, then the network
     if ((rc = run_gkb(p, ell, opts->reorth, false, 0, kMlpProbe))) return rc;

@@ -53,6 +53,9 @@ ELL_MAX = 60
 ELL_STEP = 5
 N_EVAL = 64
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "predictor.npz")
+# the same network trained on row-scaled runs (D A c = D f, D = diag(A)^-1): its features are those
+# of the scaled process, so it serves the learned solve with row_scale = 1 only
+MODEL_PATH_RS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "predictor_rs.npz")
 
 
 # --------------------------------------------------------------------------
@@ -205,12 +208,13 @@ def lambda_grid(sv: np.ndarray, n: int = 41) -> np.ndarray:
 
 
 def method_labels(mq, torch, prob: Dict, dev, ell_max: int = ELL_MAX, step: int = ELL_STEP,
-                  mode: str = "matfree_fp32") -> Optional[Dict]:
+                  mode: str = "matfree_fp32", row_scale: int = 0) -> Optional[Dict]:
     """Golub-Kahan run to ell_max, HKT solutions over a lambda grid at ell_max and at
-    lambda* for ell = 10, 15, ..., ell_max (all projected steps by the library)."""
+    lambda* for ell = 10, 15, ..., ell_max (all projected steps by the library).  row_scale 1:
+    the run on D A and D f (the coefficients, hence u, are those of the same unknowns)."""
     with mq.Problem(prob["x_int"], prob["x_bnd"], prob["kappa"], prob["eps"], mode) as pr:
         f = torch.from_numpy(np.concatenate([prob["f_int"], prob["g_bnd"]])).to(dev)
-        r = pr.gkb(f, ell_max)
+        r = pr.gkb(f, ell_max, row_scale=row_scale)
         le = int(r["ell_done"])
         if le < ell_max:
             return None  # broke down: not a training sample
@@ -248,7 +252,7 @@ def method_labels(mq, torch, prob: Dict, dev, ell_max: int = ELL_MAX, step: int 
                 n=prob["n"], kappa=prob["kappa"], eps=prob["eps"])
 
 
-def generate(n_samples: int, seed: int, log_every: int = 500) -> Dict[str, np.ndarray]:
+def generate(n_samples: int, seed: int, log_every: int = 500, row_scale: int = 0) -> Dict[str, np.ndarray]:
     import torch
 
     from . import mqhelm as mq
@@ -260,7 +264,7 @@ def generate(n_samples: int, seed: int, log_every: int = 500) -> Dict[str, np.nd
     tries = 0
     while len(rows) < n_samples:
         tries += 1
-        lab = method_labels(mq, torch, sample_problem(rng), dev)
+        lab = method_labels(mq, torch, sample_problem(rng), dev, row_scale=row_scale)
         if lab is not None:
             rows.append(lab)
         if len(rows) % log_every == 0 and lab is not None:
@@ -402,9 +406,11 @@ def make_device_predictor(mq, torch, model: Dict, h: float, dev, ell_step: int =
 # Evaluation: the learned solve against the method without it
 # --------------------------------------------------------------------------
 
-def compare(problems, model: Dict, ell: int = ELL_MAX, mode: str = "matfree_fp32", log=None) -> Dict:
+def compare(problems, model: Dict, ell: int = ELL_MAX, mode: str = "matfree_fp32", log=None,
+            row_scale: int = 0) -> Dict:
     """Per problem: HKT with GCV after ell steps (the method) and the learned solve (predicted
-    steps and lambda, GCV as judge and fallback); errors at the problems' evaluation points."""
+    steps and lambda, GCV as judge and fallback); errors at the problems' evaluation points.
+    row_scale 1: both on the row-scaled problem (with a predictor trained on such runs)."""
     import torch
 
     from . import mqhelm as mq
@@ -414,9 +420,9 @@ def compare(problems, model: Dict, ell: int = ELL_MAX, mode: str = "matfree_fp32
     for k, prob in enumerate(problems):
         pred, keep = make_device_predictor(mq, torch, model, prob["h"], dev)
         with mq.Problem(prob["x_int"], prob["x_bnd"], prob["kappa"], prob["eps"], mode) as pr:
-            base = pr.solve(prob["f_int"], prob["g_bnd"], ell)
+            base = pr.solve(prob["f_int"], prob["g_bnd"], ell, row_scale=row_scale)
             ub = pr.eval(base.coef, prob["x_eval"])
-            out = pr.solve_learned(prob["f_int"], prob["g_bnd"], ell, pred)
+            out = pr.solve_learned(prob["f_int"], prob["g_bnd"], ell, pred, row_scale=row_scale)
             un = pr.eval(out.coef, prob["x_eval"])
         nu = float(np.linalg.norm(prob["u_eval"]))
         rows.append(dict(kind=prob["kind"], n=prob["n"], kappa=prob["kappa"], eps=prob["eps"], steps=out.ell_pred,
@@ -449,6 +455,7 @@ def main(argv=None):
     g.add_argument("--samples", type=int, default=20000)
     g.add_argument("--seed", type=int, default=1)
     g.add_argument("--out", required=True)
+    g.add_argument("--row-scale", type=int, default=0)
     t = sub.add_parser("train")
     t.add_argument("--data", required=True, nargs="+")
     t.add_argument("--epochs", type=int, default=400)
@@ -456,24 +463,26 @@ def main(argv=None):
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--out", default=MODEL_PATH)
     t.add_argument("--report", default=None)
+    t.add_argument("--row-scale", type=int, default=0, help="recorded in the model's meta")
     e = sub.add_parser("evaluate")
     e.add_argument("--problems", type=int, default=200)
     e.add_argument("--seed", type=int, default=909)
     e.add_argument("--kind", default=None, help="cube / sphere / casing (default: the training mix)")
     e.add_argument("--n", type=int, default=None)
     e.add_argument("--out", default=None)
+    e.add_argument("--row-scale", type=int, default=0)
     a = ap.parse_args(argv)
     if a.cmd == "evaluate":
         rng = np.random.default_rng(a.seed)
         probs = [sample_problem(rng, kind=a.kind, n=a.n) for _ in range(a.problems)]
-        rep = compare(probs, load_predictor())
+        rep = compare(probs, load_predictor(MODEL_PATH_RS if a.row_scale else MODEL_PATH), row_scale=a.row_scale)
         print(json.dumps({k: v for k, v in rep.items() if k != "cases"}), flush=True)
         if a.out:
             with open(a.out, "w") as fh:
                 json.dump(rep, fh, indent=1)
         return 0
     if a.cmd == "generate":
-        d = generate(a.samples, a.seed)
+        d = generate(a.samples, a.seed, row_scale=a.row_scale)
         np.savez(a.out, **d)
         print(f"[learned] wrote {a.out}: {d['X'].shape[0]} samples ({int(d['tries'])} problems drawn)", flush=True)
         return 0
@@ -481,7 +490,8 @@ def main(argv=None):
     data = {k: np.concatenate([p[k] for p in parts]) for k in ("X", "T", "stop", "lam", "err_gcv", "err_opt")}
     model = train(data, a.epochs, a.batch, a.lr)
     meta = dict(samples=int(data["X"].shape[0]), epochs=a.epochs, batch=a.batch, lr=a.lr, ell_max=ELL_MAX,
-                ell_step=ELL_STEP, best_epoch=int(model["best_epoch"]), best_val_mse=float(model["best_val"]),
+                ell_step=ELL_STEP, row_scale=a.row_scale, best_epoch=int(model["best_epoch"]),
+                best_val_mse=float(model["best_val"]),
                 history=model["history"].tolist())
     save_predictor(a.out, model, meta)
     T = data["T"][model["val_idx"]]

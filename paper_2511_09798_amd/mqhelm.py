@@ -682,14 +682,14 @@ class LearnedOutput:
 
 
 def mqh_solve_learned(h, f_int, g_bnd, ell: int, predictor: mqh_predictor, coef=None, n_grid: int = 200,
-                      reorth: int = 1) -> LearnedOutput:
+                      reorth: int = 1, row_scale: int = 0) -> LearnedOutput:
     n = int(lib.mqh_problem_size(h))
     ref = f_int if f_int is not None else g_bnd
     if coef is None:
         coef = _empty_like_kind(ref, (n,))
     fl = _flags(f_int, g_bnd, coef)
     opts = mqh_solve_opts(ell=int(ell), reorth=int(reorth), method=MQH_METHOD_HKT, rule=MQH_RULE_GCV, k_trunc=0,
-                          n_grid=int(n_grid), lambda_fixed=0.0, flags=fl, row_scale=0, gcv_weight=1.0)
+                          n_grid=int(n_grid), lambda_fixed=0.0, flags=fl, row_scale=int(row_scale), gcv_weight=1.0)
     info, li = mqh_solve_info(), mqh_learned_info()
     st = _check(lib.mqh_solve_learned(h, _ptr(f_int)[0], _ptr(g_bnd)[0], ctypes.byref(opts), ctypes.byref(predictor),
                                       _ptr(coef)[0], ctypes.byref(info), ctypes.byref(li)), "mqh_solve_learned")

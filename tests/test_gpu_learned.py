@@ -170,6 +170,41 @@ def test_learned_solve_matches_oracle_network(env, model, orc):
     assert keep is not None
 
 
+def test_learned_solve_row_scaled_matches_oracle(env, model, orc):
+    # row_scale = 1: the whole run on D A and D f (D = diag(A)^-1): the features come from the
+    # scaled process and the coefficients are the scaled problem's HKT solution (the mechanism does
+    # not depend on which predictor is loaded)
+    mq, torch, dev = env
+    from paper_2511_09798_amd import learned as L
+
+    prob = L.sample_problem(np.random.default_rng(4243), kind="cube", n=1500, kappa=6.0, eps=1.5)
+    X = np.concatenate([prob["x_int"], prob["x_bnd"]])
+    f = np.concatenate([prob["f_int"], prob["g_bnd"]])
+    ni = prob["x_int"].shape[0]
+    pred, keep = L.make_device_predictor(mq, torch, model, prob["h"], dev)
+    with mq.Problem(prob["x_int"], prob["x_bnd"], prob["kappa"], prob["eps"], "matfree_fp64") as pr:
+        say("learned solve, row scaled")
+        out = pr.solve_learned(prob["f_int"], prob["g_bnd"], 60, pred, row_scale=1)
+        g = pr.gkb(f, 10, row_scale=1)
+        g0 = pr.gkb(f, 10)
+    # a different process (with f = 0 inside, D f = f and w_1 lives on the boundary rows, where
+    # D = 1, so alpha_1 agrees; the scaled interior rows show from beta_2 on)
+    b, b0 = np.asarray(g["beta"])[1:], np.asarray(g0["beta"])[1:]
+    assert np.max(np.abs(b - b0) / np.abs(b0)) > 1e-3
+    x = M.features(g["alpha"], g["beta"], prob["kappa"], prob["eps"], X.shape[0], prob["h"],
+                   model["in_mean"], model["in_std"])
+    y, _ = M.forward(model["params"].astype(np.float64), x[None, :])
+    t = y[0] * model["out_std"] + model["out_mean"]
+    assert abs(out.out[0] - t[0]) <= 1e-3 and abs(out.out[1] - t[1]) <= 1e-4
+    assert out.lambda_net == pytest.approx(g["alpha"][0] * math.exp(out.out[0]), rel=1e-12)
+    r = orc.solve(X, ni, prob["kappa"], prob["eps"], f, out.ell_pred, rule=orc.RULE_FIXED, lambda_fixed=out.lam,
+                  stored=False, row_scale=1)
+    u = orc.eval_u(X, prob["eps"], out.coef, prob["x_eval"])
+    uo = orc.eval_u(X, prob["eps"], r.coef, prob["x_eval"])
+    assert np.linalg.norm(u - uo) <= 1e-8 * np.linalg.norm(uo)
+    assert keep is not None
+
+
 def test_learned_solve_falls_back_to_gcv(env, model):
     mq, torch, dev = env
     from paper_2511_09798_amd import learned as L
