@@ -231,3 +231,19 @@ def test_learned_gain_over_gcv(env, model):
     assert rep["median_err_learned"] < rep["median_err_gcv"]
     assert rep["frac_err_below_0_5"]["learned"] > rep["frac_err_below_0_5"]["gcv"]
     assert rep["mean_steps_learned"] < 60
+
+
+def test_learned_gain_over_gcv_row_scaled(env):
+    # the predictor trained on row-scaled runs, on held-out problems of the training family solved
+    # with the row scaling: GCV after 60 steps against the learned solve
+    mq, torch, dev = env
+    from paper_2511_09798_amd import learned as L
+
+    model_rs = L.load_predictor(L.MODEL_PATH_RS)
+    assert model_rs["meta"].get("row_scale") == 1
+    rep = L.compare(_heldout(L, 919, 48), model_rs, row_scale=1,
+                    log=lambda k, r: say("gain case rs", k, r["kind"], r["n"]))
+    say("report rs", {k: v for k, v in rep.items() if k != "cases"})
+    assert rep["median_err_learned"] < rep["median_err_gcv"]
+    assert rep["frac_err_below_0_5"]["learned"] > rep["frac_err_below_0_5"]["gcv"]
+    assert rep["mean_steps_learned"] < 60
