@@ -5,7 +5,9 @@ the products A x and A^T x in all three operator modes, the Golub-Kahan
 bidiagonalisation with full reorthogonalisation, the projected SVD, the
 parameter choice, the projected solution, the lift, the evaluation and the
 whole solve, at small sizes (several tiles plus a ragged tail) element by
-element.
+element; at full size (unit ball, n = 100000) the products on sampled rows,
+the Golub-Kahan relations, and the benchmark's stored FP64 HKT + GCV solve
+step by step against the oracle on the GPU's Krylov scalars.
 
 Tolerances (derivations in the design notes):
 * FP64 entries: |dA_ij| <= 4e-15 |A_ij| (both sides evaluate the same closed
@@ -579,6 +581,52 @@ def test_gkb_relations_full_size_fp32(mq, orc, sphere_full):
         sct = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, np.abs(Wc[j]), idx, trans=True)
         zc = a[j] * Zc[j, idx] + (b[j] * Zc[j - 1, idx] if j > 0 else 0.0)
         assert np.all(np.abs(atw - zc) <= 1e-5 * sct), float(np.max(np.abs(atw - zc) / sct))
+
+
+def test_hkt_full_size_stored_fp64(mq, orc, sphere_full):
+    # The benchmark's own solve (stored FP64 A, n = 100000, ell = 300,
+    # HKT + GCV): the Golub-Kahan relations against the oracle's A on sampled
+    # rows, then every projected step against the oracle on the GPU's alpha,
+    # beta, and the coefficients against the oracle's projected solution
+    # lifted with the GPU's Z.
+    p = sphere_full
+    l = p.ell
+    with _problem(mq, p, "stored_fp64") as pr:
+        say("full-size gkb stored fp64, ell", l)
+        r = pr.gkb(p.rhs, l)
+        say("full-size solve stored fp64, ell", l)
+        out = pr.solve(p.f_int, p.g_bnd, l)
+    assert r["ell_done"] == l and out.ell_done == l
+    Wc, Zc, a, b = r["W"], r["Z"], r["alpha"], r["beta"]
+    assert np.max(np.abs(Wc @ Wc.T - np.eye(l + 1))) < 1e-12
+    assert np.max(np.abs(Zc @ Zc.T - np.eye(l))) < 1e-12
+    idx = np.arange(7, p.n, 1511).astype(np.int64)
+    worst = 0.0
+    for j in (0, l // 2, l - 1):
+        azj = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, Zc[j], idx)
+        sc = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, np.abs(Zc[j]), idx)
+        wc = a[j] * Wc[j, idx] + b[j + 1] * Wc[j + 1, idx]
+        atw = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, Wc[j], idx, trans=True)
+        sct = orc.apply_sampled(p.nodes, p.n_int, p.kappa, p.eps, np.abs(Wc[j]), idx, trans=True)
+        zc = a[j] * Zc[j, idx] + (b[j] * Zc[j - 1, idx] if j > 0 else 0.0)
+        worst = max(worst, float(np.max(np.abs(azj - wc) / sc)), float(np.max(np.abs(atw - zc) / sct)))
+    say("relations, worst ratio", worst)
+    assert worst <= 1e-12  # the FP64 product bound (1e-13) plus the reorthogonalisation rounding
+    # the solve repeats the same Golub-Kahan run
+    np.testing.assert_allclose(out.alpha, a, rtol=1e-12)
+    np.testing.assert_allclose(out.beta, b, rtol=1e-12)
+    say("projected steps against the oracle")
+    s, ft, V = orc.proj_svd(a, b)
+    sv, ftg, _ = mq.mqh_proj_svd(a, b)
+    assert np.max(np.abs(sv[:10] - s[:10]) / s[:10]) < 1e-12
+    assert np.max(np.abs(sv - s)) < 64 * l * EPS * s[0]
+    assert np.max(np.abs(out.sv[:10] - s[:10]) / s[:10]) < 1e-12
+    lam, gv, edge, grid, vals = orc.choose_lambda_gcv(s, ft, 200)
+    assert out.lam == pytest.approx(lam, rel=1e-6)
+    assert bool(out.flags & mq.MQH_INFO_GCV_AT_EDGE) == edge
+    y = orc.y_tikhonov(s, ft, V, out.lam)
+    coef = Zc.T @ y
+    assert np.linalg.norm(out.coef - coef) <= 1e-8 * np.linalg.norm(coef)
 
 
 def test_duplicate_nodes_finite(mq):
