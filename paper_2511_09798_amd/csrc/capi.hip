@@ -554,7 +554,7 @@ int ensure_gkb(mqh_problem* p, int32_t ell) {
     HIPCHK(hipMemsetAsync(p->Z, 0, (size_t)(cols * p->ldn) * sizeof(double), p->stream));
     if ((rc = dalloc(&p->alpha, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->beta, (size_t)cols + 1))) return rc;
-    if ((rc = dalloc(&p->gpart, (size_t)gemvt_blocks(p->n) * (size_t)cols))) return rc;
+    if ((rc = dalloc(&p->gpart, (size_t)cgs_partial_doubles(p->n, cols)))) return rc;
     if ((rc = dalloc(&p->cvec, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->sv, (size_t)cols))) return rc;
     if ((rc = dalloc(&p->ftil, (size_t)cols + 1))) return rc;
@@ -586,8 +586,12 @@ int run_gkb(mqh_problem* p, int32_t ell, int32_t reorth, bool timed, int32_t j0 
         int nparts;
         if (reorth && m > 0) {
             launch_gemvt(V, ldn, n, m, v, p->gpart, p->cvec, p->st, s);
-            launch_update(V, ldn, n, m, p->cvec, v, nullptr, p->st, s);
-            launch_gemvt(V, ldn, n, m, v, p->gpart, p->cvec, p->st, s);
+            if (m <= kFusedCgsMaxCols) {
+                launch_update_gemvt(V, ldn, n, m, p->cvec, v, p->gpart, p->st, s);
+            } else {
+                launch_update(V, ldn, n, m, p->cvec, v, nullptr, p->st, s);
+                launch_gemvt(V, ldn, n, m, v, p->gpart, p->cvec, p->st, s);
+            }
             launch_update(V, ldn, n, m, p->cvec, v, p->npart, p->st, s);
             nparts = nbu;
         } else {
@@ -755,7 +759,7 @@ int ensure_multi(mqh_problem* p, int nz, int32_t ell) {
     const int64_t n = p->n, ldn = p->ldn, cols = (int64_t)lc + 1;
     w.vstr = (int64_t)lc + 2;
     w.bstr = cols * ldn;
-    w.gstr = (int64_t)gemvt_blocks(n) * cols;
+    w.gstr = cgs_partial_doubles(n, cols);
     w.nstr = update_blocks(n) > 1024 ? update_blocks(n) : 1024;
     const size_t Z = (size_t)zc;
     int rc;
@@ -887,8 +891,12 @@ int run_gkb_multi(mqh_problem* p, int nz, int32_t ell, int32_t reorth, bool time
         if (reorth && m > 0) {
             const Bz ub{w.bstr, w.vstr, ldn, w.nstr};
             launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.cvec, w.st, nz, w.bstr, ldn, w.gstr, w.vstr, s);
-            launch_update_b(V, ldn, n, m, w.cvec, w.Y, nullptr, w.st, nz, ub, s);
-            launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.cvec, w.st, nz, w.bstr, ldn, w.gstr, w.vstr, s);
+            if (m <= kFusedCgsMaxCols) {
+                launch_update_gemvt_b(V, ldn, n, m, w.cvec, w.Y, w.gpart, w.st, nz, w.bstr, w.vstr, ldn, w.gstr, s);
+            } else {
+                launch_update_b(V, ldn, n, m, w.cvec, w.Y, nullptr, w.st, nz, ub, s);
+                launch_gemvt_b(V, ldn, n, m, w.Y, w.gpart, w.cvec, w.st, nz, w.bstr, ldn, w.gstr, w.vstr, s);
+            }
             launch_update_b(V, ldn, n, m, w.cvec, w.Y, w.npart, w.st, nz, ub, s);
             nparts = nbu;
         } else {

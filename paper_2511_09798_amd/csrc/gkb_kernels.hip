@@ -236,10 +236,11 @@ __global__ __launch_bounds__(kBlock) void k_gemvt_partial(const double* __restri
     }
 }
 
-// c[k] = sum_b partial[b * m + k]: one wave per column, lanes take b = lane,
+// c[k] = sum_b partial[b * sb + k * sk] (k_gemvt_partial: sb = m, sk = 1;
+// k_update_gemvt: sb = 1, sk = nb): one wave per column, lanes take b = lane,
 // lane + 64, ... and the wave reduction combines them in a fixed order.
 __global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restrict__ partial, int nb, int32_t m,
-                                                         double* __restrict__ c,
+                                                         int64_t sb, int64_t sk, double* __restrict__ c,
                                                          const GkbState* __restrict__ st, Bz bz) {
     const int64_t z = blockIdx.y;  // batch: partial + z bz.a, c + z bz.b, state z
     partial += z * bz.a;
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_gemvt_reduce(const double* __restric
     const int k = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (k >= m) return;  // wave-uniform; no barriers
     double s = 0.0;
-    for (int b = lane; b < nb; b += kWave) s += partial[(int64_t)b * m + k];
+    for (int b = lane; b < nb; b += kWave) s += partial[(int64_t)b * sb + (int64_t)k * sk];
     s = wave_sum(s);
     if (lane == 0) c[k] = s;
 }
@@ -316,6 +317,91 @@ __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V,
     if (sumsq_partial != nullptr) {
         const double s = block_sum<kBlock>(xi * xi, lds);
         if (threadIdx.x == 0) sumsq_partial[blockIdx.x] = s;
+    }
+}
+
+// The middle of classical Gram-Schmidt applied twice in one pass over V:
+// x -= V c (the first pass's update), then partial[k * nb + b] = sum over the
+// kFuRows rows of block b of V[k][i] x_i for the updated x (the second
+// pass's projection coefficients, reduced by k_gemvt_reduce).  The block's
+// rows of V[:, 0:m] come from HBM once and stay in LDS (m x kFuLd doubles of
+// dynamic shared memory) between the two, so CGS2 reads the basis three
+// times instead of four.  Thread t takes the row pair 2 (t % 16), + 1 and
+// the columns k = t / 16, t / 16 + 16, ...; the 16 column groups' sums are
+// added in group order through LDS.  Rows past n read rows 0, 1 of the
+// column (finite values; their x is zero) and are not written.
+constexpr int kFuRows = 32;
+constexpr int kFuLd = kFuRows + 1;             // padded LDS row of the tile
+constexpr int kFuPairs = kFuRows / 2;
+constexpr int kFuGroups = kBlock / kFuPairs;   // 16
+static_assert(kFuGroups * kFuPairs == kBlock, "fused CGS2 tile layout");
+static_assert(kFusedCgsMaxCols * kFuLd * 8 + (kFuGroups + 1) * kFuRows * 8 <= 65536, "fused CGS2 LDS within 64 KB");
+
+__global__ __launch_bounds__(kBlock) void k_update_gemvt(const double* __restrict__ V, int64_t ldn, int64_t n,
+                                                         int32_t m, const double* __restrict__ c,
+                                                         double* __restrict__ x, double* __restrict__ partial,
+                                                         int nb, const GkbState* __restrict__ st, Bz bz) {
+    extern __shared__ double tile[];  // [m][kFuLd]
+    __shared__ double part[kFuGroups][kFuRows];
+    __shared__ double xs[kFuRows];
+    const int64_t z = blockIdx.z;  // batch: V + z bz.a, c + z bz.b, x + z bz.c, partial + z bz.d, state z
+    V += z * bz.a;
+    c += z * bz.b;
+    x += z * bz.c;
+    partial += z * bz.d;
+    if (st != nullptr) st += z;
+    if (st != nullptr && st->stopped) return;  // uniform over the grid
+    const int t = threadIdx.x, rp = t % kFuPairs, cg = t / kFuPairs;
+    const int64_t i0 = (int64_t)blockIdx.x * kFuRows + 2 * rp;
+    const double* v = V + (i0 < n ? i0 : 0);
+    double* tr = tile + 2 * rp;
+    double s0 = 0.0, s1 = 0.0;
+    int k = cg;
+#pragma unroll 2
+    for (; k + 3 * kFuGroups < m; k += 4 * kFuGroups) {
+        v2d a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = load2(v + (int64_t)(k + u * kFuGroups) * ldn);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = k + u * kFuGroups;
+            tr[kk * kFuLd] = a[u].x;
+            tr[kk * kFuLd + 1] = a[u].y;
+            const double ck = c[kk];
+            s0 = fma(a[u].x, ck, s0);
+            s1 = fma(a[u].y, ck, s1);
+        }
+    }
+    for (; k < m; k += kFuGroups) {
+        const v2d a = load2(v + (int64_t)k * ldn);
+        tr[k * kFuLd] = a.x;
+        tr[k * kFuLd + 1] = a.y;
+        const double ck = c[k];
+        s0 = fma(a.x, ck, s0);
+        s1 = fma(a.y, ck, s1);
+    }
+    part[cg][2 * rp] = s0;
+    part[cg][2 * rp + 1] = s1;
+    __syncthreads();
+    if (t < kFuRows) {
+        double sum = 0.0;
+#pragma unroll
+        for (int g = 0; g < kFuGroups; ++g) sum += part[g][t];
+        const int64_t i = (int64_t)blockIdx.x * kFuRows + t;
+        double xi = 0.0;
+        if (i < n) {
+            xi = x[i] - sum;
+            x[i] = xi;
+        }
+        xs[t] = xi;
+    }
+    __syncthreads();
+    for (int kk = t; kk < m; kk += kBlock) {
+        const double* r = tile + kk * kFuLd;
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kFuRows; ++i) acc = fma(r[i], xs[i], acc);
+        partial[(int64_t)kk * nb + blockIdx.x] = acc;
     }
 }
 
@@ -419,8 +505,25 @@ void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const do
     const int nb = gemvt_blocks(n);
     k_gemvt_partial<<<dim3(nb, (m + kGtCols - 1) / kGtCols, nz), kBlock, 0, s>>>(V, ldn, n, m, x, partial, st,
                                                                                  Bz{sV, sx, sp, 0});
-    k_gemvt_reduce<<<dim3((m + kBlock / kWave - 1) / (kBlock / kWave), nz), kBlock, 0, s>>>(partial, nb, m, c, st,
-                                                                                           Bz{sp, sc, 0, 0});
+    k_gemvt_reduce<<<dim3((m + kBlock / kWave - 1) / (kBlock / kWave), nz), kBlock, 0, s>>>(
+        partial, nb, m, m, 1, c, st, Bz{sp, sc, 0, 0});
+}
+
+int fused_cgs_blocks(int64_t n) { return (int)((n + kFuRows - 1) / kFuRows); }
+
+void launch_update_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, double* c, double* x,
+                           double* partial, const GkbState* st, int nz, int64_t sV, int64_t sc, int64_t sx,
+                           int64_t sp, hipStream_t s) {
+    const int nb = fused_cgs_blocks(n);
+    const size_t lds = (size_t)m * kFuLd * sizeof(double);
+    k_update_gemvt<<<dim3(nb, 1, nz), kBlock, lds, s>>>(V, ldn, n, m, c, x, partial, nb, st, Bz{sV, sc, sx, sp});
+    k_gemvt_reduce<<<dim3((m + kBlock / kWave - 1) / (kBlock / kWave), nz), kBlock, 0, s>>>(
+        partial, nb, m, 1, nb, c, st, Bz{sp, sc, 0, 0});
+}
+
+void launch_update_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, double* c, double* x,
+                         double* partial, const GkbState* st, hipStream_t s) {
+    launch_update_gemvt_b(V, ldn, n, m, c, x, partial, st, 1, 0, 0, 0, 0, s);
 }
 
 void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,

@@ -164,6 +164,17 @@ void launch_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, const doub
 int update_blocks(int64_t n);
 void launch_update(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
                    double* sumsq_partial, GkbState* st, hipStream_t s);
+// x -= V c, then c = V^T x for the updated x, reading V once (partials:
+// fused_cgs_blocks(n) x m); for m <= kFusedCgsMaxCols (the LDS tile within 64 KB)
+constexpr int kFusedCgsMaxCols = 224;
+int fused_cgs_blocks(int64_t n);
+void launch_update_gemvt(const double* V, int64_t ldn, int64_t n, int32_t m, double* c, double* x,
+                         double* partial, const GkbState* st, hipStream_t s);
+// partial buffers of the reorthogonalisation for n rows and up to cols columns
+inline int64_t cgs_partial_doubles(int64_t n, int64_t cols) {
+    const int64_t b = fused_cgs_blocks(n) > gemvt_blocks(n) ? fused_cgs_blocks(n) : gemvt_blocks(n);
+    return b * cols;
+}
 void launch_lift(const double* Z, int64_t ldz, int64_t n, int32_t ell, const int32_t* ell_ptr, const double* y,
                  double* coef, hipStream_t s, int nz = 1, Bz bz = Bz{});
 // batched forms: nz slices, strides per slice as stated at the kernels
@@ -179,6 +190,9 @@ void launch_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, const do
                     const GkbState* st, int nz, int64_t sV, int64_t sx, int64_t sp, int64_t sc, hipStream_t s);
 void launch_update_b(const double* V, int64_t ldn, int64_t n, int32_t m, const double* c, double* x,
                      double* sumsq_partial, GkbState* st, int nz, Bz bz, hipStream_t s);
+void launch_update_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, double* c, double* x,
+                           double* partial, const GkbState* st, int nz, int64_t sV, int64_t sc, int64_t sx,
+                           int64_t sp, hipStream_t s);
 void launch_fill_f32(float* x, int64_t n, float v, hipStream_t s);
 
 // projected SVD (svd_kernels.hip; the QR iteration in proj_kernels.hip).
