@@ -156,6 +156,33 @@ def test_gkb_multi_bitwise_single_fp64(mq, mode):
                 assert np.array_equal(r[key][k], s[key]), (k, key)
 
 
+def test_gkb_long_runs_across_the_fused_cgs_limit(mq, orc):
+    # 240 steps: the basis grows past the 224 columns that the fused
+    # update-and-projection kernel keeps in LDS, so both forms of the
+    # reorthogonalisation run, in the single and in the lockstep path
+    p = I.multi_cube(1000, 300, 4.0, 1.5, 3, 240, seed=17)
+    ell = p.ell
+    A = orc.assemble(p.nodes, p.n_int, p.kappa, p.eps)
+    with _problem(mq, p, "stored_fp64") as pr:
+        say("gkb_multi long runs, ell", ell)
+        r = pr.gkb_multi(p.F, ell)
+        singles = [pr.gkb(p.F[k], ell) for k in range(p.nrhs)]
+    for k in range(p.nrhs):
+        s = singles[k]
+        assert r["ell_done"][k] == s["ell_done"] == ell
+        for key in ("alpha", "beta", "W", "Z"):
+            assert np.array_equal(r[key][k], s[key]), (k, key)
+        g = orc.gkb(A, p.nodes, p.n_int, p.kappa, p.eps, p.F[k], ell)
+        C = orc.bidiag_matrix(s["alpha"], s["beta"])
+        W, Z = s["W"].T, s["Z"].T
+        assert np.max(np.abs(W.T @ W - np.eye(ell + 1))) < 1e-12
+        assert np.max(np.abs(Z.T @ Z - np.eye(ell))) < 1e-12
+        assert np.linalg.norm(A @ Z - W @ C) / np.linalg.norm(C, 2) < 1e-12
+        s_gpu = np.linalg.svd(C, compute_uv=False)
+        s_orc = np.linalg.svd(orc.bidiag_matrix(g.alpha, g.beta), compute_uv=False)
+        assert np.max(np.abs(s_gpu[:10] - s_orc[:10]) / s_orc[:10]) < 1e-12, k
+
+
 def test_gkb_multi_group_of_one_fp32_bitwise_single(mq):
     p = I.multi_cube(333, 190, 6.0, 2.0, 1, 30, seed=5)
     with _problem(mq, p, "matfree_fp32") as pr:
