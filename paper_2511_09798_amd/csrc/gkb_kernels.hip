@@ -329,7 +329,11 @@ __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V,
 // times instead of four.  Thread t takes the row pair 2 (t % 16), + 1 and
 // the columns k = t / 16, t / 16 + 16, ...; the 16 column groups' sums are
 // added in group order through LDS.  Rows past n read rows 0, 1 of the
-// column (finite values; their x is zero) and are not written.
+// column (finite values; their x is zero) and are not written.  The grid
+// has 8 ceil(nb / 8) workgroups, and workgroup w takes row block
+// (w % 8) ceil(nb / 8) + w / 8: workgroups are handed to the 8 XCDs in turn,
+// so each XCD takes a contiguous range of row blocks and its L2 holds whole
+// lines of the column-major partial sums.
 constexpr int kFuRows = 32;
 constexpr int kFuLd = kFuRows + 1;             // padded LDS row of the tile
 constexpr int kFuPairs = kFuRows / 2;
@@ -351,8 +355,11 @@ __global__ __launch_bounds__(kBlock) void k_update_gemvt(const double* __restric
     partial += z * bz.d;
     if (st != nullptr) st += z;
     if (st != nullptr && st->stopped) return;  // uniform over the grid
+    const int per = (nb + 7) / 8;
+    const int b = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (b >= nb) return;  // uniform over the workgroup
     const int t = threadIdx.x, rp = t % kFuPairs, cg = t / kFuPairs;
-    const int64_t i0 = (int64_t)blockIdx.x * kFuRows + 2 * rp;
+    const int64_t i0 = (int64_t)b * kFuRows + 2 * rp;
     const double* v = V + (i0 < n ? i0 : 0);
     double* tr = tile + 2 * rp;
     double s0 = 0.0, s1 = 0.0;
@@ -387,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_update_gemvt(const double* __restric
         double sum = 0.0;
 #pragma unroll
         for (int g = 0; g < kFuGroups; ++g) sum += part[g][t];
-        const int64_t i = (int64_t)blockIdx.x * kFuRows + t;
+        const int64_t i = (int64_t)b * kFuRows + t;
         double xi = 0.0;
         if (i < n) {
             xi = x[i] - sum;
@@ -401,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_update_gemvt(const double* __restric
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < kFuRows; ++i) acc = fma(r[i], xs[i], acc);
-        partial[(int64_t)kk * nb + blockIdx.x] = acc;
+        partial[(int64_t)kk * nb + b] = acc;
     }
 }
 
@@ -516,7 +523,8 @@ void launch_update_gemvt_b(const double* V, int64_t ldn, int64_t n, int32_t m, d
                            int64_t sp, hipStream_t s) {
     const int nb = fused_cgs_blocks(n);
     const size_t lds = (size_t)m * kFuLd * sizeof(double);
-    k_update_gemvt<<<dim3(nb, 1, nz), kBlock, lds, s>>>(V, ldn, n, m, c, x, partial, nb, st, Bz{sV, sc, sx, sp});
+    k_update_gemvt<<<dim3(8 * ((nb + 7) / 8), 1, nz), kBlock, lds, s>>>(V, ldn, n, m, c, x, partial, nb, st,
+                                                                       Bz{sV, sc, sx, sp});
     k_gemvt_reduce<<<dim3((m + kBlock / kWave - 1) / (kBlock / kWave), nz), kBlock, 0, s>>>(
         partial, nb, m, 1, nb, c, st, Bz{sp, sc, 0, 0});
 }
