@@ -328,8 +328,9 @@ __global__ __launch_bounds__(kBlock) void k_update(const double* __restrict__ V,
 // dynamic shared memory) between the two, so CGS2 reads the basis three
 // times instead of four.  Thread t takes the row pair 2 (t % 16), + 1 and
 // the columns k = t / 16, t / 16 + 16, ...; the 16 column groups' sums are
-// added in group order through LDS.  Rows past n read rows 0, 1 of the
-// column (finite values; their x is zero) and are not written.  The grid
+// added in group order through LDS.  A pair past n reads rows 0, 1 of the
+// column, a pair that straddles n the zero padding below ldn (finite values
+// either way; their x is zero), and rows past n are not written.  The grid
 // has 8 ceil(nb / 8) workgroups, and workgroup w takes row block
 // (w % 8) ceil(nb / 8) + w / 8: workgroups are handed to the 8 XCDs in turn,
 // so each XCD takes a contiguous range of row blocks and its L2 holds whole
